@@ -1,0 +1,7 @@
+"""MI355X-native H-matrix BEM operators (Helmholtz / Laplace single layer at quadrature points).
+
+The compute path is the HIP library ``libhmx.so`` built from ``csrc/``; ``hmx`` is its thin
+ctypes binding.  Importing the package loads nothing; ``from paper_1804_00995_amd import hmx``
+loads the library and fails loudly if it is missing.
+"""
+__all__ = ["inputs", "hmx"]

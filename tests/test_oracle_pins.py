@@ -1,0 +1,424 @@
+"""Pins of the CPU oracle against what the mathematics and the paper fix (no GPU needed).
+
+Every oracle function is checked against something other than itself:
+  * quadrature points: polynomial exactness of the rule on mapped triangles, total weight = area;
+  * Green kernel: closed values (mpmath), symmetry, Laplace limit, r = 0 convention;
+  * dense operator: the unit sphere's single-layer eigenvalues on zonal harmonics, 1/(2l+1) for
+    Laplace and i k j_l(k) h_l(k) for Helmholtz, with the O(h) convergence of the quadrature
+    discretisation and its Richardson extrapolation;
+  * cluster and block trees: brute-force coverage of the M x M index square, the split rule and
+    the admissibility rule re-checked per block;
+  * ACA: exact separable rank, Eckart-Young lower bounds from an SVD, zero-row handling;
+  * H-matrix product: distance to the dense product at the ACA tolerance.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import special
+
+import oracle
+from paper_1804_00995_amd import inputs as I
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+# ------------------------------------------------------------------------------------ meshes
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 4])
+def test_icosphere_counts_and_euler(level):
+    v, f = I.icosphere(level)
+    assert f.shape[0] == 20 * 4 ** level
+    assert v.shape[0] == 10 * 4 ** level + 2
+    e = np.unique(np.sort(np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]]), axis=1), axis=0)
+    assert e.shape[0] == 30 * 4 ** level
+    assert v.shape[0] - e.shape[0] + f.shape[0] == 2
+    assert np.abs(np.linalg.norm(v, axis=1) - 1).max() < 1e-15
+
+
+def test_icosphere_area_increases_to_4pi():
+    areas = [I.mesh_stats(*I.icosphere(L))[3] for L in range(0, 6)]
+    assert all(a < b for a, b in zip(areas, areas[1:]))
+    assert all(a < 4 * math.pi for a in areas)
+    assert abs(areas[3] - 12.506493) < 1e-6
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 11])
+def test_geodesic_counts(m):
+    v, f = I.geodesic_sphere(m)
+    assert f.shape[0] == 20 * m * m
+    assert v.shape[0] == 10 * m * m + 2
+    a, b, c = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    n = np.cross(b - a, c - a)
+    assert (np.einsum("ij,ij->i", n, a + b + c) > 0).all()
+
+
+def test_ellipsoid_on_surface():
+    v, f = I.icosphere(2)
+    ax = np.array([2.0, 1.0, 0.5])
+    e = I.ellipsoid(v, ax)
+    assert np.abs(((e / ax) ** 2).sum(1) - 1).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------- quadrature (O1)
+def _one_triangle(a, b, c):
+    return np.array([a, b, c], np.float64), np.array([[0, 1, 2]], np.int32)
+
+
+def test_quadrature_degree2_exact_on_reference_triangle():
+    v, f = _one_triangle([0, 0, 0], [1, 0, 0], [0, 1, 0])
+    bary, w = I.rule_3pt()
+    P, W = oracle.quad_points(v, f, bary, w)
+    x, y = P[:, 0], P[:, 1]
+    # integrals over the unit right triangle
+    exact = {"1": 0.5, "x": 1 / 6, "y": 1 / 6, "x2": 1 / 12, "xy": 1 / 24, "y2": 1 / 12}
+    got = {"1": W.sum(), "x": (W * x).sum(), "y": (W * y).sum(), "x2": (W * x * x).sum(),
+           "xy": (W * x * y).sum(), "y2": (W * y * y).sum()}
+    for key in exact:
+        assert abs(got[key] - exact[key]) < 1e-15, key
+    # not exact at degree 3: the rule is the degree-2 one
+    assert abs((W * x ** 3).sum() - 1 / 20) > 1e-4
+
+
+def test_quadrature_affine_map_and_area():
+    # a general triangle in 3D: exactness is affine-invariant, area from the cross product
+    a, b, c = np.array([0.3, -1.2, 2.0]), np.array([1.7, 0.4, -0.5]), np.array([-0.8, 2.2, 0.9])
+    v, f = _one_triangle(a, b, c)
+    bary, w = I.rule_3pt()
+    P, W = oracle.quad_points(v, f, bary, w)
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a))
+    assert abs(W.sum() - area) < 1e-14 * area
+    # integral of the squared distance to vertex a: area * (|e1|^2 + |e2|^2 + e1.e2) / 6
+    e1, e2 = b - a, c - a
+    exact = area * (e1 @ e1 + e2 @ e2 + e1 @ e2) / 6
+    got = (W * ((P - a) ** 2).sum(1)).sum()
+    assert abs(got - exact) < 1e-13 * exact
+    # each point is the stated barycentric combination, point m = n_q * t + q
+    for q in range(3):
+        assert np.allclose(P[q], bary[q, 0] * a + bary[q, 1] * b + bary[q, 2] * c, rtol=0, atol=1e-15)
+
+
+def test_quadrature_total_weight_equals_mesh_area():
+    v, f = I.icosphere(3)
+    bary, w = I.rule_3pt()
+    P, W = oracle.quad_points(v, f, bary, w)
+    assert P.shape == (3 * f.shape[0], 3)
+    assert abs(W.sum() - I.mesh_stats(v, f)[3]) < 1e-12
+
+
+def test_quadrature_rejects_bad_index():
+    v, f = _one_triangle([0, 0, 0], [1, 0, 0], [0, 1, 0])
+    f[0, 2] = 3
+    with pytest.raises(ValueError):
+        oracle.quad_points(v, f, *I.rule_3pt())
+
+
+# ----------------------------------------------------------------------------- Green kernel
+def test_green_closed_values():
+    x = np.array([[0.0, 0.0, 0.0], [0.1, 0.2, 0.3], [1.0, 1.0, 1.0]])
+    y = np.array([[1.0, 0.0, 0.0], [0.1, 0.2, 0.3], [-1.0, 0.5, 2.0]])
+    g = oracle.green(oracle.HELMHOLTZ, 5.0, x, y)
+    e = mpmath.exp(5j) / (4 * mpmath.pi)
+    assert abs(g[0] - complex(e)) < 1e-16
+    assert abs(g[0] - (0.02257312 - 0.07630877j)) < 1e-8
+    assert g[1] == 0  # r = 0 pairs give 0
+    r = math.sqrt(4 + 0.25 + 1)
+    e2 = mpmath.exp(1j * 5 * mpmath.mpf(r)) / (4 * mpmath.pi * r)
+    assert abs(g[2] - complex(e2)) < 1e-16
+
+
+def test_green_symmetry_and_laplace_limit():
+    rng = np.random.default_rng(3)
+    x, y = rng.standard_normal((50, 3)), rng.standard_normal((50, 3))
+    for k in [0.0, 2.5, 40.0]:
+        assert np.array_equal(oracle.green(oracle.HELMHOLTZ, k, x, y), oracle.green(oracle.HELMHOLTZ, k, y, x))
+    r = np.linalg.norm(x - y, axis=1)
+    lap = oracle.green(oracle.LAPLACE, 7.0, x, y)
+    assert np.allclose(lap, 1 / (4 * np.pi * r), rtol=1e-15, atol=0)
+    assert np.allclose(oracle.green(oracle.HELMHOLTZ, 0.0, x, y), lap, rtol=1e-15, atol=0)
+    p2 = oracle.green(oracle.POLY2, 0.0, x, y)
+    assert np.allclose(p2, (1 + (x * y).sum(1)) ** 2, rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------------------------------ dense operator (O2)
+def sphere_eig(l, k):
+    """Single-layer eigenvalue on the unit sphere for degree-l harmonics."""
+    if k == 0:
+        return 1.0 / (2 * l + 1)
+    j = special.spherical_jn(l, k)
+    y = special.spherical_yn(l, k)
+    return 1j * k * j * (j + 1j * y)
+
+
+def test_sphere_eig_closed_form_crosscheck():
+    # the scipy closed form against mpmath Bessel functions and the l = 0 elementary form
+    for k in [5.0, 40.0]:
+        assert abs(sphere_eig(0, k) - np.exp(1j * k) * np.sin(k) / k) < 1e-15
+        for l in range(0, 5):
+            jl = mpmath.sqrt(mpmath.pi / (2 * k)) * mpmath.besselj(l + 0.5, k)
+            yl = mpmath.sqrt(mpmath.pi / (2 * k)) * mpmath.bessely(l + 0.5, k)
+            ref = 1j * k * jl * (jl + 1j * yl)
+            assert abs(sphere_eig(l, k) - complex(ref)) < 1e-14
+    assert abs(sphere_eig(0, 5.0) - (-0.054402111089 + 0.183907152908j)) < 1e-11
+
+
+def _rayleigh(level, kern, k, l, axis_seed=7):
+    v, f = I.icosphere(level)
+    P, W = oracle.quad_points(v, f, *I.rule_3pt())
+    d = np.random.default_rng(axis_seed).standard_normal(3)
+    d /= np.linalg.norm(d)
+    u = P @ d / np.linalg.norm(P, axis=1)
+    fz = special.eval_legendre(l, u).astype(np.complex128)
+    Kf = oracle.dense_matvec(P, W, kern, k, fz)
+    return np.vdot(fz, W * Kf) / np.vdot(fz, W * fz)
+
+
+@pytest.mark.parametrize("kern,k,l", [(oracle.LAPLACE, 0.0, 0), (oracle.LAPLACE, 0.0, 2),
+                                      (oracle.HELMHOLTZ, 5.0, 0), (oracle.HELMHOLTZ, 5.0, 1),
+                                      (oracle.HELMHOLTZ, 5.0, 3)])
+def test_dense_sphere_eigenvalue_convergence(kern, k, l):
+    """Rayleigh quotients on L2, L3, L4 converge at O(h) to the closed form; Richardson improves."""
+    lam = sphere_eig(l, k)
+    est = [_rayleigh(L, kern, k, l) for L in (2, 3, 4)]
+    err = [abs(e - lam) for e in est]
+    assert err[0] > err[1] > err[2]
+    # O(h): halving h halves the error (the coarsest pair is still pre-asymptotic at k = 5)
+    assert 1.4 <= err[0] / err[1] <= 2.6, err
+    assert 1.6 <= err[1] / err[2] <= 2.6, err
+    rich = 2 * est[2] - est[1]
+    assert abs(rich - lam) < 0.5 * err[2]
+    assert err[1] < 0.025  # L3: the zeroed self-cell costs about 0.016 in absolute terms
+
+
+def test_dense_matches_brute_force_tiny():
+    # brute force on a tiny mesh: explicit matrix assembled point pair by point pair
+    v, f = I.icosphere(1)
+    P, W = oracle.quad_points(v, f, *I.rule_3pt())
+    M = P.shape[0]
+    k = 3.0
+    x = I.complex_vector(M, 0)
+    K = np.zeros((M, M), np.complex128)
+    for i in range(M):
+        for j in range(M):
+            r = math.dist(P[i], P[j])
+            if r > 0:
+                K[i, j] = complex(mpmath.exp(1j * k * r) / (4 * mpmath.pi * r)) * W[j]
+    y = oracle.dense_matvec(P, W, oracle.HELMHOLTZ, k, x)
+    assert np.abs(y - K @ x).max() < 1e-13 * np.abs(K @ x).max()
+    rows = np.array([5, 0, M - 1, 17])
+    assert np.array_equal(oracle.dense_rows(P, W, oracle.HELMHOLTZ, k, x, rows), y[rows])
+
+
+# -------------------------------------------------------------------- tree and blocks (O3, O4)
+def _tree_blocks(level, leaf, eta=1.5, k=5.0):
+    v, f = I.icosphere(level)
+    P, W = oracle.quad_points(v, f, *I.rule_3pt())
+    H = oracle.HMatrix(P, W, oracle.HELMHOLTZ, k, leaf=leaf, eta=eta, tol=1e-3)
+    return P, W, H
+
+
+@pytest.mark.parametrize("leaf", [16, 64])
+def test_tree_invariants(leaf):
+    P, W, H = _tree_blocks(3, leaf)
+    T = H.tree()
+    M = P.shape[0]
+    assert np.array_equal(np.sort(T["perm"]), np.arange(M))
+    n = len(T["begin"])
+    for i in range(n):
+        b, e = T["begin"][i], T["end"][i]
+        pts = P[T["perm"][b:e]]
+        assert np.array_equal(T["box"][i, :3], pts.min(0)) and np.array_equal(T["box"][i, 3:], pts.max(0))
+        c0, c1 = T["child0"][i], T["child1"][i]
+        if c0 < 0:
+            assert e - b <= leaf or np.ptp(pts, axis=0).max() == 0
+            continue
+        assert e - b > leaf
+        assert T["begin"][c0] == b and T["end"][c0] == T["begin"][c1] and T["end"][c1] == e
+        assert T["level"][c0] == T["level"][i] + 1
+        ext = T["box"][i, 3:] - T["box"][i, :3]
+        ax = int(np.argmax(ext))
+        mid = 0.5 * (T["box"][i, ax] + T["box"][i, 3 + ax])
+        assert (P[T["perm"][b:T["end"][c0]], ax] < mid).all()
+        assert (P[T["perm"][T["begin"][c1]:e], ax] >= mid).all()
+
+
+def _py_cluster_order(P, idx, leaf):
+    """Brute-force restatement of the bisection: list comprehensions keep relative order."""
+    pts = P[idx]
+    lo, hi = pts.min(0), pts.max(0)
+    ext = hi - lo
+    ax = int(np.argmax(ext))
+    if len(idx) <= leaf or ext[ax] == 0:
+        return list(idx)
+    mid = 0.5 * (lo[ax] + hi[ax])
+    left = [i for i in idx if P[i, ax] < mid]
+    right = [i for i in idx if not P[i, ax] < mid]
+    if not left or not right:
+        return list(idx)
+    return _py_cluster_order(P, left, leaf) + _py_cluster_order(P, right, leaf)
+
+
+@pytest.mark.parametrize("level,leaf", [(2, 16), (2, 7), (3, 64)])
+def test_tree_order_matches_brute_force(level, leaf):
+    P, W, H = _tree_blocks(level, leaf)
+    assert H.tree()["perm"].tolist() == _py_cluster_order(P, list(range(P.shape[0])), leaf)
+
+
+@pytest.mark.parametrize("leaf", [16, 64])
+def test_block_partition_brute_force(leaf):
+    P, W, H = _tree_blocks(3, leaf)
+    M = P.shape[0]
+    nearR, farR, ranks = H.blocks()
+    cover = np.zeros((M, M), np.int8)
+    for R in (nearR, farR):
+        for tb, te, sb, se in R:
+            cover[tb:te, sb:se] += 1
+    assert (cover == 1).all()
+    T = H.tree()
+    perm = T["perm"]
+    leaves = {(b, e) for b, e, c in zip(T["begin"], T["end"], T["child0"]) if c < 0}
+    for tb, te, sb, se in nearR:
+        assert (tb, te) in leaves and (sb, se) in leaves
+
+    def box(b, e):
+        p = P[perm[b:e]]
+        return p.min(0), p.max(0)
+
+    for tb, te, sb, se in farR:
+        (lo1, hi1), (lo2, hi2) = box(tb, te), box(sb, se)
+        d1 = ((hi1 - lo1) ** 2).sum()
+        d2 = ((hi2 - lo2) ** 2).sum()
+        gap = np.maximum(0, np.maximum(lo2 - hi1, lo1 - hi2))
+        assert min(d1, d2) <= 1.5 ** 2 * (gap ** 2).sum()
+    keys = [tuple(r) for r in nearR]
+    assert keys == sorted(keys)
+    keys = [tuple(r) for r in farR]
+    assert keys == sorted(keys)
+
+
+def test_near_blocks_not_admissible():
+    P, W, H = _tree_blocks(3, 16)
+    nearR, _, _ = H.blocks()
+    perm = H.tree()["perm"]
+    for tb, te, sb, se in nearR:
+        p1, p2 = P[perm[tb:te]], P[perm[sb:se]]
+        d1 = (np.ptp(p1, 0) ** 2).sum()
+        d2 = (np.ptp(p2, 0) ** 2).sum()
+        gap = np.maximum(0, np.maximum(p2.min(0) - p1.max(0), p1.min(0) - p2.max(0)))
+        assert min(d1, d2) > 1.5 ** 2 * (gap ** 2).sum()
+
+
+# ------------------------------------------------------------------------------- ACA (O5)
+def test_aca_exact_rank_poly2():
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1, 1, (70, 3))
+    y = rng.uniform(-1, 1, (90, 3)) + np.array([3.0, 0, 0])
+    A = (1 + x @ y.T) ** 2
+    assert np.linalg.matrix_rank(A) == 10
+    U, V, conv = oracle.aca_dense(A.astype(np.complex128), 1e-12)
+    # the stopping rule needs one term past the exact rank, and that term is at rounding level
+    assert conv and U.shape[1] <= 11
+    assert np.linalg.norm(A - U @ V.T) <= 1e-12 * np.linalg.norm(A)
+    U, V, conv = oracle.aca_dense(A.astype(np.complex128), 1e-12, rcap=10)
+    assert U.shape[1] == 10
+    assert np.linalg.norm(A - U @ V.T) <= 1e-12 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("r", [1, 3, 7])
+def test_aca_recovers_random_low_rank(r):
+    rng = np.random.default_rng(r)
+    A = (rng.standard_normal((40, r)) + 1j * rng.standard_normal((40, r))) @ \
+        (rng.standard_normal((r, 55)) + 1j * rng.standard_normal((r, 55)))
+    U, V, conv = oracle.aca_dense(A, 1e-10)
+    assert conv and U.shape[1] <= r + 1
+    assert np.linalg.norm(A - U @ V.T) <= 1e-11 * np.linalg.norm(A)
+
+
+def test_aca_first_step_is_cross_of_first_row():
+    # with one step the approximant is a(:,j1) a(i1,:) / a(i1,j1), i1 = 0, j1 = argmax |a(0,:)|
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((6, 8)) + 1j * rng.standard_normal((6, 8))
+    U, V, conv = oracle.aca_dense(A, 1e-16, rcap=1)
+    j1 = int(np.argmax(np.abs(A[0])))
+    assert U.shape[1] == 1 and not conv
+    assert np.allclose(np.outer(U[:, 0], V[:, 0]), np.outer(A[:, j1], A[0]) / A[0, j1], atol=1e-14)
+
+
+def test_aca_zero_rows_skipped():
+    A = np.zeros((5, 4), np.complex128)
+    A[3] = [1, 2, 3, 4]
+    A[4] = [2, 4, 6, 8.5]
+    U, V, conv = oracle.aca_dense(A, 1e-12)
+    assert conv
+    assert np.linalg.norm(A - U @ V.T) <= 1e-13
+    assert U.shape[1] == 2
+
+
+def _kernel_block(P, W, rows, cols, k):
+    X = P[rows][:, None, :]
+    Y = P[cols][None, :, :]
+    r = np.sqrt(((X - Y) ** 2).sum(-1))
+    return np.exp(1j * k * r) / (4 * np.pi * r) * W[cols][None, :]
+
+
+@pytest.mark.parametrize("k", [5.0, 20.0])
+def test_aca_eckart_young_and_tolerance(k):
+    """For admissible far blocks of the oracle's own partition, the ACA error is bounded below
+    by the SVD tail (a theorem) and, heuristically, above by a small multiple of tol."""
+    P, W, H = _tree_blocks(3, 64, k=k)
+    perm = H.tree()["perm"]
+    _, farR, ranks = H.blocks()
+    sizes = (farR[:, 1] - farR[:, 0]) * (farR[:, 3] - farR[:, 2])
+    for b in np.argsort(-sizes)[:12]:
+        tb, te, sb, se = farR[b]
+        A = _kernel_block(P, W, perm[tb:te], perm[sb:se], k)
+        fac = H.far_factors(int(b), te - tb, se - sb, int(ranks[b]))
+        assert fac is not None
+        U, V = fac
+        r = U.shape[1]
+        err = np.linalg.norm(A - U @ V.T)
+        s = np.linalg.svd(A, compute_uv=False)
+        tail = math.sqrt((s[r:] ** 2).sum())
+        assert err >= tail * (1 - 1e-9)
+        assert err <= 10 * 1e-3 * np.linalg.norm(A)
+
+
+# ------------------------------------------------------------------------ H-matrix product (O6)
+@pytest.mark.parametrize("kern,k", [(oracle.HELMHOLTZ, 5.0), (oracle.LAPLACE, 0.0), (oracle.HELMHOLTZ, 15.0)])
+def test_hmatvec_close_to_dense(kern, k):
+    v, f = I.icosphere(3)
+    P, W = oracle.quad_points(v, f, *I.rule_3pt())
+    x = I.complex_vector(P.shape[0], 0)
+    H = oracle.HMatrix(P, W, kern, k, leaf=64, tol=1e-3)
+    y = oracle.dense_matvec(P, W, kern, k, x)
+    yh = H.matvec(x)
+    assert np.linalg.norm(yh - y) / np.linalg.norm(y) <= 1e-3
+    assert H.info["n_far"] > 0 and H.info["s_far"] < H.info["n_far"] * 64 * 64
+
+
+def test_hmatvec_tolerance_controls_error():
+    v, f = I.icosphere(3)
+    P, W = oracle.quad_points(v, f, *I.rule_3pt())
+    x = I.complex_vector(P.shape[0], 1)
+    y = oracle.dense_matvec(P, W, oracle.HELMHOLTZ, 8.0, x)
+    errs = []
+    for tol in (1e-2, 1e-4, 1e-6):
+        H = oracle.HMatrix(P, W, oracle.HELMHOLTZ, 8.0, leaf=32, tol=tol)
+        errs.append(np.linalg.norm(H.matvec(x) - y) / np.linalg.norm(y))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-5
+
+
+def test_hmatvec_poly2_exact():
+    v, f = I.icosphere(2)
+    P, W = oracle.quad_points(v, f, *I.rule_3pt())
+    x = I.complex_vector(P.shape[0], 2)
+    H = oracle.HMatrix(P, W, oracle.POLY2, 0.0, leaf=16, tol=1e-13)
+    K = (1 + P @ P.T) ** 2 * W[None, :]
+    y = K @ x
+    assert np.linalg.norm(H.matvec(x) - y) <= 1e-11 * np.linalg.norm(y)
+    _, _, ranks = H.blocks()
+    assert ranks.max() <= 11
