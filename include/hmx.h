@@ -1,0 +1,168 @@
+/*
+ * hmx.h -- C ABI of libhmx, the MI355X (gfx950) H-matrix boundary-element operator library.
+ *
+ * Problem statement (Alouges & Aussal, "FEM and BEM simulations with the Gypsilab framework",
+ * arXiv 1804.00995):
+ *   - a triangulated surface and a quadrature rule per triangle give the points and weights
+ *     (x_k, w_k) of the discretisation (Section 3, "build the set of quadrature points/weights";
+ *     Section 4.2, a domain is a mesh plus a quadrature formula);
+ *   - the BEM matrices are products around the dense kernel matrix G_kl = G(x_k, y_l)
+ *     (Section 5, eq. (BEM)), with the Helmholtz kernel G(x, y) = e^{ik|x-y|} / (4 pi |x-y|)
+ *     (Section 5.2, eq. (Helmholtz));
+ *   - given a tolerance, the same matrices are returned compressed as H-matrices and used through
+ *     the usual matrix product (Section 5.3); without it they are dense (Section 5.1).
+ * The operator built here is the collocation form at the quadrature points with source weights,
+ *   K = G W_y,  K_ml = G(x_m, x_l) w_l,  and K_ml = 0 when x_m = x_l,
+ * applied to complex vectors.  The compression (cluster tree, admissibility, partially pivoted
+ * ACA) is not described in the paper; libhmx uses a bounding-box bisection tree, the
+ * admissibility min(diam) <= eta * dist, and ACA with the Frobenius-norm stopping rule at tol.
+ *
+ * Conventions for every entry point:
+ *   - every function returns an hmx_status (0 = success); on failure nothing is returned through
+ *     the out-arguments, no partial operator exists, and hmx_last_error() gives a message
+ *     (thread-local, valid until the next call on the same thread);
+ *   - "device" pointers are HIP device memory on the current device; "host" pointers are host
+ *     memory; the library never takes ownership of caller memory and copies what it keeps;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream);
+ *   - complex vectors are interleaved (re, im): double pairs for HMX_FP64 operators, float pairs
+ *     for HMX_FP32_MIXED operators; vectors have one entry per quadrature point, in the original
+ *     triangle-major order m = n_q * t + q.
+ */
+#ifndef HMX_H
+#define HMX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HMX_OK = 0,
+  HMX_EINVAL = -1,       /* invalid argument (checked before any work is enqueued) */
+  HMX_ENOMEM = -2,       /* device or host allocation failed */
+  HMX_EDEVICE = -3,      /* a HIP runtime call or kernel failed */
+  HMX_EUNSUPPORTED = -4, /* valid request outside what this build supports */
+  HMX_EINTERNAL = -5     /* internal consistency check failed */
+} hmx_status;
+
+typedef enum {
+  HMX_LAPLACE = 0,    /* G = 1 / (4 pi r) */
+  HMX_HELMHOLTZ = 1,  /* G = e^{ikr} / (4 pi r) */
+  HMX_TEST_POLY2 = 99 /* test only: G = (1 + x.y)^2, exact separable rank 10 */
+} hmx_kernel;
+
+typedef enum {
+  HMX_FP64 = 0,      /* everything in FP64, vectors c128 */
+  HMX_FP32_MIXED = 1 /* blocks, factors and vectors in FP32 (c64); distance, phase k*r, ACA
+                        pivots and norms in FP64 */
+} hmx_precision;
+
+typedef enum {
+  HMX_RANK_ADAPTIVE = 0, /* plain adaptive ACA: factors grow in place, then compacted */
+  HMX_RANK_LEARNED = 1   /* storage laid out from the rank MLP's prediction, adaptive
+                            continuation for blocks the prediction under-sizes */
+} hmx_rank_model;
+
+typedef struct {
+  int32_t struct_size;   /* sizeof(hmx_params): ABI guard */
+  double tol;            /* ACA tolerance; tol <= 0 builds the dense operator */
+  int32_t leaf_size;     /* cluster-tree leaf size L (split while a node holds > L points) */
+  double eta;            /* admissibility: far when min(diam) <= eta * dist */
+  int32_t precision;     /* hmx_precision */
+  int32_t rank_model;    /* hmx_rank_model */
+  int32_t initial_rank;  /* adaptive mode: first rank capacity per far block (>= 1) */
+  double force_pred_scale; /* learned mode: multiplies the predicted rank (tests force overflow) */
+  int32_t force_rank_cap;  /* > 0: caps every far block's ACA rank (tests force dense fallback) */
+  int64_t pool_limit_bytes; /* > 0: fail with HMX_ENOMEM when the operator would exceed this */
+} hmx_params;
+
+/* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
+ * initial_rank 16, force_pred_scale 1, no rank cap, no pool limit. */
+hmx_status hmx_params_default(hmx_params* p);
+
+typedef struct hmx_op hmx_op; /* opaque, library-owned; free with hmx_destroy */
+
+/* Quadrature points and weights of a triangle mesh (Section 3: points and weights over all
+ * simplices; Section 4.2: mesh + quadrature formula).
+ *   vtx  device, n_vtx x 3 doubles, row-major vertex coordinates;
+ *   tri  device, n_tri x 3 int32, 0-based vertex indices;
+ *   q_bary host, n_q x 3 barycentric coordinates; q_w host, n_q reference weights (sum 1);
+ *   xyzw device output, 4 x M doubles (M = n_q * n_tri): X[M], Y[M], Z[M], W[M] with
+ *        x_{n_q t + q} = sum_j q_bary[q][j] * vtx[tri[t][j]], W = area(t) * q_w[q].
+ * Errors: HMX_EINVAL for null pointers, n_q < 1, a rule whose weights do not sum to 1 within
+ * 1e-12 or whose barycentrics leave the triangle, a triangle index out of range, or a
+ * non-finite vertex coordinate (the last two are detected on the device). Synchronous. */
+hmx_status hmx_quad_points(const double* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                           const double* q_bary, const double* q_w, int32_t n_q, double* xyzw,
+                           void* stream);
+
+/* Builds the operator K = G W_y of a triangle mesh with a quadrature rule (arguments as in
+ * hmx_quad_points) for kernel `kern` and wavenumber k >= 0 (Section 5.1 / 5.3: dense without a
+ * tolerance, H-matrix with one).  With p->tol > 0 the H-matrix is built on the device: cluster
+ * tree, block tree, near-field blocks, ACA on far blocks.  `p` may be NULL for the defaults.
+ * Synchronous: returns when the operator is complete.  On success *out owns all of its device
+ * memory. Errors: HMX_EINVAL (arguments as above, k < 0, leaf_size < 1, eta <= 0),
+ * HMX_ENOMEM, HMX_EDEVICE, HMX_EUNSUPPORTED (more than 2^23 points in H-matrix mode). */
+hmx_status hmx_build(const double* vtx, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                     const double* q_bary, const double* q_w, int32_t n_q, int32_t kern, double k,
+                     const hmx_params* p, void* stream, hmx_op** out);
+
+/* Same as hmx_build from given points: xyzw device, 4 x M doubles laid out as in
+ * hmx_quad_points (X, Y, Z, W).  Vectors then follow the order of these points. */
+hmx_status hmx_build_points(const double* xyzw, int64_t M, int32_t kern, double k,
+                            const hmx_params* p, void* stream, hmx_op** out);
+
+/* y = K x (Section 5.3: the compressed matrix applied through the product).
+ *   x, y device, M complex entries each (c128 for FP64 operators, c64 for FP32 ones), in the
+ *   original point order; x and y must not alias.
+ * Asynchronous on `stream`; allocates nothing and performs no host synchronisation, so it can
+ * be captured in a HIP graph.  The operator holds the product's scratch vectors: products on
+ * the same operator must not overlap in time (different operators are independent).
+ * Errors: HMX_EINVAL for null pointers. */
+hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream);
+
+typedef struct {
+  int64_t n_points, n_nodes, n_leaves, n_near, n_far;
+  int64_t near_entries;   /* sum of m*n over near blocks */
+  int64_t far_entries;    /* sum of r*(m+n) over low-rank far blocks */
+  int64_t dense_far;      /* far blocks stored dense (ACA not converged at the rank cap) */
+  int64_t dense_far_entries;
+  int64_t max_rank, sum_rank;
+  int64_t overflow_blocks; /* blocks continued past their first rank allocation */
+  int64_t bytes;           /* device bytes held by the operator */
+  int32_t precision, is_dense;
+  double t_tree_ms, t_blocks_ms, t_near_ms, t_aca_ms, t_total_ms; /* build phases (events) */
+  int64_t kernel_evals;    /* Green-kernel evaluations spent in the build */
+} hmx_info_t;
+
+/* Sizes, counts and build timings of an operator. */
+hmx_status hmx_info(const hmx_op* op, hmx_info_t* out);
+
+/* Cluster tree export (host outputs, sized from hmx_info): perm[M] (cluster position -> point
+ * index), and per node in breadth-first order begin, end, level, child0, child1 (-1 = leaf),
+ * box (6 doubles: lo xyz, hi xyz).  Any output pointer may be NULL. */
+hmx_status hmx_export_tree(const hmx_op* op, int32_t* perm, int64_t* begin, int64_t* end,
+                           int32_t* level, int32_t* child0, int32_t* child1, double* box);
+
+/* Block export (host outputs): near (n_near x 4) and far (n_far x 4) int64 rows
+ * (t.begin, t.end, s.begin, s.end) in cluster positions, sorted lexicographically, and far ranks
+ * (-1 for a far block stored dense).  Any output pointer may be NULL. */
+hmx_status hmx_export_blocks(const hmx_op* op, int64_t* near_rc, int64_t* far_rc, int32_t* ranks);
+
+/* Factors of far block b (host outputs, complex of the operator's precision): U (m x r) and
+ * V (n x r) column-major with block ~ U V^T; for a dense far block U receives the m x n block
+ * and V is untouched.  *rank receives r (or -1 for dense). */
+hmx_status hmx_export_far(const hmx_op* op, int64_t b, void* U, void* V, int32_t* rank);
+
+/* Frees the operator and all of its device memory; NULL is accepted. */
+void hmx_destroy(hmx_op* op);
+
+/* Message of the last failed call on this thread ("" when none). */
+const char* hmx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMX_H */

@@ -1,0 +1,227 @@
+// hmx_host.h -- host-side internals of libhmx: errors, device buffers, the operator object and
+// the kernel launchers implemented in the k_*.hip translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/hmx.h"
+
+namespace hmx {
+
+struct Error : std::runtime_error {
+  hmx_status code;
+  Error(hmx_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e) + " (" + file + ":" +
+                  std::to_string(line) + ")";
+  throw Error(e == hipErrorOutOfMemory ? HMX_ENOMEM : HMX_EDEVICE, m);
+}
+#define HMX_HIP(x)                                                   \
+  do {                                                               \
+    hipError_t e_ = (x);                                             \
+    if (e_ != hipSuccess) ::hmx::hip_fail(e_, #x, __FILE__, __LINE__); \
+  } while (0)
+#define HMX_LAUNCHED() HMX_HIP(hipGetLastError())
+#define HMX_REQUIRE(cond, code, msg)   \
+  do {                                 \
+    if (!(cond)) throw ::hmx::Error(code, msg); \
+  } while (0)
+
+// Owning device buffer (move-only).
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { reset(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { reset(); }
+  void alloc(size_t count) {
+    reset();
+    if (count == 0) return;
+    HMX_HIP(hipMalloc((void**)&p, count * sizeof(T)));
+    n = count;
+  }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+  T* get() const { return p; }
+};
+
+template <class T>
+void to_host(std::vector<T>& h, const T* d, size_t n, hipStream_t s) {
+  h.resize(n);
+  if (n) HMX_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  HMX_HIP(hipStreamSynchronize(s));
+}
+template <class T>
+T read1(const T* d, hipStream_t s) {
+  T v;
+  HMX_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, s));
+  HMX_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+constexpr int MAX_NQ = 32;
+struct Rule {
+  double b[MAX_NQ][3];
+  double w[MAX_NQ];
+  int nq;
+};
+
+// Far-block descriptor used by ACA and by the compaction step.
+struct FarDesc {
+  int32_t tb, m, sb, n;
+  int32_t rcap;  // rank cap: min(floor(m n / (m + n)), coefficient limit, forced cap)
+  int32_t cap;   // rank capacity of the current factor slot
+  void* U;      // slot of U (m x cap, column-major) in one of the build pools
+  void* V;      // slot of V (n x cap, column-major)
+  int64_t foff; // byte offset of the row/column used-flags (m + n bytes)
+};
+
+// Final far-block record used by the product.
+struct FarRec {
+  int32_t tb, m, sb, n;
+  int32_t r;      // rank, or n for a block stored dense (then U is the m x n block)
+  int32_t dense;  // 1 when stored dense
+  int64_t uoff, voff, toff;
+};
+
+constexpr int ACA_COEF_MAX = 1024;  // largest ACA rank (coefficients of a step held in LDS)
+enum AcaStatus : int32_t { ACA_RUNNING = 0, ACA_CONVERGED = 1, ACA_OVERFLOW = 2, ACA_DENSE = 3 };
+
+// ------------------------------------------------------------------------------- launchers
+// k_quad.hip
+void launch_quad(const double* vtx, int64_t nv, const int32_t* tri, int64_t nt, const Rule& rule,
+                 double* X, double* Y, double* Z, double* W, int* err, hipStream_t s);
+// k_scan.hip
+void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);  // out[n] = total
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+void iota_i32(int32_t* p, int64_t n, hipStream_t s);
+void sort_u64_pairs(uint64_t* key, int32_t* val, int64_t n, hipStream_t s);  // n power of two
+// k_tree.hip
+void launch_tree_level(int first, int count, const int32_t* nbegin, const int32_t* nend, int leaf,
+                       const double* cx, const double* cy, const double* cz, const double* cw,
+                       const int32_t* cperm, double* nx, double* ny, double* nz, double* nw,
+                       int32_t* nperm, double* box, int32_t* nleft, hipStream_t s);
+void launch_tree_children(int first, int count, int next_first, const int32_t* nleft,
+                          int32_t* nbegin, int32_t* nend, int32_t* level, int32_t* child0,
+                          int32_t* child1, int32_t* parent, int* next_count, hipStream_t s);
+void launch_leaf_marks(int n_nodes, const int32_t* nbegin, const int32_t* child0,
+                       int64_t* pos_flag, hipStream_t s);
+void launch_leaf_list(int64_t M, const int64_t* pos_flag, const int64_t* pos_scan,
+                      const int32_t* start_node, int32_t* leaves, hipStream_t s);
+void launch_start_node(int n_nodes, const int32_t* nbegin, const int32_t* child0,
+                       int32_t* start_node, hipStream_t s);
+void launch_leaf_index(int n_leaves, const int32_t* leaves, int32_t* leaf_of_node, hipStream_t s);
+// k_blocks.hip
+void launch_block_level(const int2* front, int nfront, const double* box, const int32_t* child0,
+                        const int32_t* child1, double eta2, int2* next, int* next_cnt,
+                        int2* nearL, int* near_cnt, int2* farL, int* far_cnt, hipStream_t s);
+void launch_pair_keys(const int2* pairs, int64_t n, int64_t npad, const int32_t* nbegin,
+                      const int32_t* level, uint64_t* key, int32_t* val, hipStream_t s);
+void launch_pair_gather(const int2* in, const int32_t* idx, int64_t n, int2* out, hipStream_t s);
+void launch_near_prep(const int2* nearL, int64_t n, const int32_t* nbegin, const int32_t* nend,
+                      const int32_t* leaf_of_node, int64_t* sizes, int64_t* leaf_cnt, hipStream_t s);
+void launch_far_prep(const int2* farL, int64_t n, const int32_t* nbegin, const int32_t* nend,
+                     int32_t* far_tb, int32_t* far_m, int32_t* far_sb, int32_t* far_n,
+                     int64_t* node_cnt, int32_t* node_first, hipStream_t s);
+void launch_leaf_far_count(int n_leaves, const int32_t* leaves, const int32_t* parent,
+                           const int64_t* node_cnt, int64_t* leaf_cnt, hipStream_t s);
+void launch_pair_ranges(const int2* pairs, int64_t n, const int32_t* nbegin, const int32_t* nend,
+                        int32_t* tb, int32_t* m, int32_t* sb, int32_t* nn, hipStream_t s);
+void launch_leaf_far_fill(int n_leaves, const int32_t* leaves, const int32_t* parent,
+                          const int64_t* node_cnt, const int32_t* node_first,
+                          const int64_t* leaf_ptr, int32_t* list, hipStream_t s);
+// k_near.hip  (T = double2 or float2)
+template <class T>
+void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, const int32_t* n,
+                     const int64_t* off, int64_t nblk, const double* X, const double* Y,
+                     const double* Z, const double* W, int kern, double k, T* pool, hipStream_t s);
+// k_aca.hip
+template <class T>
+void launch_aca(const FarDesc* d, const int32_t* order, int nb, int* counter, const double* X,
+                const double* Y, const double* Z, const double* W, int kern, double k, double tol,
+                uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
+                double* norm2, int fresh, hipStream_t s);
+template <class T>
+void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* rank,
+                         const int32_t* list, int nlist, hipStream_t s);
+template <class T>
+void launch_compact(const FarDesc* d, const FarRec* rec, const int32_t* rank, int64_t nb, T* dst,
+                    hipStream_t s);
+// k_matvec.hip
+template <class T>
+void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, hipStream_t s);
+template <class T>
+void launch_far_vt(const FarRec* rec, int64_t nf, const T* pool, const T* xp, T* t, hipStream_t s);
+template <class T>
+void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegin,
+                       const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
+                       const int32_t* near_n, const int64_t* near_off, const T* near_pool,
+                       const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
+                       const T* far_pool, const T* tbuf, const T* xp, const int32_t* perm, T* y,
+                       hipStream_t s);
+template <class T>
+void launch_dense_otf(const double* X, const double* Y, const double* Z, const double* W,
+                      int64_t M, int kern, double k, const T* x, T* partial, T* y, hipStream_t s);
+int64_t dense_otf_partial_len(int64_t M);
+
+}  // namespace hmx
+
+// The operator object.
+struct hmx_op {
+  int64_t M = 0;
+  int32_t kern = 1;
+  double k = 0.0;
+  hmx_params p{};
+  bool dense = false;
+  int32_t prec = HMX_FP64;
+  size_t elem = 16;  // bytes per complex entry
+  // points (cluster order for H operators, original order for dense ones)
+  hmx::DevBuf<double> X, Y, Z, W;
+  hmx::DevBuf<int32_t> perm;
+  // tree (breadth-first node numbering)
+  int n_nodes = 0, n_leaves = 0, depth = 0;
+  hmx::DevBuf<int32_t> nbegin, nend, nlevel, child0, child1, parent;
+  hmx::DevBuf<double> box;
+  hmx::DevBuf<int32_t> leaves, leaf_of_node;
+  // near field
+  int64_t n_near = 0, near_entries = 0;
+  hmx::DevBuf<int2> nearL;
+  hmx::DevBuf<int32_t> near_tb, near_m, near_sb, near_n;
+  hmx::DevBuf<int64_t> near_off, near_ptr;
+  hmx::DevBuf<unsigned char> near_pool;
+  // far field
+  int64_t n_far = 0, far_entries = 0, dense_far = 0, dense_far_entries = 0, max_rank = 0,
+          sum_rank = 0, overflow_blocks = 0, t_len = 0, far_pool_elems = 0;
+  hmx::DevBuf<int2> farL;
+  hmx::DevBuf<hmx::FarRec> far;
+  std::vector<hmx::FarRec> far_host;
+  hmx::DevBuf<unsigned char> far_pool;
+  hmx::DevBuf<int64_t> far_ptr;
+  hmx::DevBuf<int32_t> far_list;
+  // product scratch (allocated at build; the product allocates nothing)
+  hmx::DevBuf<unsigned char> xp, tbuf, partial;
+  // build statistics
+  double t_tree = 0, t_blocks = 0, t_near = 0, t_aca = 0, t_total = 0;
+  int64_t kernel_evals = 0;
+  int64_t bytes() const;
+};

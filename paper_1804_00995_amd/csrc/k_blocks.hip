@@ -1,0 +1,225 @@
+// k_blocks.hip -- block tree (admissibility), sorting of the block lists and the per-leaf /
+// per-node index structures used by the product.
+//
+// Definition (the paper leaves it unstated): diam(t) is the length of the box diagonal and
+// dist(t, s) the Euclidean distance between the two boxes (0 when they overlap).  Starting from
+// (root, root), a pair is far (admissible) when min(diam_t^2, diam_s^2) <= eta^2 dist^2; otherwise
+// it is near when both nodes are leaves; otherwise the non-leaf side(s) are split into their
+// children (2 or 4 pairs).  The traversal is level synchronous: one thread per pair of the
+// current frontier.  Compiled without floating-point contraction so that the squared sizes are
+// evaluated exactly as written.
+#include "hmx_dev.h"
+#include "hmx_host.h"
+
+namespace hmx {
+
+__device__ __forceinline__ double diam2(const double* bx) {
+  double ex = bx[3] - bx[0], ey = bx[4] - bx[1], ez = bx[5] - bx[2];
+  return ex * ex + ey * ey + ez * ez;
+}
+__device__ __forceinline__ double dist2(const double* a, const double* b) {
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double g = 0.0;
+    if (b[d] - a[3 + d] > g) g = b[d] - a[3 + d];
+    if (a[d] - b[3 + d] > g) g = a[d] - b[3 + d];
+    s = s + g * g;
+  }
+  return s;
+}
+
+__global__ void __launch_bounds__(WG) block_level_kernel(
+    const int2* __restrict__ front, int nfront, const double* __restrict__ box,
+    const int32_t* __restrict__ child0, const int32_t* __restrict__ child1, double eta2,
+    int2* __restrict__ next, int* next_cnt, int2* __restrict__ nearL, int* near_cnt,
+    int2* __restrict__ farL, int* far_cnt) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= nfront) return;
+  int2 ts = front[i];
+  int t = ts.x, s = ts.y;
+  const double* bt = box + 6 * (int64_t)t;
+  const double* bs = box + 6 * (int64_t)s;
+  double dt = diam2(bt), ds = diam2(bs);
+  double dmin = dt < ds ? dt : ds;
+  if (dmin <= eta2 * dist2(bt, bs)) {
+    farL[atomicAdd(far_cnt, 1)] = ts;
+    return;
+  }
+  int t0 = child0[t], s0 = child0[s];
+  bool lt = t0 < 0, ls = s0 < 0;
+  if (lt && ls) {
+    nearL[atomicAdd(near_cnt, 1)] = ts;
+  } else if (lt) {
+    int q = atomicAdd(next_cnt, 2);
+    next[q] = make_int2(t, s0);
+    next[q + 1] = make_int2(t, child1[s]);
+  } else if (ls) {
+    int q = atomicAdd(next_cnt, 2);
+    next[q] = make_int2(t0, s);
+    next[q + 1] = make_int2(child1[t], s);
+  } else {
+    int t1 = child1[t], s1 = child1[s];
+    int q = atomicAdd(next_cnt, 4);
+    next[q] = make_int2(t0, s0);
+    next[q + 1] = make_int2(t0, s1);
+    next[q + 2] = make_int2(t1, s0);
+    next[q + 3] = make_int2(t1, s1);
+  }
+}
+
+void launch_block_level(const int2* front, int nfront, const double* box, const int32_t* child0,
+                        const int32_t* child1, double eta2, int2* next, int* next_cnt,
+                        int2* nearL, int* near_cnt, int2* farL, int* far_cnt, hipStream_t s) {
+  if (nfront <= 0) return;
+  hipLaunchKernelGGL(block_level_kernel, dim3((nfront + WG - 1) / WG), dim3(WG), 0, s, front,
+                     nfront, box, child0, child1, eta2, next, next_cnt, nearL, near_cnt, farL,
+                     far_cnt);
+  HMX_LAUNCHED();
+}
+
+// Sort key of a block (t, s) equivalent to the lexicographic order of
+// (t.begin, t.end, s.begin, s.end): two distinct nodes with the same begin are nested, and the
+// deeper one ends first, so (begin, end) orders like (begin, -level).
+// Layout: [t.begin:23][63 - t.level:6][s.begin:23][63 - s.level:6]; padding keys are ~0.
+__global__ void pair_keys_kernel(const int2* __restrict__ pairs, int64_t n, int64_t npad,
+                                 const int32_t* __restrict__ nbegin, const int32_t* __restrict__ level,
+                                 uint64_t* __restrict__ key, int32_t* __restrict__ val) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= npad) return;
+  if (i >= n) {
+    key[i] = ~0ull;
+    val[i] = -1;
+    return;
+  }
+  int2 p = pairs[i];
+  uint64_t k = ((uint64_t)nbegin[p.x] << 35) | ((uint64_t)(63 - level[p.x]) << 29) |
+               ((uint64_t)nbegin[p.y] << 6) | (uint64_t)(63 - level[p.y]);
+  key[i] = k;
+  val[i] = (int32_t)i;
+}
+void launch_pair_keys(const int2* pairs, int64_t n, int64_t npad, const int32_t* nbegin,
+                      const int32_t* level, uint64_t* key, int32_t* val, hipStream_t s) {
+  hipLaunchKernelGGL(pair_keys_kernel, dim3((unsigned)((npad + WG - 1) / WG)), dim3(WG), 0, s,
+                     pairs, n, npad, nbegin, level, key, val);
+  HMX_LAUNCHED();
+}
+
+__global__ void pair_gather_kernel(const int2* __restrict__ in, const int32_t* __restrict__ idx,
+                                   int64_t n, int2* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < n) out[i] = in[idx[i]];
+}
+void launch_pair_gather(const int2* in, const int32_t* idx, int64_t n, int2* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(pair_gather_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, in,
+                     idx, n, out);
+  HMX_LAUNCHED();
+}
+
+// Near blocks (sorted): entry counts m*n for the pool offsets, and blocks per row leaf.
+__global__ void near_prep_kernel(const int2* __restrict__ nearL, int64_t n,
+                                 const int32_t* __restrict__ nbegin, const int32_t* __restrict__ nend,
+                                 const int32_t* __restrict__ leaf_of_node, int64_t* __restrict__ sizes,
+                                 int64_t* __restrict__ leaf_cnt) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  int2 p = nearL[i];
+  int64_t m = nend[p.x] - nbegin[p.x], c = nend[p.y] - nbegin[p.y];
+  sizes[i] = m * c;
+  atomicAdd((unsigned long long*)&leaf_cnt[leaf_of_node[p.x]], 1ull);
+}
+void launch_near_prep(const int2* nearL, int64_t n, const int32_t* nbegin, const int32_t* nend,
+                      const int32_t* leaf_of_node, int64_t* sizes, int64_t* leaf_cnt, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(near_prep_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, nearL,
+                     n, nbegin, nend, leaf_of_node, sizes, leaf_cnt);
+  HMX_LAUNCHED();
+}
+
+// Far blocks (sorted): ranges, far-block count per row node and the first block of each node
+// (blocks of one row node are contiguous in the sorted list).
+__global__ void far_prep_kernel(const int2* __restrict__ farL, int64_t n,
+                                const int32_t* __restrict__ nbegin, const int32_t* __restrict__ nend,
+                                int32_t* __restrict__ far_tb, int32_t* __restrict__ far_m,
+                                int32_t* __restrict__ far_sb, int32_t* __restrict__ far_n,
+                                int64_t* __restrict__ node_cnt, int32_t* __restrict__ node_first) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  int2 p = farL[i];
+  far_tb[i] = nbegin[p.x];
+  far_m[i] = nend[p.x] - nbegin[p.x];
+  far_sb[i] = nbegin[p.y];
+  far_n[i] = nend[p.y] - nbegin[p.y];
+  atomicAdd((unsigned long long*)&node_cnt[p.x], 1ull);
+  if (i == 0 || farL[i - 1].x != p.x) node_first[p.x] = (int32_t)i;
+}
+void launch_far_prep(const int2* farL, int64_t n, const int32_t* nbegin, const int32_t* nend,
+                     int32_t* far_tb, int32_t* far_m, int32_t* far_sb, int32_t* far_n,
+                     int64_t* node_cnt, int32_t* node_first, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(far_prep_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, farL, n,
+                     nbegin, nend, far_tb, far_m, far_sb, far_n, node_cnt, node_first);
+  HMX_LAUNCHED();
+}
+
+// Node ranges of a list of (t, s) pairs.
+__global__ void pair_ranges_kernel(const int2* __restrict__ pairs, int64_t n,
+                                   const int32_t* __restrict__ nbegin, const int32_t* __restrict__ nend,
+                                   int32_t* __restrict__ tb, int32_t* __restrict__ m,
+                                   int32_t* __restrict__ sb, int32_t* __restrict__ nn) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  int2 p = pairs[i];
+  tb[i] = nbegin[p.x];
+  m[i] = nend[p.x] - nbegin[p.x];
+  sb[i] = nbegin[p.y];
+  nn[i] = nend[p.y] - nbegin[p.y];
+}
+void launch_pair_ranges(const int2* pairs, int64_t n, const int32_t* nbegin, const int32_t* nend,
+                        int32_t* tb, int32_t* m, int32_t* sb, int32_t* nn, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(pair_ranges_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, pairs,
+                     n, nbegin, nend, tb, m, sb, nn);
+  HMX_LAUNCHED();
+}
+
+// For each leaf: the far blocks whose row node contains it, i.e. the far blocks of the leaf and
+// of each of its ancestors, listed from the leaf upwards (a fixed, deterministic order).
+__global__ void leaf_far_count_kernel(int n_leaves, const int32_t* __restrict__ leaves,
+                                      const int32_t* __restrict__ parent,
+                                      const int64_t* __restrict__ node_cnt, int64_t* __restrict__ leaf_cnt) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= n_leaves) return;
+  int64_t c = 0;
+  for (int a = leaves[i]; a >= 0; a = parent[a]) c += node_cnt[a];
+  leaf_cnt[i] = c;
+}
+void launch_leaf_far_count(int n_leaves, const int32_t* leaves, const int32_t* parent,
+                           const int64_t* node_cnt, int64_t* leaf_cnt, hipStream_t s) {
+  hipLaunchKernelGGL(leaf_far_count_kernel, dim3((n_leaves + WG - 1) / WG), dim3(WG), 0, s,
+                     n_leaves, leaves, parent, node_cnt, leaf_cnt);
+  HMX_LAUNCHED();
+}
+__global__ void leaf_far_fill_kernel(int n_leaves, const int32_t* __restrict__ leaves,
+                                     const int32_t* __restrict__ parent,
+                                     const int64_t* __restrict__ node_cnt,
+                                     const int32_t* __restrict__ node_first,
+                                     const int64_t* __restrict__ leaf_ptr, int32_t* __restrict__ list) {
+  int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= n_leaves) return;
+  int64_t q = leaf_ptr[i];
+  for (int a = leaves[i]; a >= 0; a = parent[a]) {
+    int64_t c = node_cnt[a];
+    for (int64_t j = 0; j < c; ++j) list[q++] = node_first[a] + (int32_t)j;
+  }
+}
+void launch_leaf_far_fill(int n_leaves, const int32_t* leaves, const int32_t* parent,
+                          const int64_t* node_cnt, const int32_t* node_first,
+                          const int64_t* leaf_ptr, int32_t* list, hipStream_t s) {
+  hipLaunchKernelGGL(leaf_far_fill_kernel, dim3((n_leaves + WG - 1) / WG), dim3(WG), 0, s,
+                     n_leaves, leaves, parent, node_cnt, node_first, leaf_ptr, list);
+  HMX_LAUNCHED();
+}
+
+}  // namespace hmx

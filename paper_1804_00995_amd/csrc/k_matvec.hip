@@ -1,0 +1,255 @@
+// k_matvec.hip -- the operator product y = K x.
+//
+// H-matrix product (row-leaf ownership; no floating-point atomics, fixed summation order):
+//   1. gather     xp[p] = x[perm[p]]                           (cluster order)
+//   2. far_vt     t_b = V_b^T xp[s_b] for every far block        (one workgroup per block)
+//   3. leaf_apply for each leaf l:
+//                 y_l = sum_{near b, row l} K_b xp[s_b] + sum_{far b, row node contains l}
+//                       U_b[rows of l] t_b, written to y[perm[.]] (scatter fused)
+// A far block stored dense is applied as U = K_b with t_b = xp[s_b].
+//
+// Dense product (operator built without a tolerance): every entry evaluated on the fly,
+//   y_i = sum_l G(x_i, x_l) w_l x_l, as a 2-D grid of (64-row tile, 256-source chunk) partial
+// sums, reduced over chunks in a fixed order.
+#include "hmx_dev.h"
+#include "hmx_host.h"
+
+namespace hmx {
+
+template <class T>
+__global__ void gather_kernel(const T* __restrict__ x, const int32_t* __restrict__ perm,
+                              T* __restrict__ xp, int64_t M) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < M) xp[i] = x[perm[i]];
+}
+
+template <class T>
+void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, hipStream_t s) {
+  hipLaunchKernelGGL(gather_kernel<T>, dim3((unsigned)((M + WG - 1) / WG)), dim3(WG), 0, s, x, perm,
+                     xp, M);
+  HMX_LAUNCHED();
+}
+
+__device__ __forceinline__ double2 wave_sum2(double2 v) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  return v;
+}
+__device__ __forceinline__ float2 wave_sum2(float2 v) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  return v;
+}
+
+// t_b[l] = sum_j V_b[j, l] xp[s_b + j]; wave w handles columns l = w, w + 4, ...
+template <class T>
+__global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ rec,
+                                                    const T* __restrict__ pool,
+                                                    const T* __restrict__ xp, T* __restrict__ t) {
+  const FarRec f = rec[blockIdx.x];
+  T* tb = t + f.toff;
+  const T* xs = xp + f.sb;
+  if (f.dense) {
+    for (int j = threadIdx.x; j < f.n; j += WG) tb[j] = xs[j];
+    return;
+  }
+  const T* V = pool + f.voff;
+  const int n = f.n, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  int l = w;
+  for (; l + NWAVE < f.r; l += 2 * NWAVE) {
+    T a0 = czero<T>(), a1 = czero<T>();
+    const T* v0 = V + (int64_t)l * n;
+    const T* v1 = V + (int64_t)(l + NWAVE) * n;
+    for (int j = lane; j < n; j += WAVE) {
+      T xj = xs[j];
+      cfma(a0, v0[j], xj);
+      cfma(a1, v1[j], xj);
+    }
+    a0 = wave_sum2(a0);
+    a1 = wave_sum2(a1);
+    if (lane == 0) {
+      tb[l] = a0;
+      tb[l + NWAVE] = a1;
+    }
+  }
+  for (; l < f.r; l += NWAVE) {
+    T a0 = czero<T>();
+    const T* v0 = V + (int64_t)l * n;
+    for (int j = lane; j < n; j += WAVE) cfma(a0, v0[j], xs[j]);
+    a0 = wave_sum2(a0);
+    if (lane == 0) tb[l] = a0;
+  }
+}
+
+template <class T>
+void launch_far_vt(const FarRec* rec, int64_t nf, const T* pool, const T* xp, T* t, hipStream_t s) {
+  if (nf <= 0) return;
+  hipLaunchKernelGGL(far_vt_kernel<T>, dim3((unsigned)nf), dim3(WG), 0, s, rec, pool, xp, t);
+  HMX_LAUNCHED();
+}
+
+constexpr int MAX_LEAF_CHUNKS = 4;  // rows per leaf <= 4 * 64
+
+template <class T>
+__global__ void __launch_bounds__(WG) leaf_apply_kernel(
+    const int32_t* __restrict__ leaves, const int32_t* __restrict__ nbegin,
+    const int32_t* __restrict__ nend, const int64_t* __restrict__ near_ptr,
+    const int32_t* __restrict__ near_sb, const int32_t* __restrict__ near_n,
+    const int64_t* __restrict__ near_off, const T* __restrict__ near_pool,
+    const int64_t* __restrict__ far_ptr, const int32_t* __restrict__ far_list,
+    const FarRec* __restrict__ far, const T* __restrict__ far_pool, const T* __restrict__ tbuf,
+    const T* __restrict__ xp, const int32_t* __restrict__ perm, T* __restrict__ y) {
+  __shared__ T part[NWAVE][MAX_LEAF_CHUNKS * WAVE];
+  const int leaf = blockIdx.x;
+  const int node = leaves[leaf];
+  const int tb = nbegin[node], m = nend[node] - tb;
+  const int64_t n0 = near_ptr[leaf], nn = near_ptr[leaf + 1] - n0;
+  const int64_t f0 = far_ptr[leaf], nfar = far_ptr[leaf + 1] - f0;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int nch = (m + WAVE - 1) / WAVE;
+  T acc[MAX_LEAF_CHUNKS];
+#pragma unroll
+  for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) acc[c] = czero<T>();
+  for (int64_t it = w; it < nn + nfar; it += NWAVE) {
+    if (it < nn) {
+      const int64_t blk = n0 + it;
+      const int sb = near_sb[blk], n = near_n[blk];
+      const T* K = near_pool + near_off[blk];
+      const T* xs = xp + sb;
+#pragma unroll 4
+      for (int j = 0; j < n; ++j) {
+        const T xj = xs[j];
+        const T* col = K + (int64_t)j * m;
+#pragma unroll
+        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
+          int i = lane + c * WAVE;
+          if (c < nch && i < m) cfma(acc[c], col[i], xj);
+        }
+      }
+    } else {
+      const FarRec f = far[far_list[f0 + (it - nn)]];
+      const int o = tb - f.tb;
+      const T* U = far_pool + f.uoff + o;
+      const T* tt = tbuf + f.toff;
+#pragma unroll 4
+      for (int l = 0; l < f.r; ++l) {
+        const T tl = tt[l];
+        const T* col = U + (int64_t)l * f.m;
+#pragma unroll
+        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
+          int i = lane + c * WAVE;
+          if (c < nch && i < m) cfma(acc[c], col[i], tl);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) part[w][lane + c * WAVE] = acc[c];
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += WG) {
+    T s = part[0][i];
+#pragma unroll
+    for (int q = 1; q < NWAVE; ++q) {
+      s.x += part[q][i].x;
+      s.y += part[q][i].y;
+    }
+    y[perm[tb + i]] = s;
+  }
+}
+
+template <class T>
+void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegin,
+                       const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
+                       const int32_t* near_n, const int64_t* near_off, const T* near_pool,
+                       const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
+                       const T* far_pool, const T* tbuf, const T* xp, const int32_t* perm, T* y,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(leaf_apply_kernel<T>, dim3(n_leaves), dim3(WG), 0, s, leaves, nbegin, nend,
+                     near_ptr, near_sb, near_n, near_off, near_pool, far_ptr, far_list, far,
+                     far_pool, tbuf, xp, perm, y);
+  HMX_LAUNCHED();
+}
+
+// ------------------------------------------------------------------------- dense on the fly
+constexpr int DOTF_CHUNK = 256;  // sources per workgroup (64 per wavefront)
+
+int64_t dense_otf_partial_len(int64_t M) {
+  int64_t nch = (M + DOTF_CHUNK - 1) / DOTF_CHUNK;
+  return nch * M;
+}
+
+template <class T>
+__global__ void __launch_bounds__(WG) dense_otf_kernel(const double* __restrict__ X,
+                                                       const double* __restrict__ Y,
+                                                       const double* __restrict__ Z,
+                                                       const double* __restrict__ W, int64_t M,
+                                                       int kern, double k, const T* __restrict__ x,
+                                                       T* __restrict__ partial) {
+  __shared__ T part[NWAVE][WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int64_t i = (int64_t)blockIdx.x * WAVE + lane;
+  const int64_t j0 = (int64_t)blockIdx.y * DOTF_CHUNK + w * WAVE;
+  const int64_t j1 = min(j0 + WAVE, M);
+  T acc = czero<T>();
+  if (i < M) {
+    const double tx = X[i], ty = Y[i], tz = Z[i];
+    for (int64_t j = j0; j < j1; ++j) {
+      T g = eval_entry<T>(kern, k, tx, ty, tz, X[j], Y[j], Z[j], W[j]);
+      cfma(acc, g, x[j]);
+    }
+  }
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && i < M) {
+    T s = part[0][lane];
+#pragma unroll
+    for (int q = 1; q < NWAVE; ++q) {
+      s.x += part[q][lane].x;
+      s.y += part[q][lane].y;
+    }
+    partial[(int64_t)blockIdx.y * M + i] = s;
+  }
+}
+
+template <class T>
+__global__ void dense_reduce_kernel(const T* __restrict__ partial, int64_t nch, int64_t M,
+                                    T* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= M) return;
+  T s = partial[i];
+  for (int64_t c = 1; c < nch; ++c) {
+    T v = partial[c * M + i];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  y[i] = s;
+}
+
+template <class T>
+void launch_dense_otf(const double* X, const double* Y, const double* Z, const double* W,
+                      int64_t M, int kern, double k, const T* x, T* partial, T* y, hipStream_t s) {
+  if (M <= 0) return;
+  int64_t nrt = (M + WAVE - 1) / WAVE, nch = (M + DOTF_CHUNK - 1) / DOTF_CHUNK;
+  hipLaunchKernelGGL(dense_otf_kernel<T>, dim3((unsigned)nrt, (unsigned)nch), dim3(WG), 0, s, X, Y,
+                     Z, W, M, kern, k, x, partial);
+  HMX_LAUNCHED();
+  hipLaunchKernelGGL(dense_reduce_kernel<T>, dim3((unsigned)((M + WG - 1) / WG)), dim3(WG), 0, s,
+                     partial, nch, M, y);
+  HMX_LAUNCHED();
+}
+
+#define HMX_INST(T)                                                                              \
+  template void launch_gather<T>(const T*, const int32_t*, T*, int64_t, hipStream_t);            \
+  template void launch_far_vt<T>(const FarRec*, int64_t, const T*, const T*, T*, hipStream_t);   \
+  template void launch_leaf_apply<T>(int, const int32_t*, const int32_t*, const int32_t*,        \
+                                     const int64_t*, const int32_t*, const int32_t*,             \
+                                     const int64_t*, const T*, const int64_t*, const int32_t*,   \
+                                     const FarRec*, const T*, const T*, const T*,                \
+                                     const int32_t*, T*, hipStream_t);                           \
+  template void launch_dense_otf<T>(const double*, const double*, const double*, const double*,  \
+                                    int64_t, int, double, const T*, T*, T*, hipStream_t);
+HMX_INST(double2)
+HMX_INST(float2)
+#undef HMX_INST
+
+}  // namespace hmx

@@ -1,0 +1,198 @@
+// k_scan.hip -- device utilities used by the build: exclusive prefix sums, fills, and a
+// bitonic sort of unique 64-bit keys (keys are unique, so the resulting order is fully defined).
+#include "hmx_dev.h"
+#include "hmx_host.h"
+
+namespace hmx {
+
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = WG * SCAN_ITEMS;
+
+__device__ __forceinline__ long long block_excl_scan_ll(long long v, long long* s, long long* total) {
+  int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  long long x = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    long long y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == WAVE - 1) s[w] = x;
+  __syncthreads();
+  long long base = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < NWAVE; ++q) {
+    if (q < w) base += s[q];
+    tot += s[q];
+  }
+  *total = tot;
+  return base + x - v;
+}
+
+__global__ void __launch_bounds__(WG) scan_sums_kernel(const int64_t* __restrict__ in, int64_t n,
+                                                       int64_t* __restrict__ bsum) {
+  __shared__ long long s[NWAVE];
+  int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+  long long acc = 0;
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    int64_t i = base + (int64_t)q * WG + threadIdx.x;
+    if (i < n) acc += in[i];
+  }
+  long long tot;
+  block_excl_scan_ll(acc, s, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(WG) scan_offsets_kernel(int64_t* __restrict__ bsum, int64_t nb) {
+  __shared__ long long s[NWAVE];
+  long long run = 0;
+  for (int64_t c = 0; c < nb; c += WG) {
+    int64_t i = c + threadIdx.x;
+    long long v = i < nb ? bsum[i] : 0;
+    long long tot;
+    long long pre = block_excl_scan_ll(v, s, &tot);
+    if (i < nb) bsum[i] = run + pre;
+    run += tot;
+  }
+  if (threadIdx.x == 0) bsum[nb] = run;
+}
+
+__global__ void __launch_bounds__(WG) scan_apply_kernel(const int64_t* __restrict__ in, int64_t n,
+                                                        const int64_t* __restrict__ boff,
+                                                        int64_t nb, int64_t* __restrict__ out) {
+  __shared__ long long s[NWAVE];
+  int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  long long v[SCAN_ITEMS];
+  long long acc = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    int64_t i = base + q;
+    v[q] = i < n ? in[i] : 0;
+    acc += v[q];
+  }
+  long long tot;
+  long long pre = block_excl_scan_ll(acc, s, &tot) + boff[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    int64_t i = base + q;
+    if (i < n) out[i] = pre;
+    pre += v[q];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = boff[nb];
+}
+
+void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n == 0) {
+    fill_i64(out, 0, 1, s);
+    return;
+  }
+  int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  DevBuf<int64_t> bsum(nb + 1);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(WG), 0, s, in, n, bsum.p);
+  HMX_LAUNCHED();
+  hipLaunchKernelGGL(scan_offsets_kernel, dim3(1), dim3(WG), 0, s, bsum.p, nb);
+  HMX_LAUNCHED();
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(WG), 0, s, in, n, bsum.p, nb, out);
+  HMX_LAUNCHED();
+  HMX_HIP(hipStreamSynchronize(s));  // bsum is freed on return
+}
+
+template <class T>
+__global__ void fill_kernel(T* p, T v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <class T>
+static void fill_any(T* p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, p, v, n);
+  HMX_LAUNCHED();
+}
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) { fill_any(p, v, n, s); }
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s) { fill_any(p, v, n, s); }
+void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) { fill_any(p, v, n, s); }
+
+__global__ void iota_kernel(int32_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+void iota_i32(int32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, p, n);
+  HMX_LAUNCHED();
+}
+
+// One compare-exchange stage of a bitonic sorting network over n = 2^p elements (ascending).
+__global__ void bitonic_global_kernel(uint64_t* __restrict__ key, int32_t* __restrict__ val,
+                                      int64_t n, int64_t j, int64_t k) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  int64_t ixj = i ^ j;
+  if (ixj <= i) return;
+  bool asc = (i & k) == 0;
+  uint64_t a = key[i], b = key[ixj];
+  if ((a > b) == asc) {
+    key[i] = b;
+    key[ixj] = a;
+    int32_t t = val[i];
+    val[i] = val[ixj];
+    val[ixj] = t;
+  }
+}
+
+// All stages with j < LOCAL of one k, inside LDS tiles of 2 * LOCAL... (tile = LOCALN elements).
+constexpr int LOCALN = 2048;
+__global__ void __launch_bounds__(WG) bitonic_local_kernel(uint64_t* __restrict__ key,
+                                                           int32_t* __restrict__ val, int64_t n,
+                                                           int64_t k, int64_t jstart) {
+  __shared__ uint64_t sk[LOCALN];
+  __shared__ int32_t sv[LOCALN];
+  int64_t base = (int64_t)blockIdx.x * LOCALN;
+  for (int t = threadIdx.x; t < LOCALN; t += WG) {
+    sk[t] = key[base + t];
+    sv[t] = val[base + t];
+  }
+  __syncthreads();
+  for (int64_t j = jstart; j > 0; j >>= 1) {
+    for (int t = threadIdx.x; t < LOCALN; t += WG) {
+      int ixj = t ^ (int)j;
+      if (ixj > t) {
+        bool asc = ((base + t) & k) == 0;
+        uint64_t a = sk[t], b = sk[ixj];
+        if ((a > b) == asc) {
+          sk[t] = b;
+          sk[ixj] = a;
+          int32_t tv = sv[t];
+          sv[t] = sv[ixj];
+          sv[ixj] = tv;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < LOCALN; t += WG) {
+    key[base + t] = sk[t];
+    val[base + t] = sv[t];
+  }
+}
+
+void sort_u64_pairs(uint64_t* key, int32_t* val, int64_t n, hipStream_t s) {
+  if (n <= 1) return;
+  unsigned g = (unsigned)((n + WG - 1) / WG);
+  for (int64_t k = 2; k <= n; k <<= 1) {
+    int64_t j = k >> 1;
+    for (; j > 0; j >>= 1) {
+      if (n >= LOCALN && j < LOCALN) {
+        hipLaunchKernelGGL(bitonic_local_kernel, dim3((unsigned)(n / LOCALN)), dim3(WG), 0, s, key,
+                           val, n, k, j);
+        HMX_LAUNCHED();
+        break;
+      }
+      hipLaunchKernelGGL(bitonic_global_kernel, dim3(g), dim3(WG), 0, s, key, val, n, j, k);
+      HMX_LAUNCHED();
+    }
+  }
+}
+
+}  // namespace hmx

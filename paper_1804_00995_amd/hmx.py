@@ -1,0 +1,239 @@
+"""Thin ctypes binding of libhmx (include/hmx.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every step of the operator runs in the
+HIP kernels of libhmx.so.  Importing this module loads the library and raises ImportError when
+it has not been built (``python -m paper_1804_00995_amd.build``): there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+# torch ships the HIP runtime it was built with; loading it first makes libhmx.so resolve its
+# libamdhip64.so.7 dependency to that same runtime, so device pointers and streams are shared.
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmx.so")
+
+LAPLACE, HELMHOLTZ, TEST_POLY2 = 0, 1, 99
+FP64, FP32_MIXED = 0, 1
+RANK_ADAPTIVE, RANK_LEARNED = 0, 1
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1804_00995_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_int32),
+        ("tol", C.c_double),
+        ("leaf_size", C.c_int32),
+        ("eta", C.c_double),
+        ("precision", C.c_int32),
+        ("rank_model", C.c_int32),
+        ("initial_rank", C.c_int32),
+        ("force_pred_scale", C.c_double),
+        ("force_rank_cap", C.c_int32),
+        ("pool_limit_bytes", C.c_int64),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "n_points", "n_nodes", "n_leaves", "n_near", "n_far", "near_entries", "far_entries",
+        "dense_far", "dense_far_entries", "max_rank", "sum_rank", "overflow_blocks", "bytes")] + [
+        ("precision", C.c_int32), ("is_dense", C.c_int32)] + [
+        (n, C.c_double) for n in ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms", "t_total_ms")] + [
+        ("kernel_evals", C.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_P, _i64, _i32, _f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+_sig = {
+    "hmx_params_default": [C.POINTER(Params)],
+    "hmx_quad_points": [_P, _i64, _P, _i64, _P, _P, _i32, _P, _P],
+    "hmx_build": [_P, _i64, _P, _i64, _P, _P, _i32, _i32, _f64, C.POINTER(Params), _P, C.POINTER(_P)],
+    "hmx_build_points": [_P, _i64, _i32, _f64, C.POINTER(Params), _P, C.POINTER(_P)],
+    "hmx_matvec": [_P, _P, _P, _P],
+    "hmx_info": [_P, C.POINTER(Info)],
+    "hmx_export_tree": [_P, _P, _P, _P, _P, _P, _P, _P],
+    "hmx_export_blocks": [_P, _P, _P, _P],
+    "hmx_export_far": [_P, _i64, _P, _P, _P],
+}
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.hmx_destroy.argtypes = [_P]
+_lib.hmx_destroy.restype = None
+_lib.hmx_last_error.argtypes = []
+_lib.hmx_last_error.restype = C.c_char_p
+
+EXPORTED = sorted(list(_sig) + ["hmx_destroy", "hmx_last_error"])
+
+
+class HmxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hmx error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise HmxError(rc, _lib.hmx_last_error().decode())
+
+
+def params(**kw) -> Params:
+    """Default parameters with keyword overrides (tol, leaf_size, eta, precision, ...)."""
+    p = Params()
+    _check(_lib.hmx_params_default(C.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host_rule(bary, w):
+    bary = np.ascontiguousarray(bary, np.float64).reshape(-1, 3)
+    w = np.ascontiguousarray(w, np.float64).reshape(-1)
+    if bary.shape[0] != w.shape[0]:
+        raise ValueError("rule barycentrics and weights differ in length")
+    return bary, w
+
+
+def quad_points(vtx, tri, bary, w, stream=None):
+    """Quadrature points and weights on the device: returns a (4, M) float64 tensor X, Y, Z, W."""
+    import torch
+    bary, w = _host_rule(bary, w)
+    nq = bary.shape[0]
+    M = tri.shape[0] * nq
+    out = torch.empty((4, M), dtype=torch.float64, device=vtx.device)
+    _check(_lib.hmx_quad_points(_dev(vtx, torch.float64, "vtx"), vtx.shape[0],
+                                _dev(tri, torch.int32, "tri"), tri.shape[0],
+                                bary.ctypes.data_as(_P), w.ctypes.data_as(_P), nq,
+                                C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+class Operator:
+    """A built operator K = G W_y (dense or H-matrix), applied with `matvec` or `@`."""
+
+    def __init__(self, handle, precision):
+        self._h = handle
+        self.precision = precision
+        self.info = self._info()
+        self.M = self.info["n_points"]
+
+    @property
+    def cdtype(self):
+        import torch
+        return torch.complex128 if self.precision == FP64 else torch.complex64
+
+    def _info(self):
+        i = Info()
+        _check(_lib.hmx_info(self._h, C.byref(i)))
+        return i.as_dict()
+
+    def matvec(self, x, y=None, stream=None):
+        import torch
+        if x.shape != (self.M,):
+            raise ValueError(f"x must have shape ({self.M},)")
+        if y is None:
+            y = torch.empty_like(x)
+        _check(_lib.hmx_matvec(self._h, _dev(x, self.cdtype, "x"), _dev(y, self.cdtype, "y"),
+                               _stream_ptr(stream)))
+        return y
+
+    def __matmul__(self, x):
+        return self.matvec(x)
+
+    def export_tree(self):
+        n = self.info["n_nodes"]
+        perm = np.empty(self.M, np.int32)
+        b, e = np.empty(n, np.int64), np.empty(n, np.int64)
+        lev, c0, c1 = (np.empty(n, np.int32) for _ in range(3))
+        box = np.empty((n, 6))
+        _check(_lib.hmx_export_tree(self._h, *(a.ctypes.data_as(_P) for a in (perm, b, e, lev, c0, c1, box))))
+        return {"perm": perm, "begin": b, "end": e, "level": lev, "child0": c0, "child1": c1, "box": box}
+
+    def export_blocks(self):
+        nn, nf = self.info["n_near"], self.info["n_far"]
+        nearR = np.empty((max(nn, 1), 4), np.int64)
+        farR = np.empty((max(nf, 1), 4), np.int64)
+        ranks = np.empty(max(nf, 1), np.int32)
+        _check(_lib.hmx_export_blocks(self._h, nearR.ctypes.data_as(_P), farR.ctypes.data_as(_P),
+                                      ranks.ctypes.data_as(_P)))
+        return nearR[:nn], farR[:nf], ranks[:nf]
+
+    def export_far(self, b, m, n):
+        cdt = np.complex128 if self.precision == FP64 else np.complex64
+        # a rank never exceeds min(m, n); a dense far block fills U with m x n entries
+        U = np.empty(max(m * n, 1), cdt)
+        V = np.empty(max(m * n, 1), cdt)
+        r = C.c_int32(0)
+        _check(_lib.hmx_export_far(self._h, b, U.ctypes.data_as(_P), V.ctypes.data_as(_P), C.byref(r)))
+        if r.value < 0:
+            return U[:m * n].reshape(n, m).T.copy(), None
+        k = r.value
+        return U[:m * k].reshape(k, m).T.copy(), V[:n * k].reshape(k, n).T.copy()
+
+    def close(self):
+        if self._h:
+            _lib.hmx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build(vtx, tri, bary, w, kern=HELMHOLTZ, k=0.0, prm: Params | None = None, stream=None) -> Operator:
+    """Operator of a triangle mesh (vtx float64 (nv,3), tri int32 (nt,3) device tensors)."""
+    import torch
+    bary, w = _host_rule(bary, w)
+    prm = prm or params()
+    h = C.c_void_p()
+    _check(_lib.hmx_build(_dev(vtx, torch.float64, "vtx"), vtx.shape[0], _dev(tri, torch.int32, "tri"),
+                          tri.shape[0], bary.ctypes.data_as(_P), w.ctypes.data_as(_P), bary.shape[0],
+                          kern, float(k), C.byref(prm), _stream_ptr(stream), C.byref(h)))
+    return Operator(h, prm.precision)
+
+
+def build_points(xyzw, kern=HELMHOLTZ, k=0.0, prm: Params | None = None, stream=None) -> Operator:
+    """Operator from points and weights: xyzw float64 (4, M) device tensor (X, Y, Z, W)."""
+    import torch
+    prm = prm or params()
+    h = C.c_void_p()
+    _check(_lib.hmx_build_points(_dev(xyzw, torch.float64, "xyzw"), xyzw.shape[1], kern, float(k),
+                                 C.byref(prm), _stream_ptr(stream), C.byref(h)))
+    return Operator(h, prm.precision)

@@ -1,0 +1,79 @@
+"""The C ABI: libhmx.so loads, exports every entry point declared in include/hmx.h, and rejects
+invalid arguments on the host before any device work (no GPU needed for these calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmx.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hmx_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def hmx():
+    from paper_1804_00995_amd import hmx as H
+    return H
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared()
+    for n in ["hmx_build", "hmx_build_points", "hmx_matvec", "hmx_quad_points", "hmx_info",
+              "hmx_destroy", "hmx_last_error", "hmx_params_default"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(hmx):
+    lib = C.CDLL(hmx.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(hmx.EXPORTED) == sorted(n for n in _declared())
+
+
+def test_params_default(hmx):
+    p = hmx.params()
+    assert p.struct_size == C.sizeof(hmx.Params)
+    assert p.tol == 1e-3 and p.leaf_size == 64 and p.eta == 1.5
+    assert p.precision == hmx.FP64 and p.rank_model == hmx.RANK_ADAPTIVE
+    assert p.initial_rank >= 1 and p.force_pred_scale == 1.0
+
+
+def test_null_arguments_rejected_on_host(hmx):
+    lib = hmx._lib
+    h = C.c_void_p()
+    p = hmx.params()
+    rc = lib.hmx_build(None, 3, None, 1, None, None, 3, 1, 5.0, C.byref(p), None, C.byref(h))
+    assert rc == hmx.EINVAL and b"null" in lib.hmx_last_error()
+    assert lib.hmx_matvec(None, None, None, None) == hmx.EINVAL
+    assert lib.hmx_info(None, None) == hmx.EINVAL
+    assert lib.hmx_params_default(None) == hmx.EINVAL
+    lib.hmx_destroy(None)  # NULL-safe
+
+
+def test_bad_params_rejected_on_host(hmx):
+    lib = hmx._lib
+    h = C.c_void_p()
+    fake = C.c_void_p(16)  # never dereferenced: parameters are checked first
+    bary = (C.c_double * 9)(2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3)
+    w = (C.c_double * 3)(1 / 3, 1 / 3, 1 / 3)
+    for kw, code in [({"leaf_size": 0}, hmx.EINVAL), ({"eta": -1.0}, hmx.EINVAL),
+                     ({"precision": 7}, hmx.EINVAL), ({"leaf_size": 300}, hmx.EUNSUPPORTED),
+                     ({"struct_size": 8}, hmx.EINVAL)]:
+        p = hmx.params(**kw)
+        rc = lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 1, 5.0, C.byref(p), None, C.byref(h))
+        assert rc == code, (kw, rc, lib.hmx_last_error())
+    p = hmx.params()
+    assert lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 1, -1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 42, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    badw = (C.c_double * 3)(0.3, 0.3, 0.3)
+    assert lib.hmx_build(fake, 3, fake, 1, bary, badw, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    badb = (C.c_double * 9)(1.2, -0.1, -0.1, 1 / 6, 2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3)
+    assert lib.hmx_build(fake, 3, fake, 1, badb, w, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build(fake, 3, fake, 1, bary, w, 0, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build(fake, 0, fake, 1, bary, w, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL

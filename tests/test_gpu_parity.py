@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the same seeded inputs.
+
+Bars: quadrature points bit-exact; cluster tree and block lists identical; dense product within
+1e-12 relative; H-matrix product within the ACA tolerance of the dense product (1e-3 at tol 1e-3,
+on all rows at small sizes and on seeded sampled rows at the 245 760-point size the bench times).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1804_00995_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    oracle.build(force=False)
+    from paper_1804_00995_amd import hmx
+    return hmx
+
+
+def mesh(level):
+    v, f = I.icosphere(level)
+    return v, f, torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+RULE = I.rule_3pt()
+
+
+def build(H, level, kern=1, k=5.0, **kw):
+    v, f, vd, fd = mesh(level)
+    op = H.build(vd, fd, *RULE, kern=kern, k=k, prm=H.params(**kw))
+    P, W = oracle.quad_points(v, f, *RULE)
+    return op, P, W
+
+
+def apply(op, x, dtype=torch.complex128):
+    xd = torch.from_numpy(x).to(dtype).cuda()
+    y = op.matvec(xd)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.complex128)
+
+
+# ------------------------------------------------------------------------------ quadrature
+@pytest.mark.parametrize("level", [0, 3])
+def test_quad_points_bit_exact(H, level):
+    v, f, vd, fd = mesh(level)
+    g = H.quad_points(vd, fd, *RULE).cpu().numpy()
+    P, W = oracle.quad_points(v, f, *RULE)
+    for d in range(3):
+        assert np.array_equal(g[d], P[:, d])
+    assert np.abs(g[3] - W).max() <= 4e-16 * W.max()
+
+
+def test_quad_points_rejects_bad_mesh(H):
+    v, f, vd, fd = mesh(1)
+    bad = fd.clone()
+    bad[3, 1] = v.shape[0] + 5
+    with pytest.raises(H.HmxError) as e:
+        H.quad_points(vd, bad, *RULE)
+    assert e.value.code == H.EINVAL
+    vbad = vd.clone()
+    vbad[2, 0] = float("nan")
+    with pytest.raises(H.HmxError) as e:
+        H.build(vbad, fd, *RULE, kern=1, k=1.0)
+    assert e.value.code == H.EINVAL
+
+
+# ------------------------------------------------------------------------------ dense (a0)
+@pytest.mark.parametrize("kern,k", [(1, 5.0), (0, 0.0), (1, 40.0)])
+def test_dense_matches_oracle(H, kern, k):
+    op, P, W = build(H, 3, kern=kern, k=k, tol=0.0)
+    assert op.info["is_dense"] == 1
+    x = I.complex_vector(P.shape[0], 0)
+    y = apply(op, x)
+    yr = oracle.dense_matvec(P, W, kern, k, x)
+    assert rel(y, yr) <= 1e-12
+
+
+def test_dense_fp32_mixed(H):
+    op, P, W = build(H, 3, kern=1, k=5.0, tol=0.0, precision=H.FP32_MIXED)
+    x = I.complex_vector(P.shape[0], 0)
+    y = apply(op, x, torch.complex64)
+    yr = oracle.dense_matvec(P, W, 1, 5.0, x)
+    assert rel(y, yr) <= 1e-5
+
+
+# ------------------------------------------------------------------------------ tree, blocks
+@pytest.mark.parametrize("level,leaf", [(2, 7), (3, 16), (3, 64), (4, 64), (4, 128)])
+def test_tree_and_blocks_identical(H, level, leaf):
+    op, P, W = build(H, level, leaf_size=leaf, tol=1e-3)
+    Ho = oracle.HMatrix(P, W, 1, 5.0, leaf=leaf, tol=1e-3)
+    T, To = op.export_tree(), Ho.tree()
+    assert np.array_equal(T["perm"], To["perm"])
+    g = {(b, e): (lv, tuple(bx)) for b, e, lv, bx in zip(T["begin"], T["end"], T["level"], T["box"])}
+    o = {(b, e): (lv, tuple(bx)) for b, e, lv, bx in zip(To["begin"], To["end"], To["level"], To["box"])}
+    assert g == o
+    nearG, farG, _ = op.export_blocks()
+    nearO, farO, _ = Ho.blocks()
+    assert np.array_equal(nearG, nearO)
+    assert np.array_equal(farG, farO)
+    assert op.info["n_leaves"] == int((To["child0"] < 0).sum())
+
+
+# ------------------------------------------------------------------------------ H product (a5-a7)
+@pytest.mark.parametrize("level,kern,k", [(3, 1, 5.0), (3, 0, 0.0), (4, 1, 10.0), (4, 1, 25.0)])
+def test_hmatvec_within_tolerance_of_dense(H, level, kern, k):
+    op, P, W = build(H, level, kern=kern, k=k, tol=1e-3)
+    x = I.complex_vector(P.shape[0], 0)
+    y = apply(op, x)
+    yr = oracle.dense_matvec(P, W, kern, k, x)
+    assert rel(y, yr) <= 1e-3
+    assert op.info["n_far"] > 0 and op.info["far_entries"] > 0
+
+
+def test_hmatvec_tight_tolerance(H):
+    op, P, W = build(H, 3, kern=1, k=8.0, tol=1e-9, leaf_size=32)
+    x = I.complex_vector(P.shape[0], 3)
+    assert rel(apply(op, x), oracle.dense_matvec(P, W, 1, 8.0, x)) <= 1e-7
+
+
+def test_near_field_only_equals_dense(H):
+    # 60 points in one leaf: the whole operator is one near block
+    op, P, W = build(H, 0, kern=1, k=3.0, tol=1e-3)
+    assert op.info["n_far"] == 0 and op.info["n_near"] == 1
+    x = I.complex_vector(P.shape[0], 1)
+    assert rel(apply(op, x), oracle.dense_matvec(P, W, 1, 3.0, x)) <= 1e-13
+
+
+def test_poly2_exact_rank(H):
+    op, P, W = build(H, 2, kern=H.TEST_POLY2, k=0.0, tol=1e-12, leaf_size=16)
+    x = I.complex_vector(P.shape[0], 2)
+    y = apply(op, x)
+    yr = oracle.dense_matvec(P, W, oracle.POLY2, 0.0, x)
+    assert rel(y, yr) <= 1e-11
+    _, _, ranks = op.export_blocks()
+    assert ranks.max() <= 11
+
+
+@pytest.mark.parametrize("k", [5.0, 20.0])
+def test_aca_blocks_error_bounds(H, k):
+    op, P, W = build(H, 3, kern=1, k=k, tol=1e-3)
+    perm = op.export_tree()["perm"]
+    _, farR, ranks = op.export_blocks()
+    sizes = (farR[:, 1] - farR[:, 0]) * (farR[:, 3] - farR[:, 2])
+    for b in np.argsort(-sizes)[:10]:
+        tb, te, sb, se = (int(v) for v in farR[b])
+        m, n = te - tb, se - sb
+        rows, cols = perm[tb:te], perm[sb:se]
+        A = oracle.green(1, k, np.repeat(P[rows], n, 0), np.tile(P[cols], (m, 1))).reshape(m, n) * W[cols][None, :]
+        U, V = op.export_far(int(b), m, n)
+        assert V is not None
+        r = U.shape[1]
+        err = np.linalg.norm(A - U @ V.T)
+        s = np.linalg.svd(A, compute_uv=False)
+        assert err >= np.sqrt((s[r:] ** 2).sum()) * (1 - 1e-9)
+        assert err <= 10 * 1e-3 * np.linalg.norm(A)
+
+
+def test_ranks_close_to_oracle(H):
+    op, P, W = build(H, 4, kern=1, k=15.0, tol=1e-3)
+    Ho = oracle.HMatrix(P, W, 1, 15.0, leaf=64, tol=1e-3)
+    _, _, rg = op.export_blocks()
+    _, _, ro = Ho.blocks()
+    assert rg.shape == ro.shape
+    assert abs(int(rg.sum()) - int(ro.sum())) <= 0.02 * ro.sum()
+    assert (np.abs(rg.astype(int) - ro.astype(int)) <= 2).mean() > 0.98
+
+
+def test_deterministic(H):
+    op1, P, W = build(H, 4, kern=1, k=12.0, tol=1e-3)
+    op2, _, _ = build(H, 4, kern=1, k=12.0, tol=1e-3)
+    x = I.complex_vector(P.shape[0], 5)
+    y1, y1b, y2 = apply(op1, x), apply(op1, x), apply(op2, x)
+    assert np.array_equal(y1, y1b)
+    assert np.array_equal(y1, y2)
+
+
+def test_forced_dense_fallback(H):
+    # a rank cap of 2 forces ACA past its cap on most blocks: those are stored exactly
+    op, P, W = build(H, 3, kern=1, k=5.0, tol=1e-3, force_rank_cap=2)
+    assert op.info["dense_far"] > 0
+    x = I.complex_vector(P.shape[0], 0)
+    assert rel(apply(op, x), oracle.dense_matvec(P, W, 1, 5.0, x)) <= 1e-3
+
+
+def test_overflow_continuation_identical(H):
+    # a first rank slot of 1 makes nearly every block continue in a larger slot; the factors
+    # must be those of a single uninterrupted run
+    opa, P, W = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=1)
+    opb, _, _ = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=64)
+    assert opa.info["overflow_blocks"] > 0
+    x = I.complex_vector(P.shape[0], 4)
+    assert np.array_equal(apply(opa, x), apply(opb, x))
+
+
+def test_full_size_sampled_rows(H):
+    """245 760 points (L6 sphere), k = 40, leaf 64, tol 1e-3: the configuration the bench times."""
+    op, P, W = build(H, 6, kern=1, k=40.0, tol=1e-3)
+    x = I.complex_vector(P.shape[0], 0)
+    y = apply(op, x)
+    rows = np.sort(np.random.default_rng(123).choice(P.shape[0], 384, replace=False))
+    yr = oracle.dense_rows(P, W, 1, 40.0, x, rows)
+    assert rel(y[rows], yr) <= 1e-3
