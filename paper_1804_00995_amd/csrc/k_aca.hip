@@ -96,6 +96,7 @@ __device__ void aca_block(const FarDesc& d, int b, const double* __restrict__ X,
     const double2 pd = to_d2(R[bj]);
     const double den = pd.x * pd.x + pd.y * pd.y;
     const T inv = from_d2<T>(make_double2(pd.x / den, -pd.y / den));
+    __syncthreads();  // every thread has read the pivot before it is scaled in place
     if (tid == 0) {
       rused[ip] = 1;
       cused[bj] = 1;
