@@ -161,6 +161,11 @@ void hmx_destroy(hmx_op* op);
 /* Message of the last failed call on this thread ("" when none). */
 const char* hmx_last_error(void);
 
+/* The library keeps freed device blocks for reuse by later builds (a caching allocator, so that
+ * repeated builds do not map and unmap memory); this returns the cached blocks of the current
+ * device to the HIP runtime.  Live operators are not affected. */
+void hmx_release_cache(void);
+
 #ifdef __cplusplus
 }
 #endif

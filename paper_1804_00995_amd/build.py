@@ -20,6 +20,8 @@ ARCH = os.environ.get("HMX_ARCH", "gfx950")
 # (source, exact) -- exact units are compiled with -ffp-contract=off
 UNITS = [
     ("hmx_api.hip", False),
+    ("hmx_build.hip", False),
+    ("hmx_mem.hip", False),
     ("k_quad.hip", True),
     ("k_scan.hip", False),
     ("k_tree.hip", True),

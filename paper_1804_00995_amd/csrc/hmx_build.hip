@@ -1,0 +1,564 @@
+// hmx_build.hip -- build pipeline of an H-matrix operator on the device: cluster tree, block
+// tree, near-field blocks, ACA of the far blocks, and the index structures of the product.  The
+// host sizes buffers, launches the kernels of the k_*.hip units and moves small index arrays;
+// all arithmetic of the operator runs in those kernels.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "hmx_host.h"
+
+namespace hmx {
+namespace {
+
+int64_t next_pow2(int64_t n) {
+  int64_t p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Grow a device array to `cap` entries keeping the first `keep`.
+template <class T>
+void grow(DevBuf<T>& b, size_t cap, size_t keep, hipStream_t s) {
+  if (b.n >= cap) return;
+  DevBuf<T> nb(cap);
+  if (keep && b.p) HMX_HIP(hipMemcpyAsync(nb.p, b.p, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
+  HMX_HIP(hipStreamSynchronize(s));
+  b = std::move(nb);
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    HMX_HIP(hipEventCreate(&a));
+    HMX_HIP(hipEventCreate(&b));
+    HMX_HIP(hipEventRecord(a, s));
+  }
+  double stop() {
+    HMX_HIP(hipEventRecord(b, s));
+    HMX_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    HMX_HIP(hipEventElapsedTime(&ms, a, b));
+    HMX_HIP(hipEventRecord(a, s));
+    return ms;
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// ------------------------------------------------------------------------------ cluster tree
+void build_tree(hmx_op* op, hipStream_t s) {
+  const int64_t M = op->M;
+  const int leaf = op->p.leaf_size;
+  DevBuf<double> bx[2][4];
+  DevBuf<int32_t> bp[2];
+  for (int q = 0; q < 2; ++q) {
+    for (int c = 0; c < 4; ++c) bx[q][c].alloc(M);
+    bp[q].alloc(M);
+  }
+  // level 0 reads the points in their original order
+  HMX_HIP(hipMemcpyAsync(bx[0][0].p, op->X.p, M * 8, hipMemcpyDeviceToDevice, s));
+  HMX_HIP(hipMemcpyAsync(bx[0][1].p, op->Y.p, M * 8, hipMemcpyDeviceToDevice, s));
+  HMX_HIP(hipMemcpyAsync(bx[0][2].p, op->Z.p, M * 8, hipMemcpyDeviceToDevice, s));
+  HMX_HIP(hipMemcpyAsync(bx[0][3].p, op->W.p, M * 8, hipMemcpyDeviceToDevice, s));
+  iota_i32(bp[0].p, M, s);
+
+  size_t cap = (size_t)std::max<int64_t>(256, 4 * (M / leaf) + 64);
+  DevBuf<int32_t> nbegin(cap), nend(cap), level(cap), child0(cap), child1(cap), parent(cap),
+      nleft(cap);
+  DevBuf<double> box(6 * cap);
+  DevBuf<int> d_next(1);
+  {
+    int32_t root[4] = {0, (int32_t)M, 0, -1};
+    HMX_HIP(hipMemcpyAsync(nbegin.p, &root[0], 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(nend.p, &root[1], 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(level.p, &root[2], 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(parent.p, &root[3], 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipStreamSynchronize(s));
+  }
+  int first = 0, count = 1, total = 1, cur = 0, depth = 0;
+  while (count > 0) {
+    size_t need = (size_t)total + 2 * (size_t)count;
+    if (need > cap) {
+      size_t nc = std::max(need, 2 * cap);
+      grow(nbegin, nc, total, s);
+      grow(nend, nc, total, s);
+      grow(level, nc, total, s);
+      grow(child0, nc, total, s);
+      grow(child1, nc, total, s);
+      grow(parent, nc, total, s);
+      grow(nleft, nc, total, s);
+      grow(box, 6 * nc, 6 * (size_t)total, s);
+      cap = nc;
+    }
+    const int nx = 1 - cur;
+    launch_tree_level(first, count, nbegin.p, nend.p, leaf, bx[cur][0].p, bx[cur][1].p,
+                      bx[cur][2].p, bx[cur][3].p, bp[cur].p, bx[nx][0].p, bx[nx][1].p,
+                      bx[nx][2].p, bx[nx][3].p, bp[nx].p, box.p, nleft.p, s);
+    launch_tree_children(first, count, total, nleft.p, nbegin.p, nend.p, level.p, child0.p,
+                         child1.p, parent.p, d_next.p, s);
+    int next = read1(d_next.p, s);
+    first = total;
+    total += next;
+    count = next;
+    cur = nx;
+    depth++;
+    HMX_REQUIRE(depth < 63, HMX_EUNSUPPORTED, "cluster tree deeper than 62 levels");
+  }
+  // every leaf range was written to both buffers at the level where it became a leaf
+  op->X = std::move(bx[cur][0]);
+  op->Y = std::move(bx[cur][1]);
+  op->Z = std::move(bx[cur][2]);
+  op->W = std::move(bx[cur][3]);
+  op->perm = std::move(bp[cur]);
+  op->n_nodes = total;
+  op->depth = depth;
+  op->nbegin = std::move(nbegin);
+  op->nend = std::move(nend);
+  op->nlevel = std::move(level);
+  op->child0 = std::move(child0);
+  op->child1 = std::move(child1);
+  op->parent = std::move(parent);
+  op->box = std::move(box);
+
+  // leaves in cluster order
+  DevBuf<int64_t> flag(M), scan(M + 1);
+  DevBuf<int32_t> start(M);
+  fill_i64(flag.p, 0, M, s);
+  launch_leaf_marks(total, op->nbegin.p, op->child0.p, flag.p, s);
+  launch_start_node(total, op->nbegin.p, op->child0.p, start.p, s);
+  scan_excl_i64(flag.p, scan.p, M, s);
+  op->n_leaves = (int)read1(scan.p + M, s);
+  op->leaves.alloc(op->n_leaves);
+  launch_leaf_list(M, flag.p, scan.p, start.p, op->leaves.p, s);
+  op->leaf_of_node.alloc(total);
+  fill_i32(op->leaf_of_node.p, -1, total, s);
+  launch_leaf_index(op->n_leaves, op->leaves.p, op->leaf_of_node.p, s);
+  HMX_HIP(hipStreamSynchronize(s));
+  // the product holds one leaf's rows in a workgroup (at most 4 x 64); a leaf can exceed the
+  // leaf size only when its points coincide
+  std::vector<int32_t> hb, he, hc;
+  to_host(hb, op->nbegin.p, total, s);
+  to_host(he, op->nend.p, total, s);
+  to_host(hc, op->child0.p, total, s);
+  for (int i = 0; i < total; ++i)
+    HMX_REQUIRE(hc[i] >= 0 || he[i] - hb[i] <= 256, HMX_EUNSUPPORTED,
+                "a leaf holds more than 256 points (coincident points)");
+}
+
+// Sort a device list of (t, s) pairs into the lexicographic order of their node ranges.
+void sort_pairs(hmx_op* op, DevBuf<int2>& L, int64_t n, hipStream_t s) {
+  if (n <= 1) return;
+  int64_t np = next_pow2(n);
+  DevBuf<uint64_t> key(np);
+  DevBuf<int32_t> val(np);
+  launch_pair_keys(L.p, n, np, op->nbegin.p, op->nlevel.p, key.p, val.p, s);
+  sort_u64_pairs(key.p, val.p, np, s);
+  DevBuf<int2> out(n);
+  launch_pair_gather(L.p, val.p, n, out.p, s);
+  HMX_HIP(hipStreamSynchronize(s));
+  L = std::move(out);
+}
+
+// ------------------------------------------------------------------------------ block tree
+void build_blocks(hmx_op* op, hipStream_t s) {
+  const double eta2 = op->p.eta * op->p.eta;
+  size_t fcap = 1024, ncap = std::max<size_t>(1024, 64 * (size_t)op->n_leaves),
+         xcap = std::max<size_t>(1024, 64 * (size_t)op->n_leaves);
+  DevBuf<int2> front(fcap), next(fcap), nearL(ncap), farL(xcap);
+  DevBuf<int> cnt(3);  // next, near, far
+  fill_i32(cnt.p, 0, 3, s);
+  int2 root = make_int2(0, 0);
+  HMX_HIP(hipMemcpyAsync(front.p, &root, sizeof(int2), hipMemcpyHostToDevice, s));
+  int64_t nfront = 1, n_near = 0, n_far = 0;
+  while (nfront > 0) {
+    if ((size_t)(4 * nfront) > next.n) {
+      next.alloc(std::max<size_t>(4 * nfront, 2 * next.n));
+    }
+    if (nearL.n < (size_t)(n_near + nfront)) grow(nearL, 2 * (n_near + nfront), n_near, s);
+    if (farL.n < (size_t)(n_far + nfront)) grow(farL, 2 * (n_far + nfront), n_far, s);
+    fill_i32(cnt.p, 0, 1, s);
+    launch_block_level(front.p, (int)nfront, op->box.p, op->child0.p, op->child1.p, eta2, next.p,
+                       cnt.p, nearL.p, cnt.p + 1, farL.p, cnt.p + 2, s);
+    int c[3];
+    HMX_HIP(hipMemcpyAsync(c, cnt.p, sizeof(c), hipMemcpyDeviceToHost, s));
+    HMX_HIP(hipStreamSynchronize(s));
+    nfront = c[0];
+    n_near = c[1];
+    n_far = c[2];
+    std::swap(front, next);
+  }
+  op->n_near = n_near;
+  op->n_far = n_far;
+  sort_pairs(op, nearL, n_near, s);
+  sort_pairs(op, farL, n_far, s);
+  op->nearL = std::move(nearL);
+  op->farL = std::move(farL);
+}
+
+// ------------------------------------------------------------------------------ near field
+template <class T>
+void build_near(hmx_op* op, hipStream_t s) {
+  const int64_t nn = op->n_near;
+  const int nl = op->n_leaves;
+  op->near_tb.alloc(std::max<int64_t>(nn, 1));
+  op->near_m.alloc(std::max<int64_t>(nn, 1));
+  op->near_sb.alloc(std::max<int64_t>(nn, 1));
+  op->near_n.alloc(std::max<int64_t>(nn, 1));
+  DevBuf<int64_t> sizes(std::max<int64_t>(nn, 1)), lcnt(nl);
+  op->near_off.alloc(nn + 1);
+  op->near_ptr.alloc(nl + 1);
+  fill_i64(lcnt.p, 0, nl, s);
+  launch_pair_ranges(op->nearL.p, nn, op->nbegin.p, op->nend.p, op->near_tb.p, op->near_m.p,
+                     op->near_sb.p, op->near_n.p, s);
+  launch_near_prep(op->nearL.p, nn, op->nbegin.p, op->nend.p, op->leaf_of_node.p, sizes.p, lcnt.p, s);
+  scan_excl_i64(sizes.p, op->near_off.p, nn, s);
+  scan_excl_i64(lcnt.p, op->near_ptr.p, nl, s);
+  op->near_entries = read1(op->near_off.p + nn, s);
+  size_t bytes = (size_t)op->near_entries * sizeof(T);
+  if (op->p.pool_limit_bytes > 0 && (int64_t)bytes > op->p.pool_limit_bytes)
+    throw Error(HMX_ENOMEM, "near field exceeds pool_limit_bytes");
+  op->near_pool.alloc(std::max<size_t>(bytes, 1));
+  launch_assemble<T>(op->near_tb.p, op->near_m.p, op->near_sb.p, op->near_n.p, op->near_off.p, nn,
+                     op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern, op->k, (T*)op->near_pool.p, s);
+  HMX_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------------------ far field
+template <class T>
+void build_far(hmx_op* op, hipStream_t s) {
+  const int64_t nf = op->n_far;
+  const int nl = op->n_leaves;
+  const int64_t nf1 = std::max<int64_t>(nf, 1);
+  DevBuf<int32_t> ftb(nf1), fm(nf1), fsb(nf1), fn(nf1);
+  DevBuf<int64_t> node_cnt(op->n_nodes);
+  DevBuf<int32_t> node_first(op->n_nodes);
+  fill_i64(node_cnt.p, 0, op->n_nodes, s);
+  fill_i32(node_first.p, -1, op->n_nodes, s);
+  launch_far_prep(op->farL.p, nf, op->nbegin.p, op->nend.p, ftb.p, fm.p, fsb.p, fn.p, node_cnt.p,
+                  node_first.p, s);
+  std::vector<int32_t> htb, hm, hsb, hn;
+  to_host(htb, ftb.p, nf, s);
+  to_host(hm, fm.p, nf, s);
+  to_host(hsb, fsb.p, nf, s);
+  to_host(hn, fn.p, nf, s);
+
+  // descriptors: rank cap, first slot capacity (slots are taken from the device pool by the
+  // kernels: workgroup blocks at their start, wavefront blocks at their end, exactly sized)
+  std::vector<FarDesc> desc(nf);
+  std::vector<uint8_t> is_wave(nf);
+  int64_t flag_bytes = 0, sum_mn = 0;
+  for (int64_t b = 0; b < nf; ++b) {
+    FarDesc& d = desc[b];
+    d.tb = htb[b];
+    d.m = hm[b];
+    d.sb = hsb[b];
+    d.n = hn[b];
+    int64_t rc = ((int64_t)d.m * d.n) / ((int64_t)d.m + d.n);
+    rc = std::min<int64_t>(rc, ACA_COEF_MAX);
+    if (op->p.force_rank_cap > 0) rc = std::min<int64_t>(rc, op->p.force_rank_cap);
+    d.rcap = (int32_t)rc;
+    // first slot: initial_rank columns, more for large blocks (their ranks grow with size)
+    const int64_t mn = (int64_t)d.m + d.n;
+    const int64_t c0 = mn >= 2 * ACA_BIG ? 3 * (int64_t)op->p.initial_rank
+                       : mn >= ACA_BIG   ? 2 * (int64_t)op->p.initial_rank
+                                         : (int64_t)op->p.initial_rank;
+    d.cap = (int32_t)std::min<int64_t>(rc, c0);
+    d.U = d.V = nullptr;
+    d.foff = flag_bytes;
+    flag_bytes += d.m + d.n;
+    is_wave[b] = d.m <= ACA_WAVE_N && d.n <= ACA_WAVE_N;
+    // pool estimate: wavefront blocks take exactly their rank (<= 16, typically ~8); workgroup
+    // blocks their first slot plus one doubling
+    sum_mn += is_wave[b] ? 12 * mn : 2 * (int64_t)d.cap * mn;
+  }
+  // device pool for factor slots, within the free memory
+  size_t free_b = 0, total_b = 0;
+  HMX_HIP(hipMemGetInfo(&free_b, &total_b));
+  int64_t gcap = std::max<int64_t>(sum_mn, (int64_t)(64 << 20) / (int64_t)sizeof(T));
+  gcap = std::min<int64_t>(gcap, (int64_t)(0.6 * (double)free_b) / (int64_t)sizeof(T));
+  gcap = std::max<int64_t>(gcap, 1);
+  DevBuf<T> gpool(gcap);
+  DevBuf<uint8_t> flags(std::max<int64_t>(flag_bytes, 1));
+  DevBuf<FarDesc> d_desc(nf1);
+  DevBuf<int32_t> d_order(nf1), rank(nf1), ipiv(nf1), status(nf1);
+  DevBuf<double> norm2(nf1);
+  DevBuf<int> counter(3);
+  DevBuf<unsigned long long> gtop(1);
+  if (nf) HMX_HIP(hipMemcpyAsync(d_desc.p, desc.data(), nf * sizeof(FarDesc), hipMemcpyHostToDevice, s));
+  fill_i64((int64_t*)gtop.p, 0, 1, s);
+
+  // side streams for the block classes (default priority), joined back to `s`
+  hipStream_t s2_ = nullptr, s3_ = nullptr;
+  hipEvent_t ev_ready = nullptr, ev_d2 = nullptr, ev_d3 = nullptr;
+  struct StreamGuard {
+    hipStream_t* st[2];
+    hipEvent_t* ev[3];
+    ~StreamGuard() {
+      for (auto e : ev)
+        if (*e) (void)hipEventDestroy(*e);
+      for (auto q : st)
+        if (*q) (void)hipStreamDestroy(*q);
+    }
+  } guard{{&s2_, &s3_}, {&ev_ready, &ev_d2, &ev_d3}};
+  HMX_HIP(hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking));
+  HMX_HIP(hipStreamCreateWithFlags(&s3_, hipStreamNonBlocking));
+  HMX_HIP(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
+  HMX_HIP(hipEventCreateWithFlags(&ev_d2, hipEventDisableTiming));
+  HMX_HIP(hipEventCreateWithFlags(&ev_d3, hipEventDisableTiming));
+
+  // run ACA on a list of blocks, largest first within each class: m + n >= ACA_BIG in
+  // 512-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per wavefront (stream s3, fresh
+  // blocks only), the others in 256-thread workgroups (stream s)
+  auto run_aca = [&](const std::vector<int32_t>& list, int fresh) {
+    // each class ordered by decreasing floor(log2(m + n)) (bucket order, linear time)
+    std::vector<int32_t> bucket[3][32];
+    for (int32_t b : list) {
+      const FarDesc& d = desc[b];
+      const int64_t mn = (int64_t)d.m + d.n;
+      const int cls = mn >= ACA_BIG ? 0 : (fresh && is_wave[b]) ? 2 : 1;
+      bucket[cls][31 - std::min(31, 63 - __builtin_clzll((unsigned long long)mn))].push_back(b);
+    }
+    std::vector<int32_t> big, mid, small;
+    for (int q = 0; q < 32; ++q) {
+      big.insert(big.end(), bucket[0][q].begin(), bucket[0][q].end());
+      mid.insert(mid.end(), bucket[1][q].begin(), bucket[1][q].end());
+      small.insert(small.end(), bucket[2][q].begin(), bucket[2][q].end());
+    }
+    std::vector<int32_t> ord(big);
+    ord.insert(ord.end(), mid.begin(), mid.end());
+    ord.insert(ord.end(), small.begin(), small.end());
+    if (!ord.empty())
+      HMX_HIP(hipMemcpyAsync(d_order.p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s));
+    fill_i32(counter.p, 0, 3, s);
+    // HMX_ACA_SERIAL=1 runs the classes one after the other on `s` (same work; used to time
+    // each class on its own)
+    static const bool serial = [] {
+      const char* e = std::getenv("HMX_ACA_SERIAL");
+      return e && e[0] == '1';
+    }();
+    hipStream_t s2 = serial ? s : s2_;
+    hipStream_t s3 = serial ? s : s3_;
+    HMX_HIP(hipEventRecord(ev_ready, s));
+    HMX_HIP(hipStreamWaitEvent(s2, ev_ready, 0));
+    HMX_HIP(hipStreamWaitEvent(s3, ev_ready, 0));
+    launch_aca<T>(d_desc.p, d_order.p, (int)big.size(), counter.p, 1, op->X.p, op->Y.p, op->Z.p,
+                  op->W.p, op->kern, op->k, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
+                  fresh, gpool.p, gcap, gtop.p, s2);
+    launch_aca_wave<T>(d_desc.p, d_order.p + big.size() + mid.size(), (int)small.size(), op->X.p,
+                       op->Y.p, op->Z.p, op->W.p, op->kern, op->k, op->p.tol, flags.p, rank.p,
+                       ipiv.p, status.p, norm2.p, gpool.p, gcap, gtop.p, s3);
+    launch_aca<T>(d_desc.p, d_order.p + big.size(), (int)mid.size(), counter.p + 1, 0, op->X.p,
+                  op->Y.p, op->Z.p, op->W.p, op->kern, op->k, op->p.tol, flags.p, rank.p, ipiv.p,
+                  status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, s);
+    HMX_HIP(hipEventRecord(ev_d2, s2));
+    HMX_HIP(hipEventRecord(ev_d3, s3));
+    HMX_HIP(hipStreamWaitEvent(s, ev_d2, 0));
+    HMX_HIP(hipStreamWaitEvent(s, ev_d3, 0));
+    HMX_HIP(hipStreamSynchronize(s));
+  };
+  {
+    std::vector<int32_t> all(nf);
+    std::iota(all.begin(), all.end(), 0);
+    run_aca(all, 1);
+  }
+  std::vector<int32_t> hst, hrank;
+  to_host(hst, status.p, nf, s);
+  // blocks stopped with OVERFLOW (device pool exhausted, or a wavefront block past its register
+  // capacity) continue in the workgroup kernel; those without room get a slot in a new pool
+  std::vector<uint8_t> continued(nf, 0);
+  std::vector<int32_t> first_cap(nf);
+  for (int64_t b = 0; b < nf; ++b) first_cap[b] = desc[b].cap;
+  std::vector<DevBuf<T>> extra_pools;
+  for (;;) {
+    std::vector<int32_t> list;
+    for (int64_t b = 0; b < nf; ++b)
+      if (hst[b] == ACA_OVERFLOW) list.push_back((int32_t)b);
+    if (list.empty()) break;
+    for (int32_t b : list) continued[b] = 1;
+    to_host(hrank, rank.p, nf, s);
+    to_host(desc, d_desc.p, nf, s);  // slots are assigned and moved on the device
+    std::vector<FarDesc> nd = desc;
+    std::vector<int32_t> moved;
+    int64_t extra = 0;
+    for (int32_t b : list) {
+      FarDesc& d = nd[b];
+      if (d.U != nullptr && d.cap > hrank[b]) continue;
+      d.cap = (int32_t)std::min<int64_t>(
+          d.rcap, std::max<int64_t>({2 * (int64_t)d.cap, (int64_t)d.cap + 8, (int64_t)hrank[b] + 8}));
+      extra += (int64_t)d.cap * (d.m + d.n);
+      moved.push_back(b);
+    }
+    if (!moved.empty()) {
+      extra_pools.emplace_back(extra);
+      T* base = extra_pools.back().p;
+      int64_t off = 0;
+      for (int32_t b : moved) {
+        FarDesc& d = nd[b];
+        d.U = base + off;
+        off += (int64_t)d.cap * d.m;
+        d.V = base + off;
+        off += (int64_t)d.cap * d.n;
+      }
+      DevBuf<FarDesc> d_nd(nf);
+      DevBuf<int32_t> d_moved(moved.size());
+      HMX_HIP(hipMemcpyAsync(d_nd.p, nd.data(), nf * sizeof(FarDesc), hipMemcpyHostToDevice, s));
+      HMX_HIP(hipMemcpyAsync(d_moved.p, moved.data(), moved.size() * 4, hipMemcpyHostToDevice, s));
+      launch_copy_factors<T>(d_desc.p, d_nd.p, rank.p, d_moved.p, (int)moved.size(), s);
+      HMX_HIP(hipStreamSynchronize(s));
+      desc.swap(nd);
+      d_desc = std::move(d_nd);
+    }
+    run_aca(list, 0);
+    to_host(hst, status.p, nf, s);
+  }
+  to_host(hrank, rank.p, nf, s);
+  to_host(desc, d_desc.p, nf, s);
+
+  // records of the product: factors stay in the slots ACA wrote; dense blocks are assembled
+  std::vector<FarRec> rec(nf);
+  int64_t trun = 0, drun = 0, grown = 0;  // grown: blocks that left their first slot
+  std::vector<int32_t> dtb, dm, dsb, dn;
+  std::vector<int64_t> doff;
+  op->far_entries = op->dense_far = op->dense_far_entries = op->max_rank = op->sum_rank = 0;
+  int64_t evals = 0;
+  for (int64_t b = 0; b < nf; ++b) {
+    const FarDesc& d = desc[b];
+    FarRec& f = rec[b];
+    f.tb = d.tb;
+    f.m = d.m;
+    f.sb = d.sb;
+    f.n = d.n;
+    HMX_REQUIRE(hst[b] == ACA_CONVERGED || hst[b] == ACA_DENSE, HMX_EINTERNAL,
+                "ACA left a block unfinished");
+    if (continued[b] || (!is_wave[b] && d.cap != first_cap[b])) grown++;
+    if (hst[b] == ACA_DENSE) {
+      f.dense = 1;
+      f.r = d.n;
+      f.U = nullptr;  // set below
+      f.V = nullptr;
+      f.toff = trun;
+      trun += d.n;
+      op->dense_far++;
+      op->dense_far_entries += (int64_t)d.m * d.n;
+      dtb.push_back(d.tb);
+      dm.push_back(d.m);
+      dsb.push_back(d.sb);
+      dn.push_back(d.n);
+      doff.push_back(drun);
+      drun += (int64_t)d.m * d.n;
+      evals += (int64_t)d.m * d.n + (int64_t)hrank[b] * (d.m + d.n);
+    } else {
+      f.dense = 0;
+      f.r = hrank[b];
+      f.U = d.U;
+      f.V = d.V;
+      f.toff = trun;
+      trun += f.r;
+      op->far_entries += (int64_t)f.r * (d.m + d.n);
+      op->max_rank = std::max<int64_t>(op->max_rank, f.r);
+      op->sum_rank += f.r;
+      evals += (int64_t)f.r * (d.m + d.n);
+    }
+  }
+  op->overflow_blocks = grown;
+  op->kernel_evals += evals;
+  op->dense_pool.alloc(std::max<int64_t>(drun, 1) * sizeof(T));
+  for (int64_t b = 0, q = 0; b < nf; ++b)
+    if (rec[b].dense) rec[b].U = (const T*)op->dense_pool.p + doff[q++];
+  const int64_t used = (int64_t)read1(gtop.p, s);
+  op->pool_used_bytes = std::min(used, gcap) * (int64_t)sizeof(T);
+  for (auto& p : extra_pools) op->pool_used_bytes += (int64_t)p.bytes();
+  if (op->p.pool_limit_bytes > 0 &&
+      op->pool_used_bytes + (int64_t)op->near_pool.bytes() + (int64_t)op->dense_pool.bytes() >
+          op->p.pool_limit_bytes)
+    throw Error(HMX_ENOMEM, "operator exceeds pool_limit_bytes");
+  // keep the pools (they hold the factors)
+  op->far_pools.clear();
+  {
+    DevBuf<unsigned char> g;
+    g.p = (unsigned char*)gpool.p;
+    g.n = gpool.bytes();
+    gpool.p = nullptr;
+    gpool.n = 0;
+    op->far_pools.push_back(std::move(g));
+    for (auto& p : extra_pools) {
+      DevBuf<unsigned char> e;
+      e.p = (unsigned char*)p.p;
+      e.n = p.bytes();
+      p.p = nullptr;
+      p.n = 0;
+      op->far_pools.push_back(std::move(e));
+    }
+  }
+  op->t_len = trun;
+  op->far.alloc(nf1);
+  if (nf) HMX_HIP(hipMemcpyAsync(op->far.p, rec.data(), nf * sizeof(FarRec), hipMemcpyHostToDevice, s));
+  if (!dtb.empty()) {
+    int64_t nd = (int64_t)dtb.size();
+    DevBuf<int32_t> a(nd), b2(nd), c(nd), e(nd);
+    DevBuf<int64_t> o(nd);
+    HMX_HIP(hipMemcpyAsync(a.p, dtb.data(), nd * 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(b2.p, dm.data(), nd * 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(c.p, dsb.data(), nd * 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(e.p, dn.data(), nd * 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(o.p, doff.data(), nd * 8, hipMemcpyHostToDevice, s));
+    launch_assemble<T>(a.p, b2.p, c.p, e.p, o.p, nd, op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern,
+                       op->k, (T*)op->dense_pool.p, s);
+    HMX_HIP(hipStreamSynchronize(s));
+  }
+  HMX_HIP(hipStreamSynchronize(s));
+  op->far_host = std::move(rec);
+
+  // per leaf: far blocks whose row node contains it
+  DevBuf<int64_t> lcnt(nl);
+  op->far_ptr.alloc(nl + 1);
+  launch_leaf_far_count(nl, op->leaves.p, op->parent.p, node_cnt.p, lcnt.p, s);
+  scan_excl_i64(lcnt.p, op->far_ptr.p, nl, s);
+  int64_t ninc = read1(op->far_ptr.p + nl, s);
+  op->far_list.alloc(std::max<int64_t>(ninc, 1));
+  launch_leaf_far_fill(nl, op->leaves.p, op->parent.p, node_cnt.p, node_first.p, op->far_ptr.p,
+                       op->far_list.p, s);
+  HMX_HIP(hipStreamSynchronize(s));
+}
+
+template <class T>
+void build_h(hmx_op* op, hipStream_t s) {
+  HMX_REQUIRE(op->M < (int64_t(1) << 23), HMX_EUNSUPPORTED,
+              "H-matrix mode supports at most 2^23 - 1 points");
+  Timer tm(s);
+  Timer total(s);
+  build_tree(op, s);
+  op->t_tree = tm.stop();
+  build_blocks(op, s);
+  op->t_blocks = tm.stop();
+  build_near<T>(op, s);
+  op->kernel_evals += op->near_entries;
+  op->t_near = tm.stop();
+  build_far<T>(op, s);
+  op->t_aca = tm.stop();
+  op->xp.alloc((size_t)op->M * sizeof(T));
+  op->tbuf.alloc(std::max<size_t>((size_t)op->t_len * sizeof(T), sizeof(T)));
+  op->t_total = total.stop();
+}
+
+}  // namespace
+
+void finish_build(hmx_op* op, hipStream_t s) {
+  const size_t es = op->prec == HMX_FP64 ? sizeof(double2) : sizeof(float2);
+  op->elem = es;
+  if (op->p.tol <= 0) {
+    op->dense = true;
+    op->partial.alloc((size_t)dense_otf_partial_len(op->M) * es);
+    return;
+  }
+  if (op->prec == HMX_FP64) build_h<double2>(op, s);
+  else build_h<float2>(op, s);
+}
+
+}  // namespace hmx

@@ -117,9 +117,11 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
-// Block-wide argmax over a 256-thread workgroup; every thread receives the result.
-// `sv`, `si` are LDS scratch of NWAVE entries.
+// Workgroup-wide argmax over NT threads; every thread receives the result.
+// `sv`, `si` are LDS scratch of NT / 64 entries.
+template <int NT = WG>
 __device__ __forceinline__ void block_amax(double& v, int& i, double* sv, int* si) {
+  constexpr int NW = NT / WAVE;
   wave_amax(v, i);
   int w = threadIdx.x / WAVE;
   __syncthreads();
@@ -131,10 +133,12 @@ __device__ __forceinline__ void block_amax(double& v, int& i, double* sv, int* s
   v = sv[0];
   i = si[0];
 #pragma unroll
-  for (int q = 1; q < NWAVE; ++q) amax_merge(v, i, sv[q], si[q]);
+  for (int q = 1; q < NW; ++q) amax_merge(v, i, sv[q], si[q]);
 }
 
+template <int NT = WG>
 __device__ __forceinline__ int block_min(int v, int* s) {
+  constexpr int NW = NT / WAVE;
   v = wave_min(v);
   int w = threadIdx.x / WAVE;
   __syncthreads();
@@ -142,30 +146,34 @@ __device__ __forceinline__ int block_min(int v, int* s) {
   __syncthreads();
   int r = s[0];
 #pragma unroll
-  for (int q = 1; q < NWAVE; ++q) r = min(r, s[q]);
+  for (int q = 1; q < NW; ++q) r = min(r, s[q]);
   return r;
 }
 
-// Sum of N doubles per thread over the workgroup, in a fixed order (deterministic).
-// `s` is LDS scratch of N * NWAVE doubles.  Every thread receives the N sums.
-template <int N>
+// Sum of N doubles per thread over NT threads, in a fixed order (deterministic): wavefront
+// sums, then thread q adds the NT / 64 partials of value q, then every thread reads the N sums.
+// `s` is LDS scratch of N * (NT / 64 + 1) doubles; N <= NT.
+template <int N, int NT = WG>
 __device__ __forceinline__ void block_sum(double* v, double* s) {
+  constexpr int NW = NT / WAVE;
 #pragma unroll
   for (int q = 0; q < N; ++q) v[q] = wave_sum(v[q]);
-  int w = threadIdx.x / WAVE;
+  const int w = threadIdx.x / WAVE;
   __syncthreads();
   if ((threadIdx.x & (WAVE - 1)) == 0) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) s[q * NWAVE + w] = v[q];
+    for (int q = 0; q < N; ++q) s[q * NW + w] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    const int q = threadIdx.x;
+    double a = s[q * NW];
+    for (int p = 1; p < NW; ++p) a += s[q * NW + p];
+    s[N * NW + q] = a;
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < N; ++q) {
-    double a = s[q * NWAVE];
-#pragma unroll
-    for (int p = 1; p < NWAVE; ++p) a += s[q * NWAVE + p];
-    v[q] = a;
-  }
+  for (int q = 0; q < N; ++q) v[q] = s[N * NW + q];
 }
 
 // Exclusive scan of one int per thread over the workgroup; returns the thread's prefix and
@@ -241,4 +249,22 @@ template <class T> __device__ __forceinline__ T czero();
 template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
 template <> __device__ __forceinline__ float2 czero<float2>() { return make_float2(0.0f, 0.0f); }
 
+}  // namespace hmx
+
+namespace hmx {
+// Value of lane `lane` (wave-uniform) broadcast to the whole wavefront.
+__device__ __forceinline__ double readlane(double x, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float readlane(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double2 readlane(double2 v, int lane) {
+  return make_double2(readlane(v.x, lane), readlane(v.y, lane));
+}
+__device__ __forceinline__ float2 readlane(float2 v, int lane) {
+  return make_float2(readlane(v.x, lane), readlane(v.y, lane));
+}
 }  // namespace hmx

@@ -33,6 +33,13 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::hmx::Error(code, msg); \
   } while (0)
 
+// Device memory: a caching allocator (freed blocks are kept per size class and reused, so that
+// repeated builds do not map and unmap memory; dev_free waits for the device first, as hipFree
+// does).  dev_release_cache returns the cached blocks to the runtime.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+void dev_release_cache();
+
 // Owning device buffer (move-only).
 template <class T>
 struct DevBuf {
@@ -51,11 +58,11 @@ struct DevBuf {
   void alloc(size_t count) {
     reset();
     if (count == 0) return;
-    HMX_HIP(hipMalloc((void**)&p, count * sizeof(T)));
+    p = (T*)dev_alloc(count * sizeof(T));
     n = count;
   }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
     n = 0;
   }
@@ -99,7 +106,9 @@ struct FarRec {
   int32_t tb, m, sb, n;
   int32_t r;      // rank, or n for a block stored dense (then U is the m x n block)
   int32_t dense;  // 1 when stored dense
-  int64_t uoff, voff, toff;
+  const void* U;  // m x r column-major (or the m x n block when dense)
+  const void* V;  // n x r column-major (unused when dense)
+  int64_t toff;   // offset of t_b = V^T x_s in the product scratch
 };
 
 constexpr int ACA_COEF_MAX = 1024;  // largest ACA rank (coefficients of a step held in LDS)
@@ -157,27 +166,33 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
                      const double* Z, const double* W, int kern, double k, T* pool, hipStream_t s);
 // k_aca.hip
 template <class T>
-void launch_aca(const FarDesc* d, const int32_t* order, int nb, int* counter, const double* X,
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
                 const double* Y, const double* Z, const double* W, int kern, double k, double tol,
-                uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
-                double* norm2, int fresh, hipStream_t s);
+                uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status, double* norm2,
+                int fresh, T* gpool, int64_t gcap, unsigned long long* gtop, hipStream_t s);
+constexpr int ACA_BIG = 4096;  // blocks with m + n >= ACA_BIG run in 512-thread workgroups
+constexpr int ACA_WAVE_N = 64; // blocks with m, n <= ACA_WAVE_N run one per wavefront
+constexpr int ACA_WAVE_RC = 16; // terms a wavefront block holds in registers
+template <class T>
+void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
+                     const double* Y, const double* Z, const double* W, int kern, double k,
+                     double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
+                     double* norm2, T* gpool, int64_t gcap, unsigned long long* gtop,
+                     hipStream_t s);
 template <class T>
 void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* rank,
                          const int32_t* list, int nlist, hipStream_t s);
-template <class T>
-void launch_compact(const FarDesc* d, const FarRec* rec, const int32_t* rank, int64_t nb, T* dst,
-                    hipStream_t s);
 // k_matvec.hip
 template <class T>
 void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, hipStream_t s);
 template <class T>
-void launch_far_vt(const FarRec* rec, int64_t nf, const T* pool, const T* xp, T* t, hipStream_t s);
+void launch_far_vt(const FarRec* rec, int64_t nf, const T* xp, T* t, hipStream_t s);
 template <class T>
 void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegin,
                        const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
                        const int32_t* near_n, const int64_t* near_off, const T* near_pool,
                        const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
-                       const T* far_pool, const T* tbuf, const T* xp, const int32_t* perm, T* y,
+                       const T* tbuf, const T* xp, const int32_t* perm, T* y,
                        hipStream_t s);
 template <class T>
 void launch_dense_otf(const double* X, const double* Y, const double* Z, const double* W,
@@ -211,11 +226,12 @@ struct hmx_op {
   hmx::DevBuf<unsigned char> near_pool;
   // far field
   int64_t n_far = 0, far_entries = 0, dense_far = 0, dense_far_entries = 0, max_rank = 0,
-          sum_rank = 0, overflow_blocks = 0, t_len = 0, far_pool_elems = 0;
+          sum_rank = 0, overflow_blocks = 0, t_len = 0, pool_used_bytes = 0;
   hmx::DevBuf<int2> farL;
   hmx::DevBuf<hmx::FarRec> far;
   std::vector<hmx::FarRec> far_host;
-  hmx::DevBuf<unsigned char> far_pool;
+  std::vector<hmx::DevBuf<unsigned char>> far_pools;  // factor slots (ACA writes in place)
+  hmx::DevBuf<unsigned char> dense_pool;               // far blocks stored dense
   hmx::DevBuf<int64_t> far_ptr;
   hmx::DevBuf<int32_t> far_list;
   // product scratch (allocated at build; the product allocates nothing)
@@ -225,3 +241,8 @@ struct hmx_op {
   int64_t kernel_evals = 0;
   int64_t bytes() const;
 };
+
+namespace hmx {
+// hmx_build.hip: builds the operator from its points (dense when tol <= 0, else H-matrix).
+void finish_build(hmx_op* op, hipStream_t s);
+}  // namespace hmx

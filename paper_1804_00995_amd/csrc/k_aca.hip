@@ -15,35 +15,57 @@
 // A ~ sum_k u_k v_k^T with U (m x cap) and V (n x cap) stored column-major.  Pivot magnitudes,
 // norms and the cross terms are accumulated in FP64 in both precisions.
 //
-// Schedule: a persistent grid; each 256-thread workgroup takes the next block from an atomic
-// counter (blocks pre-ordered by decreasing size) and runs its whole sequential step chain.
-// A block that needs a term beyond its slot capacity saves (rank, pivot row, norm) and stops
-// with status OVERFLOW; the host gives it a larger slot and the kernel continues from the saved
-// state, so the sequence of pivots, and therefore the factors, are the same as in one run.
-// A block that needs a term beyond its rank cap is marked DENSE (stored exactly).
+// Schedule: persistent grids; each workgroup takes the next block from an atomic counter
+// (blocks pre-ordered by decreasing size) and runs its whole sequential step chain.  Blocks with
+// m + n above a threshold run in 512-thread workgroups, the others in 256-thread workgroups, and
+// blocks with m, n <= 64 in single wavefronts (register-resident, below); the three classes run
+// on three streams.  The inner sums over previous terms keep LU independent loads in flight.
+//
+// Rank slots: a block starts in a slot of `cap` columns.  When it needs one more term it moves
+// itself to a slot of twice the size taken from a device bump pool (atomic offset) and goes
+// on; if the pool is exhausted it saves (rank, pivot row, norm) and stops with status OVERFLOW,
+// and the host continues it in a new pool.  Either way the pivot sequence, and therefore the
+// factors, equal those of one uninterrupted run.  A block that needs a term beyond its rank cap
+// is marked DENSE (stored exactly).
 #include <limits.h>
+
+#include <algorithm>
 
 #include "hmx_dev.h"
 #include "hmx_host.h"
 
 namespace hmx {
 
-template <class T>
-__device__ void aca_block(const FarDesc& d, int b, const double* __restrict__ X,
+
+struct AcaShared {
+  double sv[16];
+  int si[16];
+  double ssum[32 * 9];  // block_sum scratch: N * (NT / 64 + 1) for N <= 32, NT <= 512
+  int64_t off;
+  int q;
+};
+
+template <class T, int NT>
+__device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __restrict__ X,
                           const double* __restrict__ Y, const double* __restrict__ Z,
                           const double* __restrict__ W, int kern, double k, double tol,
                           uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
-                          double* norm2, int fresh, T* coef, double* sv, int* si, double* ssum) {
+                          double* norm2, int fresh, T* gpool, int64_t gcap,
+                          unsigned long long* gtop, T* coef, AcaShared& sh) {
+  constexpr int JC = 1;                  // elements per thread per round
+  constexpr int LU = NT >= 512 ? 8 : 4;  // previous terms loaded per round (loads in flight)
   const int tid = threadIdx.x;
+  const FarDesc d = descs[b];
   const int m = d.m, n = d.n, tb = d.tb, sb = d.sb;
   T* U = (T*)d.U;
   T* V = (T*)d.V;
+  int cap = d.cap;
   uint8_t* rused = flags + d.foff;
   uint8_t* cused = rused + m;
   int kk, ip;
   double nrm2;
   if (fresh) {
-    for (int i = tid; i < m + n; i += WG) rused[i] = 0;
+    for (int i = tid; i < m + n; i += NT) rused[i] = 0;
     kk = 0;
     ip = 0;
     nrm2 = 0.0;
@@ -52,35 +74,84 @@ __device__ void aca_block(const FarDesc& d, int b, const double* __restrict__ X,
     ip = ipiv[b];
     nrm2 = norm2[b];
   }
-  __syncthreads();
   int st = d.rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
+  if (st == ACA_RUNNING && U == nullptr) {
+    // first slot, taken from the device pool
+    const int64_t need = (int64_t)cap * (m + n);
+    if (tid == 0) sh.off = (int64_t)atomicAdd(gtop, (unsigned long long)need);
+    __syncthreads();
+    const int64_t off = sh.off;
+    if (gpool == nullptr || off + need > gcap) {
+      st = ACA_OVERFLOW;
+    } else {
+      U = gpool + off;
+      V = U + (int64_t)cap * m;
+      if (tid == 0) {
+        descs[b].U = U;
+        descs[b].V = V;
+      }
+    }
+  }
+  __syncthreads();
   while (st == ACA_RUNNING) {
     // (1) residual row ip, stored as column kk of V when the slot has room
-    for (int l = tid; l < kk; l += WG) coef[l] = U[(int64_t)l * m + ip];
+    for (int l = tid; l < kk; l += NT) coef[l] = U[(int64_t)l * m + ip];
     __syncthreads();
     const double px = X[tb + ip], py = Y[tb + ip], pz = Z[tb + ip];
-    const bool store = kk < d.cap;
+    const bool store = kk < cap;
     T* R = V + (int64_t)kk * n;
     double best = -1.0;
     int bj = INT_MAX;
-    for (int j = tid; j < n; j += WG) {
-      T a = eval_entry<T>(kern, k, px, py, pz, X[sb + j], Y[sb + j], Z[sb + j], W[sb + j]);
-      for (int l = 0; l < kk; ++l) cfms(a, coef[l], V[(int64_t)l * n + j]);
-      if (store) R[j] = a;
-      if (!cused[j]) amax_merge(best, bj, abs2(a), j);
+    for (int j0 = tid; j0 < n; j0 += NT * JC) {
+      T a[JC];
+      int jx[JC];
+#pragma unroll
+      for (int q = 0; q < JC; ++q) {
+        const int j = j0 + q * NT;
+        jx[q] = j < n ? j : n - 1;
+        a[q] = eval_entry<T>(kern, k, px, py, pz, X[sb + jx[q]], Y[sb + jx[q]], Z[sb + jx[q]],
+                             W[sb + jx[q]]);
+      }
+      int l = 0;
+      for (; l + LU <= kk; l += LU) {
+        T vv[LU][JC];
+#pragma unroll
+        for (int u = 0; u < LU; ++u)
+#pragma unroll
+          for (int q = 0; q < JC; ++q) vv[u][q] = V[(int64_t)(l + u) * n + jx[q]];
+#pragma unroll
+        for (int u = 0; u < LU; ++u) {
+          const T c = coef[l + u];
+#pragma unroll
+          for (int q = 0; q < JC; ++q) cfms(a[q], c, vv[u][q]);
+        }
+      }
+      for (; l < kk; ++l) {
+        const T c = coef[l];
+#pragma unroll
+        for (int q = 0; q < JC; ++q) cfms(a[q], c, V[(int64_t)l * n + jx[q]]);
+      }
+#pragma unroll
+      for (int q = 0; q < JC; ++q) {
+        const int j = j0 + q * NT;
+        if (j < n) {
+          if (store) R[j] = a[q];
+          if (!cused[j]) amax_merge(best, bj, abs2(a[q]), j);
+        }
+      }
     }
-    block_amax(best, bj, sv, si);
+    block_amax<NT>(best, bj, sh.sv, sh.si);
     if (bj == INT_MAX || best <= 1e-300) {
       // (2') zero residual row: mark it, move to the lowest unused row
       if (tid == 0) rused[ip] = 1;
       __syncthreads();
       int nx = INT_MAX;
-      for (int i = tid; i < m; i += WG)
+      for (int i = tid; i < m; i += NT)
         if (!rused[i]) {
           nx = i;
           break;
         }
-      nx = block_min(nx, si);
+      nx = block_min<NT>(nx, sh.si);
       if (nx == INT_MAX) {
         st = ACA_CONVERGED;
         break;
@@ -89,8 +160,35 @@ __device__ void aca_block(const FarDesc& d, int b, const double* __restrict__ X,
       continue;
     }
     if (!store) {
-      st = d.cap >= d.rcap ? ACA_DENSE : ACA_OVERFLOW;
-      break;
+      if (cap >= d.rcap) {
+        st = ACA_DENSE;
+        break;
+      }
+      // move to a slot of twice the size from the device pool
+      const int ncap = min(d.rcap, max(2 * cap, cap + 8));
+      const int64_t need = (int64_t)ncap * (m + n);
+      if (tid == 0) sh.off = (int64_t)atomicAdd(gtop, (unsigned long long)need);
+      __syncthreads();
+      const int64_t off = sh.off;
+      if (gpool == nullptr || off + need > gcap) {
+        st = ACA_OVERFLOW;
+        break;
+      }
+      T* nU = gpool + off;
+      T* nV = nU + (int64_t)ncap * m;
+      const int64_t cu = (int64_t)kk * m, cv = (int64_t)kk * n;
+      for (int64_t e = tid; e < cu; e += NT) nU[e] = U[e];
+      for (int64_t e = tid; e < cv; e += NT) nV[e] = V[e];
+      __syncthreads();
+      U = nU;
+      V = nV;
+      cap = ncap;
+      if (tid == 0) {
+        descs[b].U = nU;
+        descs[b].V = nV;
+        descs[b].cap = ncap;
+      }
+      continue;  // recompute the residual row into the new slot
     }
     // (3) v_k = R / R[bj]
     const double2 pd = to_d2(R[bj]);
@@ -102,66 +200,120 @@ __device__ void aca_block(const FarDesc& d, int b, const double* __restrict__ X,
       cused[bj] = 1;
     }
     double nv2 = 0.0;
-    for (int j = tid; j < n; j += WG) {
+    for (int j = tid; j < n; j += NT) {
       T v = cmul(R[j], inv);
       R[j] = v;
       nv2 += abs2(v);
     }
     __syncthreads();
     // (4) residual column bj, stored as column kk of U
-    for (int l = tid; l < kk; l += WG) coef[l] = V[(int64_t)l * n + bj];
+    for (int l = tid; l < kk; l += NT) coef[l] = V[(int64_t)l * n + bj];
     __syncthreads();
     const double qx = X[sb + bj], qy = Y[sb + bj], qz = Z[sb + bj], qw = W[sb + bj];
     T* Uk = U + (int64_t)kk * m;
     double ub = -1.0, nu2 = 0.0;
     int ui = INT_MAX;
-    for (int i = tid; i < m; i += WG) {
-      T a = eval_entry<T>(kern, k, X[tb + i], Y[tb + i], Z[tb + i], qx, qy, qz, qw);
-      for (int l = 0; l < kk; ++l) cfms(a, coef[l], U[(int64_t)l * m + i]);
-      Uk[i] = a;
-      double a2 = abs2(a);
-      nu2 += a2;
-      if (!rused[i]) amax_merge(ub, ui, a2, i);
+    for (int i0 = tid; i0 < m; i0 += NT * JC) {
+      T a[JC];
+      int ix[JC];
+#pragma unroll
+      for (int q = 0; q < JC; ++q) {
+        const int i = i0 + q * NT;
+        ix[q] = i < m ? i : m - 1;
+        a[q] = eval_entry<T>(kern, k, X[tb + ix[q]], Y[tb + ix[q]], Z[tb + ix[q]], qx, qy, qz, qw);
+      }
+      int l = 0;
+      for (; l + LU <= kk; l += LU) {
+        T uu[LU][JC];
+#pragma unroll
+        for (int u = 0; u < LU; ++u)
+#pragma unroll
+          for (int q = 0; q < JC; ++q) uu[u][q] = U[(int64_t)(l + u) * m + ix[q]];
+#pragma unroll
+        for (int u = 0; u < LU; ++u) {
+          const T c = coef[l + u];
+#pragma unroll
+          for (int q = 0; q < JC; ++q) cfms(a[q], c, uu[u][q]);
+        }
+      }
+      for (; l < kk; ++l) {
+        const T c = coef[l];
+#pragma unroll
+        for (int q = 0; q < JC; ++q) cfms(a[q], c, U[(int64_t)l * m + ix[q]]);
+      }
+#pragma unroll
+      for (int q = 0; q < JC; ++q) {
+        const int i = i0 + q * NT;
+        if (i < m) {
+          Uk[i] = a[q];
+          const double a2 = abs2(a[q]);
+          nu2 += a2;
+          if (!rused[i]) amax_merge(ub, ui, a2, i);
+        }
+      }
     }
     __syncthreads();
-    // (5) cross terms sum_{l<kk} (u_l^H u_k)(v_l^H v_k), four l at a time
+    // (5) cross terms sum_{l<kk} (u_l^H u_k)(v_l^H v_k), LG terms at a time (LG loads in
+    // flight per thread per round)
+    constexpr int LG = NT >= 512 ? 8 : 4;
+    constexpr int CJ = 1;  // elements per thread per round in this pass
     double cross = 0.0;
-    for (int l0 = 0; l0 < kk; l0 += 4) {
-      double acc[16];
+    for (int l0 = 0; l0 < kk; l0 += LG) {
+      const int lc = min(LG, kk - l0);
+      double acc[4 * LG];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-      for (int i = tid; i < m; i += WG) {
-        double2 uk = to_d2(Uk[i]);
+      for (int q = 0; q < 4 * LG; ++q) acc[q] = 0.0;
+      for (int i0 = tid; i0 < m; i0 += NT * CJ) {
+        double2 uk[CJ];
+        T ul[CJ][LG];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (l0 + q < kk) {
-            double2 ul = to_d2(U[(int64_t)(l0 + q) * m + i]);
-            acc[2 * q] += ul.x * uk.x + ul.y * uk.y;
-            acc[2 * q + 1] += ul.x * uk.y - ul.y * uk.x;
-          }
+        for (int c = 0; c < CJ; ++c) {
+          const int i = i0 + c * NT;
+          const int ix = i < m ? i : m - 1;
+          uk[c] = i < m ? to_d2(Uk[ix]) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int q = 0; q < LG; ++q) ul[c][q] = q < lc ? U[(int64_t)(l0 + q) * m + ix] : czero<T>();
         }
-      }
-      for (int j = tid; j < n; j += WG) {
-        double2 vk = to_d2(R[j]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (l0 + q < kk) {
-            double2 vl = to_d2(V[(int64_t)(l0 + q) * n + j]);
-            acc[8 + 2 * q] += vl.x * vk.x + vl.y * vk.y;
-            acc[8 + 2 * q + 1] += vl.x * vk.y - vl.y * vk.x;
+        for (int c = 0; c < CJ; ++c)
+#pragma unroll
+          for (int q = 0; q < LG; ++q) {
+            const double2 a = to_d2(ul[c][q]);
+            acc[2 * q] += a.x * uk[c].x + a.y * uk[c].y;
+            acc[2 * q + 1] += a.x * uk[c].y - a.y * uk[c].x;
           }
-        }
       }
-      block_sum<16>(acc, ssum);
+      for (int j0 = tid; j0 < n; j0 += NT * CJ) {
+        double2 vk[CJ];
+        T vl[CJ][LG];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (l0 + q < kk) cross += acc[2 * q] * acc[8 + 2 * q] - acc[2 * q + 1] * acc[8 + 2 * q + 1];
+        for (int c = 0; c < CJ; ++c) {
+          const int j = j0 + c * NT;
+          const int jx = j < n ? j : n - 1;
+          vk[c] = j < n ? to_d2(R[jx]) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int q = 0; q < LG; ++q) vl[c][q] = q < lc ? V[(int64_t)(l0 + q) * n + jx] : czero<T>();
+        }
+#pragma unroll
+        for (int c = 0; c < CJ; ++c)
+#pragma unroll
+          for (int q = 0; q < LG; ++q) {
+            const double2 a = to_d2(vl[c][q]);
+            acc[2 * LG + 2 * q] += a.x * vk[c].x + a.y * vk[c].y;
+            acc[2 * LG + 2 * q + 1] += a.x * vk[c].y - a.y * vk[c].x;
+          }
+      }
+      block_sum<4 * LG, NT>(acc, sh.ssum);
+#pragma unroll
+      for (int q = 0; q < LG; ++q)
+        if (q < lc)
+          cross += acc[2 * q] * acc[2 * LG + 2 * q] - acc[2 * q + 1] * acc[2 * LG + 2 * q + 1];
     }
     double nn2[2] = {nu2, nv2};
-    block_sum<2>(nn2, ssum);
+    block_sum<2, NT>(nn2, sh.ssum);
     nrm2 = nrm2 + 2.0 * cross + nn2[0] * nn2[1];
     kk += 1;
-    block_amax(ub, ui, sv, si);
+    block_amax<NT>(ub, ui, sh.sv, sh.si);
     // (6) stopping rule, (7) next pivot row
     if (sqrt(nn2[0]) * sqrt(nn2[1]) <= tol * sqrt(nrm2)) {
       st = ACA_CONVERGED;
@@ -182,8 +334,8 @@ __device__ void aca_block(const FarDesc& d, int b, const double* __restrict__ X,
   __syncthreads();
 }
 
-template <class T>
-__global__ void __launch_bounds__(WG) aca_kernel(const FarDesc* __restrict__ desc,
+template <class T, int NT>
+__global__ void __launch_bounds__(NT) aca_kernel(FarDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order, int nb,
                                                  int* counter, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
@@ -191,41 +343,235 @@ __global__ void __launch_bounds__(WG) aca_kernel(const FarDesc* __restrict__ des
                                                  const double* __restrict__ W, int kern, double k,
                                                  double tol, uint8_t* flags, int32_t* rank,
                                                  int32_t* ipiv, int32_t* status, double* norm2,
-                                                 int fresh) {
+                                                 int fresh, T* gpool, int64_t gcap,
+                                                 unsigned long long* gtop) {
   __shared__ T coef[ACA_COEF_MAX];
-  __shared__ double sv[NWAVE];
-  __shared__ int si[NWAVE];
-  __shared__ double ssum[16 * NWAVE];
-  __shared__ int s_q;
+  __shared__ AcaShared sh;
   for (;;) {
-    if (threadIdx.x == 0) s_q = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) sh.q = atomicAdd(counter, 1);
     __syncthreads();
-    const int q = s_q;
+    const int q = sh.q;
     __syncthreads();
     if (q >= nb) break;
+    aca_block<T, NT>(desc, order[q], X, Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2,
+                     fresh, gpool, gcap, gtop, coef, sh);
+  }
+}
+
+// ------------------------------------------------------------------ register-resident ACA
+// Blocks with m, n <= 64: one wavefront per block, lane i owns row i of U and column i of V,
+// up to RC terms held in registers.  Coefficients u_l[i_k] and v_l[j_k] are broadcast from
+// their owner lane with readlane, pivots come from wavefront argmax reductions, and the cross
+// term of step (5) is evaluated as sum_i u_k[i] * sum_l conj(u_l[i]) (v_l^H v_k), i.e. k
+// wavefront sums for the v_l^H v_k and one for the final sum.  Nothing touches memory between
+// loading the points and storing the factors.  A block that needs more than RC terms stores its
+// state and stops with status OVERFLOW; the workgroup kernel continues it.
+template <class T, int RC>
+__global__ void __launch_bounds__(WG) aca_wave_kernel(
+    FarDesc* __restrict__ desc, const int32_t* __restrict__ order, int nb,
+    const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
+    const double* __restrict__ W, int kern, double k, double tol, uint8_t* flags, int32_t* rank,
+    int32_t* ipiv, int32_t* status, double* norm2, T* gpool, int64_t gcap,
+    unsigned long long* gtop) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  // static round-robin over the (size-ordered) list: wavefront w takes w, w + nw, ...; the
+  // loop carries no lane-dependent control flow
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * NWAVE + threadIdx.x / WAVE));
+  const int nw = (int)gridDim.x * NWAVE;
+  for (int q = gw; q < nb; q += nw) {
     const int b = order[q];
     const FarDesc d = desc[b];
-    aca_block<T>(d, b, X, Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2, fresh,
-                 coef, sv, si, ssum);
+    const int m = d.m, n = d.n;
+    const bool hr = lane < m, hc = lane < n;
+    const int ir = hr ? lane : 0, ic = hc ? lane : 0;
+    const double tx = X[d.tb + ir], ty = Y[d.tb + ir], tz = Z[d.tb + ir];
+    const double sx = X[d.sb + ic], sy = Y[d.sb + ic], sz = Z[d.sb + ic], sw = W[d.sb + ic];
+    T u[RC], v[RC];
+#pragma unroll
+    for (int l = 0; l < RC; ++l) u[l] = v[l] = czero<T>();
+    bool rused = !hr, cused = !hc;
+    int kk = 0, ip = 0;
+    double nrm2 = 0.0;
+    int st = d.rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
+    while (st == ACA_RUNNING) {
+      // (1) residual row ip
+      const double px = readlane(tx, ip), py = readlane(ty, ip), pz = readlane(tz, ip);
+      T a = eval_entry<T>(kern, k, px, py, pz, sx, sy, sz, sw);
+#pragma unroll
+      for (int l = 0; l < RC; ++l)
+        if (l < kk) cfms(a, readlane(u[l], ip), v[l]);
+      if (!hc) a = czero<T>();
+      // (2) pivot column
+      double best = cused ? -1.0 : abs2(a);
+      int bj = cused ? INT_MAX : lane;
+      wave_amax(best, bj);
+      bj = __builtin_amdgcn_readfirstlane(bj);
+      const int zero_row = __builtin_amdgcn_readfirstlane((bj == INT_MAX || best <= 1e-300) ? 1 : 0);
+      if (zero_row) {
+        if (lane == ip) rused = true;
+        const int nx = __builtin_amdgcn_readfirstlane(wave_min(rused ? INT_MAX : lane));
+        if (nx == INT_MAX) {
+          st = ACA_CONVERGED;
+          break;
+        }
+        ip = nx;
+        continue;
+      }
+      if (kk >= d.rcap) {
+        st = ACA_DENSE;
+        break;
+      }
+      if (kk >= RC) {
+        st = ACA_OVERFLOW;
+        break;
+      }
+      // (3) v_k = R / R[bj]
+      const double2 pd = to_d2(readlane(a, bj));
+      const double den = pd.x * pd.x + pd.y * pd.y;
+      const T inv = from_d2<T>(make_double2(pd.x / den, -pd.y / den));
+      const T vn = cmul(a, inv);
+      if (lane == ip) rused = true;
+      if (lane == bj) cused = true;
+      // (4) residual column bj
+      const double qx = readlane(sx, bj), qy = readlane(sy, bj), qz = readlane(sz, bj),
+                   qw = readlane(sw, bj);
+      T c = eval_entry<T>(kern, k, tx, ty, tz, qx, qy, qz, qw);
+#pragma unroll
+      for (int l = 0; l < RC; ++l)
+        if (l < kk) cfms(c, readlane(v[l], bj), u[l]);
+      const T un = hr ? c : czero<T>();
+      // (5) norms and cross term
+      const double nu2 = wave_sum(abs2(un)), nv2 = wave_sum(abs2(vn));
+      double2 s = make_double2(0.0, 0.0);
+      const double2 und = to_d2(un), vnd = to_d2(vn);
+#pragma unroll
+      for (int l = 0; l < RC; ++l) {
+        if (l < kk) {
+          const double2 vl = to_d2(v[l]);
+          double2 dv = make_double2(vl.x * vnd.x + vl.y * vnd.y, vl.x * vnd.y - vl.y * vnd.x);
+          dv.x = wave_sum(dv.x);
+          dv.y = wave_sum(dv.y);
+          const double2 ul = to_d2(u[l]);
+          // s += conj(u_l[i]) * dv
+          s.x += ul.x * dv.x + ul.y * dv.y;
+          s.y += ul.x * dv.y - ul.y * dv.x;
+        }
+      }
+      const double cross = wave_sum(und.x * s.x - und.y * s.y);
+      nrm2 = nrm2 + 2.0 * cross + nu2 * nv2;
+#pragma unroll
+      for (int l = 0; l < RC; ++l)
+        if (l == kk) {
+          u[l] = un;
+          v[l] = vn;
+        }
+      kk += 1;
+      // (6) stopping rule, (7) next pivot row
+      if (__builtin_amdgcn_readfirstlane(sqrt(nu2) * sqrt(nv2) <= tol * sqrt(nrm2) ? 1 : 0)) {
+        st = ACA_CONVERGED;
+        break;
+      }
+      double bu = rused ? -1.0 : abs2(un);
+      int bi = rused ? INT_MAX : lane;
+      wave_amax(bu, bi);
+      bi = __builtin_amdgcn_readfirstlane(bi);
+      if (bi == INT_MAX) {
+        st = ACA_CONVERGED;
+        break;
+      }
+      ip = bi;
+    }
+    // factors go to a slot of exactly kk columns (or twice RC for a block continued by the
+    // workgroup kernel) taken from the device pool; if the pool is exhausted the block is
+    // restarted from scratch by the workgroup kernel
+    const int scap = st == ACA_OVERFLOW ? min(d.rcap, 2 * RC) : kk;
+    T* Ug = nullptr;
+    T* Vg = nullptr;
+    if (scap > 0 && st != ACA_DENSE) {
+      const int64_t need = (int64_t)scap * (m + n);
+      // every lane issues the atomic (no lane-dependent branch); only lane 0 adds `need`, and
+      // lane 0's return value is the slot offset
+      unsigned long long off =
+          atomicAdd(gtop, lane == 0 ? (unsigned long long)need : 0ull);
+      off = ((unsigned long long)(unsigned int)__builtin_amdgcn_readlane((int)(off >> 32), 0) << 32) |
+            (unsigned int)__builtin_amdgcn_readlane((int)(off & 0xffffffffu), 0);
+      if (gpool != nullptr && (int64_t)off + need <= gcap) {
+        Ug = gpool + off;
+        Vg = Ug + (int64_t)scap * m;
+      } else {
+        st = ACA_OVERFLOW;
+        kk = 0;
+        ip = 0;
+        nrm2 = 0.0;
+        rused = false;
+        cused = false;
+      }
+    }
+    if (Ug != nullptr) {
+#pragma unroll
+      for (int l = 0; l < RC; ++l) {
+        if (l < kk) {
+          if (hr) Ug[(int64_t)l * m + lane] = u[l];
+          if (hc) Vg[(int64_t)l * n + lane] = v[l];
+        }
+      }
+    }
+    if (st == ACA_OVERFLOW) {
+      uint8_t* rf = flags + d.foff;
+      if (hr) rf[lane] = rused ? 1 : 0;
+      if (hc) rf[m + lane] = cused ? 1 : 0;
+    }
+    if (lane == 0) {
+      desc[b].U = Ug;
+      desc[b].V = Vg;
+      desc[b].cap = Ug ? scap : 0;
+    }
+    if (lane == 0) {
+      rank[b] = kk;
+      ipiv[b] = ip;
+      norm2[b] = nrm2;
+      status[b] = st;
+    }
   }
 }
 
 template <class T>
-void launch_aca(const FarDesc* d, const int32_t* order, int nb, int* counter, const double* X,
-                const double* Y, const double* Z, const double* W, int kern, double k, double tol,
-                uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status, double* norm2,
-                int fresh, hipStream_t s) {
+void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
+                     const double* Y, const double* Z, const double* W, int kern, double k,
+                     double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
+                     double* norm2, T* gpool, int64_t gcap, unsigned long long* gtop,
+                     hipStream_t s) {
   if (nb <= 0) return;
   int dev = 0, ncu = 0;
   HMX_HIP(hipGetDevice(&dev));
   HMX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  int per_cu = 0;
-  HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, aca_kernel<T>, WG, 0));
-  if (per_cu < 1) per_cu = 1;
-  int grid = ncu * per_cu;
-  if (grid > nb) grid = nb;
-  hipLaunchKernelGGL(aca_kernel<T>, dim3(grid), dim3(WG), 0, s, d, order, nb, counter, X, Y, Z, W,
-                     kern, k, tol, flags, rank, ipiv, status, norm2, fresh);
+  const int grid = std::min((nb + NWAVE - 1) / NWAVE, 8 * ncu);
+  hipLaunchKernelGGL((aca_wave_kernel<T, ACA_WAVE_RC>), dim3(grid), dim3(WG), 0, s, d, order, nb,
+                     X, Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2, gpool, gcap,
+                     gtop);
+  HMX_LAUNCHED();
+}
+
+template <class T>
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
+                const double* Y, const double* Z, const double* W, int kern, double k, double tol,
+                uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status, double* norm2,
+                int fresh, T* gpool, int64_t gcap, unsigned long long* gtop, hipStream_t s) {
+  if (nb <= 0) return;
+  int dev = 0, ncu = 0;
+  HMX_HIP(hipGetDevice(&dev));
+  HMX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (big) {
+    int grid = std::min(nb, 2 * ncu);
+    hipLaunchKernelGGL((aca_kernel<T, 512>), dim3(grid), dim3(512), 0, s, d, order, nb, counter,
+                       X, Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
+                       gcap, gtop);
+  } else {
+    int grid = std::min(nb, 8 * ncu);
+    hipLaunchKernelGGL((aca_kernel<T, WG>), dim3(grid), dim3(WG), 0, s, d, order, nb, counter, X,
+                       Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2, fresh, gpool, gcap,
+                       gtop);
+  }
   HMX_LAUNCHED();
 }
 
@@ -256,41 +602,18 @@ void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* 
   HMX_LAUNCHED();
 }
 
-// Final compaction: low-rank blocks' U (m x r) and V (n x r) into their final offsets.
-template <class T>
-__global__ void __launch_bounds__(WG) compact_kernel(const FarDesc* __restrict__ d,
-                                                     const FarRec* __restrict__ rec,
-                                                     const int32_t* __restrict__ rank,
-                                                     T* __restrict__ dst) {
-  const int b = blockIdx.x;
-  const FarRec f = rec[b];
-  if (f.dense) return;
-  const FarDesc a = d[b];
-  const int64_t r = rank[b];
-  const int64_t nu = r * a.m, nv = r * a.n;
-  const T* su = (const T*)a.U;
-  const T* sv = (const T*)a.V;
-  for (int64_t e = threadIdx.x; e < nu; e += WG) dst[f.uoff + e] = su[e];
-  for (int64_t e = threadIdx.x; e < nv; e += WG) dst[f.voff + e] = sv[e];
-}
-
-template <class T>
-void launch_compact(const FarDesc* d, const FarRec* rec, const int32_t* rank, int64_t nb, T* dst,
-                    hipStream_t s) {
-  if (nb <= 0) return;
-  hipLaunchKernelGGL(compact_kernel<T>, dim3((unsigned)nb), dim3(WG), 0, s, d, rec, rank, dst);
-  HMX_LAUNCHED();
-}
-
 #define HMX_INST(T)                                                                              \
-  template void launch_aca<T>(const FarDesc*, const int32_t*, int, int*, const double*,          \
+  template void launch_aca_wave<T>(FarDesc*, const int32_t*, int, const double*,                \
+                                   const double*, const double*, const double*, int, double,     \
+                                   double, uint8_t*, int32_t*, int32_t*, int32_t*, double*, T*,  \
+                                   int64_t, unsigned long long*, hipStream_t);                   \
+  template void launch_aca<T>(FarDesc*, const int32_t*, int, int*, int, const double*,           \
                               const double*, const double*, const double*, int, double, double,  \
-                              uint8_t*, int32_t*, int32_t*, int32_t*, double*, int,              \
-                              hipStream_t);                                                      \
+                              uint8_t*, int32_t*, int32_t*, int32_t*, double*, int, T*, int64_t, \
+                              unsigned long long*, hipStream_t);                                 \
   template void launch_copy_factors<T>(const FarDesc*, const FarDesc*, const int32_t*,           \
                                        const int32_t*, int, hipStream_t);                        \
-  template void launch_compact<T>(const FarDesc*, const FarRec*, const int32_t*, int64_t, T*,    \
-                                  hipStream_t);
+
 HMX_INST(double2)
 HMX_INST(float2)
 #undef HMX_INST

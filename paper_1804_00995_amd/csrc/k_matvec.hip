@@ -44,7 +44,6 @@ __device__ __forceinline__ float2 wave_sum2(float2 v) {
 // t_b[l] = sum_j V_b[j, l] xp[s_b + j]; wave w handles columns l = w, w + 4, ...
 template <class T>
 __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ rec,
-                                                    const T* __restrict__ pool,
                                                     const T* __restrict__ xp, T* __restrict__ t) {
   const FarRec f = rec[blockIdx.x];
   T* tb = t + f.toff;
@@ -53,7 +52,7 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
     for (int j = threadIdx.x; j < f.n; j += WG) tb[j] = xs[j];
     return;
   }
-  const T* V = pool + f.voff;
+  const T* V = (const T*)f.V;
   const int n = f.n, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   int l = w;
   for (; l + NWAVE < f.r; l += 2 * NWAVE) {
@@ -82,9 +81,9 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
 }
 
 template <class T>
-void launch_far_vt(const FarRec* rec, int64_t nf, const T* pool, const T* xp, T* t, hipStream_t s) {
+void launch_far_vt(const FarRec* rec, int64_t nf, const T* xp, T* t, hipStream_t s) {
   if (nf <= 0) return;
-  hipLaunchKernelGGL(far_vt_kernel<T>, dim3((unsigned)nf), dim3(WG), 0, s, rec, pool, xp, t);
+  hipLaunchKernelGGL(far_vt_kernel<T>, dim3((unsigned)nf), dim3(WG), 0, s, rec, xp, t);
   HMX_LAUNCHED();
 }
 
@@ -97,7 +96,7 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
     const int32_t* __restrict__ near_sb, const int32_t* __restrict__ near_n,
     const int64_t* __restrict__ near_off, const T* __restrict__ near_pool,
     const int64_t* __restrict__ far_ptr, const int32_t* __restrict__ far_list,
-    const FarRec* __restrict__ far, const T* __restrict__ far_pool, const T* __restrict__ tbuf,
+    const FarRec* __restrict__ far, const T* __restrict__ tbuf,
     const T* __restrict__ xp, const int32_t* __restrict__ perm, T* __restrict__ y) {
   __shared__ T part[NWAVE][MAX_LEAF_CHUNKS * WAVE];
   const int leaf = blockIdx.x;
@@ -129,7 +128,7 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
     } else {
       const FarRec f = far[far_list[f0 + (it - nn)]];
       const int o = tb - f.tb;
-      const T* U = far_pool + f.uoff + o;
+      const T* U = (const T*)f.U + o;
       const T* tt = tbuf + f.toff;
 #pragma unroll 4
       for (int l = 0; l < f.r; ++l) {
@@ -162,11 +161,10 @@ void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegi
                        const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
                        const int32_t* near_n, const int64_t* near_off, const T* near_pool,
                        const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
-                       const T* far_pool, const T* tbuf, const T* xp, const int32_t* perm, T* y,
-                       hipStream_t s) {
+                       const T* tbuf, const T* xp, const int32_t* perm, T* y, hipStream_t s) {
   hipLaunchKernelGGL(leaf_apply_kernel<T>, dim3(n_leaves), dim3(WG), 0, s, leaves, nbegin, nend,
-                     near_ptr, near_sb, near_n, near_off, near_pool, far_ptr, far_list, far,
-                     far_pool, tbuf, xp, perm, y);
+                     near_ptr, near_sb, near_n, near_off, near_pool, far_ptr, far_list, far, tbuf,
+                     xp, perm, y);
   HMX_LAUNCHED();
 }
 
@@ -240,12 +238,12 @@ void launch_dense_otf(const double* X, const double* Y, const double* Z, const d
 
 #define HMX_INST(T)                                                                              \
   template void launch_gather<T>(const T*, const int32_t*, T*, int64_t, hipStream_t);            \
-  template void launch_far_vt<T>(const FarRec*, int64_t, const T*, const T*, T*, hipStream_t);   \
+  template void launch_far_vt<T>(const FarRec*, int64_t, const T*, T*, hipStream_t);             \
   template void launch_leaf_apply<T>(int, const int32_t*, const int32_t*, const int32_t*,        \
                                      const int64_t*, const int32_t*, const int32_t*,             \
                                      const int64_t*, const T*, const int64_t*, const int32_t*,   \
-                                     const FarRec*, const T*, const T*, const T*,                \
-                                     const int32_t*, T*, hipStream_t);                           \
+                                     const FarRec*, const T*, const T*, const int32_t*, T*,      \
+                                     hipStream_t);                                               \
   template void launch_dense_otf<T>(const double*, const double*, const double*, const double*,  \
                                     int64_t, int, double, const T*, T*, T*, hipStream_t);
 HMX_INST(double2)

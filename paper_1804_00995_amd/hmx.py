@@ -75,8 +75,15 @@ _lib.hmx_destroy.argtypes = [_P]
 _lib.hmx_destroy.restype = None
 _lib.hmx_last_error.argtypes = []
 _lib.hmx_last_error.restype = C.c_char_p
+_lib.hmx_release_cache.argtypes = []
+_lib.hmx_release_cache.restype = None
 
-EXPORTED = sorted(list(_sig) + ["hmx_destroy", "hmx_last_error"])
+EXPORTED = sorted(list(_sig) + ["hmx_destroy", "hmx_last_error", "hmx_release_cache"])
+
+
+def release_cache():
+    """Return the library's cached free device blocks to the HIP runtime."""
+    _lib.hmx_release_cache()
 
 
 class HmxError(RuntimeError):
