@@ -134,6 +134,8 @@ typedef struct {
   int32_t precision, is_dense;
   double t_tree_ms, t_blocks_ms, t_near_ms, t_aca_ms, t_total_ms; /* build phases (events) */
   int64_t kernel_evals;    /* Green-kernel evaluations spent in the build */
+  int64_t factor_bytes;    /* device bytes of the slots holding far-block factors (used part) */
+  int64_t predicted_entries; /* learned layout: sum of r_alloc * (m + n) over far blocks */
 } hmx_info_t;
 
 /* Sizes, counts and build timings of an operator. */
@@ -154,6 +156,45 @@ hmx_status hmx_export_blocks(const hmx_op* op, int64_t* near_rc, int64_t* far_rc
  * V (n x r) column-major with block ~ U V^T; for a dense far block U receives the m x n block
  * and V is untouched.  *rank receives r (or -1 for dense). */
 hmx_status hmx_export_far(const hmx_op* op, int64_t b, void* U, void* V, int32_t* rank);
+
+/* ------------------------------------------------------------------ learned block ranks
+ * The paper shows the local rank of each block of its H-matrix (Section 5.4, the spy plot of
+ * the compressed acoustic operator) but does not predict it.  libhmx can lay out the factor
+ * storage from ranks predicted by a small network: 4 -> 64 -> 64 -> 1 with ReLU, FP32, input the
+ * standardized block features [log2 m, log2 n, ln(dist / max diam), k max diam / (2 pi)], output
+ * ln(1 + rank).  Parameters are one float vector of HMX_MLP_NPARAMS entries:
+ *   W1 (64 x 4, row-major) | b1 (64) | W2 (64 x 64, row-major) | b2 (64) | W3 (64) | b3 (1).
+ * `norm` is 8 floats: the 4 feature means, then the 4 feature standard deviations (> 0). */
+#define HMX_MLP_NPARAMS 4545
+
+/* Raw (unstandardized) features of the operator's far blocks, in the order of
+ * hmx_export_blocks: feat host, n_far x 4 floats. */
+hmx_status hmx_far_features(const hmx_op* op, float* feat);
+
+/* Predicted ln(1 + rank) of n blocks: theta, norm host; feat device (n x 4 raw features);
+ * out device (n floats).  Synchronous. */
+hmx_status hmx_mlp_predict(const float* theta, const float* norm, const float* feat, int64_t n,
+                           float* out, void* stream);
+
+/* Mean squared error (1/n) sum (o - y)^2 of the network on n samples and its gradient:
+ * theta host; X device (n x 4 standardized features); y device (n targets); grad host
+ * (HMX_MLP_NPARAMS); loss host.  n <= 2^24.  Synchronous. */
+hmx_status hmx_mlp_loss_grad(const float* theta, const float* X, const float* y, int64_t n,
+                             float* grad, float* loss, void* stream);
+
+/* Trains the network with Adam (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on minibatches of
+ * `batch` consecutive samples, `epochs` passes in order (shuffle beforehand if wanted).
+ * theta host, initial values in, trained values out; X, y device as in hmx_mlp_loss_grad;
+ * loss_hist host (epochs floats, mean batch loss per epoch) or NULL.  Synchronous. */
+hmx_status hmx_mlp_train(float* theta, const float* X, const float* y, int64_t n, int32_t epochs,
+                         int32_t batch, float lr, float* loss_hist, void* stream);
+
+/* Sets the process-wide model used by builds with rank_model = HMX_RANK_LEARNED: a far block
+ * gets a first slot of r_alloc = min(rank cap, ceil(alpha * max(exp(pred) - 1, 0)) + beta)
+ * columns (at least 1), laid out contiguously before ACA runs; a block that needs more continues
+ * in a growth pool, with the same pivots and factors as plain adaptive ACA.  theta, norm host
+ * (copied); theta NULL clears the model.  alpha > 0, beta >= 0. */
+hmx_status hmx_set_rank_model(const float* theta, const float* norm, float alpha, float beta);
 
 /* Frees the operator and all of its device memory; NULL is accepted. */
 void hmx_destroy(hmx_op* op);

@@ -22,6 +22,7 @@ UNITS = [
     ("hmx_api.hip", False),
     ("hmx_build.hip", False),
     ("hmx_mem.hip", False),
+    ("hmx_mlp.hip", False),
     ("k_quad.hip", True),
     ("k_scan.hip", False),
     ("k_tree.hip", True),

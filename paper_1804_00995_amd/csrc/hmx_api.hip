@@ -24,6 +24,12 @@ hmx_status fail(hmx_status c, const std::string& m) {
   return c;
 }
 
+}  // namespace
+
+void hmx::set_last_error(const std::string& m) { g_err = m; }
+
+namespace {
+
 #define API_TRY try {
 #define API_CATCH                                            \
   }                                                          \
@@ -264,6 +270,8 @@ hmx_status hmx_info(const hmx_op* op, hmx_info_t* out) {
   out->t_aca_ms = op->t_aca;
   out->t_total_ms = op->t_total;
   out->kernel_evals = op->kernel_evals;
+  out->factor_bytes = op->pool_used_bytes;
+  out->predicted_entries = op->predicted_entries;
   return HMX_OK;
 }
 

@@ -277,6 +277,41 @@ void build_far(hmx_op* op, hipStream_t s) {
     // blocks their first slot plus one doubling
     sum_mn += is_wave[b] ? 12 * mn : 2 * (int64_t)d.cap * mn;
   }
+  // learned layout: every block gets a static slot of the predicted size, laid out on the host;
+  // the device pool then only serves blocks that outgrow their prediction
+  DevBuf<T> static_pool;
+  if (op->p.rank_model == HMX_RANK_LEARNED && nf > 0) {
+    const RankModel rm = get_rank_model();
+    HMX_REQUIRE(rm.set, HMX_EINVAL, "rank_model is learned but no model was set (hmx_set_rank_model)");
+    DevBuf<float> feat(4 * nf), pred(nf), th(MLP_NPARAMS), nm(8);
+    HMX_HIP(hipMemcpyAsync(th.p, rm.theta, MLP_NPARAMS * 4, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(nm.p, rm.norm, 8 * 4, hipMemcpyHostToDevice, s));
+    launch_mlp_features(op->farL.p, nf, op->nbegin.p, op->nend.p, op->box.p, op->k, feat.p, s);
+    launch_mlp_predict(th.p, nm.p, feat.p, nf, pred.p, s);
+    std::vector<float> hp;
+    to_host(hp, pred.p, nf, s);
+    int64_t total = 0;
+    for (int64_t b = 0; b < nf; ++b) {
+      FarDesc& d = desc[b];
+      const double rhat = std::expm1((double)hp[b]) * op->p.force_pred_scale;
+      int64_t ra = (int64_t)std::ceil(rm.alpha * std::max(rhat, 0.0)) + (int64_t)std::lround(rm.beta);
+      ra = std::min<int64_t>(std::max<int64_t>(ra, d.rcap > 0 ? 1 : 0), d.rcap);
+      d.cap = (int32_t)ra;
+      total += ra * ((int64_t)d.m + d.n);
+    }
+    static_pool.alloc(std::max<int64_t>(total, 1));
+    int64_t off = 0;
+    for (int64_t b = 0; b < nf; ++b) {
+      FarDesc& d = desc[b];
+      if (d.cap == 0) continue;
+      d.U = static_pool.p + off;
+      off += (int64_t)d.cap * d.m;
+      d.V = static_pool.p + off;
+      off += (int64_t)d.cap * d.n;
+    }
+    sum_mn = std::max<int64_t>(total / 4, (int64_t)(64 << 20) / (int64_t)sizeof(T));
+    op->predicted_entries = total;
+  }
   // device pool for factor slots, within the free memory
   size_t free_b = 0, total_b = 0;
   HMX_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -472,7 +507,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   for (int64_t b = 0, q = 0; b < nf; ++b)
     if (rec[b].dense) rec[b].U = (const T*)op->dense_pool.p + doff[q++];
   const int64_t used = (int64_t)read1(gtop.p, s);
-  op->pool_used_bytes = std::min(used, gcap) * (int64_t)sizeof(T);
+  op->pool_used_bytes = std::min(used, gcap) * (int64_t)sizeof(T) + (int64_t)static_pool.bytes();
   for (auto& p : extra_pools) op->pool_used_bytes += (int64_t)p.bytes();
   if (op->p.pool_limit_bytes > 0 &&
       op->pool_used_bytes + (int64_t)op->near_pool.bytes() + (int64_t)op->dense_pool.bytes() >
@@ -487,6 +522,14 @@ void build_far(hmx_op* op, hipStream_t s) {
     gpool.p = nullptr;
     gpool.n = 0;
     op->far_pools.push_back(std::move(g));
+    if (static_pool.p) {
+      DevBuf<unsigned char> e;
+      e.p = (unsigned char*)static_pool.p;
+      e.n = static_pool.bytes();
+      static_pool.p = nullptr;
+      static_pool.n = 0;
+      op->far_pools.push_back(std::move(e));
+    }
     for (auto& p : extra_pools) {
       DevBuf<unsigned char> e;
       e.p = (unsigned char*)p.p;

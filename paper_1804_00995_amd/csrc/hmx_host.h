@@ -40,6 +40,9 @@ void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 void dev_release_cache();
 
+// Message returned by hmx_last_error on this thread.
+void set_last_error(const std::string& m);
+
 // Owning device buffer (move-only).
 template <class T>
 struct DevBuf {
@@ -182,6 +185,26 @@ void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
 template <class T>
 void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* rank,
                          const int32_t* list, int nlist, hipStream_t s);
+// k_mlp.hip -- block-rank MLP (4 -> 64 -> 64 -> 1, ReLU, FP32)
+constexpr int MLP_IN = 4, MLP_H = 64, MLP_NPARAMS = 4545;
+void launch_mlp_features(const int2* pairs, int64_t n, const int32_t* nbegin, const int32_t* nend,
+                         const double* box, double k, float* feat, hipStream_t s);
+void launch_mlp_predict(const float* theta, const float* norm, const float* feat, int64_t n,
+                        float* out, hipStream_t s);
+size_t mlp_cache_floats(int B);
+void launch_mlp_grad(const float* theta, const float* X, const float* y, int64_t b0, int B,
+                     float* cache, float* grad, hipStream_t s);
+void launch_mlp_adam(float* theta, const float* grad, float* m, float* v, int t, float lr,
+                     hipStream_t s);
+// model used by builds with HMX_RANK_LEARNED (hmx_mlp.hip)
+struct RankModel {
+  bool set = false;
+  float theta[MLP_NPARAMS];
+  float norm[8];
+  float alpha = 1.0f, beta = 0.0f;
+};
+RankModel get_rank_model();
+
 // k_matvec.hip
 template <class T>
 void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, hipStream_t s);
@@ -226,7 +249,8 @@ struct hmx_op {
   hmx::DevBuf<unsigned char> near_pool;
   // far field
   int64_t n_far = 0, far_entries = 0, dense_far = 0, dense_far_entries = 0, max_rank = 0,
-          sum_rank = 0, overflow_blocks = 0, t_len = 0, pool_used_bytes = 0;
+          sum_rank = 0, overflow_blocks = 0, t_len = 0, pool_used_bytes = 0,
+          predicted_entries = 0;
   hmx::DevBuf<int2> farL;
   hmx::DevBuf<hmx::FarRec> far;
   std::vector<hmx::FarRec> far_host;

@@ -484,10 +484,16 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
     // factors go to a slot of exactly kk columns (or twice RC for a block continued by the
     // workgroup kernel) taken from the device pool; if the pool is exhausted the block is
     // restarted from scratch by the workgroup kernel
-    const int scap = st == ACA_OVERFLOW ? min(d.rcap, 2 * RC) : kk;
+    int scap = st == ACA_OVERFLOW ? min(d.rcap, 2 * RC) : kk;
     T* Ug = nullptr;
     T* Vg = nullptr;
-    if (scap > 0 && st != ACA_DENSE) {
+    // a slot laid out in advance (learned layout) is used when it is large enough
+    const bool pre = d.U != nullptr && (st == ACA_OVERFLOW ? d.cap > kk : d.cap >= kk);
+    if (pre && scap > 0 && st != ACA_DENSE) {
+      Ug = (T*)d.U;
+      Vg = (T*)d.V;
+      scap = d.cap;
+    } else if (scap > 0 && st != ACA_DENSE) {
       const int64_t need = (int64_t)scap * (m + n);
       // every lane issues the atomic (no lane-dependent branch); only lane 0 adds `need`, and
       // lane 0's return value is the slot offset

@@ -49,7 +49,7 @@ class Info(C.Structure):
         "dense_far", "dense_far_entries", "max_rank", "sum_rank", "overflow_blocks", "bytes")] + [
         ("precision", C.c_int32), ("is_dense", C.c_int32)] + [
         (n, C.c_double) for n in ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms", "t_total_ms")] + [
-        ("kernel_evals", C.c_int64)]
+        ("kernel_evals", C.c_int64), ("factor_bytes", C.c_int64), ("predicted_entries", C.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -66,7 +66,13 @@ _sig = {
     "hmx_export_tree": [_P, _P, _P, _P, _P, _P, _P, _P],
     "hmx_export_blocks": [_P, _P, _P, _P],
     "hmx_export_far": [_P, _i64, _P, _P, _P],
+    "hmx_far_features": [_P, _P],
+    "hmx_mlp_predict": [_P, _P, _P, _i64, _P, _P],
+    "hmx_mlp_loss_grad": [_P, _P, _P, _i64, _P, _P, _P],
+    "hmx_mlp_train": [_P, _P, _P, _i64, _i32, _i32, C.c_float, _P, _P],
+    "hmx_set_rank_model": [_P, _P, C.c_float, C.c_float],
 }
+MLP_NPARAMS = 4545
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
@@ -212,6 +218,13 @@ class Operator:
         k = r.value
         return U[:m * k].reshape(k, m).T.copy(), V[:n * k].reshape(k, n).T.copy()
 
+    def far_features(self):
+        """Raw features (n_far x 4 float32) of the far blocks, in export_blocks order."""
+        nf = self.info["n_far"]
+        f = np.empty((max(nf, 1), 4), np.float32)
+        _check(_lib.hmx_far_features(self._h, f.ctypes.data_as(_P)))
+        return f[:nf]
+
     def close(self):
         if self._h:
             _lib.hmx_destroy(self._h)
@@ -244,3 +257,55 @@ def build_points(xyzw, kern=HELMHOLTZ, k=0.0, prm: Params | None = None, stream=
     _check(_lib.hmx_build_points(_dev(xyzw, torch.float64, "xyzw"), xyzw.shape[1], kern, float(k),
                                  C.byref(prm), _stream_ptr(stream), C.byref(h)))
     return Operator(h, prm.precision)
+
+
+# ------------------------------------------------------------------------ learned block ranks
+def _f32(a, n=None):
+    a = np.ascontiguousarray(a, np.float32).reshape(-1)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} floats, got {a.size}")
+    return a
+
+
+def mlp_predict(theta, norm, feat, stream=None):
+    """Predicted ln(1 + rank) of blocks with raw features `feat` (device float32 (n, 4))."""
+    import torch
+    theta, norm = _f32(theta, MLP_NPARAMS), _f32(norm, 8)
+    n = feat.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device=feat.device)
+    _check(_lib.hmx_mlp_predict(theta.ctypes.data_as(_P), norm.ctypes.data_as(_P),
+                                _dev(feat, torch.float32, "feat"), n, C.c_void_p(out.data_ptr()),
+                                _stream_ptr(stream)))
+    return out
+
+
+def mlp_loss_grad(theta, X, y, stream=None):
+    """(loss, gradient) of the mean squared error on standardized features X, targets y (device)."""
+    import torch
+    theta = _f32(theta, MLP_NPARAMS)
+    g = np.empty(MLP_NPARAMS, np.float32)
+    loss = C.c_float(0)
+    _check(_lib.hmx_mlp_loss_grad(theta.ctypes.data_as(_P), _dev(X, torch.float32, "X"),
+                                  _dev(y, torch.float32, "y"), X.shape[0], g.ctypes.data_as(_P),
+                                  C.byref(loss), _stream_ptr(stream)))
+    return float(loss.value), g
+
+
+def mlp_train(theta, X, y, epochs=40, batch=4096, lr=1e-3, stream=None):
+    """Adam training on the device; returns (trained theta, mean batch loss per epoch)."""
+    import torch
+    th = _f32(theta, MLP_NPARAMS).copy()
+    hist = np.empty(epochs, np.float32)
+    _check(_lib.hmx_mlp_train(th.ctypes.data_as(_P), _dev(X, torch.float32, "X"),
+                              _dev(y, torch.float32, "y"), X.shape[0], epochs, batch, lr,
+                              hist.ctypes.data_as(_P), _stream_ptr(stream)))
+    return th, hist
+
+
+def set_rank_model(theta=None, norm=None, alpha=1.0, beta=0.0):
+    """Process-wide model for builds with rank_model=RANK_LEARNED (None clears it)."""
+    if theta is None:
+        _check(_lib.hmx_set_rank_model(None, None, 1.0, 0.0))
+        return
+    theta, norm = _f32(theta, MLP_NPARAMS), _f32(norm, 8)
+    _check(_lib.hmx_set_rank_model(theta.ctypes.data_as(_P), norm.ctypes.data_as(_P), alpha, beta))

@@ -209,3 +209,27 @@ def test_full_size_sampled_rows(H):
     rows = np.sort(np.random.default_rng(123).choice(P.shape[0], 384, replace=False))
     yr = oracle.dense_rows(P, W, 1, 40.0, x, rows)
     assert rel(y[rows], yr) <= 1e-3
+
+
+# ------------------------------------------------------------------------------ FP32 mixed (a8)
+@pytest.mark.parametrize("level,k,rows", [(4, 15.0, None), (6, 40.0, 256)])
+def test_fp32_mixed_against_oracle_and_fp64(H, level, k, rows):
+    """FP32 blocks and factors with FP64 distance, phase and ACA norms: error against the
+    FP64 oracle's dense product and against the GPU FP64 H-matrix product."""
+    op32, P, W = build(H, level, kern=1, k=k, tol=1e-3, precision=H.FP32_MIXED)
+    op64, _, _ = build(H, level, kern=1, k=k, tol=1e-3)
+    x = I.complex_vector(P.shape[0], 0)
+    y32 = apply(op32, x, torch.complex64)
+    y64 = apply(op64, x)
+    if rows is None:
+        idx = np.arange(P.shape[0])
+        yr = oracle.dense_matvec(P, W, 1, k, x)
+    else:
+        idx = np.sort(np.random.default_rng(321).choice(P.shape[0], rows, replace=False))
+        yr = oracle.dense_rows(P, W, 1, k, x, idx)
+    e_oracle = rel(y32[idx], yr)
+    e_fp64 = rel(y32, y64)
+    print(f"fp32 vs oracle {e_oracle:.3e}, vs gpu fp64 {e_fp64:.3e}, fp64 vs oracle {rel(y64[idx], yr):.3e}")
+    assert e_oracle <= 1e-3
+    assert e_fp64 <= 1e-3
+    assert op32.info["bytes"] < op64.info["bytes"]
