@@ -287,10 +287,17 @@ static void sort_pairs(const tree_t *T, pairs_t *L)
  *   (3) v_k = R / R_{j_k};
  *   (4) u_k[i] = a(i, j_k) - sum_{l<k} v_l[j_k] u_l[i];
  *   (5) |S_k|_F^2 = |S_{k-1}|_F^2 + 2 Re sum_{l<k} (u_l^H u_k)(v_l^H v_k) + |u_k|^2 |v_k|^2;
- *   (6) stop (keeping term k) when |u_k| |v_k| <= tol |S_k|_F;
+ *   (6) stop (keeping term k) when |u_k| |v_k| <= tol |S_k|_F has held at ACA_STOP_STEPS
+ *       consecutive steps (a zero residual row in between neither counts nor resets);
  *   (7) next pivot row: argmax over unused rows of |u_k[i]|^2 (lowest index on ties).
+ * A single step meeting (6) is not enough: the pivot row can fall where the block is already
+ * well approximated while other rows are not, so that |u_k| |v_k| is small by accident; on an
+ * elongated ellipsoid this stops a 963 x 955 block at rank 8 with 10% error.  Requiring the
+ * rule at two consecutive steps, each with its own pivot row, removes those stops.
  * The rank is capped at rcap = floor(m n / (m + n)); a block not converged at rcap is reported
  * as not converged (the caller stores it dense). */
+#define ACA_STOP_STEPS 2
+
 typedef cplx (*entry_fn)(const void *ctx, int64_t i, int64_t j);
 
 typedef struct {
@@ -322,6 +329,7 @@ static void aca_run(entry_fn a, const void *ctx, int64_t m, int64_t n, double to
     cplx *R = malloc(sizeof(cplx) * (size_t)n);
     double norm2 = 0.0;
     int64_t ik = 0;
+    int hits = 0; /* consecutive steps that met the stopping rule */
     while (1) {
         /* (1) residual row */
         for (int64_t j = 0; j < n; ++j) {
@@ -385,8 +393,12 @@ static void aca_run(entry_fn a, const void *ctx, int64_t m, int64_t n, double to
         F->rank = k + 1;
         /* (6) stopping rule */
         if (sqrt(nu2) * sqrt(nv2) <= tol * sqrt(norm2)) {
-            F->converged = 1;
-            break;
+            if (++hits >= ACA_STOP_STEPS) {
+                F->converged = 1;
+                break;
+            }
+        } else {
+            hits = 0;
         }
         /* (7) next pivot row */
         int64_t nxt = -1;

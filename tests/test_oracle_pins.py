@@ -319,8 +319,9 @@ def test_aca_exact_rank_poly2():
     A = (1 + x @ y.T) ** 2
     assert np.linalg.matrix_rank(A) == 10
     U, V, conv = oracle.aca_dense(A.astype(np.complex128), 1e-12)
-    # the stopping rule needs one term past the exact rank, and that term is at rounding level
-    assert conv and U.shape[1] <= 11
+    # the stopping rule must hold at two consecutive steps: two terms past the exact rank, both
+    # at rounding level
+    assert conv and U.shape[1] <= 12
     assert np.linalg.norm(A - U @ V.T) <= 1e-12 * np.linalg.norm(A)
     U, V, conv = oracle.aca_dense(A.astype(np.complex128), 1e-12, rcap=10)
     assert U.shape[1] == 10
@@ -333,7 +334,7 @@ def test_aca_recovers_random_low_rank(r):
     A = (rng.standard_normal((40, r)) + 1j * rng.standard_normal((40, r))) @ \
         (rng.standard_normal((r, 55)) + 1j * rng.standard_normal((r, 55)))
     U, V, conv = oracle.aca_dense(A, 1e-10)
-    assert conv and U.shape[1] <= r + 1
+    assert conv and U.shape[1] <= r + 2
     assert np.linalg.norm(A - U @ V.T) <= 1e-11 * np.linalg.norm(A)
 
 
@@ -421,4 +422,19 @@ def test_hmatvec_poly2_exact():
     y = K @ x
     assert np.linalg.norm(H.matvec(x) - y) <= 1e-11 * np.linalg.norm(y)
     _, _, ranks = H.blocks()
-    assert ranks.max() <= 11
+    assert ranks.max() <= 12
+
+
+def test_hmatvec_elongated_ellipsoid_within_tolerance():
+    """Mesh 45 of the seeded 64-ellipsoid batch (semi-axes 1.45, 1.24, 0.75; 43 740 points,
+    k = 10.9): with the stopping rule met at a single step, one far block stops at rank 8 with 10%
+    error and the product is off by 2.7e-3 on sampled rows.  Brute force on 512 seeded rows."""
+    d = I.batch_ellipsoids(64, seed=0)[45]
+    v, f = I.batch_mesh(d)
+    P, W = oracle.quad_points(v, f, *I.rule_3pt())
+    x = I.complex_vector(P.shape[0], d["seed"])
+    H = oracle.HMatrix(P, W, oracle.HELMHOLTZ, d["k"], leaf=64, tol=1e-3)
+    y = H.matvec(x)
+    rows = np.sort(np.random.default_rng(1045).choice(P.shape[0], 512, replace=False))
+    yr = oracle.dense_rows(P, W, oracle.HELMHOLTZ, d["k"], x, rows)
+    assert np.linalg.norm(y[rows] - yr) <= 1e-3 * np.linalg.norm(yr)
