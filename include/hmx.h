@@ -59,7 +59,8 @@ typedef enum {
 } hmx_precision;
 
 typedef enum {
-  HMX_RANK_ADAPTIVE = 0, /* plain adaptive ACA: factors grow in place, then compacted */
+  HMX_RANK_ADAPTIVE = 0, /* plain adaptive ACA: each block's factors grow in slots taken from a
+                            device pool as its rank grows */
   HMX_RANK_LEARNED = 1   /* storage laid out from the rank MLP's prediction, adaptive
                             continuation for blocks the prediction under-sizes */
 } hmx_rank_model;
@@ -113,6 +114,35 @@ hmx_status hmx_build(const double* vtx, int64_t n_vtx, const int32_t* tri, int64
 hmx_status hmx_build_points(const double* xyzw, int64_t M, int32_t kern, double k,
                             const hmx_params* p, void* stream, hmx_op** out);
 
+/* One surface of a batch: vtx, tri device arrays as in hmx_build, and the surface's wavenumber. */
+typedef struct {
+  const double* vtx;
+  int64_t n_vtx;
+  const int32_t* tri;
+  int64_t n_tri;
+  double k;
+} hmx_mesh;
+
+/* Builds one operator for n_meshes independent surfaces that share the quadrature rule, the
+ * kernel and the parameters (each surface keeps its own wavenumber).  The result is the
+ * block-diagonal operator diag(K_0, ..., K_{n-1}) on the concatenated points: the points of mesh
+ * i occupy [off_i, off_{i+1}) with off_0 = 0 and off_{i+1} = off_i + n_q * meshes[i].n_tri, and
+ * the surfaces never interact (each gets its own cluster tree under a common forest, and blocks
+ * pair clusters of one surface only).  All surfaces are built and applied together, so one set
+ * of launches serves the whole batch.  Vectors for hmx_matvec are the per-mesh vectors
+ * concatenated in mesh order; each slice is that mesh's product K_i x_i.  meshes host array.
+ * Requires p->tol > 0 (the dense form is the single-mesh hmx_build).  Errors: as hmx_build for
+ * each mesh, HMX_EINVAL for n_meshes < 1 or tol <= 0, HMX_EUNSUPPORTED for more than 2^23 - 1
+ * points in total.  Synchronous. */
+hmx_status hmx_build_batch(const hmx_mesh* meshes, int32_t n_meshes, const double* q_bary,
+                           const double* q_w, int32_t n_q, int32_t kern, const hmx_params* p,
+                           void* stream, hmx_op** out);
+
+/* Mesh offsets of an operator: *n_meshes receives the number of meshes (1 for operators built
+ * by hmx_build / hmx_build_points); off (host, may be NULL) receives n_meshes + 1 offsets when
+ * cap >= n_meshes + 1, else HMX_EINVAL. */
+hmx_status hmx_mesh_offsets(const hmx_op* op, int64_t* off, int32_t cap, int32_t* n_meshes);
+
 /* y = K x (Section 5.3: the compressed matrix applied through the product).
  *   x, y device, M complex entries each (c128 for FP64 operators, c64 for FP32 ones), in the
  *   original point order; x and y must not alias.
@@ -121,6 +151,16 @@ hmx_status hmx_build_points(const double* xyzw, int64_t M, int32_t kern, double 
  * the same operator must not overlap in time (different operators are independent).
  * Errors: HMX_EINVAL for null pointers. */
 hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream);
+
+/* Product replay: hmx_matvec(op, x, y) captured once into a HIP graph (fixed operator and
+ * vector addresses) and replayed with one launch per call.  The graph holds kernels only.
+ * hmx_graph_create captures on a private stream and instantiates (synchronous); hmx_graph_launch
+ * enqueues `reps` replays on `stream` (asynchronous); the operator must outlive the graph and
+ * replays follow the same no-overlap rule as hmx_matvec. */
+typedef struct hmx_graph hmx_graph;
+hmx_status hmx_graph_create(const hmx_op* op, const void* x, void* y, hmx_graph** out);
+hmx_status hmx_graph_launch(hmx_graph* g, int32_t reps, void* stream);
+void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
 
 typedef struct {
   int64_t n_points, n_nodes, n_leaves, n_near, n_far;

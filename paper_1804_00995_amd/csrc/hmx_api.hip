@@ -216,11 +216,9 @@ hmx_status hmx_build_points(const double* xyzw, int64_t M, int32_t kern, double 
   API_CATCH
 }
 
-hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream) {
-  API_TRY
-  HMX_REQUIRE(op && x && y, HMX_EINVAL, "null pointer");
-  HMX_REQUIRE(x != y, HMX_EINVAL, "x and y must not alias");
-  hipStream_t s = as_stream(stream);
+namespace {
+// The product's launches (no synchronisation, no allocation: capturable).
+void enqueue_matvec(const hmx_op* op, const void* x, void* y, hipStream_t s) {
   if (op->dense) {
     if (op->prec == HMX_FP64)
       launch_dense_otf<double2>(op->X.p, op->Y.p, op->Z.p, op->W.p, op->M, op->kern, op->k,
@@ -228,7 +226,7 @@ hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream) {
     else
       launch_dense_otf<float2>(op->X.p, op->Y.p, op->Z.p, op->W.p, op->M, op->kern, op->k,
                                (const float2*)x, (float2*)op->partial.p, (float2*)y, s);
-    return HMX_OK;
+    return;
   }
   auto run = [&](auto tag) {
     using T = decltype(tag);
@@ -242,8 +240,116 @@ hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream) {
   };
   if (op->prec == HMX_FP64) run(double2{});
   else run(float2{});
+}
+}  // namespace
+
+hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream) {
+  API_TRY
+  HMX_REQUIRE(op && x && y, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(x != y, HMX_EINVAL, "x and y must not alias");
+  enqueue_matvec(op, x, y, as_stream(stream));
   return HMX_OK;
   API_CATCH
+}
+
+hmx_status hmx_graph_create(const hmx_op* op, const void* x, void* y, hmx_graph** out) {
+  API_TRY
+  HMX_REQUIRE(op && x && y && out, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(x != y, HMX_EINVAL, "x and y must not alias");
+  auto g = std::make_unique<hmx_graph>();
+  hipStream_t cs = nullptr;
+  HMX_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  try {
+    HMX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_matvec(op, x, y, cs);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(cs, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    HMX_HIP(hipStreamEndCapture(cs, &g->graph));
+    HMX_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  } catch (...) {
+    (void)hipStreamDestroy(cs);
+    throw;
+  }
+  HMX_HIP(hipStreamDestroy(cs));
+  *out = g.release();
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_graph_launch(hmx_graph* g, int32_t reps, void* stream) {
+  API_TRY
+  HMX_REQUIRE(g && g->exec, HMX_EINVAL, "null graph");
+  HMX_REQUIRE(reps >= 0, HMX_EINVAL, "reps must be >= 0");
+  for (int32_t r = 0; r < reps; ++r) HMX_HIP(hipGraphLaunch(g->exec, as_stream(stream)));
+  return HMX_OK;
+  API_CATCH
+}
+
+void hmx_graph_destroy(hmx_graph* g) { delete g; }
+
+hmx_status hmx_build_batch(const hmx_mesh* meshes, int32_t n_meshes, const double* q_bary,
+                           const double* q_w, int32_t n_q, int32_t kern, const hmx_params* p,
+                           void* stream, hmx_op** out) {
+  API_TRY
+  HMX_REQUIRE(meshes && out, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(n_meshes >= 1, HMX_EINVAL, "n_meshes must be >= 1");
+  hmx_params prm = resolve(p);
+  HMX_REQUIRE(prm.tol > 0, HMX_EINVAL, "a batch operator needs tol > 0");
+  Rule r = make_rule(q_bary, q_w, n_q);
+  auto op = std::make_unique<hmx_op>();
+  op->mesh_off.assign(1, 0);
+  for (int32_t i = 0; i < n_meshes; ++i) {
+    const hmx_mesh& m = meshes[i];
+    HMX_REQUIRE(m.vtx && m.tri, HMX_EINVAL, "null mesh pointer");
+    HMX_REQUIRE(m.n_vtx >= 1 && m.n_tri >= 1, HMX_EINVAL, "empty mesh");
+    check_build_args(kern, m.k);
+    HMX_REQUIRE(m.n_tri <= (int64_t(1) << 23), HMX_EUNSUPPORTED,
+                "H-matrix mode supports at most 2^23 - 1 points");
+    op->mesh_off.push_back(op->mesh_off.back() + m.n_tri * n_q);
+    op->mesh_k.push_back(m.k);
+  }
+  hipStream_t s = as_stream(stream);
+  op->M = op->mesh_off.back();
+  HMX_REQUIRE(op->M < (int64_t(1) << 23), HMX_EUNSUPPORTED,
+              "H-matrix mode supports at most 2^23 - 1 points");
+  op->kern = kern;
+  op->k = op->mesh_k[0];
+  op->p = prm;
+  op->prec = prm.precision;
+  op->X.alloc(op->M);
+  op->Y.alloc(op->M);
+  op->Z.alloc(op->M);
+  op->W.alloc(op->M);
+  DevBuf<int> err(1);
+  fill_i32(err.p, 0, 1, s);
+  for (int32_t i = 0; i < n_meshes; ++i) {
+    const int64_t o = op->mesh_off[i];
+    launch_quad(meshes[i].vtx, meshes[i].n_vtx, meshes[i].tri, meshes[i].n_tri, r, op->X.p + o,
+                op->Y.p + o, op->Z.p + o, op->W.p + o, err.p, s);
+  }
+  int e = read1(err.p, s);
+  HMX_REQUIRE(!(e & 1), HMX_EINVAL, "triangle vertex index out of range");
+  HMX_REQUIRE(!(e & 2), HMX_EINVAL, "non-finite vertex coordinate");
+  finish_build(op.get(), s);
+  *out = op.release();
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_mesh_offsets(const hmx_op* op, int64_t* off, int32_t cap, int32_t* n_meshes) {
+  if (!op || !n_meshes) return fail(HMX_EINVAL, "null pointer");
+  const int32_t n = (int32_t)op->mesh_off.size() - 1;
+  if (off) {
+    if (cap < n + 1) return fail(HMX_EINVAL, "offset array too small");
+    std::memcpy(off, op->mesh_off.data(), sizeof(int64_t) * (n + 1));
+  }
+  *n_meshes = n;
+  return HMX_OK;
 }
 
 hmx_status hmx_info(const hmx_op* op, hmx_info_t* out) {

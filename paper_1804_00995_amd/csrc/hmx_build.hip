@@ -73,15 +73,27 @@ void build_tree(hmx_op* op, hipStream_t s) {
       nleft(cap);
   DevBuf<double> box(6 * cap);
   DevBuf<int> d_next(1);
+  // level 0: one root per mesh (a single mesh has one root spanning all points)
+  const int nroot = (int)op->mesh_off.size() - 1;
   {
-    int32_t root[4] = {0, (int32_t)M, 0, -1};
-    HMX_HIP(hipMemcpyAsync(nbegin.p, &root[0], 4, hipMemcpyHostToDevice, s));
-    HMX_HIP(hipMemcpyAsync(nend.p, &root[1], 4, hipMemcpyHostToDevice, s));
-    HMX_HIP(hipMemcpyAsync(level.p, &root[2], 4, hipMemcpyHostToDevice, s));
-    HMX_HIP(hipMemcpyAsync(parent.p, &root[3], 4, hipMemcpyHostToDevice, s));
+    std::vector<int32_t> rb(nroot), re(nroot), rl(nroot, 0), rp(nroot, -1);
+    for (int i = 0; i < nroot; ++i) {
+      rb[i] = (int32_t)op->mesh_off[i];
+      re[i] = (int32_t)op->mesh_off[i + 1];
+    }
+    if ((size_t)nroot > cap) {
+      cap = 2 * (size_t)nroot;
+      for (DevBuf<int32_t>* b : {&nbegin, &nend, &level, &child0, &child1, &parent, &nleft})
+        b->alloc(cap);
+      box.alloc(6 * cap);
+    }
+    HMX_HIP(hipMemcpyAsync(nbegin.p, rb.data(), 4 * nroot, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(nend.p, re.data(), 4 * nroot, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(level.p, rl.data(), 4 * nroot, hipMemcpyHostToDevice, s));
+    HMX_HIP(hipMemcpyAsync(parent.p, rp.data(), 4 * nroot, hipMemcpyHostToDevice, s));
     HMX_HIP(hipStreamSynchronize(s));
   }
-  int first = 0, count = 1, total = 1, cur = 0, depth = 0;
+  int first = 0, count = nroot, total = nroot, cur = 0, depth = 0;
   while (count > 0) {
     size_t need = (size_t)total + 2 * (size_t)count;
     if (need > cap) {
@@ -173,9 +185,14 @@ void build_blocks(hmx_op* op, hipStream_t s) {
   DevBuf<int2> front(fcap), next(fcap), nearL(ncap), farL(xcap);
   DevBuf<int> cnt(3);  // next, near, far
   fill_i32(cnt.p, 0, 3, s);
-  int2 root = make_int2(0, 0);
-  HMX_HIP(hipMemcpyAsync(front.p, &root, sizeof(int2), hipMemcpyHostToDevice, s));
-  int64_t nfront = 1, n_near = 0, n_far = 0;
+  // the frontier starts with (root, root) of every mesh: meshes never interact
+  const int nroot = (int)op->mesh_off.size() - 1;
+  std::vector<int2> roots(nroot);
+  for (int i = 0; i < nroot; ++i) roots[i] = make_int2(i, i);
+  if ((size_t)nroot > front.n) front.alloc(nroot);
+  HMX_HIP(hipMemcpyAsync(front.p, roots.data(), sizeof(int2) * nroot, hipMemcpyHostToDevice, s));
+  HMX_HIP(hipStreamSynchronize(s));
+  int64_t nfront = nroot, n_near = 0, n_far = 0;
   while (nfront > 0) {
     if ((size_t)(4 * nfront) > next.n) {
       next.alloc(std::max<size_t>(4 * nfront, 2 * next.n));
@@ -225,7 +242,7 @@ void build_near(hmx_op* op, hipStream_t s) {
     throw Error(HMX_ENOMEM, "near field exceeds pool_limit_bytes");
   op->near_pool.alloc(std::max<size_t>(bytes, 1));
   launch_assemble<T>(op->near_tb.p, op->near_m.p, op->near_sb.p, op->near_n.p, op->near_off.p, nn,
-                     op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern, op->k, (T*)op->near_pool.p, s);
+                     op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, (T*)op->near_pool.p, s);
   HMX_HIP(hipStreamSynchronize(s));
 }
 
@@ -286,7 +303,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     DevBuf<float> feat(4 * nf), pred(nf), th(MLP_NPARAMS), nm(8);
     HMX_HIP(hipMemcpyAsync(th.p, rm.theta, MLP_NPARAMS * 4, hipMemcpyHostToDevice, s));
     HMX_HIP(hipMemcpyAsync(nm.p, rm.norm, 8 * 4, hipMemcpyHostToDevice, s));
-    launch_mlp_features(op->farL.p, nf, op->nbegin.p, op->nend.p, op->box.p, op->k, feat.p, s);
+    launch_mlp_features(op->farL.p, nf, op->nbegin.p, op->nend.p, op->box.p, op->kpt.p, feat.p, s);
     launch_mlp_predict(th.p, nm.p, feat.p, nf, pred.p, s);
     std::vector<float> hp;
     to_host(hp, pred.p, nf, s);
@@ -383,13 +400,13 @@ void build_far(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipStreamWaitEvent(s2, ev_ready, 0));
     HMX_HIP(hipStreamWaitEvent(s3, ev_ready, 0));
     launch_aca<T>(d_desc.p, d_order.p, (int)big.size(), counter.p, 1, op->X.p, op->Y.p, op->Z.p,
-                  op->W.p, op->kern, op->k, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
+                  op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
                   fresh, gpool.p, gcap, gtop.p, s2);
     launch_aca_wave<T>(d_desc.p, d_order.p + big.size() + mid.size(), (int)small.size(), op->X.p,
-                       op->Y.p, op->Z.p, op->W.p, op->kern, op->k, op->p.tol, flags.p, rank.p,
+                       op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p,
                        ipiv.p, status.p, norm2.p, gpool.p, gcap, gtop.p, s3);
     launch_aca<T>(d_desc.p, d_order.p + big.size(), (int)mid.size(), counter.p + 1, 0, op->X.p,
-                  op->Y.p, op->Z.p, op->W.p, op->kern, op->k, op->p.tol, flags.p, rank.p, ipiv.p,
+                  op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p,
                   status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, s);
     HMX_HIP(hipEventRecord(ev_d2, s2));
     HMX_HIP(hipEventRecord(ev_d3, s3));
@@ -552,7 +569,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipMemcpyAsync(e.p, dn.data(), nd * 4, hipMemcpyHostToDevice, s));
     HMX_HIP(hipMemcpyAsync(o.p, doff.data(), nd * 8, hipMemcpyHostToDevice, s));
     launch_assemble<T>(a.p, b2.p, c.p, e.p, o.p, nd, op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern,
-                       op->k, (T*)op->dense_pool.p, s);
+                       op->kpt.p, (T*)op->dense_pool.p, s);
     HMX_HIP(hipStreamSynchronize(s));
   }
   HMX_HIP(hipStreamSynchronize(s));
@@ -595,6 +612,14 @@ void build_h(hmx_op* op, hipStream_t s) {
 void finish_build(hmx_op* op, hipStream_t s) {
   const size_t es = op->prec == HMX_FP64 ? sizeof(double2) : sizeof(float2);
   op->elem = es;
+  if (op->mesh_off.empty()) {
+    op->mesh_off = {0, op->M};
+    op->mesh_k = {op->k};
+  }
+  HMX_REQUIRE(op->mesh_off.back() == op->M, HMX_EINTERNAL, "mesh offsets do not cover the points");
+  op->kpt.alloc(op->M);
+  for (size_t i = 0; i + 1 < op->mesh_off.size(); ++i)
+    fill_f64(op->kpt.p + op->mesh_off[i], op->mesh_k[i], op->mesh_off[i + 1] - op->mesh_off[i], s);
   if (op->p.tol <= 0) {
     op->dense = true;
     op->partial.alloc((size_t)dense_otf_partial_len(op->M) * es);

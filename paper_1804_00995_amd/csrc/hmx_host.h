@@ -116,6 +116,14 @@ struct FarRec {
 
 constexpr int ACA_COEF_MAX = 1024;  // largest ACA rank (coefficients of a step held in LDS)
 enum AcaStatus : int32_t { ACA_RUNNING = 0, ACA_CONVERGED = 1, ACA_OVERFLOW = 2, ACA_DENSE = 3 };
+// ACA stops once |u_k| |v_k| <= tol |S_k|_F has held at this many consecutive steps (one step
+// can meet it by accident when its pivot row lies where the block is already well approximated).
+// A block's saved state keeps the count of steps met so far in the ACA_HIT_SHIFT bits of its
+// next-pivot-row word.
+constexpr int ACA_STOP_STEPS = 2;
+constexpr int ACA_HIT_SHIFT = 28;
+constexpr int32_t ACA_ROW_MASK = (1 << ACA_HIT_SHIFT) - 1;
+static_assert(ACA_STOP_STEPS < 8, "hit count fits the saved state word");
 
 // ------------------------------------------------------------------------------- launchers
 // k_quad.hip
@@ -126,6 +134,7 @@ void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);  
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+void fill_f64(double* p, double v, int64_t n, hipStream_t s);
 void iota_i32(int32_t* p, int64_t n, hipStream_t s);
 void sort_u64_pairs(uint64_t* key, int32_t* val, int64_t n, hipStream_t s);  // n power of two
 // k_tree.hip
@@ -166,20 +175,21 @@ void launch_leaf_far_fill(int n_leaves, const int32_t* leaves, const int32_t* pa
 template <class T>
 void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, const int32_t* n,
                      const int64_t* off, int64_t nblk, const double* X, const double* Y,
-                     const double* Z, const double* W, int kern, double k, T* pool, hipStream_t s);
+                     const double* Z, const double* W, int kern, const double* kp, T* pool,
+                     hipStream_t s);
 // k_aca.hip
 template <class T>
 void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
-                const double* Y, const double* Z, const double* W, int kern, double k, double tol,
-                uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status, double* norm2,
+                const double* Y, const double* Z, const double* W, int kern, const double* kp,
+                double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status, double* norm2,
                 int fresh, T* gpool, int64_t gcap, unsigned long long* gtop, hipStream_t s);
 constexpr int ACA_BIG = 4096;  // blocks with m + n >= ACA_BIG run in 512-thread workgroups
 constexpr int ACA_WAVE_N = 64; // blocks with m, n <= ACA_WAVE_N run one per wavefront
 constexpr int ACA_WAVE_RC = 16; // terms a wavefront block holds in registers
 template <class T>
 void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
-                     const double* Y, const double* Z, const double* W, int kern, double k,
-                     double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
+                     const double* Y, const double* Z, const double* W, int kern,
+                     const double* kp, double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                      double* norm2, T* gpool, int64_t gcap, unsigned long long* gtop,
                      hipStream_t s);
 template <class T>
@@ -188,7 +198,7 @@ void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* 
 // k_mlp.hip -- block-rank MLP (4 -> 64 -> 64 -> 1, ReLU, FP32)
 constexpr int MLP_IN = 4, MLP_H = 64, MLP_NPARAMS = 4545;
 void launch_mlp_features(const int2* pairs, int64_t n, const int32_t* nbegin, const int32_t* nend,
-                         const double* box, double k, float* feat, hipStream_t s);
+                         const double* box, const double* kp, float* feat, hipStream_t s);
 void launch_mlp_predict(const float* theta, const float* norm, const float* feat, int64_t n,
                         float* out, hipStream_t s);
 size_t mlp_cache_floats(int B);
@@ -236,6 +246,12 @@ struct hmx_op {
   // points (cluster order for H operators, original order for dense ones)
   hmx::DevBuf<double> X, Y, Z, W;
   hmx::DevBuf<int32_t> perm;
+  // wavenumber at each point (that of the point's mesh; the same in both point orders since
+  // cluster ranges never cross a mesh boundary)
+  hmx::DevBuf<double> kpt;
+  // meshes of a batched operator: points [mesh_off[i], mesh_off[i + 1]) belong to mesh i
+  std::vector<int64_t> mesh_off;
+  std::vector<double> mesh_k;
   // tree (breadth-first node numbering)
   int n_nodes = 0, n_leaves = 0, depth = 0;
   hmx::DevBuf<int32_t> nbegin, nend, nlevel, child0, child1, parent;
@@ -264,6 +280,16 @@ struct hmx_op {
   double t_tree = 0, t_blocks = 0, t_near = 0, t_aca = 0, t_total = 0;
   int64_t kernel_evals = 0;
   int64_t bytes() const;
+};
+
+// A captured product (hmx_graph_create).
+struct hmx_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~hmx_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
 };
 
 namespace hmx {

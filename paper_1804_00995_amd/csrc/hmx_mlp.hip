@@ -127,7 +127,7 @@ hmx_status hmx_far_features(const hmx_op* op, float* feat) {
   const int64_t nf = op->n_far;
   if (nf == 0) return HMX_OK;
   DevBuf<float> f(4 * nf);
-  launch_mlp_features(op->farL.p, nf, op->nbegin.p, op->nend.p, op->box.p, op->k, f.p, nullptr);
+  launch_mlp_features(op->farL.p, nf, op->nbegin.p, op->nend.p, op->box.p, op->kpt.p, f.p, nullptr);
   std::vector<float> h;
   to_host(h, f.p, 4 * (size_t)nf, nullptr);
   std::memcpy(feat, h.data(), 4 * (size_t)nf * 4);

@@ -48,7 +48,7 @@ struct AcaShared {
 template <class T, int NT>
 __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __restrict__ X,
                           const double* __restrict__ Y, const double* __restrict__ Z,
-                          const double* __restrict__ W, int kern, double k, double tol,
+                          const double* __restrict__ W, int kern, const double* kp, double tol,
                           uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                           double* norm2, int fresh, T* gpool, int64_t gcap,
                           unsigned long long* gtop, T* coef, AcaShared& sh) {
@@ -57,21 +57,24 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   const int tid = threadIdx.x;
   const FarDesc d = descs[b];
   const int m = d.m, n = d.n, tb = d.tb, sb = d.sb;
+  const double k = kp[tb];  // wavenumber of the block's mesh
   T* U = (T*)d.U;
   T* V = (T*)d.V;
   int cap = d.cap;
   uint8_t* rused = flags + d.foff;
   uint8_t* cused = rused + m;
-  int kk, ip;
+  int kk, ip, hits;
   double nrm2;
   if (fresh) {
     for (int i = tid; i < m + n; i += NT) rused[i] = 0;
     kk = 0;
     ip = 0;
+    hits = 0;
     nrm2 = 0.0;
   } else {
     kk = rank[b];
-    ip = ipiv[b];
+    ip = ipiv[b] & ACA_ROW_MASK;
+    hits = ipiv[b] >> ACA_HIT_SHIFT;
     nrm2 = norm2[b];
   }
   int st = d.rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
@@ -314,10 +317,14 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     nrm2 = nrm2 + 2.0 * cross + nn2[0] * nn2[1];
     kk += 1;
     block_amax<NT>(ub, ui, sh.sv, sh.si);
-    // (6) stopping rule, (7) next pivot row
+    // (6) stopping rule (met at ACA_STOP_STEPS consecutive steps), (7) next pivot row
     if (sqrt(nn2[0]) * sqrt(nn2[1]) <= tol * sqrt(nrm2)) {
-      st = ACA_CONVERGED;
-      break;
+      if (++hits >= ACA_STOP_STEPS) {
+        st = ACA_CONVERGED;
+        break;
+      }
+    } else {
+      hits = 0;
     }
     if (ui == INT_MAX) {
       st = ACA_CONVERGED;
@@ -327,7 +334,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   }
   if (tid == 0) {
     rank[b] = kk;
-    ipiv[b] = ip;
+    ipiv[b] = ip | (hits << ACA_HIT_SHIFT);
     norm2[b] = nrm2;
     status[b] = st;
   }
@@ -340,7 +347,7 @@ __global__ void __launch_bounds__(NT) aca_kernel(FarDesc* __restrict__ desc,
                                                  int* counter, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
                                                  const double* __restrict__ Z,
-                                                 const double* __restrict__ W, int kern, double k,
+                                                 const double* __restrict__ W, int kern, const double* kp,
                                                  double tol, uint8_t* flags, int32_t* rank,
                                                  int32_t* ipiv, int32_t* status, double* norm2,
                                                  int fresh, T* gpool, int64_t gcap,
@@ -353,7 +360,7 @@ __global__ void __launch_bounds__(NT) aca_kernel(FarDesc* __restrict__ desc,
     const int q = sh.q;
     __syncthreads();
     if (q >= nb) break;
-    aca_block<T, NT>(desc, order[q], X, Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2,
+    aca_block<T, NT>(desc, order[q], X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2,
                      fresh, gpool, gcap, gtop, coef, sh);
   }
 }
@@ -370,7 +377,7 @@ template <class T, int RC>
 __global__ void __launch_bounds__(WG) aca_wave_kernel(
     FarDesc* __restrict__ desc, const int32_t* __restrict__ order, int nb,
     const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
-    const double* __restrict__ W, int kern, double k, double tol, uint8_t* flags, int32_t* rank,
+    const double* __restrict__ W, int kern, const double* kp, double tol, uint8_t* flags, int32_t* rank,
     int32_t* ipiv, int32_t* status, double* norm2, T* gpool, int64_t gcap,
     unsigned long long* gtop) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -382,6 +389,7 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
     const int b = order[q];
     const FarDesc d = desc[b];
     const int m = d.m, n = d.n;
+    const double k = kp[d.tb];
     const bool hr = lane < m, hc = lane < n;
     const int ir = hr ? lane : 0, ic = hc ? lane : 0;
     const double tx = X[d.tb + ir], ty = Y[d.tb + ir], tz = Z[d.tb + ir];
@@ -390,7 +398,7 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
 #pragma unroll
     for (int l = 0; l < RC; ++l) u[l] = v[l] = czero<T>();
     bool rused = !hr, cused = !hc;
-    int kk = 0, ip = 0;
+    int kk = 0, ip = 0, hits = 0;
     double nrm2 = 0.0;
     int st = d.rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
     while (st == ACA_RUNNING) {
@@ -468,8 +476,12 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
       kk += 1;
       // (6) stopping rule, (7) next pivot row
       if (__builtin_amdgcn_readfirstlane(sqrt(nu2) * sqrt(nv2) <= tol * sqrt(nrm2) ? 1 : 0)) {
-        st = ACA_CONVERGED;
-        break;
+        if (++hits >= ACA_STOP_STEPS) {
+          st = ACA_CONVERGED;
+          break;
+        }
+      } else {
+        hits = 0;
       }
       double bu = rused ? -1.0 : abs2(un);
       int bi = rused ? INT_MAX : lane;
@@ -508,6 +520,7 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
         st = ACA_OVERFLOW;
         kk = 0;
         ip = 0;
+        hits = 0;
         nrm2 = 0.0;
         rused = false;
         cused = false;
@@ -534,7 +547,7 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
     }
     if (lane == 0) {
       rank[b] = kk;
-      ipiv[b] = ip;
+      ipiv[b] = ip | (hits << ACA_HIT_SHIFT);
       norm2[b] = nrm2;
       status[b] = st;
     }
@@ -543,7 +556,7 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
 
 template <class T>
 void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
-                     const double* Y, const double* Z, const double* W, int kern, double k,
+                     const double* Y, const double* Z, const double* W, int kern, const double* kp,
                      double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                      double* norm2, T* gpool, int64_t gcap, unsigned long long* gtop,
                      hipStream_t s) {
@@ -553,14 +566,14 @@ void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
   HMX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const int grid = std::min((nb + NWAVE - 1) / NWAVE, 8 * ncu);
   hipLaunchKernelGGL((aca_wave_kernel<T, ACA_WAVE_RC>), dim3(grid), dim3(WG), 0, s, d, order, nb,
-                     X, Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2, gpool, gcap,
+                     X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, gpool, gcap,
                      gtop);
   HMX_LAUNCHED();
 }
 
 template <class T>
 void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
-                const double* Y, const double* Z, const double* W, int kern, double k, double tol,
+                const double* Y, const double* Z, const double* W, int kern, const double* kp, double tol,
                 uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status, double* norm2,
                 int fresh, T* gpool, int64_t gcap, unsigned long long* gtop, hipStream_t s) {
   if (nb <= 0) return;
@@ -570,12 +583,12 @@ void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big,
   if (big) {
     int grid = std::min(nb, 2 * ncu);
     hipLaunchKernelGGL((aca_kernel<T, 512>), dim3(grid), dim3(512), 0, s, d, order, nb, counter,
-                       X, Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
+                       X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
                        gcap, gtop);
   } else {
     int grid = std::min(nb, 8 * ncu);
     hipLaunchKernelGGL((aca_kernel<T, WG>), dim3(grid), dim3(WG), 0, s, d, order, nb, counter, X,
-                       Y, Z, W, kern, k, tol, flags, rank, ipiv, status, norm2, fresh, gpool, gcap,
+                       Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool, gcap,
                        gtop);
   }
   HMX_LAUNCHED();
@@ -610,11 +623,12 @@ void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* 
 
 #define HMX_INST(T)                                                                              \
   template void launch_aca_wave<T>(FarDesc*, const int32_t*, int, const double*,                \
-                                   const double*, const double*, const double*, int, double,     \
-                                   double, uint8_t*, int32_t*, int32_t*, int32_t*, double*, T*,  \
+                                   const double*, const double*, const double*, int,             \
+                                   const double*, double, uint8_t*, int32_t*, int32_t*, int32_t*, double*, T*,  \
                                    int64_t, unsigned long long*, hipStream_t);                   \
   template void launch_aca<T>(FarDesc*, const int32_t*, int, int*, int, const double*,           \
-                              const double*, const double*, const double*, int, double, double,  \
+                              const double*, const double*, const double*, int, const double*,   \
+                              double,                                                            \
                               uint8_t*, int32_t*, int32_t*, int32_t*, double*, int, T*, int64_t, \
                               unsigned long long*, hipStream_t);                                 \
   template void launch_copy_factors<T>(const FarDesc*, const FarDesc*, const int32_t*,           \

@@ -23,8 +23,8 @@ static_assert(OB3 + 1 == MLP_NPARAMS, "parameter layout");
 
 __global__ void __launch_bounds__(WG) mlp_features_kernel(
     const int2* __restrict__ pairs, int64_t n, const int32_t* __restrict__ nbegin,
-    const int32_t* __restrict__ nend, const double* __restrict__ box, double k,
-    float* __restrict__ feat) {
+    const int32_t* __restrict__ nend, const double* __restrict__ box,
+    const double* __restrict__ kp, float* __restrict__ feat) {
   const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (i >= n) return;
   const int2 p = pairs[i];
@@ -46,14 +46,14 @@ __global__ void __launch_bounds__(WG) mlp_features_kernel(
   feat[4 * i + 0] = (float)log2(m);
   feat[4 * i + 1] = (float)log2(nn);
   feat[4 * i + 2] = (float)log(fmax(sqrt(dist), 1e-12) / dmax);
-  feat[4 * i + 3] = (float)(k * dmax / TWO_PI);
+  feat[4 * i + 3] = (float)(kp[nbegin[p.x]] * dmax / TWO_PI);  // k of the block's mesh
 }
 
 void launch_mlp_features(const int2* pairs, int64_t n, const int32_t* nbegin, const int32_t* nend,
-                         const double* box, double k, float* feat, hipStream_t s) {
+                         const double* box, const double* kp, float* feat, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s,
-                     pairs, n, nbegin, nend, box, k, feat);
+                     pairs, n, nbegin, nend, box, kp, feat);
   HMX_LAUNCHED();
 }
 

@@ -12,9 +12,10 @@ __global__ void __launch_bounds__(WG) assemble_kernel(
     const int32_t* __restrict__ tb, const int32_t* __restrict__ mm, const int32_t* __restrict__ sb,
     const int32_t* __restrict__ nn, const int64_t* __restrict__ off, const double* __restrict__ X,
     const double* __restrict__ Y, const double* __restrict__ Z, const double* __restrict__ W,
-    int kern, double k, T* __restrict__ pool) {
+    int kern, const double* __restrict__ kp, T* __restrict__ pool) {
   const int blk = blockIdx.x;
   const int t0 = tb[blk], m = mm[blk], s0 = sb[blk], n = nn[blk];
+  const double k = kp[t0];  // wavenumber of the block's mesh
   T* K = pool + off[blk];
   const int64_t total = (int64_t)m * n;
   int i = threadIdx.x % m, j = threadIdx.x / m;
@@ -35,7 +36,8 @@ __global__ void __launch_bounds__(WG) assemble_kernel(
 template <class T>
 void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, const int32_t* n,
                      const int64_t* off, int64_t nblk, const double* X, const double* Y,
-                     const double* Z, const double* W, int kern, double k, T* pool, hipStream_t s) {
+                     const double* Z, const double* W, int kern, const double* k, T* pool,
+                     hipStream_t s) {
   if (nblk <= 0) return;
   hipLaunchKernelGGL(assemble_kernel<T>, dim3((unsigned)nblk), dim3(WG), 0, s, tb, m, sb, n, off,
                      X, Y, Z, W, kern, k, pool);
@@ -44,11 +46,13 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
 
 template void launch_assemble<double2>(const int32_t*, const int32_t*, const int32_t*,
                                        const int32_t*, const int64_t*, int64_t, const double*,
-                                       const double*, const double*, const double*, int, double,
+                                       const double*, const double*, const double*, int,
+                                       const double*,
                                        double2*, hipStream_t);
 template void launch_assemble<float2>(const int32_t*, const int32_t*, const int32_t*,
                                       const int32_t*, const int64_t*, int64_t, const double*,
-                                      const double*, const double*, const double*, int, double,
+                                      const double*, const double*, const double*, int,
+                                      const double*,
                                       float2*, hipStream_t);
 
 }  // namespace hmx

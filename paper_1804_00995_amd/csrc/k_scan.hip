@@ -112,6 +112,7 @@ static void fill_any(T* p, T v, int64_t n, hipStream_t s) {
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) { fill_any(p, v, n, s); }
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s) { fill_any(p, v, n, s); }
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) { fill_any(p, v, n, s); }
+void fill_f64(double* p, double v, int64_t n, hipStream_t s) { fill_any(p, v, n, s); }
 
 __global__ void iota_kernel(int32_t* p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;

@@ -71,6 +71,10 @@ _sig = {
     "hmx_mlp_loss_grad": [_P, _P, _P, _i64, _P, _P, _P],
     "hmx_mlp_train": [_P, _P, _P, _i64, _i32, _i32, C.c_float, _P, _P],
     "hmx_set_rank_model": [_P, _P, C.c_float, C.c_float],
+    "hmx_build_batch": [_P, _i32, _P, _P, _i32, _i32, C.POINTER(Params), _P, C.POINTER(_P)],
+    "hmx_mesh_offsets": [_P, _P, _i32, C.POINTER(_i32)],
+    "hmx_graph_create": [_P, _P, _P, C.POINTER(_P)],
+    "hmx_graph_launch": [_P, _i32, _P],
 }
 MLP_NPARAMS = 4545
 for _name, _args in _sig.items():
@@ -83,8 +87,15 @@ _lib.hmx_last_error.argtypes = []
 _lib.hmx_last_error.restype = C.c_char_p
 _lib.hmx_release_cache.argtypes = []
 _lib.hmx_release_cache.restype = None
+_lib.hmx_graph_destroy.argtypes = [_P]
+_lib.hmx_graph_destroy.restype = None
 
-EXPORTED = sorted(list(_sig) + ["hmx_destroy", "hmx_last_error", "hmx_release_cache"])
+EXPORTED = sorted(list(_sig) + ["hmx_destroy", "hmx_last_error", "hmx_release_cache",
+                                "hmx_graph_destroy"])
+
+
+class Mesh(C.Structure):
+    _fields_ = [("vtx", _P), ("n_vtx", _i64), ("tri", _P), ("n_tri", _i64), ("k", _f64)]
 
 
 def release_cache():
@@ -188,6 +199,23 @@ class Operator:
     def __matmul__(self, x):
         return self.matvec(x)
 
+    def mesh_offsets(self):
+        """Point offsets of the operator's meshes (n_meshes + 1 entries)."""
+        n = C.c_int32(0)
+        _check(_lib.hmx_mesh_offsets(self._h, None, 0, C.byref(n)))
+        off = np.empty(n.value + 1, np.int64)
+        _check(_lib.hmx_mesh_offsets(self._h, off.ctypes.data_as(_P), off.size, C.byref(n)))
+        return off
+
+    def split(self, v):
+        """Per-mesh views of a concatenated vector."""
+        off = self.mesh_offsets()
+        return [v[off[i]:off[i + 1]] for i in range(off.size - 1)]
+
+    def graph(self, x, y):
+        """The product y = K x captured once in a HIP graph (replay with Graph.launch)."""
+        return Graph(self, x, y)
+
     def export_tree(self):
         n = self.info["n_nodes"]
         perm = np.empty(self.M, np.int32)
@@ -257,6 +285,49 @@ def build_points(xyzw, kern=HELMHOLTZ, k=0.0, prm: Params | None = None, stream=
     _check(_lib.hmx_build_points(_dev(xyzw, torch.float64, "xyzw"), xyzw.shape[1], kern, float(k),
                                  C.byref(prm), _stream_ptr(stream), C.byref(h)))
     return Operator(h, prm.precision)
+
+
+def build_batch(meshes, bary, w, kern=HELMHOLTZ, prm: Params | None = None, stream=None) -> Operator:
+    """One block-diagonal operator for independent meshes: `meshes` is a list of
+    (vtx float64 (nv,3), tri int32 (nt,3) device tensors, k).  Vectors are the per-mesh vectors
+    concatenated in mesh order (Operator.split gives the per-mesh views)."""
+    import torch
+    bary, w = _host_rule(bary, w)
+    prm = prm or params()
+    arr = (Mesh * len(meshes))()
+    for i, (vtx, tri, k) in enumerate(meshes):
+        arr[i] = Mesh(_dev(vtx, torch.float64, "vtx").value, vtx.shape[0],
+                      _dev(tri, torch.int32, "tri").value, tri.shape[0], float(k))
+    h = C.c_void_p()
+    _check(_lib.hmx_build_batch(arr, len(meshes), bary.ctypes.data_as(_P), w.ctypes.data_as(_P),
+                                bary.shape[0], kern, C.byref(prm), _stream_ptr(stream), C.byref(h)))
+    return Operator(h, prm.precision)
+
+
+class Graph:
+    """A product captured in a HIP graph (fixed operator, x and y); `launch(reps)` replays it."""
+
+    def __init__(self, op, x, y):
+        if x.shape != (op.M,) or y.shape != (op.M,):
+            raise ValueError(f"x and y must have shape ({op.M},)")
+        self._op, self._x, self._y = op, x, y  # keep the captured buffers alive
+        self._g = C.c_void_p()
+        _check(_lib.hmx_graph_create(op._h, _dev(x, op.cdtype, "x"), _dev(y, op.cdtype, "y"),
+                                     C.byref(self._g)))
+
+    def launch(self, reps=1, stream=None):
+        _check(_lib.hmx_graph_launch(self._g, reps, _stream_ptr(stream)))
+
+    def close(self):
+        if self._g:
+            _lib.hmx_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------------ learned block ranks

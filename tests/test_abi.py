@@ -77,3 +77,30 @@ def test_bad_params_rejected_on_host(hmx):
     assert lib.hmx_build(fake, 3, fake, 1, badb, w, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
     assert lib.hmx_build(fake, 3, fake, 1, bary, w, 0, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
     assert lib.hmx_build(fake, 0, fake, 1, bary, w, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+
+
+def test_batch_argument_errors_without_gpu():
+    import ctypes as C
+    from paper_1804_00995_amd import hmx
+    lib = hmx._lib
+    p = hmx.params()
+    h = C.c_void_p()
+    bary = (C.c_double * 9)(2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3)
+    w = (C.c_double * 3)(1 / 3, 1 / 3, 1 / 3)
+    fake = C.c_void_p(4096)
+    meshes = (hmx.Mesh * 2)(hmx.Mesh(fake, 3, fake, 1, 5.0), hmx.Mesh(fake, 3, fake, 1, 7.0))
+    assert lib.hmx_build_batch(None, 2, bary, w, 3, 1, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build_batch(meshes, 0, bary, w, 3, 1, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    dense = hmx.params(tol=0.0)
+    assert lib.hmx_build_batch(meshes, 2, bary, w, 3, 1, C.byref(dense), None, C.byref(h)) == hmx.EINVAL
+    assert b"tol" in lib.hmx_last_error()
+    meshes[1].k = -1.0
+    assert lib.hmx_build_batch(meshes, 2, bary, w, 3, 1, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    meshes[1].k = 7.0
+    meshes[1].n_tri = 0
+    assert lib.hmx_build_batch(meshes, 2, bary, w, 3, 1, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    n = C.c_int32(0)
+    assert lib.hmx_mesh_offsets(None, None, 0, C.byref(n)) == hmx.EINVAL
+    assert lib.hmx_graph_create(None, None, None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_graph_launch(None, 1, None) == hmx.EINVAL
+    lib.hmx_graph_destroy(None)  # NULL-safe
