@@ -27,10 +27,55 @@ if ROOT not in sys.path:
 
 METRIC = "H-matvec ms and H-build s at 1e-3 rel err; kernel evals/s; frac of HBM/FP peak"
 HBM_PEAK_GBS = 8000.0
+ACA_BIG_KERNEL = "hmx::aca_kernel<T, 512> (ACA of the far blocks with m + n >= 4096)"
+PMC_SUMMARY = {"fp64": os.path.join(ROOT, "profiles", "aca_big_icosphere_L6_k40_fp64_pmc.txt"),
+               "fp32": os.path.join(ROOT, "profiles", "aca_big_icosphere_L6_k40_fp32_pmc.txt")}
+ACA_SOURCE = os.path.join(ROOT, "paper_1804_00995_amd", "csrc", "k_aca.hip")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(precision):
+    """HBM bytes per launch of the large-block ACA kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when the summary
+    is missing or the kernel source has changed since the counters were taken."""
+    path = PMC_SUMMARY[precision]
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                key, _, val = line.partition(":")
+                vals[key.strip()] = val.strip()
+    if vals.get("k_aca.hip sha256[:16]") != source_digest(ACA_SOURCE):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """A plain elementwise copy (torch.neg into a second buffer) of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters: reads and writes mib MiB per launch, 5 launches."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": n * 8,
+                                           "bytes_written_per_launch": n * 8, "launches": 5}}))
 
 
 def main():
@@ -44,10 +89,15 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=30)
     ap.add_argument("--sample-rows", type=int, default=384)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run the copy kernel used to scale the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures a single GPU; --gpus above 1 is not supported")
         sys.exit(2)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
 
@@ -81,9 +131,11 @@ def main():
         op.close()
         log(f"warmup {i} done")
     torch.cuda.synchronize()
+    aca = []  # per timed step: (ms, algorithmic bytes, rounds) of the large-block ACA launch
     t0 = time.perf_counter()
     for i in range(args.steps):
         op, y = step()
+        aca.append((op.info["aca_ms"][0], op.info["aca_bytes"][0], op.info["aca_rounds"]))
         op.close()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -114,8 +166,13 @@ def main():
     elem = 16 if prec == hmx.FP64 else 8
     stored = info["near_entries"] + info["far_entries"] + info["dense_far_entries"]
     mv_bytes = elem * (stored + 4 * M) + 8 * M
-    achieved = mv_bytes / (mv_ms * 1e-3) / 1e9
+    mv_achieved = mv_bytes / (mv_ms * 1e-3) / 1e9
     build_s = info["t_total_ms"] / 1e3
+    # dominant kernel of the step: ACA of the large far blocks (one launch per build)
+    aca_ms = float(np.mean([a[0] for a in aca])) if aca else info["aca_ms"][0]
+    aca_bytes = aca[-1][1] if aca else info["aca_bytes"][0]
+    aca_gbs = aca_bytes / (aca_ms * 1e-3) / 1e9 if aca_ms > 0 else 0.0
+    traffic = measured_traffic(args.precision)
 
     cpu = None
     if args.cpu_baseline == "on":
@@ -155,8 +212,16 @@ def main():
                             ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
         "sizes": {k2: info[k2] for k2 in ("n_near", "n_far", "near_entries", "far_entries",
                                            "dense_far", "max_rank", "overflow_blocks", "bytes")},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": ACA_BIG_KERNEL, "achieved": round(aca_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(aca_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "launch_ms": round(aca_ms, 3),
+                     "algorithmic_bytes_per_launch": aca_bytes,
+                     "blocks": info["aca_blocks"][0], "rounds": max(a[2] for a in aca) if aca else None},
+        "roofline_matvec": {"bound": "hbm", "achieved": round(mv_achieved, 1), "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(mv_achieved / HBM_PEAK_GBS, 4),
+                            "bytes_per_product": mv_bytes},
+        "aca_classes": {"blocks": info["aca_blocks"], "first_launch_ms": [round(t, 3) for t in info["aca_ms"]],
+                        "algorithmic_bytes": info["aca_bytes"]},
         "cpu_baseline": cpu,
     }
     op.close()

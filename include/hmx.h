@@ -176,6 +176,15 @@ typedef struct {
   int64_t kernel_evals;    /* Green-kernel evaluations spent in the build */
   int64_t factor_bytes;    /* device bytes of the slots holding far-block factors (used part) */
   int64_t predicted_entries; /* learned layout: sum of r_alloc * (m + n) over far blocks */
+  /* ACA by block class: [0] m + n >= 4096 (512-thread workgroups), [1] the other workgroup
+   * blocks (256 threads), [2] m, n <= 64 (one wavefront each).  aca_ms: duration of the class's
+   * first launch (events on the stream it ran on); aca_bytes: bytes the method must move for
+   * the class, es (m + n) r (r + 1) / 2 per block of final rank r (step k reads the k previous
+   * columns of U and V once and writes one column pair; es = bytes of one complex entry). */
+  int64_t aca_blocks[3];
+  double aca_ms[3];
+  int64_t aca_bytes[3];
+  int32_t aca_rounds; /* ACA launch rounds: 1 + continuation rounds (device pool exhausted) */
 } hmx_info_t;
 
 /* Sizes, counts and build timings of an operator. */

@@ -378,6 +378,12 @@ hmx_status hmx_info(const hmx_op* op, hmx_info_t* out) {
   out->kernel_evals = op->kernel_evals;
   out->factor_bytes = op->pool_used_bytes;
   out->predicted_entries = op->predicted_entries;
+  for (int c = 0; c < 3; ++c) {
+    out->aca_blocks[c] = op->aca_blocks[c];
+    out->aca_ms[c] = op->aca_ms[c];
+    out->aca_bytes[c] = op->aca_bytes[c];
+  }
+  out->aca_rounds = op->aca_rounds;
   return HMX_OK;
 }
 

@@ -363,6 +363,17 @@ void build_far(hmx_op* op, hipStream_t s) {
   HMX_HIP(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
   HMX_HIP(hipEventCreateWithFlags(&ev_d2, hipEventDisableTiming));
   HMX_HIP(hipEventCreateWithFlags(&ev_d3, hipEventDisableTiming));
+  // timing of each class's first launch, on the stream it runs on
+  hipEvent_t tev[6] = {};
+  struct EventGuard {
+    hipEvent_t* e;
+    ~EventGuard() {
+      for (int i = 0; i < 6; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } tguard{tev};
+  for (auto& e : tev) HMX_HIP(hipEventCreate(&e));
+  std::vector<uint8_t> cls0(nf, 0);  // class of each block in the first launch
 
   // run ACA on a list of blocks, largest first within each class: m + n >= ACA_BIG in
   // 512-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per wavefront (stream s3, fresh
@@ -374,6 +385,7 @@ void build_far(hmx_op* op, hipStream_t s) {
       const FarDesc& d = desc[b];
       const int64_t mn = (int64_t)d.m + d.n;
       const int cls = mn >= ACA_BIG ? 0 : (fresh && is_wave[b]) ? 2 : 1;
+      if (fresh) cls0[b] = (uint8_t)cls;
       bucket[cls][31 - std::min(31, 63 - __builtin_clzll((unsigned long long)mn))].push_back(b);
     }
     std::vector<int32_t> big, mid, small;
@@ -399,15 +411,21 @@ void build_far(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipEventRecord(ev_ready, s));
     HMX_HIP(hipStreamWaitEvent(s2, ev_ready, 0));
     HMX_HIP(hipStreamWaitEvent(s3, ev_ready, 0));
+    if (fresh) HMX_HIP(hipEventRecord(tev[0], s2));
     launch_aca<T>(d_desc.p, d_order.p, (int)big.size(), counter.p, 1, op->X.p, op->Y.p, op->Z.p,
                   op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
                   fresh, gpool.p, gcap, gtop.p, s2);
+    if (fresh) HMX_HIP(hipEventRecord(tev[1], s2));
+    if (fresh) HMX_HIP(hipEventRecord(tev[4], s3));
     launch_aca_wave<T>(d_desc.p, d_order.p + big.size() + mid.size(), (int)small.size(), op->X.p,
                        op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p,
                        ipiv.p, status.p, norm2.p, gpool.p, gcap, gtop.p, s3);
+    if (fresh) HMX_HIP(hipEventRecord(tev[5], s3));
+    if (fresh) HMX_HIP(hipEventRecord(tev[2], s));
     launch_aca<T>(d_desc.p, d_order.p + big.size(), (int)mid.size(), counter.p + 1, 0, op->X.p,
                   op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p,
                   status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, s);
+    if (fresh) HMX_HIP(hipEventRecord(tev[3], s));
     HMX_HIP(hipEventRecord(ev_d2, s2));
     HMX_HIP(hipEventRecord(ev_d3, s3));
     HMX_HIP(hipStreamWaitEvent(s, ev_d2, 0));
@@ -418,7 +436,13 @@ void build_far(hmx_op* op, hipStream_t s) {
     std::vector<int32_t> all(nf);
     std::iota(all.begin(), all.end(), 0);
     run_aca(all, 1);
+    for (int c = 0; c < 3; ++c) {
+      float ms = 0.f;
+      HMX_HIP(hipEventElapsedTime(&ms, tev[2 * c], tev[2 * c + 1]));
+      op->aca_ms[c] = ms;
+    }
   }
+  op->aca_rounds = 1;
   std::vector<int32_t> hst, hrank;
   to_host(hst, status.p, nf, s);
   // blocks stopped with OVERFLOW (device pool exhausted, or a wavefront block past its register
@@ -467,6 +491,7 @@ void build_far(hmx_op* op, hipStream_t s) {
       d_desc = std::move(d_nd);
     }
     run_aca(list, 0);
+    op->aca_rounds++;
     to_host(hst, status.p, nf, s);
   }
   to_host(hrank, rank.p, nf, s);
@@ -517,6 +542,15 @@ void build_far(hmx_op* op, hipStream_t s) {
       op->sum_rank += f.r;
       evals += (int64_t)f.r * (d.m + d.n);
     }
+  }
+  // per class: blocks, and the bytes ACA must move: step k reads the k previous columns of U
+  // and V once (residual row and column) and writes one column pair, so a block of final rank r
+  // moves es (m + n) r (r + 1) / 2 bytes
+  for (int c = 0; c < 3; ++c) op->aca_blocks[c] = op->aca_bytes[c] = 0;
+  for (int64_t b = 0; b < nf; ++b) {
+    const int64_t r = hrank[b];
+    op->aca_blocks[cls0[b]]++;
+    op->aca_bytes[cls0[b]] += (int64_t)sizeof(T) * ((int64_t)desc[b].m + desc[b].n) * r * (r + 1) / 2;
   }
   op->overflow_blocks = grown;
   op->kernel_evals += evals;

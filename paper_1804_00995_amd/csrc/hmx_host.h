@@ -278,6 +278,10 @@ struct hmx_op {
   hmx::DevBuf<unsigned char> xp, tbuf, partial;
   // build statistics
   double t_tree = 0, t_blocks = 0, t_near = 0, t_aca = 0, t_total = 0;
+  // ACA by block class (0: m + n >= ACA_BIG, 1: other workgroup blocks, 2: wavefront blocks)
+  int64_t aca_blocks[3] = {0, 0, 0}, aca_bytes[3] = {0, 0, 0};
+  double aca_ms[3] = {0, 0, 0};
+  int32_t aca_rounds = 0;
   int64_t kernel_evals = 0;
   int64_t bytes() const;
 };

@@ -49,10 +49,16 @@ class Info(C.Structure):
         "dense_far", "dense_far_entries", "max_rank", "sum_rank", "overflow_blocks", "bytes")] + [
         ("precision", C.c_int32), ("is_dense", C.c_int32)] + [
         (n, C.c_double) for n in ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms", "t_total_ms")] + [
-        ("kernel_evals", C.c_int64), ("factor_bytes", C.c_int64), ("predicted_entries", C.c_int64)]
+        ("kernel_evals", C.c_int64), ("factor_bytes", C.c_int64), ("predicted_entries", C.c_int64),
+        ("aca_blocks", C.c_int64 * 3), ("aca_ms", C.c_double * 3), ("aca_bytes", C.c_int64 * 3),
+        ("aca_rounds", C.c_int32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if isinstance(v, C.Array) else v
+        return d
 
 
 _P, _i64, _i32, _f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
