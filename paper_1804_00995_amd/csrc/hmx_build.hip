@@ -373,6 +373,15 @@ void build_far(hmx_op* op, hipStream_t s) {
     }
   } tguard{tev};
   for (auto& e : tev) HMX_HIP(hipEventCreate(&e));
+  // Gram scratch of the two workgroup classes (first launch only)
+  const int64_t gram_per_wg = 2 * (int64_t)ACA_GRAM_R * ACA_GRAM_R;
+  DevBuf<double2> gram_big((size_t)aca_grid<T>(1) * gram_per_wg);
+  DevBuf<double2> gram_mid((size_t)aca_grid<T>(0) * gram_per_wg);
+  // blocks below this m + n take the direct cross sums (fewer barriers per step pays off there)
+  static const int gram_min = [] {
+    const char* e = std::getenv("HMX_ACA_GRAM_MIN");
+    return e ? std::atoi(e) : 1024;
+  }();
   std::vector<uint8_t> cls0(nf, 0);  // class of each block in the first launch
 
   // run ACA on a list of blocks, largest first within each class: m + n >= ACA_BIG in
@@ -414,7 +423,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     if (fresh) HMX_HIP(hipEventRecord(tev[0], s2));
     launch_aca<T>(d_desc.p, d_order.p, (int)big.size(), counter.p, 1, op->X.p, op->Y.p, op->Z.p,
                   op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
-                  fresh, gpool.p, gcap, gtop.p, s2);
+                  fresh, gpool.p, gcap, gtop.p, fresh ? gram_big.p : nullptr, gram_min, s2);
     if (fresh) HMX_HIP(hipEventRecord(tev[1], s2));
     if (fresh) HMX_HIP(hipEventRecord(tev[4], s3));
     launch_aca_wave<T>(d_desc.p, d_order.p + big.size() + mid.size(), (int)small.size(), op->X.p,
@@ -424,7 +433,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     if (fresh) HMX_HIP(hipEventRecord(tev[2], s));
     launch_aca<T>(d_desc.p, d_order.p + big.size(), (int)mid.size(), counter.p + 1, 0, op->X.p,
                   op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p,
-                  status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, s);
+                  status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, fresh ? gram_mid.p : nullptr, gram_min, s);
     if (fresh) HMX_HIP(hipEventRecord(tev[3], s));
     HMX_HIP(hipEventRecord(ev_d2, s2));
     HMX_HIP(hipEventRecord(ev_d3, s3));

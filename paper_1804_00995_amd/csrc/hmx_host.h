@@ -181,8 +181,14 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
 template <class T>
 void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
                 const double* Y, const double* Z, const double* W, int kern, const double* kp,
-                double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status, double* norm2,
-                int fresh, T* gpool, int64_t gcap, unsigned long long* gtop, hipStream_t s);
+                double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
+                double* norm2, int fresh, T* gpool, int64_t gcap, unsigned long long* gtop,
+                double2* gram, int gram_min, hipStream_t s);
+// workgroups of the persistent grid of the 512-thread (big = 1) or 256-thread ACA kernel
+template <class T>
+int aca_grid(int big);
+// Gram-matrix order per workgroup of the ACA kernels (steps past it use direct cross sums)
+constexpr int ACA_GRAM_R = 128;
 constexpr int ACA_BIG = 4096;  // blocks with m + n >= ACA_BIG run in 512-thread workgroups
 constexpr int ACA_WAVE_N = 64; // blocks with m, n <= ACA_WAVE_N run one per wavefront
 constexpr int ACA_WAVE_RC = 16; // terms a wavefront block holds in registers

@@ -41,9 +41,31 @@ struct AcaShared {
   double sv[16];
   int si[16];
   double ssum[32 * 9];  // block_sum scratch: N * (NT / 64 + 1) for N <= 32, NT <= 512
+  double2 h[ACA_GRAM_R];  // per previous term: v_l^H (row residual) or u_l^H (column residual)
   int64_t off;
   int q;
 };
+
+// sum_{p0 <= p < kk} c_p G[l][p] for one Gram row (8 independent loads per round).
+template <class T>
+__device__ __forceinline__ double2 gram_row_dot(const double2* __restrict__ row, const T* coef,
+                                                int p0, int kk) {
+  double2 t = make_double2(0.0, 0.0);
+  for (int p = p0; p < kk; p += 8) {
+    double2 gv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) gv[q] = p + q < kk ? row[p + q] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (p + q < kk) {
+        const double2 c = to_d2(coef[p + q]);
+        t.x += c.x * gv[q].x - c.y * gv[q].y;
+        t.y += c.x * gv[q].y + c.y * gv[q].x;
+      }
+    }
+  }
+  return t;
+}
 
 template <class T, int NT>
 __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __restrict__ X,
@@ -51,7 +73,9 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
                           const double* __restrict__ W, int kern, const double* kp, double tol,
                           uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                           double* norm2, int fresh, T* gpool, int64_t gcap,
-                          unsigned long long* gtop, T* coef, AcaShared& sh) {
+                          unsigned long long* gtop, double2* gram, int gram_min, T* coef,
+                          AcaShared& sh) {
+  constexpr int GW = NT >= 512 ? 8 : 4;  // terms per window of the Gram passes
   constexpr int JC = 1;                  // elements per thread per round
   constexpr int LU = NT >= 512 ? 8 : 4;  // previous terms loaded per round (loads in flight)
   const int tid = threadIdx.x;
@@ -77,6 +101,15 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     hits = ipiv[b] >> ACA_HIT_SHIFT;
     nrm2 = norm2[b];
   }
+  // Gram matrices of the factors, GV[l][p] = v_l^H v_p and GU[l][p] = u_l^H u_p (FP64,
+  // ACA_GRAM_R x ACA_GRAM_R each, row-major, this workgroup's scratch).  With them the cross
+  // terms of step (5) come from dot products taken in the residual passes themselves:
+  //   v_l^H R = v_l^H R' - sum_{p in and after l's window} u_p[i_k] GV[l][p],
+  // R' the residual before l's window, so the previous columns are read once per step.  Blocks
+  // resumed from a saved state, and ranks past ACA_GRAM_R, take the direct sums instead.
+  double2* GV = gram;
+  double2* GU = gram ? gram + ACA_GRAM_R * ACA_GRAM_R : nullptr;
+  bool use_gram = fresh && gram != nullptr && m + n >= gram_min;
   int st = d.rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
   if (st == ACA_RUNNING && U == nullptr) {
     // first slot, taken from the device pool
@@ -97,14 +130,53 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   }
   __syncthreads();
   while (st == ACA_RUNNING) {
+    if (kk >= ACA_GRAM_R) use_gram = false;
     // (1) residual row ip, stored as column kk of V when the slot has room
     for (int l = tid; l < kk; l += NT) coef[l] = U[(int64_t)l * m + ip];
     __syncthreads();
     const double px = X[tb + ip], py = Y[tb + ip], pz = Z[tb + ip];
     const bool store = kk < cap;
+    const bool gstep = use_gram && store;  // this step keeps the Gram matrices
     T* R = V + (int64_t)kk * n;
     double best = -1.0;
     int bj = INT_MAX;
+    // Gram part of v_l^H R for this thread's l (gstep: kk < ACA_GRAM_R <= NT, one l per thread);
+    // it needs only the coefficients, so its loads go out before the row pass
+    double2 gcorr = make_double2(0.0, 0.0);
+    if (gstep && tid < kk) gcorr = gram_row_dot(GV + (int64_t)tid * ACA_GRAM_R, coef, (tid / GW) * GW, kk);
+    if (gstep) {
+      // windows of GW previous terms; the partial residual lives in column kk between windows
+      for (int l0 = 0; l0 < max(kk, 1); l0 += GW) {
+        const int lc = min(GW, kk - l0);
+        const bool first = l0 == 0, last = l0 + GW >= kk;
+        double g[2 * GW];
+#pragma unroll
+        for (int q = 0; q < 2 * GW; ++q) g[q] = 0.0;
+        for (int j = tid; j < n; j += NT) {
+          T r = first ? eval_entry<T>(kern, k, px, py, pz, X[sb + j], Y[sb + j], Z[sb + j], W[sb + j])
+                      : R[j];
+          const double2 r0 = to_d2(r);
+          T vv[GW];
+#pragma unroll
+          for (int u = 0; u < GW; ++u) vv[u] = u < lc ? V[(int64_t)(l0 + u) * n + j] : czero<T>();
+#pragma unroll
+          for (int u = 0; u < GW; ++u) {
+            const double2 a = to_d2(vv[u]);
+            g[2 * u] += a.x * r0.x + a.y * r0.y;
+            g[2 * u + 1] += a.x * r0.y - a.y * r0.x;
+            if (u < lc) cfms(r, coef[l0 + u], vv[u]);
+          }
+          R[j] = r;
+          if (last && !cused[j]) amax_merge(best, bj, abs2(r), j);
+        }
+        if (lc > 0) {
+          block_sum<2 * GW, NT>(g, sh.ssum);
+#pragma unroll
+          for (int u = 0; u < GW; ++u)
+            if (tid == u && u < lc) sh.h[l0 + u] = make_double2(g[2 * u], g[2 * u + 1]);
+        }
+      }
+    } else {
     for (int j0 = tid; j0 < n; j0 += NT * JC) {
       T a[JC];
       int jx[JC];
@@ -142,6 +214,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           if (!cused[j]) amax_merge(best, bj, abs2(a[q]), j);
         }
       }
+    }
     }
     block_amax<NT>(best, bj, sh.sv, sh.si);
     if (bj == INT_MAX || best <= 1e-300) {
@@ -197,6 +270,13 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     const double2 pd = to_d2(R[bj]);
     const double den = pd.x * pd.x + pd.y * pd.y;
     const T inv = from_d2<T>(make_double2(pd.x / den, -pd.y / den));
+    // v_l^H v_k for this thread's l (gstep: kk < ACA_GRAM_R <= NT, one l per thread)
+    double2 vdot = make_double2(0.0, 0.0);
+    if (gstep && tid < kk) {
+      const double2 t = make_double2(sh.h[tid].x - gcorr.x, sh.h[tid].y - gcorr.y);
+      const double ix = pd.x / den, iy = -pd.y / den;
+      vdot = make_double2(t.x * ix - t.y * iy, t.x * iy + t.y * ix);
+    }
     __syncthreads();  // every thread has read the pivot before it is scaled in place
     if (tid == 0) {
       rused[ip] = 1;
@@ -216,6 +296,59 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     T* Uk = U + (int64_t)kk * m;
     double ub = -1.0, nu2 = 0.0;
     int ui = INT_MAX;
+    double cross = 0.0;
+    if (gstep) {
+      const double2 ucorr = tid < kk ? gram_row_dot(GU + (int64_t)tid * ACA_GRAM_R, coef,
+                                                    (tid / GW) * GW, kk)
+                                     : make_double2(0.0, 0.0);
+      for (int l0 = 0; l0 < max(kk, 1); l0 += GW) {
+        const int lc = min(GW, kk - l0);
+        const bool first = l0 == 0, last = l0 + GW >= kk;
+        double g[2 * GW];
+#pragma unroll
+        for (int q = 0; q < 2 * GW; ++q) g[q] = 0.0;
+        for (int i = tid; i < m; i += NT) {
+          T r = first ? eval_entry<T>(kern, k, X[tb + i], Y[tb + i], Z[tb + i], qx, qy, qz, qw)
+                      : Uk[i];
+          const double2 r0 = to_d2(r);
+          T uu[GW];
+#pragma unroll
+          for (int u = 0; u < GW; ++u) uu[u] = u < lc ? U[(int64_t)(l0 + u) * m + i] : czero<T>();
+#pragma unroll
+          for (int u = 0; u < GW; ++u) {
+            const double2 a = to_d2(uu[u]);
+            g[2 * u] += a.x * r0.x + a.y * r0.y;
+            g[2 * u + 1] += a.x * r0.y - a.y * r0.x;
+            if (u < lc) cfms(r, coef[l0 + u], uu[u]);
+          }
+          Uk[i] = r;
+          if (last) {
+            const double a2 = abs2(r);
+            nu2 += a2;
+            if (!rused[i]) amax_merge(ub, ui, a2, i);
+          }
+        }
+        if (lc > 0) {
+          block_sum<2 * GW, NT>(g, sh.ssum);
+#pragma unroll
+          for (int u = 0; u < GW; ++u)
+            if (tid == u && u < lc) sh.h[l0 + u] = make_double2(g[2 * u], g[2 * u + 1]);
+        }
+      }
+      __syncthreads();
+      // u_l^H u_k, the cross term, and the new Gram entries
+      double2 udot = make_double2(0.0, 0.0);
+      if (tid < kk) udot = make_double2(sh.h[tid].x - ucorr.x, sh.h[tid].y - ucorr.y);
+      double cr[1] = {udot.x * vdot.x - udot.y * vdot.y};
+      block_sum<1, NT>(cr, sh.ssum);
+      cross = cr[0];
+      if (tid < kk) {
+        GV[(int64_t)tid * ACA_GRAM_R + kk] = vdot;
+        GV[(int64_t)kk * ACA_GRAM_R + tid] = make_double2(vdot.x, -vdot.y);
+        GU[(int64_t)tid * ACA_GRAM_R + kk] = udot;
+        GU[(int64_t)kk * ACA_GRAM_R + tid] = make_double2(udot.x, -udot.y);
+      }
+    } else {
     for (int i0 = tid; i0 < m; i0 += NT * JC) {
       T a[JC];
       int ix[JC];
@@ -258,9 +391,8 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     __syncthreads();
     // (5) cross terms sum_{l<kk} (u_l^H u_k)(v_l^H v_k), LG terms at a time (LG loads in
     // flight per thread per round)
-    constexpr int LG = NT >= 512 ? 8 : 4;
+    constexpr int LG = NT >= 512 ? 4 : 2;
     constexpr int CJ = 1;  // elements per thread per round in this pass
-    double cross = 0.0;
     for (int l0 = 0; l0 < kk; l0 += LG) {
       const int lc = min(LG, kk - l0);
       double acc[4 * LG];
@@ -312,8 +444,13 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
         if (q < lc)
           cross += acc[2 * q] * acc[2 * LG + 2 * q] - acc[2 * q + 1] * acc[2 * LG + 2 * q + 1];
     }
+    }
     double nn2[2] = {nu2, nv2};
     block_sum<2, NT>(nn2, sh.ssum);
+    if (gstep && tid == 0) {
+      GV[(int64_t)kk * ACA_GRAM_R + kk] = make_double2(nn2[1], 0.0);
+      GU[(int64_t)kk * ACA_GRAM_R + kk] = make_double2(nn2[0], 0.0);
+    }
     nrm2 = nrm2 + 2.0 * cross + nn2[0] * nn2[1];
     kk += 1;
     block_amax<NT>(ub, ui, sh.sv, sh.si);
@@ -342,7 +479,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
 }
 
 template <class T, int NT>
-__global__ void __launch_bounds__(NT) aca_kernel(FarDesc* __restrict__ desc,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 2 : 3))) aca_kernel(FarDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order, int nb,
                                                  int* counter, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
@@ -351,9 +488,11 @@ __global__ void __launch_bounds__(NT) aca_kernel(FarDesc* __restrict__ desc,
                                                  double tol, uint8_t* flags, int32_t* rank,
                                                  int32_t* ipiv, int32_t* status, double* norm2,
                                                  int fresh, T* gpool, int64_t gcap,
-                                                 unsigned long long* gtop) {
+                                                 unsigned long long* gtop, double2* gram,
+                                                 int gram_min) {
   __shared__ T coef[ACA_COEF_MAX];
   __shared__ AcaShared sh;
+  double2* my_gram = gram ? gram + (int64_t)blockIdx.x * 2 * ACA_GRAM_R * ACA_GRAM_R : nullptr;
   for (;;) {
     if (threadIdx.x == 0) sh.q = atomicAdd(counter, 1);
     __syncthreads();
@@ -361,7 +500,7 @@ __global__ void __launch_bounds__(NT) aca_kernel(FarDesc* __restrict__ desc,
     __syncthreads();
     if (q >= nb) break;
     aca_block<T, NT>(desc, order[q], X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2,
-                     fresh, gpool, gcap, gtop, coef, sh);
+                     fresh, gpool, gcap, gtop, my_gram, gram_min, coef, sh);
   }
 }
 
@@ -571,26 +710,37 @@ void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
   HMX_LAUNCHED();
 }
 
+// Workgroups of a persistent ACA grid: as many as can be resident at once.
 template <class T>
-void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
-                const double* Y, const double* Z, const double* W, int kern, const double* kp, double tol,
-                uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status, double* norm2,
-                int fresh, T* gpool, int64_t gcap, unsigned long long* gtop, hipStream_t s) {
-  if (nb <= 0) return;
-  int dev = 0, ncu = 0;
+int aca_grid(int big) {
+  int dev = 0, ncu = 0, occ = 0;
   HMX_HIP(hipGetDevice(&dev));
   HMX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  if (big) {
-    int grid = std::min(nb, 2 * ncu);
+  if (big)
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 512>, 512, 0));
+  else
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, WG>, WG, 0));
+  return std::max(1, occ) * ncu;
+}
+
+template <class T>
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
+                const double* Y, const double* Z, const double* W, int kern, const double* kp,
+                double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
+                double* norm2, int fresh, T* gpool, int64_t gcap, unsigned long long* gtop,
+                double2* gram, int gram_min, hipStream_t s) {
+  if (nb <= 0) return;
+  // `gram` (when given) holds 2 ACA_GRAM_R^2 entries for each of aca_grid(big) workgroups;
+  // blocks with m + n >= gram_min use it
+  const int grid = std::min(nb, aca_grid<T>(big));
+  if (big)
     hipLaunchKernelGGL((aca_kernel<T, 512>), dim3(grid), dim3(512), 0, s, d, order, nb, counter,
                        X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
-                       gcap, gtop);
-  } else {
-    int grid = std::min(nb, 8 * ncu);
+                       gcap, gtop, gram, gram_min);
+  else
     hipLaunchKernelGGL((aca_kernel<T, WG>), dim3(grid), dim3(WG), 0, s, d, order, nb, counter, X,
                        Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool, gcap,
-                       gtop);
-  }
+                       gtop, gram, gram_min);
   HMX_LAUNCHED();
 }
 
@@ -628,9 +778,9 @@ void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* 
                                    int64_t, unsigned long long*, hipStream_t);                   \
   template void launch_aca<T>(FarDesc*, const int32_t*, int, int*, int, const double*,           \
                               const double*, const double*, const double*, int, const double*,   \
-                              double,                                                            \
-                              uint8_t*, int32_t*, int32_t*, int32_t*, double*, int, T*, int64_t, \
-                              unsigned long long*, hipStream_t);                                 \
+                              double, uint8_t*, int32_t*, int32_t*, int32_t*, double*, int, T*,  \
+                              int64_t, unsigned long long*, double2*, int, hipStream_t);         \
+  template int aca_grid<T>(int);                                                                 \
   template void launch_copy_factors<T>(const FarDesc*, const FarDesc*, const int32_t*,           \
                                        const int32_t*, int, hipStream_t);                        \
 
