@@ -76,10 +76,20 @@ typedef struct {
   double force_pred_scale; /* learned mode: multiplies the predicted rank (tests force overflow) */
   int32_t force_rank_cap;  /* > 0: caps every far block's ACA rank (tests force dense fallback) */
   int64_t pool_limit_bytes; /* > 0: fail with HMX_ENOMEM when the operator would exceed this */
+  /* ACA schedule (results may differ in rounding between schedules, not in method):
+   * far blocks with m + n >= aca_big_mn run in 512-thread workgroups, those with m, n <= 64 one
+   * per wavefront, the others in 256-thread workgroups; blocks with m + n >= aca_gram_min_mn
+   * take the cross terms from Gram matrices (one read of the factors per step); aca_serial = 1
+   * runs the three classes one after the other instead of on three concurrent streams.
+   * hmx_autotune picks these for a workload. */
+  int32_t aca_big_mn;      /* >= 2 (default 4096) */
+  int32_t aca_gram_min_mn; /* >= 0 (default 1024) */
+  int32_t aca_serial;      /* 0 or 1 (default 0) */
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
- * initial_rank 16, force_pred_scale 1, no rank cap, no pool limit. */
+ * initial_rank 16, force_pred_scale 1, no rank cap, no pool limit, ACA schedule 4096 / 1024 /
+ * concurrent. */
 hmx_status hmx_params_default(hmx_params* p);
 
 typedef struct hmx_op hmx_op; /* opaque, library-owned; free with hmx_destroy */
@@ -161,6 +171,20 @@ typedef struct hmx_graph hmx_graph;
 hmx_status hmx_graph_create(const hmx_op* op, const void* x, void* y, hmx_graph** out);
 hmx_status hmx_graph_launch(hmx_graph* g, int32_t reps, void* stream);
 void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
+
+/* Autotuner of the ACA schedule (aca_big_mn, aca_gram_min_mn, aca_serial of hmx_params).
+ * Times hmx_build_points(xyzw, M, kern, k) under a grid of settings: class thresholds
+ * {2048, 4096, 8192, none} x Gram thresholds {0, 1024, 4096, none} on concurrent streams, then
+ * serial classes at the best pair; best of two builds each.  *out receives *p (defaults when
+ * NULL) with the fastest settings, *best_ms (may be NULL) that build time in ms.
+ * cache_path (host string, may be NULL): a JSON file of earlier choices keyed by device
+ * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size and eta; a key
+ * found there is returned without timing, a new one is added to the file.  Synchronous; builds
+ * and frees up to 19 operators.  Errors: as hmx_build_points, HMX_EINVAL for tol <= 0 or an
+ * unwritable cache file. */
+hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
+                        const hmx_params* p, const char* cache_path, void* stream,
+                        hmx_params* out, double* best_ms);
 
 typedef struct {
   int64_t n_points, n_nodes, n_leaves, n_near, n_far;

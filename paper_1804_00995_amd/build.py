@@ -23,6 +23,7 @@ UNITS = [
     ("hmx_build.hip", False),
     ("hmx_mem.hip", False),
     ("hmx_mlp.hip", False),
+    ("hmx_tune.hip", False),
     ("k_quad.hip", True),
     ("k_scan.hip", False),
     ("k_tree.hip", True),

@@ -55,6 +55,9 @@ void defaults(hmx_params* p) {
   p->force_pred_scale = 1.0;
   p->force_rank_cap = 0;
   p->pool_limit_bytes = 0;
+  p->aca_big_mn = 4096;
+  p->aca_gram_min_mn = 1024;
+  p->aca_serial = 0;
 }
 
 hmx_params resolve(const hmx_params* in) {
@@ -78,6 +81,9 @@ hmx_params resolve(const hmx_params* in) {
               "force_pred_scale must be finite and >= 0");
   HMX_REQUIRE(p.force_rank_cap >= 0, HMX_EINVAL, "force_rank_cap must be >= 0");
   HMX_REQUIRE(p.pool_limit_bytes >= 0, HMX_EINVAL, "pool_limit_bytes must be >= 0");
+  HMX_REQUIRE(p.aca_big_mn >= 2, HMX_EINVAL, "aca_big_mn must be >= 2");
+  HMX_REQUIRE(p.aca_gram_min_mn >= 0, HMX_EINVAL, "aca_gram_min_mn must be >= 0");
+  HMX_REQUIRE(p.aca_serial == 0 || p.aca_serial == 1, HMX_EINVAL, "aca_serial must be 0 or 1");
   return p;
 }
 

@@ -283,7 +283,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     // first slot: initial_rank columns, more for large blocks (their ranks grow with size)
     const int64_t mn = (int64_t)d.m + d.n;
     const int64_t c0 = mn >= 2 * ACA_BIG ? 3 * (int64_t)op->p.initial_rank
-                       : mn >= ACA_BIG   ? 2 * (int64_t)op->p.initial_rank
+                       : mn >= ACA_BIG ? 2 * (int64_t)op->p.initial_rank
                                          : (int64_t)op->p.initial_rank;
     d.cap = (int32_t)std::min<int64_t>(rc, c0);
     d.U = d.V = nullptr;
@@ -377,14 +377,12 @@ void build_far(hmx_op* op, hipStream_t s) {
   const int64_t gram_per_wg = 2 * (int64_t)ACA_GRAM_R * ACA_GRAM_R;
   DevBuf<double2> gram_big((size_t)aca_grid<T>(1) * gram_per_wg);
   DevBuf<double2> gram_mid((size_t)aca_grid<T>(0) * gram_per_wg);
-  // blocks below this m + n take the direct cross sums (fewer barriers per step pays off there)
-  static const int gram_min = [] {
-    const char* e = std::getenv("HMX_ACA_GRAM_MIN");
-    return e ? std::atoi(e) : 1024;
-  }();
+  // blocks below aca_gram_min_mn take the direct cross sums (fewer barriers per step)
+  const int gram_min = op->p.aca_gram_min_mn;
   std::vector<uint8_t> cls0(nf, 0);  // class of each block in the first launch
 
-  // run ACA on a list of blocks, largest first within each class: m + n >= ACA_BIG in
+  const int64_t big_mn = op->p.aca_big_mn;
+  // run ACA on a list of blocks, largest first within each class: m + n >= aca_big_mn in
   // 512-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per wavefront (stream s3, fresh
   // blocks only), the others in 256-thread workgroups (stream s)
   auto run_aca = [&](const std::vector<int32_t>& list, int fresh) {
@@ -393,7 +391,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     for (int32_t b : list) {
       const FarDesc& d = desc[b];
       const int64_t mn = (int64_t)d.m + d.n;
-      const int cls = mn >= ACA_BIG ? 0 : (fresh && is_wave[b]) ? 2 : 1;
+      const int cls = mn >= big_mn ? 0 : (fresh && is_wave[b]) ? 2 : 1;
       if (fresh) cls0[b] = (uint8_t)cls;
       bucket[cls][31 - std::min(31, 63 - __builtin_clzll((unsigned long long)mn))].push_back(b);
     }
@@ -409,12 +407,9 @@ void build_far(hmx_op* op, hipStream_t s) {
     if (!ord.empty())
       HMX_HIP(hipMemcpyAsync(d_order.p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s));
     fill_i32(counter.p, 0, 3, s);
-    // HMX_ACA_SERIAL=1 runs the classes one after the other on `s` (same work; used to time
+    // aca_serial = 1 runs the classes one after the other on `s` (same work; also used to time
     // each class on its own)
-    static const bool serial = [] {
-      const char* e = std::getenv("HMX_ACA_SERIAL");
-      return e && e[0] == '1';
-    }();
+    const bool serial = op->p.aca_serial != 0;
     hipStream_t s2 = serial ? s : s2_;
     hipStream_t s3 = serial ? s : s3_;
     HMX_HIP(hipEventRecord(ev_ready, s));

@@ -189,7 +189,7 @@ template <class T>
 int aca_grid(int big);
 // Gram-matrix order per workgroup of the ACA kernels (steps past it use direct cross sums)
 constexpr int ACA_GRAM_R = 128;
-constexpr int ACA_BIG = 4096;  // blocks with m + n >= ACA_BIG run in 512-thread workgroups
+constexpr int ACA_BIG = 4096;  // block size (m + n) from which first rank slots are enlarged
 constexpr int ACA_WAVE_N = 64; // blocks with m, n <= ACA_WAVE_N run one per wavefront
 constexpr int ACA_WAVE_RC = 16; // terms a wavefront block holds in registers
 template <class T>
@@ -284,7 +284,7 @@ struct hmx_op {
   hmx::DevBuf<unsigned char> xp, tbuf, partial;
   // build statistics
   double t_tree = 0, t_blocks = 0, t_near = 0, t_aca = 0, t_total = 0;
-  // ACA by block class (0: m + n >= ACA_BIG, 1: other workgroup blocks, 2: wavefront blocks)
+  // ACA by block class (0: m + n >= aca_big_mn, 1: other workgroup blocks, 2: wavefront blocks)
   int64_t aca_blocks[3] = {0, 0, 0}, aca_bytes[3] = {0, 0, 0};
   double aca_ms[3] = {0, 0, 0};
   int32_t aca_rounds = 0;

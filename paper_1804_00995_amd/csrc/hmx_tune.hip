@@ -1,0 +1,181 @@
+// hmx_tune.hip -- autotuner of the ACA schedule (hmx_autotune).  A client of the library's own
+// entry points: it builds the caller's operator under a grid of schedule settings, times each
+// build, and keeps the fastest.  Results are cached in a small JSON file keyed by device
+// architecture and problem class, so a later call for the same class returns at once.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "hmx_host.h"
+
+namespace {
+
+struct Choice {
+  int big = 4096, gram = 1024, serial = 0;
+  double ms = 0.0;
+};
+
+// "<arch>|<precision>|<kernel>|M2^<floor(log2 M)>|tol1e<round(log10 tol)>|leaf<L>|eta<eta>"
+std::string class_key(int64_t M, int32_t kern, const hmx_params& p) {
+  int dev = 0;
+  HMX_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HMX_HIP(hipGetDeviceProperties(&prop, dev));
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  int lm = 0;
+  while ((int64_t(1) << (lm + 1)) <= M) ++lm;
+  const long te = std::lround(std::log10(p.tol));
+  std::ostringstream o;
+  o << arch << "|" << (p.precision == HMX_FP64 ? "fp64" : "fp32") << "|"
+    << (kern == HMX_LAPLACE ? "laplace" : kern == HMX_HELMHOLTZ ? "helmholtz" : "poly2")
+    << "|M2^" << lm << "|tol1e" << te << "|leaf" << p.leaf_size << "|eta" << p.eta;
+  return o.str();
+}
+
+// The cache file is one JSON object of entries
+//   "key": {"aca_big_mn": N, "aca_gram_min_mn": N, "aca_serial": N, "ms": X}
+// written by this file; the reader accepts exactly that shape.
+double field(const std::string& body, const char* name, double dflt) {
+  const std::string pat = std::string("\"") + name + "\":";
+  size_t i = body.find(pat);
+  if (i == std::string::npos) return dflt;
+  return std::strtod(body.c_str() + i + pat.size(), nullptr);
+}
+
+std::map<std::string, Choice> read_cache(const char* path) {
+  std::map<std::string, Choice> out;
+  if (!path) return out;
+  std::ifstream f(path);
+  if (!f) return out;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t pos = 0;
+  for (;;) {
+    const size_t q0 = t.find('"', pos);
+    if (q0 == std::string::npos) break;
+    const size_t q1 = t.find('"', q0 + 1);
+    const size_t b0 = t.find('{', q1);
+    const size_t b1 = t.find('}', b0);
+    if (q1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) break;
+    const std::string key = t.substr(q0 + 1, q1 - q0 - 1);
+    const std::string body = t.substr(b0, b1 - b0 + 1);
+    Choice c;
+    c.big = (int)field(body, "aca_big_mn", 4096);
+    c.gram = (int)field(body, "aca_gram_min_mn", 1024);
+    c.serial = (int)field(body, "aca_serial", 0);
+    c.ms = field(body, "ms", 0.0);
+    out[key] = c;
+    pos = b1 + 1;
+  }
+  return out;
+}
+
+void write_cache(const char* path, const std::map<std::string, Choice>& m) {
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    HMX_REQUIRE(bool(f), HMX_EINVAL, "cannot write the autotuner cache file");
+    f << "{\n";
+    size_t i = 0;
+    for (const auto& kv : m) {
+      char buf[256];
+      std::snprintf(buf, sizeof(buf),
+                    "{\"aca_big_mn\": %d, \"aca_gram_min_mn\": %d, \"aca_serial\": %d, \"ms\": %.3f}",
+                    kv.second.big, kv.second.gram, kv.second.serial, kv.second.ms);
+      f << "  \"" << kv.first << "\": " << buf << (++i < m.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+  }
+  HMX_REQUIRE(std::rename(tmp.c_str(), path) == 0, HMX_EINVAL,
+              "cannot replace the autotuner cache file");
+}
+
+// Best of `reps` synchronous builds, in ms (wall clock around the synchronous call).
+double time_build(const double* xyzw, int64_t M, int32_t kern, double k, const hmx_params& p,
+                  void* stream, int reps) {
+  double best = 1e300;
+  for (int r = 0; r < reps; ++r) {
+    hmx_op* op = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    const hmx_status st = hmx_build_points(xyzw, M, kern, k, &p, stream, &op);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (st != HMX_OK) throw hmx::Error(st, hmx_last_error());
+    hmx_destroy(op);
+    best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
+  }
+  return best;
+}
+
+}  // namespace
+
+extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
+                                   const hmx_params* p, const char* cache_path, void* stream,
+                                   hmx_params* out, double* best_ms) {
+  try {
+    HMX_REQUIRE(xyzw && out, HMX_EINVAL, "null pointer");
+    HMX_REQUIRE(M >= 1, HMX_EINVAL, "M must be >= 1");
+    hmx_params base;
+    if (p) {
+      base = *p;
+    } else {
+      const hmx_status st = hmx_params_default(&base);
+      if (st != HMX_OK) return st;
+    }
+    HMX_REQUIRE(base.struct_size == (int32_t)sizeof(hmx_params), HMX_EINVAL,
+                "hmx_params.struct_size does not match this library (use hmx_params_default)");
+    HMX_REQUIRE(base.tol > 0, HMX_EINVAL, "the autotuner needs an H-matrix build (tol > 0)");
+    const std::string key = class_key(M, kern, base);
+    auto cache = read_cache(cache_path);
+    auto hit = cache.find(key);
+    Choice best;
+    if (hit != cache.end()) {
+      best = hit->second;
+    } else {
+      // the class thresholds first (concurrent classes), then serial vs concurrent at the best
+      const int bigs[] = {2048, 4096, 8192, 1 << 30};
+      const int grams[] = {0, 1024, 4096, 1 << 30};
+      hmx_params q = base;
+      q.aca_serial = 0;
+      (void)time_build(xyzw, M, kern, k, q, stream, 1);  // warm the allocator and the code
+      best.ms = 1e300;
+      for (int b : bigs)
+        for (int g : grams) {
+          q.aca_big_mn = b;
+          q.aca_gram_min_mn = g;
+          const double ms = time_build(xyzw, M, kern, k, q, stream, 2);
+          if (ms < best.ms) best = Choice{b, g, 0, ms};
+        }
+      q.aca_big_mn = best.big;
+      q.aca_gram_min_mn = best.gram;
+      q.aca_serial = 1;
+      const double ms = time_build(xyzw, M, kern, k, q, stream, 2);
+      if (ms < best.ms) best = Choice{best.big, best.gram, 1, ms};
+      cache[key] = best;
+      write_cache(cache_path, cache);
+    }
+    *out = base;
+    out->aca_big_mn = best.big;
+    out->aca_gram_min_mn = best.gram;
+    out->aca_serial = best.serial;
+    if (best_ms) *best_ms = best.ms;
+    return HMX_OK;
+  } catch (const hmx::Error& e) {
+    hmx::set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    hmx::set_last_error(e.what());
+    return HMX_EINTERNAL;
+  }
+}

@@ -40,6 +40,9 @@ class Params(C.Structure):
         ("force_pred_scale", C.c_double),
         ("force_rank_cap", C.c_int32),
         ("pool_limit_bytes", C.c_int64),
+        ("aca_big_mn", C.c_int32),
+        ("aca_gram_min_mn", C.c_int32),
+        ("aca_serial", C.c_int32),
     ]
 
 
@@ -81,6 +84,8 @@ _sig = {
     "hmx_mesh_offsets": [_P, _P, _i32, C.POINTER(_i32)],
     "hmx_graph_create": [_P, _P, _P, C.POINTER(_P)],
     "hmx_graph_launch": [_P, _i32, _P],
+    "hmx_autotune": [_P, _i64, _i32, _f64, C.POINTER(Params), C.c_char_p, _P, C.POINTER(Params),
+                     C.POINTER(_f64)],
 }
 MLP_NPARAMS = 4545
 for _name, _args in _sig.items():
@@ -334,6 +339,20 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def autotune(xyzw, kern=HELMHOLTZ, k=0.0, prm: Params | None = None, cache_path=None, stream=None):
+    """Fastest ACA schedule for building from these points (xyzw float64 (4, M) device tensor):
+    returns (params with the chosen schedule, build ms).  A cache file, when given, is read and
+    updated."""
+    import torch
+    prm = prm or params()
+    out = Params()
+    ms = C.c_double(0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(_lib.hmx_autotune(_dev(xyzw, torch.float64, "xyzw"), xyzw.shape[1], kern, float(k),
+                             C.byref(prm), path, _stream_ptr(stream), C.byref(out), C.byref(ms)))
+    return out, ms.value
 
 
 # ------------------------------------------------------------------------ learned block ranks

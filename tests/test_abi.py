@@ -104,3 +104,22 @@ def test_batch_argument_errors_without_gpu():
     assert lib.hmx_graph_create(None, None, None, C.byref(h)) == hmx.EINVAL
     assert lib.hmx_graph_launch(None, 1, None) == hmx.EINVAL
     lib.hmx_graph_destroy(None)  # NULL-safe
+
+
+def test_autotune_argument_errors_without_gpu():
+    import ctypes as C
+    from paper_1804_00995_amd import hmx
+    lib = hmx._lib
+    out = hmx.Params()
+    ms = C.c_double(0)
+    fake = C.c_void_p(4096)
+    assert lib.hmx_autotune(None, 10, 1, 1.0, None, None, None, C.byref(out), C.byref(ms)) == hmx.EINVAL
+    assert lib.hmx_autotune(fake, 0, 1, 1.0, None, None, None, C.byref(out), C.byref(ms)) == hmx.EINVAL
+    dense = hmx.params(tol=0.0)
+    assert lib.hmx_autotune(fake, 10, 1, 1.0, C.byref(dense), None, None, C.byref(out),
+                            C.byref(ms)) == hmx.EINVAL
+    bad = hmx.params(aca_serial=2)
+    h = C.c_void_p()
+    assert lib.hmx_build_points(fake, 10, 1, 1.0, C.byref(bad), None, C.byref(h)) == hmx.EINVAL
+    bad = hmx.params(aca_big_mn=1)
+    assert lib.hmx_build_points(fake, 10, 1, 1.0, C.byref(bad), None, C.byref(h)) == hmx.EINVAL
