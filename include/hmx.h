@@ -85,6 +85,14 @@ typedef struct {
   int32_t aca_big_mn;      /* >= 2 (default 4096) */
   int32_t aca_gram_min_mn; /* >= 0 (default 1024) */
   int32_t aca_serial;      /* 0 or 1 (default 0) */
+  /* Row share (the part of the operator one of row_shares devices would hold): with
+   * row_shares = 2^s > 1, the operator keeps only the rows of cluster-tree node number
+   * row_share (breadth-first order) at level s, against all columns; the product then writes
+   * K x on those rows and 0 elsewhere, and the shares' products sum to the whole product.
+   * Requires tol > 0 and a single mesh; HMX_EUNSUPPORTED when the tree has a leaf above level
+   * s or a block would cross the share's boundary. */
+  int32_t row_shares; /* power of two >= 1 (default 1) */
+  int32_t row_share;  /* 0 <= row_share < row_shares (default 0) */
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
@@ -209,6 +217,7 @@ typedef struct {
   double aca_ms[3];
   int64_t aca_bytes[3];
   int32_t aca_rounds; /* ACA launch rounds: 1 + continuation rounds (device pool exhausted) */
+  int64_t row_begin, row_end; /* rows held, in cluster positions (all rows: 0, n_points) */
 } hmx_info_t;
 
 /* Sizes, counts and build timings of an operator. */

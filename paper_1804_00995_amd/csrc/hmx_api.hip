@@ -58,6 +58,8 @@ void defaults(hmx_params* p) {
   p->aca_big_mn = 4096;
   p->aca_gram_min_mn = 1024;
   p->aca_serial = 0;
+  p->row_shares = 1;
+  p->row_share = 0;
 }
 
 hmx_params resolve(const hmx_params* in) {
@@ -84,6 +86,13 @@ hmx_params resolve(const hmx_params* in) {
   HMX_REQUIRE(p.aca_big_mn >= 2, HMX_EINVAL, "aca_big_mn must be >= 2");
   HMX_REQUIRE(p.aca_gram_min_mn >= 0, HMX_EINVAL, "aca_gram_min_mn must be >= 0");
   HMX_REQUIRE(p.aca_serial == 0 || p.aca_serial == 1, HMX_EINVAL, "aca_serial must be 0 or 1");
+  HMX_REQUIRE(p.row_shares >= 1 && p.row_shares <= (1 << 20) &&
+                  (p.row_shares & (p.row_shares - 1)) == 0,
+              HMX_EINVAL, "row_shares must be a power of two in [1, 2^20]");
+  HMX_REQUIRE(p.row_share >= 0 && p.row_share < p.row_shares, HMX_EINVAL,
+              "row_share must be in [0, row_shares)");
+  HMX_REQUIRE(p.row_shares == 1 || p.tol > 0, HMX_EUNSUPPORTED,
+              "row shares need an H-matrix operator (tol > 0)");
   return p;
 }
 
@@ -306,6 +315,7 @@ hmx_status hmx_build_batch(const hmx_mesh* meshes, int32_t n_meshes, const doubl
   HMX_REQUIRE(n_meshes >= 1, HMX_EINVAL, "n_meshes must be >= 1");
   hmx_params prm = resolve(p);
   HMX_REQUIRE(prm.tol > 0, HMX_EINVAL, "a batch operator needs tol > 0");
+  HMX_REQUIRE(prm.row_shares == 1, HMX_EUNSUPPORTED, "row shares of a batch operator");
   Rule r = make_rule(q_bary, q_w, n_q);
   auto op = std::make_unique<hmx_op>();
   op->mesh_off.assign(1, 0);
@@ -390,6 +400,8 @@ hmx_status hmx_info(const hmx_op* op, hmx_info_t* out) {
     out->aca_bytes[c] = op->aca_bytes[c];
   }
   out->aca_rounds = op->aca_rounds;
+  out->row_begin = op->dense ? 0 : op->row_begin;
+  out->row_end = op->dense ? op->M : op->row_end;
   return HMX_OK;
 }
 

@@ -183,8 +183,28 @@ void build_blocks(hmx_op* op, hipStream_t s) {
   size_t fcap = 1024, ncap = std::max<size_t>(1024, 64 * (size_t)op->n_leaves),
          xcap = std::max<size_t>(1024, 64 * (size_t)op->n_leaves);
   DevBuf<int2> front(fcap), next(fcap), nearL(ncap), farL(xcap);
-  DevBuf<int> cnt(3);  // next, near, far
-  fill_i32(cnt.p, 0, 3, s);
+  DevBuf<int> cnt(4);  // next, near, far, error flag
+  fill_i32(cnt.p, 0, 4, s);
+  // row share: the point range of node number row_share at tree level log2(row_shares)
+  int rb = 0, re = (int)op->M;
+  if (op->p.row_shares > 1) {
+    HMX_REQUIRE(op->mesh_off.size() == 2, HMX_EUNSUPPORTED, "row shares of a batch operator");
+    int lev = 0;
+    while ((1 << lev) < op->p.row_shares) ++lev;
+    std::vector<int32_t> hl, hb, he;
+    to_host(hl, op->nlevel.p, op->n_nodes, s);
+    to_host(hb, op->nbegin.p, op->n_nodes, s);
+    to_host(he, op->nend.p, op->n_nodes, s);
+    std::vector<int> at;
+    for (int v = 0; v < op->n_nodes; ++v)
+      if (hl[v] == lev) at.push_back(v);
+    HMX_REQUIRE((int)at.size() == op->p.row_shares, HMX_EUNSUPPORTED,
+                "the cluster tree has a leaf above the row-share level");
+    rb = hb[at[op->p.row_share]];
+    re = he[at[op->p.row_share]];
+  }
+  op->row_begin = rb;
+  op->row_end = re;
   // the frontier starts with (root, root) of every mesh: meshes never interact
   const int nroot = (int)op->mesh_off.size() - 1;
   std::vector<int2> roots(nroot);
@@ -200,11 +220,14 @@ void build_blocks(hmx_op* op, hipStream_t s) {
     if (nearL.n < (size_t)(n_near + nfront)) grow(nearL, 2 * (n_near + nfront), n_near, s);
     if (farL.n < (size_t)(n_far + nfront)) grow(farL, 2 * (n_far + nfront), n_far, s);
     fill_i32(cnt.p, 0, 1, s);
-    launch_block_level(front.p, (int)nfront, op->box.p, op->child0.p, op->child1.p, eta2, next.p,
-                       cnt.p, nearL.p, cnt.p + 1, farL.p, cnt.p + 2, s);
-    int c[3];
+    launch_block_level(front.p, (int)nfront, op->box.p, op->child0.p, op->child1.p,
+                       op->nbegin.p, op->nend.p, rb, re, eta2, next.p, cnt.p, nearL.p, cnt.p + 1,
+                       farL.p, cnt.p + 2, cnt.p + 3, s);
+    int c[4];
     HMX_HIP(hipMemcpyAsync(c, cnt.p, sizeof(c), hipMemcpyDeviceToHost, s));
     HMX_HIP(hipStreamSynchronize(s));
+    HMX_REQUIRE(c[3] == 0, HMX_EUNSUPPORTED,
+                "a block crosses the row-share boundary (use fewer row shares)");
     nfront = c[0];
     n_near = c[1];
     n_far = c[2];

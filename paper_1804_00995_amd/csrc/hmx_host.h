@@ -154,8 +154,9 @@ void launch_start_node(int n_nodes, const int32_t* nbegin, const int32_t* child0
 void launch_leaf_index(int n_leaves, const int32_t* leaves, int32_t* leaf_of_node, hipStream_t s);
 // k_blocks.hip
 void launch_block_level(const int2* front, int nfront, const double* box, const int32_t* child0,
-                        const int32_t* child1, double eta2, int2* next, int* next_cnt,
-                        int2* nearL, int* near_cnt, int2* farL, int* far_cnt, hipStream_t s);
+                        const int32_t* child1, const int32_t* nbegin, const int32_t* nend, int rb,
+                        int re, double eta2, int2* next, int* next_cnt, int2* nearL,
+                        int* near_cnt, int2* farL, int* far_cnt, int* err, hipStream_t s);
 void launch_pair_keys(const int2* pairs, int64_t n, int64_t npad, const int32_t* nbegin,
                       const int32_t* level, uint64_t* key, int32_t* val, hipStream_t s);
 void launch_pair_gather(const int2* in, const int32_t* idx, int64_t n, int2* out, hipStream_t s);
@@ -258,6 +259,8 @@ struct hmx_op {
   // meshes of a batched operator: points [mesh_off[i], mesh_off[i + 1]) belong to mesh i
   std::vector<int64_t> mesh_off;
   std::vector<double> mesh_k;
+  // rows held (cluster positions [row_begin, row_end)); all rows unless built as a row share
+  int64_t row_begin = 0, row_end = 0;
   // tree (breadth-first node numbering)
   int n_nodes = 0, n_leaves = 0, depth = 0;
   hmx::DevBuf<int32_t> nbegin, nend, nlevel, child0, child1, parent;

@@ -29,27 +29,37 @@ __device__ __forceinline__ double dist2(const double* a, const double* b) {
   return s;
 }
 
+// Row shares: only pairs whose row node meets the point range [rb, re) (cluster positions) are
+// followed, and a block is emitted only when its row node lies inside the range; a block that
+// would straddle the range sets *err (the caller picks the range as a node below every emitted
+// block).  rb = 0, re = M keeps everything.
 __global__ void __launch_bounds__(WG) block_level_kernel(
     const int2* __restrict__ front, int nfront, const double* __restrict__ box,
-    const int32_t* __restrict__ child0, const int32_t* __restrict__ child1, double eta2,
-    int2* __restrict__ next, int* next_cnt, int2* __restrict__ nearL, int* near_cnt,
-    int2* __restrict__ farL, int* far_cnt) {
+    const int32_t* __restrict__ child0, const int32_t* __restrict__ child1,
+    const int32_t* __restrict__ nbegin, const int32_t* __restrict__ nend, int rb, int re,
+    double eta2, int2* __restrict__ next, int* next_cnt, int2* __restrict__ nearL, int* near_cnt,
+    int2* __restrict__ farL, int* far_cnt, int* err) {
   int i = blockIdx.x * WG + threadIdx.x;
   if (i >= nfront) return;
   int2 ts = front[i];
   int t = ts.x, s = ts.y;
+  const int tb = nbegin[t], te = nend[t];
+  if (te <= rb || tb >= re) return;  // rows outside the share
+  const bool inside = tb >= rb && te <= re;
   const double* bt = box + 6 * (int64_t)t;
   const double* bs = box + 6 * (int64_t)s;
   double dt = diam2(bt), ds = diam2(bs);
   double dmin = dt < ds ? dt : ds;
   if (dmin <= eta2 * dist2(bt, bs)) {
-    farL[atomicAdd(far_cnt, 1)] = ts;
+    if (inside) farL[atomicAdd(far_cnt, 1)] = ts;
+    else atomicOr(err, 1);
     return;
   }
   int t0 = child0[t], s0 = child0[s];
   bool lt = t0 < 0, ls = s0 < 0;
   if (lt && ls) {
-    nearL[atomicAdd(near_cnt, 1)] = ts;
+    if (inside) nearL[atomicAdd(near_cnt, 1)] = ts;
+    else atomicOr(err, 1);
   } else if (lt) {
     int q = atomicAdd(next_cnt, 2);
     next[q] = make_int2(t, s0);
@@ -69,12 +79,13 @@ __global__ void __launch_bounds__(WG) block_level_kernel(
 }
 
 void launch_block_level(const int2* front, int nfront, const double* box, const int32_t* child0,
-                        const int32_t* child1, double eta2, int2* next, int* next_cnt,
-                        int2* nearL, int* near_cnt, int2* farL, int* far_cnt, hipStream_t s) {
+                        const int32_t* child1, const int32_t* nbegin, const int32_t* nend, int rb,
+                        int re, double eta2, int2* next, int* next_cnt, int2* nearL,
+                        int* near_cnt, int2* farL, int* far_cnt, int* err, hipStream_t s) {
   if (nfront <= 0) return;
   hipLaunchKernelGGL(block_level_kernel, dim3((nfront + WG - 1) / WG), dim3(WG), 0, s, front,
-                     nfront, box, child0, child1, eta2, next, next_cnt, nearL, near_cnt, farL,
-                     far_cnt);
+                     nfront, box, child0, child1, nbegin, nend, rb, re, eta2, next, next_cnt,
+                     nearL, near_cnt, farL, far_cnt, err);
   HMX_LAUNCHED();
 }
 

@@ -43,6 +43,8 @@ class Params(C.Structure):
         ("aca_big_mn", C.c_int32),
         ("aca_gram_min_mn", C.c_int32),
         ("aca_serial", C.c_int32),
+        ("row_shares", C.c_int32),
+        ("row_share", C.c_int32),
     ]
 
 
@@ -54,7 +56,7 @@ class Info(C.Structure):
         (n, C.c_double) for n in ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms", "t_total_ms")] + [
         ("kernel_evals", C.c_int64), ("factor_bytes", C.c_int64), ("predicted_entries", C.c_int64),
         ("aca_blocks", C.c_int64 * 3), ("aca_ms", C.c_double * 3), ("aca_bytes", C.c_int64 * 3),
-        ("aca_rounds", C.c_int32)]
+        ("aca_rounds", C.c_int32), ("row_begin", C.c_int64), ("row_end", C.c_int64)]
 
     def as_dict(self):
         d = {}

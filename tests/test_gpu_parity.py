@@ -233,3 +233,49 @@ def test_fp32_mixed_against_oracle_and_fp64(H, level, k, rows):
     assert e_oracle <= 1e-3
     assert e_fp64 <= 1e-3
     assert op32.info["bytes"] < op64.info["bytes"]
+
+
+# ------------------------------------------------------------------------------ row shares
+@pytest.mark.parametrize("shares", [2, 4, 8])
+def test_row_shares_sum_to_whole_product(H, shares):
+    """The operator split by rows into `shares` parts (one per device of a row-sharded build):
+    each share's blocks are the whole operator's blocks whose row node lies in the share, and
+    the shares' products add up to the whole product bit for bit (each row comes from exactly
+    one share, computed with the same blocks in the same order)."""
+    v, f, vd, fd = mesh(4)
+    full = H.build(vd, fd, *RULE, kern=1, k=12.0)
+    x = torch.from_numpy(I.complex_vector(full.M, 8)).cuda()
+    y_full = full.matvec(x)
+    nearF, farF, rankF = full.export_blocks()
+    acc = torch.zeros_like(y_full)
+    covered = np.zeros(full.M, bool)
+    perm = full.export_tree()["perm"]
+    for r in range(shares):
+        op = H.build(vd, fd, *RULE, kern=1, k=12.0, prm=H.params(row_shares=shares, row_share=r))
+        rb, re = op.info["row_begin"], op.info["row_end"]
+        assert 0 <= rb < re <= full.M
+        covered[rb:re] = True
+        nearS, farS, rankS = op.export_blocks()
+        inN = (nearF[:, 0] >= rb) & (nearF[:, 1] <= re)
+        inF = (farF[:, 0] >= rb) & (farF[:, 1] <= re)
+        assert np.array_equal(nearS, nearF[inN]) and np.array_equal(farS, farF[inF])
+        y = op.matvec(x)
+        rows = torch.from_numpy(perm[rb:re].astype(np.int64)).cuda()
+        others = torch.ones(full.M, dtype=torch.bool, device="cuda")
+        others[rows] = False
+        assert torch.equal(y[rows], y_full[rows])
+        assert bool((y[others] == 0).all())
+        acc += y
+        op.close()
+    assert covered.all()
+    assert torch.equal(acc, y_full)
+
+
+def test_row_share_errors(H):
+    v, f, vd, fd = mesh(1)  # 240 points: a tree of depth 2 at leaf 64
+    with pytest.raises(H.HmxError) as e:
+        H.build(vd, fd, *RULE, kern=1, k=3.0, prm=H.params(row_shares=1024, row_share=0))
+    assert e.value.code == H.EUNSUPPORTED
+    with pytest.raises(H.HmxError) as e:
+        H.build(vd, fd, *RULE, kern=1, k=3.0, prm=H.params(row_shares=3))
+    assert e.value.code == H.EINVAL
