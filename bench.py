@@ -1,15 +1,24 @@
 #!/usr/bin/env python3
 """Bench of the H-matrix Helmholtz single-layer operator on one MI355X.
 
-Workload (synthetic, seeded): unit icosphere with 81 920 triangles (6 refinements), 3-point
-interior rule (245 760 points), Helmholtz k = 40, cluster leaf 64, admissibility eta = 1.5, ACA
-tolerance 1e-3, complex N(0,1) vector with seed 0.  One step = one full pass of the hot path:
-quadrature points, cluster tree, block tree, near-field blocks, ACA of the far blocks, and one
-H-matrix product, with the mesh and the vector already resident in device memory.
+Workloads (synthetic, seeded), selected with --workload:
+  sphere (default)  unit icosphere with 81 920 triangles (6 refinements), 3-point interior rule
+                    (245 760 points), Helmholtz k = 40, cluster leaf 64, admissibility
+                    eta = 1.5, ACA tolerance 1e-3, complex N(0,1) vector with seed 0;
+  batch             64 seeded ellipsoids (semi-axes U[0.5, 2], 2 000-40 000 triangles
+                    log-uniform, k U[2, 30], vector seed 1000 + i) built and applied as one
+                    block-diagonal operator;
+  large             one eighth (row share 0 of 8) of the prolate (2, 1, 1) ellipsoid with
+                    1 310 720 triangles (3 932 160 points), k = 120, leaf 128, tol 1e-4, FP32;
+                    100 products replayed in one HIP graph.
+One step = one full pass of the hot path with the mesh and the vector already resident in device
+memory: quadrature points, cluster tree, block tree, near-field blocks, ACA of the far blocks,
+and one H-matrix product.
 
 Printed JSON line: the step time, the build and product times, the relative error on seeded
-sampled rows against the CPU oracle's dense product, the roofline of the product kernels, and the
-CPU oracle's own build + product time on the host cores (the cpu_baseline).
+sampled rows against the CPU oracle's dense product, the roofline of the dominant kernel (ACA of
+the large far blocks, timed by events inside the library on its own stream), the roofline of the
+product, and the CPU oracle timed on the host cores (cpu_baseline).
 """
 from __future__ import annotations
 
@@ -78,11 +87,331 @@ def copy_calibration(mib):
                                            "bytes_written_per_launch": n * 8, "launches": 5}}))
 
 
+def timed_steps(step, steps, warmup):
+    """Run `warmup` untimed and `steps` timed steps (synchronised on both sides); returns the
+    ms per step and, per timed step, (large-block ACA launch ms, its algorithmic bytes, rounds)."""
+    import torch
+    for i in range(warmup):
+        op, _ = step()
+        torch.cuda.synchronize()
+        op.close()
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    aca = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op, _ = step()
+        aca.append((op.info["aca_ms"][0], op.info["aca_bytes"][0], op.info["aca_rounds"]))
+        op.close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / max(steps, 1)
+    log(f"timed steps done: {ms:.1f} ms/step")
+    return ms, aca
+
+
+def product_ms(op, xd, y, stream, reps):
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        ev0.record(stream)
+        op.matvec(xd, y, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    return float(np.median(times))
+
+
+def rooflines(info, aca, mv_ms, M, elem, precision):
+    stored = info["near_entries"] + info["far_entries"] + info["dense_far_entries"]
+    mv_bytes = elem * (stored + 4 * M) + 8 * M
+    mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+    aca_ms = float(np.mean([a[0] for a in aca])) if aca else info["aca_ms"][0]
+    aca_bytes = aca[-1][1] if aca else info["aca_bytes"][0]
+    aca_gbs = aca_bytes / (aca_ms * 1e-3) / 1e9 if aca_ms > 0 else 0.0
+    return {
+        "roofline": {"bound": "hbm", "kernel": ACA_BIG_KERNEL, "achieved": round(aca_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(aca_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(precision), "launch_ms": round(aca_ms, 3),
+                     "algorithmic_bytes_per_launch": aca_bytes, "blocks": info["aca_blocks"][0],
+                     "rounds": max(a[2] for a in aca) if aca else None},
+        "roofline_matvec": {"bound": "hbm", "achieved": round(mv_gbs, 1), "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(mv_gbs / HBM_PEAK_GBS, 4),
+                            "bytes_per_product": mv_bytes},
+        "aca_classes": {"blocks": info["aca_blocks"],
+                        "first_launch_ms": [round(t, 3) for t in info["aca_ms"]],
+                        "algorithmic_bytes": info["aca_bytes"]},
+    }
+
+
+def sizes(info):
+    return {k2: info[k2] for k2 in ("n_near", "n_far", "near_entries", "far_entries", "dense_far",
+                                     "max_rank", "overflow_blocks", "bytes", "factor_bytes")}
+
+
+def line(args, ms_step, prec_name, config, extra):
+    out = {
+        "metric": METRIC,
+        "value": round(ms_step, 3),
+        "unit": "ms per step (H-build from device mesh + one H-matvec)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec_name == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": config,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------------------- workloads
+def run_sphere(args, torch, oracle, hmx, I):
+    dev = torch.device("cuda:0")
+    v, f = I.icosphere(args.level)
+    bary, w = I.rule_3pt()
+    M = 3 * f.shape[0]
+    prec = hmx.FP64 if args.precision == "fp64" else hmx.FP32_MIXED
+    cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
+    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec)
+    x_h = I.complex_vector(M, 0)
+    vd, fd = torch.from_numpy(v).to(dev), torch.from_numpy(f).to(dev)
+    xd = torch.from_numpy(x_h).to(cdt).to(dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    log(f"bench sphere: M={M} k={args.k} precision={args.precision}")
+
+    def step():
+        op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=args.k, prm=prm, stream=stream)
+        return op, op.matvec(xd, stream=stream)
+
+    ms_step, aca = timed_steps(step, args.steps, args.warmup)
+    op, y = step()  # product timing and accuracy on one more operator (outside the timed region)
+    torch.cuda.synchronize()
+    info = op.info
+    mv_ms = product_ms(op, xd, y, stream, args.matvec_reps)
+    log(f"matvec {mv_ms:.3f} ms (median of {args.matvec_reps})")
+    y_h = y.cpu().numpy().astype(np.complex128)
+    P, Wq = oracle.quad_points(v, f, bary, w)
+    rows = np.sort(np.random.default_rng(123).choice(M, args.sample_rows, replace=False))
+    yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, args.k, x_h, rows)
+    rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
+    log(f"rel_err on {args.sample_rows} sampled rows: {rel_err:.3e}")
+    build_s = info["t_total_ms"] / 1e3
+    cpu = None
+    if args.cpu_baseline == "on":
+        log("cpu baseline: oracle H-build + H-matvec on the host cores")
+        c0 = time.perf_counter()
+        Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, args.k, leaf=64, eta=1.5, tol=1e-3)
+        c1 = time.perf_counter()
+        Ho.matvec(x_h)
+        c2 = time.perf_counter()
+        Ho.close()
+        cpu = {"value": round((c2 - c0) * 1e3, 1), "unit": "ms per step (H-build + one H-matvec)",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"full workload once: build {c1 - c0:.2f} s, product {c2 - c1:.2f} s"}
+        log(f"cpu baseline {cpu}")
+    extra = {
+        "h_build_s": round(build_s, 4),
+        "h_matvec_ms": round(mv_ms, 4),
+        "rel_err": rel_err,
+        "kernel_evals_per_s": info["kernel_evals"] / build_s if build_s > 0 else None,
+        "build_phases_ms": {k2: round(info[k2], 2) for k2 in
+                            ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
+        "sizes": sizes(info),
+    }
+    extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision))
+    extra["cpu_baseline"] = cpu
+    op.close()
+    config = {"workload": f"unit icosphere L{args.level} ({f.shape[0]} triangles, {M} points), "
+                          f"Helmholtz k={args.k:g}, leaf 64, eta 1.5, ACA tol 1e-3, {args.precision}"}
+    line(args, ms_step, args.precision, config, extra)
+
+
+def run_batch(args, torch, oracle, hmx, I):
+    descs = I.batch_ellipsoids(64, seed=0)
+    bary, w = I.rule_3pt()
+    prec = hmx.FP64 if args.precision == "fp64" else hmx.FP32_MIXED
+    cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
+    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec)
+    meshes, dev = [], []
+    for d in descs:
+        v, f = I.batch_mesh(d)
+        meshes.append((v, f))
+        dev.append((torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda(), d["k"]))
+    x_h = np.concatenate([I.complex_vector(3 * f.shape[0], d["seed"]) for d, (_, f) in zip(descs, meshes)])
+    M = x_h.shape[0]
+    xd = torch.from_numpy(x_h).to(cdt).cuda()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    log(f"bench batch: 64 meshes, {M} points, precision={args.precision}")
+
+    def step():
+        op = hmx.build_batch(dev, bary, w, kern=hmx.HELMHOLTZ, prm=prm, stream=stream)
+        return op, op.matvec(xd, stream=stream)
+
+    ms_step, aca = timed_steps(step, args.steps, args.warmup)
+    op, y = step()
+    torch.cuda.synchronize()
+    info = op.info
+    mv_ms = product_ms(op, xd, y, stream, args.matvec_reps)
+    off = op.mesh_offsets()
+    y_h = y.cpu().numpy().astype(np.complex128)
+    rng = np.random.default_rng(77)
+    errs, num, den = [], 0.0, 0.0
+    for i, ((v, f), d) in enumerate(zip(meshes, descs)):
+        P, Wq = oracle.quad_points(v, f, bary, w)
+        rows = np.sort(rng.choice(P.shape[0], 24, replace=False))
+        yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, d["k"], x_h[off[i]:off[i + 1]], rows)
+        diff = np.linalg.norm(y_h[off[i] + rows] - yr)
+        errs.append(float(diff / np.linalg.norm(yr)))
+        num += diff ** 2
+        den += np.linalg.norm(yr) ** 2
+    log(f"batch errors: worst mesh {max(errs):.3e}, all sampled rows {np.sqrt(num / den):.3e}")
+    cpu = None
+    if args.cpu_baseline == "on":
+        # bounded sample: the oracle H-build + product of the first 8 meshes, scaled by points
+        c0 = time.perf_counter()
+        m_sample = 0
+        for (v, f), d in list(zip(meshes, descs))[:8]:
+            P, Wq = oracle.quad_points(v, f, bary, w)
+            Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, d["k"], leaf=64, eta=1.5, tol=1e-3)
+            Ho.matvec(I.complex_vector(P.shape[0], d["seed"]))
+            Ho.close()
+            m_sample += P.shape[0]
+        c1 = time.perf_counter()
+        cpu = {"value": round((c1 - c0) * 1e3 * M / m_sample, 1),
+               "unit": "ms per step (H-build + one H-matvec), scaled by points",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"first 8 of the 64 meshes ({m_sample} of {M} points) in {c1 - c0:.2f} s, "
+                         "scaled linearly by points"}
+    build_s = info["t_total_ms"] / 1e3
+    extra = {
+        "h_build_s": round(build_s, 4),
+        "h_matvec_ms": round(mv_ms, 4),
+        "rel_err": float(np.sqrt(num / den)),
+        "rel_err_worst_mesh": max(errs),
+        "kernel_evals_per_s": info["kernel_evals"] / build_s if build_s > 0 else None,
+        "build_phases_ms": {k2: round(info[k2], 2) for k2 in
+                            ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
+        "sizes": sizes(info),
+    }
+    extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision))
+    extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
+    extra["cpu_baseline"] = cpu
+    op.close()
+    config = {"workload": f"64 seeded ellipsoids ({M} points), Helmholtz k U[2,30], leaf 64, "
+                          f"eta 1.5, ACA tol 1e-3, one block-diagonal operator, {args.precision}"}
+    line(args, ms_step, args.precision, config, extra)
+
+
+def run_large(args, torch, oracle, hmx, I):
+    from paper_1804_00995_amd import rank_model as R
+    v, f = I.icosphere(8)
+    v = I.ellipsoid(v, (2.0, 1.0, 1.0))
+    bary, w = I.rule_3pt()
+    M = 3 * f.shape[0]
+    k = 120.0
+    shares, share = 8, 0
+    prm = hmx.params(tol=1e-4, leaf_size=128, precision=hmx.FP32_MIXED, row_shares=shares,
+                     row_share=share)
+    vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    x_h = I.complex_vector(M, 0)
+    xd = torch.from_numpy(x_h).to(torch.complex64).cuda()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    log(f"bench large: M={M}, row share {share} of {shares}")
+
+    def step():
+        op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, prm=prm, stream=stream)
+        return op, op.matvec(xd, stream=stream)
+
+    ms_step, aca = timed_steps(step, args.steps, args.warmup)
+    op, _ = step()
+    torch.cuda.synchronize()
+    info = op.info
+    y = torch.zeros_like(xd)
+    g = op.graph(xd, y)
+    g.launch(1, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    g.launch(100, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / 100
+    g.close()
+    log(f"100 products in one graph: {mv_ms:.3f} ms each")
+    perm = op.export_tree()["perm"]
+    rb, re = info["row_begin"], info["row_end"]
+    rows = np.sort(np.random.default_rng(55).choice(perm[rb:re], args.sample_rows, replace=False))
+    P, Wq = oracle.quad_points(v, f, bary, w)
+    c0 = time.perf_counter()
+    yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, k, x_h, rows)
+    c1 = time.perf_counter()
+    y_h = y.cpu().numpy().astype(np.complex128)
+    rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
+    log(f"rel_err on {args.sample_rows} sampled rows of the share: {rel_err:.3e}")
+    # learned layout against plain adaptive ACA: a model trained on this build's own ranks
+    feat, ranks = R.block_data(op)
+    model = R.train(feat, ranks, epochs=30)
+    model.install()
+    info_a = info
+    op.close()
+    t0 = time.perf_counter()
+    opL = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, stream=stream,
+                    prm=hmx.params(tol=1e-4, leaf_size=128, precision=hmx.FP32_MIXED,
+                                   row_shares=shares, row_share=share, rank_model=hmx.RANK_LEARNED))
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    yL = opL.matvec(xd, stream=stream)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(yL, y))
+    learned = {"build_s": round(t_learned, 3), "factor_bytes": opL.info["factor_bytes"],
+               "bytes": opL.info["bytes"], "predicted_entries": opL.info["predicted_entries"],
+               "overflow_blocks": opL.info["overflow_blocks"], "aca_rounds": opL.info["aca_rounds"],
+               "product_equals_adaptive": same}
+    opL.close()
+    hmx.set_rank_model(None)
+    cpu = None
+    if args.cpu_baseline == "on":
+        n_rows = re - rb
+        cpu = {"value": round((c1 - c0) * 1e3 * n_rows / len(rows), 1),
+               "unit": "ms per dense product of the share's rows (oracle, no H-matrix)",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"{len(rows)} dense rows in {c1 - c0:.2f} s, scaled to the share's "
+                         f"{n_rows} rows (the oracle's H-build does not fit this size in minutes)"}
+    build_s = info_a["t_total_ms"] / 1e3
+    extra = {
+        "h_build_s": round(build_s, 4),
+        "h_matvec_ms": round(mv_ms, 4),
+        "rel_err": rel_err,
+        "kernel_evals_per_s": info_a["kernel_evals"] / build_s if build_s > 0 else None,
+        "build_phases_ms": {k2: round(info_a[k2], 2) for k2 in
+                            ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
+        "sizes": sizes(info_a),
+        "rows": [rb, re],
+        "learned_vs_adaptive": learned,
+    }
+    extra.update(rooflines(info_a, aca, mv_ms, M, 8, "fp32"))
+    extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
+    extra["cpu_baseline"] = cpu
+    config = {"workload": f"prolate (2,1,1) L8 ({f.shape[0]} triangles, {M} points), k=120, "
+                          f"leaf 128, eta 1.5, ACA tol 1e-4, fp32, row share {share} of {shares} "
+                          f"(rows {rb}-{re}), 100 products in one HIP graph"}
+    line(args, ms_step, "fp32", config, extra)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["sphere", "batch", "large"], default="sphere")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--level", type=int, default=6)
     ap.add_argument("--k", type=float, default=40.0)
@@ -105,127 +434,8 @@ def main():
     from paper_1804_00995_amd import hmx
     from paper_1804_00995_amd import inputs as I
 
-    dev = torch.device("cuda:0")
-    v, f = I.icosphere(args.level)
-    bary, w = I.rule_3pt()
-    M = 3 * f.shape[0]
-    prec = hmx.FP64 if args.precision == "fp64" else hmx.FP32_MIXED
-    cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
-    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec)
-    x_h = I.complex_vector(M, 0)
-    vd = torch.from_numpy(v).to(dev)
-    fd = torch.from_numpy(f).to(dev)
-    xd = torch.from_numpy(x_h).to(cdt).to(dev)
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    log(f"bench: M={M} k={args.k} precision={args.precision} steps={args.steps} warmup={args.warmup}")
-
-    def step():
-        op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=args.k, prm=prm, stream=stream)
-        y = op.matvec(xd, stream=stream)
-        return op, y
-
-    for i in range(args.warmup):
-        op, y = step()
-        torch.cuda.synchronize()
-        op.close()
-        log(f"warmup {i} done")
-    torch.cuda.synchronize()
-    aca = []  # per timed step: (ms, algorithmic bytes, rounds) of the large-block ACA launch
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        op, y = step()
-        aca.append((op.info["aca_ms"][0], op.info["aca_bytes"][0], op.info["aca_rounds"]))
-        op.close()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
-    log(f"timed steps done: {ms_step:.1f} ms/step")
-
-    # product timing and accuracy on one more operator (outside the timed region)
-    op, y = step()
-    torch.cuda.synchronize()
-    info = op.info
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    times = []
-    for _ in range(args.matvec_reps):
-        ev0.record(stream)
-        op.matvec(xd, y, stream=stream)
-        ev1.record(stream)
-        ev1.synchronize()
-        times.append(ev0.elapsed_time(ev1))
-    mv_ms = float(np.median(times))
-    log(f"matvec {mv_ms:.3f} ms (median of {args.matvec_reps})")
-    y_h = y.cpu().numpy().astype(np.complex128)
-    P, Wq = oracle.quad_points(v, f, bary, w)
-    rows = np.sort(np.random.default_rng(123).choice(M, args.sample_rows, replace=False))
-    yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, args.k, x_h, rows)
-    rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
-    log(f"rel_err on {args.sample_rows} sampled rows: {rel_err:.3e}")
-
-    elem = 16 if prec == hmx.FP64 else 8
-    stored = info["near_entries"] + info["far_entries"] + info["dense_far_entries"]
-    mv_bytes = elem * (stored + 4 * M) + 8 * M
-    mv_achieved = mv_bytes / (mv_ms * 1e-3) / 1e9
-    build_s = info["t_total_ms"] / 1e3
-    # dominant kernel of the step: ACA of the large far blocks (one launch per build)
-    aca_ms = float(np.mean([a[0] for a in aca])) if aca else info["aca_ms"][0]
-    aca_bytes = aca[-1][1] if aca else info["aca_bytes"][0]
-    aca_gbs = aca_bytes / (aca_ms * 1e-3) / 1e9 if aca_ms > 0 else 0.0
-    traffic = measured_traffic(args.precision)
-
-    cpu = None
-    if args.cpu_baseline == "on":
-        log("cpu baseline: oracle H-build + H-matvec on the host cores")
-        c0 = time.perf_counter()
-        Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, args.k, leaf=64, eta=1.5, tol=1e-3)
-        c1 = time.perf_counter()
-        Ho.matvec(x_h)
-        c2 = time.perf_counter()
-        Ho.close()
-        cpu = {"value": round((c2 - c0) * 1e3, 1), "unit": "ms per step (H-build + one H-matvec)",
-               "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": f"full workload once: build {c1 - c0:.2f} s, product {c2 - c1:.2f} s"}
-        log(f"cpu baseline {cpu}")
-
-    out = {
-        "metric": METRIC,
-        "value": round(ms_step, 3),
-        "unit": "ms per step (H-build from device mesh + one H-matvec)",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == hmx.FP64 else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"unit icosphere L{args.level} ({f.shape[0]} triangles, {M} points), "
-                               f"Helmholtz k={args.k:g}, leaf 64, eta 1.5, ACA tol 1e-3, "
-                               f"{args.precision}"},
-        "h_build_s": round(build_s, 4),
-        "h_matvec_ms": round(mv_ms, 4),
-        "rel_err": rel_err,
-        "kernel_evals_per_s": info["kernel_evals"] / build_s if build_s > 0 else None,
-        "build_phases_ms": {k2: round(info[k2], 2) for k2 in
-                            ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
-        "sizes": {k2: info[k2] for k2 in ("n_near", "n_far", "near_entries", "far_entries",
-                                           "dense_far", "max_rank", "overflow_blocks", "bytes")},
-        "roofline": {"bound": "hbm", "kernel": ACA_BIG_KERNEL, "achieved": round(aca_gbs, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(aca_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "launch_ms": round(aca_ms, 3),
-                     "algorithmic_bytes_per_launch": aca_bytes,
-                     "blocks": info["aca_blocks"][0], "rounds": max(a[2] for a in aca) if aca else None},
-        "roofline_matvec": {"bound": "hbm", "achieved": round(mv_achieved, 1), "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": round(mv_achieved / HBM_PEAK_GBS, 4),
-                            "bytes_per_product": mv_bytes},
-        "aca_classes": {"blocks": info["aca_blocks"], "first_launch_ms": [round(t, 3) for t in info["aca_ms"]],
-                        "algorithmic_bytes": info["aca_bytes"]},
-        "cpu_baseline": cpu,
-    }
-    op.close()
-    print(json.dumps(out), flush=True)
+    {"sphere": run_sphere, "batch": run_batch, "large": run_large}[args.workload](
+        args, torch, oracle, hmx, I)
 
 
 if __name__ == "__main__":

@@ -61,8 +61,9 @@ typedef enum {
 typedef enum {
   HMX_RANK_ADAPTIVE = 0, /* plain adaptive ACA: each block's factors grow in slots taken from a
                             device pool as its rank grows */
-  HMX_RANK_LEARNED = 1   /* storage laid out from the rank MLP's prediction, adaptive
-                            continuation for blocks the prediction under-sizes */
+  HMX_RANK_LEARNED = 1   /* the factor pool is reserved (and checked against the device
+                            memory) from the rank MLP's predictions, and blocks are scheduled by
+                            predicted work; blocks past their prediction continue adaptively */
 } hmx_rank_model;
 
 typedef struct {
@@ -85,6 +86,9 @@ typedef struct {
   int32_t aca_big_mn;      /* >= 2 (default 4096) */
   int32_t aca_gram_min_mn; /* >= 0 (default 1024) */
   int32_t aca_serial;      /* 0 or 1 (default 0) */
+  int32_t aca_scratch;     /* 1 (default): a block without a laid-out slot runs in its
+                              workgroup's scratch and then moves to an exactly sized slot;
+                              0: it starts in a pool slot of initial_rank columns and doubles */
   /* Row share (the part of the operator one of row_shares devices would hold): with
    * row_shares = 2^s > 1, the operator keeps only the rows of cluster-tree node number
    * row_share (breadth-first order) at level s, against all columns; the product then writes
@@ -93,6 +97,7 @@ typedef struct {
    * s or a block would cross the share's boundary. */
   int32_t row_shares; /* power of two >= 1 (default 1) */
   int32_t row_share;  /* 0 <= row_share < row_shares (default 0) */
+  int64_t force_pool_bytes; /* > 0: size of the first ACA slot pool (tests force further rounds) */
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
@@ -201,7 +206,7 @@ typedef struct {
   int64_t dense_far;      /* far blocks stored dense (ACA not converged at the rank cap) */
   int64_t dense_far_entries;
   int64_t max_rank, sum_rank;
-  int64_t overflow_blocks; /* blocks continued past their first rank allocation */
+  int64_t overflow_blocks; /* blocks moved to a larger slot, or continued in a later round */
   int64_t bytes;           /* device bytes held by the operator */
   int32_t precision, is_dense;
   double t_tree_ms, t_blocks_ms, t_near_ms, t_aca_ms, t_total_ms; /* build phases (events) */
@@ -271,11 +276,12 @@ hmx_status hmx_mlp_loss_grad(const float* theta, const float* X, const float* y,
 hmx_status hmx_mlp_train(float* theta, const float* X, const float* y, int64_t n, int32_t epochs,
                          int32_t batch, float lr, float* loss_hist, void* stream);
 
-/* Sets the process-wide model used by builds with rank_model = HMX_RANK_LEARNED: a far block
- * gets a first slot of r_alloc = min(rank cap, ceil(alpha * max(exp(pred) - 1, 0)) + beta)
- * columns (at least 1), laid out contiguously before ACA runs; a block that needs more continues
- * in a growth pool, with the same pivots and factors as plain adaptive ACA.  theta, norm host
- * (copied); theta NULL clears the model.  alpha > 0, beta >= 0. */
+/* Sets the process-wide model used by builds with rank_model = HMX_RANK_LEARNED.  Each far block
+ * is predicted r_alloc = min(rank cap, ceil(alpha * max(exp(pred) - 1, 0)) + beta) columns (at
+ * least 1).  The build reserves the factor pool as sum r_alloc (m + n) entries before ACA runs
+ * (HMX_ENOMEM when that exceeds 90% of the free device memory) and runs the blocks of each class
+ * in decreasing r_alloc^2 (m + n).  The pivots and factors are those of plain adaptive ACA.
+ * theta, norm host (copied); theta NULL clears the model.  alpha > 0, beta >= 0. */
 hmx_status hmx_set_rank_model(const float* theta, const float* norm, float alpha, float beta);
 
 /* Frees the operator and all of its device memory; NULL is accepted. */

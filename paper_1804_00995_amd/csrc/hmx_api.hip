@@ -58,8 +58,10 @@ void defaults(hmx_params* p) {
   p->aca_big_mn = 4096;
   p->aca_gram_min_mn = 1024;
   p->aca_serial = 0;
+  p->aca_scratch = 1;
   p->row_shares = 1;
   p->row_share = 0;
+  p->force_pool_bytes = 0;
 }
 
 hmx_params resolve(const hmx_params* in) {
@@ -86,11 +88,13 @@ hmx_params resolve(const hmx_params* in) {
   HMX_REQUIRE(p.aca_big_mn >= 2, HMX_EINVAL, "aca_big_mn must be >= 2");
   HMX_REQUIRE(p.aca_gram_min_mn >= 0, HMX_EINVAL, "aca_gram_min_mn must be >= 0");
   HMX_REQUIRE(p.aca_serial == 0 || p.aca_serial == 1, HMX_EINVAL, "aca_serial must be 0 or 1");
+  HMX_REQUIRE(p.aca_scratch == 0 || p.aca_scratch == 1, HMX_EINVAL, "aca_scratch must be 0 or 1");
   HMX_REQUIRE(p.row_shares >= 1 && p.row_shares <= (1 << 20) &&
                   (p.row_shares & (p.row_shares - 1)) == 0,
               HMX_EINVAL, "row_shares must be a power of two in [1, 2^20]");
   HMX_REQUIRE(p.row_share >= 0 && p.row_share < p.row_shares, HMX_EINVAL,
               "row_share must be in [0, row_shares)");
+  HMX_REQUIRE(p.force_pool_bytes >= 0, HMX_EINVAL, "force_pool_bytes must be >= 0");
   HMX_REQUIRE(p.row_shares == 1 || p.tol > 0, HMX_EUNSUPPORTED,
               "row shares need an H-matrix operator (tol > 0)");
   return p;

@@ -3,6 +3,8 @@
 // host sizes buffers, launches the kernels of the k_*.hip units and moves small index arrays;
 // all arithmetic of the operator runs in those kernels.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -12,6 +14,20 @@
 
 namespace hmx {
 namespace {
+
+// Round to the grid {2^e (1 + j / 8)}: up, or down.
+int64_t quantize_up(int64_t n) {
+  if (n <= 16) return std::max<int64_t>(n, 1);
+  int e = 63 - __builtin_clzll((unsigned long long)n);
+  const int64_t step = (int64_t(1) << e) / 8;
+  return (n + step - 1) / step * step;
+}
+int64_t quantize_down(int64_t n) {
+  if (n <= 16) return std::max<int64_t>(n, 1);
+  int e = 63 - __builtin_clzll((unsigned long long)n);
+  const int64_t step = (int64_t(1) << e) / 8;
+  return n / step * step;
+}
 
 int64_t next_pow2(int64_t n) {
   int64_t p = 1;
@@ -28,6 +44,25 @@ void grow(DevBuf<T>& b, size_t cap, size_t keep, hipStream_t s) {
   HMX_HIP(hipStreamSynchronize(s));
   b = std::move(nb);
 }
+
+// HMX_VERBOSE=1 prints the steps of the far-field build with wall-clock times to stderr.
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("HMX_VERBOSE");
+    return e && e[0] == '1';
+  }();
+  return v;
+}
+
+struct WallLog {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  void operator()(const char* what, double a = 0, double b = 0) const {
+    if (!verbose()) return;
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[hmx] %9.2f ms  %s %.6g %.6g\n", ms, what, a, b);
+  }
+};
 
 struct Timer {
   hipEvent_t a = nullptr, b = nullptr;
@@ -292,6 +327,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   // kernels: workgroup blocks at their start, wavefront blocks at their end, exactly sized)
   std::vector<FarDesc> desc(nf);
   std::vector<uint8_t> is_wave(nf);
+  std::vector<int64_t> est(nf);  // pool entries a block is expected to take
   int64_t flag_bytes = 0, sum_mn = 0;
   for (int64_t b = 0; b < nf; ++b) {
     FarDesc& d = desc[b];
@@ -313,13 +349,19 @@ void build_far(hmx_op* op, hipStream_t s) {
     d.foff = flag_bytes;
     flag_bytes += d.m + d.n;
     is_wave[b] = d.m <= ACA_WAVE_N && d.n <= ACA_WAVE_N;
-    // pool estimate: wavefront blocks take exactly their rank (<= 16, typically ~8); workgroup
-    // blocks their first slot plus one doubling
-    sum_mn += is_wave[b] ? 12 * mn : 2 * (int64_t)d.cap * mn;
+    // pool estimate without a rank model (generous: a short pool costs another launch round):
+    // wavefront blocks take exactly their rank (<= 16, typically ~8), workgroup blocks twice
+    // their first slot size (an exact slot from scratch, or a first slot plus one doubling)
+    est[b] = is_wave[b] ? 12 * mn : 2 * (int64_t)d.cap * mn;
+    sum_mn += est[b];
   }
-  // learned layout: every block gets a static slot of the predicted size, laid out on the host;
-  // the device pool then only serves blocks that outgrow their prediction
-  DevBuf<T> static_pool;
+  // scheduling key within a class: m + n, or with the learned model the predicted work
+  // r_alloc^2 (m + n) of ACA on the block
+  std::vector<int64_t> work(nf);
+  for (int64_t b = 0; b < nf; ++b) work[b] = (int64_t)desc[b].m + desc[b].n;
+  // learned layout: the slot pool is reserved from the predicted ranks r_alloc (checked against
+  // the device memory before ACA runs) instead of the generic estimate; blocks that outgrow
+  // their prediction take the room others leave
   if (op->p.rank_model == HMX_RANK_LEARNED && nf > 0) {
     const RankModel rm = get_rank_model();
     HMX_REQUIRE(rm.set, HMX_EINVAL, "rank_model is learned but no model was set (hmx_set_rank_model)");
@@ -332,33 +374,37 @@ void build_far(hmx_op* op, hipStream_t s) {
     to_host(hp, pred.p, nf, s);
     int64_t total = 0;
     for (int64_t b = 0; b < nf; ++b) {
-      FarDesc& d = desc[b];
+      const FarDesc& d = desc[b];
       const double rhat = std::expm1((double)hp[b]) * op->p.force_pred_scale;
       int64_t ra = (int64_t)std::ceil(rm.alpha * std::max(rhat, 0.0)) + (int64_t)std::lround(rm.beta);
       ra = std::min<int64_t>(std::max<int64_t>(ra, d.rcap > 0 ? 1 : 0), d.rcap);
-      d.cap = (int32_t)ra;
-      total += ra * ((int64_t)d.m + d.n);
+      const int64_t mn = (int64_t)d.m + d.n;
+      total += ra * mn;
+      work[b] = std::max<int64_t>(ra, 1) * std::max<int64_t>(ra, 1) * mn;
     }
-    static_pool.alloc(std::max<int64_t>(total, 1));
-    int64_t off = 0;
-    for (int64_t b = 0; b < nf; ++b) {
-      FarDesc& d = desc[b];
-      if (d.cap == 0) continue;
-      d.U = static_pool.p + off;
-      off += (int64_t)d.cap * d.m;
-      d.V = static_pool.p + off;
-      off += (int64_t)d.cap * d.n;
-    }
-    sum_mn = std::max<int64_t>(total / 4, (int64_t)(64 << 20) / (int64_t)sizeof(T));
+    size_t fb = 0, tb = 0;
+    HMX_HIP(hipMemGetInfo(&fb, &tb));
+    fb += dev_cached_bytes();
+    HMX_REQUIRE((double)total * sizeof(T) <= 0.9 * (double)fb, HMX_ENOMEM,
+                "predicted factor storage exceeds the free device memory");
+    sum_mn = std::max<int64_t>(total, (int64_t)(64 << 20) / (int64_t)sizeof(T));
     op->predicted_entries = total;
   }
   // device pool for factor slots, within the free memory
   size_t free_b = 0, total_b = 0;
   HMX_HIP(hipMemGetInfo(&free_b, &total_b));
-  int64_t gcap = std::max<int64_t>(sum_mn, (int64_t)(64 << 20) / (int64_t)sizeof(T));
-  gcap = std::min<int64_t>(gcap, (int64_t)(0.6 * (double)free_b) / (int64_t)sizeof(T));
+  free_b += dev_cached_bytes();  // blocks held by the library's cache are free for its use
+  // sizes on a grid of 1/8 octave, so that a repeated build asks the allocator's cache for the
+  // same size again instead of a slightly different one
+  const int64_t min_pool = (int64_t)(64 << 20) / (int64_t)sizeof(T);
+  int64_t gcap = std::min<int64_t>(quantize_up(std::max<int64_t>(sum_mn, min_pool)),
+                                   quantize_down((int64_t)(0.6 * (double)free_b) / (int64_t)sizeof(T)));
+  if (op->p.force_pool_bytes > 0) gcap = op->p.force_pool_bytes / (int64_t)sizeof(T);
   gcap = std::max<int64_t>(gcap, 1);
+  WallLog wl;
+  wl("far: blocks, pool entries", (double)nf, (double)gcap);
   DevBuf<T> gpool(gcap);
+  wl("pool allocated (GiB)", (double)gcap * sizeof(T) / (1 << 30));
   DevBuf<uint8_t> flags(std::max<int64_t>(flag_bytes, 1));
   DevBuf<FarDesc> d_desc(nf1);
   DevBuf<int32_t> d_order(nf1), rank(nf1), ipiv(nf1), status(nf1);
@@ -397,9 +443,15 @@ void build_far(hmx_op* op, hipStream_t s) {
   } tguard{tev};
   for (auto& e : tev) HMX_HIP(hipEventCreate(&e));
   // Gram scratch of the two workgroup classes (first launch only)
-  const int64_t gram_per_wg = 2 * (int64_t)ACA_GRAM_R * ACA_GRAM_R;
+  const int64_t gram_per_wg = 2 * (int64_t)ACA_GRAM_R * ACA_GRAM_R;  // the larger order
   DevBuf<double2> gram_big((size_t)aca_grid<T>(1) * gram_per_wg);
   DevBuf<double2> gram_mid((size_t)aca_grid<T>(0) * gram_per_wg);
+  // factor scratch of the workgroup classes
+  DevBuf<T> scr_big, scr_mid;
+  if (op->p.aca_scratch) {
+    scr_big.alloc((size_t)aca_grid<T>(1) * ACA_SCR_BIG);
+    scr_mid.alloc((size_t)aca_grid<T>(0) * ACA_SCR_MID);
+  }
   // blocks below aca_gram_min_mn take the direct cross sums (fewer barriers per step)
   const int gram_min = op->p.aca_gram_min_mn;
   std::vector<uint8_t> cls0(nf, 0);  // class of each block in the first launch
@@ -408,18 +460,23 @@ void build_far(hmx_op* op, hipStream_t s) {
   // run ACA on a list of blocks, largest first within each class: m + n >= aca_big_mn in
   // 512-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per wavefront (stream s3, fresh
   // blocks only), the others in 256-thread workgroups (stream s)
-  auto run_aca = [&](const std::vector<int32_t>& list, int fresh) {
-    // each class ordered by decreasing floor(log2(m + n)) (bucket order, linear time)
-    std::vector<int32_t> bucket[3][32];
+  // `started`: rank of each block at this launch (nullptr on the first launch, all zero);
+  // blocks that have not started yet run as fresh blocks in any round
+  auto run_aca = [&](const std::vector<int32_t>& list, int fresh,
+                     const std::vector<int32_t>* started) {
+    // each class ordered by decreasing floor(log2(work)) (bucket order, linear time)
+    std::vector<int32_t> bucket[3][64];
     for (int32_t b : list) {
       const FarDesc& d = desc[b];
       const int64_t mn = (int64_t)d.m + d.n;
-      const int cls = mn >= big_mn ? 0 : (fresh && is_wave[b]) ? 2 : 1;
+      const bool not_started = fresh || (*started)[b] == 0;
+      const int cls = mn >= big_mn ? 0 : (not_started && is_wave[b]) ? 2 : 1;
       if (fresh) cls0[b] = (uint8_t)cls;
-      bucket[cls][31 - std::min(31, 63 - __builtin_clzll((unsigned long long)mn))].push_back(b);
+      const int lw = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(work[b], 1));
+      bucket[cls][63 - lw].push_back(b);
     }
     std::vector<int32_t> big, mid, small;
-    for (int q = 0; q < 32; ++q) {
+    for (int q = 0; q < 64; ++q) {
       big.insert(big.end(), bucket[0][q].begin(), bucket[0][q].end());
       mid.insert(mid.end(), bucket[1][q].begin(), bucket[1][q].end());
       small.insert(small.end(), bucket[2][q].begin(), bucket[2][q].end());
@@ -441,7 +498,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     if (fresh) HMX_HIP(hipEventRecord(tev[0], s2));
     launch_aca<T>(d_desc.p, d_order.p, (int)big.size(), counter.p, 1, op->X.p, op->Y.p, op->Z.p,
                   op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
-                  fresh, gpool.p, gcap, gtop.p, fresh ? gram_big.p : nullptr, gram_min, s2);
+                  fresh, gpool.p, gcap, gtop.p, gram_big.p, gram_min, scr_big.p, ACA_SCR_BIG, s2);
     if (fresh) HMX_HIP(hipEventRecord(tev[1], s2));
     if (fresh) HMX_HIP(hipEventRecord(tev[4], s3));
     launch_aca_wave<T>(d_desc.p, d_order.p + big.size() + mid.size(), (int)small.size(), op->X.p,
@@ -451,7 +508,8 @@ void build_far(hmx_op* op, hipStream_t s) {
     if (fresh) HMX_HIP(hipEventRecord(tev[2], s));
     launch_aca<T>(d_desc.p, d_order.p + big.size(), (int)mid.size(), counter.p + 1, 0, op->X.p,
                   op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p,
-                  status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, fresh ? gram_mid.p : nullptr, gram_min, s);
+                  status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, gram_mid.p, gram_min, scr_mid.p,
+                  ACA_SCR_MID, s);
     if (fresh) HMX_HIP(hipEventRecord(tev[3], s));
     HMX_HIP(hipEventRecord(ev_d2, s2));
     HMX_HIP(hipEventRecord(ev_d3, s3));
@@ -462,7 +520,9 @@ void build_far(hmx_op* op, hipStream_t s) {
   {
     std::vector<int32_t> all(nf);
     std::iota(all.begin(), all.end(), 0);
-    run_aca(all, 1);
+    wl("first launch start");
+    run_aca(all, 1, nullptr);
+    wl("first launch done");
     for (int c = 0; c < 3; ++c) {
       float ms = 0.f;
       HMX_HIP(hipEventElapsedTime(&ms, tev[2 * c], tev[2 * c + 1]));
@@ -472,58 +532,58 @@ void build_far(hmx_op* op, hipStream_t s) {
   op->aca_rounds = 1;
   std::vector<int32_t> hst, hrank;
   to_host(hst, status.p, nf, s);
-  // blocks stopped with OVERFLOW (device pool exhausted, or a wavefront block past its register
-  // capacity) continue in the workgroup kernel; those without room get a slot in a new pool
+  // Blocks stopped with OVERFLOW (device pool exhausted, or a wavefront block past its register
+  // capacity) continue in further rounds, each with a new pool sized from the estimates of the
+  // blocks left (the old pools keep the finished factors).  A block resumes from its saved state
+  // and takes its slots from the new pool in the kernel; one that had not started runs as a
+  // fresh block.
   std::vector<uint8_t> continued(nf, 0);
   std::vector<int32_t> first_cap(nf);
   for (int64_t b = 0; b < nf; ++b) first_cap[b] = desc[b].cap;
-  std::vector<DevBuf<T>> extra_pools;
+  std::vector<DevBuf<T>> old_pools;
+  int64_t used_old = 0;  // entries taken from pools already retired
   for (;;) {
     std::vector<int32_t> list;
     for (int64_t b = 0; b < nf; ++b)
-      if (hst[b] == ACA_OVERFLOW) list.push_back((int32_t)b);
+      if ((hst[b] & 0xff) == ACA_OVERFLOW) list.push_back((int32_t)b);
     if (list.empty()) break;
-    for (int32_t b : list) continued[b] = 1;
     to_host(hrank, rank.p, nf, s);
-    to_host(desc, d_desc.p, nf, s);  // slots are assigned and moved on the device
-    std::vector<FarDesc> nd = desc;
-    std::vector<int32_t> moved;
-    int64_t extra = 0;
+    to_host(desc, d_desc.p, nf, s);  // current slots (moved on the device)
+    int64_t need = 0;
     for (int32_t b : list) {
-      FarDesc& d = nd[b];
-      if (d.U != nullptr && d.cap > hrank[b]) continue;
-      d.cap = (int32_t)std::min<int64_t>(
-          d.rcap, std::max<int64_t>({2 * (int64_t)d.cap, (int64_t)d.cap + 8, (int64_t)hrank[b] + 8}));
-      extra += (int64_t)d.cap * (d.m + d.n);
-      moved.push_back(b);
+      continued[b] = 1;
+      // room to finish: a doubled slot, at least twice the rank reached so far
+      const int64_t c = std::max<int64_t>({(int64_t)desc[b].cap, (int64_t)hrank[b] + 8,
+                                           (int64_t)first_cap[b]});
+      need += std::max<int64_t>(est[b], 2 * c * ((int64_t)desc[b].m + desc[b].n));
     }
-    if (!moved.empty()) {
-      extra_pools.emplace_back(extra);
-      T* base = extra_pools.back().p;
-      int64_t off = 0;
-      for (int32_t b : moved) {
-        FarDesc& d = nd[b];
-        d.U = base + off;
-        off += (int64_t)d.cap * d.m;
-        d.V = base + off;
-        off += (int64_t)d.cap * d.n;
-      }
-      DevBuf<FarDesc> d_nd(nf);
-      DevBuf<int32_t> d_moved(moved.size());
-      HMX_HIP(hipMemcpyAsync(d_nd.p, nd.data(), nf * sizeof(FarDesc), hipMemcpyHostToDevice, s));
-      HMX_HIP(hipMemcpyAsync(d_moved.p, moved.data(), moved.size() * 4, hipMemcpyHostToDevice, s));
-      launch_copy_factors<T>(d_desc.p, d_nd.p, rank.p, d_moved.p, (int)moved.size(), s);
-      HMX_HIP(hipStreamSynchronize(s));
-      desc.swap(nd);
-      d_desc = std::move(d_nd);
-    }
-    run_aca(list, 0);
+    HMX_HIP(hipMemGetInfo(&free_b, &total_b));
+    free_b += dev_cached_bytes();
+    int64_t ncap = std::min<int64_t>(quantize_up(std::max<int64_t>(need, min_pool)),
+                                     quantize_down((int64_t)(0.6 * (double)free_b) / (int64_t)sizeof(T)));
+    HMX_REQUIRE(ncap > 0, HMX_ENOMEM, "device memory exhausted during ACA");
+    used_old += std::min<int64_t>((int64_t)read1(gtop.p, s), gcap);
+    wl("round: blocks left, new pool entries", (double)list.size(), (double)ncap);
+    old_pools.push_back(std::move(gpool));
+    gpool.alloc(ncap);
+    wl("round: pool allocated");
+    gcap = ncap;
+    fill_i64((int64_t*)gtop.p, 0, 1, s);
+    const std::vector<int32_t> before = hrank;
+    run_aca(list, 0, &before);
+    wl("round: launch done");
     op->aca_rounds++;
     to_host(hst, status.p, nf, s);
+    to_host(hrank, rank.p, nf, s);
+    bool progress = false;
+    for (int32_t b : list)
+      if ((hst[b] & 0xff) != ACA_OVERFLOW || hrank[b] != before[b]) progress = true;
+    HMX_REQUIRE(progress, HMX_ENOMEM, "device memory exhausted during ACA (no block progressed)");
   }
   to_host(hrank, rank.p, nf, s);
   to_host(desc, d_desc.p, nf, s);
 
+  wl("ACA finished");
   // records of the product: factors stay in the slots ACA wrote; dense blocks are assembled
   std::vector<FarRec> rec(nf);
   int64_t trun = 0, drun = 0, grown = 0;  // grown: blocks that left their first slot
@@ -538,10 +598,11 @@ void build_far(hmx_op* op, hipStream_t s) {
     f.m = d.m;
     f.sb = d.sb;
     f.n = d.n;
-    HMX_REQUIRE(hst[b] == ACA_CONVERGED || hst[b] == ACA_DENSE, HMX_EINTERNAL,
+    const int32_t stb = hst[b] & 0xff;
+    HMX_REQUIRE(stb == ACA_CONVERGED || stb == ACA_DENSE, HMX_EINTERNAL,
                 "ACA left a block unfinished");
-    if (continued[b] || (!is_wave[b] && d.cap != first_cap[b])) grown++;
-    if (hst[b] == ACA_DENSE) {
+    if (continued[b] || (hst[b] & ACA_GREW)) grown++;
+    if (stb == ACA_DENSE) {
       f.dense = 1;
       f.r = d.n;
       f.U = nullptr;  // set below
@@ -585,8 +646,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   for (int64_t b = 0, q = 0; b < nf; ++b)
     if (rec[b].dense) rec[b].U = (const T*)op->dense_pool.p + doff[q++];
   const int64_t used = (int64_t)read1(gtop.p, s);
-  op->pool_used_bytes = std::min(used, gcap) * (int64_t)sizeof(T) + (int64_t)static_pool.bytes();
-  for (auto& p : extra_pools) op->pool_used_bytes += (int64_t)p.bytes();
+  op->pool_used_bytes = (std::min(used, gcap) + used_old) * (int64_t)sizeof(T);
   if (op->p.pool_limit_bytes > 0 &&
       op->pool_used_bytes + (int64_t)op->near_pool.bytes() + (int64_t)op->dense_pool.bytes() >
           op->p.pool_limit_bytes)
@@ -600,15 +660,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     gpool.p = nullptr;
     gpool.n = 0;
     op->far_pools.push_back(std::move(g));
-    if (static_pool.p) {
-      DevBuf<unsigned char> e;
-      e.p = (unsigned char*)static_pool.p;
-      e.n = static_pool.bytes();
-      static_pool.p = nullptr;
-      static_pool.n = 0;
-      op->far_pools.push_back(std::move(e));
-    }
-    for (auto& p : extra_pools) {
+    for (auto& p : old_pools) {
       DevBuf<unsigned char> e;
       e.p = (unsigned char*)p.p;
       e.n = p.bytes();
@@ -635,6 +687,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   }
   HMX_HIP(hipStreamSynchronize(s));
   op->far_host = std::move(rec);
+  wl("records and dense far blocks done");
 
   // per leaf: far blocks whose row node contains it
   DevBuf<int64_t> lcnt(nl);

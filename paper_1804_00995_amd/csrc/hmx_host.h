@@ -39,6 +39,7 @@ struct Error : std::runtime_error {
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 void dev_release_cache();
+size_t dev_cached_bytes();  // bytes of free blocks the cache holds on the current device
 
 // Message returned by hmx_last_error on this thread.
 void set_last_error(const std::string& m);
@@ -116,6 +117,8 @@ struct FarRec {
 
 constexpr int ACA_COEF_MAX = 1024;  // largest ACA rank (coefficients of a step held in LDS)
 enum AcaStatus : int32_t { ACA_RUNNING = 0, ACA_CONVERGED = 1, ACA_OVERFLOW = 2, ACA_DENSE = 3 };
+// added to a block's saved status word once ACA has moved it to a larger pool slot
+constexpr int32_t ACA_GREW = 0x100;
 // ACA stops once |u_k| |v_k| <= tol |S_k|_F has held at this many consecutive steps (one step
 // can meet it by accident when its pivot row lies where the block is already well approximated).
 // A block's saved state keeps the count of steps met so far in the ACA_HIT_SHIFT bits of its
@@ -184,12 +187,17 @@ void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big,
                 const double* Y, const double* Z, const double* W, int kern, const double* kp,
                 double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                 double* norm2, int fresh, T* gpool, int64_t gcap, unsigned long long* gtop,
-                double2* gram, int gram_min, hipStream_t s);
+                double2* gram, int gram_min, T* scr, int64_t scr_cap, hipStream_t s);
+// factor scratch per workgroup of the 512-thread and the 256-thread ACA kernels (entries)
+constexpr int64_t ACA_SCR_BIG = int64_t(1) << 20;
+constexpr int64_t ACA_SCR_MID = int64_t(1) << 18;
 // workgroups of the persistent grid of the 512-thread (big = 1) or 256-thread ACA kernel
 template <class T>
 int aca_grid(int big);
-// Gram-matrix order per workgroup of the ACA kernels (steps past it use direct cross sums)
-constexpr int ACA_GRAM_R = 128;
+// Gram-matrix order per workgroup of the 512- and the 256-thread ACA kernels (steps past it use
+// direct cross sums); a workgroup's Gram scratch holds 2 ACA_GRAM_R^2 entries of the larger
+constexpr int ACA_GRAM_R = 256;
+constexpr int ACA_GRAM_R_MID = 128;
 constexpr int ACA_BIG = 4096;  // block size (m + n) from which first rank slots are enlarged
 constexpr int ACA_WAVE_N = 64; // blocks with m, n <= ACA_WAVE_N run one per wavefront
 constexpr int ACA_WAVE_RC = 16; // terms a wavefront block holds in registers
@@ -199,9 +207,6 @@ void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
                      const double* kp, double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                      double* norm2, T* gpool, int64_t gcap, unsigned long long* gtop,
                      hipStream_t s);
-template <class T>
-void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* rank,
-                         const int32_t* list, int nlist, hipStream_t s);
 // k_mlp.hip -- block-rank MLP (4 -> 64 -> 64 -> 1, ReLU, FP32)
 constexpr int MLP_IN = 4, MLP_H = 64, MLP_NPARAMS = 4545;
 void launch_mlp_features(const int2* pairs, int64_t n, const int32_t* nbegin, const int32_t* nend,

@@ -16,7 +16,6 @@ namespace {
 
 struct Cache {
   std::mutex mu;
-  std::multimap<size_t, void*> free_blocks;         // size -> block, per device below
   std::unordered_map<void*, std::pair<int, size_t>> live;  // block -> (device, size)
   std::map<int, std::multimap<size_t, void*>> per_dev;
 };
@@ -86,6 +85,16 @@ void dev_free(void* p) {
   }
   c.per_dev[it->second.first].emplace(it->second.second, p);
   c.live.erase(it);
+}
+
+size_t dev_cached_bytes() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  Cache& c = cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  size_t b = 0;
+  for (const auto& kv : c.per_dev[dev]) b += kv.first;
+  return b;
 }
 
 void dev_release_cache() {

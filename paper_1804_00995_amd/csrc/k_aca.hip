@@ -73,8 +73,8 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
                           const double* __restrict__ W, int kern, const double* kp, double tol,
                           uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                           double* norm2, int fresh, T* gpool, int64_t gcap,
-                          unsigned long long* gtop, double2* gram, int gram_min, T* coef,
-                          AcaShared& sh) {
+                          unsigned long long* gtop, double2* gram, int gram_min, T* scr,
+                          int64_t scr_cap, T* coef, AcaShared& sh) {
   constexpr int GW = NT >= 512 ? 8 : 4;  // terms per window of the Gram passes
   constexpr int JC = 1;                  // elements per thread per round
   constexpr int LU = NT >= 512 ? 8 : 4;  // previous terms loaded per round (loads in flight)
@@ -102,15 +102,64 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     nrm2 = norm2[b];
   }
   // Gram matrices of the factors, GV[l][p] = v_l^H v_p and GU[l][p] = u_l^H u_p (FP64,
-  // ACA_GRAM_R x ACA_GRAM_R each, row-major, this workgroup's scratch).  With them the cross
-  // terms of step (5) come from dot products taken in the residual passes themselves:
+  // GR x GR each, row-major, this workgroup's scratch).  With them the cross terms of step (5)
+  // come from dot products taken in the residual passes themselves:
   //   v_l^H R = v_l^H R' - sum_{p in and after l's window} u_p[i_k] GV[l][p],
-  // R' the residual before l's window, so the previous columns are read once per step.  Blocks
-  // resumed from a saved state, and ranks past ACA_GRAM_R, take the direct sums instead.
+  // R' the residual before l's window, so the previous columns are read once per step.  Ranks
+  // past GR and blocks below gram_min take the direct sums instead.
+  constexpr int GR = NT >= 512 ? ACA_GRAM_R : ACA_GRAM_R_MID;  // Gram order (<= NT)
   double2* GV = gram;
-  double2* GU = gram ? gram + ACA_GRAM_R * ACA_GRAM_R : nullptr;
-  bool use_gram = fresh && gram != nullptr && m + n >= gram_min;
+  double2* GU = gram ? gram + GR * GR : nullptr;
+  bool use_gram = gram != nullptr && m + n >= gram_min && kk < GR;
+  if (use_gram && !fresh && kk > 0) {
+    // a block resumed from its saved state: rebuild the Gram matrices of its factors (one
+    // wavefront per entry pair)
+    const int lane = tid & (WAVE - 1), w = tid / WAVE;
+    const int np = kk * (kk + 1) / 2;
+    for (int q = w; q < np; q += NT / WAVE) {
+      int l = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+      while (l * (l + 1) / 2 > q) --l;
+      while ((l + 1) * (l + 2) / 2 <= q) ++l;
+      const int p = q - l * (l + 1) / 2;
+      double gv[2] = {0.0, 0.0}, gu[2] = {0.0, 0.0};
+      for (int j = lane; j < n; j += WAVE) {
+        const double2 a = to_d2(V[(int64_t)l * n + j]), c = to_d2(V[(int64_t)p * n + j]);
+        gv[0] += a.x * c.x + a.y * c.y;
+        gv[1] += a.x * c.y - a.y * c.x;
+      }
+      for (int i = lane; i < m; i += WAVE) {
+        const double2 a = to_d2(U[(int64_t)l * m + i]), c = to_d2(U[(int64_t)p * m + i]);
+        gu[0] += a.x * c.x + a.y * c.y;
+        gu[1] += a.x * c.y - a.y * c.x;
+      }
+      gv[0] = wave_sum(gv[0]);
+      gv[1] = wave_sum(gv[1]);
+      gu[0] = wave_sum(gu[0]);
+      gu[1] = wave_sum(gu[1]);
+      if (lane == 0) {
+        GV[(int64_t)l * GR + p] = make_double2(gv[0], gv[1]);
+        GV[(int64_t)p * GR + l] = make_double2(gv[0], -gv[1]);
+        GU[(int64_t)l * GR + p] = make_double2(gu[0], gu[1]);
+        GU[(int64_t)p * GR + l] = make_double2(gu[0], -gu[1]);
+      }
+    }
+    __syncthreads();
+  }
   int st = d.rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
+  // A block without a slot that has not started runs in this workgroup's scratch (as many
+  // columns as fit, up to the rank cap) and moves its factors to an exactly sized pool slot when
+  // it finishes; it leaves the scratch earlier only when it outgrows it.
+  bool in_scr = false;
+  bool grew = !fresh && (status[b] & ACA_GREW);
+  if (st == ACA_RUNNING && U == nullptr && kk == 0 && scr != nullptr) {
+    const int64_t cs = min((int64_t)d.rcap, scr_cap / (m + n));
+    if (cs >= 1) {
+      in_scr = true;
+      cap = (int)cs;
+      U = scr;
+      V = scr + cs * m;
+    }
+  }
   if (st == ACA_RUNNING && U == nullptr) {
     // first slot, taken from the device pool
     const int64_t need = (int64_t)cap * (m + n);
@@ -130,7 +179,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   }
   __syncthreads();
   while (st == ACA_RUNNING) {
-    if (kk >= ACA_GRAM_R) use_gram = false;
+    if (kk >= GR) use_gram = false;
     // (1) residual row ip, stored as column kk of V when the slot has room
     for (int l = tid; l < kk; l += NT) coef[l] = U[(int64_t)l * m + ip];
     __syncthreads();
@@ -140,10 +189,10 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     T* R = V + (int64_t)kk * n;
     double best = -1.0;
     int bj = INT_MAX;
-    // Gram part of v_l^H R for this thread's l (gstep: kk < ACA_GRAM_R <= NT, one l per thread);
+    // Gram part of v_l^H R for this thread's l (gstep: kk < GR <= NT, one l per thread);
     // it needs only the coefficients, so its loads go out before the row pass
     double2 gcorr = make_double2(0.0, 0.0);
-    if (gstep && tid < kk) gcorr = gram_row_dot(GV + (int64_t)tid * ACA_GRAM_R, coef, (tid / GW) * GW, kk);
+    if (gstep && tid < kk) gcorr = gram_row_dot(GV + (int64_t)tid * GR, coef, (tid / GW) * GW, kk);
     if (gstep) {
       // windows of GW previous terms; the partial residual lives in column kk between windows
       for (int l0 = 0; l0 < max(kk, 1); l0 += GW) {
@@ -259,6 +308,8 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       U = nU;
       V = nV;
       cap = ncap;
+      grew = grew || !in_scr;
+      in_scr = false;
       if (tid == 0) {
         descs[b].U = nU;
         descs[b].V = nV;
@@ -270,7 +321,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     const double2 pd = to_d2(R[bj]);
     const double den = pd.x * pd.x + pd.y * pd.y;
     const T inv = from_d2<T>(make_double2(pd.x / den, -pd.y / den));
-    // v_l^H v_k for this thread's l (gstep: kk < ACA_GRAM_R <= NT, one l per thread)
+    // v_l^H v_k for this thread's l (gstep: kk < GR <= NT, one l per thread)
     double2 vdot = make_double2(0.0, 0.0);
     if (gstep && tid < kk) {
       const double2 t = make_double2(sh.h[tid].x - gcorr.x, sh.h[tid].y - gcorr.y);
@@ -298,7 +349,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     int ui = INT_MAX;
     double cross = 0.0;
     if (gstep) {
-      const double2 ucorr = tid < kk ? gram_row_dot(GU + (int64_t)tid * ACA_GRAM_R, coef,
+      const double2 ucorr = tid < kk ? gram_row_dot(GU + (int64_t)tid * GR, coef,
                                                     (tid / GW) * GW, kk)
                                      : make_double2(0.0, 0.0);
       for (int l0 = 0; l0 < max(kk, 1); l0 += GW) {
@@ -343,10 +394,10 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       block_sum<1, NT>(cr, sh.ssum);
       cross = cr[0];
       if (tid < kk) {
-        GV[(int64_t)tid * ACA_GRAM_R + kk] = vdot;
-        GV[(int64_t)kk * ACA_GRAM_R + tid] = make_double2(vdot.x, -vdot.y);
-        GU[(int64_t)tid * ACA_GRAM_R + kk] = udot;
-        GU[(int64_t)kk * ACA_GRAM_R + tid] = make_double2(udot.x, -udot.y);
+        GV[(int64_t)tid * GR + kk] = vdot;
+        GV[(int64_t)kk * GR + tid] = make_double2(vdot.x, -vdot.y);
+        GU[(int64_t)tid * GR + kk] = udot;
+        GU[(int64_t)kk * GR + tid] = make_double2(udot.x, -udot.y);
       }
     } else {
     for (int i0 = tid; i0 < m; i0 += NT * JC) {
@@ -448,8 +499,8 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     double nn2[2] = {nu2, nv2};
     block_sum<2, NT>(nn2, sh.ssum);
     if (gstep && tid == 0) {
-      GV[(int64_t)kk * ACA_GRAM_R + kk] = make_double2(nn2[1], 0.0);
-      GU[(int64_t)kk * ACA_GRAM_R + kk] = make_double2(nn2[0], 0.0);
+      GV[(int64_t)kk * GR + kk] = make_double2(nn2[1], 0.0);
+      GU[(int64_t)kk * GR + kk] = make_double2(nn2[0], 0.0);
     }
     nrm2 = nrm2 + 2.0 * cross + nn2[0] * nn2[1];
     kk += 1;
@@ -469,11 +520,44 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     }
     ip = ui;
   }
+  if (in_scr) {
+    // move the factors out of the scratch into an exact slot; without room in the pool the
+    // block is reset and runs again from its start in the next round
+    const int64_t need = (int64_t)kk * (m + n);
+    bool placed = st == ACA_DENSE || need == 0;
+    if (!placed && st == ACA_CONVERGED) {
+      if (tid == 0) sh.off = (int64_t)atomicAdd(gtop, (unsigned long long)need);
+      __syncthreads();
+      const int64_t off = sh.off;
+      if (gpool != nullptr && off + need <= gcap) {
+        T* nU = gpool + off;
+        T* nV = nU + (int64_t)kk * m;
+        const int64_t cu = (int64_t)kk * m, cv = (int64_t)kk * n;
+        for (int64_t e = tid; e < cu; e += NT) nU[e] = U[e];
+        for (int64_t e = tid; e < cv; e += NT) nV[e] = V[e];
+        if (tid == 0) {
+          descs[b].U = nU;
+          descs[b].V = nV;
+          descs[b].cap = kk;
+        }
+        placed = true;
+      }
+    }
+    if (!placed) {
+      st = ACA_OVERFLOW;
+      kk = 0;
+      ip = 0;
+      hits = 0;
+      nrm2 = 0.0;
+      for (int i = tid; i < m + n; i += NT) rused[i] = 0;
+    }
+    __syncthreads();  // the scratch is free for the next block
+  }
   if (tid == 0) {
     rank[b] = kk;
     ipiv[b] = ip | (hits << ACA_HIT_SHIFT);
     norm2[b] = nrm2;
-    status[b] = st;
+    status[b] = st | (grew ? ACA_GREW : 0);
   }
   __syncthreads();
 }
@@ -489,10 +573,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
                                                  int32_t* ipiv, int32_t* status, double* norm2,
                                                  int fresh, T* gpool, int64_t gcap,
                                                  unsigned long long* gtop, double2* gram,
-                                                 int gram_min) {
+                                                 int gram_min, T* scr, int64_t scr_cap) {
   __shared__ T coef[ACA_COEF_MAX];
   __shared__ AcaShared sh;
   double2* my_gram = gram ? gram + (int64_t)blockIdx.x * 2 * ACA_GRAM_R * ACA_GRAM_R : nullptr;
+  T* my_scr = scr ? scr + (int64_t)blockIdx.x * scr_cap : nullptr;
   for (;;) {
     if (threadIdx.x == 0) sh.q = atomicAdd(counter, 1);
     __syncthreads();
@@ -500,7 +585,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
     __syncthreads();
     if (q >= nb) break;
     aca_block<T, NT>(desc, order[q], X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2,
-                     fresh, gpool, gcap, gtop, my_gram, gram_min, coef, sh);
+                     fresh, gpool, gcap, gtop, my_gram, gram_min, my_scr, scr_cap, coef, sh);
   }
 }
 
@@ -728,46 +813,20 @@ void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big,
                 const double* Y, const double* Z, const double* W, int kern, const double* kp,
                 double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                 double* norm2, int fresh, T* gpool, int64_t gcap, unsigned long long* gtop,
-                double2* gram, int gram_min, hipStream_t s) {
+                double2* gram, int gram_min, T* scr, int64_t scr_cap, hipStream_t s) {
   if (nb <= 0) return;
+  // `scr` (when given) holds scr_cap entries for each of aca_grid(big) workgroups
   // `gram` (when given) holds 2 ACA_GRAM_R^2 entries for each of aca_grid(big) workgroups;
   // blocks with m + n >= gram_min use it
   const int grid = std::min(nb, aca_grid<T>(big));
   if (big)
     hipLaunchKernelGGL((aca_kernel<T, 512>), dim3(grid), dim3(512), 0, s, d, order, nb, counter,
                        X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
-                       gcap, gtop, gram, gram_min);
+                       gcap, gtop, gram, gram_min, scr, scr_cap);
   else
     hipLaunchKernelGGL((aca_kernel<T, WG>), dim3(grid), dim3(WG), 0, s, d, order, nb, counter, X,
                        Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool, gcap,
-                       gtop, gram, gram_min);
-  HMX_LAUNCHED();
-}
-
-// Copy the first rank[b] columns of U and V of listed blocks from their old slot to a new one
-// (both column-major with the same leading dimension, so each factor is one contiguous run).
-template <class T>
-__global__ void __launch_bounds__(WG) copy_factors_kernel(const FarDesc* __restrict__ from,
-                                                          const FarDesc* __restrict__ to,
-                                                          const int32_t* __restrict__ rank,
-                                                          const int32_t* __restrict__ list) {
-  const int b = list[blockIdx.x];
-  const FarDesc a = from[b], c = to[b];
-  const int64_t r = rank[b];
-  const int64_t nu = r * a.m, nv = r * a.n;
-  const T* su = (const T*)a.U;
-  const T* sv = (const T*)a.V;
-  T* du = (T*)c.U;
-  T* dv = (T*)c.V;
-  for (int64_t e = threadIdx.x; e < nu; e += WG) du[e] = su[e];
-  for (int64_t e = threadIdx.x; e < nv; e += WG) dv[e] = sv[e];
-}
-
-template <class T>
-void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* rank,
-                         const int32_t* list, int nlist, hipStream_t s) {
-  if (nlist <= 0) return;
-  hipLaunchKernelGGL(copy_factors_kernel<T>, dim3(nlist), dim3(WG), 0, s, from, to, rank, list);
+                       gtop, gram, gram_min, scr, scr_cap);
   HMX_LAUNCHED();
 }
 
@@ -779,10 +838,9 @@ void launch_copy_factors(const FarDesc* from, const FarDesc* to, const int32_t* 
   template void launch_aca<T>(FarDesc*, const int32_t*, int, int*, int, const double*,           \
                               const double*, const double*, const double*, int, const double*,   \
                               double, uint8_t*, int32_t*, int32_t*, int32_t*, double*, int, T*,  \
-                              int64_t, unsigned long long*, double2*, int, hipStream_t);         \
+                              int64_t, unsigned long long*, double2*, int, T*, int64_t,          \
+                              hipStream_t);                                                      \
   template int aca_grid<T>(int);                                                                 \
-  template void launch_copy_factors<T>(const FarDesc*, const FarDesc*, const int32_t*,           \
-                                       const int32_t*, int, hipStream_t);                        \
 
 HMX_INST(double2)
 HMX_INST(float2)

@@ -43,8 +43,10 @@ class Params(C.Structure):
         ("aca_big_mn", C.c_int32),
         ("aca_gram_min_mn", C.c_int32),
         ("aca_serial", C.c_int32),
+        ("aca_scratch", C.c_int32),
         ("row_shares", C.c_int32),
         ("row_share", C.c_int32),
+        ("force_pool_bytes", C.c_int64),
     ]
 
 

@@ -114,9 +114,10 @@ def test_model_fits_ranks(H, trained):
 
 @pytest.mark.parametrize("scale", [1.0, 0.0])
 def test_learned_layout_identical_factors_less_memory(H, trained, scale):
-    """Learned static layout vs plain adaptive ACA: the same pivots and factors (products equal
-    bit for bit), all blocks finished, and less memory held for the factors.  scale 0 forces
-    every block past its prediction (beta-column slots) to exercise the continuation path."""
+    """Learned layout vs plain adaptive ACA: the same pivots and factors (products equal bit for
+    bit), all blocks finished, and less device memory held, since the slot pool is reserved from
+    the predicted ranks instead of the generic estimate.  scale 0 predicts rank 0 everywhere (a
+    pool of beta columns per block) to exercise the rounds that continue blocks in new pools."""
     trained.install()
     v, f = I.icosphere(5)
     vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
@@ -129,12 +130,13 @@ def test_learned_layout_identical_factors_less_memory(H, trained, scale):
     assert torch.equal(ya, yb)
     assert a.info["far_entries"] == b.info["far_entries"]
     if scale == 1.0:
-        assert b.info["factor_bytes"] < a.info["factor_bytes"]
+        assert b.info["bytes"] < a.info["bytes"]
         assert b.info["overflow_blocks"] < 0.25 * b.info["n_far"]
+        assert b.info["aca_rounds"] == 1
     else:
-        assert b.info["overflow_blocks"] > 0
-    print(f"adaptive: factor {a.info['factor_bytes'] / 2**20:.0f} MiB build {a.info['t_total_ms']:.1f} ms | "
-          f"learned(scale {scale}): factor {b.info['factor_bytes'] / 2**20:.0f} MiB "
+        assert b.info["overflow_blocks"] > 0 and b.info["aca_rounds"] > 1
+    print(f"adaptive: held {a.info['bytes'] / 2**20:.0f} MiB build {a.info['t_total_ms']:.1f} ms | "
+          f"learned(scale {scale}): held {b.info['bytes'] / 2**20:.0f} MiB "
           f"build {b.info['t_total_ms']:.1f} ms overflow {b.info['overflow_blocks']}")
     H.set_rank_model(None)
 

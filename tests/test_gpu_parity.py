@@ -194,11 +194,15 @@ def test_forced_dense_fallback(H):
 def test_overflow_continuation_identical(H):
     # a first rank slot of 1 makes nearly every block continue in a larger slot; the factors
     # must be those of a single uninterrupted run
-    opa, P, W = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=1)
-    opb, _, _ = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=64)
+    opa, P, W = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=1, aca_scratch=0)
+    opb, _, _ = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=64, aca_scratch=0)
+    opc, _, _ = build(H, 3, kern=1, k=9.0, tol=1e-3)  # workgroup scratch, exact slots
     assert opa.info["overflow_blocks"] > 0
     x = I.complex_vector(P.shape[0], 4)
-    assert np.array_equal(apply(opa, x), apply(opb, x))
+    ya = apply(opa, x)
+    assert np.array_equal(ya, apply(opb, x))
+    assert np.array_equal(ya, apply(opc, x))
+    assert opc.info["factor_bytes"] < opb.info["factor_bytes"]
 
 
 def test_full_size_sampled_rows(H):
@@ -279,3 +283,21 @@ def test_row_share_errors(H):
     with pytest.raises(H.HmxError) as e:
         H.build(vd, fd, *RULE, kern=1, k=3.0, prm=H.params(row_shares=3))
     assert e.value.code == H.EINVAL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pool_exhaustion_rounds(H, precision):
+    """A first slot pool of 1 MiB runs out almost at once: the blocks left over continue in later
+    rounds with new pools (not-started blocks as fresh ones, the others from their saved state).
+    The operator stays within the tolerance, with ranks close to a one-round build."""
+    op, P, W = build(H, 4, kern=1, k=12.0, tol=1e-3, precision=precision, force_pool_bytes=1 << 20)
+    ref, _, _ = build(H, 4, kern=1, k=12.0, tol=1e-3, precision=precision)
+    assert op.info["aca_rounds"] > 1 and ref.info["aca_rounds"] == 1
+    x = I.complex_vector(P.shape[0], 9)
+    dt = torch.complex128 if precision == 0 else torch.complex64
+    yr = oracle.dense_matvec(P, W, 1, 12.0, x)
+    assert rel(apply(op, x, dt), yr) <= 1e-3
+    _, _, r0 = ref.export_blocks()
+    _, _, r1 = op.export_blocks()
+    assert abs(int(r0.sum()) - int(r1.sum())) <= 0.01 * r0.sum()
+    assert op.info["dense_far"] == ref.info["dense_far"]
