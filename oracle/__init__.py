@@ -47,7 +47,7 @@ def lib():
         L.hmo_dense_rows.argtypes = [P, P, P, P, i64, i32, f64, P, P, i64, P, i32]
         L.hmo_aca_dense.argtypes = [P, i64, i64, f64, i64, P, P, i64, P]
         L.hmo_aca_dense.restype = C.c_int
-        L.hmo_hbuild.argtypes = [P, P, P, P, i64, i32, f64, i32, f64, f64, i32]
+        L.hmo_hbuild.argtypes = [P, P, P, P, i64, i32, f64, i32, f64, f64, i32, i64]
         L.hmo_hbuild.restype = P
         L.hmo_hmatvec.argtypes = [P, P, P]
         L.hmo_hinfo.argtypes = [P, P]
@@ -138,11 +138,12 @@ def aca_dense(A, tol, rcap=None):
 class HMatrix:
     """Oracle H-matrix: cluster tree, block tree, dense near blocks, reference ACA far blocks."""
 
-    def __init__(self, pts, w, kern, k, leaf=64, eta=1.5, tol=1e-3, nthreads=0):
+    def __init__(self, pts, w, kern, k, leaf=64, eta=1.5, tol=1e-3, nthreads=0, max_mn=0):
         X, Y, Z = _soa(pts)
         w = np.ascontiguousarray(w, np.float64)
         self.M = X.shape[0]
-        self._h = lib().hmo_hbuild(_p(X), _p(Y), _p(Z), _p(w), self.M, kern, k, leaf, eta, tol, nthreads)
+        self._h = lib().hmo_hbuild(_p(X), _p(Y), _p(Z), _p(w), self.M, kern, k, leaf, eta, tol, nthreads,
+                                   max_mn)
         info = np.zeros(9, np.int64)
         lib().hmo_hinfo(self._h, _p(info))
         keys = ["n_nodes", "n_near", "n_far", "s_near", "s_far", "n_dense_far", "s_dense_far",

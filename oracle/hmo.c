@@ -221,29 +221,35 @@ static void pairs_push(pairs_t *L, int32_t t, int32_t s)
     L->n++;
 }
 
-static void block_rec(const tree_t *T, double eta2, int32_t t, int32_t s, pairs_t *nearL, pairs_t *farL)
+/* max_mn > 0 bounds the far blocks: an admissible pair whose two clusters hold more than max_mn
+ * points together is not taken as one far block but recursed into like an inadmissible one
+ * (a pair of leaves is far whatever its size).  max_mn = 0 is the plain definition above. */
+static void block_rec(const tree_t *T, double eta2, int64_t max_mn, int32_t t, int32_t s,
+                      pairs_t *nearL, pairs_t *farL)
 {
     const double *bt = T->box + 6 * (int64_t)t, *bs = T->box + 6 * (int64_t)s;
     double dt = diam2(bt), ds = diam2(bs);
     double dmin = dt < ds ? dt : ds;
-    if (dmin <= eta2 * dist2(bt, bs)) {
+    int lt = T->child0[t] < 0, ls = T->child0[s] < 0;
+    int64_t mn = (T->end[t] - T->begin[t]) + (T->end[s] - T->begin[s]);
+    int small = max_mn <= 0 || mn <= max_mn || (lt && ls);
+    if (small && dmin <= eta2 * dist2(bt, bs)) {
         pairs_push(farL, t, s);
         return;
     }
-    int lt = T->child0[t] < 0, ls = T->child0[s] < 0;
     if (lt && ls) {
         pairs_push(nearL, t, s);
     } else if (lt) {
-        block_rec(T, eta2, t, T->child0[s], nearL, farL);
-        block_rec(T, eta2, t, T->child1[s], nearL, farL);
+        block_rec(T, eta2, max_mn, t, T->child0[s], nearL, farL);
+        block_rec(T, eta2, max_mn, t, T->child1[s], nearL, farL);
     } else if (ls) {
-        block_rec(T, eta2, T->child0[t], s, nearL, farL);
-        block_rec(T, eta2, T->child1[t], s, nearL, farL);
+        block_rec(T, eta2, max_mn, T->child0[t], s, nearL, farL);
+        block_rec(T, eta2, max_mn, T->child1[t], s, nearL, farL);
     } else {
-        block_rec(T, eta2, T->child0[t], T->child0[s], nearL, farL);
-        block_rec(T, eta2, T->child0[t], T->child1[s], nearL, farL);
-        block_rec(T, eta2, T->child1[t], T->child0[s], nearL, farL);
-        block_rec(T, eta2, T->child1[t], T->child1[s], nearL, farL);
+        block_rec(T, eta2, max_mn, T->child0[t], T->child0[s], nearL, farL);
+        block_rec(T, eta2, max_mn, T->child0[t], T->child1[s], nearL, farL);
+        block_rec(T, eta2, max_mn, T->child1[t], T->child0[s], nearL, farL);
+        block_rec(T, eta2, max_mn, T->child1[t], T->child1[s], nearL, farL);
     }
 }
 
@@ -492,7 +498,8 @@ static cplx *dense_block(const hmo_h *H, int64_t tb, int64_t m, int64_t sb, int6
 }
 
 void *hmo_hbuild(const double *X, const double *Y, const double *Z, const double *W, int64_t M,
-                 int32_t kern, double k, int32_t leaf, double eta, double tol, int32_t nthreads)
+                 int32_t kern, double k, int32_t leaf, double eta, double tol, int32_t nthreads,
+                 int64_t max_mn)
 {
     set_threads(nthreads);
     hmo_h *H = calloc(1, sizeof(hmo_h));
@@ -527,7 +534,7 @@ void *hmo_hbuild(const double *X, const double *Y, const double *Z, const double
     T->level = malloc(sizeof(int32_t) * (size_t)T->cap);
     T->box = malloc(sizeof(double) * 6 * (size_t)T->cap);
     tree_node(T, 0, M, 0);
-    block_rec(T, eta * eta, 0, 0, &H->nearL, &H->farL);
+    block_rec(T, eta * eta, max_mn, 0, 0, &H->nearL, &H->farL);
     sort_pairs(T, &H->nearL);
     sort_pairs(T, &H->farL);
     int64_t nn = H->nearL.n, nf = H->farL.n;

@@ -213,10 +213,10 @@ def test_dense_matches_brute_force_tiny():
 
 
 # -------------------------------------------------------------------- tree and blocks (O3, O4)
-def _tree_blocks(level, leaf, eta=1.5, k=5.0):
+def _tree_blocks(level, leaf, eta=1.5, k=5.0, max_mn=0):
     v, f = I.icosphere(level)
     P, W = oracle.quad_points(v, f, *I.rule_3pt())
-    H = oracle.HMatrix(P, W, oracle.HELMHOLTZ, k, leaf=leaf, eta=eta, tol=1e-3)
+    H = oracle.HMatrix(P, W, oracle.HELMHOLTZ, k, leaf=leaf, eta=eta, tol=1e-3, max_mn=max_mn)
     return P, W, H
 
 
@@ -438,3 +438,43 @@ def test_hmatvec_elongated_ellipsoid_within_tolerance():
     rows = np.sort(np.random.default_rng(1045).choice(P.shape[0], 512, replace=False))
     yr = oracle.dense_rows(P, W, oracle.HELMHOLTZ, d["k"], x, rows)
     assert np.linalg.norm(y[rows] - yr) <= 1e-3 * np.linalg.norm(yr)
+
+
+@pytest.mark.parametrize("max_mn", [256, 96, 32])
+def test_block_partition_with_size_bound(max_mn):
+    """Far blocks bounded to max_mn points: still an exact partition (brute-force bitmap), every
+    far block admissible and within the bound unless it pairs two leaves, near blocks leaf pairs,
+    and the product within the tolerance of the dense one."""
+    P, W, H = _tree_blocks(3, 16, max_mn=max_mn)
+    M = P.shape[0]
+    nearR, farR, ranks = H.blocks()
+    cover = np.zeros((M, M), np.int8)
+    for R in (nearR, farR):
+        for tb, te, sb, se in R:
+            cover[tb:te, sb:se] += 1
+    assert (cover == 1).all()
+    T = H.tree()
+    perm = T["perm"]
+    leaves = {(b, e) for b, e, c in zip(T["begin"], T["end"], T["child0"]) if c < 0}
+    for tb, te, sb, se in nearR:
+        assert (tb, te) in leaves and (sb, se) in leaves
+    for tb, te, sb, se in farR:
+        both_leaves = (tb, te) in leaves and (sb, se) in leaves
+        assert (te - tb) + (se - sb) <= max_mn or both_leaves
+        p1, p2 = P[perm[tb:te]], P[perm[sb:se]]
+        d1 = (np.ptp(p1, 0) ** 2).sum()
+        d2 = (np.ptp(p2, 0) ** 2).sum()
+        gap = np.maximum(0, np.maximum(p2.min(0) - p1.max(0), p1.min(0) - p2.max(0)))
+        assert min(d1, d2) <= 1.5 ** 2 * (gap ** 2).sum()
+    _, farPlain, _ = _tree_blocks(3, 16)[2].blocks()
+    assert farR.shape[0] > farPlain.shape[0]  # the bound splits some far blocks
+    x = I.complex_vector(M, 3)
+    y = oracle.dense_matvec(P, W, oracle.HELMHOLTZ, 5.0, x)
+    assert np.linalg.norm(H.matvec(x) - y) <= 1e-3 * np.linalg.norm(y)
+
+
+def test_block_size_bound_above_problem_is_plain():
+    P, W, H = _tree_blocks(3, 16, max_mn=10 ** 6)
+    _, _, H0 = _tree_blocks(3, 16)
+    for a, b in zip(H.blocks()[:2], H0.blocks()[:2]):
+        assert np.array_equal(a, b)
