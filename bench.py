@@ -318,8 +318,9 @@ def run_large(args, torch, oracle, hmx, I):
     M = 3 * f.shape[0]
     k = 120.0
     shares, share = 8, 0
+    # far blocks bounded to 32 768 points (the fastest bound of a sweep at this size)
     prm = hmx.params(tol=1e-4, leaf_size=128, precision=hmx.FP32_MIXED, row_shares=shares,
-                     row_share=share)
+                     row_share=share, max_far_mn=32768)
     vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
     x_h = I.complex_vector(M, 0)
     xd = torch.from_numpy(x_h).to(torch.complex64).cuda()
@@ -365,7 +366,8 @@ def run_large(args, torch, oracle, hmx, I):
     t0 = time.perf_counter()
     opL = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, stream=stream,
                     prm=hmx.params(tol=1e-4, leaf_size=128, precision=hmx.FP32_MIXED,
-                                   row_shares=shares, row_share=share, rank_model=hmx.RANK_LEARNED))
+                                   row_shares=shares, row_share=share, max_far_mn=32768,
+                                   rank_model=hmx.RANK_LEARNED))
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     yL = opL.matvec(xd, stream=stream)
@@ -401,7 +403,7 @@ def run_large(args, torch, oracle, hmx, I):
     extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
     extra["cpu_baseline"] = cpu
     config = {"workload": f"prolate (2,1,1) L8 ({f.shape[0]} triangles, {M} points), k=120, "
-                          f"leaf 128, eta 1.5, ACA tol 1e-4, fp32, row share {share} of {shares} "
+                          f"leaf 128, eta 1.5, far blocks <= 32768 points, ACA tol 1e-4, fp32, row share {share} of {shares} "
                           f"(rows {rb}-{re}), 100 products in one HIP graph"}
     line(args, ms_step, "fp32", config, extra)
 

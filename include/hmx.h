@@ -98,11 +98,15 @@ typedef struct {
   int32_t row_shares; /* power of two >= 1 (default 1) */
   int32_t row_share;  /* 0 <= row_share < row_shares (default 0) */
   int64_t force_pool_bytes; /* > 0: size of the first ACA slot pool (tests force further rounds) */
+  int32_t max_far_mn; /* > 0 (default 16384): an admissible pair with more than max_far_mn
+                         points (m + n) is split into its children's pairs instead of becoming
+                         one far block (smaller ranks, less ACA work and better balance per
+                         block); 0: no limit (the plain admissibility recursion) */
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
  * initial_rank 16, force_pred_scale 1, no rank cap, no pool limit, ACA schedule 4096 / 1024 /
- * concurrent. */
+ * concurrent / scratch, one row share, far blocks up to 16384 points. */
 hmx_status hmx_params_default(hmx_params* p);
 
 typedef struct hmx_op hmx_op; /* opaque, library-owned; free with hmx_destroy */
@@ -185,15 +189,16 @@ hmx_status hmx_graph_create(const hmx_op* op, const void* x, void* y, hmx_graph*
 hmx_status hmx_graph_launch(hmx_graph* g, int32_t reps, void* stream);
 void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
 
-/* Autotuner of the ACA schedule (aca_big_mn, aca_gram_min_mn, aca_serial of hmx_params).
- * Times hmx_build_points(xyzw, M, kern, k) under a grid of settings: class thresholds
- * {2048, 4096, 8192, none} x Gram thresholds {0, 1024, 4096, none} on concurrent streams, then
- * serial classes at the best pair; best of two builds each.  *out receives *p (defaults when
+/* Autotuner of the build schedule (max_far_mn, aca_big_mn, aca_gram_min_mn, aca_serial of
+ * hmx_params).  Times hmx_build_points(xyzw, M, kern, k) under a grid of settings: far-block
+ * bounds {none, 32768, 16384, 8192}; then at the best one class thresholds {2048, 4096, 8192,
+ * none} x Gram thresholds {0, 1024, 4096, none} on concurrent streams; then serial classes at the
+ * best pair; best of two builds each.  *out receives *p (defaults when
  * NULL) with the fastest settings, *best_ms (may be NULL) that build time in ms.
  * cache_path (host string, may be NULL): a JSON file of earlier choices keyed by device
  * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size and eta; a key
  * found there is returned without timing, a new one is added to the file.  Synchronous; builds
- * and frees up to 19 operators.  Errors: as hmx_build_points, HMX_EINVAL for tol <= 0 or an
+ * and frees up to 23 operators.  Errors: as hmx_build_points, HMX_EINVAL for tol <= 0 or an
  * unwritable cache file. */
 hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
                         const hmx_params* p, const char* cache_path, void* stream,

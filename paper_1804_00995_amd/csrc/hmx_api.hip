@@ -62,6 +62,7 @@ void defaults(hmx_params* p) {
   p->row_shares = 1;
   p->row_share = 0;
   p->force_pool_bytes = 0;
+  p->max_far_mn = 16384;
 }
 
 hmx_params resolve(const hmx_params* in) {
@@ -95,6 +96,7 @@ hmx_params resolve(const hmx_params* in) {
   HMX_REQUIRE(p.row_share >= 0 && p.row_share < p.row_shares, HMX_EINVAL,
               "row_share must be in [0, row_shares)");
   HMX_REQUIRE(p.force_pool_bytes >= 0, HMX_EINVAL, "force_pool_bytes must be >= 0");
+  HMX_REQUIRE(p.max_far_mn >= 0, HMX_EINVAL, "max_far_mn must be >= 0");
   HMX_REQUIRE(p.row_shares == 1 || p.tol > 0, HMX_EUNSUPPORTED,
               "row shares need an H-matrix operator (tol > 0)");
   return p;

@@ -256,7 +256,8 @@ void build_blocks(hmx_op* op, hipStream_t s) {
     if (farL.n < (size_t)(n_far + nfront)) grow(farL, 2 * (n_far + nfront), n_far, s);
     fill_i32(cnt.p, 0, 1, s);
     launch_block_level(front.p, (int)nfront, op->box.p, op->child0.p, op->child1.p,
-                       op->nbegin.p, op->nend.p, rb, re, eta2, next.p, cnt.p, nearL.p, cnt.p + 1,
+                       op->nbegin.p, op->nend.p, rb, re, eta2, op->p.max_far_mn, next.p, cnt.p,
+                       nearL.p, cnt.p + 1,
                        farL.p, cnt.p + 2, cnt.p + 3, s);
     int c[4];
     HMX_HIP(hipMemcpyAsync(c, cnt.p, sizeof(c), hipMemcpyDeviceToHost, s));

@@ -158,8 +158,9 @@ void launch_leaf_index(int n_leaves, const int32_t* leaves, int32_t* leaf_of_nod
 // k_blocks.hip
 void launch_block_level(const int2* front, int nfront, const double* box, const int32_t* child0,
                         const int32_t* child1, const int32_t* nbegin, const int32_t* nend, int rb,
-                        int re, double eta2, int2* next, int* next_cnt, int2* nearL,
-                        int* near_cnt, int2* farL, int* far_cnt, int* err, hipStream_t s);
+                        int re, double eta2, int max_mn, int2* next, int* next_cnt,
+                        int2* nearL, int* near_cnt, int2* farL, int* far_cnt, int* err,
+                        hipStream_t s);
 void launch_pair_keys(const int2* pairs, int64_t n, int64_t npad, const int32_t* nbegin,
                       const int32_t* level, uint64_t* key, int32_t* val, hipStream_t s);
 void launch_pair_gather(const int2* in, const int32_t* idx, int64_t n, int2* out, hipStream_t s);

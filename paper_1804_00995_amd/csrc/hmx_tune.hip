@@ -1,4 +1,4 @@
-// hmx_tune.hip -- autotuner of the ACA schedule (hmx_autotune).  A client of the library's own
+// hmx_tune.hip -- autotuner of the build schedule (hmx_autotune).  A client of the library's own
 // entry points: it builds the caller's operator under a grid of schedule settings, times each
 // build, and keeps the fastest.  Results are cached in a small JSON file keyed by device
 // architecture and problem class, so a later call for the same class returns at once.
@@ -20,7 +20,7 @@
 namespace {
 
 struct Choice {
-  int big = 4096, gram = 1024, serial = 0;
+  int big = 4096, gram = 1024, serial = 0, maxmn = 16384;
   double ms = 0.0;
 };
 
@@ -43,7 +43,7 @@ std::string class_key(int64_t M, int32_t kern, const hmx_params& p) {
 }
 
 // The cache file is one JSON object of entries
-//   "key": {"aca_big_mn": N, "aca_gram_min_mn": N, "aca_serial": N, "ms": X}
+//   "key": {"max_far_mn": N, "aca_big_mn": N, "aca_gram_min_mn": N, "aca_serial": N, "ms": X}
 // written by this file; the reader accepts exactly that shape.
 double field(const std::string& body, const char* name, double dflt) {
   const std::string pat = std::string("\"") + name + "\":";
@@ -74,6 +74,7 @@ std::map<std::string, Choice> read_cache(const char* path) {
     c.big = (int)field(body, "aca_big_mn", 4096);
     c.gram = (int)field(body, "aca_gram_min_mn", 1024);
     c.serial = (int)field(body, "aca_serial", 0);
+    c.maxmn = (int)field(body, "max_far_mn", 16384);
     c.ms = field(body, "ms", 0.0);
     out[key] = c;
     pos = b1 + 1;
@@ -92,8 +93,9 @@ void write_cache(const char* path, const std::map<std::string, Choice>& m) {
     for (const auto& kv : m) {
       char buf[256];
       std::snprintf(buf, sizeof(buf),
-                    "{\"aca_big_mn\": %d, \"aca_gram_min_mn\": %d, \"aca_serial\": %d, \"ms\": %.3f}",
-                    kv.second.big, kv.second.gram, kv.second.serial, kv.second.ms);
+                    "{\"max_far_mn\": %d, \"aca_big_mn\": %d, \"aca_gram_min_mn\": %d, "
+                    "\"aca_serial\": %d, \"ms\": %.3f}",
+                    kv.second.maxmn, kv.second.big, kv.second.gram, kv.second.serial, kv.second.ms);
       f << "  \"" << kv.first << "\": " << buf << (++i < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -143,25 +145,33 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
     if (hit != cache.end()) {
       best = hit->second;
     } else {
-      // the class thresholds first (concurrent classes), then serial vs concurrent at the best
+      // the far-block size bound first (default schedule), then the class thresholds
+      // (concurrent classes), then serial vs concurrent at the best
+      const int maxmns[] = {0, 32768, 16384, 8192};
       const int bigs[] = {2048, 4096, 8192, 1 << 30};
       const int grams[] = {0, 1024, 4096, 1 << 30};
       hmx_params q = base;
       q.aca_serial = 0;
       (void)time_build(xyzw, M, kern, k, q, stream, 1);  // warm the allocator and the code
       best.ms = 1e300;
+      for (int mx : maxmns) {
+        q.max_far_mn = mx;
+        const double ms = time_build(xyzw, M, kern, k, q, stream, 2);
+        if (ms < best.ms) best = Choice{q.aca_big_mn, q.aca_gram_min_mn, 0, mx, ms};
+      }
+      q.max_far_mn = best.maxmn;
       for (int b : bigs)
         for (int g : grams) {
           q.aca_big_mn = b;
           q.aca_gram_min_mn = g;
           const double ms = time_build(xyzw, M, kern, k, q, stream, 2);
-          if (ms < best.ms) best = Choice{b, g, 0, ms};
+          if (ms < best.ms) best = Choice{b, g, 0, best.maxmn, ms};
         }
       q.aca_big_mn = best.big;
       q.aca_gram_min_mn = best.gram;
       q.aca_serial = 1;
       const double ms = time_build(xyzw, M, kern, k, q, stream, 2);
-      if (ms < best.ms) best = Choice{best.big, best.gram, 1, ms};
+      if (ms < best.ms) best = Choice{best.big, best.gram, 1, best.maxmn, ms};
       cache[key] = best;
       write_cache(cache_path, cache);
     }
@@ -169,6 +179,7 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
     out->aca_big_mn = best.big;
     out->aca_gram_min_mn = best.gram;
     out->aca_serial = best.serial;
+    out->max_far_mn = best.maxmn;
     if (best_ms) *best_ms = best.ms;
     return HMX_OK;
   } catch (const hmx::Error& e) {

@@ -37,8 +37,8 @@ __global__ void __launch_bounds__(WG) block_level_kernel(
     const int2* __restrict__ front, int nfront, const double* __restrict__ box,
     const int32_t* __restrict__ child0, const int32_t* __restrict__ child1,
     const int32_t* __restrict__ nbegin, const int32_t* __restrict__ nend, int rb, int re,
-    double eta2, int2* __restrict__ next, int* next_cnt, int2* __restrict__ nearL, int* near_cnt,
-    int2* __restrict__ farL, int* far_cnt, int* err) {
+    double eta2, int max_mn, int2* __restrict__ next, int* next_cnt, int2* __restrict__ nearL,
+    int* near_cnt, int2* __restrict__ farL, int* far_cnt, int* err) {
   int i = blockIdx.x * WG + threadIdx.x;
   if (i >= nfront) return;
   int2 ts = front[i];
@@ -50,13 +50,17 @@ __global__ void __launch_bounds__(WG) block_level_kernel(
   const double* bs = box + 6 * (int64_t)s;
   double dt = diam2(bt), ds = diam2(bs);
   double dmin = dt < ds ? dt : ds;
-  if (dmin <= eta2 * dist2(bt, bs)) {
+  int t0 = child0[t], s0 = child0[s];
+  bool lt = t0 < 0, ls = s0 < 0;
+  // an admissible pair is far unless it exceeds max_mn points (then its children are taken,
+  // down to leaf pairs, which are far whatever their size)
+  const bool small = max_mn <= 0 || (te - tb) + (nend[s] - nbegin[s]) <= max_mn || (lt && ls);
+  if (small && dmin <= eta2 * dist2(bt, bs)) {
     if (inside) farL[atomicAdd(far_cnt, 1)] = ts;
     else atomicOr(err, 1);
     return;
   }
-  int t0 = child0[t], s0 = child0[s];
-  bool lt = t0 < 0, ls = s0 < 0;
+  if (!small && lt && ls) return;  // unreachable: leaf pairs are small
   if (lt && ls) {
     if (inside) nearL[atomicAdd(near_cnt, 1)] = ts;
     else atomicOr(err, 1);
@@ -80,12 +84,13 @@ __global__ void __launch_bounds__(WG) block_level_kernel(
 
 void launch_block_level(const int2* front, int nfront, const double* box, const int32_t* child0,
                         const int32_t* child1, const int32_t* nbegin, const int32_t* nend, int rb,
-                        int re, double eta2, int2* next, int* next_cnt, int2* nearL,
-                        int* near_cnt, int2* farL, int* far_cnt, int* err, hipStream_t s) {
+                        int re, double eta2, int max_mn, int2* next, int* next_cnt,
+                        int2* nearL, int* near_cnt, int2* farL, int* far_cnt, int* err,
+                        hipStream_t s) {
   if (nfront <= 0) return;
   hipLaunchKernelGGL(block_level_kernel, dim3((nfront + WG - 1) / WG), dim3(WG), 0, s, front,
-                     nfront, box, child0, child1, nbegin, nend, rb, re, eta2, next, next_cnt,
-                     nearL, near_cnt, farL, far_cnt, err);
+                     nfront, box, child0, child1, nbegin, nend, rb, re, eta2, max_mn, next,
+                     next_cnt, nearL, near_cnt, farL, far_cnt, err);
   HMX_LAUNCHED();
 }
 

@@ -47,6 +47,7 @@ class Params(C.Structure):
         ("row_shares", C.c_int32),
         ("row_share", C.c_int32),
         ("force_pool_bytes", C.c_int64),
+        ("max_far_mn", C.c_int32),
     ]
 
 

@@ -93,10 +93,12 @@ def test_dense_fp32_mixed(H):
 
 
 # ------------------------------------------------------------------------------ tree, blocks
-@pytest.mark.parametrize("level,leaf", [(2, 7), (3, 16), (3, 64), (4, 64), (4, 128)])
-def test_tree_and_blocks_identical(H, level, leaf):
-    op, P, W = build(H, level, leaf_size=leaf, tol=1e-3)
-    Ho = oracle.HMatrix(P, W, 1, 5.0, leaf=leaf, tol=1e-3)
+@pytest.mark.parametrize("level,leaf,max_mn", [(2, 7, 0), (3, 16, 0), (3, 64, 0), (4, 64, 0),
+                                              (4, 128, 0), (3, 16, 96), (4, 64, 4096),
+                                              (5, 64, 16384)])
+def test_tree_and_blocks_identical(H, level, leaf, max_mn):
+    op, P, W = build(H, level, leaf_size=leaf, tol=1e-3, max_far_mn=max_mn)
+    Ho = oracle.HMatrix(P, W, 1, 5.0, leaf=leaf, tol=1e-3, max_mn=max_mn)
     T, To = op.export_tree(), Ho.tree()
     assert np.array_equal(T["perm"], To["perm"])
     g = {(b, e): (lv, tuple(bx)) for b, e, lv, bx in zip(T["begin"], T["end"], T["level"], T["box"])}
