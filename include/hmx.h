@@ -86,6 +86,8 @@ typedef struct {
   int32_t aca_big_mn;      /* >= 2 (default 4096) */
   int32_t aca_gram_min_mn; /* >= 0 (default 1024) */
   int32_t aca_serial;      /* 0 or 1 (default 0) */
+  int32_t aca_mid_threads; /* workgroup size of the blocks between the wavefront and the
+                              512-thread classes: 256, 128 (default) or 64 */
   int32_t aca_scratch;     /* 1 (default): a block without a laid-out slot runs in its
                               workgroup's scratch and then moves to an exactly sized slot;
                               0: it starts in a pool slot of initial_rank columns and doubles */
@@ -189,16 +191,17 @@ hmx_status hmx_graph_create(const hmx_op* op, const void* x, void* y, hmx_graph*
 hmx_status hmx_graph_launch(hmx_graph* g, int32_t reps, void* stream);
 void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
 
-/* Autotuner of the build schedule (max_far_mn, aca_big_mn, aca_gram_min_mn, aca_serial of
- * hmx_params).  Times hmx_build_points(xyzw, M, kern, k) under a grid of settings: far-block
- * bounds {none, 32768, 16384, 8192}; then at the best one class thresholds {2048, 4096, 8192,
- * none} x Gram thresholds {0, 1024, 4096, none} on concurrent streams; then serial classes at the
- * best pair; best of two builds each.  *out receives *p (defaults when
+/* Autotuner of the build schedule (max_far_mn, aca_big_mn, aca_gram_min_mn, aca_mid_threads,
+ * aca_serial of hmx_params).  Times hmx_build_points(xyzw, M, kern, k) under a grid of
+ * settings, each stage at the best of the previous ones: far-block bounds {none, 32768, 16384,
+ * 8192}; class thresholds {2048, 4096, 8192, none} x Gram thresholds {0, 1024, 4096, none} on
+ * concurrent streams; middle-class workgroups {256, 128, 64}; serial classes; best of two
+ * builds each.  *out receives *p (defaults when
  * NULL) with the fastest settings, *best_ms (may be NULL) that build time in ms.
  * cache_path (host string, may be NULL): a JSON file of earlier choices keyed by device
  * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size and eta; a key
  * found there is returned without timing, a new one is added to the file.  Synchronous; builds
- * and frees up to 23 operators.  Errors: as hmx_build_points, HMX_EINVAL for tol <= 0 or an
+ * and frees up to 26 operators.  Errors: as hmx_build_points, HMX_EINVAL for tol <= 0 or an
  * unwritable cache file. */
 hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
                         const hmx_params* p, const char* cache_path, void* stream,

@@ -58,6 +58,7 @@ void defaults(hmx_params* p) {
   p->aca_big_mn = 4096;
   p->aca_gram_min_mn = 1024;
   p->aca_serial = 0;
+  p->aca_mid_threads = 128;
   p->aca_scratch = 1;
   p->row_shares = 1;
   p->row_share = 0;
@@ -90,6 +91,8 @@ hmx_params resolve(const hmx_params* in) {
   HMX_REQUIRE(p.aca_gram_min_mn >= 0, HMX_EINVAL, "aca_gram_min_mn must be >= 0");
   HMX_REQUIRE(p.aca_serial == 0 || p.aca_serial == 1, HMX_EINVAL, "aca_serial must be 0 or 1");
   HMX_REQUIRE(p.aca_scratch == 0 || p.aca_scratch == 1, HMX_EINVAL, "aca_scratch must be 0 or 1");
+  HMX_REQUIRE(p.aca_mid_threads == 256 || p.aca_mid_threads == 128 || p.aca_mid_threads == 64,
+              HMX_EINVAL, "aca_mid_threads must be 256, 128 or 64");
   HMX_REQUIRE(p.row_shares >= 1 && p.row_shares <= (1 << 20) &&
                   (p.row_shares & (p.row_shares - 1)) == 0,
               HMX_EINVAL, "row_shares must be a power of two in [1, 2^20]");

@@ -308,6 +308,7 @@ void build_near(hmx_op* op, hipStream_t s) {
 // ------------------------------------------------------------------------------ far field
 template <class T>
 void build_far(hmx_op* op, hipStream_t s) {
+  WallLog wl;
   const int64_t nf = op->n_far;
   const int nl = op->n_leaves;
   const int64_t nf1 = std::max<int64_t>(nf, 1);
@@ -402,8 +403,7 @@ void build_far(hmx_op* op, hipStream_t s) {
                                    quantize_down((int64_t)(0.6 * (double)free_b) / (int64_t)sizeof(T)));
   if (op->p.force_pool_bytes > 0) gcap = op->p.force_pool_bytes / (int64_t)sizeof(T);
   gcap = std::max<int64_t>(gcap, 1);
-  WallLog wl;
-  wl("far: blocks, pool entries", (double)nf, (double)gcap);
+  wl("descriptors built: blocks, pool entries", (double)nf, (double)gcap);
   DevBuf<T> gpool(gcap);
   wl("pool allocated (GiB)", (double)gcap * sizeof(T) / (1 << 30));
   DevBuf<uint8_t> flags(std::max<int64_t>(flag_bytes, 1));
@@ -415,6 +415,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   if (nf) HMX_HIP(hipMemcpyAsync(d_desc.p, desc.data(), nf * sizeof(FarDesc), hipMemcpyHostToDevice, s));
   fill_i64((int64_t*)gtop.p, 0, 1, s);
 
+  wl("device state ready");
   // side streams for the block classes (default priority), joined back to `s`
   hipStream_t s2_ = nullptr, s3_ = nullptr;
   hipEvent_t ev_ready = nullptr, ev_d2 = nullptr, ev_d3 = nullptr;
@@ -445,13 +446,14 @@ void build_far(hmx_op* op, hipStream_t s) {
   for (auto& e : tev) HMX_HIP(hipEventCreate(&e));
   // Gram scratch of the two workgroup classes (first launch only)
   const int64_t gram_per_wg = 2 * (int64_t)ACA_GRAM_R * ACA_GRAM_R;  // the larger order
-  DevBuf<double2> gram_big((size_t)aca_grid<T>(1) * gram_per_wg);
-  DevBuf<double2> gram_mid((size_t)aca_grid<T>(0) * gram_per_wg);
+  const int mid_threads = op->p.aca_mid_threads;
+  DevBuf<double2> gram_big((size_t)aca_grid<T>(512) * gram_per_wg);
+  DevBuf<double2> gram_mid((size_t)aca_grid<T>(mid_threads) * gram_per_wg);
   // factor scratch of the workgroup classes
   DevBuf<T> scr_big, scr_mid;
   if (op->p.aca_scratch) {
-    scr_big.alloc((size_t)aca_grid<T>(1) * ACA_SCR_BIG);
-    scr_mid.alloc((size_t)aca_grid<T>(0) * ACA_SCR_MID);
+    scr_big.alloc((size_t)aca_grid<T>(512) * ACA_SCR_BIG);
+    scr_mid.alloc((size_t)aca_grid<T>(mid_threads) * ACA_SCR_MID);
   }
   // blocks below aca_gram_min_mn take the direct cross sums (fewer barriers per step)
   const int gram_min = op->p.aca_gram_min_mn;
@@ -497,7 +499,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipStreamWaitEvent(s2, ev_ready, 0));
     HMX_HIP(hipStreamWaitEvent(s3, ev_ready, 0));
     if (fresh) HMX_HIP(hipEventRecord(tev[0], s2));
-    launch_aca<T>(d_desc.p, d_order.p, (int)big.size(), counter.p, 1, op->X.p, op->Y.p, op->Z.p,
+    launch_aca<T>(d_desc.p, d_order.p, (int)big.size(), counter.p, 512, op->X.p, op->Y.p, op->Z.p,
                   op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
                   fresh, gpool.p, gcap, gtop.p, gram_big.p, gram_min, scr_big.p, ACA_SCR_BIG, s2);
     if (fresh) HMX_HIP(hipEventRecord(tev[1], s2));
@@ -507,7 +509,8 @@ void build_far(hmx_op* op, hipStream_t s) {
                        ipiv.p, status.p, norm2.p, gpool.p, gcap, gtop.p, s3);
     if (fresh) HMX_HIP(hipEventRecord(tev[5], s3));
     if (fresh) HMX_HIP(hipEventRecord(tev[2], s));
-    launch_aca<T>(d_desc.p, d_order.p + big.size(), (int)mid.size(), counter.p + 1, 0, op->X.p,
+    launch_aca<T>(d_desc.p, d_order.p + big.size(), (int)mid.size(), counter.p + 1, mid_threads,
+                  op->X.p,
                   op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p,
                   status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, gram_mid.p, gram_min, scr_mid.p,
                   ACA_SCR_MID, s);
@@ -690,6 +693,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   op->far_host = std::move(rec);
   wl("records and dense far blocks done");
 
+  wl("far records on device");
   // per leaf: far blocks whose row node contains it
   DevBuf<int64_t> lcnt(nl);
   op->far_ptr.alloc(nl + 1);
@@ -700,6 +704,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   launch_leaf_far_fill(nl, op->leaves.p, op->parent.p, node_cnt.p, node_first.p, op->far_ptr.p,
                        op->far_list.p, s);
   HMX_HIP(hipStreamSynchronize(s));
+  wl("per-leaf far lists done");
 }
 
 template <class T>

@@ -184,17 +184,18 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
                      hipStream_t s);
 // k_aca.hip
 template <class T>
-void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
-                const double* Y, const double* Z, const double* W, int kern, const double* kp,
-                double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
-                double* norm2, int fresh, T* gpool, int64_t gcap, unsigned long long* gtop,
-                double2* gram, int gram_min, T* scr, int64_t scr_cap, hipStream_t s);
-// factor scratch per workgroup of the 512-thread and the 256-thread ACA kernels (entries)
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads,
+                const double* X, const double* Y, const double* Z, const double* W, int kern,
+                const double* kp, double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv,
+                int32_t* status, double* norm2, int fresh, T* gpool, int64_t gcap,
+                unsigned long long* gtop, double2* gram, int gram_min, T* scr, int64_t scr_cap,
+                hipStream_t s);
+// factor scratch per workgroup of the 512-thread and the smaller ACA kernels (entries)
 constexpr int64_t ACA_SCR_BIG = int64_t(1) << 20;
 constexpr int64_t ACA_SCR_MID = int64_t(1) << 18;
-// workgroups of the persistent grid of the 512-thread (big = 1) or 256-thread ACA kernel
+// workgroups of the persistent grid of the ACA kernel with `threads` (512, 256 or 128) threads
 template <class T>
-int aca_grid(int big);
+int aca_grid(int threads);
 // Gram-matrix order per workgroup of the 512- and the 256-thread ACA kernels (steps past it use
 // direct cross sums); a workgroup's Gram scratch holds 2 ACA_GRAM_R^2 entries of the larger
 constexpr int ACA_GRAM_R = 256;

@@ -20,7 +20,7 @@
 namespace {
 
 struct Choice {
-  int big = 4096, gram = 1024, serial = 0, maxmn = 16384;
+  int big = 4096, gram = 1024, serial = 0, maxmn = 16384, mid = 128;
   double ms = 0.0;
 };
 
@@ -43,7 +43,8 @@ std::string class_key(int64_t M, int32_t kern, const hmx_params& p) {
 }
 
 // The cache file is one JSON object of entries
-//   "key": {"max_far_mn": N, "aca_big_mn": N, "aca_gram_min_mn": N, "aca_serial": N, "ms": X}
+//   "key": {"max_far_mn": N, "aca_big_mn": N, "aca_gram_min_mn": N, "aca_mid_threads": N,
+//           "aca_serial": N, "ms": X}
 // written by this file; the reader accepts exactly that shape.
 double field(const std::string& body, const char* name, double dflt) {
   const std::string pat = std::string("\"") + name + "\":";
@@ -75,6 +76,7 @@ std::map<std::string, Choice> read_cache(const char* path) {
     c.gram = (int)field(body, "aca_gram_min_mn", 1024);
     c.serial = (int)field(body, "aca_serial", 0);
     c.maxmn = (int)field(body, "max_far_mn", 16384);
+    c.mid = (int)field(body, "aca_mid_threads", 128);
     c.ms = field(body, "ms", 0.0);
     out[key] = c;
     pos = b1 + 1;
@@ -94,8 +96,9 @@ void write_cache(const char* path, const std::map<std::string, Choice>& m) {
       char buf[256];
       std::snprintf(buf, sizeof(buf),
                     "{\"max_far_mn\": %d, \"aca_big_mn\": %d, \"aca_gram_min_mn\": %d, "
-                    "\"aca_serial\": %d, \"ms\": %.3f}",
-                    kv.second.maxmn, kv.second.big, kv.second.gram, kv.second.serial, kv.second.ms);
+                    "\"aca_mid_threads\": %d, \"aca_serial\": %d, \"ms\": %.3f}",
+                    kv.second.maxmn, kv.second.big, kv.second.gram, kv.second.mid, kv.second.serial,
+                    kv.second.ms);
       f << "  \"" << kv.first << "\": " << buf << (++i < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -150,28 +153,37 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
       const int maxmns[] = {0, 32768, 16384, 8192};
       const int bigs[] = {2048, 4096, 8192, 1 << 30};
       const int grams[] = {0, 1024, 4096, 1 << 30};
+      const int mids[] = {256, 128, 64};
       hmx_params q = base;
       q.aca_serial = 0;
       (void)time_build(xyzw, M, kern, k, q, stream, 1);  // warm the allocator and the code
-      best.ms = 1e300;
+      best = Choice{q.aca_big_mn, q.aca_gram_min_mn, 0, q.max_far_mn, q.aca_mid_threads, 1e300};
+      auto trial = [&](const hmx_params& t) {
+        const double ms = time_build(xyzw, M, kern, k, t, stream, 2);
+        if (ms < best.ms)
+          best = Choice{t.aca_big_mn, t.aca_gram_min_mn, t.aca_serial, t.max_far_mn,
+                        t.aca_mid_threads, ms};
+      };
       for (int mx : maxmns) {
         q.max_far_mn = mx;
-        const double ms = time_build(xyzw, M, kern, k, q, stream, 2);
-        if (ms < best.ms) best = Choice{q.aca_big_mn, q.aca_gram_min_mn, 0, mx, ms};
+        trial(q);
       }
       q.max_far_mn = best.maxmn;
       for (int b : bigs)
         for (int g : grams) {
           q.aca_big_mn = b;
           q.aca_gram_min_mn = g;
-          const double ms = time_build(xyzw, M, kern, k, q, stream, 2);
-          if (ms < best.ms) best = Choice{b, g, 0, best.maxmn, ms};
+          trial(q);
         }
       q.aca_big_mn = best.big;
       q.aca_gram_min_mn = best.gram;
+      for (int mt : mids) {
+        q.aca_mid_threads = mt;
+        trial(q);
+      }
+      q.aca_mid_threads = best.mid;
       q.aca_serial = 1;
-      const double ms = time_build(xyzw, M, kern, k, q, stream, 2);
-      if (ms < best.ms) best = Choice{best.big, best.gram, 1, best.maxmn, ms};
+      trial(q);
       cache[key] = best;
       write_cache(cache_path, cache);
     }
@@ -180,6 +192,7 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
     out->aca_gram_min_mn = best.gram;
     out->aca_serial = best.serial;
     out->max_far_mn = best.maxmn;
+    out->aca_mid_threads = best.mid;
     if (best_ms) *best_ms = best.ms;
     return HMX_OK;
   } catch (const hmx::Error& e) {

@@ -107,7 +107,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   //   v_l^H R = v_l^H R' - sum_{p in and after l's window} u_p[i_k] GV[l][p],
   // R' the residual before l's window, so the previous columns are read once per step.  Ranks
   // past GR and blocks below gram_min take the direct sums instead.
-  constexpr int GR = NT >= 512 ? ACA_GRAM_R : ACA_GRAM_R_MID;  // Gram order (<= NT)
+  constexpr int GR = NT >= 512 ? ACA_GRAM_R : NT >= 128 ? ACA_GRAM_R_MID : NT;  // Gram order <= NT
   double2* GV = gram;
   double2* GU = gram ? gram + GR * GR : nullptr;
   bool use_gram = gram != nullptr && m + n >= gram_min && kk < GR;
@@ -795,38 +795,51 @@ void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
   HMX_LAUNCHED();
 }
 
-// Workgroups of a persistent ACA grid: as many as can be resident at once.
+// Workgroups of a persistent ACA grid (512-, 256- or 128-thread workgroups): as many as can be
+// resident at once.
 template <class T>
-int aca_grid(int big) {
+int aca_grid(int threads) {
   int dev = 0, ncu = 0, occ = 0;
   HMX_HIP(hipGetDevice(&dev));
   HMX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  if (big)
+  if (threads == 512)
     HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 512>, 512, 0));
+  else if (threads == 256)
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 256>, 256, 0));
+  else if (threads == 128)
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 128>, 128, 0));
   else
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, WG>, WG, 0));
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 64>, 64, 0));
   return std::max(1, occ) * ncu;
 }
 
 template <class T>
-void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int big, const double* X,
-                const double* Y, const double* Z, const double* W, int kern, const double* kp,
-                double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
-                double* norm2, int fresh, T* gpool, int64_t gcap, unsigned long long* gtop,
-                double2* gram, int gram_min, T* scr, int64_t scr_cap, hipStream_t s) {
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads,
+                const double* X, const double* Y, const double* Z, const double* W, int kern,
+                const double* kp, double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv,
+                int32_t* status, double* norm2, int fresh, T* gpool, int64_t gcap,
+                unsigned long long* gtop, double2* gram, int gram_min, T* scr, int64_t scr_cap,
+                hipStream_t s) {
   if (nb <= 0) return;
-  // `scr` (when given) holds scr_cap entries for each of aca_grid(big) workgroups
-  // `gram` (when given) holds 2 ACA_GRAM_R^2 entries for each of aca_grid(big) workgroups;
-  // blocks with m + n >= gram_min use it
-  const int grid = std::min(nb, aca_grid<T>(big));
-  if (big)
+  // `gram` (when given) holds 2 ACA_GRAM_R^2 entries and `scr` scr_cap entries for each of
+  // aca_grid(threads) workgroups; blocks with m + n >= gram_min use the Gram matrices
+  const int grid = std::min(nb, aca_grid<T>(threads));
+  if (threads == 512)
     hipLaunchKernelGGL((aca_kernel<T, 512>), dim3(grid), dim3(512), 0, s, d, order, nb, counter,
                        X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
                        gcap, gtop, gram, gram_min, scr, scr_cap);
+  else if (threads == 256)
+    hipLaunchKernelGGL((aca_kernel<T, 256>), dim3(grid), dim3(256), 0, s, d, order, nb, counter,
+                       X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
+                       gcap, gtop, gram, gram_min, scr, scr_cap);
+  else if (threads == 128)
+    hipLaunchKernelGGL((aca_kernel<T, 128>), dim3(grid), dim3(128), 0, s, d, order, nb, counter,
+                       X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
+                       gcap, gtop, gram, gram_min, scr, scr_cap);
   else
-    hipLaunchKernelGGL((aca_kernel<T, WG>), dim3(grid), dim3(WG), 0, s, d, order, nb, counter, X,
-                       Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool, gcap,
-                       gtop, gram, gram_min, scr, scr_cap);
+    hipLaunchKernelGGL((aca_kernel<T, 64>), dim3(grid), dim3(64), 0, s, d, order, nb, counter,
+                       X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
+                       gcap, gtop, gram, gram_min, scr, scr_cap);
   HMX_LAUNCHED();
 }
 

@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("aca_big_mn", C.c_int32),
         ("aca_gram_min_mn", C.c_int32),
         ("aca_serial", C.c_int32),
+        ("aca_mid_threads", C.c_int32),
         ("aca_scratch", C.c_int32),
         ("row_shares", C.c_int32),
         ("row_share", C.c_int32),

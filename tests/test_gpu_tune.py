@@ -34,12 +34,14 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("big,gram,serial", [(2, 0, 0), (2, 1 << 30, 1), (1 << 30, 0, 0),
-                                             (4096, 1024, 1), (1 << 30, 1 << 30, 0)])
-def test_schedules_within_tolerance(H, sphere4, big, gram, serial):
+@pytest.mark.parametrize("big,gram,serial,mid", [(2, 0, 0, 256), (2, 1 << 30, 1, 128),
+                                                 (1 << 30, 0, 0, 64), (4096, 1024, 1, 64),
+                                                 (1 << 30, 1 << 30, 0, 256)])
+def test_schedules_within_tolerance(H, sphere4, big, gram, serial, mid):
     P, W, xyzw, x, yr = sphere4
     op = H.build_points(xyzw, kern=1, k=14.0,
-                        prm=H.params(aca_big_mn=big, aca_gram_min_mn=gram, aca_serial=serial))
+                        prm=H.params(aca_big_mn=big, aca_gram_min_mn=gram, aca_serial=serial,
+                                     aca_mid_threads=mid))
     y = op.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
     assert rel(y, yr) <= 1e-3
     ref = H.build_points(xyzw, kern=1, k=14.0)
@@ -59,6 +61,7 @@ def test_autotune_choice_and_cache(H, sphere4, tmp_path):
     assert prm.aca_gram_min_mn in (0, 1024, 4096, 1 << 30)
     assert prm.aca_serial in (0, 1) and ms > 0
     assert prm.max_far_mn in (0, 32768, 16384, 8192)
+    assert prm.aca_mid_threads in (256, 128, 64)
     entries = json.loads(cache.read_text())
     assert len(entries) == 1
     (key, val), = entries.items()
