@@ -252,6 +252,16 @@ hmx_status hmx_export_blocks(const hmx_op* op, int64_t* near_rc, int64_t* far_rc
  * and V is untouched.  *rank receives r (or -1 for dense). */
 hmx_status hmx_export_far(const hmx_op* op, int64_t b, void* U, void* V, int32_t* rank);
 
+/* Test support (apply-only checks against another implementation's factors): replaces the
+ * factors of the operator's low-rank far blocks.  ranks host, n_far entries in the order of
+ * hmx_export_blocks: the new rank r_b of each low-rank block (0 <= r_b <= min(m, n)), and -1 for
+ * each block stored dense (which keeps its entries).  U, V host, complex of the operator's
+ * precision: for each low-rank block in turn, U_b (m x r_b) concatenated into U and V_b
+ * (n x r_b) into V, column-major, with the block ~ U_b V_b^T.  The operator copies them into a
+ * new factor pool (the old factors stay allocated until hmx_destroy).  Synchronous; not to be
+ * called while a product on the operator is in flight or captured in a graph. */
+hmx_status hmx_import_far(hmx_op* op, const int32_t* ranks, const void* U, const void* V);
+
 /* ------------------------------------------------------------------ learned block ranks
  * The paper shows the local rank of each block of its H-matrix (Section 5.4, the spy plot of
  * the compressed acoustic operator) but does not predict it.  libhmx can lay out the factor

@@ -508,6 +508,64 @@ hmx_status hmx_export_far(const hmx_op* op, int64_t b, void* U, void* V, int32_t
   API_CATCH
 }
 
+hmx_status hmx_import_far(hmx_op* op, const int32_t* ranks, const void* U, const void* V) {
+  API_TRY
+  HMX_REQUIRE(op && ranks, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(!op->dense, HMX_EINVAL, "dense operators have no far blocks");
+  const int64_t nf = op->n_far;
+  std::vector<FarRec> rec = op->far_host;
+  int64_t total = 0, trun = 0;
+  for (int64_t b = 0; b < nf; ++b) {
+    const FarRec& f = rec[b];
+    if (f.dense) {
+      HMX_REQUIRE(ranks[b] == -1, HMX_EINVAL, "a far block stored dense must be given rank -1");
+      continue;
+    }
+    HMX_REQUIRE(ranks[b] >= 0 && ranks[b] <= std::min(f.m, f.n), HMX_EINVAL,
+                "rank out of range for a low-rank far block");
+    total += (int64_t)ranks[b] * (f.m + f.n);
+  }
+  HMX_REQUIRE(total == 0 || (U && V), HMX_EINVAL, "null factors");
+  // factors in one new pool: U_b then V_b for every low-rank block in turn
+  DevBuf<unsigned char> pool(std::max<int64_t>(total, 1) * op->elem);
+  int64_t ou = 0, ov = 0, off = 0;
+  const unsigned char* hu = (const unsigned char*)U;
+  const unsigned char* hv = (const unsigned char*)V;
+  op->far_entries = op->sum_rank = op->max_rank = 0;
+  for (int64_t b = 0; b < nf; ++b) {
+    FarRec& f = rec[b];
+    f.toff = trun;
+    if (f.dense) {
+      trun += f.n;
+      continue;
+    }
+    const int64_t r = ranks[b];
+    unsigned char* du = pool.p + off * op->elem;
+    unsigned char* dv = du + r * f.m * op->elem;
+    if (r) {
+      HMX_HIP(hipMemcpy(du, hu + ou * op->elem, r * f.m * op->elem, hipMemcpyHostToDevice));
+      HMX_HIP(hipMemcpy(dv, hv + ov * op->elem, r * f.n * op->elem, hipMemcpyHostToDevice));
+    }
+    ou += r * f.m;
+    ov += r * f.n;
+    off += r * (f.m + f.n);
+    f.r = (int32_t)r;
+    f.U = du;
+    f.V = dv;
+    trun += r;
+    op->far_entries += r * (f.m + f.n);
+    op->sum_rank += r;
+    op->max_rank = std::max<int64_t>(op->max_rank, r);
+  }
+  HMX_HIP(hipMemcpy(op->far.p, rec.data(), nf * sizeof(FarRec), hipMemcpyHostToDevice));
+  op->far_host = std::move(rec);
+  op->far_pools.push_back(std::move(pool));
+  op->t_len = trun;
+  op->tbuf.alloc(std::max<size_t>((size_t)trun * op->elem, op->elem));
+  return HMX_OK;
+  API_CATCH
+}
+
 void hmx_destroy(hmx_op* op) {
   if (!op) return;
   (void)hipDeviceSynchronize();

@@ -90,6 +90,7 @@ _sig = {
     "hmx_mesh_offsets": [_P, _P, _i32, C.POINTER(_i32)],
     "hmx_graph_create": [_P, _P, _P, C.POINTER(_P)],
     "hmx_graph_launch": [_P, _i32, _P],
+    "hmx_import_far": [_P, _P, _P, _P],
     "hmx_autotune": [_P, _i64, _i32, _f64, C.POINTER(Params), C.c_char_p, _P, C.POINTER(Params),
                      C.POINTER(_f64)],
 }
@@ -262,6 +263,18 @@ class Operator:
             return U[:m * n].reshape(n, m).T.copy(), None
         k = r.value
         return U[:m * k].reshape(k, m).T.copy(), V[:n * k].reshape(k, n).T.copy()
+
+    def import_far(self, ranks, Us, Vs):
+        """Replace the low-rank far factors (test support): ranks (n_far,) with -1 for blocks
+        stored dense; Us, Vs lists of (m x r) and (n x r) arrays for the low-rank blocks in order."""
+        cdt = np.complex128 if self.precision == FP64 else np.complex64
+        ranks = np.ascontiguousarray(ranks, np.int32)
+        U = np.concatenate([np.asarray(u, cdt).T.ravel() for u in Us]) if Us else np.zeros(1, cdt)
+        V = np.concatenate([np.asarray(v, cdt).T.ravel() for v in Vs]) if Vs else np.zeros(1, cdt)
+        U, V = np.ascontiguousarray(U), np.ascontiguousarray(V)
+        _check(_lib.hmx_import_far(self._h, ranks.ctypes.data_as(_P), U.ctypes.data_as(_P),
+                                   V.ctypes.data_as(_P)))
+        self.info = self._info()
 
     def far_features(self):
         """Raw features (n_far x 4 float32) of the far blocks, in export_blocks order."""

@@ -123,3 +123,9 @@ def test_autotune_argument_errors_without_gpu():
     assert lib.hmx_build_points(fake, 10, 1, 1.0, C.byref(bad), None, C.byref(h)) == hmx.EINVAL
     bad = hmx.params(aca_big_mn=1)
     assert lib.hmx_build_points(fake, 10, 1, 1.0, C.byref(bad), None, C.byref(h)) == hmx.EINVAL
+
+
+def test_import_far_argument_errors_without_gpu():
+    from paper_1804_00995_amd import hmx
+    lib = hmx._lib
+    assert lib.hmx_import_far(None, None, None, None) == hmx.EINVAL

@@ -303,3 +303,57 @@ def test_pool_exhaustion_rounds(H, precision):
     _, _, r1 = op.export_blocks()
     assert abs(int(r0.sum()) - int(r1.sum())) <= 0.01 * r0.sum()
     assert op.info["dense_far"] == ref.info["dense_far"]
+
+
+# ------------------------------------------------------------------------------ apply only
+@pytest.mark.parametrize("level,k", [(3, 5.0), (4, 12.0)])
+def test_apply_only_with_oracle_factors(H, level, k):
+    """The GPU product with the oracle's own far factors imported (same tree and blocks; near
+    blocks assembled on the GPU) equals the oracle's H-matrix product to 1e-13: this checks
+    gather, the block products, the per-leaf sums and the scatter apart from ACA."""
+    op, P, W = build(H, level, kern=1, k=k, tol=1e-3)
+    Ho = oracle.HMatrix(P, W, 1, k, leaf=64, tol=1e-3)
+    nearG, farG, rG = op.export_blocks()
+    nearO, farO, rO = Ho.blocks()
+    assert np.array_equal(nearG, nearO) and np.array_equal(farG, farO)
+    assert (rO >= 0).all() and (rG >= 0).all()  # no block stored dense at this tolerance
+    Us, Vs = [], []
+    for b, (tb, te, sb, se) in enumerate(farO):
+        U, V = Ho.far_factors(b, int(te - tb), int(se - sb), int(rO[b]))
+        Us.append(U)
+        Vs.append(V)
+    op.import_far(rO, Us, Vs)
+    assert op.info["far_entries"] == Ho.info["s_far"]
+    x = I.complex_vector(P.shape[0], 12)
+    y = apply(op, x)
+    yo = Ho.matvec(x)
+    assert rel(y, yo) <= 1e-13
+    # and once more through a captured graph
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros_like(xd)
+    g = op.graph(xd, yd)
+    g.launch(2)
+    torch.cuda.synchronize()
+    assert np.array_equal(yd.cpu().numpy(), y)
+
+
+# ------------------------------------------------------------------------------ kernel values
+@pytest.mark.parametrize("precision,bound", [(0, 1e-14), (1, 2e-6)])
+def test_kernel_values_match_golden(H, precision, bound):
+    """Two points at distance r with unit weights: the dense operator's entry K_01 = G(r) against
+    the closed form written by tests/golden/make_golden.py (FP32 mode reduces k r in FP64)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "green_kernel_values.txt")
+    rows = [l.split() for l in open(path) if not l.startswith("#") and l.strip()]
+    dt = torch.complex128 if precision == 0 else torch.complex64
+    x = torch.tensor([0.0, 1.0], dtype=dt).cuda()
+    for r, k, gre, gim in rows:
+        r, k = float(r), float(k)
+        g = complex(float(gre), float(gim))
+        xyzw = torch.tensor([[0.0, r], [0.0, 0.0], [0.0, 0.0], [1.0, 1.0]], dtype=torch.float64).cuda()
+        op = H.build_points(xyzw, kern=H.LAPLACE if k == 0 else H.HELMHOLTZ, k=k,
+                            prm=H.params(tol=0.0, precision=precision))
+        y = op.matvec(x).cpu().numpy()
+        assert abs(complex(y[0]) - g) <= bound * abs(g), (r, k, y[0], g)
+        assert y[1] == 0  # K_11 = 0 (r = 0) and K_10 x_0 = 0
+        op.close()

@@ -12,6 +12,7 @@ Every oracle function is checked against something other than itself:
   * H-matrix product: distance to the dense product at the ACA tolerance.
 """
 import math
+import os
 
 import mpmath
 import numpy as np
@@ -128,6 +129,31 @@ def test_green_closed_values():
     r = math.sqrt(4 + 0.25 + 1)
     e2 = mpmath.exp(1j * 5 * mpmath.mpf(r)) / (4 * mpmath.pi * r)
     assert abs(g[2] - complex(e2)) < 1e-16
+
+
+def _golden(name):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            a, b, re_, im_ = line.split()
+            rows.append((float(a), float(b), complex(float(re_), float(im_))))
+    return rows
+
+
+def test_green_matches_golden():
+    """The oracle's kernel (libm) against the closed form written by tests/golden/make_golden.py."""
+    for r, k, g in _golden("green_kernel_values.txt"):
+        kern = oracle.LAPLACE if k == 0 else oracle.HELMHOLTZ
+        v = oracle.green(kern, k, np.zeros((1, 3)), np.array([[r, 0.0, 0.0]]))[0]
+        assert abs(v - g) <= 1e-14 * abs(g), (r, k, v, g)
+
+
+def test_sphere_eig_matches_golden():
+    for k, l, lam in _golden("sphere_single_layer_eigenvalues.txt"):
+        assert abs(sphere_eig(int(l), k) - lam) <= 1e-12 * abs(lam), (k, l)
 
 
 def test_green_symmetry_and_laplace_limit():
