@@ -129,6 +129,12 @@ void build_tree(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipStreamSynchronize(s));
   }
   int first = 0, count = nroot, total = nroot, cur = 0, depth = 0;
+  // scratch of the multi-workgroup level step (levels of at most max_chunked_nodes nodes)
+  const int max_chunked_nodes = 1024;
+  const int64_t chunk_cap = M / TREE_CHUNK_PTS + max_chunked_nodes + 1;
+  DevBuf<int32_t> choff(max_chunked_nodes + 1), saxis(max_chunked_nodes), ccnt(chunk_cap),
+      cleft(chunk_cap);
+  DevBuf<double> pbox(6 * chunk_cap), smid(max_chunked_nodes);
   while (count > 0) {
     size_t need = (size_t)total + 2 * (size_t)count;
     if (need > cap) {
@@ -144,9 +150,18 @@ void build_tree(hmx_op* op, hipStream_t s) {
       cap = nc;
     }
     const int nx = 1 - cur;
-    launch_tree_level(first, count, nbegin.p, nend.p, leaf, bx[cur][0].p, bx[cur][1].p,
-                      bx[cur][2].p, bx[cur][3].p, bp[cur].p, bx[nx][0].p, bx[nx][1].p,
-                      bx[nx][2].p, bx[nx][3].p, bp[nx].p, box.p, nleft.p, s);
+    if (count <= max_chunked_nodes && M >= (int64_t)count * 4 * TREE_CHUNK_PTS) {
+      // few large nodes: every node spread over many workgroups
+      const int max_chunks = (int)(M / TREE_CHUNK_PTS) + count + 1;
+      launch_tree_level_chunked(first, count, max_chunks, nbegin.p, nend.p, leaf, bx[cur][0].p,
+                                bx[cur][1].p, bx[cur][2].p, bx[cur][3].p, bp[cur].p, bx[nx][0].p,
+                                bx[nx][1].p, bx[nx][2].p, bx[nx][3].p, bp[nx].p, box.p, nleft.p,
+                                choff.p, pbox.p, saxis.p, smid.p, ccnt.p, cleft.p, s);
+    } else {
+      launch_tree_level(first, count, nbegin.p, nend.p, leaf, bx[cur][0].p, bx[cur][1].p,
+                        bx[cur][2].p, bx[cur][3].p, bp[cur].p, bx[nx][0].p, bx[nx][1].p,
+                        bx[nx][2].p, bx[nx][3].p, bp[nx].p, box.p, nleft.p, s);
+    }
     launch_tree_children(first, count, total, nleft.p, nbegin.p, nend.p, level.p, child0.p,
                          child1.p, parent.p, d_next.p, s);
     int next = read1(d_next.p, s);

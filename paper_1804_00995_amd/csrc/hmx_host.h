@@ -145,6 +145,15 @@ void launch_tree_level(int first, int count, const int32_t* nbegin, const int32_
                        const double* cx, const double* cy, const double* cz, const double* cw,
                        const int32_t* cperm, double* nx, double* ny, double* nz, double* nw,
                        int32_t* nperm, double* box, int32_t* nleft, hipStream_t s);
+// multi-workgroup variant for levels of few large nodes; max_chunks >= sum ceil(n / 2048)
+void launch_tree_level_chunked(int first, int count, int max_chunks, const int32_t* nbegin,
+                               const int32_t* nend, int leaf, const double* cx, const double* cy,
+                               const double* cz, const double* cw, const int32_t* cperm,
+                               double* nx, double* ny, double* nz, double* nw, int32_t* nperm,
+                               double* box, int32_t* nleft, int32_t* choff, double* pbox,
+                               int32_t* saxis, double* smid, int32_t* ccnt, int32_t* cleft,
+                               hipStream_t s);
+constexpr int TREE_CHUNK_PTS = 2048;  // points per chunk of launch_tree_level_chunked
 void launch_tree_children(int first, int count, int next_first, const int32_t* nleft,
                           int32_t* nbegin, int32_t* nend, int32_t* level, int32_t* child0,
                           int32_t* child1, int32_t* parent, int* next_count, hipStream_t s);
