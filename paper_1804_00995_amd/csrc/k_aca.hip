@@ -75,7 +75,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
                           double* norm2, int fresh, T* gpool, int64_t gcap,
                           unsigned long long* gtop, double2* gram, int gram_min, T* scr,
                           int64_t scr_cap, T* coef, AcaShared& sh) {
-  constexpr int GW = NT >= 512 ? 8 : 4;  // terms per window of the Gram passes
+  constexpr int GW = NT >= 512 ? (sizeof(T) == 16 ? 12 : 16) : 4;  // terms per Gram window
   constexpr int JC = 1;                  // elements per thread per round
   constexpr int LU = NT >= 512 ? 8 : 4;  // previous terms loaded per round (loads in flight)
   const int tid = threadIdx.x;
