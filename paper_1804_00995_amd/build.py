@@ -30,6 +30,7 @@ UNITS = [
     ("k_blocks.hip", True),
     ("k_near.hip", False),
     ("k_aca.hip", False),
+    ("k_far.hip", False),
     ("k_matvec.hip", False),
     ("k_mlp.hip", False),
 ]

@@ -473,8 +473,10 @@ hmx_status hmx_export_blocks(const hmx_op* op, int64_t* near_rc, int64_t* far_rc
       near_rc[4 * i + 3] = c[i] + d[i];
     }
   }
+  std::vector<FarRec> rec;
+  to_host(rec, op->far.p, op->n_far, s);
   for (int64_t i = 0; i < op->n_far; ++i) {
-    const FarRec& f = op->far_host[i];
+    const FarRec& f = rec[i];
     if (far_rc) {
       far_rc[4 * i] = f.tb;
       far_rc[4 * i + 1] = f.tb + f.m;
@@ -492,7 +494,8 @@ hmx_status hmx_export_far(const hmx_op* op, int64_t b, void* U, void* V, int32_t
   HMX_REQUIRE(op && U && rank, HMX_EINVAL, "null pointer");
   HMX_REQUIRE(!op->dense, HMX_EINVAL, "dense operators have no far blocks");
   HMX_REQUIRE(b >= 0 && b < op->n_far, HMX_EINVAL, "far block index out of range");
-  const FarRec& f = op->far_host[b];
+  FarRec f;
+  HMX_HIP(hipMemcpy(&f, op->far.p + b, sizeof(FarRec), hipMemcpyDeviceToHost));
   if (f.dense) {
     HMX_HIP(hipMemcpy(U, f.U, (size_t)f.m * f.n * op->elem, hipMemcpyDeviceToHost));
     *rank = -1;
@@ -513,7 +516,8 @@ hmx_status hmx_import_far(hmx_op* op, const int32_t* ranks, const void* U, const
   HMX_REQUIRE(op && ranks, HMX_EINVAL, "null pointer");
   HMX_REQUIRE(!op->dense, HMX_EINVAL, "dense operators have no far blocks");
   const int64_t nf = op->n_far;
-  std::vector<FarRec> rec = op->far_host;
+  std::vector<FarRec> rec;
+  to_host(rec, op->far.p, nf, (hipStream_t) nullptr);
   int64_t total = 0, trun = 0;
   for (int64_t b = 0; b < nf; ++b) {
     const FarRec& f = rec[b];
@@ -558,7 +562,6 @@ hmx_status hmx_import_far(hmx_op* op, const int32_t* ranks, const void* U, const
     op->max_rank = std::max<int64_t>(op->max_rank, r);
   }
   HMX_HIP(hipMemcpy(op->far.p, rec.data(), nf * sizeof(FarRec), hipMemcpyHostToDevice));
-  op->far_host = std::move(rec);
   op->far_pools.push_back(std::move(pool));
   op->t_len = trun;
   op->tbuf.alloc(std::max<size_t>((size_t)trun * op->elem, op->elem));

@@ -334,71 +334,40 @@ void build_far(hmx_op* op, hipStream_t s) {
   fill_i32(node_first.p, -1, op->n_nodes, s);
   launch_far_prep(op->farL.p, nf, op->nbegin.p, op->nend.p, ftb.p, fm.p, fsb.p, fn.p, node_cnt.p,
                   node_first.p, s);
-  std::vector<int32_t> htb, hm, hsb, hn;
-  to_host(htb, ftb.p, nf, s);
-  to_host(hm, fm.p, nf, s);
-  to_host(hsb, fsb.p, nf, s);
-  to_host(hn, fn.p, nf, s);
 
-  // descriptors: rank cap, first slot capacity (slots are taken from the device pool by the
-  // kernels: workgroup blocks at their start, wavefront blocks at their end, exactly sized)
-  std::vector<FarDesc> desc(nf);
-  std::vector<uint8_t> is_wave(nf);
-  std::vector<int64_t> est(nf);  // pool entries a block is expected to take
-  int64_t flag_bytes = 0, sum_mn = 0;
-  for (int64_t b = 0; b < nf; ++b) {
-    FarDesc& d = desc[b];
-    d.tb = htb[b];
-    d.m = hm[b];
-    d.sb = hsb[b];
-    d.n = hn[b];
-    int64_t rc = ((int64_t)d.m * d.n) / ((int64_t)d.m + d.n);
-    rc = std::min<int64_t>(rc, ACA_COEF_MAX);
-    if (op->p.force_rank_cap > 0) rc = std::min<int64_t>(rc, op->p.force_rank_cap);
-    d.rcap = (int32_t)rc;
-    // first slot: initial_rank columns, more for large blocks (their ranks grow with size)
-    const int64_t mn = (int64_t)d.m + d.n;
-    const int64_t c0 = mn >= 2 * ACA_BIG ? 3 * (int64_t)op->p.initial_rank
-                       : mn >= ACA_BIG ? 2 * (int64_t)op->p.initial_rank
-                                         : (int64_t)op->p.initial_rank;
-    d.cap = (int32_t)std::min<int64_t>(rc, c0);
-    d.U = d.V = nullptr;
-    d.foff = flag_bytes;
-    flag_bytes += d.m + d.n;
-    is_wave[b] = d.m <= ACA_WAVE_N && d.n <= ACA_WAVE_N;
-    // pool estimate without a rank model (generous: a short pool costs another launch round):
-    // wavefront blocks take exactly their rank (<= 16, typically ~8), workgroup blocks twice
-    // their first slot size (an exact slot from scratch, or a first slot plus one doubling)
-    est[b] = is_wave[b] ? 12 * mn : 2 * (int64_t)d.cap * mn;
-    sum_mn += est[b];
-  }
-  // scheduling key within a class: m + n, or with the learned model the predicted work
-  // r_alloc^2 (m + n) of ACA on the block
-  std::vector<int64_t> work(nf);
-  for (int64_t b = 0; b < nf; ++b) work[b] = (int64_t)desc[b].m + desc[b].n;
+  // descriptors on the device: rank cap, first slot size, used-flag offsets, pool estimate,
+  // scheduling key (slots are taken from the device pool by the kernels)
+  DevBuf<FarDesc> d_desc(nf1);
+  DevBuf<int64_t> mnv(nf1), foff(nf1 + 1), estv(nf1), ests(nf1 + 1), work(nf1);
+  DevBuf<uint8_t> wave(nf1);
+  launch_far_desc(op->farL.p, nf, op->nbegin.p, op->nend.p, op->p.initial_rank,
+                  op->p.force_rank_cap, d_desc.p, mnv.p, estv.p, wave.p, work.p, s);
+  scan_excl_i64(mnv.p, foff.p, nf, s);
+  scan_excl_i64(estv.p, ests.p, nf, s);
+  launch_far_foff(d_desc.p, foff.p, nf, s);
+  int64_t sums[2] = {0, 0};  // used-flag bytes, pool estimate
+  HMX_HIP(hipMemcpyAsync(&sums[0], foff.p + nf, 8, hipMemcpyDeviceToHost, s));
+  HMX_HIP(hipMemcpyAsync(&sums[1], ests.p + nf, 8, hipMemcpyDeviceToHost, s));
+  HMX_HIP(hipStreamSynchronize(s));
+  const int64_t flag_bytes = sums[0];
+  int64_t sum_mn = sums[1];
   // learned layout: the slot pool is reserved from the predicted ranks r_alloc (checked against
-  // the device memory before ACA runs) instead of the generic estimate; blocks that outgrow
-  // their prediction take the room others leave
+  // the device memory before ACA runs) instead of the generic estimate, and the scheduling key
+  // becomes the predicted work r_alloc^2 (m + n); blocks that outgrow their prediction take the
+  // room others leave
   if (op->p.rank_model == HMX_RANK_LEARNED && nf > 0) {
     const RankModel rm = get_rank_model();
     HMX_REQUIRE(rm.set, HMX_EINVAL, "rank_model is learned but no model was set (hmx_set_rank_model)");
     DevBuf<float> feat(4 * nf), pred(nf), th(MLP_NPARAMS), nm(8);
+    DevBuf<int64_t> ramn(nf1), rsum(nf1 + 1);
     HMX_HIP(hipMemcpyAsync(th.p, rm.theta, MLP_NPARAMS * 4, hipMemcpyHostToDevice, s));
     HMX_HIP(hipMemcpyAsync(nm.p, rm.norm, 8 * 4, hipMemcpyHostToDevice, s));
     launch_mlp_features(op->farL.p, nf, op->nbegin.p, op->nend.p, op->box.p, op->kpt.p, feat.p, s);
     launch_mlp_predict(th.p, nm.p, feat.p, nf, pred.p, s);
-    std::vector<float> hp;
-    to_host(hp, pred.p, nf, s);
-    int64_t total = 0;
-    for (int64_t b = 0; b < nf; ++b) {
-      const FarDesc& d = desc[b];
-      const double rhat = std::expm1((double)hp[b]) * op->p.force_pred_scale;
-      int64_t ra = (int64_t)std::ceil(rm.alpha * std::max(rhat, 0.0)) + (int64_t)std::lround(rm.beta);
-      ra = std::min<int64_t>(std::max<int64_t>(ra, d.rcap > 0 ? 1 : 0), d.rcap);
-      const int64_t mn = (int64_t)d.m + d.n;
-      total += ra * mn;
-      work[b] = std::max<int64_t>(ra, 1) * std::max<int64_t>(ra, 1) * mn;
-    }
+    launch_far_pred(pred.p, d_desc.p, nf, rm.alpha, (int64_t)std::lround(rm.beta),
+                    op->p.force_pred_scale, ramn.p, work.p, s);
+    scan_excl_i64(ramn.p, rsum.p, nf, s);
+    const int64_t total = read1(rsum.p + nf, s);
     size_t fb = 0, tb = 0;
     HMX_HIP(hipMemGetInfo(&fb, &tb));
     fb += dev_cached_bytes();
@@ -406,6 +375,17 @@ void build_far(hmx_op* op, hipStream_t s) {
                 "predicted factor storage exceeds the free device memory");
     sum_mn = std::max<int64_t>(total, (int64_t)(64 << 20) / (int64_t)sizeof(T));
     op->predicted_entries = total;
+  }
+  // launch order of the first round: by class, then by decreasing floor(log2(work))
+  const int64_t big_mn = op->p.aca_big_mn;
+  DevBuf<int32_t> d_order(nf1);
+  DevBuf<int> key_hist(FAR_ORDER_KEYS), key_cursor(FAR_ORDER_KEYS);
+  launch_far_order(d_desc.p, wave.p, work.p, nf, big_mn, key_hist.p, key_cursor.p, d_order.p, s);
+  int class_count[3] = {0, 0, 0};
+  {
+    std::vector<int> hh;
+    to_host(hh, key_hist.p, nf > 0 ? FAR_ORDER_KEYS : 0, s);
+    for (size_t q = 0; q < hh.size(); ++q) class_count[q / 64] += hh[q];
   }
   // device pool for factor slots, within the free memory
   size_t free_b = 0, total_b = 0;
@@ -422,12 +402,10 @@ void build_far(hmx_op* op, hipStream_t s) {
   DevBuf<T> gpool(gcap);
   wl("pool allocated (GiB)", (double)gcap * sizeof(T) / (1 << 30));
   DevBuf<uint8_t> flags(std::max<int64_t>(flag_bytes, 1));
-  DevBuf<FarDesc> d_desc(nf1);
-  DevBuf<int32_t> d_order(nf1), rank(nf1), ipiv(nf1), status(nf1);
+  DevBuf<int32_t> rank(nf1), ipiv(nf1), status(nf1);
   DevBuf<double> norm2(nf1);
   DevBuf<int> counter(3);
   DevBuf<unsigned long long> gtop(1);
-  if (nf) HMX_HIP(hipMemcpyAsync(d_desc.p, desc.data(), nf * sizeof(FarDesc), hipMemcpyHostToDevice, s));
   fill_i64((int64_t*)gtop.p, 0, 1, s);
 
   wl("device state ready");
@@ -472,38 +450,16 @@ void build_far(hmx_op* op, hipStream_t s) {
   }
   // blocks below aca_gram_min_mn take the direct cross sums (fewer barriers per step)
   const int gram_min = op->p.aca_gram_min_mn;
-  std::vector<uint8_t> cls0(nf, 0);  // class of each block in the first launch
 
-  const int64_t big_mn = op->p.aca_big_mn;
-  // run ACA on a list of blocks, largest first within each class: m + n >= aca_big_mn in
-  // 512-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per wavefront (stream s3, fresh
-  // blocks only), the others in 256-thread workgroups (stream s)
-  // `started`: rank of each block at this launch (nullptr on the first launch, all zero);
-  // blocks that have not started yet run as fresh blocks in any round
-  auto run_aca = [&](const std::vector<int32_t>& list, int fresh,
-                     const std::vector<int32_t>* started) {
-    // each class ordered by decreasing floor(log2(work)) (bucket order, linear time)
-    std::vector<int32_t> bucket[3][64];
-    for (int32_t b : list) {
-      const FarDesc& d = desc[b];
-      const int64_t mn = (int64_t)d.m + d.n;
-      const bool not_started = fresh || (*started)[b] == 0;
-      const int cls = mn >= big_mn ? 0 : (not_started && is_wave[b]) ? 2 : 1;
-      if (fresh) cls0[b] = (uint8_t)cls;
-      const int lw = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(work[b], 1));
-      bucket[cls][63 - lw].push_back(b);
-    }
-    std::vector<int32_t> big, mid, small;
-    for (int q = 0; q < 64; ++q) {
-      big.insert(big.end(), bucket[0][q].begin(), bucket[0][q].end());
-      mid.insert(mid.end(), bucket[1][q].begin(), bucket[1][q].end());
-      small.insert(small.end(), bucket[2][q].begin(), bucket[2][q].end());
-    }
-    std::vector<int32_t> ord(big);
-    ord.insert(ord.end(), mid.begin(), mid.end());
-    ord.insert(ord.end(), small.begin(), small.end());
-    if (!ord.empty())
-      HMX_HIP(hipMemcpyAsync(d_order.p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s));
+  // host copies for the rounds that continue blocks (filled only if a round is needed)
+  std::vector<FarDesc> desc;
+  std::vector<uint8_t> is_wave;
+  std::vector<int64_t> est, hwork;
+  // run ACA with the classes of (nbig, nmid, nsmall) blocks laid out in that order in d_order:
+  // m + n >= aca_big_mn in 512-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per
+  // wavefront (stream s3, blocks that have not started), the others in aca_mid_threads-thread
+  // workgroups (stream s)
+  auto launch_round = [&](int nbig, int nmid, int nsmall, int fresh) {
     fill_i32(counter.p, 0, 3, s);
     // aca_serial = 1 runs the classes one after the other on `s` (same work; also used to time
     // each class on its own)
@@ -514,17 +470,17 @@ void build_far(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipStreamWaitEvent(s2, ev_ready, 0));
     HMX_HIP(hipStreamWaitEvent(s3, ev_ready, 0));
     if (fresh) HMX_HIP(hipEventRecord(tev[0], s2));
-    launch_aca<T>(d_desc.p, d_order.p, (int)big.size(), counter.p, 512, op->X.p, op->Y.p, op->Z.p,
+    launch_aca<T>(d_desc.p, d_order.p, nbig, counter.p, 512, op->X.p, op->Y.p, op->Z.p,
                   op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
                   fresh, gpool.p, gcap, gtop.p, gram_big.p, gram_min, scr_big.p, ACA_SCR_BIG, s2);
     if (fresh) HMX_HIP(hipEventRecord(tev[1], s2));
     if (fresh) HMX_HIP(hipEventRecord(tev[4], s3));
-    launch_aca_wave<T>(d_desc.p, d_order.p + big.size() + mid.size(), (int)small.size(), op->X.p,
+    launch_aca_wave<T>(d_desc.p, d_order.p + nbig + nmid, nsmall, op->X.p,
                        op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p,
                        ipiv.p, status.p, norm2.p, gpool.p, gcap, gtop.p, s3);
     if (fresh) HMX_HIP(hipEventRecord(tev[5], s3));
     if (fresh) HMX_HIP(hipEventRecord(tev[2], s));
-    launch_aca<T>(d_desc.p, d_order.p + big.size(), (int)mid.size(), counter.p + 1, mid_threads,
+    launch_aca<T>(d_desc.p, d_order.p + nbig, nmid, counter.p + 1, mid_threads,
                   op->X.p,
                   op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p,
                   status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, gram_mid.p, gram_min, scr_mid.p,
@@ -536,11 +492,31 @@ void build_far(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipStreamWaitEvent(s, ev_d3, 0));
     HMX_HIP(hipStreamSynchronize(s));
   };
+  // a later round: the listed blocks ordered on the host like the first round, with the
+  // wavefront class for the blocks that have not started (`started`: ranks before the round)
+  auto run_list = [&](const std::vector<int32_t>& list, const std::vector<int32_t>& started) {
+    std::vector<int32_t> bucket[3][64];
+    for (int32_t b : list) {
+      const FarDesc& d = desc[b];
+      const int64_t mn = (int64_t)d.m + d.n;
+      const int cls = mn >= big_mn ? 0 : (started[b] == 0 && is_wave[b]) ? 2 : 1;
+      const int lw = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(hwork[b], 1));
+      bucket[cls][63 - lw].push_back(b);
+    }
+    std::vector<int32_t> ord;
+    int cnt[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c)
+      for (int q = 0; q < 64; ++q) {
+        ord.insert(ord.end(), bucket[c][q].begin(), bucket[c][q].end());
+        cnt[c] += (int)bucket[c][q].size();
+      }
+    if (!ord.empty())
+      HMX_HIP(hipMemcpyAsync(d_order.p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s));
+    launch_round(cnt[0], cnt[1], cnt[2], 0);
+  };
   {
-    std::vector<int32_t> all(nf);
-    std::iota(all.begin(), all.end(), 0);
     wl("first launch start");
-    run_aca(all, 1, nullptr);
+    launch_round(class_count[0], class_count[1], class_count[2], 1);
     wl("first launch done");
     for (int c = 0; c < 3; ++c) {
       float ms = 0.f;
@@ -549,127 +525,128 @@ void build_far(hmx_op* op, hipStream_t s) {
     }
   }
   op->aca_rounds = 1;
-  std::vector<int32_t> hst, hrank;
-  to_host(hst, status.p, nf, s);
   // Blocks stopped with OVERFLOW (device pool exhausted, or a wavefront block past its register
   // capacity) continue in further rounds, each with a new pool sized from the estimates of the
   // blocks left (the old pools keep the finished factors).  A block resumes from its saved state
   // and takes its slots from the new pool in the kernel; one that had not started runs as a
-  // fresh block.
-  std::vector<uint8_t> continued(nf, 0);
-  std::vector<int32_t> first_cap(nf);
-  for (int64_t b = 0; b < nf; ++b) first_cap[b] = desc[b].cap;
+  // fresh block.  The first launch's statuses are summarised on the device; the host reads the
+  // per-block state only when a round is needed.
   std::vector<DevBuf<T>> old_pools;
   int64_t used_old = 0;  // entries taken from pools already retired
-  for (;;) {
-    std::vector<int32_t> list;
-    for (int64_t b = 0; b < nf; ++b)
-      if ((hst[b] & 0xff) == ACA_OVERFLOW) list.push_back((int32_t)b);
-    if (list.empty()) break;
-    to_host(hrank, rank.p, nf, s);
-    to_host(desc, d_desc.p, nf, s);  // current slots (moved on the device)
-    int64_t need = 0;
-    for (int32_t b : list) {
-      continued[b] = 1;
-      // room to finish: a doubled slot, at least twice the rank reached so far
-      const int64_t c = std::max<int64_t>({(int64_t)desc[b].cap, (int64_t)hrank[b] + 8,
-                                           (int64_t)first_cap[b]});
-      need += std::max<int64_t>(est[b], 2 * c * ((int64_t)desc[b].m + desc[b].n));
-    }
-    HMX_HIP(hipMemGetInfo(&free_b, &total_b));
-    free_b += dev_cached_bytes();
-    int64_t ncap = std::min<int64_t>(quantize_up(std::max<int64_t>(need, min_pool)),
-                                     quantize_down((int64_t)(0.6 * (double)free_b) / (int64_t)sizeof(T)));
-    HMX_REQUIRE(ncap > 0, HMX_ENOMEM, "device memory exhausted during ACA");
-    used_old += std::min<int64_t>((int64_t)read1(gtop.p, s), gcap);
-    wl("round: blocks left, new pool entries", (double)list.size(), (double)ncap);
-    old_pools.push_back(std::move(gpool));
-    gpool.alloc(ncap);
-    wl("round: pool allocated");
-    gcap = ncap;
-    fill_i64((int64_t*)gtop.p, 0, 1, s);
-    const std::vector<int32_t> before = hrank;
-    run_aca(list, 0, &before);
-    wl("round: launch done");
-    op->aca_rounds++;
+  DevBuf<uint8_t> d_cont;  // blocks continued in a later round (allocated with the first round)
+  DevBuf<int> nover(1);
+  launch_count_status(status.p, nf, ACA_OVERFLOW, nover.p, s);
+  if (nf > 0 && read1(nover.p, s) > 0) {
+    std::vector<int32_t> hst, hrank, first_cap(nf);
+    std::vector<uint8_t> continued(nf, 0);
+    to_host(desc, d_desc.p, nf, s);
+    to_host(is_wave, wave.p, nf, s);
+    to_host(est, estv.p, nf, s);
+    to_host(hwork, work.p, nf, s);
     to_host(hst, status.p, nf, s);
-    to_host(hrank, rank.p, nf, s);
-    bool progress = false;
-    for (int32_t b : list)
-      if ((hst[b] & 0xff) != ACA_OVERFLOW || hrank[b] != before[b]) progress = true;
-    HMX_REQUIRE(progress, HMX_ENOMEM, "device memory exhausted during ACA (no block progressed)");
+    for (int64_t b = 0; b < nf; ++b) first_cap[b] = desc[b].cap;  // cap of a block not grown
+    for (;;) {
+      std::vector<int32_t> list;
+      for (int64_t b = 0; b < nf; ++b)
+        if ((hst[b] & 0xff) == ACA_OVERFLOW) list.push_back((int32_t)b);
+      if (list.empty()) break;
+      to_host(hrank, rank.p, nf, s);
+      to_host(desc, d_desc.p, nf, s);  // current slots (moved on the device)
+      int64_t need = 0;
+      for (int32_t b : list) {
+        continued[b] = 1;
+        // room to finish: a doubled slot, at least twice the rank reached so far
+        const int64_t c = std::max<int64_t>({(int64_t)desc[b].cap, (int64_t)hrank[b] + 8,
+                                             (int64_t)first_cap[b]});
+        need += std::max<int64_t>(est[b], 2 * c * ((int64_t)desc[b].m + desc[b].n));
+      }
+      HMX_HIP(hipMemGetInfo(&free_b, &total_b));
+      free_b += dev_cached_bytes();
+      int64_t ncap = std::min<int64_t>(quantize_up(std::max<int64_t>(need, min_pool)),
+                                       quantize_down((int64_t)(0.6 * (double)free_b) / (int64_t)sizeof(T)));
+      HMX_REQUIRE(ncap > 0, HMX_ENOMEM, "device memory exhausted during ACA");
+      used_old += std::min<int64_t>((int64_t)read1(gtop.p, s), gcap);
+      wl("round: blocks left, new pool entries", (double)list.size(), (double)ncap);
+      old_pools.push_back(std::move(gpool));
+      gpool.alloc(ncap);
+      wl("round: pool allocated");
+      gcap = ncap;
+      fill_i64((int64_t*)gtop.p, 0, 1, s);
+      const std::vector<int32_t> before = hrank;
+      run_list(list, before);
+      wl("round: launch done");
+      op->aca_rounds++;
+      to_host(hst, status.p, nf, s);
+      to_host(hrank, rank.p, nf, s);
+      bool progress = false;
+      for (int32_t b : list)
+        if ((hst[b] & 0xff) != ACA_OVERFLOW || hrank[b] != before[b]) progress = true;
+      HMX_REQUIRE(progress, HMX_ENOMEM, "device memory exhausted during ACA (no block progressed)");
+    }
+    d_cont.alloc(nf);
+    HMX_HIP(hipMemcpyAsync(d_cont.p, continued.data(), nf, hipMemcpyHostToDevice, s));
   }
-  to_host(hrank, rank.p, nf, s);
-  to_host(desc, d_desc.p, nf, s);
 
   wl("ACA finished");
   // records of the product: factors stay in the slots ACA wrote; dense blocks are assembled
-  std::vector<FarRec> rec(nf);
-  int64_t trun = 0, drun = 0, grown = 0;  // grown: blocks that left their first slot
-  std::vector<int32_t> dtb, dm, dsb, dn;
-  std::vector<int64_t> doff;
-  op->far_entries = op->dense_far = op->dense_far_entries = op->max_rank = op->sum_rank = 0;
-  int64_t evals = 0;
-  for (int64_t b = 0; b < nf; ++b) {
-    const FarDesc& d = desc[b];
-    FarRec& f = rec[b];
-    f.tb = d.tb;
-    f.m = d.m;
-    f.sb = d.sb;
-    f.n = d.n;
-    const int32_t stb = hst[b] & 0xff;
-    HMX_REQUIRE(stb == ACA_CONVERGED || stb == ACA_DENSE, HMX_EINTERNAL,
-                "ACA left a block unfinished");
-    if (continued[b] || (hst[b] & ACA_GREW)) grown++;
-    if (stb == ACA_DENSE) {
-      f.dense = 1;
-      f.r = d.n;
-      f.U = nullptr;  // set below
-      f.V = nullptr;
-      f.toff = trun;
-      trun += d.n;
-      op->dense_far++;
-      op->dense_far_entries += (int64_t)d.m * d.n;
-      dtb.push_back(d.tb);
-      dm.push_back(d.m);
-      dsb.push_back(d.sb);
-      dn.push_back(d.n);
-      doff.push_back(drun);
-      drun += (int64_t)d.m * d.n;
-      evals += (int64_t)d.m * d.n + (int64_t)hrank[b] * (d.m + d.n);
-    } else {
-      f.dense = 0;
-      f.r = hrank[b];
-      f.U = d.U;
-      f.V = d.V;
-      f.toff = trun;
-      trun += f.r;
-      op->far_entries += (int64_t)f.r * (d.m + d.n);
-      op->max_rank = std::max<int64_t>(op->max_rank, f.r);
-      op->sum_rank += f.r;
-      evals += (int64_t)f.r * (d.m + d.n);
-    }
+  op->far.alloc(nf1);
+  DevBuf<int64_t> tcnt(nf1), toff(nf1 + 1), dcnt(nf1), doff(nf1 + 1), dflg(nf1), dpos(nf1 + 1);
+  DevBuf<unsigned long long> stats(FAR_STATS);
+  DevBuf<int> bad(1);
+  fill_i64((int64_t*)stats.p, 0, FAR_STATS, s);
+  fill_i32(bad.p, 0, 1, s);
+  launch_far_rec(d_desc.p, rank.p, status.p, d_cont.p, wave.p, big_mn, (int)sizeof(T), nf,
+                 op->far.p, tcnt.p, dcnt.p, dflg.p, stats.p, bad.p, s);
+  scan_excl_i64(tcnt.p, toff.p, nf, s);
+  scan_excl_i64(dcnt.p, doff.p, nf, s);
+  scan_excl_i64(dflg.p, dpos.p, nf, s);
+  struct {
+    unsigned long long st[FAR_STATS];
+    int64_t t_len, drun, nd, used;
+    int bad;
+  } h{};
+  HMX_HIP(hipMemcpyAsync(h.st, stats.p, sizeof(h.st), hipMemcpyDeviceToHost, s));
+  if (nf > 0) {
+    HMX_HIP(hipMemcpyAsync(&h.t_len, toff.p + nf, 8, hipMemcpyDeviceToHost, s));
+    HMX_HIP(hipMemcpyAsync(&h.drun, doff.p + nf, 8, hipMemcpyDeviceToHost, s));
+    HMX_HIP(hipMemcpyAsync(&h.nd, dpos.p + nf, 8, hipMemcpyDeviceToHost, s));
   }
+  HMX_HIP(hipMemcpyAsync(&h.used, gtop.p, 8, hipMemcpyDeviceToHost, s));
+  HMX_HIP(hipMemcpyAsync(&h.bad, bad.p, 4, hipMemcpyDeviceToHost, s));
+  HMX_HIP(hipStreamSynchronize(s));
+  HMX_REQUIRE(!h.bad, HMX_EINTERNAL, "ACA left a block unfinished");
+  op->far_entries = (int64_t)h.st[0];
+  op->sum_rank = (int64_t)h.st[1];
+  op->max_rank = (int64_t)h.st[2];
+  op->dense_far = (int64_t)h.st[3];
+  op->dense_far_entries = (int64_t)h.st[4];
+  op->overflow_blocks = (int64_t)h.st[5];
+  op->kernel_evals += (int64_t)h.st[6];
   // per class: blocks, and the bytes ACA must move: step k reads the k previous columns of U
   // and V once (residual row and column) and writes one column pair, so a block of final rank r
   // moves es (m + n) r (r + 1) / 2 bytes
-  for (int c = 0; c < 3; ++c) op->aca_blocks[c] = op->aca_bytes[c] = 0;
-  for (int64_t b = 0; b < nf; ++b) {
-    const int64_t r = hrank[b];
-    op->aca_blocks[cls0[b]]++;
-    op->aca_bytes[cls0[b]] += (int64_t)sizeof(T) * ((int64_t)desc[b].m + desc[b].n) * r * (r + 1) / 2;
+  for (int c = 0; c < 3; ++c) {
+    op->aca_blocks[c] = (int64_t)h.st[7 + c];
+    op->aca_bytes[c] = (int64_t)h.st[10 + c];
   }
-  op->overflow_blocks = grown;
-  op->kernel_evals += evals;
-  op->dense_pool.alloc(std::max<int64_t>(drun, 1) * sizeof(T));
-  for (int64_t b = 0, q = 0; b < nf; ++b)
-    if (rec[b].dense) rec[b].U = (const T*)op->dense_pool.p + doff[q++];
-  const int64_t used = (int64_t)read1(gtop.p, s);
-  op->pool_used_bytes = (std::min(used, gcap) + used_old) * (int64_t)sizeof(T);
+  op->t_len = h.t_len;
+  op->pool_used_bytes = (std::min(h.used, gcap) + used_old) * (int64_t)sizeof(T);
+  op->dense_pool.alloc(std::max<int64_t>(h.drun, 1) * sizeof(T));
   if (op->p.pool_limit_bytes > 0 &&
       op->pool_used_bytes + (int64_t)op->near_pool.bytes() + (int64_t)op->dense_pool.bytes() >
           op->p.pool_limit_bytes)
     throw Error(HMX_ENOMEM, "operator exceeds pool_limit_bytes");
+  {
+    const int64_t nd = std::max<int64_t>(h.nd, 1);
+    DevBuf<int32_t> dtb(nd), dm(nd), dsb(nd), dn(nd);
+    DevBuf<int64_t> dofs(nd);
+    launch_far_rec_finish<T>(op->far.p, toff.p, doff.p, dpos.p, nf, (T*)op->dense_pool.p, dtb.p,
+                             dm.p, dsb.p, dn.p, dofs.p, s);
+    if (h.nd > 0)
+      launch_assemble<T>(dtb.p, dm.p, dsb.p, dn.p, dofs.p, h.nd, op->X.p, op->Y.p, op->Z.p,
+                         op->W.p, op->kern, op->kpt.p, (T*)op->dense_pool.p, s);
+    HMX_HIP(hipStreamSynchronize(s));
+  }
   // keep the pools (they hold the factors)
   op->far_pools.clear();
   {
@@ -688,24 +665,6 @@ void build_far(hmx_op* op, hipStream_t s) {
       op->far_pools.push_back(std::move(e));
     }
   }
-  op->t_len = trun;
-  op->far.alloc(nf1);
-  if (nf) HMX_HIP(hipMemcpyAsync(op->far.p, rec.data(), nf * sizeof(FarRec), hipMemcpyHostToDevice, s));
-  if (!dtb.empty()) {
-    int64_t nd = (int64_t)dtb.size();
-    DevBuf<int32_t> a(nd), b2(nd), c(nd), e(nd);
-    DevBuf<int64_t> o(nd);
-    HMX_HIP(hipMemcpyAsync(a.p, dtb.data(), nd * 4, hipMemcpyHostToDevice, s));
-    HMX_HIP(hipMemcpyAsync(b2.p, dm.data(), nd * 4, hipMemcpyHostToDevice, s));
-    HMX_HIP(hipMemcpyAsync(c.p, dsb.data(), nd * 4, hipMemcpyHostToDevice, s));
-    HMX_HIP(hipMemcpyAsync(e.p, dn.data(), nd * 4, hipMemcpyHostToDevice, s));
-    HMX_HIP(hipMemcpyAsync(o.p, doff.data(), nd * 8, hipMemcpyHostToDevice, s));
-    launch_assemble<T>(a.p, b2.p, c.p, e.p, o.p, nd, op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern,
-                       op->kpt.p, (T*)op->dense_pool.p, s);
-    HMX_HIP(hipStreamSynchronize(s));
-  }
-  HMX_HIP(hipStreamSynchronize(s));
-  op->far_host = std::move(rec);
   wl("records and dense far blocks done");
 
   wl("far records on device");

@@ -238,6 +238,27 @@ struct RankModel {
 };
 RankModel get_rank_model();
 
+// k_far.hip: far-field bookkeeping around ACA
+void launch_far_desc(const int2* pairs, int64_t nf, const int32_t* nbegin, const int32_t* nend,
+                     int initial_rank, int force_cap, FarDesc* desc, int64_t* mn, int64_t* est,
+                     uint8_t* wave, int64_t* work, hipStream_t s);
+void launch_far_foff(FarDesc* desc, const int64_t* foff, int64_t nf, hipStream_t s);
+void launch_far_pred(const float* pred, const FarDesc* desc, int64_t nf, double alpha,
+                     int64_t beta, double scale, int64_t* ramn, int64_t* work, hipStream_t s);
+constexpr int FAR_ORDER_KEYS = 3 * 64;  // class * 64 + (63 - floor(log2 work))
+void launch_far_order(const FarDesc* desc, const uint8_t* wave, const int64_t* work, int64_t nf,
+                      int64_t big_mn, int* hist, int* cursor, int32_t* order, hipStream_t s);
+void launch_count_status(const int32_t* status, int64_t nf, int code, int* count, hipStream_t s);
+constexpr int FAR_STATS = 13;
+void launch_far_rec(const FarDesc* desc, const int32_t* rank, const int32_t* status,
+                    const uint8_t* continued, const uint8_t* wave, int64_t big_mn, int es,
+                    int64_t nf, FarRec* rec, int64_t* tcount, int64_t* dcount, int64_t* dflag,
+                    unsigned long long* stats, int* bad, hipStream_t s);
+template <class T>
+void launch_far_rec_finish(FarRec* rec, const int64_t* toff, const int64_t* doff,
+                           const int64_t* dpos, int64_t nf, T* dense_pool, int32_t* dtb,
+                           int32_t* dm, int32_t* dsb, int32_t* dn, int64_t* dofs, hipStream_t s);
+
 // k_matvec.hip
 template <class T>
 void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, hipStream_t s);
@@ -294,7 +315,6 @@ struct hmx_op {
           predicted_entries = 0;
   hmx::DevBuf<int2> farL;
   hmx::DevBuf<hmx::FarRec> far;
-  std::vector<hmx::FarRec> far_host;
   std::vector<hmx::DevBuf<unsigned char>> far_pools;  // factor slots (ACA writes in place)
   hmx::DevBuf<unsigned char> dense_pool;               // far blocks stored dense
   hmx::DevBuf<int64_t> far_ptr;
