@@ -36,7 +36,7 @@ if ROOT not in sys.path:
 
 METRIC = "H-matvec ms and H-build s at 1e-3 rel err; kernel evals/s; frac of HBM/FP peak"
 HBM_PEAK_GBS = 8000.0
-ACA_BIG_KERNEL = "hmx::aca_kernel<T, 512> (ACA of the far blocks with m + n >= 4096)"
+ACA_BIG_KERNEL = "hmx::aca_kernel<T, NT, true> (ACA of the far blocks with m + n >= 4096; NT = 512 for FP64, 256 for FP32)"
 PMC_SUMMARY = {"fp64": os.path.join(ROOT, "profiles", "aca_big_icosphere_L6_k40_fp64_pmc.txt"),
                "fp32": os.path.join(ROOT, "profiles", "aca_big_icosphere_L6_k40_fp32_pmc.txt")}
 ACA_SOURCE = os.path.join(ROOT, "paper_1804_00995_amd", "csrc", "k_aca.hip")

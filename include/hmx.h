@@ -78,8 +78,8 @@ typedef struct {
   int32_t force_rank_cap;  /* > 0: caps every far block's ACA rank (tests force dense fallback) */
   int64_t pool_limit_bytes; /* > 0: fail with HMX_ENOMEM when the operator would exceed this */
   /* ACA schedule (results may differ in rounding between schedules, not in method):
-   * far blocks with m + n >= aca_big_mn run in 512-thread workgroups, those with m, n <= 64 one
-   * per wavefront, the others in 256-thread workgroups; blocks with m + n >= aca_gram_min_mn
+   * far blocks with m + n >= aca_big_mn run in aca_big_threads-thread workgroups, those with
+   * m, n <= 64 one per wavefront, the others in aca_mid_threads-thread workgroups; blocks with m + n >= aca_gram_min_mn
    * take the cross terms from Gram matrices (one read of the factors per step); aca_serial = 1
    * runs the three classes one after the other instead of on three concurrent streams.
    * hmx_autotune picks these for a workload. */
@@ -87,10 +87,11 @@ typedef struct {
   int32_t aca_gram_min_mn; /* >= 0 (default 1024) */
   int32_t aca_serial;      /* 0 or 1 (default 0) */
   int32_t aca_mid_threads; /* workgroup size of the blocks between the wavefront and the
-                              512-thread classes: 256, 128 (default) or 64 */
-  int32_t aca_scratch;     /* 1 (default): a block without a laid-out slot runs in its
-                              workgroup's scratch and then moves to an exactly sized slot;
-                              0: it starts in a pool slot of initial_rank columns and doubles */
+                              large-block classes: 256, 128 (default) or 64 */
+  int32_t aca_arena;       /* 1 (default): each workgroup places its blocks' factors one after
+                              the other in arenas taken from the slot pool, a block keeping
+                              exactly rank (m + n) entries (no copies); 0: every block starts
+                              in a pool slot of its own of initial_rank columns and doubles */
   /* Row share (the part of the operator one of row_shares devices would hold): with
    * row_shares = 2^s > 1, the operator keeps only the rows of cluster-tree node number
    * row_share (breadth-first order) at level s, against all columns; the product then writes
@@ -104,11 +105,14 @@ typedef struct {
                          points (m + n) is split into its children's pairs instead of becoming
                          one far block (smaller ranks, less ACA work and better balance per
                          block); 0: no limit (the plain admissibility recursion) */
+  int32_t aca_big_threads; /* workgroup size of the blocks with m + n >= aca_big_mn: 512 (one
+                              workgroup per CU), 256 (two per CU) or 0 (default: 512 for FP64,
+                              256 for FP32) */
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
  * initial_rank 16, force_pred_scale 1, no rank cap, no pool limit, ACA schedule 4096 / 1024 /
- * concurrent / scratch, one row share, far blocks up to 16384 points. */
+ * concurrent / arenas, one row share, far blocks up to 16384 points. */
 hmx_status hmx_params_default(hmx_params* p);
 
 typedef struct hmx_op hmx_op; /* opaque, library-owned; free with hmx_destroy */
@@ -192,17 +196,17 @@ hmx_status hmx_graph_launch(hmx_graph* g, int32_t reps, void* stream);
 void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
 
 /* Autotuner of the build schedule (max_far_mn, aca_big_mn, aca_gram_min_mn, aca_mid_threads,
- * aca_serial of hmx_params).  Times hmx_build_points(xyzw, M, kern, k) under a grid of
- * settings, each stage at the best of the previous ones: far-block bounds {none, 32768, 16384,
- * 8192}; class thresholds {2048, 4096, 8192, none} x Gram thresholds {0, 1024, 4096, none} on
- * concurrent streams; middle-class workgroups {256, 128, 64}; serial classes; best of two
- * builds each.  *out receives *p (defaults when
+ * aca_big_threads, aca_serial of hmx_params).  Times hmx_build_points(xyzw, M, kern, k) under a
+ * grid of settings, each stage at the best of the previous ones: far-block bounds {none, 32768,
+ * 16384, 8192}; class thresholds {2048, 4096, 8192, none} x Gram thresholds {0, 1024, 4096,
+ * none} on concurrent streams; middle-class workgroups {256, 128, 64}; large-block workgroups
+ * {512, 256}; serial classes; best of two builds each.  *out receives *p (defaults when
  * NULL) with the fastest settings, *best_ms (may be NULL) that build time in ms.
  * cache_path (host string, may be NULL): a JSON file of earlier choices keyed by device
  * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size and eta; a key
  * found there is returned without timing, a new one is added to the file.  Synchronous; builds
- * and frees up to 26 operators.  Errors: as hmx_build_points, HMX_EINVAL for tol <= 0 or an
- * unwritable cache file. */
+ * and frees up to 53 operators (26 settings, two builds each, one warm-up).  Errors: as
+ * hmx_build_points, HMX_EINVAL for tol <= 0 or an unwritable cache file. */
 hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
                         const hmx_params* p, const char* cache_path, void* stream,
                         hmx_params* out, double* best_ms);
@@ -221,8 +225,8 @@ typedef struct {
   int64_t kernel_evals;    /* Green-kernel evaluations spent in the build */
   int64_t factor_bytes;    /* device bytes of the slots holding far-block factors (used part) */
   int64_t predicted_entries; /* learned layout: sum of r_alloc * (m + n) over far blocks */
-  /* ACA by block class: [0] m + n >= 4096 (512-thread workgroups), [1] the other workgroup
-   * blocks (256 threads), [2] m, n <= 64 (one wavefront each).  aca_ms: duration of the class's
+  /* ACA by block class: [0] m + n >= aca_big_mn (aca_big_threads-thread workgroups), [1] the
+   * other workgroup blocks (aca_mid_threads threads), [2] m, n <= 64 (one wavefront each).  aca_ms: duration of the class's
    * first launch (events on the stream it ran on); aca_bytes: bytes the method must move for
    * the class, es (m + n) r (r + 1) / 2 per block of final rank r (step k reads the k previous
    * columns of U and V once and writes one column pair; es = bytes of one complex entry). */

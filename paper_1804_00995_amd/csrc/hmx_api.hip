@@ -59,7 +59,8 @@ void defaults(hmx_params* p) {
   p->aca_gram_min_mn = 1024;
   p->aca_serial = 0;
   p->aca_mid_threads = 128;
-  p->aca_scratch = 1;
+  p->aca_big_threads = 0;
+  p->aca_arena = 1;
   p->row_shares = 1;
   p->row_share = 0;
   p->force_pool_bytes = 0;
@@ -90,9 +91,14 @@ hmx_params resolve(const hmx_params* in) {
   HMX_REQUIRE(p.aca_big_mn >= 2, HMX_EINVAL, "aca_big_mn must be >= 2");
   HMX_REQUIRE(p.aca_gram_min_mn >= 0, HMX_EINVAL, "aca_gram_min_mn must be >= 0");
   HMX_REQUIRE(p.aca_serial == 0 || p.aca_serial == 1, HMX_EINVAL, "aca_serial must be 0 or 1");
-  HMX_REQUIRE(p.aca_scratch == 0 || p.aca_scratch == 1, HMX_EINVAL, "aca_scratch must be 0 or 1");
+  HMX_REQUIRE(p.aca_arena == 0 || p.aca_arena == 1, HMX_EINVAL, "aca_arena must be 0 or 1");
   HMX_REQUIRE(p.aca_mid_threads == 256 || p.aca_mid_threads == 128 || p.aca_mid_threads == 64,
               HMX_EINVAL, "aca_mid_threads must be 256, 128 or 64");
+  HMX_REQUIRE(p.aca_big_threads == 0 || p.aca_big_threads == 512 || p.aca_big_threads == 256,
+              HMX_EINVAL, "aca_big_threads must be 0, 512 or 256");
+  // 0: by precision (measured on the 245 760-point sphere: FP64 streams 16-byte factor entries
+  // and runs best with one 512-thread workgroup per CU, FP32 with two 256-thread ones)
+  if (p.aca_big_threads == 0) p.aca_big_threads = p.precision == HMX_FP64 ? 512 : 256;
   HMX_REQUIRE(p.row_shares >= 1 && p.row_shares <= (1 << 20) &&
                   (p.row_shares & (p.row_shares - 1)) == 0,
               HMX_EINVAL, "row_shares must be a power of two in [1, 2^20]");
@@ -502,8 +508,12 @@ hmx_status hmx_export_far(const hmx_op* op, int64_t b, void* U, void* V, int32_t
   } else {
     HMX_REQUIRE(V || f.r == 0, HMX_EINVAL, "null V");
     if (f.r) {
-      HMX_HIP(hipMemcpy(U, f.U, (size_t)f.m * f.r * op->elem, hipMemcpyDeviceToHost));
-      HMX_HIP(hipMemcpy(V, f.V, (size_t)f.n * f.r * op->elem, hipMemcpyDeviceToHost));
+      // columns of stride ldu / ldv on the device, packed column-major on the host
+      const size_t es = op->elem;
+      HMX_HIP(hipMemcpy2D(U, (size_t)f.m * es, f.U, (size_t)f.ldu * es, (size_t)f.m * es, f.r,
+                          hipMemcpyDeviceToHost));
+      HMX_HIP(hipMemcpy2D(V, (size_t)f.n * es, f.V, (size_t)f.ldv * es, (size_t)f.n * es, f.r,
+                          hipMemcpyDeviceToHost));
     }
     *rank = f.r;
   }
@@ -556,6 +566,8 @@ hmx_status hmx_import_far(hmx_op* op, const int32_t* ranks, const void* U, const
     f.r = (int32_t)r;
     f.U = du;
     f.V = dv;
+    f.ldu = f.m;
+    f.ldv = f.n;
     trun += r;
     op->far_entries += r * (f.m + f.n);
     op->sum_rank += r;

@@ -387,6 +387,19 @@ void build_far(hmx_op* op, hipStream_t s) {
     to_host(hh, key_hist.p, nf > 0 ? FAR_ORDER_KEYS : 0, s);
     for (size_t q = 0; q < hh.size(); ++q) class_count[q / 64] += hh[q];
   }
+  // arenas of the two workgroup classes: at most ACA_ARENA_* entries, and no more than a quarter
+  // of each workgroup's share of the estimate (small problems take small arenas); each
+  // workgroup may leave the unused rest of one arena, which the pool provides for
+  const int mid_threads = op->p.aca_mid_threads;
+  const int big_threads = op->p.aca_big_threads;
+  const int64_t grid_big = aca_grid<T>(big_threads, 1), grid_mid = aca_grid<T>(mid_threads, 0);
+  int64_t arena_big = 0, arena_mid = 0;
+  if (op->p.aca_arena) {
+    const int64_t share = sum_mn / (4 * (grid_big + grid_mid));
+    arena_big = std::min<int64_t>(ACA_ARENA_BIG, std::max<int64_t>(share, 1));
+    arena_mid = std::min<int64_t>(ACA_ARENA_MID, std::max<int64_t>(share, 1));
+    sum_mn += grid_big * arena_big + grid_mid * arena_mid;
+  }
   // device pool for factor slots, within the free memory
   size_t free_b = 0, total_b = 0;
   HMX_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -439,15 +452,8 @@ void build_far(hmx_op* op, hipStream_t s) {
   for (auto& e : tev) HMX_HIP(hipEventCreate(&e));
   // Gram scratch of the two workgroup classes (first launch only)
   const int64_t gram_per_wg = 2 * (int64_t)ACA_GRAM_R * ACA_GRAM_R;  // the larger order
-  const int mid_threads = op->p.aca_mid_threads;
-  DevBuf<double2> gram_big((size_t)aca_grid<T>(512) * gram_per_wg);
-  DevBuf<double2> gram_mid((size_t)aca_grid<T>(mid_threads) * gram_per_wg);
-  // factor scratch of the workgroup classes
-  DevBuf<T> scr_big, scr_mid;
-  if (op->p.aca_scratch) {
-    scr_big.alloc((size_t)aca_grid<T>(512) * ACA_SCR_BIG);
-    scr_mid.alloc((size_t)aca_grid<T>(mid_threads) * ACA_SCR_MID);
-  }
+  DevBuf<double2> gram_big((size_t)grid_big * gram_per_wg);
+  DevBuf<double2> gram_mid((size_t)grid_mid * gram_per_wg);
   // blocks below aca_gram_min_mn take the direct cross sums (fewer barriers per step)
   const int gram_min = op->p.aca_gram_min_mn;
 
@@ -456,7 +462,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   std::vector<uint8_t> is_wave;
   std::vector<int64_t> est, hwork;
   // run ACA with the classes of (nbig, nmid, nsmall) blocks laid out in that order in d_order:
-  // m + n >= aca_big_mn in 512-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per
+  // m + n >= aca_big_mn in aca_big_threads-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per
   // wavefront (stream s3, blocks that have not started), the others in aca_mid_threads-thread
   // workgroups (stream s)
   auto launch_round = [&](int nbig, int nmid, int nsmall, int fresh) {
@@ -470,9 +476,9 @@ void build_far(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipStreamWaitEvent(s2, ev_ready, 0));
     HMX_HIP(hipStreamWaitEvent(s3, ev_ready, 0));
     if (fresh) HMX_HIP(hipEventRecord(tev[0], s2));
-    launch_aca<T>(d_desc.p, d_order.p, nbig, counter.p, 512, op->X.p, op->Y.p, op->Z.p,
+    launch_aca<T>(d_desc.p, d_order.p, nbig, counter.p, big_threads, 1, op->X.p, op->Y.p, op->Z.p,
                   op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
-                  fresh, gpool.p, gcap, gtop.p, gram_big.p, gram_min, scr_big.p, ACA_SCR_BIG, s2);
+                  fresh, gpool.p, gcap, gtop.p, gram_big.p, gram_min, arena_big, s2);
     if (fresh) HMX_HIP(hipEventRecord(tev[1], s2));
     if (fresh) HMX_HIP(hipEventRecord(tev[4], s3));
     launch_aca_wave<T>(d_desc.p, d_order.p + nbig + nmid, nsmall, op->X.p,
@@ -480,11 +486,11 @@ void build_far(hmx_op* op, hipStream_t s) {
                        ipiv.p, status.p, norm2.p, gpool.p, gcap, gtop.p, s3);
     if (fresh) HMX_HIP(hipEventRecord(tev[5], s3));
     if (fresh) HMX_HIP(hipEventRecord(tev[2], s));
-    launch_aca<T>(d_desc.p, d_order.p + nbig, nmid, counter.p + 1, mid_threads,
+    launch_aca<T>(d_desc.p, d_order.p + nbig, nmid, counter.p + 1, mid_threads, 0,
                   op->X.p,
                   op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p,
-                  status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, gram_mid.p, gram_min, scr_mid.p,
-                  ACA_SCR_MID, s);
+                  status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, gram_mid.p, gram_min, arena_mid,
+                  s);
     if (fresh) HMX_HIP(hipEventRecord(tev[3], s));
     HMX_HIP(hipEventRecord(ev_d2, s2));
     HMX_HIP(hipEventRecord(ev_d3, s3));

@@ -6,6 +6,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Address-space qualifiers of device pointers whose space the compiler cannot infer (addresses
+// read from memory): global (1) and LDS (3).  They matter only to device code generation, so the
+// host pass of the same source, which checks kernel bodies without generating them, sees plain
+// pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HMX_GLOBAL __attribute__((address_space(1)))
+#define HMX_LDS __attribute__((address_space(3)))
+#else
+#define HMX_GLOBAL
+#define HMX_LDS
+#endif
+
 namespace hmx {
 
 constexpr int WG = 256;

@@ -99,10 +99,12 @@ struct Rule {
 struct FarDesc {
   int32_t tb, m, sb, n;
   int32_t rcap;  // rank cap: min(floor(m n / (m + n)), coefficient limit, forced cap)
-  int32_t cap;   // rank capacity of the current factor slot
-  void* U;      // slot of U (m x cap, column-major) in one of the build pools
-  void* V;      // slot of V (n x cap, column-major)
+  int32_t cap;   // rank capacity of the current factor slot (its initial size before ACA)
+  void* U;      // slot in one of the build pools: column l of U at U + l ld (m entries)
+  void* V;      // column l of V at V + l ld (n entries); V = U + m
   int64_t foff; // byte offset of the row/column used-flags (m + n bytes)
+  int32_t ld;   // column stride of both factors: m + n (interleaved column pairs)
+  int32_t pad_;
 };
 
 // Final far-block record used by the product.
@@ -110,9 +112,10 @@ struct FarRec {
   int32_t tb, m, sb, n;
   int32_t r;      // rank, or n for a block stored dense (then U is the m x n block)
   int32_t dense;  // 1 when stored dense
-  const void* U;  // m x r column-major (or the m x n block when dense)
-  const void* V;  // n x r column-major (unused when dense)
+  const void* U;  // m x r, column stride ldu (or the m x n block when dense, ldu = m)
+  const void* V;  // n x r, column stride ldv (unused when dense)
   int64_t toff;   // offset of t_b = V^T x_s in the product scratch
+  int32_t ldu, ldv;
 };
 
 constexpr int ACA_COEF_MAX = 1024;  // largest ACA rank (coefficients of a step held in LDS)
@@ -193,18 +196,19 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
                      hipStream_t s);
 // k_aca.hip
 template <class T>
-void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads,
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads, int big,
                 const double* X, const double* Y, const double* Z, const double* W, int kern,
                 const double* kp, double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv,
                 int32_t* status, double* norm2, int fresh, T* gpool, int64_t gcap,
-                unsigned long long* gtop, double2* gram, int gram_min, T* scr, int64_t scr_cap,
+                unsigned long long* gtop, double2* gram, int gram_min, int64_t arena,
                 hipStream_t s);
-// factor scratch per workgroup of the 512-thread and the smaller ACA kernels (entries)
-constexpr int64_t ACA_SCR_BIG = int64_t(1) << 20;
-constexpr int64_t ACA_SCR_MID = int64_t(1) << 18;
-// workgroups of the persistent grid of the ACA kernel with `threads` (512, 256 or 128) threads
+// arena size (entries) of a workgroup of the large-block and of the smaller ACA kernels
+constexpr int64_t ACA_ARENA_BIG = int64_t(1) << 20;
+constexpr int64_t ACA_ARENA_MID = int64_t(1) << 16;
+// workgroups of the persistent grid of the ACA kernel with `threads` threads (big: the
+// large-block class, 512 or 256; else 256, 128 or 64)
 template <class T>
-int aca_grid(int threads);
+int aca_grid(int threads, int big);
 // Gram-matrix order per workgroup of the 512- and the 256-thread ACA kernels (steps past it use
 // direct cross sums); a workgroup's Gram scratch holds 2 ACA_GRAM_R^2 entries of the larger
 constexpr int ACA_GRAM_R = 256;

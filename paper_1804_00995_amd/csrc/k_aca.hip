@@ -15,6 +15,12 @@
 // A ~ sum_k u_k v_k^T with U (m x cap) and V (n x cap) stored column-major.  Pivot magnitudes,
 // norms and the cross terms are accumulated in FP64 in both precisions.
 //
+// Stored form: column k of V holds the residual row R itself and column k of U holds
+// u_k / R_{j_k}, so the product of the two equals u_k v_k^T of steps (3)-(4) without a pass that
+// rescales R.  The residual formulas (1) and (4) are unchanged in this form, the norms in (6)
+// and the cross terms in (5) are the same products (the scales cancel), and both pivot searches
+// use the residual values before any scaling.
+//
 // Schedule: persistent grids; each workgroup takes the next block from an atomic counter
 // (blocks pre-ordered by decreasing size) and runs its whole sequential step chain.  Blocks with
 // m + n above a threshold run in 512-thread workgroups, the others in 256-thread workgroups, and
@@ -67,25 +73,47 @@ __device__ __forceinline__ double2 gram_row_dot(const double2* __restrict__ row,
   return t;
 }
 
-template <class T, int NT>
+// Values that are the same in every lane (block fields, pivots, ranks), moved to scalar registers
+// so that the factor loads take a scalar base address and a 32-bit lane offset.
+__device__ __forceinline__ int ufl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t ufl(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class P>
+__device__ __forceinline__ P* ufl(P* p) {
+  return (P*)(uintptr_t)ufl((int64_t)(uintptr_t)p);
+}
+
+template <class T, int NT, bool BIG, int RL>
 __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __restrict__ X,
                           const double* __restrict__ Y, const double* __restrict__ Z,
                           const double* __restrict__ W, int kern, const double* kp, double tol,
                           uint8_t* flags, int32_t* rank, int32_t* ipiv, int32_t* status,
                           double* norm2, int fresh, T* gpool, int64_t gcap,
-                          unsigned long long* gtop, double2* gram, int gram_min, T* scr,
-                          int64_t scr_cap, T* coef, AcaShared& sh) {
-  constexpr int GW = NT >= 512 ? (sizeof(T) == 16 ? 12 : 16) : 4;  // terms per Gram window
+                          unsigned long long* gtop, double2* gram, int gram_min, int64_t arena,
+                          int64_t& a_top, int64_t& a_end, T* coef, HMX_LDS T* rbuf,
+                          AcaShared& sh) {
+  constexpr int GW = BIG ? (sizeof(T) == 16 ? 6 : 8) : 4;  // terms per Gram window
+  constexpr int JW = BIG ? (sizeof(T) == 16 ? 2 : 4) : 1;  // elements per thread per window round
   constexpr int JC = 1;                  // elements per thread per round
-  constexpr int LU = NT >= 512 ? 8 : 4;  // previous terms loaded per round (loads in flight)
+  constexpr int LU = BIG ? 8 : 4;  // previous terms loaded per round (loads in flight)
   const int tid = threadIdx.x;
   const FarDesc d = descs[b];
-  const int m = d.m, n = d.n, tb = d.tb, sb = d.sb;
+  const int m = ufl(d.m), n = ufl(d.n), tb = ufl(d.tb), sb = ufl(d.sb), rcap = ufl(d.rcap);
   const double k = kp[tb];  // wavenumber of the block's mesh
-  T* U = (T*)d.U;
-  T* V = (T*)d.V;
-  int cap = d.cap;
-  uint8_t* rused = flags + d.foff;
+  // factor slots are device memory: global-address-space pointers (the slot addresses come from
+  // the descriptor in memory, where the compiler cannot infer the space), so that their loads do
+  // not count against the LDS counter the coefficient and residual reads wait on
+  using gT = HMX_GLOBAL T;
+  // slot layout: column l of U at U + l ld and column l of V at V + l ld with V = U + m and
+  // ld = m + n (interleaved column pairs), so the factors of rank r fill r ld consecutive entries
+  const int ld = m + n;
+  gT* U = ufl((gT*)d.U);
+  gT* V = U ? U + m : nullptr;
+  int cap = ufl(d.cap);
+  uint8_t* rused = flags + ufl(d.foff);
   uint8_t* cused = rused + m;
   int kk, ip, hits;
   double nrm2;
@@ -96,9 +124,9 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     hits = 0;
     nrm2 = 0.0;
   } else {
-    kk = rank[b];
-    ip = ipiv[b] & ACA_ROW_MASK;
-    hits = ipiv[b] >> ACA_HIT_SHIFT;
+    kk = ufl(rank[b]);
+    ip = ufl(ipiv[b] & ACA_ROW_MASK);
+    hits = ufl(ipiv[b] >> ACA_HIT_SHIFT);
     nrm2 = norm2[b];
   }
   // Gram matrices of the factors, GV[l][p] = v_l^H v_p and GU[l][p] = u_l^H u_p (FP64,
@@ -107,7 +135,8 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   //   v_l^H R = v_l^H R' - sum_{p in and after l's window} u_p[i_k] GV[l][p],
   // R' the residual before l's window, so the previous columns are read once per step.  Ranks
   // past GR and blocks below gram_min take the direct sums instead.
-  constexpr int GR = NT >= 512 ? ACA_GRAM_R : NT >= 128 ? ACA_GRAM_R_MID : NT;  // Gram order <= NT
+  constexpr int GR = BIG ? ACA_GRAM_R : NT >= 128 ? ACA_GRAM_R_MID : NT;  // Gram order <= NT
+  static_assert(GR <= NT, "one Gram row per thread");
   double2* GV = gram;
   double2* GU = gram ? gram + GR * GR : nullptr;
   bool use_gram = gram != nullptr && m + n >= gram_min && kk < GR;
@@ -123,12 +152,12 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       const int p = q - l * (l + 1) / 2;
       double gv[2] = {0.0, 0.0}, gu[2] = {0.0, 0.0};
       for (int j = lane; j < n; j += WAVE) {
-        const double2 a = to_d2(V[(int64_t)l * n + j]), c = to_d2(V[(int64_t)p * n + j]);
+        const double2 a = to_d2(V[(int64_t)l * ld + j]), c = to_d2(V[(int64_t)p * ld + j]);
         gv[0] += a.x * c.x + a.y * c.y;
         gv[1] += a.x * c.y - a.y * c.x;
       }
       for (int i = lane; i < m; i += WAVE) {
-        const double2 a = to_d2(U[(int64_t)l * m + i]), c = to_d2(U[(int64_t)p * m + i]);
+        const double2 a = to_d2(U[(int64_t)l * ld + i]), c = to_d2(U[(int64_t)p * ld + i]);
         gu[0] += a.x * c.x + a.y * c.y;
         gu[1] += a.x * c.y - a.y * c.x;
       }
@@ -145,78 +174,121 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     }
     __syncthreads();
   }
-  int st = d.rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
-  // A block without a slot that has not started runs in this workgroup's scratch (as many
-  // columns as fit, up to the rank cap) and moves its factors to an exactly sized pool slot when
-  // it finishes; it leaves the scratch earlier only when it outgrows it.
-  bool in_scr = false;
+  int st = rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
   bool grew = !fresh && (status[b] & ACA_GREW);
-  if (st == ACA_RUNNING && U == nullptr && kk == 0 && scr != nullptr) {
-    const int64_t cs = min((int64_t)d.rcap, scr_cap / (m + n));
-    if (cs >= 1) {
-      in_scr = true;
-      cap = (int)cs;
-      U = scr;
-      V = scr + cs * m;
+  // Slots.  With arenas (arena > 0) the workgroup takes pool space in arenas of `arena` entries
+  // and places its blocks one after the other: a block claims the whole free rest of the arena
+  // (up to its rank cap) and, when it stops, keeps exactly its kk ld entries, so slots are exact
+  // without moving the factors.  Without arenas every slot is a pool allocation of its own.
+  // claim(want) returns the first entry of a slot of at least `want` columns (the rest of the
+  // arena when it holds them, else a new arena of max(arena, want ld) entries; the old arena's
+  // rest stays unused) and sets ncap to its capacity; -1 when the pool is exhausted.
+  bool mine = false;  // the slot lies at the top of this workgroup's arena
+  auto claim = [&](int want, int& ncap) -> int64_t {
+    if (arena > 0 && a_end - a_top >= (int64_t)want * ld) {
+      ncap = (int)min((int64_t)rcap, (a_end - a_top) / ld);
+      mine = true;
+      return a_top;
     }
-  }
-  if (st == ACA_RUNNING && U == nullptr) {
-    // first slot, taken from the device pool
-    const int64_t need = (int64_t)cap * (m + n);
-    if (tid == 0) sh.off = (int64_t)atomicAdd(gtop, (unsigned long long)need);
+    const int64_t size = arena > 0 ? max(arena, (int64_t)want * ld) : (int64_t)want * ld;
+    if (tid == 0) sh.off = (int64_t)atomicAdd(gtop, (unsigned long long)size);
     __syncthreads();
-    const int64_t off = sh.off;
-    if (gpool == nullptr || off + need > gcap) {
+    const int64_t off = ufl(sh.off);
+    __syncthreads();  // every thread has read sh.off before it is written again
+    if (gpool == nullptr || off + size > gcap) return -1;
+    if (arena > 0) {
+      a_top = off;
+      a_end = off + size;
+      ncap = (int)min((int64_t)rcap, size / ld);
+      mine = true;
+    } else {
+      ncap = want;
+    }
+    return off;
+  };
+  if (st == ACA_RUNNING && U == nullptr) {
+    // first slot: at least the descriptor's initial capacity
+    int ncap = 0;
+    const int64_t off = claim(min(cap, rcap), ncap);
+    if (off < 0) {
       st = ACA_OVERFLOW;
     } else {
-      U = gpool + off;
-      V = U + (int64_t)cap * m;
-      if (tid == 0) {
-        descs[b].U = U;
-        descs[b].V = V;
-      }
+      U = (gT*)(gpool + off);
+      V = U + m;
+      cap = ncap;
     }
   }
   __syncthreads();
   while (st == ACA_RUNNING) {
     if (kk >= GR) use_gram = false;
     // (1) residual row ip, stored as column kk of V when the slot has room
-    for (int l = tid; l < kk; l += NT) coef[l] = U[(int64_t)l * m + ip];
+    for (int l = tid; l < kk; l += NT) coef[l] = U[(int64_t)l * ld + ip];
     __syncthreads();
     const double px = X[tb + ip], py = Y[tb + ip], pz = Z[tb + ip];
     const bool store = kk < cap;
     const bool gstep = use_gram && store;  // this step keeps the Gram matrices
-    T* R = V + (int64_t)kk * n;
-    double best = -1.0;
+    gT* R = V + (int64_t)kk * ld;
+    double best = -1.0, nv2 = 0.0;
     int bj = INT_MAX;
     // Gram part of v_l^H R for this thread's l (gstep: kk < GR <= NT, one l per thread);
     // it needs only the coefficients, so its loads go out before the row pass
     double2 gcorr = make_double2(0.0, 0.0);
     if (gstep && tid < kk) gcorr = gram_row_dot(GV + (int64_t)tid * GR, coef, (tid / GW) * GW, kk);
     if (gstep) {
-      // windows of GW previous terms; the partial residual lives in column kk between windows
+      // windows of GW previous terms; a thread takes JW elements per round (j0 + q NT), so that
+      // JW GW factor loads are in flight together while the Gram sums and coefficients are
+      // shared.  The partial residual between windows lives in LDS for j < RL (RL is a multiple
+      // of NT, so the choice is uniform across the workgroup) and in column kk beyond.
       for (int l0 = 0; l0 < max(kk, 1); l0 += GW) {
         const int lc = min(GW, kk - l0);
         const bool first = l0 == 0, last = l0 + GW >= kk;
         double g[2 * GW];
 #pragma unroll
         for (int q = 0; q < 2 * GW; ++q) g[q] = 0.0;
-        for (int j = tid; j < n; j += NT) {
-          T r = first ? eval_entry<T>(kern, k, px, py, pz, X[sb + j], Y[sb + j], Z[sb + j], W[sb + j])
-                      : R[j];
-          const double2 r0 = to_d2(r);
-          T vv[GW];
+        for (int j0 = tid; j0 < n; j0 += NT * JW) {
+          T vv[JW][GW], r[JW];
 #pragma unroll
-          for (int u = 0; u < GW; ++u) vv[u] = u < lc ? V[(int64_t)(l0 + u) * n + j] : czero<T>();
+          for (int q = 0; q < JW; ++q) {
+            const int jc = min(j0 + q * NT, n - 1);  // in bounds; lanes past n are zeroed below
 #pragma unroll
-          for (int u = 0; u < GW; ++u) {
-            const double2 a = to_d2(vv[u]);
-            g[2 * u] += a.x * r0.x + a.y * r0.y;
-            g[2 * u + 1] += a.x * r0.y - a.y * r0.x;
-            if (u < lc) cfms(r, coef[l0 + u], vv[u]);
+            for (int u = 0; u < GW; ++u)
+              vv[q][u] = u < lc ? V[(int64_t)(l0 + u) * ld + jc] : czero<T>();
           }
-          R[j] = r;
-          if (last && !cused[j]) amax_merge(best, bj, abs2(r), j);
+#pragma unroll
+          for (int q = 0; q < JW; ++q) {
+            const int j = j0 + q * NT, jc = min(j, n - 1);
+            const bool inl = j < RL;
+            T x = first ? eval_entry<T>(kern, k, px, py, pz, X[sb + jc], Y[sb + jc], Z[sb + jc], W[sb + jc])
+                        : inl ? (T)rbuf[inl ? j : 0] : (T)R[jc];
+            r[q] = j < n ? x : czero<T>();
+          }
+#pragma unroll
+          for (int q = 0; q < JW; ++q) {
+            const double2 r0 = to_d2(r[q]);
+#pragma unroll
+            for (int u = 0; u < GW; ++u) {
+              const double2 a = to_d2(vv[q][u]);
+              g[2 * u] += a.x * r0.x + a.y * r0.y;
+              g[2 * u + 1] += a.x * r0.y - a.y * r0.x;
+              if (u < lc) cfms(r[q], coef[l0 + u], vv[q][u]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < JW; ++q) {
+            const int j = j0 + q * NT;
+            if (j < n) {
+              if (last) {
+                R[j] = r[q];
+                const double a2 = abs2(r[q]);
+                nv2 += a2;
+                if (!cused[j]) amax_merge(best, bj, a2, j);
+              } else if (j < RL) {
+                rbuf[j < RL ? j : 0] = r[q];
+              } else {
+                R[j] = r[q];
+              }
+            }
+          }
         }
         if (lc > 0) {
           block_sum<2 * GW, NT>(g, sh.ssum);
@@ -242,7 +314,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
 #pragma unroll
         for (int u = 0; u < LU; ++u)
 #pragma unroll
-          for (int q = 0; q < JC; ++q) vv[u][q] = V[(int64_t)(l + u) * n + jx[q]];
+          for (int q = 0; q < JC; ++q) vv[u][q] = V[(int64_t)(l + u) * ld + jx[q]];
 #pragma unroll
         for (int u = 0; u < LU; ++u) {
           const T c = coef[l + u];
@@ -253,19 +325,22 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       for (; l < kk; ++l) {
         const T c = coef[l];
 #pragma unroll
-        for (int q = 0; q < JC; ++q) cfms(a[q], c, V[(int64_t)l * n + jx[q]]);
+        for (int q = 0; q < JC; ++q) cfms(a[q], c, V[(int64_t)l * ld + jx[q]]);
       }
 #pragma unroll
       for (int q = 0; q < JC; ++q) {
         const int j = j0 + q * NT;
         if (j < n) {
+          const double a2 = abs2(a[q]);
           if (store) R[j] = a[q];
-          if (!cused[j]) amax_merge(best, bj, abs2(a[q]), j);
+          nv2 += a2;
+          if (!cused[j]) amax_merge(best, bj, a2, j);
         }
       }
     }
     }
     block_amax<NT>(best, bj, sh.sv, sh.si);
+    bj = ufl(bj);
     if (bj == INT_MAX || best <= 1e-300) {
       // (2') zero residual row: mark it, move to the lowest unused row
       if (tid == 0) rused[ip] = 1;
@@ -276,7 +351,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           nx = i;
           break;
         }
-      nx = block_min<NT>(nx, sh.si);
+      nx = ufl(block_min<NT>(nx, sh.si));
       if (nx == INT_MAX) {
         st = ACA_CONVERGED;
         break;
@@ -285,66 +360,45 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       continue;
     }
     if (!store) {
-      if (cap >= d.rcap) {
+      if (cap >= rcap) {
         st = ACA_DENSE;
         break;
       }
-      // move to a slot of twice the size from the device pool
-      const int ncap = min(d.rcap, max(2 * cap, cap + 8));
-      const int64_t need = (int64_t)ncap * (m + n);
-      if (tid == 0) sh.off = (int64_t)atomicAdd(gtop, (unsigned long long)need);
-      __syncthreads();
-      const int64_t off = sh.off;
-      if (gpool == nullptr || off + need > gcap) {
+      // move to a slot of at least twice the size (a new arena, or the free rest of this
+      // workgroup's arena for a block resumed from an earlier pool; never its own slot)
+      int ncap = 0;
+      const int64_t off = claim(min(rcap, max(2 * cap, cap + 8)), ncap);
+      if (off < 0) {
         st = ACA_OVERFLOW;
         break;
       }
-      T* nU = gpool + off;
-      T* nV = nU + (int64_t)ncap * m;
-      const int64_t cu = (int64_t)kk * m, cv = (int64_t)kk * n;
-      for (int64_t e = tid; e < cu; e += NT) nU[e] = U[e];
-      for (int64_t e = tid; e < cv; e += NT) nV[e] = V[e];
+      gT* nU = (gT*)(gpool + off);
+      const int64_t cnt = (int64_t)kk * ld;  // the kk column pairs, contiguous
+      for (int64_t e = tid; e < cnt; e += NT) nU[e] = U[e];
       __syncthreads();
       U = nU;
-      V = nV;
+      V = nU + m;
       cap = ncap;
-      grew = grew || !in_scr;
-      in_scr = false;
-      if (tid == 0) {
-        descs[b].U = nU;
-        descs[b].V = nV;
-        descs[b].cap = ncap;
-      }
+      grew = true;
       continue;  // recompute the residual row into the new slot
     }
-    // (3) v_k = R / R[bj]
+    // (3) the scale 1 / R[bj] of v_k, folded into u_k (R stays as stored)
     const double2 pd = to_d2(R[bj]);
     const double den = pd.x * pd.x + pd.y * pd.y;
-    const T inv = from_d2<T>(make_double2(pd.x / den, -pd.y / den));
+    const double2 invd = make_double2(pd.x / den, -pd.y / den);
+    const T inv = from_d2<T>(invd);
     // v_l^H v_k for this thread's l (gstep: kk < GR <= NT, one l per thread)
     double2 vdot = make_double2(0.0, 0.0);
-    if (gstep && tid < kk) {
-      const double2 t = make_double2(sh.h[tid].x - gcorr.x, sh.h[tid].y - gcorr.y);
-      const double ix = pd.x / den, iy = -pd.y / den;
-      vdot = make_double2(t.x * ix - t.y * iy, t.x * iy + t.y * ix);
-    }
-    __syncthreads();  // every thread has read the pivot before it is scaled in place
+    if (gstep && tid < kk) vdot = make_double2(sh.h[tid].x - gcorr.x, sh.h[tid].y - gcorr.y);
     if (tid == 0) {
       rused[ip] = 1;
       cused[bj] = 1;
     }
-    double nv2 = 0.0;
-    for (int j = tid; j < n; j += NT) {
-      T v = cmul(R[j], inv);
-      R[j] = v;
-      nv2 += abs2(v);
-    }
-    __syncthreads();
     // (4) residual column bj, stored as column kk of U
-    for (int l = tid; l < kk; l += NT) coef[l] = V[(int64_t)l * n + bj];
+    for (int l = tid; l < kk; l += NT) coef[l] = V[(int64_t)l * ld + bj];
     __syncthreads();
     const double qx = X[sb + bj], qy = Y[sb + bj], qz = Z[sb + bj], qw = W[sb + bj];
-    T* Uk = U + (int64_t)kk * m;
+    gT* Uk = U + (int64_t)kk * ld;
     double ub = -1.0, nu2 = 0.0;
     int ui = INT_MAX;
     double cross = 0.0;
@@ -358,25 +412,50 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
         double g[2 * GW];
 #pragma unroll
         for (int q = 0; q < 2 * GW; ++q) g[q] = 0.0;
-        for (int i = tid; i < m; i += NT) {
-          T r = first ? eval_entry<T>(kern, k, X[tb + i], Y[tb + i], Z[tb + i], qx, qy, qz, qw)
-                      : Uk[i];
-          const double2 r0 = to_d2(r);
-          T uu[GW];
+        // JW elements per thread and round, as in the row pass
+        for (int i0 = tid; i0 < m; i0 += NT * JW) {
+          T uu[JW][GW], r[JW];
 #pragma unroll
-          for (int u = 0; u < GW; ++u) uu[u] = u < lc ? U[(int64_t)(l0 + u) * m + i] : czero<T>();
+          for (int q = 0; q < JW; ++q) {
+            const int ic = min(i0 + q * NT, m - 1);
 #pragma unroll
-          for (int u = 0; u < GW; ++u) {
-            const double2 a = to_d2(uu[u]);
-            g[2 * u] += a.x * r0.x + a.y * r0.y;
-            g[2 * u + 1] += a.x * r0.y - a.y * r0.x;
-            if (u < lc) cfms(r, coef[l0 + u], uu[u]);
+            for (int u = 0; u < GW; ++u)
+              uu[q][u] = u < lc ? U[(int64_t)(l0 + u) * ld + ic] : czero<T>();
           }
-          Uk[i] = r;
-          if (last) {
-            const double a2 = abs2(r);
-            nu2 += a2;
-            if (!rused[i]) amax_merge(ub, ui, a2, i);
+#pragma unroll
+          for (int q = 0; q < JW; ++q) {
+            const int i = i0 + q * NT, ic = min(i, m - 1);
+            const bool inl = i < RL;
+            T x = first ? eval_entry<T>(kern, k, X[tb + ic], Y[tb + ic], Z[tb + ic], qx, qy, qz, qw)
+                        : inl ? (T)rbuf[inl ? i : 0] : (T)Uk[ic];
+            r[q] = i < m ? x : czero<T>();
+          }
+#pragma unroll
+          for (int q = 0; q < JW; ++q) {
+            const double2 r0 = to_d2(r[q]);
+#pragma unroll
+            for (int u = 0; u < GW; ++u) {
+              const double2 a = to_d2(uu[q][u]);
+              g[2 * u] += a.x * r0.x + a.y * r0.y;
+              g[2 * u + 1] += a.x * r0.y - a.y * r0.x;
+              if (u < lc) cfms(r[q], coef[l0 + u], uu[q][u]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < JW; ++q) {
+            const int i = i0 + q * NT;
+            if (i < m) {
+              if (last) {
+                if (!rused[i]) amax_merge(ub, ui, abs2(r[q]), i);
+                const T us = cmul(r[q], inv);
+                Uk[i] = us;
+                nu2 += abs2(us);
+              } else if (i < RL) {
+                rbuf[i < RL ? i : 0] = r[q];
+              } else {
+                Uk[i] = r[q];
+              }
+            }
           }
         }
         if (lc > 0) {
@@ -387,9 +466,13 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
         }
       }
       __syncthreads();
-      // u_l^H u_k, the cross term, and the new Gram entries
+      // u_l^H u_k (the window sums hold u_l^H times the unscaled column), the cross term, and
+      // the new Gram entries
       double2 udot = make_double2(0.0, 0.0);
-      if (tid < kk) udot = make_double2(sh.h[tid].x - ucorr.x, sh.h[tid].y - ucorr.y);
+      if (tid < kk) {
+        const double2 t = make_double2(sh.h[tid].x - ucorr.x, sh.h[tid].y - ucorr.y);
+        udot = make_double2(t.x * invd.x - t.y * invd.y, t.x * invd.y + t.y * invd.x);
+      }
       double cr[1] = {udot.x * vdot.x - udot.y * vdot.y};
       block_sum<1, NT>(cr, sh.ssum);
       cross = cr[0];
@@ -415,7 +498,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
 #pragma unroll
         for (int u = 0; u < LU; ++u)
 #pragma unroll
-          for (int q = 0; q < JC; ++q) uu[u][q] = U[(int64_t)(l + u) * m + ix[q]];
+          for (int q = 0; q < JC; ++q) uu[u][q] = U[(int64_t)(l + u) * ld + ix[q]];
 #pragma unroll
         for (int u = 0; u < LU; ++u) {
           const T c = coef[l + u];
@@ -426,23 +509,23 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       for (; l < kk; ++l) {
         const T c = coef[l];
 #pragma unroll
-        for (int q = 0; q < JC; ++q) cfms(a[q], c, U[(int64_t)l * m + ix[q]]);
+        for (int q = 0; q < JC; ++q) cfms(a[q], c, U[(int64_t)l * ld + ix[q]]);
       }
 #pragma unroll
       for (int q = 0; q < JC; ++q) {
         const int i = i0 + q * NT;
         if (i < m) {
-          Uk[i] = a[q];
-          const double a2 = abs2(a[q]);
-          nu2 += a2;
-          if (!rused[i]) amax_merge(ub, ui, a2, i);
+          if (!rused[i]) amax_merge(ub, ui, abs2(a[q]), i);
+          const T us = cmul(a[q], inv);
+          Uk[i] = us;
+          nu2 += abs2(us);
         }
       }
     }
     __syncthreads();
     // (5) cross terms sum_{l<kk} (u_l^H u_k)(v_l^H v_k), LG terms at a time (LG loads in
     // flight per thread per round)
-    constexpr int LG = NT >= 512 ? 4 : 2;
+    constexpr int LG = BIG ? 4 : 2;
     constexpr int CJ = 1;  // elements per thread per round in this pass
     for (int l0 = 0; l0 < kk; l0 += LG) {
       const int lc = min(LG, kk - l0);
@@ -458,7 +541,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           const int ix = i < m ? i : m - 1;
           uk[c] = i < m ? to_d2(Uk[ix]) : make_double2(0.0, 0.0);
 #pragma unroll
-          for (int q = 0; q < LG; ++q) ul[c][q] = q < lc ? U[(int64_t)(l0 + q) * m + ix] : czero<T>();
+          for (int q = 0; q < LG; ++q) ul[c][q] = q < lc ? U[(int64_t)(l0 + q) * ld + ix] : czero<T>();
         }
 #pragma unroll
         for (int c = 0; c < CJ; ++c)
@@ -478,7 +561,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           const int jx = j < n ? j : n - 1;
           vk[c] = j < n ? to_d2(R[jx]) : make_double2(0.0, 0.0);
 #pragma unroll
-          for (int q = 0; q < LG; ++q) vl[c][q] = q < lc ? V[(int64_t)(l0 + q) * n + jx] : czero<T>();
+          for (int q = 0; q < LG; ++q) vl[c][q] = q < lc ? V[(int64_t)(l0 + q) * ld + jx] : czero<T>();
         }
 #pragma unroll
         for (int c = 0; c < CJ; ++c)
@@ -505,6 +588,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     nrm2 = nrm2 + 2.0 * cross + nn2[0] * nn2[1];
     kk += 1;
     block_amax<NT>(ub, ui, sh.sv, sh.si);
+    ui = ufl(ui);
     // (6) stopping rule (met at ACA_STOP_STEPS consecutive steps), (7) next pivot row
     if (sqrt(nn2[0]) * sqrt(nn2[1]) <= tol * sqrt(nrm2)) {
       if (++hits >= ACA_STOP_STEPS) {
@@ -520,40 +604,17 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     }
     ip = ui;
   }
-  if (in_scr) {
-    // move the factors out of the scratch into an exact slot; without room in the pool the
-    // block is reset and runs again from its start in the next round
-    const int64_t need = (int64_t)kk * (m + n);
-    bool placed = st == ACA_DENSE || need == 0;
-    if (!placed && st == ACA_CONVERGED) {
-      if (tid == 0) sh.off = (int64_t)atomicAdd(gtop, (unsigned long long)need);
-      __syncthreads();
-      const int64_t off = sh.off;
-      if (gpool != nullptr && off + need <= gcap) {
-        T* nU = gpool + off;
-        T* nV = nU + (int64_t)kk * m;
-        const int64_t cu = (int64_t)kk * m, cv = (int64_t)kk * n;
-        for (int64_t e = tid; e < cu; e += NT) nU[e] = U[e];
-        for (int64_t e = tid; e < cv; e += NT) nV[e] = V[e];
-        if (tid == 0) {
-          descs[b].U = nU;
-          descs[b].V = nV;
-          descs[b].cap = kk;
-        }
-        placed = true;
-      }
-    }
-    if (!placed) {
-      st = ACA_OVERFLOW;
-      kk = 0;
-      ip = 0;
-      hits = 0;
-      nrm2 = 0.0;
-      for (int i = tid; i < m + n; i += NT) rused[i] = 0;
-    }
-    __syncthreads();  // the scratch is free for the next block
+  if (mine) {
+    // the block keeps exactly kk ld entries at the top of the arena (none when it is stored
+    // dense); a block stopped for a later round resumes from them and moves on its next step
+    if (st != ACA_DENSE) a_top += (int64_t)kk * ld;
+    cap = kk;
   }
   if (tid == 0) {
+    descs[b].U = (void*)U;
+    descs[b].V = (void*)V;
+    descs[b].cap = cap;
+    descs[b].ld = ld;
     rank[b] = kk;
     ipiv[b] = ip | (hits << ACA_HIT_SHIFT);
     norm2[b] = nrm2;
@@ -562,8 +623,18 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   __syncthreads();
 }
 
-template <class T, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 2 : 3))) aca_kernel(FarDesc* __restrict__ desc,
+// Length of the LDS residual buffer (a multiple of NT): the large-block class keeps up to 7680
+// (FP64) or 15360 (FP32) entries of the partial residual in LDS with 512-thread workgroups (one
+// per CU), 3584 or 8192 with 256-thread workgroups (two per CU); the other classes keep theirs in
+// the factor slot.
+template <class T, int NT, bool BIG>
+constexpr int aca_rl() {
+  return !BIG ? 0 : NT >= 512 ? (sizeof(T) == 16 ? 7680 : 15360) : (sizeof(T) == 16 ? 3584 : 8192);
+}
+
+// BIG: the large-block class (long Gram windows, two waves per SIMD, LDS residual)
+template <class T, int NT, bool BIG>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BIG ? 2 : 3))) aca_kernel(FarDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order, int nb,
                                                  int* counter, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
@@ -573,19 +644,22 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 5
                                                  int32_t* ipiv, int32_t* status, double* norm2,
                                                  int fresh, T* gpool, int64_t gcap,
                                                  unsigned long long* gtop, double2* gram,
-                                                 int gram_min, T* scr, int64_t scr_cap) {
+                                                 int gram_min, int64_t arena) {
+  constexpr int RL = aca_rl<T, NT, BIG>();
   __shared__ T coef[ACA_COEF_MAX];
+  __shared__ T rbuf[RL > 0 ? RL : 1];
   __shared__ AcaShared sh;
   double2* my_gram = gram ? gram + (int64_t)blockIdx.x * 2 * ACA_GRAM_R * ACA_GRAM_R : nullptr;
-  T* my_scr = scr ? scr + (int64_t)blockIdx.x * scr_cap : nullptr;
+  int64_t a_top = 0, a_end = 0;  // this workgroup's arena: free entries [a_top, a_end) of gpool
   for (;;) {
     if (threadIdx.x == 0) sh.q = atomicAdd(counter, 1);
     __syncthreads();
-    const int q = sh.q;
+    const int q = ufl(sh.q);
     __syncthreads();
     if (q >= nb) break;
-    aca_block<T, NT>(desc, order[q], X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2,
-                     fresh, gpool, gcap, gtop, my_gram, gram_min, my_scr, scr_cap, coef, sh);
+    aca_block<T, NT, BIG, RL>(desc, ufl(order[q]), X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status,
+                         norm2, fresh, gpool, gcap, gtop, my_gram, gram_min, arena, a_top, a_end, coef,
+                         (HMX_LDS T*)rbuf, sh);
   }
 }
 
@@ -657,11 +731,11 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
         st = ACA_OVERFLOW;
         break;
       }
-      // (3) v_k = R / R[bj]
+      // (3) stored form: v_k is R itself, u_k carries the scale 1 / R[bj]
       const double2 pd = to_d2(readlane(a, bj));
       const double den = pd.x * pd.x + pd.y * pd.y;
       const T inv = from_d2<T>(make_double2(pd.x / den, -pd.y / den));
-      const T vn = cmul(a, inv);
+      const T vn = a;
       if (lane == ip) rused = true;
       if (lane == bj) cused = true;
       // (4) residual column bj
@@ -671,7 +745,8 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
 #pragma unroll
       for (int l = 0; l < RC; ++l)
         if (l < kk) cfms(c, readlane(v[l], bj), u[l]);
-      const T un = hr ? c : czero<T>();
+      const T uraw = hr ? c : czero<T>();
+      const T un = cmul(uraw, inv);
       // (5) norms and cross term
       const double nu2 = wave_sum(abs2(un)), nv2 = wave_sum(abs2(vn));
       double2 s = make_double2(0.0, 0.0);
@@ -707,7 +782,7 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
       } else {
         hits = 0;
       }
-      double bu = rused ? -1.0 : abs2(un);
+      double bu = rused ? -1.0 : abs2(uraw);
       int bi = rused ? INT_MAX : lane;
       wave_amax(bu, bi);
       bi = __builtin_amdgcn_readfirstlane(bi);
@@ -718,19 +793,16 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
       ip = bi;
     }
     // factors go to a slot of exactly kk columns (or twice RC for a block continued by the
-    // workgroup kernel) taken from the device pool; if the pool is exhausted the block is
-    // restarted from scratch by the workgroup kernel
+    // workgroup kernel) taken from the device pool, laid out as interleaved column pairs
+    // (ld = m + n); if the pool is exhausted the block is restarted from scratch by the
+    // workgroup kernel
+    const int ld = m + n;
     int scap = st == ACA_OVERFLOW ? min(d.rcap, 2 * RC) : kk;
-    T* Ug = nullptr;
-    T* Vg = nullptr;
-    // a slot laid out in advance (learned layout) is used when it is large enough
-    const bool pre = d.U != nullptr && (st == ACA_OVERFLOW ? d.cap > kk : d.cap >= kk);
-    if (pre && scap > 0 && st != ACA_DENSE) {
-      Ug = (T*)d.U;
-      Vg = (T*)d.V;
-      scap = d.cap;
-    } else if (scap > 0 && st != ACA_DENSE) {
-      const int64_t need = (int64_t)scap * (m + n);
+    using gT = HMX_GLOBAL T;
+    gT* Ug = nullptr;
+    gT* Vg = nullptr;
+    if (scap > 0 && st != ACA_DENSE) {
+      const int64_t need = (int64_t)scap * ld;
       // every lane issues the atomic (no lane-dependent branch); only lane 0 adds `need`, and
       // lane 0's return value is the slot offset
       unsigned long long off =
@@ -738,8 +810,8 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
       off = ((unsigned long long)(unsigned int)__builtin_amdgcn_readlane((int)(off >> 32), 0) << 32) |
             (unsigned int)__builtin_amdgcn_readlane((int)(off & 0xffffffffu), 0);
       if (gpool != nullptr && (int64_t)off + need <= gcap) {
-        Ug = gpool + off;
-        Vg = Ug + (int64_t)scap * m;
+        Ug = (gT*)(gpool + off);
+        Vg = Ug + m;
       } else {
         st = ACA_OVERFLOW;
         kk = 0;
@@ -754,8 +826,8 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
 #pragma unroll
       for (int l = 0; l < RC; ++l) {
         if (l < kk) {
-          if (hr) Ug[(int64_t)l * m + lane] = u[l];
-          if (hc) Vg[(int64_t)l * n + lane] = v[l];
+          if (hr) Ug[(int64_t)l * ld + lane] = u[l];
+          if (hc) Vg[(int64_t)l * ld + lane] = v[l];
         }
       }
     }
@@ -765,9 +837,10 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
       if (hc) rf[m + lane] = cused ? 1 : 0;
     }
     if (lane == 0) {
-      desc[b].U = Ug;
-      desc[b].V = Vg;
-      desc[b].cap = Ug ? scap : 0;
+      desc[b].U = (void*)Ug;
+      desc[b].V = (void*)Vg;
+      desc[b].cap = Ug ? scap : d.cap;
+      desc[b].ld = ld;
     }
     if (lane == 0) {
       rank[b] = kk;
@@ -795,51 +868,53 @@ void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
   HMX_LAUNCHED();
 }
 
-// Workgroups of a persistent ACA grid (512-, 256- or 128-thread workgroups): as many as can be
-// resident at once.
+// Workgroups of a persistent ACA grid (big: the large-block class, 512 or 256 threads; else 256,
+// 128 or 64 threads): as many as can be resident at once.
 template <class T>
-int aca_grid(int threads) {
+int aca_grid(int threads, int big) {
   int dev = 0, ncu = 0, occ = 0;
   HMX_HIP(hipGetDevice(&dev));
   HMX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  if (threads == 512)
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 512>, 512, 0));
+  if (big && threads == 512)
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 512, true>, 512, 0));
+  else if (big)
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 256, true>, 256, 0));
   else if (threads == 256)
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 256>, 256, 0));
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 256, false>, 256, 0));
   else if (threads == 128)
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 128>, 128, 0));
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 128, false>, 128, 0));
   else
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 64>, 64, 0));
+    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 64, false>, 64, 0));
   return std::max(1, occ) * ncu;
 }
 
 template <class T>
-void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads,
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads, int big,
                 const double* X, const double* Y, const double* Z, const double* W, int kern,
                 const double* kp, double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv,
                 int32_t* status, double* norm2, int fresh, T* gpool, int64_t gcap,
-                unsigned long long* gtop, double2* gram, int gram_min, T* scr, int64_t scr_cap,
+                unsigned long long* gtop, double2* gram, int gram_min, int64_t arena,
                 hipStream_t s) {
   if (nb <= 0) return;
-  // `gram` (when given) holds 2 ACA_GRAM_R^2 entries and `scr` scr_cap entries for each of
-  // aca_grid(threads) workgroups; blocks with m + n >= gram_min use the Gram matrices
-  const int grid = std::min(nb, aca_grid<T>(threads));
-  if (threads == 512)
-    hipLaunchKernelGGL((aca_kernel<T, 512>), dim3(grid), dim3(512), 0, s, d, order, nb, counter,
-                       X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
-                       gcap, gtop, gram, gram_min, scr, scr_cap);
+  // `gram` (when given) holds 2 ACA_GRAM_R^2 entries for each of aca_grid(threads, big)
+  // workgroups; blocks with m + n >= gram_min use the Gram matrices; arena > 0: slots placed in
+  // per-workgroup arenas of that many entries
+  const int grid = std::min(nb, aca_grid<T>(threads, big));
+#define HMX_ACA_LAUNCH(NT_, BIG_)                                                                \
+  hipLaunchKernelGGL((aca_kernel<T, NT_, BIG_>), dim3(grid), dim3(NT_), 0, s, d, order, nb,      \
+                     counter, X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, \
+                     gpool, gcap, gtop, gram, gram_min, arena)
+  if (big && threads == 512)
+    HMX_ACA_LAUNCH(512, true);
+  else if (big)
+    HMX_ACA_LAUNCH(256, true);
   else if (threads == 256)
-    hipLaunchKernelGGL((aca_kernel<T, 256>), dim3(grid), dim3(256), 0, s, d, order, nb, counter,
-                       X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
-                       gcap, gtop, gram, gram_min, scr, scr_cap);
+    HMX_ACA_LAUNCH(256, false);
   else if (threads == 128)
-    hipLaunchKernelGGL((aca_kernel<T, 128>), dim3(grid), dim3(128), 0, s, d, order, nb, counter,
-                       X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
-                       gcap, gtop, gram, gram_min, scr, scr_cap);
+    HMX_ACA_LAUNCH(128, false);
   else
-    hipLaunchKernelGGL((aca_kernel<T, 64>), dim3(grid), dim3(64), 0, s, d, order, nb, counter,
-                       X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool,
-                       gcap, gtop, gram, gram_min, scr, scr_cap);
+    HMX_ACA_LAUNCH(64, false);
+#undef HMX_ACA_LAUNCH
   HMX_LAUNCHED();
 }
 
@@ -848,12 +923,11 @@ void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int thre
                                    const double*, const double*, const double*, int,             \
                                    const double*, double, uint8_t*, int32_t*, int32_t*, int32_t*, double*, T*,  \
                                    int64_t, unsigned long long*, hipStream_t);                   \
-  template void launch_aca<T>(FarDesc*, const int32_t*, int, int*, int, const double*,           \
+  template void launch_aca<T>(FarDesc*, const int32_t*, int, int*, int, int, const double*,      \
                               const double*, const double*, const double*, int, const double*,   \
                               double, uint8_t*, int32_t*, int32_t*, int32_t*, double*, int, T*,  \
-                              int64_t, unsigned long long*, double2*, int, T*, int64_t,          \
-                              hipStream_t);                                                      \
-  template int aca_grid<T>(int);                                                                 \
+                              int64_t, unsigned long long*, double2*, int, int64_t, hipStream_t); \
+  template int aca_grid<T>(int, int);                                                            \
 
 HMX_INST(double2)
 HMX_INST(float2)

@@ -38,6 +38,8 @@ __global__ void __launch_bounds__(WG) far_desc_kernel(
   d.U = nullptr;
   d.V = nullptr;
   d.foff = 0;
+  d.ld = (int32_t)mn;
+  d.pad_ = 0;
   desc[b] = d;
   const bool w = d.m <= ACA_WAVE_N && d.n <= ACA_WAVE_N;
   wave[b] = w ? 1 : 0;
@@ -170,6 +172,8 @@ __global__ void __launch_bounds__(WG) far_rec_kernel(
     f.U = dense ? nullptr : d.U;
     f.V = dense ? nullptr : d.V;
     f.toff = 0;
+    f.ldu = dense ? d.m : d.ld;
+    f.ldv = dense ? d.n : d.ld;
     rec[b] = f;
     const int64_t mn = (int64_t)d.m + d.n, mxn = (int64_t)d.m * d.n;
     tcount[b] = dense ? d.n : r;

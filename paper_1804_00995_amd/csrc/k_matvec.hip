@@ -54,11 +54,12 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
   }
   const T* V = (const T*)f.V;
   const int n = f.n, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int64_t ldv = f.ldv;
   int l = w;
   for (; l + NWAVE < f.r; l += 2 * NWAVE) {
     T a0 = czero<T>(), a1 = czero<T>();
-    const T* v0 = V + (int64_t)l * n;
-    const T* v1 = V + (int64_t)(l + NWAVE) * n;
+    const T* v0 = V + l * ldv;
+    const T* v1 = V + (l + NWAVE) * ldv;
     for (int j = lane; j < n; j += WAVE) {
       T xj = xs[j];
       cfma(a0, v0[j], xj);
@@ -73,7 +74,7 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
   }
   for (; l < f.r; l += NWAVE) {
     T a0 = czero<T>();
-    const T* v0 = V + (int64_t)l * n;
+    const T* v0 = V + l * ldv;
     for (int j = lane; j < n; j += WAVE) cfma(a0, v0[j], xs[j]);
     a0 = wave_sum2(a0);
     if (lane == 0) tb[l] = a0;
@@ -133,7 +134,7 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
 #pragma unroll 4
       for (int l = 0; l < f.r; ++l) {
         const T tl = tt[l];
-        const T* col = U + (int64_t)l * f.m;
+        const T* col = U + (int64_t)l * f.ldu;
 #pragma unroll
         for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
           int i = lane + c * WAVE;

@@ -44,11 +44,12 @@ class Params(C.Structure):
         ("aca_gram_min_mn", C.c_int32),
         ("aca_serial", C.c_int32),
         ("aca_mid_threads", C.c_int32),
-        ("aca_scratch", C.c_int32),
+        ("aca_arena", C.c_int32),
         ("row_shares", C.c_int32),
         ("row_share", C.c_int32),
         ("force_pool_bytes", C.c_int64),
         ("max_far_mn", C.c_int32),
+        ("aca_big_threads", C.c_int32),
     ]
 
 

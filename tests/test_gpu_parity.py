@@ -196,9 +196,9 @@ def test_forced_dense_fallback(H):
 def test_overflow_continuation_identical(H):
     # a first rank slot of 1 makes nearly every block continue in a larger slot; the factors
     # must be those of a single uninterrupted run
-    opa, P, W = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=1, aca_scratch=0)
-    opb, _, _ = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=64, aca_scratch=0)
-    opc, _, _ = build(H, 3, kern=1, k=9.0, tol=1e-3)  # workgroup scratch, exact slots
+    opa, P, W = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=1, aca_arena=0)
+    opb, _, _ = build(H, 3, kern=1, k=9.0, tol=1e-3, initial_rank=64, aca_arena=0)
+    opc, _, _ = build(H, 3, kern=1, k=9.0, tol=1e-3)  # workgroup arenas, exact slots
     assert opa.info["overflow_blocks"] > 0
     x = I.complex_vector(P.shape[0], 4)
     ya = apply(opa, x)

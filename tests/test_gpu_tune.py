@@ -62,12 +62,14 @@ def test_autotune_choice_and_cache(H, sphere4, tmp_path):
     assert prm.aca_serial in (0, 1) and ms > 0
     assert prm.max_far_mn in (0, 32768, 16384, 8192)
     assert prm.aca_mid_threads in (256, 128, 64)
+    assert prm.aca_big_threads in (0, 512, 256)
     entries = json.loads(cache.read_text())
     assert len(entries) == 1
     (key, val), = entries.items()
     assert key.startswith("gfx") and f"|helmholtz|M2^{int(np.log2(P.shape[0]))}|tol1e-3|leaf64|" in key
     assert val["aca_big_mn"] == prm.aca_big_mn and val["aca_serial"] == prm.aca_serial
     assert val["max_far_mn"] == prm.max_far_mn
+    assert val["aca_big_threads"] == prm.aca_big_threads
     # a second call for the same class is answered from the cache, without builds
     t2 = time.perf_counter()
     prm2, ms2 = H.autotune(xyzw, kern=1, k=14.0, cache_path=str(cache))
