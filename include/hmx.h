@@ -108,6 +108,10 @@ typedef struct {
   int32_t aca_big_threads; /* workgroup size of the blocks with m + n >= aca_big_mn: 512 (one
                               workgroup per CU), 256 (two per CU) or 0 (default: 512 for FP64,
                               256 for FP32) */
+  int32_t aca_small_mn; /* >= 0 (default 1024): blocks with m + n below it (other than the
+                           wavefront blocks) run in 64-thread workgroups holding 256 ACA
+                           coefficients, many per CU, with direct cross sums whatever
+                           aca_gram_min_mn says; 0 puts them in the middle class */
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
@@ -196,16 +200,17 @@ hmx_status hmx_graph_launch(hmx_graph* g, int32_t reps, void* stream);
 void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
 
 /* Autotuner of the build schedule (max_far_mn, aca_big_mn, aca_gram_min_mn, aca_mid_threads,
- * aca_big_threads, aca_serial of hmx_params).  Times hmx_build_points(xyzw, M, kern, k) under a
- * grid of settings, each stage at the best of the previous ones: far-block bounds {none, 32768,
- * 16384, 8192}; class thresholds {2048, 4096, 8192, none} x Gram thresholds {0, 1024, 4096,
- * none} on concurrent streams; middle-class workgroups {256, 128, 64}; large-block workgroups
- * {512, 256}; serial classes; best of two builds each.  *out receives *p (defaults when
+ * aca_big_threads, aca_small_mn, aca_serial of hmx_params).  Times hmx_build_points(xyzw, M,
+ * kern, k) under a grid of settings, each stage at the best of the previous ones: far-block
+ * bounds {none, 32768, 16384, 8192}; class thresholds {2048, 4096, 8192, none} x Gram
+ * thresholds {0, 1024, 4096, none} on concurrent streams; middle-class workgroups {256, 128,
+ * 64}; large-block workgroups {512, 256}; small-block bounds {512, 2048, none}; serial classes;
+ * best of two builds each.  *out receives *p (defaults when
  * NULL) with the fastest settings, *best_ms (may be NULL) that build time in ms.
  * cache_path (host string, may be NULL): a JSON file of earlier choices keyed by device
  * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size and eta; a key
  * found there is returned without timing, a new one is added to the file.  Synchronous; builds
- * and frees up to 53 operators (26 settings, two builds each, one warm-up).  Errors: as
+ * and frees up to 59 operators (29 settings, two builds each, one warm-up).  Errors: as
  * hmx_build_points, HMX_EINVAL for tol <= 0 or an unwritable cache file. */
 hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
                         const hmx_params* p, const char* cache_path, void* stream,
@@ -226,13 +231,14 @@ typedef struct {
   int64_t factor_bytes;    /* device bytes of the slots holding far-block factors (used part) */
   int64_t predicted_entries; /* learned layout: sum of r_alloc * (m + n) over far blocks */
   /* ACA by block class: [0] m + n >= aca_big_mn (aca_big_threads-thread workgroups), [1] the
-   * other workgroup blocks (aca_mid_threads threads), [2] m, n <= 64 (one wavefront each).  aca_ms: duration of the class's
+   * other workgroup blocks (aca_mid_threads threads), [2] m, n <= 64 (one wavefront each), [3]
+   * m + n < aca_small_mn (64-thread workgroups).  aca_ms: duration of the class's
    * first launch (events on the stream it ran on); aca_bytes: bytes the method must move for
    * the class, es (m + n) r (r + 1) / 2 per block of final rank r (step k reads the k previous
    * columns of U and V once and writes one column pair; es = bytes of one complex entry). */
-  int64_t aca_blocks[3];
-  double aca_ms[3];
-  int64_t aca_bytes[3];
+  int64_t aca_blocks[4];
+  double aca_ms[4];
+  int64_t aca_bytes[4];
   int32_t aca_rounds; /* ACA launch rounds: 1 + continuation rounds (device pool exhausted) */
   int64_t row_begin, row_end; /* rows held, in cluster positions (all rows: 0, n_points) */
 } hmx_info_t;

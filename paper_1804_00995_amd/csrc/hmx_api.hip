@@ -60,6 +60,7 @@ void defaults(hmx_params* p) {
   p->aca_serial = 0;
   p->aca_mid_threads = 128;
   p->aca_big_threads = 0;
+  p->aca_small_mn = 1024;
   p->aca_arena = 1;
   p->row_shares = 1;
   p->row_share = 0;
@@ -99,6 +100,7 @@ hmx_params resolve(const hmx_params* in) {
   // 0: by precision (measured on the 245 760-point sphere: FP64 streams 16-byte factor entries
   // and runs best with one 512-thread workgroup per CU, FP32 with two 256-thread ones)
   if (p.aca_big_threads == 0) p.aca_big_threads = p.precision == HMX_FP64 ? 512 : 256;
+  HMX_REQUIRE(p.aca_small_mn >= 0, HMX_EINVAL, "aca_small_mn must be >= 0");
   HMX_REQUIRE(p.row_shares >= 1 && p.row_shares <= (1 << 20) &&
                   (p.row_shares & (p.row_shares - 1)) == 0,
               HMX_EINVAL, "row_shares must be a power of two in [1, 2^20]");
@@ -409,7 +411,7 @@ hmx_status hmx_info(const hmx_op* op, hmx_info_t* out) {
   out->kernel_evals = op->kernel_evals;
   out->factor_bytes = op->pool_used_bytes;
   out->predicted_entries = op->predicted_entries;
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < 4; ++c) {
     out->aca_blocks[c] = op->aca_blocks[c];
     out->aca_ms[c] = op->aca_ms[c];
     out->aca_bytes[c] = op->aca_bytes[c];

@@ -377,11 +377,12 @@ void build_far(hmx_op* op, hipStream_t s) {
     op->predicted_entries = total;
   }
   // launch order of the first round: by class, then by decreasing floor(log2(work))
-  const int64_t big_mn = op->p.aca_big_mn;
+  const int64_t big_mn = op->p.aca_big_mn, small_mn = op->p.aca_small_mn;
   DevBuf<int32_t> d_order(nf1);
   DevBuf<int> key_hist(FAR_ORDER_KEYS), key_cursor(FAR_ORDER_KEYS);
-  launch_far_order(d_desc.p, wave.p, work.p, nf, big_mn, key_hist.p, key_cursor.p, d_order.p, s);
-  int class_count[3] = {0, 0, 0};
+  launch_far_order(d_desc.p, wave.p, work.p, nf, big_mn, small_mn, key_hist.p, key_cursor.p,
+                   d_order.p, s);
+  int class_count[4] = {0, 0, 0, 0};
   {
     std::vector<int> hh;
     to_host(hh, key_hist.p, nf > 0 ? FAR_ORDER_KEYS : 0, s);
@@ -392,13 +393,16 @@ void build_far(hmx_op* op, hipStream_t s) {
   // workgroup may leave the unused rest of one arena, which the pool provides for
   const int mid_threads = op->p.aca_mid_threads;
   const int big_threads = op->p.aca_big_threads;
-  const int64_t grid_big = aca_grid<T>(big_threads, 1), grid_mid = aca_grid<T>(mid_threads, 0);
-  int64_t arena_big = 0, arena_mid = 0;
+  const int64_t grid_big = aca_grid<T>(big_threads, ACA_KIND_BIG);
+  const int64_t grid_mid = aca_grid<T>(mid_threads, ACA_KIND_MID);
+  const int64_t grid_small = aca_grid<T>(64, ACA_KIND_SMALL);
+  int64_t arena_big = 0, arena_mid = 0, arena_small = 0;
   if (op->p.aca_arena) {
-    const int64_t share = sum_mn / (4 * (grid_big + grid_mid));
+    const int64_t share = sum_mn / (4 * (grid_big + grid_mid + grid_small));
     arena_big = std::min<int64_t>(ACA_ARENA_BIG, std::max<int64_t>(share, 1));
     arena_mid = std::min<int64_t>(ACA_ARENA_MID, std::max<int64_t>(share, 1));
-    sum_mn += grid_big * arena_big + grid_mid * arena_mid;
+    arena_small = std::min<int64_t>(ACA_ARENA_SMALL, std::max<int64_t>(share, 1));
+    sum_mn += grid_big * arena_big + grid_mid * arena_mid + grid_small * arena_small;
   }
   // device pool for factor slots, within the free memory
   size_t free_b = 0, total_b = 0;
@@ -441,19 +445,23 @@ void build_far(hmx_op* op, hipStream_t s) {
   HMX_HIP(hipEventCreateWithFlags(&ev_d2, hipEventDisableTiming));
   HMX_HIP(hipEventCreateWithFlags(&ev_d3, hipEventDisableTiming));
   // timing of each class's first launch, on the stream it runs on
-  hipEvent_t tev[6] = {};
+  hipEvent_t tev[8] = {};
   struct EventGuard {
     hipEvent_t* e;
     ~EventGuard() {
-      for (int i = 0; i < 6; ++i)
+      for (int i = 0; i < 8; ++i)
         if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } tguard{tev};
   for (auto& e : tev) HMX_HIP(hipEventCreate(&e));
-  // Gram scratch of the two workgroup classes (first launch only)
-  const int64_t gram_per_wg = 2 * (int64_t)ACA_GRAM_R * ACA_GRAM_R;  // the larger order
-  DevBuf<double2> gram_big((size_t)grid_big * gram_per_wg);
-  DevBuf<double2> gram_mid((size_t)grid_mid * gram_per_wg);
+  // Gram scratch of the three workgroup classes: 2 order^2 entries per workgroup
+  auto gram_entries = [](int64_t grid, int threads, int kind) {
+    const int64_t g = aca_gram_order(threads, kind);
+    return (size_t)(grid * 2 * g * g);
+  };
+  DevBuf<double2> gram_big(gram_entries(grid_big, big_threads, ACA_KIND_BIG));
+  DevBuf<double2> gram_mid(gram_entries(grid_mid, mid_threads, ACA_KIND_MID));
+  DevBuf<double2> gram_small(gram_entries(grid_small, 64, ACA_KIND_SMALL));
   // blocks below aca_gram_min_mn take the direct cross sums (fewer barriers per step)
   const int gram_min = op->p.aca_gram_min_mn;
 
@@ -461,11 +469,12 @@ void build_far(hmx_op* op, hipStream_t s) {
   std::vector<FarDesc> desc;
   std::vector<uint8_t> is_wave;
   std::vector<int64_t> est, hwork;
-  // run ACA with the classes of (nbig, nmid, nsmall) blocks laid out in that order in d_order:
-  // m + n >= aca_big_mn in aca_big_threads-thread workgroups (stream s2), m, n <= ACA_WAVE_N one per
-  // wavefront (stream s3, blocks that have not started), the others in aca_mid_threads-thread
-  // workgroups (stream s)
-  auto launch_round = [&](int nbig, int nmid, int nsmall, int fresh) {
+  // run ACA with the classes of (nbig, nmid, nwave, nsmall) blocks laid out in that order in
+  // d_order: m + n >= aca_big_mn in aca_big_threads-thread workgroups (stream s2), m, n <=
+  // ACA_WAVE_N one per wavefront (stream s3, blocks that have not started), then the small
+  // blocks (m + n < aca_small_mn) in 64-thread workgroups (stream s3), the others in
+  // aca_mid_threads-thread workgroups (stream s)
+  auto launch_round = [&](int nbig, int nmid, int nwave, int nsmall, int fresh) {
     fill_i32(counter.p, 0, 3, s);
     // aca_serial = 1 runs the classes one after the other on `s` (same work; also used to time
     // each class on its own)
@@ -476,17 +485,23 @@ void build_far(hmx_op* op, hipStream_t s) {
     HMX_HIP(hipStreamWaitEvent(s2, ev_ready, 0));
     HMX_HIP(hipStreamWaitEvent(s3, ev_ready, 0));
     if (fresh) HMX_HIP(hipEventRecord(tev[0], s2));
-    launch_aca<T>(d_desc.p, d_order.p, nbig, counter.p, big_threads, 1, op->X.p, op->Y.p, op->Z.p,
+    launch_aca<T>(d_desc.p, d_order.p, nbig, counter.p, big_threads, ACA_KIND_BIG, op->X.p, op->Y.p, op->Z.p,
                   op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p,
                   fresh, gpool.p, gcap, gtop.p, gram_big.p, gram_min, arena_big, s2);
     if (fresh) HMX_HIP(hipEventRecord(tev[1], s2));
     if (fresh) HMX_HIP(hipEventRecord(tev[4], s3));
-    launch_aca_wave<T>(d_desc.p, d_order.p + nbig + nmid, nsmall, op->X.p,
+    launch_aca_wave<T>(d_desc.p, d_order.p + nbig + nmid, nwave, op->X.p,
                        op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p,
                        ipiv.p, status.p, norm2.p, gpool.p, gcap, gtop.p, s3);
     if (fresh) HMX_HIP(hipEventRecord(tev[5], s3));
+    if (fresh) HMX_HIP(hipEventRecord(tev[6], s3));
+    launch_aca<T>(d_desc.p, d_order.p + nbig + nmid + nwave, nsmall, counter.p + 2, 64,
+                  ACA_KIND_SMALL, op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p,
+                  op->p.tol, flags.p, rank.p, ipiv.p, status.p, norm2.p, fresh, gpool.p, gcap,
+                  gtop.p, gram_small.p, gram_min, arena_small, s3);
+    if (fresh) HMX_HIP(hipEventRecord(tev[7], s3));
     if (fresh) HMX_HIP(hipEventRecord(tev[2], s));
-    launch_aca<T>(d_desc.p, d_order.p + nbig, nmid, counter.p + 1, mid_threads, 0,
+    launch_aca<T>(d_desc.p, d_order.p + nbig, nmid, counter.p + 1, mid_threads, ACA_KIND_MID,
                   op->X.p,
                   op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, op->p.tol, flags.p, rank.p, ipiv.p,
                   status.p, norm2.p, fresh, gpool.p, gcap, gtop.p, gram_mid.p, gram_min, arena_mid,
@@ -501,30 +516,33 @@ void build_far(hmx_op* op, hipStream_t s) {
   // a later round: the listed blocks ordered on the host like the first round, with the
   // wavefront class for the blocks that have not started (`started`: ranks before the round)
   auto run_list = [&](const std::vector<int32_t>& list, const std::vector<int32_t>& started) {
-    std::vector<int32_t> bucket[3][64];
+    std::vector<int32_t> bucket[4][64];
     for (int32_t b : list) {
       const FarDesc& d = desc[b];
       const int64_t mn = (int64_t)d.m + d.n;
-      const int cls = mn >= big_mn ? 0 : (started[b] == 0 && is_wave[b]) ? 2 : 1;
+      const int cls = mn >= big_mn                        ? 0
+                      : (started[b] == 0 && is_wave[b])   ? 2
+                      : (mn < small_mn && d.rcap <= ACA_COEF_SMALL) ? 3
+                                                          : 1;
       const int lw = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(hwork[b], 1));
       bucket[cls][63 - lw].push_back(b);
     }
     std::vector<int32_t> ord;
-    int cnt[3] = {0, 0, 0};
-    for (int c = 0; c < 3; ++c)
+    int cnt[4] = {0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c)
       for (int q = 0; q < 64; ++q) {
         ord.insert(ord.end(), bucket[c][q].begin(), bucket[c][q].end());
         cnt[c] += (int)bucket[c][q].size();
       }
     if (!ord.empty())
       HMX_HIP(hipMemcpyAsync(d_order.p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, s));
-    launch_round(cnt[0], cnt[1], cnt[2], 0);
+    launch_round(cnt[0], cnt[1], cnt[2], cnt[3], 0);
   };
   {
     wl("first launch start");
-    launch_round(class_count[0], class_count[1], class_count[2], 1);
+    launch_round(class_count[0], class_count[1], class_count[2], class_count[3], 1);
     wl("first launch done");
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 4; ++c) {
       float ms = 0.f;
       HMX_HIP(hipEventElapsedTime(&ms, tev[2 * c], tev[2 * c + 1]));
       op->aca_ms[c] = ms;
@@ -601,7 +619,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   DevBuf<int> bad(1);
   fill_i64((int64_t*)stats.p, 0, FAR_STATS, s);
   fill_i32(bad.p, 0, 1, s);
-  launch_far_rec(d_desc.p, rank.p, status.p, d_cont.p, wave.p, big_mn, (int)sizeof(T), nf,
+  launch_far_rec(d_desc.p, rank.p, status.p, d_cont.p, wave.p, big_mn, small_mn, (int)sizeof(T), nf,
                  op->far.p, tcnt.p, dcnt.p, dflg.p, stats.p, bad.p, s);
   scan_excl_i64(tcnt.p, toff.p, nf, s);
   scan_excl_i64(dcnt.p, doff.p, nf, s);
@@ -631,9 +649,9 @@ void build_far(hmx_op* op, hipStream_t s) {
   // per class: blocks, and the bytes ACA must move: step k reads the k previous columns of U
   // and V once (residual row and column) and writes one column pair, so a block of final rank r
   // moves es (m + n) r (r + 1) / 2 bytes
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < 4; ++c) {
     op->aca_blocks[c] = (int64_t)h.st[7 + c];
-    op->aca_bytes[c] = (int64_t)h.st[10 + c];
+    op->aca_bytes[c] = (int64_t)h.st[11 + c];
   }
   op->t_len = h.t_len;
   op->pool_used_bytes = (std::min(h.used, gcap) + used_old) * (int64_t)sizeof(T);

@@ -119,6 +119,10 @@ struct FarRec {
 };
 
 constexpr int ACA_COEF_MAX = 1024;  // largest ACA rank (coefficients of a step held in LDS)
+// The small-block class (m + n below aca_small_mn, not a wavefront block) keeps at most this
+// many coefficients: its blocks have rank cap floor(m n / (m + n)) <= (m + n) / 4 <= 256 for
+// m + n < 1024, and only blocks with rank cap <= ACA_COEF_SMALL are placed in the class.
+constexpr int ACA_COEF_SMALL = 256;
 enum AcaStatus : int32_t { ACA_RUNNING = 0, ACA_CONVERGED = 1, ACA_OVERFLOW = 2, ACA_DENSE = 3 };
 // added to a block's saved status word once ACA has moved it to a larger pool slot
 constexpr int32_t ACA_GREW = 0x100;
@@ -196,7 +200,7 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
                      hipStream_t s);
 // k_aca.hip
 template <class T>
-void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads, int big,
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads, int kind,
                 const double* X, const double* Y, const double* Z, const double* W, int kern,
                 const double* kp, double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv,
                 int32_t* status, double* norm2, int fresh, T* gpool, int64_t gcap,
@@ -205,14 +209,22 @@ void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int thre
 // arena size (entries) of a workgroup of the large-block and of the smaller ACA kernels
 constexpr int64_t ACA_ARENA_BIG = int64_t(1) << 20;
 constexpr int64_t ACA_ARENA_MID = int64_t(1) << 16;
-// workgroups of the persistent grid of the ACA kernel with `threads` threads (big: the
-// large-block class, 512 or 256; else 256, 128 or 64)
+constexpr int64_t ACA_ARENA_SMALL = int64_t(1) << 15;
+// ACA workgroup kinds: the middle class (256, 128 or 64 threads), the large-block class (512 or
+// 256 threads) and the small-block class (64 threads, ACA_COEF_SMALL coefficients)
+enum AcaKind : int { ACA_KIND_MID = 0, ACA_KIND_BIG = 1, ACA_KIND_SMALL = 2 };
+// workgroups of the persistent grid of the ACA kernel of this kind and size
 template <class T>
-int aca_grid(int threads, int big);
-// Gram-matrix order per workgroup of the 512- and the 256-thread ACA kernels (steps past it use
-// direct cross sums); a workgroup's Gram scratch holds 2 ACA_GRAM_R^2 entries of the larger
+int aca_grid(int threads, int kind);
+// Gram-matrix order per workgroup of the large-block and the middle ACA kernels (steps past it
+// use direct cross sums)
 constexpr int ACA_GRAM_R = 256;
 constexpr int ACA_GRAM_R_MID = 128;
+// order of a kind's per-workgroup Gram matrices (one row per thread, at most the workgroup
+// size); a workgroup's Gram scratch holds 2 order^2 FP64 complex entries
+constexpr int aca_gram_order(int threads, int kind) {
+  return kind == ACA_KIND_BIG ? ACA_GRAM_R : threads >= 128 ? ACA_GRAM_R_MID : threads;
+}
 constexpr int ACA_BIG = 4096;  // block size (m + n) from which first rank slots are enlarged
 constexpr int ACA_WAVE_N = 64; // blocks with m, n <= ACA_WAVE_N run one per wavefront
 constexpr int ACA_WAVE_RC = 16; // terms a wavefront block holds in registers
@@ -249,13 +261,15 @@ void launch_far_desc(const int2* pairs, int64_t nf, const int32_t* nbegin, const
 void launch_far_foff(FarDesc* desc, const int64_t* foff, int64_t nf, hipStream_t s);
 void launch_far_pred(const float* pred, const FarDesc* desc, int64_t nf, double alpha,
                      int64_t beta, double scale, int64_t* ramn, int64_t* work, hipStream_t s);
-constexpr int FAR_ORDER_KEYS = 3 * 64;  // class * 64 + (63 - floor(log2 work))
+constexpr int FAR_ORDER_KEYS = 4 * 64;  // class * 64 + (63 - floor(log2 work))
 void launch_far_order(const FarDesc* desc, const uint8_t* wave, const int64_t* work, int64_t nf,
-                      int64_t big_mn, int* hist, int* cursor, int32_t* order, hipStream_t s);
+                      int64_t big_mn, int64_t small_mn, int* hist, int* cursor, int32_t* order,
+                      hipStream_t s);
 void launch_count_status(const int32_t* status, int64_t nf, int code, int* count, hipStream_t s);
-constexpr int FAR_STATS = 13;
+constexpr int FAR_STATS = 15;
 void launch_far_rec(const FarDesc* desc, const int32_t* rank, const int32_t* status,
-                    const uint8_t* continued, const uint8_t* wave, int64_t big_mn, int es,
+                    const uint8_t* continued, const uint8_t* wave, int64_t big_mn,
+                    int64_t small_mn, int es,
                     int64_t nf, FarRec* rec, int64_t* tcount, int64_t* dcount, int64_t* dflag,
                     unsigned long long* stats, int* bad, hipStream_t s);
 template <class T>
@@ -328,8 +342,8 @@ struct hmx_op {
   // build statistics
   double t_tree = 0, t_blocks = 0, t_near = 0, t_aca = 0, t_total = 0;
   // ACA by block class (0: m + n >= aca_big_mn, 1: other workgroup blocks, 2: wavefront blocks)
-  int64_t aca_blocks[3] = {0, 0, 0}, aca_bytes[3] = {0, 0, 0};
-  double aca_ms[3] = {0, 0, 0};
+  int64_t aca_blocks[4] = {0, 0, 0, 0}, aca_bytes[4] = {0, 0, 0, 0};
+  double aca_ms[4] = {0, 0, 0, 0};
   int32_t aca_rounds = 0;
   int64_t kernel_evals = 0;
   int64_t bytes() const;

@@ -20,7 +20,7 @@
 namespace {
 
 struct Choice {
-  int big = 4096, gram = 1024, serial = 0, maxmn = 16384, mid = 128, bigt = 0;
+  int big = 4096, gram = 1024, serial = 0, maxmn = 16384, mid = 128, bigt = 0, small = 1024;
   double ms = 0.0;
 };
 
@@ -44,7 +44,7 @@ std::string class_key(int64_t M, int32_t kern, const hmx_params& p) {
 
 // The cache file is one JSON object of entries
 //   "key": {"max_far_mn": N, "aca_big_mn": N, "aca_gram_min_mn": N, "aca_mid_threads": N,
-//           "aca_big_threads": N, "aca_serial": N, "ms": X}
+//           "aca_big_threads": N, "aca_small_mn": N, "aca_serial": N, "ms": X}
 // written by this file; the reader accepts exactly that shape.
 double field(const std::string& body, const char* name, double dflt) {
   const std::string pat = std::string("\"") + name + "\":";
@@ -78,6 +78,7 @@ std::map<std::string, Choice> read_cache(const char* path) {
     c.maxmn = (int)field(body, "max_far_mn", 16384);
     c.mid = (int)field(body, "aca_mid_threads", 128);
     c.bigt = (int)field(body, "aca_big_threads", 0);
+    c.small = (int)field(body, "aca_small_mn", 1024);
     c.ms = field(body, "ms", 0.0);
     out[key] = c;
     pos = b1 + 1;
@@ -97,10 +98,10 @@ void write_cache(const char* path, const std::map<std::string, Choice>& m) {
       char buf[320];
       std::snprintf(buf, sizeof(buf),
                     "{\"max_far_mn\": %d, \"aca_big_mn\": %d, \"aca_gram_min_mn\": %d, "
-                    "\"aca_mid_threads\": %d, \"aca_big_threads\": %d, \"aca_serial\": %d, "
-                    "\"ms\": %.3f}",
+                    "\"aca_mid_threads\": %d, \"aca_big_threads\": %d, \"aca_small_mn\": %d, "
+                    "\"aca_serial\": %d, \"ms\": %.3f}",
                     kv.second.maxmn, kv.second.big, kv.second.gram, kv.second.mid, kv.second.bigt,
-                    kv.second.serial, kv.second.ms);
+                    kv.second.small, kv.second.serial, kv.second.ms);
       f << "  \"" << kv.first << "\": " << buf << (++i < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -151,22 +152,24 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
       best = hit->second;
     } else {
       // the far-block size bound first (default schedule), then the class thresholds
-      // (concurrent classes), the two workgroup sizes, then serial vs concurrent at the best
+      // (concurrent classes), the two workgroup sizes, the small-block bound, then serial vs
+      // concurrent at the best
       const int maxmns[] = {0, 32768, 16384, 8192};
       const int bigs[] = {2048, 4096, 8192, 1 << 30};
       const int grams[] = {0, 1024, 4096, 1 << 30};
       const int mids[] = {256, 128, 64};
       const int bigts[] = {512, 256};
+      const int smalls[] = {512, 2048, 0};
       hmx_params q = base;
       q.aca_serial = 0;
       (void)time_build(xyzw, M, kern, k, q, stream, 1);  // warm the allocator and the code
       best = Choice{q.aca_big_mn, q.aca_gram_min_mn, 0, q.max_far_mn, q.aca_mid_threads,
-                    q.aca_big_threads, 1e300};
+                    q.aca_big_threads, q.aca_small_mn, 1e300};
       auto trial = [&](const hmx_params& t) {
         const double ms = time_build(xyzw, M, kern, k, t, stream, 2);
         if (ms < best.ms)
           best = Choice{t.aca_big_mn, t.aca_gram_min_mn, t.aca_serial, t.max_far_mn,
-                        t.aca_mid_threads, t.aca_big_threads, ms};
+                        t.aca_mid_threads, t.aca_big_threads, t.aca_small_mn, ms};
       };
       for (int mx : maxmns) {
         q.max_far_mn = mx;
@@ -191,6 +194,11 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
         trial(q);
       }
       q.aca_big_threads = best.bigt;
+      for (int sm : smalls) {
+        q.aca_small_mn = sm;
+        trial(q);
+      }
+      q.aca_small_mn = best.small;
       q.aca_serial = 1;
       trial(q);
       cache[key] = best;
@@ -203,6 +211,7 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
     out->max_far_mn = best.maxmn;
     out->aca_mid_threads = best.mid;
     out->aca_big_threads = best.bigt;
+    out->aca_small_mn = best.small;
     if (best_ms) *best_ms = best.ms;
     return HMX_OK;
   } catch (const hmx::Error& e) {

@@ -43,11 +43,13 @@
 namespace hmx {
 
 
+// Workgroup state in LDS; NW wavefronts, Gram order GR.
+template <int NW, int GR>
 struct AcaShared {
   double sv[16];
   int si[16];
-  double ssum[32 * 9];  // block_sum scratch: N * (NT / 64 + 1) for N <= 32, NT <= 512
-  double2 h[ACA_GRAM_R];  // per previous term: v_l^H (row residual) or u_l^H (column residual)
+  double ssum[32 * (NW + 1)];  // block_sum scratch: N (NW + 1) doubles for N <= 32
+  double2 h[GR];  // per previous term: v_l^H (row residual) or u_l^H (column residual)
   int64_t off;
   int q;
 };
@@ -86,7 +88,7 @@ __device__ __forceinline__ P* ufl(P* p) {
   return (P*)(uintptr_t)ufl((int64_t)(uintptr_t)p);
 }
 
-template <class T, int NT, bool BIG, int RL>
+template <class T, int NT, bool BIG, int RL, int CO, class Sh>
 __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __restrict__ X,
                           const double* __restrict__ Y, const double* __restrict__ Z,
                           const double* __restrict__ W, int kern, const double* kp, double tol,
@@ -94,14 +96,17 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
                           double* norm2, int fresh, T* gpool, int64_t gcap,
                           unsigned long long* gtop, double2* gram, int gram_min, int64_t arena,
                           int64_t& a_top, int64_t& a_end, T* coef, HMX_LDS T* rbuf,
-                          AcaShared& sh) {
+                          Sh& sh) {
   constexpr int GW = BIG ? (sizeof(T) == 16 ? 6 : 8) : 4;  // terms per Gram window
   constexpr int JW = BIG ? (sizeof(T) == 16 ? 2 : 4) : 1;  // elements per thread per window round
   constexpr int JC = 1;                  // elements per thread per round
   constexpr int LU = BIG ? 8 : 4;  // previous terms loaded per round (loads in flight)
   const int tid = threadIdx.x;
   const FarDesc d = descs[b];
-  const int m = ufl(d.m), n = ufl(d.n), tb = ufl(d.tb), sb = ufl(d.sb), rcap = ufl(d.rcap);
+  const int m = ufl(d.m), n = ufl(d.n), tb = ufl(d.tb), sb = ufl(d.sb);
+  // CO coefficients in LDS bound the rank (the host places only blocks with rank cap <= CO in a
+  // kind with CO < ACA_COEF_MAX; the bound only guards the coefficient array)
+  const int rcap = min(ufl(d.rcap), CO);
   const double k = kp[tb];  // wavenumber of the block's mesh
   // factor slots are device memory: global-address-space pointers (the slot addresses come from
   // the descriptor in memory, where the compiler cannot infer the space), so that their loads do
@@ -135,11 +140,14 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   //   v_l^H R = v_l^H R' - sum_{p in and after l's window} u_p[i_k] GV[l][p],
   // R' the residual before l's window, so the previous columns are read once per step.  Ranks
   // past GR and blocks below gram_min take the direct sums instead.
-  constexpr int GR = BIG ? ACA_GRAM_R : NT >= 128 ? ACA_GRAM_R_MID : NT;  // Gram order <= NT
+  constexpr int GR = aca_gram_order(NT, BIG ? ACA_KIND_BIG : ACA_KIND_MID);  // Gram order
   static_assert(GR <= NT, "one Gram row per thread");
   double2* GV = gram;
   double2* GU = gram ? gram + GR * GR : nullptr;
-  bool use_gram = gram != nullptr && m + n >= gram_min && kk < GR;
+  // (the small-block kind, CO < ACA_COEF_MAX, always takes the direct sums: its blocks lie below
+  // the Gram threshold's useful range, and without that code it holds fewer registers and more
+  // workgroups per CU)
+  bool use_gram = CO >= ACA_COEF_MAX && gram != nullptr && m + n >= gram_min && kk < GR;
   if (use_gram && !fresh && kk > 0) {
     // a block resumed from its saved state: rebuild the Gram matrices of its factors (one
     // wavefront per entry pair)
@@ -632,8 +640,9 @@ constexpr int aca_rl() {
   return !BIG ? 0 : NT >= 512 ? (sizeof(T) == 16 ? 7680 : 15360) : (sizeof(T) == 16 ? 3584 : 8192);
 }
 
-// BIG: the large-block class (long Gram windows, two waves per SIMD, LDS residual)
-template <class T, int NT, bool BIG>
+// BIG: the large-block class (long Gram windows, two waves per SIMD, LDS residual); CO: the
+// coefficient capacity (ACA_COEF_SMALL for the small-block class)
+template <class T, int NT, bool BIG, int CO = ACA_COEF_MAX>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BIG ? 2 : 3))) aca_kernel(FarDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order, int nb,
                                                  int* counter, const double* __restrict__ X,
@@ -646,10 +655,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BIG ? 2
                                                  unsigned long long* gtop, double2* gram,
                                                  int gram_min, int64_t arena) {
   constexpr int RL = aca_rl<T, NT, BIG>();
-  __shared__ T coef[ACA_COEF_MAX];
+  constexpr int GR = aca_gram_order(NT, BIG ? ACA_KIND_BIG : ACA_KIND_MID);
+  __shared__ T coef[CO];
   __shared__ T rbuf[RL > 0 ? RL : 1];
-  __shared__ AcaShared sh;
-  double2* my_gram = gram ? gram + (int64_t)blockIdx.x * 2 * ACA_GRAM_R * ACA_GRAM_R : nullptr;
+  __shared__ AcaShared<NT / WAVE, GR> sh;
+  double2* my_gram = gram ? gram + (int64_t)blockIdx.x * 2 * GR * GR : nullptr;
   int64_t a_top = 0, a_end = 0;  // this workgroup's arena: free entries [a_top, a_end) of gpool
   for (;;) {
     if (threadIdx.x == 0) sh.q = atomicAdd(counter, 1);
@@ -657,7 +667,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BIG ? 2
     const int q = ufl(sh.q);
     __syncthreads();
     if (q >= nb) break;
-    aca_block<T, NT, BIG, RL>(desc, ufl(order[q]), X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status,
+    aca_block<T, NT, BIG, RL, CO>(desc, ufl(order[q]), X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status,
                          norm2, fresh, gpool, gcap, gtop, my_gram, gram_min, arena, a_top, a_end, coef,
                          (HMX_LDS T*)rbuf, sh);
   }
@@ -868,52 +878,59 @@ void launch_aca_wave(FarDesc* d, const int32_t* order, int nb, const double* X,
   HMX_LAUNCHED();
 }
 
-// Workgroups of a persistent ACA grid (big: the large-block class, 512 or 256 threads; else 256,
-// 128 or 64 threads): as many as can be resident at once.
+// Workgroups of a persistent ACA grid of one kind (ACA_KIND_BIG: 512 or 256 threads;
+// ACA_KIND_MID: 256, 128 or 64; ACA_KIND_SMALL: 64): as many as can be resident at once.
 template <class T>
-int aca_grid(int threads, int big) {
+int aca_grid(int threads, int kind) {
   int dev = 0, ncu = 0, occ = 0;
   HMX_HIP(hipGetDevice(&dev));
   HMX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  if (big && threads == 512)
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 512, true>, 512, 0));
-  else if (big)
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 256, true>, 256, 0));
+#define HMX_ACA_OCC(...) \
+  HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, __VA_ARGS__, threads, 0))
+  if (kind == ACA_KIND_SMALL)
+    HMX_ACA_OCC(aca_kernel<T, 64, false, ACA_COEF_SMALL>);
+  else if (kind == ACA_KIND_BIG && threads == 512)
+    HMX_ACA_OCC(aca_kernel<T, 512, true>);
+  else if (kind == ACA_KIND_BIG)
+    HMX_ACA_OCC(aca_kernel<T, 256, true>);
   else if (threads == 256)
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 256, false>, 256, 0));
+    HMX_ACA_OCC(aca_kernel<T, 256, false>);
   else if (threads == 128)
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 128, false>, 128, 0));
+    HMX_ACA_OCC(aca_kernel<T, 128, false>);
   else
-    HMX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, aca_kernel<T, 64, false>, 64, 0));
+    HMX_ACA_OCC(aca_kernel<T, 64, false>);
+#undef HMX_ACA_OCC
   return std::max(1, occ) * ncu;
 }
 
 template <class T>
-void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads, int big,
+void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads, int kind,
                 const double* X, const double* Y, const double* Z, const double* W, int kern,
                 const double* kp, double tol, uint8_t* flags, int32_t* rank, int32_t* ipiv,
                 int32_t* status, double* norm2, int fresh, T* gpool, int64_t gcap,
                 unsigned long long* gtop, double2* gram, int gram_min, int64_t arena,
                 hipStream_t s) {
   if (nb <= 0) return;
-  // `gram` (when given) holds 2 ACA_GRAM_R^2 entries for each of aca_grid(threads, big)
-  // workgroups; blocks with m + n >= gram_min use the Gram matrices; arena > 0: slots placed in
-  // per-workgroup arenas of that many entries
-  const int grid = std::min(nb, aca_grid<T>(threads, big));
-#define HMX_ACA_LAUNCH(NT_, BIG_)                                                                \
-  hipLaunchKernelGGL((aca_kernel<T, NT_, BIG_>), dim3(grid), dim3(NT_), 0, s, d, order, nb,      \
-                     counter, X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, \
-                     gpool, gcap, gtop, gram, gram_min, arena)
-  if (big && threads == 512)
-    HMX_ACA_LAUNCH(512, true);
-  else if (big)
-    HMX_ACA_LAUNCH(256, true);
+  // `gram` (when given) holds 2 aca_gram_order(threads, kind)^2 entries for each of
+  // aca_grid(threads, kind) workgroups; blocks with m + n >= gram_min use the Gram matrices;
+  // arena > 0: slots placed in per-workgroup arenas of that many entries
+  const int grid = std::min(nb, aca_grid<T>(threads, kind));
+#define HMX_ACA_LAUNCH(NT_, ...)                                                                 \
+  hipLaunchKernelGGL((__VA_ARGS__), dim3(grid), dim3(NT_), 0, s, d, order, nb, counter, X, Y, Z, \
+                     W, kern, kp, tol, flags, rank, ipiv, status, norm2, fresh, gpool, gcap,     \
+                     gtop, gram, gram_min, arena)
+  if (kind == ACA_KIND_SMALL)
+    HMX_ACA_LAUNCH(64, aca_kernel<T, 64, false, ACA_COEF_SMALL>);
+  else if (kind == ACA_KIND_BIG && threads == 512)
+    HMX_ACA_LAUNCH(512, aca_kernel<T, 512, true>);
+  else if (kind == ACA_KIND_BIG)
+    HMX_ACA_LAUNCH(256, aca_kernel<T, 256, true>);
   else if (threads == 256)
-    HMX_ACA_LAUNCH(256, false);
+    HMX_ACA_LAUNCH(256, aca_kernel<T, 256, false>);
   else if (threads == 128)
-    HMX_ACA_LAUNCH(128, false);
+    HMX_ACA_LAUNCH(128, aca_kernel<T, 128, false>);
   else
-    HMX_ACA_LAUNCH(64, false);
+    HMX_ACA_LAUNCH(64, aca_kernel<T, 64, false>);
 #undef HMX_ACA_LAUNCH
   HMX_LAUNCHED();
 }

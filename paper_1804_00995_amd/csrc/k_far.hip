@@ -76,15 +76,21 @@ __global__ void __launch_bounds__(WG) far_pred_kernel(const float* __restrict__ 
   work[b] = r1 * r1 * mn;
 }
 
-// Launch order: key = class * 64 + (63 - floor(log2 work)), class 0 for m + n >= big_mn, 2 for
-// wavefront blocks, 1 otherwise; blocks are counted per key, the counts scanned, and each block
-// placed in its key's range (order inside a key is arbitrary).
+// ACA class of a block that has not started: 0 for m + n >= big_mn, 2 for wavefront blocks, 3
+// for m + n < small_mn with rank cap <= ACA_COEF_SMALL, 1 otherwise.
+__device__ __forceinline__ int far_class(const FarDesc& d, uint8_t wave, int64_t big_mn,
+                                         int64_t small_mn) {
+  const int64_t mn = (int64_t)d.m + d.n;
+  return mn >= big_mn ? 0 : wave ? 2 : (mn < small_mn && d.rcap <= ACA_COEF_SMALL) ? 3 : 1;
+}
+
+// Launch order: key = class * 64 + (63 - floor(log2 work)); blocks are counted per key, the
+// counts scanned, and each block placed in its key's range (order inside a key is arbitrary).
 constexpr int ORDER_KEYS = FAR_ORDER_KEYS;
 
 __device__ __forceinline__ int far_key(const FarDesc& d, uint8_t wave, int64_t work,
-                                       int64_t big_mn) {
-  const int64_t mn = (int64_t)d.m + d.n;
-  const int cls = mn >= big_mn ? 0 : wave ? 2 : 1;
+                                       int64_t big_mn, int64_t small_mn) {
+  const int cls = far_class(d, wave, big_mn, small_mn);
   const int lw = 63 - __clzll((unsigned long long)(work > 1 ? work : 1));
   return cls * 64 + (63 - lw);
 }
@@ -93,12 +99,13 @@ __global__ void __launch_bounds__(WG) far_key_hist_kernel(const FarDesc* __restr
                                                           const uint8_t* __restrict__ wave,
                                                           const int64_t* __restrict__ work,
                                                           int64_t nf, int64_t big_mn,
+                                                          int64_t small_mn,
                                                           int* __restrict__ hist) {
   __shared__ int lh[ORDER_KEYS];
   for (int q = threadIdx.x; q < ORDER_KEYS; q += WG) lh[q] = 0;
   __syncthreads();
   const int64_t b = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (b < nf) atomicAdd(&lh[far_key(desc[b], wave[b], work[b], big_mn)], 1);
+  if (b < nf) atomicAdd(&lh[far_key(desc[b], wave[b], work[b], big_mn, small_mn)], 1);
   __syncthreads();
   for (int q = threadIdx.x; q < ORDER_KEYS; q += WG)
     if (lh[q]) atomicAdd(&hist[q], lh[q]);
@@ -123,6 +130,7 @@ __global__ void __launch_bounds__(WG) far_key_scatter_kernel(const FarDesc* __re
                                                              const uint8_t* __restrict__ wave,
                                                              const int64_t* __restrict__ work,
                                                              int64_t nf, int64_t big_mn,
+                                                             int64_t small_mn,
                                                              int* __restrict__ cursor,
                                                              int32_t* __restrict__ order) {
   __shared__ int lh[ORDER_KEYS], base[ORDER_KEYS];
@@ -131,7 +139,7 @@ __global__ void __launch_bounds__(WG) far_key_scatter_kernel(const FarDesc* __re
   const int64_t b = (int64_t)blockIdx.x * WG + threadIdx.x;
   int key = 0, local = 0;
   if (b < nf) {
-    key = far_key(desc[b], wave[b], work[b], big_mn);
+    key = far_key(desc[b], wave[b], work[b], big_mn, small_mn);
     local = atomicAdd(&lh[key], 1);
   }
   __syncthreads();
@@ -146,12 +154,12 @@ __global__ void __launch_bounds__(WG) far_key_scatter_kernel(const FarDesc* __re
 // block, dflag = 1 for a dense block; stats (int64 atomics): [0] far entries sum r (m + n),
 // [1] sum of ranks, [2] max rank, [3] dense blocks, [4] dense entries, [5] blocks that moved to a
 // larger slot or were continued in a later round, [6] kernel evaluations, [7 + c] blocks of
-// first-launch class c, [10 + c] bytes ACA must move in class c: es (m + n) r (r + 1) / 2 per
+// first-launch class c, [11 + c] bytes ACA must move in class c: es (m + n) r (r + 1) / 2 per
 // block (step k reads the k previous columns of U and V once and writes one column pair).
 __global__ void __launch_bounds__(WG) far_rec_kernel(
     const FarDesc* __restrict__ desc, const int32_t* __restrict__ rank,
     const int32_t* __restrict__ status, const uint8_t* __restrict__ continued,
-    const uint8_t* __restrict__ wave, int64_t big_mn, int es, int64_t nf,
+    const uint8_t* __restrict__ wave, int64_t big_mn, int64_t small_mn, int es, int64_t nf,
     FarRec* __restrict__ rec, int64_t* __restrict__ tcount, int64_t* __restrict__ dcount,
     int64_t* __restrict__ dflag, unsigned long long* __restrict__ stats, int* __restrict__ bad) {
   const int64_t b = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -189,9 +197,9 @@ __global__ void __launch_bounds__(WG) far_rec_kernel(
     }
     v[5] = ((status[b] & ACA_GREW) || (continued && continued[b])) ? 1 : 0;
     v[6] = dense ? mxn + r * mn : r * mn;
-    const int cls = mn >= big_mn ? 0 : wave[b] ? 2 : 1;
+    const int cls = far_class(d, wave[b], big_mn, small_mn);
     v[7 + cls] = 1;
-    v[10 + cls] = (int64_t)es * mn * r * (r + 1) / 2;
+    v[11 + cls] = (int64_t)es * mn * r * (r + 1) / 2;
   }
   // one atomic per wavefront and statistic
   const int lane = threadIdx.x & 63;
@@ -272,14 +280,15 @@ void launch_far_pred(const float* pred, const FarDesc* desc, int64_t nf, double 
 }
 
 void launch_far_order(const FarDesc* desc, const uint8_t* wave, const int64_t* work, int64_t nf,
-                      int64_t big_mn, int* hist, int* cursor, int32_t* order, hipStream_t s) {
+                      int64_t big_mn, int64_t small_mn, int* hist, int* cursor, int32_t* order,
+                      hipStream_t s) {
   if (nf <= 0) return;
   fill_i32(hist, 0, ORDER_KEYS, s);
   hipLaunchKernelGGL(far_key_hist_kernel, grid_of(nf), dim3(WG), 0, s, desc, wave, work, nf,
-                     big_mn, hist);
+                     big_mn, small_mn, hist);
   hipLaunchKernelGGL(far_key_scan_kernel, dim3(1), dim3(WG), 0, s, hist, cursor);
   hipLaunchKernelGGL(far_key_scatter_kernel, grid_of(nf), dim3(WG), 0, s, desc, wave, work, nf,
-                     big_mn, cursor, order);
+                     big_mn, small_mn, cursor, order);
   HMX_LAUNCHED();
 }
 
@@ -291,12 +300,13 @@ void launch_count_status(const int32_t* status, int64_t nf, int code, int* count
 }
 
 void launch_far_rec(const FarDesc* desc, const int32_t* rank, const int32_t* status,
-                    const uint8_t* continued, const uint8_t* wave, int64_t big_mn, int es,
+                    const uint8_t* continued, const uint8_t* wave, int64_t big_mn,
+                    int64_t small_mn, int es,
                     int64_t nf, FarRec* rec, int64_t* tcount, int64_t* dcount, int64_t* dflag,
                     unsigned long long* stats, int* bad, hipStream_t s) {
   if (nf <= 0) return;
   hipLaunchKernelGGL(far_rec_kernel, grid_of(nf), dim3(WG), 0, s, desc, rank, status, continued,
-                     wave, big_mn, es, nf, rec, tcount, dcount, dflag, stats, bad);
+                     wave, big_mn, small_mn, es, nf, rec, tcount, dcount, dflag, stats, bad);
   HMX_LAUNCHED();
 }
 

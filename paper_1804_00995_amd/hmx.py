@@ -50,6 +50,7 @@ class Params(C.Structure):
         ("force_pool_bytes", C.c_int64),
         ("max_far_mn", C.c_int32),
         ("aca_big_threads", C.c_int32),
+        ("aca_small_mn", C.c_int32),
     ]
 
 
@@ -60,7 +61,7 @@ class Info(C.Structure):
         ("precision", C.c_int32), ("is_dense", C.c_int32)] + [
         (n, C.c_double) for n in ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms", "t_total_ms")] + [
         ("kernel_evals", C.c_int64), ("factor_bytes", C.c_int64), ("predicted_entries", C.c_int64),
-        ("aca_blocks", C.c_int64 * 3), ("aca_ms", C.c_double * 3), ("aca_bytes", C.c_int64 * 3),
+        ("aca_blocks", C.c_int64 * 4), ("aca_ms", C.c_double * 4), ("aca_bytes", C.c_int64 * 4),
         ("aca_rounds", C.c_int32), ("row_begin", C.c_int64), ("row_end", C.c_int64)]
 
     def as_dict(self):

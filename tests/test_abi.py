@@ -42,6 +42,7 @@ def test_params_default(hmx):
     assert p.tol == 1e-3 and p.leaf_size == 64 and p.eta == 1.5
     assert p.precision == hmx.FP64 and p.rank_model == hmx.RANK_ADAPTIVE
     assert p.initial_rank >= 1 and p.force_pred_scale == 1.0
+    assert p.aca_arena == 1 and p.aca_big_threads == 0 and p.aca_small_mn == 1024
 
 
 def test_null_arguments_rejected_on_host(hmx):
@@ -64,7 +65,9 @@ def test_bad_params_rejected_on_host(hmx):
     w = (C.c_double * 3)(1 / 3, 1 / 3, 1 / 3)
     for kw, code in [({"leaf_size": 0}, hmx.EINVAL), ({"eta": -1.0}, hmx.EINVAL),
                      ({"precision": 7}, hmx.EINVAL), ({"leaf_size": 300}, hmx.EUNSUPPORTED),
-                     ({"struct_size": 8}, hmx.EINVAL)]:
+                     ({"struct_size": 8}, hmx.EINVAL), ({"aca_big_threads": 128}, hmx.EINVAL),
+                     ({"aca_mid_threads": 512}, hmx.EINVAL), ({"aca_small_mn": -1}, hmx.EINVAL),
+                     ({"aca_arena": 2}, hmx.EINVAL)]:
         p = hmx.params(**kw)
         rc = lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 1, 5.0, C.byref(p), None, C.byref(h))
         assert rc == code, (kw, rc, lib.hmx_last_error())

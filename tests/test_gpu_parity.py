@@ -207,6 +207,24 @@ def test_overflow_continuation_identical(H):
     assert opc.info["factor_bytes"] < opb.info["factor_bytes"]
 
 
+def test_schedule_classes_agree(H):
+    # the same operator built with every far block in the middle class, and with the small-block
+    # and 256-thread large-block kinds: each within the tolerance of the oracle's dense product,
+    # and the per-class counts account for every far block
+    ops = {}
+    for name, kw in [("default", {}), ("mid_only", dict(aca_small_mn=0, aca_big_mn=1 << 30)),
+                     ("big256", dict(aca_big_threads=256, aca_big_mn=512, aca_small_mn=256))]:
+        ops[name], P, W = build(H, 4, kern=1, k=15.0, tol=1e-3, **kw)
+    x = I.complex_vector(P.shape[0], 7)
+    yr = oracle.dense_matvec(P, W, 1, 15.0, x)
+    for name, op in ops.items():
+        assert sum(op.info["aca_blocks"]) == op.info["n_far"], name
+        assert rel(apply(op, x), yr) <= 1e-3, name
+    assert ops["default"].info["aca_blocks"][3] > 0
+    assert ops["mid_only"].info["aca_blocks"][3] == 0 and ops["mid_only"].info["aca_blocks"][0] == 0
+    assert ops["big256"].info["aca_blocks"][0] > 0
+
+
 def test_full_size_sampled_rows(H):
     """245 760 points (L6 sphere), k = 40, leaf 64, tol 1e-3: the configuration the bench times."""
     op, P, W = build(H, 6, kern=1, k=40.0, tol=1e-3)

@@ -63,6 +63,7 @@ def test_autotune_choice_and_cache(H, sphere4, tmp_path):
     assert prm.max_far_mn in (0, 32768, 16384, 8192)
     assert prm.aca_mid_threads in (256, 128, 64)
     assert prm.aca_big_threads in (0, 512, 256)
+    assert prm.aca_small_mn in (1024, 512, 2048, 0)
     entries = json.loads(cache.read_text())
     assert len(entries) == 1
     (key, val), = entries.items()
@@ -70,6 +71,7 @@ def test_autotune_choice_and_cache(H, sphere4, tmp_path):
     assert val["aca_big_mn"] == prm.aca_big_mn and val["aca_serial"] == prm.aca_serial
     assert val["max_far_mn"] == prm.max_far_mn
     assert val["aca_big_threads"] == prm.aca_big_threads
+    assert val["aca_small_mn"] == prm.aca_small_mn
     # a second call for the same class is answered from the cache, without builds
     t2 = time.perf_counter()
     prm2, ms2 = H.autotune(xyzw, kern=1, k=14.0, cache_path=str(cache))
