@@ -510,12 +510,22 @@ hmx_status hmx_export_far(const hmx_op* op, int64_t b, void* U, void* V, int32_t
   } else {
     HMX_REQUIRE(V || f.r == 0, HMX_EINVAL, "null V");
     if (f.r) {
-      // columns of stride ldu / ldv on the device, packed column-major on the host
+      // columns of stride ldu / ldv in up to two segments on the device, packed column-major on
+      // the host
       const size_t es = op->elem;
-      HMX_HIP(hipMemcpy2D(U, (size_t)f.m * es, f.U, (size_t)f.ldu * es, (size_t)f.m * es, f.r,
+      const int r0 = std::min(f.r, f.split), r1 = f.r - r0;
+      unsigned char* hu = (unsigned char*)U;
+      unsigned char* hv = (unsigned char*)V;
+      HMX_HIP(hipMemcpy2D(hu, (size_t)f.m * es, f.U, (size_t)f.ldu * es, (size_t)f.m * es, r0,
                           hipMemcpyDeviceToHost));
-      HMX_HIP(hipMemcpy2D(V, (size_t)f.n * es, f.V, (size_t)f.ldv * es, (size_t)f.n * es, f.r,
+      HMX_HIP(hipMemcpy2D(hv, (size_t)f.n * es, f.V, (size_t)f.ldv * es, (size_t)f.n * es, r0,
                           hipMemcpyDeviceToHost));
+      if (r1 > 0) {
+        HMX_HIP(hipMemcpy2D(hu + (size_t)r0 * f.m * es, (size_t)f.m * es, f.U1, (size_t)f.ldu * es,
+                            (size_t)f.m * es, r1, hipMemcpyDeviceToHost));
+        HMX_HIP(hipMemcpy2D(hv + (size_t)r0 * f.n * es, (size_t)f.n * es, f.V1, (size_t)f.ldv * es,
+                            (size_t)f.n * es, r1, hipMemcpyDeviceToHost));
+      }
     }
     *rank = f.r;
   }
@@ -570,6 +580,9 @@ hmx_status hmx_import_far(hmx_op* op, const int32_t* ranks, const void* U, const
     f.V = dv;
     f.ldu = f.m;
     f.ldv = f.n;
+    f.split = (int32_t)r;
+    f.U1 = nullptr;
+    f.V1 = nullptr;
     trun += r;
     op->far_entries += r * (f.m + f.n);
     op->sum_rank += r;

@@ -568,7 +568,7 @@ void build_far(hmx_op* op, hipStream_t s) {
     to_host(est, estv.p, nf, s);
     to_host(hwork, work.p, nf, s);
     to_host(hst, status.p, nf, s);
-    for (int64_t b = 0; b < nf; ++b) first_cap[b] = desc[b].cap;  // cap of a block not grown
+    for (int64_t b = 0; b < nf; ++b) first_cap[b] = desc[b].cap + desc[b].cap1;
     for (;;) {
       std::vector<int32_t> list;
       for (int64_t b = 0; b < nf; ++b)
@@ -580,10 +580,13 @@ void build_far(hmx_op* op, hipStream_t s) {
       for (int32_t b : list) {
         continued[b] = 1;
         // room to finish: a doubled slot, at least twice the rank reached so far
-        const int64_t c = std::max<int64_t>({(int64_t)desc[b].cap, (int64_t)hrank[b] + 8,
+        const int64_t c = std::max<int64_t>({(int64_t)desc[b].cap + desc[b].cap1, (int64_t)hrank[b] + 8,
                                              (int64_t)first_cap[b]});
         need += std::max<int64_t>(est[b], 2 * c * ((int64_t)desc[b].m + desc[b].n));
       }
+      // each workgroup that takes a block may leave the unused rest of one arena
+      need += std::min<int64_t>((int64_t)list.size(), grid_big + grid_mid + grid_small) *
+              std::max({arena_big, arena_mid, arena_small});
       HMX_HIP(hipMemGetInfo(&free_b, &total_b));
       free_b += dev_cached_bytes();
       int64_t ncap = std::min<int64_t>(quantize_up(std::max<int64_t>(need, min_pool)),

@@ -99,12 +99,12 @@ struct Rule {
 struct FarDesc {
   int32_t tb, m, sb, n;
   int32_t rcap;  // rank cap: min(floor(m n / (m + n)), coefficient limit, forced cap)
-  int32_t cap;   // rank capacity of the current factor slot (its initial size before ACA)
-  void* U;      // slot in one of the build pools: column l of U at U + l ld (m entries)
-  void* V;      // column l of V at V + l ld (n entries); V = U + m
-  int64_t foff; // byte offset of the row/column used-flags (m + n bytes)
-  int32_t ld;   // column stride of both factors: m + n (interleaved column pairs)
-  int32_t pad_;
+  int32_t cap;   // columns of the first segment (before ACA: the initial capacity wanted)
+  void* U;       // first segment: column l of U at U + l ld (m entries), of V at that + m
+  void* U1;      // second segment (columns cap .. cap + cap1 - 1), or null
+  int64_t foff;  // byte offset of the row/column used-flags (m + n bytes)
+  int32_t ld;    // column stride of both factors: m + n (interleaved column pairs)
+  int32_t cap1;  // columns of the second segment
 };
 
 // Final far-block record used by the product.
@@ -112,10 +112,14 @@ struct FarRec {
   int32_t tb, m, sb, n;
   int32_t r;      // rank, or n for a block stored dense (then U is the m x n block)
   int32_t dense;  // 1 when stored dense
-  const void* U;  // m x r, column stride ldu (or the m x n block when dense, ldu = m)
-  const void* V;  // n x r, column stride ldv (unused when dense)
+  const void* U;  // m x r, column stride ldu (or the m x n block when dense, ldu = m);
+  const void* V;  // n x r, column stride ldv (unused when dense);
   int64_t toff;   // offset of t_b = V^T x_s in the product scratch
   int32_t ldu, ldv;
+  int32_t split;  // columns >= split live in the second segment: column l of U at
+  int32_t pad_;   // U1 + (l - split) ldu, of V at V1 + (l - split) ldv
+  const void* U1;
+  const void* V1;
 };
 
 constexpr int ACA_COEF_MAX = 1024;  // largest ACA rank (coefficients of a step held in LDS)

@@ -22,17 +22,19 @@
 // use the residual values before any scaling.
 //
 // Schedule: persistent grids; each workgroup takes the next block from an atomic counter
-// (blocks pre-ordered by decreasing size) and runs its whole sequential step chain.  Blocks with
-// m + n above a threshold run in 512-thread workgroups, the others in 256-thread workgroups, and
-// blocks with m, n <= 64 in single wavefronts (register-resident, below); the three classes run
-// on three streams.  The inner sums over previous terms keep LU independent loads in flight.
+// (blocks pre-ordered by decreasing size) and runs its whole sequential step chain.  Four
+// classes: m + n above a threshold in 512- or 256-thread workgroups, the middle sizes in 128-
+// (or 256- / 64-) thread workgroups, small blocks in 64-thread workgroups holding 256
+// coefficients, and blocks with m, n <= 64 in single wavefronts (register-resident, below).  The
+// classes run on three streams.
 //
-// Rank slots: a block starts in a slot of `cap` columns.  When it needs one more term it moves
-// itself to a slot of twice the size taken from a device bump pool (atomic offset) and goes
-// on; if the pool is exhausted it saves (rank, pivot row, norm) and stops with status OVERFLOW,
-// and the host continues it in a new pool.  Either way the pivot sequence, and therefore the
-// factors, equal those of one uninterrupted run.  A block that needs a term beyond its rank cap
-// is marked DENSE (stored exactly).
+// Factor storage: segments of interleaved column pairs taken from a device bump pool (atomic
+// offset), placed one after the other in per-workgroup arenas so that a finished block keeps
+// exactly its columns.  A block that outgrows its segment goes on in a second one; one that
+// outgrows both moves to a segment of twice the size.  If the pool is exhausted it saves (rank,
+// pivot row, norm) and stops with status OVERFLOW, and the host continues it in a new pool.
+// Either way the pivot sequence, and therefore the factors, equal those of one uninterrupted
+// run.  A block that needs a term beyond its rank cap is marked DENSE (stored exactly).
 #include <limits.h>
 
 #include <algorithm>
@@ -112,12 +114,19 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   // the descriptor in memory, where the compiler cannot infer the space), so that their loads do
   // not count against the LDS counter the coefficient and residual reads wait on
   using gT = HMX_GLOBAL T;
-  // slot layout: column l of U at U + l ld and column l of V at V + l ld with V = U + m and
-  // ld = m + n (interleaved column pairs), so the factors of rank r fill r ld consecutive entries
+  // Slot layout: interleaved column pairs, ld = m + n; column l of U at colU(l) (m entries) and
+  // column l of V at colU(l) + m (n entries).  A slot has at most two segments, columns
+  // [0, c0) at S0 and [c0, c0 + c1) at S1, so a block that outgrows its first segment goes on
+  // in a second one without moving its columns.  Before its first claim a block has S0 = null
+  // and c0 = the initial capacity of its descriptor.
   const int ld = m + n;
-  gT* U = ufl((gT*)d.U);
-  gT* V = U ? U + m : nullptr;
-  int cap = ufl(d.cap);
+  gT* S0 = ufl((gT*)d.U);
+  gT* S1 = ufl((gT*)d.U1);
+  int c0 = ufl(d.cap), c1 = ufl(d.cap1);
+  auto colU = [&](int l) -> gT* {
+    return l < c0 ? S0 + (int64_t)l * ld : S1 + (int64_t)(l - c0) * ld;
+  };
+  auto colV = [&](int l) -> gT* { return colU(l) + m; };
   uint8_t* rused = flags + ufl(d.foff);
   uint8_t* cused = rused + m;
   int kk, ip, hits;
@@ -160,12 +169,12 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       const int p = q - l * (l + 1) / 2;
       double gv[2] = {0.0, 0.0}, gu[2] = {0.0, 0.0};
       for (int j = lane; j < n; j += WAVE) {
-        const double2 a = to_d2(V[(int64_t)l * ld + j]), c = to_d2(V[(int64_t)p * ld + j]);
+        const double2 a = to_d2(colV(l)[j]), c = to_d2(colV(p)[j]);
         gv[0] += a.x * c.x + a.y * c.y;
         gv[1] += a.x * c.y - a.y * c.x;
       }
       for (int i = lane; i < m; i += WAVE) {
-        const double2 a = to_d2(U[(int64_t)l * ld + i]), c = to_d2(U[(int64_t)p * ld + i]);
+        const double2 a = to_d2(colU(l)[i]), c = to_d2(colU(p)[i]);
         gu[0] += a.x * c.x + a.y * c.y;
         gu[1] += a.x * c.y - a.y * c.x;
       }
@@ -184,18 +193,21 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   }
   int st = rcap <= 0 ? ACA_DENSE : ACA_RUNNING;
   bool grew = !fresh && (status[b] & ACA_GREW);
-  // Slots.  With arenas (arena > 0) the workgroup takes pool space in arenas of `arena` entries
-  // and places its blocks one after the other: a block claims the whole free rest of the arena
-  // (up to its rank cap) and, when it stops, keeps exactly its kk ld entries, so slots are exact
-  // without moving the factors.  Without arenas every slot is a pool allocation of its own.
-  // claim(want) returns the first entry of a slot of at least `want` columns (the rest of the
-  // arena when it holds them, else a new arena of max(arena, want ld) entries; the old arena's
-  // rest stays unused) and sets ncap to its capacity; -1 when the pool is exhausted.
-  bool mine = false;  // the slot lies at the top of this workgroup's arena
-  auto claim = [&](int want, int& ncap) -> int64_t {
-    if (arena > 0 && a_end - a_top >= (int64_t)want * ld) {
-      ncap = (int)min((int64_t)rcap, (a_end - a_top) / ld);
+  // Segments.  With arenas (arena > 0) the workgroup takes pool space in arenas of `arena`
+  // entries and places its blocks one after the other: a block claims the whole free rest of the
+  // arena (up to its rank cap) and, when it stops, keeps exactly the columns it used, so slots
+  // are exact without moving factors.  Without arenas every segment is a pool allocation of its
+  // own.  claim(need, want, lim) returns the first entry of a segment of at least `need`
+  // columns: the rest of the arena when it holds them, else a new arena of max(arena, want ld)
+  // entries (the old arena's rest stays unused; without arenas, `want` columns); ncap receives
+  // its capacity, at most lim; -1 when the pool is exhausted.
+  bool mine = false;     // the last claimed segment lies at the top of this workgroup's arena
+  int64_t mine_off = 0;  // its first entry
+  auto claim = [&](int need, int want, int lim, int& ncap) -> int64_t {
+    if (arena > 0 && a_end - a_top >= (int64_t)need * ld) {
+      ncap = (int)min((int64_t)lim, (a_end - a_top) / ld);
       mine = true;
+      mine_off = a_top;
       return a_top;
     }
     const int64_t size = arena > 0 ? max(arena, (int64_t)want * ld) : (int64_t)want * ld;
@@ -207,35 +219,38 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     if (arena > 0) {
       a_top = off;
       a_end = off + size;
-      ncap = (int)min((int64_t)rcap, size / ld);
+      ncap = (int)min((int64_t)lim, size / ld);
       mine = true;
+      mine_off = off;
     } else {
-      ncap = want;
+      ncap = min(want, lim);
+      mine = false;
     }
     return off;
   };
-  if (st == ACA_RUNNING && U == nullptr) {
-    // first slot: at least the descriptor's initial capacity
+  const int want0 = max(min(c0, rcap), 1);  // a first segment of this many columns when new
+  if (st == ACA_RUNNING && S0 == nullptr) {
     int ncap = 0;
-    const int64_t off = claim(min(cap, rcap), ncap);
+    const int64_t off = claim(1, want0, rcap, ncap);
     if (off < 0) {
       st = ACA_OVERFLOW;
     } else {
-      U = (gT*)(gpool + off);
-      V = U + m;
-      cap = ncap;
+      S0 = (gT*)(gpool + off);
+      c0 = ncap;
+      S1 = nullptr;
+      c1 = 0;
     }
   }
   __syncthreads();
   while (st == ACA_RUNNING) {
     if (kk >= GR) use_gram = false;
     // (1) residual row ip, stored as column kk of V when the slot has room
-    for (int l = tid; l < kk; l += NT) coef[l] = U[(int64_t)l * ld + ip];
+    for (int l = tid; l < kk; l += NT) coef[l] = colU(l)[ip];
     __syncthreads();
     const double px = X[tb + ip], py = Y[tb + ip], pz = Z[tb + ip];
-    const bool store = kk < cap;
+    const bool store = kk < c0 + c1;
     const bool gstep = use_gram && store;  // this step keeps the Gram matrices
-    gT* R = V + (int64_t)kk * ld;
+    gT* R = store ? colV(kk) : nullptr;
     double best = -1.0, nv2 = 0.0;
     int bj = INT_MAX;
     // Gram part of v_l^H R for this thread's l (gstep: kk < GR <= NT, one l per thread);
@@ -253,14 +268,16 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
         double g[2 * GW];
 #pragma unroll
         for (int q = 0; q < 2 * GW; ++q) g[q] = 0.0;
+        gT* vcol[GW];  // the window's columns of V
+#pragma unroll
+        for (int u = 0; u < GW; ++u) vcol[u] = u < lc ? colV(l0 + u) : nullptr;
         for (int j0 = tid; j0 < n; j0 += NT * JW) {
           T vv[JW][GW], r[JW];
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
             const int jc = min(j0 + q * NT, n - 1);  // in bounds; lanes past n are zeroed below
 #pragma unroll
-            for (int u = 0; u < GW; ++u)
-              vv[q][u] = u < lc ? V[(int64_t)(l0 + u) * ld + jc] : czero<T>();
+            for (int u = 0; u < GW; ++u) vv[q][u] = u < lc ? (T)vcol[u][jc] : czero<T>();
           }
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
@@ -322,7 +339,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
 #pragma unroll
         for (int u = 0; u < LU; ++u)
 #pragma unroll
-          for (int q = 0; q < JC; ++q) vv[u][q] = V[(int64_t)(l + u) * ld + jx[q]];
+          for (int q = 0; q < JC; ++q) vv[u][q] = colV(l + u)[jx[q]];
 #pragma unroll
         for (int u = 0; u < LU; ++u) {
           const T c = coef[l + u];
@@ -333,7 +350,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       for (; l < kk; ++l) {
         const T c = coef[l];
 #pragma unroll
-        for (int q = 0; q < JC; ++q) cfms(a[q], c, V[(int64_t)l * ld + jx[q]]);
+        for (int q = 0; q < JC; ++q) cfms(a[q], c, (T)colV(l)[jx[q]]);
       }
 #pragma unroll
       for (int q = 0; q < JC; ++q) {
@@ -368,25 +385,41 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       continue;
     }
     if (!store) {
-      if (cap >= rcap) {
+      if (c0 + c1 >= rcap) {
         st = ACA_DENSE;
         break;
       }
-      // move to a slot of at least twice the size (a new arena, or the free rest of this
-      // workgroup's arena for a block resumed from an earlier pool; never its own slot)
-      int ncap = 0;
-      const int64_t off = claim(min(rcap, max(2 * cap, cap + 8)), ncap);
-      if (off < 0) {
-        st = ACA_OVERFLOW;
-        break;
+      if (S1 == nullptr) {
+        // a second segment; the columns so far stay in the first, which is now full
+        if (mine) a_top = mine_off + (int64_t)c0 * ld;
+        int ncap = 0;
+        const int64_t off = claim(1, max(want0, c0), rcap - c0, ncap);
+        if (off < 0) {
+          st = ACA_OVERFLOW;
+          break;
+        }
+        S1 = (gT*)(gpool + off);
+        c1 = ncap;
+      } else {
+        // both segments full: one segment of twice the capacity, the columns moved there
+        if (mine) a_top = mine_off + (int64_t)c1 * ld;
+        const int want = min(rcap, max(2 * (c0 + c1), c0 + c1 + 8));
+        int ncap = 0;
+        const int64_t off = claim(want, want, rcap, ncap);
+        if (off < 0) {
+          st = ACA_OVERFLOW;
+          break;
+        }
+        gT* nS = (gT*)(gpool + off);
+        const int64_t e0 = (int64_t)c0 * ld, e1 = (int64_t)c1 * ld;
+        for (int64_t e = tid; e < e0; e += NT) nS[e] = S0[e];
+        for (int64_t e = tid; e < e1; e += NT) nS[e0 + e] = S1[e];
+        __syncthreads();
+        S0 = nS;
+        c0 = ncap;
+        S1 = nullptr;
+        c1 = 0;
       }
-      gT* nU = (gT*)(gpool + off);
-      const int64_t cnt = (int64_t)kk * ld;  // the kk column pairs, contiguous
-      for (int64_t e = tid; e < cnt; e += NT) nU[e] = U[e];
-      __syncthreads();
-      U = nU;
-      V = nU + m;
-      cap = ncap;
       grew = true;
       continue;  // recompute the residual row into the new slot
     }
@@ -403,10 +436,10 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       cused[bj] = 1;
     }
     // (4) residual column bj, stored as column kk of U
-    for (int l = tid; l < kk; l += NT) coef[l] = V[(int64_t)l * ld + bj];
+    for (int l = tid; l < kk; l += NT) coef[l] = colV(l)[bj];
     __syncthreads();
     const double qx = X[sb + bj], qy = Y[sb + bj], qz = Z[sb + bj], qw = W[sb + bj];
-    gT* Uk = U + (int64_t)kk * ld;
+    gT* Uk = colU(kk);
     double ub = -1.0, nu2 = 0.0;
     int ui = INT_MAX;
     double cross = 0.0;
@@ -421,14 +454,16 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
 #pragma unroll
         for (int q = 0; q < 2 * GW; ++q) g[q] = 0.0;
         // JW elements per thread and round, as in the row pass
+        gT* ucol[GW];  // the window's columns of U
+#pragma unroll
+        for (int u = 0; u < GW; ++u) ucol[u] = u < lc ? colU(l0 + u) : nullptr;
         for (int i0 = tid; i0 < m; i0 += NT * JW) {
           T uu[JW][GW], r[JW];
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
             const int ic = min(i0 + q * NT, m - 1);
 #pragma unroll
-            for (int u = 0; u < GW; ++u)
-              uu[q][u] = u < lc ? U[(int64_t)(l0 + u) * ld + ic] : czero<T>();
+            for (int u = 0; u < GW; ++u) uu[q][u] = u < lc ? (T)ucol[u][ic] : czero<T>();
           }
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
@@ -506,7 +541,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
 #pragma unroll
         for (int u = 0; u < LU; ++u)
 #pragma unroll
-          for (int q = 0; q < JC; ++q) uu[u][q] = U[(int64_t)(l + u) * ld + ix[q]];
+          for (int q = 0; q < JC; ++q) uu[u][q] = colU(l + u)[ix[q]];
 #pragma unroll
         for (int u = 0; u < LU; ++u) {
           const T c = coef[l + u];
@@ -517,7 +552,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       for (; l < kk; ++l) {
         const T c = coef[l];
 #pragma unroll
-        for (int q = 0; q < JC; ++q) cfms(a[q], c, U[(int64_t)l * ld + ix[q]]);
+        for (int q = 0; q < JC; ++q) cfms(a[q], c, (T)colU(l)[ix[q]]);
       }
 #pragma unroll
       for (int q = 0; q < JC; ++q) {
@@ -549,7 +584,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           const int ix = i < m ? i : m - 1;
           uk[c] = i < m ? to_d2(Uk[ix]) : make_double2(0.0, 0.0);
 #pragma unroll
-          for (int q = 0; q < LG; ++q) ul[c][q] = q < lc ? U[(int64_t)(l0 + q) * ld + ix] : czero<T>();
+          for (int q = 0; q < LG; ++q) ul[c][q] = q < lc ? (T)colU(l0 + q)[ix] : czero<T>();
         }
 #pragma unroll
         for (int c = 0; c < CJ; ++c)
@@ -569,7 +604,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           const int jx = j < n ? j : n - 1;
           vk[c] = j < n ? to_d2(R[jx]) : make_double2(0.0, 0.0);
 #pragma unroll
-          for (int q = 0; q < LG; ++q) vl[c][q] = q < lc ? V[(int64_t)(l0 + q) * ld + jx] : czero<T>();
+          for (int q = 0; q < LG; ++q) vl[c][q] = q < lc ? (T)colV(l0 + q)[jx] : czero<T>();
         }
 #pragma unroll
         for (int c = 0; c < CJ; ++c)
@@ -613,15 +648,21 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     ip = ui;
   }
   if (mine) {
-    // the block keeps exactly kk ld entries at the top of the arena (none when it is stored
-    // dense); a block stopped for a later round resumes from them and moves on its next step
-    if (st != ACA_DENSE) a_top += (int64_t)kk * ld;
-    cap = kk;
+    // the last segment keeps exactly the columns it used, at the top of the arena (none when the
+    // block is stored dense); a block stopped for a later round resumes from them and claims
+    // more on its next step
+    const int used = st == ACA_DENSE ? 0 : max(S1 != nullptr ? kk - c0 : kk, 0);
+    a_top = mine_off + (int64_t)used * ld;
+    if (S1 != nullptr)
+      c1 = used;
+    else
+      c0 = used;
   }
   if (tid == 0) {
-    descs[b].U = (void*)U;
-    descs[b].V = (void*)V;
-    descs[b].cap = cap;
+    descs[b].U = (void*)S0;
+    descs[b].U1 = (void*)S1;
+    descs[b].cap = c0;
+    descs[b].cap1 = c1;
     descs[b].ld = ld;
     rank[b] = kk;
     ipiv[b] = ip | (hits << ACA_HIT_SHIFT);
@@ -848,8 +889,9 @@ __global__ void __launch_bounds__(WG) aca_wave_kernel(
     }
     if (lane == 0) {
       desc[b].U = (void*)Ug;
-      desc[b].V = (void*)Vg;
+      desc[b].U1 = nullptr;
       desc[b].cap = Ug ? scap : d.cap;
+      desc[b].cap1 = 0;
       desc[b].ld = ld;
     }
     if (lane == 0) {

@@ -36,10 +36,10 @@ __global__ void __launch_bounds__(WG) far_desc_kernel(
                                        : (int64_t)initial_rank;
   d.cap = (int32_t)(c0 < rc ? c0 : rc);
   d.U = nullptr;
-  d.V = nullptr;
+  d.U1 = nullptr;
   d.foff = 0;
   d.ld = (int32_t)mn;
-  d.pad_ = 0;
+  d.cap1 = 0;
   desc[b] = d;
   const bool w = d.m <= ACA_WAVE_N && d.n <= ACA_WAVE_N;
   wave[b] = w ? 1 : 0;
@@ -177,11 +177,17 @@ __global__ void __launch_bounds__(WG) far_rec_kernel(
     f.n = d.n;
     f.dense = dense ? 1 : 0;
     f.r = dense ? d.n : (int32_t)r;
+    // factors: interleaved column pairs in up to two segments (V = U + m within a segment)
+    const size_t es_m = (size_t)es * d.m;
     f.U = dense ? nullptr : d.U;
-    f.V = dense ? nullptr : d.V;
+    f.V = dense || !d.U ? nullptr : (const void*)((const char*)d.U + es_m);
     f.toff = 0;
     f.ldu = dense ? d.m : d.ld;
     f.ldv = dense ? d.n : d.ld;
+    f.split = dense ? d.n : d.cap;
+    f.pad_ = 0;
+    f.U1 = dense ? nullptr : d.U1;
+    f.V1 = dense || !d.U1 ? nullptr : (const void*)((const char*)d.U1 + es_m);
     rec[b] = f;
     const int64_t mn = (int64_t)d.m + d.n, mxn = (int64_t)d.m * d.n;
     tcount[b] = dense ? d.n : r;

@@ -52,14 +52,17 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
     for (int j = threadIdx.x; j < f.n; j += WG) tb[j] = xs[j];
     return;
   }
-  const T* V = (const T*)f.V;
   const int n = f.n, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int64_t ldv = f.ldv;
+  // column l of V: in the first segment below f.split, else in the second
+  auto colv = [&](int l) -> const T* {
+    return l < f.split ? (const T*)f.V + l * ldv : (const T*)f.V1 + (l - f.split) * ldv;
+  };
   int l = w;
   for (; l + NWAVE < f.r; l += 2 * NWAVE) {
     T a0 = czero<T>(), a1 = czero<T>();
-    const T* v0 = V + l * ldv;
-    const T* v1 = V + (l + NWAVE) * ldv;
+    const T* v0 = colv(l);
+    const T* v1 = colv(l + NWAVE);
     for (int j = lane; j < n; j += WAVE) {
       T xj = xs[j];
       cfma(a0, v0[j], xj);
@@ -74,7 +77,7 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
   }
   for (; l < f.r; l += NWAVE) {
     T a0 = czero<T>();
-    const T* v0 = V + l * ldv;
+    const T* v0 = colv(l);
     for (int j = lane; j < n; j += WAVE) cfma(a0, v0[j], xs[j]);
     a0 = wave_sum2(a0);
     if (lane == 0) tb[l] = a0;
@@ -134,7 +137,9 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
 #pragma unroll 4
       for (int l = 0; l < f.r; ++l) {
         const T tl = tt[l];
-        const T* col = U + (int64_t)l * f.ldu;
+        // column l of U: in the first segment below f.split, else in the second
+        const T* col = l < f.split ? U + (int64_t)l * f.ldu
+                                   : (const T*)f.U1 + o + (int64_t)(l - f.split) * f.ldu;
 #pragma unroll
         for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
           int i = lane + c * WAVE;
