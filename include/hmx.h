@@ -112,6 +112,9 @@ typedef struct {
                            wavefront blocks) run in 64-thread workgroups holding 256 ACA
                            coefficients, many per CU, with direct cross sums whatever
                            aca_gram_min_mn says; 0 puts them in the middle class */
+  int32_t aca_wave; /* 1: blocks with m, n <= 64 run one per wavefront with their factors in
+                       registers; 0 (default): they go to the small-block class, which was
+                       measured faster on MI355X (FP64 by about 2 ms at 245 760 points) */
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
@@ -200,17 +203,17 @@ hmx_status hmx_graph_launch(hmx_graph* g, int32_t reps, void* stream);
 void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
 
 /* Autotuner of the build schedule (max_far_mn, aca_big_mn, aca_gram_min_mn, aca_mid_threads,
- * aca_big_threads, aca_small_mn, aca_serial of hmx_params).  Times hmx_build_points(xyzw, M,
- * kern, k) under a grid of settings, each stage at the best of the previous ones: far-block
- * bounds {none, 32768, 16384, 8192}; class thresholds {2048, 4096, 8192, none} x Gram
- * thresholds {0, 1024, 4096, none} on concurrent streams; middle-class workgroups {256, 128,
- * 64}; large-block workgroups {512, 256}; small-block bounds {512, 2048, none}; serial classes;
- * best of two builds each.  *out receives *p (defaults when
+ * aca_big_threads, aca_small_mn, aca_wave, aca_serial of hmx_params).  Times
+ * hmx_build_points(xyzw, M, kern, k) under a grid of settings, each stage at the best of the
+ * previous ones: far-block bounds {none, 32768, 16384, 8192}; class thresholds {2048, 4096,
+ * 8192, none} x Gram thresholds {0, 1024, 4096, none} on concurrent streams; middle-class
+ * workgroups {256, 128, 64}; large-block workgroups {512, 256}; small-block bounds {512, 2048,
+ * none}; the other wavefront setting; serial classes; best of two builds each.  *out receives *p (defaults when
  * NULL) with the fastest settings, *best_ms (may be NULL) that build time in ms.
  * cache_path (host string, may be NULL): a JSON file of earlier choices keyed by device
  * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size and eta; a key
  * found there is returned without timing, a new one is added to the file.  Synchronous; builds
- * and frees up to 59 operators (29 settings, two builds each, one warm-up).  Errors: as
+ * and frees up to 61 operators (30 settings, two builds each, one warm-up).  Errors: as
  * hmx_build_points, HMX_EINVAL for tol <= 0 or an unwritable cache file. */
 hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
                         const hmx_params* p, const char* cache_path, void* stream,

@@ -61,6 +61,7 @@ void defaults(hmx_params* p) {
   p->aca_mid_threads = 128;
   p->aca_big_threads = 0;
   p->aca_small_mn = 1024;
+  p->aca_wave = 0;
   p->aca_arena = 1;
   p->row_shares = 1;
   p->row_share = 0;
@@ -101,6 +102,7 @@ hmx_params resolve(const hmx_params* in) {
   // and runs best with one 512-thread workgroup per CU, FP32 with two 256-thread ones)
   if (p.aca_big_threads == 0) p.aca_big_threads = p.precision == HMX_FP64 ? 512 : 256;
   HMX_REQUIRE(p.aca_small_mn >= 0, HMX_EINVAL, "aca_small_mn must be >= 0");
+  HMX_REQUIRE(p.aca_wave == 0 || p.aca_wave == 1, HMX_EINVAL, "aca_wave must be 0 or 1");
   HMX_REQUIRE(p.row_shares >= 1 && p.row_shares <= (1 << 20) &&
                   (p.row_shares & (p.row_shares - 1)) == 0,
               HMX_EINVAL, "row_shares must be a power of two in [1, 2^20]");

@@ -341,7 +341,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   DevBuf<int64_t> mnv(nf1), foff(nf1 + 1), estv(nf1), ests(nf1 + 1), work(nf1);
   DevBuf<uint8_t> wave(nf1);
   launch_far_desc(op->farL.p, nf, op->nbegin.p, op->nend.p, op->p.initial_rank,
-                  op->p.force_rank_cap, d_desc.p, mnv.p, estv.p, wave.p, work.p, s);
+                  op->p.force_rank_cap, op->p.aca_wave, d_desc.p, mnv.p, estv.p, wave.p, work.p, s);
   scan_excl_i64(mnv.p, foff.p, nf, s);
   scan_excl_i64(estv.p, ests.p, nf, s);
   launch_far_foff(d_desc.p, foff.p, nf, s);

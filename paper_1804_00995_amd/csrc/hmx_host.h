@@ -260,8 +260,8 @@ RankModel get_rank_model();
 
 // k_far.hip: far-field bookkeeping around ACA
 void launch_far_desc(const int2* pairs, int64_t nf, const int32_t* nbegin, const int32_t* nend,
-                     int initial_rank, int force_cap, FarDesc* desc, int64_t* mn, int64_t* est,
-                     uint8_t* wave, int64_t* work, hipStream_t s);
+                     int initial_rank, int force_cap, int use_wave, FarDesc* desc, int64_t* mn,
+                     int64_t* est, uint8_t* wave, int64_t* work, hipStream_t s);
 void launch_far_foff(FarDesc* desc, const int64_t* foff, int64_t nf, hipStream_t s);
 void launch_far_pred(const float* pred, const FarDesc* desc, int64_t nf, double alpha,
                      int64_t beta, double scale, int64_t* ramn, int64_t* work, hipStream_t s);

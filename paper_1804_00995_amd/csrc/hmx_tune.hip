@@ -20,7 +20,8 @@
 namespace {
 
 struct Choice {
-  int big = 4096, gram = 1024, serial = 0, maxmn = 16384, mid = 128, bigt = 0, small = 1024;
+  int big = 4096, gram = 1024, serial = 0, maxmn = 16384, mid = 128, bigt = 0, small = 1024,
+      wave = 0;
   double ms = 0.0;
 };
 
@@ -44,7 +45,7 @@ std::string class_key(int64_t M, int32_t kern, const hmx_params& p) {
 
 // The cache file is one JSON object of entries
 //   "key": {"max_far_mn": N, "aca_big_mn": N, "aca_gram_min_mn": N, "aca_mid_threads": N,
-//           "aca_big_threads": N, "aca_small_mn": N, "aca_serial": N, "ms": X}
+//           "aca_big_threads": N, "aca_small_mn": N, "aca_wave": N, "aca_serial": N, "ms": X}
 // written by this file; the reader accepts exactly that shape.
 double field(const std::string& body, const char* name, double dflt) {
   const std::string pat = std::string("\"") + name + "\":";
@@ -79,6 +80,7 @@ std::map<std::string, Choice> read_cache(const char* path) {
     c.mid = (int)field(body, "aca_mid_threads", 128);
     c.bigt = (int)field(body, "aca_big_threads", 0);
     c.small = (int)field(body, "aca_small_mn", 1024);
+    c.wave = (int)field(body, "aca_wave", 0);
     c.ms = field(body, "ms", 0.0);
     out[key] = c;
     pos = b1 + 1;
@@ -99,9 +101,9 @@ void write_cache(const char* path, const std::map<std::string, Choice>& m) {
       std::snprintf(buf, sizeof(buf),
                     "{\"max_far_mn\": %d, \"aca_big_mn\": %d, \"aca_gram_min_mn\": %d, "
                     "\"aca_mid_threads\": %d, \"aca_big_threads\": %d, \"aca_small_mn\": %d, "
-                    "\"aca_serial\": %d, \"ms\": %.3f}",
+                    "\"aca_wave\": %d, \"aca_serial\": %d, \"ms\": %.3f}",
                     kv.second.maxmn, kv.second.big, kv.second.gram, kv.second.mid, kv.second.bigt,
-                    kv.second.small, kv.second.serial, kv.second.ms);
+                    kv.second.small, kv.second.wave, kv.second.serial, kv.second.ms);
       f << "  \"" << kv.first << "\": " << buf << (++i < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -164,12 +166,12 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
       q.aca_serial = 0;
       (void)time_build(xyzw, M, kern, k, q, stream, 1);  // warm the allocator and the code
       best = Choice{q.aca_big_mn, q.aca_gram_min_mn, 0, q.max_far_mn, q.aca_mid_threads,
-                    q.aca_big_threads, q.aca_small_mn, 1e300};
+                    q.aca_big_threads, q.aca_small_mn, q.aca_wave, 1e300};
       auto trial = [&](const hmx_params& t) {
         const double ms = time_build(xyzw, M, kern, k, t, stream, 2);
         if (ms < best.ms)
           best = Choice{t.aca_big_mn, t.aca_gram_min_mn, t.aca_serial, t.max_far_mn,
-                        t.aca_mid_threads, t.aca_big_threads, t.aca_small_mn, ms};
+                        t.aca_mid_threads, t.aca_big_threads, t.aca_small_mn, t.aca_wave, ms};
       };
       for (int mx : maxmns) {
         q.max_far_mn = mx;
@@ -199,6 +201,9 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
         trial(q);
       }
       q.aca_small_mn = best.small;
+      q.aca_wave = 1 - q.aca_wave;
+      trial(q);
+      q.aca_wave = best.wave;
       q.aca_serial = 1;
       trial(q);
       cache[key] = best;
@@ -212,6 +217,7 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
     out->aca_mid_threads = best.mid;
     out->aca_big_threads = best.bigt;
     out->aca_small_mn = best.small;
+    out->aca_wave = best.wave;
     if (best_ms) *best_ms = best.ms;
     return HMX_OK;
   } catch (const hmx::Error& e) {

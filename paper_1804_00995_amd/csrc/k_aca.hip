@@ -99,8 +99,11 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
                           unsigned long long* gtop, double2* gram, int gram_min, int64_t arena,
                           int64_t& a_top, int64_t& a_end, T* coef, HMX_LDS T* rbuf,
                           Sh& sh) {
-  constexpr int GW = BIG ? (sizeof(T) == 16 ? 6 : 8) : 4;  // terms per Gram window
-  constexpr int JW = BIG ? (sizeof(T) == 16 ? 2 : 4) : 1;  // elements per thread per window round
+  // terms per Gram window and elements per thread per window round (see aca_rl for the
+  // large-block kinds' occupancy)
+  constexpr bool F32_256 = sizeof(T) == 8 && NT == 256;
+  constexpr int GW = BIG ? (sizeof(T) == 16 || F32_256 ? 6 : 8) : 4;
+  constexpr int JW = BIG ? (sizeof(T) == 16 || F32_256 ? 2 : 4) : 1;
   constexpr int JC = 1;                  // elements per thread per round
   constexpr int LU = BIG ? 8 : 4;  // previous terms loaded per round (loads in flight)
   const int tid = threadIdx.x;
@@ -672,19 +675,27 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
   __syncthreads();
 }
 
-// Length of the LDS residual buffer (a multiple of NT): the large-block class keeps up to 7680
-// (FP64) or 15360 (FP32) entries of the partial residual in LDS with 512-thread workgroups (one
-// per CU), 3584 or 8192 with 256-thread workgroups (two per CU); the other classes keep theirs in
-// the factor slot.
+// Length of the LDS residual buffer (a multiple of NT) of the large-block class.  FP64 and
+// 512-thread FP32 workgroups keep most of the partial residual in LDS: 7680 / 15360 entries with
+// 512 threads (one workgroup per CU), 3584 FP64 entries with 256 threads (two per CU).  FP32
+// 256-thread workgroups keep 1024 entries and run three per CU, which leaves LDS for the other
+// classes on the same CUs (measured faster for FP32, slower for FP64).  The other classes keep
+// their partial residual in the factor slot.
 template <class T, int NT, bool BIG>
 constexpr int aca_rl() {
-  return !BIG ? 0 : NT >= 512 ? (sizeof(T) == 16 ? 7680 : 15360) : (sizeof(T) == 16 ? 3584 : 8192);
+  return !BIG ? 0
+         : NT >= 512 ? (sizeof(T) == 16 ? 7680 : 15360)
+                     : (sizeof(T) == 16 ? 3584 : 1024);
+}
+template <class T, int NT, bool BIG>
+constexpr int aca_waves_per_eu() {
+  return BIG && !(sizeof(T) == 8 && NT == 256) ? 2 : 3;
 }
 
-// BIG: the large-block class (long Gram windows, two waves per SIMD, LDS residual); CO: the
-// coefficient capacity (ACA_COEF_SMALL for the small-block class)
+// BIG: the large-block class (long Gram windows, LDS residual); CO: the coefficient capacity
+// (ACA_COEF_SMALL for the small-block class)
 template <class T, int NT, bool BIG, int CO = ACA_COEF_MAX>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BIG ? 2 : 3))) aca_kernel(FarDesc* __restrict__ desc,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(aca_waves_per_eu<T, NT, BIG>()))) aca_kernel(FarDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order, int nb,
                                                  int* counter, const double* __restrict__ X,
                                                  const double* __restrict__ Y,

@@ -12,10 +12,12 @@ namespace hmx {
 
 // Descriptor of far block b (pair (t, s) of tree nodes): rows [tb, tb + m), columns [sb, sb + n),
 // rank cap min(floor(mn / (m + n)), ACA_COEF_MAX, force_cap), first slot of initial_rank columns
-// (twice / three times that for m + n >= ACA_BIG / 2 ACA_BIG), no slot yet.
+// (twice / three times that for m + n >= ACA_BIG / 2 ACA_BIG), no slot yet; wavefront class
+// (m, n <= ACA_WAVE_N) only when use_wave.
 __global__ void __launch_bounds__(WG) far_desc_kernel(
     const int2* __restrict__ pairs, int64_t nf, const int32_t* __restrict__ nbegin,
-    const int32_t* __restrict__ nend, int initial_rank, int force_cap, FarDesc* __restrict__ desc,
+    const int32_t* __restrict__ nend, int initial_rank, int force_cap, int use_wave,
+    FarDesc* __restrict__ desc,
     int64_t* __restrict__ mn_out, int64_t* __restrict__ est, uint8_t* __restrict__ wave,
     int64_t* __restrict__ work) {
   const int64_t b = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -41,7 +43,7 @@ __global__ void __launch_bounds__(WG) far_desc_kernel(
   d.ld = (int32_t)mn;
   d.cap1 = 0;
   desc[b] = d;
-  const bool w = d.m <= ACA_WAVE_N && d.n <= ACA_WAVE_N;
+  const bool w = use_wave && d.m <= ACA_WAVE_N && d.n <= ACA_WAVE_N;
   wave[b] = w ? 1 : 0;
   mn_out[b] = mn;
   // pool estimate without a rank model (generous: a short pool costs another launch round):
@@ -263,11 +265,11 @@ __global__ void __launch_bounds__(WG) far_count_status_kernel(const int32_t* __r
 static dim3 grid_of(int64_t n) { return dim3((unsigned)((n + WG - 1) / WG)); }
 
 void launch_far_desc(const int2* pairs, int64_t nf, const int32_t* nbegin, const int32_t* nend,
-                     int initial_rank, int force_cap, FarDesc* desc, int64_t* mn, int64_t* est,
+                     int initial_rank, int force_cap, int use_wave, FarDesc* desc, int64_t* mn, int64_t* est,
                      uint8_t* wave, int64_t* work, hipStream_t s) {
   if (nf <= 0) return;
   hipLaunchKernelGGL(far_desc_kernel, grid_of(nf), dim3(WG), 0, s, pairs, nf, nbegin, nend,
-                     initial_rank, force_cap, desc, mn, est, wave, work);
+                     initial_rank, force_cap, use_wave, desc, mn, est, wave, work);
   HMX_LAUNCHED();
 }
 

@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("max_far_mn", C.c_int32),
         ("aca_big_threads", C.c_int32),
         ("aca_small_mn", C.c_int32),
+        ("aca_wave", C.c_int32),
     ]
 
 

@@ -67,7 +67,7 @@ def test_bad_params_rejected_on_host(hmx):
                      ({"precision": 7}, hmx.EINVAL), ({"leaf_size": 300}, hmx.EUNSUPPORTED),
                      ({"struct_size": 8}, hmx.EINVAL), ({"aca_big_threads": 128}, hmx.EINVAL),
                      ({"aca_mid_threads": 512}, hmx.EINVAL), ({"aca_small_mn": -1}, hmx.EINVAL),
-                     ({"aca_arena": 2}, hmx.EINVAL)]:
+                     ({"aca_arena": 2}, hmx.EINVAL), ({"aca_wave": 3}, hmx.EINVAL)]:
         p = hmx.params(**kw)
         rc = lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 1, 5.0, C.byref(p), None, C.byref(h))
         assert rc == code, (kw, rc, lib.hmx_last_error())

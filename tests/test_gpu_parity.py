@@ -213,16 +213,29 @@ def test_schedule_classes_agree(H):
     # and the per-class counts account for every far block
     ops = {}
     for name, kw in [("default", {}), ("mid_only", dict(aca_small_mn=0, aca_big_mn=1 << 30)),
-                     ("big256", dict(aca_big_threads=256, aca_big_mn=512, aca_small_mn=256))]:
+                     ("big256", dict(aca_big_threads=256, aca_big_mn=512, aca_small_mn=256)),
+                     ("wave", dict(aca_wave=1)), ("wave32", dict(aca_wave=1, precision=H.FP32_MIXED))]:
         ops[name], P, W = build(H, 4, kern=1, k=15.0, tol=1e-3, **kw)
     x = I.complex_vector(P.shape[0], 7)
     yr = oracle.dense_matvec(P, W, 1, 15.0, x)
     for name, op in ops.items():
         assert sum(op.info["aca_blocks"]) == op.info["n_far"], name
-        assert rel(apply(op, x), yr) <= 1e-3, name
+        dt = torch.complex64 if op.precision == H.FP32_MIXED else torch.complex128
+        assert rel(apply(op, x, dt), yr) <= 1e-3, name
     assert ops["default"].info["aca_blocks"][3] > 0
     assert ops["mid_only"].info["aca_blocks"][3] == 0 and ops["mid_only"].info["aca_blocks"][0] == 0
     assert ops["big256"].info["aca_blocks"][0] > 0
+    assert ops["default"].info["aca_blocks"][2] == 0
+    assert ops["wave"].info["aca_blocks"][2] > 0 and ops["wave32"].info["aca_blocks"][2] > 0
+
+
+def test_wavefront_overflow_continues_in_workgroups(H):
+    # at tol 1e-8 wavefront blocks need more than the register capacity of 16 terms: they store
+    # their state and continue in the workgroup kernel; the product stays within tolerance
+    op, P, W = build(H, 4, kern=1, k=15.0, tol=1e-8, aca_wave=1)
+    assert op.info["aca_blocks"][2] > 0 and op.info["overflow_blocks"] > 0
+    x = I.complex_vector(P.shape[0], 8)
+    assert rel(apply(op, x), oracle.dense_matvec(P, W, 1, 15.0, x)) <= 1e-7
 
 
 def test_full_size_sampled_rows(H):

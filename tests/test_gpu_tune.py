@@ -64,6 +64,7 @@ def test_autotune_choice_and_cache(H, sphere4, tmp_path):
     assert prm.aca_mid_threads in (256, 128, 64)
     assert prm.aca_big_threads in (0, 512, 256)
     assert prm.aca_small_mn in (1024, 512, 2048, 0)
+    assert prm.aca_wave in (0, 1)
     entries = json.loads(cache.read_text())
     assert len(entries) == 1
     (key, val), = entries.items()
@@ -72,6 +73,7 @@ def test_autotune_choice_and_cache(H, sphere4, tmp_path):
     assert val["max_far_mn"] == prm.max_far_mn
     assert val["aca_big_threads"] == prm.aca_big_threads
     assert val["aca_small_mn"] == prm.aca_small_mn
+    assert val["aca_wave"] == prm.aca_wave
     # a second call for the same class is answered from the cache, without builds
     t2 = time.perf_counter()
     prm2, ms2 = H.autotune(xyzw, kern=1, k=14.0, cache_path=str(cache))
