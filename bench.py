@@ -62,8 +62,8 @@ def measured_traffic(precision):
     vals = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line and not line.startswith(" "):
-                key, _, val = line.partition(":")
+            if ": " in line and not line.startswith(" "):
+                key, _, val = line.partition(": ")  # keys may hold a colon ("sha256[:16]")
                 vals[key.strip()] = val.strip()
     if vals.get("k_aca.hip sha256[:16]") != source_digest(ACA_SOURCE):
         return None
