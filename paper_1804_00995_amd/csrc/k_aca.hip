@@ -45,6 +45,10 @@
 namespace hmx {
 
 
+// Terms whose Gram sums the large-block kind keeps per wavefront (the sliced passes run for
+// ranks up to GB).
+constexpr int GB = 64;
+
 // Workgroup state in LDS; NW wavefronts, Gram order GR.
 template <int NW, int GR>
 struct AcaShared {
@@ -90,6 +94,38 @@ __device__ __forceinline__ P* ufl(P* p) {
   return (P*)(uintptr_t)ufl((int64_t)(uintptr_t)p);
 }
 
+// Gram sums of one window taken by one wavefront over its slice: the 2 GW partial sums are
+// reduced over the wavefront and lane u stores term l0 + u in the wavefront's row of gbuf.
+template <int GW>
+__device__ __forceinline__ void wave_gram_sums(double* g, int lc, int l0, HMX_LDS double2* row,
+                                               int lane) {
+#pragma unroll
+  for (int q = 0; q < 2 * GW; ++q) g[q] = wave_sum(g[q]);
+#pragma unroll
+  for (int u = 0; u < GW; ++u)
+    if (lane == u && u < lc) row[l0 + u] = make_double2(g[2 * u], g[2 * u + 1]);
+}
+
+// After the sliced windows of a pass: h[l] = sum over the NW wavefront rows of gbuf, in
+// wavefront order (deterministic).  Thread l adds term l; the first barrier makes every row
+// visible, the second lets gbuf be written again by the next pass.
+template <int NW>
+__device__ __forceinline__ void gram_sums_total(HMX_LDS double2* gbuf, int kk, double2* h,
+                                                int tid) {
+  __syncthreads();
+  if (tid < kk) {
+    double2 a = gbuf[tid];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const double2 b = gbuf[w * GB + tid];
+      a.x += b.x;
+      a.y += b.y;
+    }
+    h[tid] = a;
+  }
+  __syncthreads();
+}
+
 template <class T, int NT, bool BIG, int RL, int CO, class Sh>
 __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __restrict__ X,
                           const double* __restrict__ Y, const double* __restrict__ Z,
@@ -98,7 +134,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
                           double* norm2, int fresh, T* gpool, int64_t gcap,
                           unsigned long long* gtop, double2* gram, int gram_min, int64_t arena,
                           int64_t& a_top, int64_t& a_end, T* coef, HMX_LDS T* rbuf,
-                          Sh& sh) {
+                          HMX_LDS double2* gbuf, Sh& sh) {
   // terms per Gram window and elements per thread per window round (see aca_rl for the
   // large-block kinds' occupancy)
   constexpr bool F32_256 = sizeof(T) == 8 && NT == 256;
@@ -261,10 +297,19 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
     double2 gcorr = make_double2(0.0, 0.0);
     if (gstep && tid < kk) gcorr = gram_row_dot(GV + (int64_t)tid * GR, coef, (tid / GW) * GW, kk);
     if (gstep) {
-      // windows of GW previous terms; a thread takes JW elements per round (j0 + q NT), so that
-      // JW GW factor loads are in flight together while the Gram sums and coefficients are
-      // shared.  The partial residual between windows lives in LDS for j < RL (RL is a multiple
-      // of NT, so the choice is uniform across the workgroup) and in column kk beyond.
+      // Windows of GW previous terms.  A thread takes JW elements per round, so that JW GW factor
+      // loads are in flight together while the Gram sums and coefficients are shared.  The
+      // partial residual between windows lives in LDS for j < RL (RL is a multiple of the round
+      // width, so the choice is uniform across a wavefront) and in column kk beyond.
+      // Large-block kind with kk <= GB: each wavefront owns a contiguous slice of the row and
+      // runs all windows over it without workgroup barriers; its Gram sums go to its own row of
+      // gbuf and are added in wavefront order once at the end.  Otherwise elements are
+      // interleaved over the workgroup (j0 + q NT) and each window ends in a workgroup sum.
+      const bool slice = BIG && kk <= GB;
+      const int wv = tid / WAVE, lane = tid & (WAVE - 1);
+      const int sl = ((n + NT - 1) / NT) * WAVE;  // slice length, a multiple of 64
+      const int e0 = slice ? wv * sl + lane : tid, es = slice ? WAVE : NT;
+      const int eend = slice ? min(n, wv * sl + sl) : n;
       for (int l0 = 0; l0 < max(kk, 1); l0 += GW) {
         const int lc = min(GW, kk - l0);
         const bool first = l0 == 0, last = l0 + GW >= kk;
@@ -274,21 +319,21 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
         gT* vcol[GW];  // the window's columns of V
 #pragma unroll
         for (int u = 0; u < GW; ++u) vcol[u] = u < lc ? colV(l0 + u) : nullptr;
-        for (int j0 = tid; j0 < n; j0 += NT * JW) {
+        for (int j0 = e0; j0 < eend; j0 += es * JW) {
           T vv[JW][GW], r[JW];
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
-            const int jc = min(j0 + q * NT, n - 1);  // in bounds; lanes past n are zeroed below
+            const int jc = min(j0 + q * es, eend - 1);  // in bounds; past eend zeroed below
 #pragma unroll
             for (int u = 0; u < GW; ++u) vv[q][u] = u < lc ? (T)vcol[u][jc] : czero<T>();
           }
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
-            const int j = j0 + q * NT, jc = min(j, n - 1);
+            const int j = j0 + q * es, jc = min(j, eend - 1);
             const bool inl = j < RL;
             T x = first ? eval_entry<T>(kern, k, px, py, pz, X[sb + jc], Y[sb + jc], Z[sb + jc], W[sb + jc])
                         : inl ? (T)rbuf[inl ? j : 0] : (T)R[jc];
-            r[q] = j < n ? x : czero<T>();
+            r[q] = j < eend ? x : czero<T>();
           }
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
@@ -303,8 +348,8 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           }
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
-            const int j = j0 + q * NT;
-            if (j < n) {
+            const int j = j0 + q * es;
+            if (j < eend) {
               if (last) {
                 R[j] = r[q];
                 const double a2 = abs2(r[q]);
@@ -319,12 +364,17 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           }
         }
         if (lc > 0) {
-          block_sum<2 * GW, NT>(g, sh.ssum);
+          if (slice) {
+            wave_gram_sums<GW>(g, lc, l0, gbuf + wv * GB, lane);
+          } else {
+            block_sum<2 * GW, NT>(g, sh.ssum);
 #pragma unroll
-          for (int u = 0; u < GW; ++u)
-            if (tid == u && u < lc) sh.h[l0 + u] = make_double2(g[2 * u], g[2 * u + 1]);
+            for (int u = 0; u < GW; ++u)
+              if (tid == u && u < lc) sh.h[l0 + u] = make_double2(g[2 * u], g[2 * u + 1]);
+          }
         }
       }
+      if (slice) gram_sums_total<NT / WAVE>(gbuf, kk, sh.h, tid);
     } else {
     for (int j0 = tid; j0 < n; j0 += NT * JC) {
       T a[JC];
@@ -450,31 +500,36 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
       const double2 ucorr = tid < kk ? gram_row_dot(GU + (int64_t)tid * GR, coef,
                                                     (tid / GW) * GW, kk)
                                      : make_double2(0.0, 0.0);
+      const bool slice = BIG && kk <= GB;  // as in the row pass, over the m rows
+      const int wv = tid / WAVE, lane = tid & (WAVE - 1);
+      const int sl = ((m + NT - 1) / NT) * WAVE;
+      const int e0 = slice ? wv * sl + lane : tid, es = slice ? WAVE : NT;
+      const int eend = slice ? min(m, wv * sl + sl) : m;
       for (int l0 = 0; l0 < max(kk, 1); l0 += GW) {
         const int lc = min(GW, kk - l0);
         const bool first = l0 == 0, last = l0 + GW >= kk;
         double g[2 * GW];
 #pragma unroll
         for (int q = 0; q < 2 * GW; ++q) g[q] = 0.0;
-        // JW elements per thread and round, as in the row pass
+        // JW elements per thread and round, sliced or interleaved as in the row pass
         gT* ucol[GW];  // the window's columns of U
 #pragma unroll
         for (int u = 0; u < GW; ++u) ucol[u] = u < lc ? colU(l0 + u) : nullptr;
-        for (int i0 = tid; i0 < m; i0 += NT * JW) {
+        for (int i0 = e0; i0 < eend; i0 += es * JW) {
           T uu[JW][GW], r[JW];
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
-            const int ic = min(i0 + q * NT, m - 1);
+            const int ic = min(i0 + q * es, eend - 1);
 #pragma unroll
             for (int u = 0; u < GW; ++u) uu[q][u] = u < lc ? (T)ucol[u][ic] : czero<T>();
           }
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
-            const int i = i0 + q * NT, ic = min(i, m - 1);
+            const int i = i0 + q * es, ic = min(i, eend - 1);
             const bool inl = i < RL;
             T x = first ? eval_entry<T>(kern, k, X[tb + ic], Y[tb + ic], Z[tb + ic], qx, qy, qz, qw)
                         : inl ? (T)rbuf[inl ? i : 0] : (T)Uk[ic];
-            r[q] = i < m ? x : czero<T>();
+            r[q] = i < eend ? x : czero<T>();
           }
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
@@ -489,8 +544,8 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           }
 #pragma unroll
           for (int q = 0; q < JW; ++q) {
-            const int i = i0 + q * NT;
-            if (i < m) {
+            const int i = i0 + q * es;
+            if (i < eend) {
               if (last) {
                 if (!rused[i]) amax_merge(ub, ui, abs2(r[q]), i);
                 const T us = cmul(r[q], inv);
@@ -505,12 +560,17 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
           }
         }
         if (lc > 0) {
-          block_sum<2 * GW, NT>(g, sh.ssum);
+          if (slice) {
+            wave_gram_sums<GW>(g, lc, l0, gbuf + wv * GB, lane);
+          } else {
+            block_sum<2 * GW, NT>(g, sh.ssum);
 #pragma unroll
-          for (int u = 0; u < GW; ++u)
-            if (tid == u && u < lc) sh.h[l0 + u] = make_double2(g[2 * u], g[2 * u + 1]);
+            for (int u = 0; u < GW; ++u)
+              if (tid == u && u < lc) sh.h[l0 + u] = make_double2(g[2 * u], g[2 * u + 1]);
+          }
         }
       }
+      if (slice) gram_sums_total<NT / WAVE>(gbuf, kk, sh.h, tid);
       __syncthreads();
       // u_l^H u_k (the window sums hold u_l^H times the unscaled column), the cross term, and
       // the new Gram entries
@@ -677,7 +737,7 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
 
 // Length of the LDS residual buffer (a multiple of NT) of the large-block class.  FP64 and
 // 512-thread FP32 workgroups keep most of the partial residual in LDS: 7680 / 15360 entries with
-// 512 threads (one workgroup per CU), 3584 FP64 entries with 256 threads (two per CU).  FP32
+// 512 threads (one workgroup per CU), 3328 FP64 entries with 256 threads (two per CU).  FP32
 // 256-thread workgroups keep 1024 entries and run three per CU, which leaves LDS for the other
 // classes on the same CUs (measured faster for FP32, slower for FP64).  The other classes keep
 // their partial residual in the factor slot.
@@ -685,7 +745,7 @@ template <class T, int NT, bool BIG>
 constexpr int aca_rl() {
   return !BIG ? 0
          : NT >= 512 ? (sizeof(T) == 16 ? 7680 : 15360)
-                     : (sizeof(T) == 16 ? 3584 : 1024);
+                     : (sizeof(T) == 16 ? 3328 : 1024);
 }
 template <class T, int NT, bool BIG>
 constexpr int aca_waves_per_eu() {
@@ -710,6 +770,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(aca_wav
   constexpr int GR = aca_gram_order(NT, BIG ? ACA_KIND_BIG : ACA_KIND_MID);
   __shared__ T coef[CO];
   __shared__ T rbuf[RL > 0 ? RL : 1];
+  __shared__ double2 gbuf[BIG ? (NT / WAVE) * GB : 1];  // per-wavefront Gram sums
   __shared__ AcaShared<NT / WAVE, GR> sh;
   double2* my_gram = gram ? gram + (int64_t)blockIdx.x * 2 * GR * GR : nullptr;
   int64_t a_top = 0, a_end = 0;  // this workgroup's arena: free entries [a_top, a_end) of gpool
@@ -721,7 +782,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(aca_wav
     if (q >= nb) break;
     aca_block<T, NT, BIG, RL, CO>(desc, ufl(order[q]), X, Y, Z, W, kern, kp, tol, flags, rank, ipiv, status,
                          norm2, fresh, gpool, gcap, gtop, my_gram, gram_min, arena, a_top, a_end, coef,
-                         (HMX_LDS T*)rbuf, sh);
+                         (HMX_LDS T*)rbuf, (HMX_LDS double2*)gbuf, sh);
   }
 }
 
