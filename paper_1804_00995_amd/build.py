@@ -26,6 +26,7 @@ UNITS = [
     ("hmx_tune.hip", False),
     ("k_quad.hip", True),
     ("k_scan.hip", False),
+    ("k_sort.hip", False),
     ("k_tree.hip", True),
     ("k_blocks.hip", True),
     ("k_near.hip", False),

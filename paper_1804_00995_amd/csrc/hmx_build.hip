@@ -29,12 +29,6 @@ int64_t quantize_down(int64_t n) {
   return n / step * step;
 }
 
-int64_t next_pow2(int64_t n) {
-  int64_t p = 1;
-  while (p < n) p <<= 1;
-  return p;
-}
-
 // Grow a device array to `cap` entries keeping the first `keep`.
 template <class T>
 void grow(DevBuf<T>& b, size_t cap, size_t keep, hipStream_t s) {
@@ -216,13 +210,14 @@ void build_tree(hmx_op* op, hipStream_t s) {
 // Sort a device list of (t, s) pairs into the lexicographic order of their node ranges.
 void sort_pairs(hmx_op* op, DevBuf<int2>& L, int64_t n, hipStream_t s) {
   if (n <= 1) return;
-  int64_t np = next_pow2(n);
-  DevBuf<uint64_t> key(np);
-  DevBuf<int32_t> val(np);
-  launch_pair_keys(L.p, n, np, op->nbegin.p, op->nlevel.p, key.p, val.p, s);
-  sort_u64_pairs(key.p, val.p, np, s);
+  // key = (begin_t, 63 - level_t, begin_s, 63 - level_s) in 23 + 6 + 23 + 6 bits (M < 2^23)
+  DevBuf<uint64_t> key(n), skey(n);
+  DevBuf<int32_t> val(n), sval(n);
+  DevBuf<unsigned char> tmp;
+  launch_pair_keys(L.p, n, n, op->nbegin.p, op->nlevel.p, key.p, val.p, s);
+  radix_sort_u64_pairs(key.p, skey.p, val.p, sval.p, n, 58, tmp, s);
   DevBuf<int2> out(n);
-  launch_pair_gather(L.p, val.p, n, out.p, s);
+  launch_pair_gather(L.p, sval.p, n, out.p, s);
   HMX_HIP(hipStreamSynchronize(s));
   L = std::move(out);
 }

@@ -150,7 +150,10 @@ void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 void fill_f64(double* p, double v, int64_t n, hipStream_t s);
 void iota_i32(int32_t* p, int64_t n, hipStream_t s);
-void sort_u64_pairs(uint64_t* key, int32_t* val, int64_t n, hipStream_t s);  // n power of two
+// k_sort.hip: ascending radix sort of pairs on key bits [0, end_bit); `tmp` holds the sort's
+// scratch and must outlive the enqueued sort (the caller synchronises before dropping it)
+void radix_sort_u64_pairs(const uint64_t* kin, uint64_t* kout, const int32_t* vin, int32_t* vout,
+                          int64_t n, int end_bit, DevBuf<unsigned char>& tmp, hipStream_t s);
 // k_tree.hip
 void launch_tree_level(int first, int count, const int32_t* nbegin, const int32_t* nend, int leaf,
                        const double* cx, const double* cy, const double* cz, const double* cw,

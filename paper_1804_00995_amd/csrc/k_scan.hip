@@ -1,5 +1,4 @@
-// k_scan.hip -- device utilities used by the build: exclusive prefix sums, fills, and a
-// bitonic sort of unique 64-bit keys (keys are unique, so the resulting order is fully defined).
+// k_scan.hip -- device utilities used by the build: exclusive prefix sums and fills.
 #include "hmx_dev.h"
 #include "hmx_host.h"
 
@@ -122,78 +121,6 @@ void iota_i32(int32_t* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, p, n);
   HMX_LAUNCHED();
-}
-
-// One compare-exchange stage of a bitonic sorting network over n = 2^p elements (ascending).
-__global__ void bitonic_global_kernel(uint64_t* __restrict__ key, int32_t* __restrict__ val,
-                                      int64_t n, int64_t j, int64_t k) {
-  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (i >= n) return;
-  int64_t ixj = i ^ j;
-  if (ixj <= i) return;
-  bool asc = (i & k) == 0;
-  uint64_t a = key[i], b = key[ixj];
-  if ((a > b) == asc) {
-    key[i] = b;
-    key[ixj] = a;
-    int32_t t = val[i];
-    val[i] = val[ixj];
-    val[ixj] = t;
-  }
-}
-
-// All stages with j < LOCAL of one k, inside LDS tiles of 2 * LOCAL... (tile = LOCALN elements).
-constexpr int LOCALN = 2048;
-__global__ void __launch_bounds__(WG) bitonic_local_kernel(uint64_t* __restrict__ key,
-                                                           int32_t* __restrict__ val, int64_t n,
-                                                           int64_t k, int64_t jstart) {
-  __shared__ uint64_t sk[LOCALN];
-  __shared__ int32_t sv[LOCALN];
-  int64_t base = (int64_t)blockIdx.x * LOCALN;
-  for (int t = threadIdx.x; t < LOCALN; t += WG) {
-    sk[t] = key[base + t];
-    sv[t] = val[base + t];
-  }
-  __syncthreads();
-  for (int64_t j = jstart; j > 0; j >>= 1) {
-    for (int t = threadIdx.x; t < LOCALN; t += WG) {
-      int ixj = t ^ (int)j;
-      if (ixj > t) {
-        bool asc = ((base + t) & k) == 0;
-        uint64_t a = sk[t], b = sk[ixj];
-        if ((a > b) == asc) {
-          sk[t] = b;
-          sk[ixj] = a;
-          int32_t tv = sv[t];
-          sv[t] = sv[ixj];
-          sv[ixj] = tv;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  for (int t = threadIdx.x; t < LOCALN; t += WG) {
-    key[base + t] = sk[t];
-    val[base + t] = sv[t];
-  }
-}
-
-void sort_u64_pairs(uint64_t* key, int32_t* val, int64_t n, hipStream_t s) {
-  if (n <= 1) return;
-  unsigned g = (unsigned)((n + WG - 1) / WG);
-  for (int64_t k = 2; k <= n; k <<= 1) {
-    int64_t j = k >> 1;
-    for (; j > 0; j >>= 1) {
-      if (n >= LOCALN && j < LOCALN) {
-        hipLaunchKernelGGL(bitonic_local_kernel, dim3((unsigned)(n / LOCALN)), dim3(WG), 0, s, key,
-                           val, n, k, j);
-        HMX_LAUNCHED();
-        break;
-      }
-      hipLaunchKernelGGL(bitonic_global_kernel, dim3(g), dim3(WG), 0, s, key, val, n, j, k);
-      HMX_LAUNCHED();
-    }
-  }
 }
 
 }  // namespace hmx
