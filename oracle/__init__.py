@@ -47,7 +47,11 @@ def lib():
         L.hmo_dense_rows.argtypes = [P, P, P, P, i64, i32, f64, P, P, i64, P, i32]
         L.hmo_aca_dense.argtypes = [P, i64, i64, f64, i64, P, P, i64, P]
         L.hmo_aca_dense.restype = C.c_int
-        L.hmo_hbuild.argtypes = [P, P, P, P, i64, i32, f64, i32, f64, f64, i32, i64]
+        L.hmo_hbuild.argtypes = [P, P, P, P, i64, i32, f64, i32, f64, f64, i32, i64, P, P, i32, P,
+                                 f64]
+        L.hmo_tri_moments.argtypes = [P, P, P]
+        L.hmo_tri_lagrange.argtypes = [P, P, P, P]
+        L.hmo_reg_apply.argtypes = [P, P, P, P, i64, P, P, i64, i32, P, f64, P, P, i32]
         L.hmo_hbuild.restype = P
         L.hmo_hmatvec.argtypes = [P, P, P]
         L.hmo_hinfo.argtypes = [P, P]
@@ -135,15 +139,78 @@ def aca_dense(A, tol, rcap=None):
     return U[:k].T.copy(), V[:k].T.copy(), bool(rc)
 
 
-class HMatrix:
-    """Oracle H-matrix: cluster tree, block tree, dense near blocks, reference ACA far blocks."""
+# ------------------------------------------------------------------ singular correction (O7)
+def lagrange_matrix(bary):
+    """Coefficients of the linear functions through a 3-point rule (Section 5.2 reading): row q
+    holds c_qi with L_q = sum_i c_qi lambda_i and L_q(point p) = delta_qp, i.e. (B^-1)^T for B the
+    rule's barycentric coordinates (one point per row)."""
+    B = np.asarray(bary, np.float64).reshape(-1, 3)
+    if B.shape[0] != 3:
+        raise ValueError("the correction needs a 3-point rule")
+    return np.ascontiguousarray(np.linalg.inv(B).T)
 
-    def __init__(self, pts, w, kern, k, leaf=64, eta=1.5, tol=1e-3, nthreads=0, max_mn=0):
+
+def tri_moments(x, tv):
+    """(I1, Irho): int_T 1/|x-y| dy and int_T (y - rho)/|x-y| dy, rho the projection of x on
+    the plane of T = tv (3 x 3, one vertex per row)."""
+    x = np.ascontiguousarray(x, np.float64)
+    tv = np.ascontiguousarray(tv, np.float64)
+    out = np.empty(4)
+    lib().hmo_tri_moments(_p(x), _p(tv), _p(out))
+    return out[0], out[1:].copy()
+
+
+def tri_lagrange(x, tv, lag):
+    """int_T L_q(y)/|x-y| dy for q = 0, 1, 2 (L_q = sum_i lag[q, i] lambda_i)."""
+    x = np.ascontiguousarray(x, np.float64)
+    tv = np.ascontiguousarray(tv, np.float64)
+    lag = np.ascontiguousarray(lag, np.float64)
+    out = np.empty(3)
+    lib().hmo_tri_lagrange(_p(x), _p(tv), _p(lag), _p(out))
+    return out
+
+
+def reg_apply(pts, w, vtx, tri, bary, alpha, x, nthreads=0):
+    """C x: the singular correction of every close pair applied to x (points of the 3-point rule
+    bary on mesh (vtx, tri), triangle-major)."""
+    X, Y, Z = _soa(pts)
+    w = np.ascontiguousarray(w, np.float64)
+    vtx = np.ascontiguousarray(vtx, np.float64)
+    tri = np.ascontiguousarray(tri, np.int32)
+    lag = lagrange_matrix(bary)
+    x = np.ascontiguousarray(x, np.complex128)
+    y = np.empty(X.shape[0], np.complex128)
+    lib().hmo_reg_apply(_p(X), _p(Y), _p(Z), _p(w), X.shape[0], _p(vtx), _p(tri), tri.shape[0], 3,
+                        _p(lag), alpha, _p(x), _p(y), nthreads)
+    return y
+
+
+def reg_dense_matvec(pts, w, kern, k, vtx, tri, bary, alpha, x, nthreads=0):
+    """The regularized dense product: K x plus the correction of every close pair."""
+    return dense_matvec(pts, w, kern, k, x, nthreads) + reg_apply(pts, w, vtx, tri, bary, alpha, x,
+                                                                  nthreads)
+
+
+class HMatrix:
+    """Oracle H-matrix: cluster tree, block tree, dense near blocks, reference ACA far blocks.
+
+    mesh = (vtx, tri, bary) and reg_radius = alpha add the singular correction to the close
+    pairs of the near blocks."""
+
+    def __init__(self, pts, w, kern, k, leaf=64, eta=1.5, tol=1e-3, nthreads=0, max_mn=0, mesh=None,
+                 reg_radius=2.0):
         X, Y, Z = _soa(pts)
         w = np.ascontiguousarray(w, np.float64)
         self.M = X.shape[0]
+        vtx = tri = lag = None
+        if mesh is not None:
+            vtx = np.ascontiguousarray(mesh[0], np.float64)
+            tri = np.ascontiguousarray(mesh[1], np.int32)
+            lag = lagrange_matrix(mesh[2])
         self._h = lib().hmo_hbuild(_p(X), _p(Y), _p(Z), _p(w), self.M, kern, k, leaf, eta, tol, nthreads,
-                                   max_mn)
+                                   max_mn, None if vtx is None else _p(vtx),
+                                   None if tri is None else _p(tri), 3,
+                                   None if lag is None else _p(lag), float(reg_radius))
         info = np.zeros(9, np.int64)
         lib().hmo_hinfo(self._h, _p(info))
         keys = ["n_nodes", "n_near", "n_far", "s_near", "s_far", "n_dense_far", "s_dense_far",

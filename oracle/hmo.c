@@ -19,6 +19,9 @@
  *                                           the Frobenius-norm stopping rule at tolerance tol.
  *   O6 H-matrix times vector .............. Section 5.3 (the compressed matrix used like a
  *                                           matrix through the product operator).
+ *   O7 singular correction ................ Section 5.2 (regularization of the kernels): the
+ *                                           1/(4 pi r) part integrated in y analytically over
+ *                                           close source triangles, minus its Gauss value.
  * Pinned by the CPU tests: closed-form sphere eigenvalues, quadrature exactness, exact-rank and
  * SVD (Eckart-Young) bounds for ACA, brute-force coverage of the block partition.
  */
@@ -114,6 +117,203 @@ void hmo_dense_rows(const double *X, const double *Y, const double *Z, const dou
             acc += green(kern, k, xi, xl) * W[l] * x[l];
         }
         y[ii] = acc;
+    }
+}
+
+/* ---------------------------------------------------------------- O7: singular correction */
+/* Section 5.2 (regularization of the kernels).  The kernel behaves like 1/(4 pi |x - y|) as
+ * y -> x; that part is integrated over the source triangle exactly in y while x stays a
+ * quadrature point, and the Gauss-rule value of the same integral is subtracted, for close pairs
+ * only (a sparse correction).
+ *
+ * Reading (the paper corrects Galerkin entries of a finite element space; this operator acts on
+ * values at the quadrature points): a rule of three non-collinear points per triangle carries
+ * exactly one linear function per triangle through the three values, so the trial function of
+ * point q of triangle T is L_q, the linear function on T with L_q = 1 at its q-th point and 0 at
+ * the other two.  The correction of the pair (target x, source point y_l = q-th point of T) is
+ *   c(x, l) = ( int_T L_q(y) / |x - y| dy  -  g(x, y_l) w_l ) / (4 pi),
+ * g(x, y) = 1 / |x - y|, and g = 0 when x = y (the operator sets its r = 0 entries to 0, so
+ * nothing is subtracted there).  A pair is close when |x - c_T| <= alpha * d_T (c_T the
+ * centroid, d_T the longest edge of T).
+ *
+ * The y-integrals over a flat triangle T = (v0, v1, v2) use the edge sums of Wilton, Rao,
+ * Glisson, Schaubert, Al-Bundak and Butler (IEEE Trans. Antennas Propag. 32(3), 1984) and
+ * Graglia (IEEE Trans. Antennas Propag. 41(10), 1993).  With n the unit normal of
+ * (v1 - v0) x (v2 - v0), h = n.(x - v0), rho = x - h n the projection of x on the plane, and for
+ * each edge (a, b) = (v_i, v_{i+1}) its unit direction s, in-plane outward normal m = s x n,
+ * l+ = (b - rho).s, l- = (a - rho).s, P = (a - rho).m, R0^2 = P^2 + h^2, R+- = sqrt(R0^2 + l+-^2),
+ * f = ln((R+ + l+) / (R- + l-)):
+ *   I1      = int_T 1 / |x - y| dy        = sum_edges [ P f - |h| (atan(P l+ / (R0^2 + |h| R+))
+ *                                                               - atan(P l- / (R0^2 + |h| R-))) ]
+ *   Irho    = int_T (y - rho) / |x - y| dy = sum_edges m (R0^2 f + l+ R+ - l- R-) / 2.
+ * An edge whose line passes through x (R0 = 0) contributes only m (l+ R+ - l- R-) / 2 (the other
+ * terms vanish with P and R0).  R + l is evaluated as R0^2 / (R - l) when l < 0 (the same number,
+ * without cancellation). */
+static void sub3(const double *a, const double *b, double *c)
+{
+    c[0] = a[0] - b[0];
+    c[1] = a[1] - b[1];
+    c[2] = a[2] - b[2];
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double r_plus_l(double R, double l, double R02) { return l >= 0.0 ? R + l : R02 / (R - l); }
+
+/* out = {I1, Irho_x, Irho_y, Irho_z} for target x and triangle tv = (v0, v1, v2) (9 doubles). */
+void hmo_tri_moments(const double *x, const double *tv, double *out)
+{
+    const double *v[3] = {tv, tv + 3, tv + 6};
+    double e1[3], e2[3], N[3], n[3], rho[3];
+    sub3(v[1], v[0], e1);
+    sub3(v[2], v[0], e2);
+    cross3(e1, e2, N);
+    double A2 = sqrt(dot3(N, N));
+    for (int d = 0; d < 3; ++d) n[d] = N[d] / A2;
+    double xv[3];
+    sub3(x, v[0], xv);
+    double h = dot3(n, xv), ah = fabs(h);
+    for (int d = 0; d < 3; ++d) rho[d] = x[d] - h * n[d];
+    double I1 = 0.0, Ir[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 3; ++i) {
+        const double *a = v[i], *b = v[(i + 1) % 3];
+        double s[3], m[3], br[3], ar[3];
+        sub3(b, a, s);
+        double L = sqrt(dot3(s, s));
+        for (int d = 0; d < 3; ++d) s[d] /= L;
+        cross3(s, n, m);
+        sub3(b, rho, br);
+        sub3(a, rho, ar);
+        double lp = dot3(br, s), lm = dot3(ar, s), P = dot3(ar, m);
+        double R02 = P * P + h * h;
+        double Rp = sqrt(R02 + lp * lp), Rm = sqrt(R02 + lm * lm);
+        double c = 0.5 * (lp * Rp - lm * Rm);
+        if (R02 > 1e-24 * L * L) {
+            double f = log(r_plus_l(Rp, lp, R02) / r_plus_l(Rm, lm, R02));
+            double beta = atan(P * lp / (R02 + ah * Rp)) - atan(P * lm / (R02 + ah * Rm));
+            I1 += P * f - ah * beta;
+            c += 0.5 * R02 * f;
+        }
+        for (int d = 0; d < 3; ++d) Ir[d] += c * m[d];
+    }
+    out[0] = I1;
+    out[1] = Ir[0];
+    out[2] = Ir[1];
+    out[3] = Ir[2];
+}
+
+/* out[q] = int_T L_q(y) / |x - y| dy for q = 0, 1, 2, where L_q = sum_i lag[3 q + i] lambda_i
+ * (lambda_i the barycentric coordinates of T).  Each lambda_i is affine, so with rho the
+ * projection of x: int lambda_i / R = lambda_i(rho) I1 + grad(lambda_i) . Irho. */
+void hmo_tri_lagrange(const double *x, const double *tv, const double *lag, double *out)
+{
+    const double *v[3] = {tv, tv + 3, tv + 6};
+    double mom[4];
+    hmo_tri_moments(x, tv, mom);
+    double e1[3], e2[3], N[3], n[3], xv[3], rho[3];
+    sub3(v[1], v[0], e1);
+    sub3(v[2], v[0], e2);
+    cross3(e1, e2, N);
+    double A2 = sqrt(dot3(N, N));
+    for (int d = 0; d < 3; ++d) n[d] = N[d] / A2;
+    sub3(x, v[0], xv);
+    double h = dot3(n, xv);
+    for (int d = 0; d < 3; ++d) rho[d] = x[d] - h * n[d];
+    double J[3];
+    for (int i = 0; i < 3; ++i) {
+        const double *b = v[(i + 1) % 3], *c = v[(i + 2) % 3];
+        double br[3], cr[3], bc[3], cb[3], g[3];
+        sub3(b, rho, br);
+        sub3(c, rho, cr);
+        cross3(br, cr, bc);
+        double lam = dot3(bc, n) / A2; /* lambda_i(rho) */
+        sub3(c, b, cb);
+        cross3(n, cb, g);              /* A2 * grad(lambda_i) */
+        J[i] = lam * mom[0] + (g[0] * mom[1] + g[1] * mom[2] + g[2] * mom[3]) / A2;
+    }
+    for (int q = 0; q < 3; ++q) out[q] = lag[3 * q] * J[0] + lag[3 * q + 1] * J[1] + lag[3 * q + 2] * J[2];
+}
+
+/* Mesh data of the correction: vertices, triangles, points per triangle (3), the Lagrange
+ * matrix of the rule and the closeness factor alpha. */
+typedef struct {
+    const double *vtx;
+    const int32_t *tri;
+    int32_t nq;
+    double lag[9];
+    double alpha;
+} reg_t;
+
+static void tri_vertices(const reg_t *R, int64_t t, double *tv)
+{
+    for (int j = 0; j < 3; ++j)
+        for (int d = 0; d < 3; ++d) tv[3 * j + d] = R->vtx[3 * (int64_t)R->tri[3 * t + j] + d];
+}
+
+/* Is triangle tv close to x: |x - c_T|^2 <= alpha^2 d_T^2. */
+static int tri_close(const reg_t *R, const double *x, const double *tv)
+{
+    double c[3], e[3], d2 = 0.0;
+    for (int d = 0; d < 3; ++d) c[d] = (tv[d] + tv[3 + d] + tv[6 + d]) / 3.0;
+    for (int j = 0; j < 3; ++j) {
+        sub3(tv + 3 * ((j + 1) % 3), tv + 3 * j, e);
+        double l2 = dot3(e, e);
+        if (l2 > d2) d2 = l2;
+    }
+    double xc[3];
+    sub3(x, c, xc);
+    return dot3(xc, xc) <= R->alpha * R->alpha * d2;
+}
+
+/* c(x, l) of the definition above for source point l (original index) at y with weight w, or 0
+ * when the pair is not close. */
+static double reg_corr(const reg_t *R, const double *x, int64_t l, const double *y, double w)
+{
+    int64_t t = l / R->nq;
+    int q = (int)(l - t * R->nq);
+    double tv[9];
+    tri_vertices(R, t, tv);
+    if (!tri_close(R, x, tv)) return 0.0;
+    double J[3];
+    hmo_tri_lagrange(x, tv, R->lag, J);
+    double xy[3];
+    sub3(x, y, xy);
+    double r = sqrt(dot3(xy, xy));
+    double gauss = r == 0.0 ? 0.0 : w / r;
+    return (J[q] - gauss) / (4.0 * PI);
+}
+
+/* y_i = sum over every close pair (i, l) of c(x_i, l) x_l, for all M points (points are the
+ * nq-point rule's, triangle-major: l = nq t + q). */
+void hmo_reg_apply(const double *X, const double *Y, const double *Z, const double *W, int64_t M,
+                   const double *vtx, const int32_t *tri, int64_t ntri, int32_t nq, const double *lag,
+                   double alpha, const cplx *x, cplx *y, int32_t nthreads)
+{
+    set_threads(nthreads);
+    reg_t R = {vtx, tri, nq, {0}, alpha};
+    memcpy(R.lag, lag, sizeof(R.lag));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < M; ++i) {
+        double xi[3] = {X[i], Y[i], Z[i]};
+        cplx acc = 0.0;
+        for (int64_t t = 0; t < ntri; ++t) {
+            double tv[9];
+            tri_vertices(&R, t, tv);
+            if (!tri_close(&R, xi, tv)) continue;
+            for (int q = 0; q < nq; ++q) {
+                int64_t l = nq * t + q;
+                double yl[3] = {X[l], Y[l], Z[l]};
+                acc += reg_corr(&R, xi, l, yl, W[l]) * x[l];
+            }
+        }
+        y[i] = acc;
     }
 }
 
@@ -471,6 +671,8 @@ typedef struct {
     cplx **nearK;        /* per near block, m x n column-major */
     aca_t *farF;         /* per far block */
     cplx **farDense;     /* per far block: dense fallback (or NULL) */
+    int has_reg;         /* near blocks carry the singular correction (O7) */
+    reg_t reg;
 } hmo_h;
 
 typedef struct {
@@ -497,12 +699,38 @@ static cplx *dense_block(const hmo_h *H, int64_t tb, int64_t m, int64_t sb, int6
     return K;
 }
 
+/* O7 inside the H-matrix: the close pairs of a near block get their correction (far blocks,
+ * including those stored dense, keep the plain kernel). */
+static void correct_block(const hmo_h *H, cplx *K, int64_t tb, int64_t m, int64_t sb, int64_t n)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t gj = H->T.perm[sb + j];
+        double yj[3] = {H->X[gj], H->Y[gj], H->Z[gj]};
+        for (int64_t i = 0; i < m; ++i) {
+            int64_t gi = H->T.perm[tb + i];
+            double xi[3] = {H->X[gi], H->Y[gi], H->Z[gi]};
+            K[j * m + i] += reg_corr(&H->reg, xi, gj, yj, H->W[gj]);
+        }
+    }
+}
+
+/* vtx == NULL: no correction; otherwise the near blocks carry O7 for the mesh (vtx, tri) whose
+ * nq-point rule produced the points, with Lagrange matrix lag and closeness factor alpha. */
 void *hmo_hbuild(const double *X, const double *Y, const double *Z, const double *W, int64_t M,
                  int32_t kern, double k, int32_t leaf, double eta, double tol, int32_t nthreads,
-                 int64_t max_mn)
+                 int64_t max_mn, const double *vtx, const int32_t *tri, int32_t nq,
+                 const double *lag, double alpha)
 {
     set_threads(nthreads);
     hmo_h *H = calloc(1, sizeof(hmo_h));
+    if (vtx) {
+        H->has_reg = 1;
+        H->reg.vtx = vtx;
+        H->reg.tri = tri;
+        H->reg.nq = nq;
+        memcpy(H->reg.lag, lag, sizeof(H->reg.lag));
+        H->reg.alpha = alpha;
+    }
     H->M = M;
     H->kern = kern;
     H->k = k;
@@ -545,6 +773,9 @@ void *hmo_hbuild(const double *X, const double *Y, const double *Z, const double
     for (int64_t b = 0; b < nn; ++b) {
         int32_t t = H->nearL.t[b], s = H->nearL.s[b];
         H->nearK[b] = dense_block(H, T->begin[t], T->end[t] - T->begin[t], T->begin[s], T->end[s] - T->begin[s]);
+        if (H->has_reg)
+            correct_block(H, H->nearK[b], T->begin[t], T->end[t] - T->begin[t], T->begin[s],
+                          T->end[s] - T->begin[s]);
     }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t b = 0; b < nf; ++b) {
