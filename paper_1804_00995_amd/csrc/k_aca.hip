@@ -747,15 +747,20 @@ constexpr int aca_rl() {
          : NT >= 512 ? (sizeof(T) == 16 ? 7680 : 15360)
                      : (sizeof(T) == 16 ? 3328 : 1024);
 }
-template <class T, int NT, bool BIG>
+// Minimum waves per SIMD the register allocation has to allow.  The FP32 small-block kind is
+// bound by the latency of its steps, not by bandwidth: six waves per SIMD (a few spilled
+// registers) run more blocks at once and measured faster than five without spills; in FP64 the
+// same limit spills more and gained nothing.
+template <class T, int NT, bool BIG, int CO>
 constexpr int aca_waves_per_eu() {
-  return BIG && !(sizeof(T) == 8 && NT == 256) ? 2 : 3;
+  return BIG ? (sizeof(T) == 8 && NT == 256 ? 3 : 2)
+             : (CO < ACA_COEF_MAX && sizeof(T) == 8 ? 6 : 3);
 }
 
 // BIG: the large-block class (long Gram windows, LDS residual); CO: the coefficient capacity
 // (ACA_COEF_SMALL for the small-block class)
 template <class T, int NT, bool BIG, int CO = ACA_COEF_MAX>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(aca_waves_per_eu<T, NT, BIG>()))) aca_kernel(FarDesc* __restrict__ desc,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(aca_waves_per_eu<T, NT, BIG, CO>()))) aca_kernel(FarDesc* __restrict__ desc,
                                                  const int32_t* __restrict__ order, int nb,
                                                  int* counter, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
