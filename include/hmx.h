@@ -115,11 +115,24 @@ typedef struct {
   int32_t aca_wave; /* 1: blocks with m, n <= 64 run one per wavefront with their factors in
                        registers; 0 (default): they go to the small-block class, which was
                        measured faster on MI355X (FP64 by about 2 ms at 245 760 points) */
+  /* Singular correction (Section 5.2, regularization of the kernels): with regularize = 1 every
+   * close pair of the near field gets, on top of its kernel entry, the exact y-integral of the
+   * 1/(4 pi r) part over the source triangle minus that part's Gauss value (nothing is subtracted
+   * for r = 0, whose entry is 0).  The three rule points of a triangle carry the linear function
+   * through their values, so the rule must have 3 non-collinear points.  A pair (x, point of
+   * triangle T) is close when |x - centroid(T)| <= reg_radius * (longest edge of T); close pairs
+   * that fall in far blocks keep the plain kernel.  Needs a mesh (hmx_build, hmx_build_batch;
+   * HMX_EINVAL for hmx_build_points), the Laplace or Helmholtz kernel (else HMX_EINVAL) and
+   * tol > 0 (HMX_EUNSUPPORTED for the dense operator).  The correction is assembled into the
+   * near-field blocks: the product costs the same with or without it. */
+  int32_t regularize; /* 0 (default) or 1 */
+  double reg_radius;  /* > 0 (default 2) */
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
  * initial_rank 16, force_pred_scale 1, no rank cap, no pool limit, ACA schedule 4096 / 1024 /
- * concurrent / arenas, one row share, far blocks up to 16384 points. */
+ * concurrent / arenas, one row share, far blocks up to 16384 points, no singular correction
+ * (reg_radius 2). */
 hmx_status hmx_params_default(hmx_params* p);
 
 typedef struct hmx_op hmx_op; /* opaque, library-owned; free with hmx_destroy */

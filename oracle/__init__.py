@@ -51,7 +51,7 @@ def lib():
                                  f64]
         L.hmo_tri_moments.argtypes = [P, P, P]
         L.hmo_tri_lagrange.argtypes = [P, P, P, P]
-        L.hmo_reg_apply.argtypes = [P, P, P, P, i64, P, P, i64, i32, P, f64, P, P, i32]
+        L.hmo_reg_apply.argtypes = [P, P, P, P, i64, P, P, i64, i32, P, f64, P, P, i64, P, i32]
         L.hmo_hbuild.restype = P
         L.hmo_hmatvec.argtypes = [P, P, P]
         L.hmo_hinfo.argtypes = [P, P]
@@ -170,25 +170,30 @@ def tri_lagrange(x, tv, lag):
     return out
 
 
-def reg_apply(pts, w, vtx, tri, bary, alpha, x, nthreads=0):
-    """C x: the singular correction of every close pair applied to x (points of the 3-point rule
-    bary on mesh (vtx, tri), triangle-major)."""
+def reg_apply(pts, w, vtx, tri, bary, alpha, x, rows=None, nthreads=0):
+    """(C x)[rows]: the singular correction of every close pair applied to x (points of the
+    3-point rule bary on mesh (vtx, tri), triangle-major); all rows when rows is None."""
     X, Y, Z = _soa(pts)
     w = np.ascontiguousarray(w, np.float64)
     vtx = np.ascontiguousarray(vtx, np.float64)
     tri = np.ascontiguousarray(tri, np.int32)
     lag = lagrange_matrix(bary)
     x = np.ascontiguousarray(x, np.complex128)
-    y = np.empty(X.shape[0], np.complex128)
+    if rows is None:
+        rp, nr = None, X.shape[0]
+    else:
+        rows = np.ascontiguousarray(rows, np.int64)
+        rp, nr = _p(rows), rows.shape[0]
+    y = np.empty(nr, np.complex128)
     lib().hmo_reg_apply(_p(X), _p(Y), _p(Z), _p(w), X.shape[0], _p(vtx), _p(tri), tri.shape[0], 3,
-                        _p(lag), alpha, _p(x), _p(y), nthreads)
+                        _p(lag), alpha, _p(x), rp, nr, _p(y), nthreads)
     return y
 
 
 def reg_dense_matvec(pts, w, kern, k, vtx, tri, bary, alpha, x, nthreads=0):
     """The regularized dense product: K x plus the correction of every close pair."""
     return dense_matvec(pts, w, kern, k, x, nthreads) + reg_apply(pts, w, vtx, tri, bary, alpha, x,
-                                                                  nthreads)
+                                                                  nthreads=nthreads)
 
 
 class HMatrix:

@@ -290,17 +290,20 @@ static double reg_corr(const reg_t *R, const double *x, int64_t l, const double 
     return (J[q] - gauss) / (4.0 * PI);
 }
 
-/* y_i = sum over every close pair (i, l) of c(x_i, l) x_l, for all M points (points are the
- * nq-point rule's, triangle-major: l = nq t + q). */
+/* y_ii = sum over every close pair (i, l) of c(x_i, l) x_l for the requested rows i = rows[ii]
+ * (all M rows when rows is NULL); points are the nq-point rule's, triangle-major: l = nq t + q. */
 void hmo_reg_apply(const double *X, const double *Y, const double *Z, const double *W, int64_t M,
                    const double *vtx, const int32_t *tri, int64_t ntri, int32_t nq, const double *lag,
-                   double alpha, const cplx *x, cplx *y, int32_t nthreads)
+                   double alpha, const cplx *x, const int64_t *rows, int64_t nrows, cplx *y,
+                   int32_t nthreads)
 {
     set_threads(nthreads);
     reg_t R = {vtx, tri, nq, {0}, alpha};
     memcpy(R.lag, lag, sizeof(R.lag));
+    if (!rows) nrows = M;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t i = 0; i < M; ++i) {
+    for (int64_t ii = 0; ii < nrows; ++ii) {
+        int64_t i = rows ? rows[ii] : ii;
         double xi[3] = {X[i], Y[i], Z[i]};
         cplx acc = 0.0;
         for (int64_t t = 0; t < ntri; ++t) {
@@ -313,7 +316,7 @@ void hmo_reg_apply(const double *X, const double *Y, const double *Z, const doub
                 acc += reg_corr(&R, xi, l, yl, W[l]) * x[l];
             }
         }
-        y[i] = acc;
+        y[ii] = acc;
     }
 }
 

@@ -30,6 +30,7 @@ UNITS = [
     ("k_tree.hip", True),
     ("k_blocks.hip", True),
     ("k_near.hip", False),
+    ("k_reg.hip", True),
     ("k_aca.hip", False),
     ("k_far.hip", False),
     ("k_matvec.hip", False),

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "hmx_host.h"
+#include "hmx_reg_dev.h"
 
 using namespace hmx;
 
@@ -67,6 +68,8 @@ void defaults(hmx_params* p) {
   p->row_share = 0;
   p->force_pool_bytes = 0;
   p->max_far_mn = 16384;
+  p->regularize = 0;
+  p->reg_radius = 2.0;
 }
 
 hmx_params resolve(const hmx_params* in) {
@@ -112,6 +115,11 @@ hmx_params resolve(const hmx_params* in) {
   HMX_REQUIRE(p.max_far_mn >= 0, HMX_EINVAL, "max_far_mn must be >= 0");
   HMX_REQUIRE(p.row_shares == 1 || p.tol > 0, HMX_EUNSUPPORTED,
               "row shares need an H-matrix operator (tol > 0)");
+  HMX_REQUIRE(p.regularize == 0 || p.regularize == 1, HMX_EINVAL, "regularize must be 0 or 1");
+  HMX_REQUIRE(std::isfinite(p.reg_radius) && p.reg_radius > 0, HMX_EINVAL,
+              "reg_radius must be finite and > 0");
+  HMX_REQUIRE(p.regularize == 0 || p.tol > 0, HMX_EUNSUPPORTED,
+              "the singular correction needs an H-matrix operator (tol > 0)");
   return p;
 }
 
@@ -148,6 +156,30 @@ void check_build_args(int32_t kern, double k) {
   HMX_REQUIRE(std::isfinite(k) && k >= 0, HMX_EINVAL, "k must be finite and >= 0");
 }
 
+// Singular correction (Section 5.2): the rule's three points carry one linear function per
+// triangle; lag[3 q + i] is the coefficient of lambda_i in L_q, the function equal to 1 at point
+// q and 0 at the two others.  With B[q][i] the barycentric coordinates of point q,
+// L_q(point p) = sum_i lag[q][i] B[p][i] = delta_qp, so lag = (B^-1)^T (inverse by cofactors).
+void setup_reg(hmx_op* op, const Rule& r, int32_t kern) {
+  HMX_REQUIRE(kern == HMX_LAPLACE || kern == HMX_HELMHOLTZ, HMX_EINVAL,
+              "the singular correction needs the Laplace or Helmholtz kernel");
+  HMX_REQUIRE(r.nq == 3, HMX_EINVAL, "the singular correction needs a 3-point rule");
+  const double(*B)[3] = r.b;
+  double cof[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      cof[i][j] = B[i1][j1] * B[i2][j2] - B[i1][j2] * B[i2][j1];
+    }
+  const double det = B[0][0] * cof[0][0] + B[0][1] * cof[0][1] + B[0][2] * cof[0][2];
+  HMX_REQUIRE(std::fabs(det) > 1e-9, HMX_EINVAL,
+              "the singular correction needs three non-collinear rule points");
+  // (B^-1)[i][q] = cof[q][i] / det, so lag[q][i] = (B^-1)[i][q] = cof[q][i] / det
+  for (int q = 0; q < 3; ++q)
+    for (int i = 0; i < 3; ++i) op->reg_lag[3 * q + i] = cof[q][i] / det;
+  op->reg = true;
+}
+
 }  // namespace
 
 int64_t hmx_op::bytes() const {
@@ -157,7 +189,7 @@ int64_t hmx_op::bytes() const {
              near_m.bytes() + near_sb.bytes() + near_n.bytes() + near_off.bytes() +
              near_ptr.bytes() + near_pool.bytes() + farL.bytes() + far.bytes() +
              dense_pool.bytes() + far_ptr.bytes() + far_list.bytes() + xp.bytes() + tbuf.bytes() +
-             partial.bytes();
+             partial.bytes() + tgeo.bytes();
   for (const auto& p : far_pools) b += p.bytes();
   return (int64_t)b;
 }
@@ -205,6 +237,7 @@ hmx_status hmx_build(const double* vtx, int64_t n_vtx, const int32_t* tri, int64
   op->k = k;
   op->p = prm;
   op->prec = prm.precision;
+  if (prm.regularize) setup_reg(op.get(), r, kern);  // host checks before any device work
   op->X.alloc(op->M);
   op->Y.alloc(op->M);
   op->Z.alloc(op->M);
@@ -215,6 +248,11 @@ hmx_status hmx_build(const double* vtx, int64_t n_vtx, const int32_t* tri, int64
   int e = read1(err.p, s);
   HMX_REQUIRE(!(e & 1), HMX_EINVAL, "triangle vertex index out of range");
   HMX_REQUIRE(!(e & 2), HMX_EINVAL, "non-finite vertex coordinate");
+  if (prm.regularize) {
+    // triangle records (the indices were checked above)
+    op->tgeo.alloc((size_t)n_tri * TGEO);
+    launch_tri_geom(vtx, tri, n_tri, prm.reg_radius, op->tgeo.p, s);
+  }
   finish_build(op.get(), s);
   *out = op.release();
   return HMX_OK;
@@ -228,6 +266,7 @@ hmx_status hmx_build_points(const double* xyzw, int64_t M, int32_t kern, double 
   HMX_REQUIRE(M >= 1, HMX_EINVAL, "M must be >= 1");
   check_build_args(kern, k);
   hmx_params prm = resolve(p);
+  HMX_REQUIRE(!prm.regularize, HMX_EINVAL, "the singular correction needs the mesh (hmx_build)");
   hipStream_t s = as_stream(stream);
   auto op = std::make_unique<hmx_op>();
   op->M = M;
@@ -356,6 +395,7 @@ hmx_status hmx_build_batch(const hmx_mesh* meshes, int32_t n_meshes, const doubl
   op->k = op->mesh_k[0];
   op->p = prm;
   op->prec = prm.precision;
+  if (prm.regularize) setup_reg(op.get(), r, kern);  // host checks before any device work
   op->X.alloc(op->M);
   op->Y.alloc(op->M);
   op->Z.alloc(op->M);
@@ -370,6 +410,13 @@ hmx_status hmx_build_batch(const hmx_mesh* meshes, int32_t n_meshes, const doubl
   int e = read1(err.p, s);
   HMX_REQUIRE(!(e & 1), HMX_EINVAL, "triangle vertex index out of range");
   HMX_REQUIRE(!(e & 2), HMX_EINVAL, "non-finite vertex coordinate");
+  if (prm.regularize) {
+    // the records of all meshes, concatenated like their points (triangle o / 3 of point o)
+    op->tgeo.alloc((size_t)(op->M / n_q) * TGEO);
+    for (int32_t i = 0; i < n_meshes; ++i)
+      launch_tri_geom(meshes[i].vtx, meshes[i].tri, meshes[i].n_tri, prm.reg_radius,
+                      op->tgeo.p + (op->mesh_off[i] / n_q) * TGEO, s);
+  }
   finish_build(op.get(), s);
   *out = op.release();
   return HMX_OK;

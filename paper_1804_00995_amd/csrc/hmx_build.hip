@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "hmx_host.h"
+#include "hmx_reg_dev.h"
 
 namespace hmx {
 namespace {
@@ -310,8 +311,16 @@ void build_near(hmx_op* op, hipStream_t s) {
   if (op->p.pool_limit_bytes > 0 && (int64_t)bytes > op->p.pool_limit_bytes)
     throw Error(HMX_ENOMEM, "near field exceeds pool_limit_bytes");
   op->near_pool.alloc(std::max<size_t>(bytes, 1));
+  // the singular correction of close pairs (Section 5.2) goes into the near field only
+  RegArgs ra{};
+  if (op->reg) {
+    ra.perm = op->perm.p;
+    ra.tgeo = op->tgeo.p;
+    std::copy(op->reg_lag, op->reg_lag + 9, ra.lag);
+  }
   launch_assemble<T>(op->near_tb.p, op->near_m.p, op->near_sb.p, op->near_n.p, op->near_off.p, nn,
-                     op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, (T*)op->near_pool.p, s);
+                     op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p, (T*)op->near_pool.p,
+                     op->reg ? &ra : nullptr, s);
   HMX_HIP(hipStreamSynchronize(s));
 }
 
@@ -666,7 +675,7 @@ void build_far(hmx_op* op, hipStream_t s) {
                              dm.p, dsb.p, dn.p, dofs.p, s);
     if (h.nd > 0)
       launch_assemble<T>(dtb.p, dm.p, dsb.p, dn.p, dofs.p, h.nd, op->X.p, op->Y.p, op->Z.p,
-                         op->W.p, op->kern, op->kpt.p, (T*)op->dense_pool.p, s);
+                         op->W.p, op->kern, op->kpt.p, (T*)op->dense_pool.p, nullptr, s);
     HMX_HIP(hipStreamSynchronize(s));
   }
   // keep the pools (they hold the factors)

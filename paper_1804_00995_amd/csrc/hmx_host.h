@@ -199,12 +199,16 @@ void launch_pair_ranges(const int2* pairs, int64_t n, const int32_t* nbegin, con
 void launch_leaf_far_fill(int n_leaves, const int32_t* leaves, const int32_t* parent,
                           const int64_t* node_cnt, const int32_t* node_first,
                           const int64_t* leaf_ptr, int32_t* list, hipStream_t s);
-// k_near.hip  (T = double2 or float2)
+// k_near.hip  (T = double2 or float2); reg: the singular correction of close pairs, or null
+struct RegArgs;
 template <class T>
 void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, const int32_t* n,
                      const int64_t* off, int64_t nblk, const double* X, const double* Y,
                      const double* Z, const double* W, int kern, const double* kp, T* pool,
-                     hipStream_t s);
+                     const RegArgs* reg, hipStream_t s);
+// k_reg.hip: per-triangle records of the singular correction (TGEO doubles each)
+void launch_tri_geom(const double* vtx, const int32_t* tri, int64_t nt, double alpha,
+                     double* tgeo, hipStream_t s);
 // k_aca.hip
 template <class T>
 void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads, int kind,
@@ -353,6 +357,11 @@ struct hmx_op {
   double aca_ms[4] = {0, 0, 0, 0};
   int32_t aca_rounds = 0;
   int64_t kernel_evals = 0;
+  // singular correction of the near field (Section 5.2): triangle records of the points'
+  // meshes and the Lagrange coefficients of the 3-point rule
+  bool reg = false;
+  double reg_lag[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  hmx::DevBuf<double> tgeo;
   int64_t bytes() const;
 };
 

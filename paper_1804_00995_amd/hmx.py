@@ -52,6 +52,8 @@ class Params(C.Structure):
         ("aca_big_threads", C.c_int32),
         ("aca_small_mn", C.c_int32),
         ("aca_wave", C.c_int32),
+        ("regularize", C.c_int32),
+        ("reg_radius", C.c_double),
     ]
 
 

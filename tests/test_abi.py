@@ -43,6 +43,7 @@ def test_params_default(hmx):
     assert p.precision == hmx.FP64 and p.rank_model == hmx.RANK_ADAPTIVE
     assert p.initial_rank >= 1 and p.force_pred_scale == 1.0
     assert p.aca_arena == 1 and p.aca_big_threads == 0 and p.aca_small_mn == 1024
+    assert p.regularize == 0 and p.reg_radius == 2.0
 
 
 def test_null_arguments_rejected_on_host(hmx):
@@ -67,7 +68,10 @@ def test_bad_params_rejected_on_host(hmx):
                      ({"precision": 7}, hmx.EINVAL), ({"leaf_size": 300}, hmx.EUNSUPPORTED),
                      ({"struct_size": 8}, hmx.EINVAL), ({"aca_big_threads": 128}, hmx.EINVAL),
                      ({"aca_mid_threads": 512}, hmx.EINVAL), ({"aca_small_mn": -1}, hmx.EINVAL),
-                     ({"aca_arena": 2}, hmx.EINVAL), ({"aca_wave": 3}, hmx.EINVAL)]:
+                     ({"aca_arena": 2}, hmx.EINVAL), ({"aca_wave": 3}, hmx.EINVAL),
+                     ({"regularize": 2}, hmx.EINVAL), ({"regularize": 1, "reg_radius": 0.0}, hmx.EINVAL),
+                     ({"regularize": 1, "reg_radius": float("nan")}, hmx.EINVAL),
+                     ({"regularize": 1, "tol": 0.0}, hmx.EUNSUPPORTED)]:
         p = hmx.params(**kw)
         rc = lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 1, 5.0, C.byref(p), None, C.byref(h))
         assert rc == code, (kw, rc, lib.hmx_last_error())
@@ -80,6 +84,31 @@ def test_bad_params_rejected_on_host(hmx):
     assert lib.hmx_build(fake, 3, fake, 1, badb, w, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
     assert lib.hmx_build(fake, 3, fake, 1, bary, w, 0, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
     assert lib.hmx_build(fake, 0, fake, 1, bary, w, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+
+
+def test_singular_correction_arguments_rejected_on_host(hmx):
+    """The correction needs the mesh, a 3-point rule with non-collinear points and the Laplace or
+    Helmholtz kernel; every case is rejected before any device work."""
+    lib = hmx._lib
+    h = C.c_void_p()
+    fake = C.c_void_p(16)
+    p = hmx.params(regularize=1)
+    w3 = (C.c_double * 3)(1 / 3, 1 / 3, 1 / 3)
+    bary = (C.c_double * 9)(2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3)
+    one = (C.c_double * 3)(1 / 3, 1 / 3, 1 / 3)
+    w1 = (C.c_double * 1)(1.0)
+    assert lib.hmx_build(fake, 3, fake, 1, one, w1, 1, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert b"3-point" in lib.hmx_last_error()
+    # three points on one line of the triangle
+    line = (C.c_double * 9)(0.5, 0.5, 0.0, 0.25, 0.75, 0.0, 0.75, 0.25, 0.0)
+    assert lib.hmx_build(fake, 3, fake, 1, line, w3, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert b"collinear" in lib.hmx_last_error()
+    assert lib.hmx_build(fake, 3, fake, 1, bary, w3, 3, hmx.TEST_POLY2, 1.0, C.byref(p), None,
+                         C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build_points(fake, 10, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert b"mesh" in lib.hmx_last_error()
+    meshes = (hmx.Mesh * 1)(hmx.Mesh(fake, 3, fake, 1, 5.0))
+    assert lib.hmx_build_batch(meshes, 1, one, w1, 1, 1, C.byref(p), None, C.byref(h)) == hmx.EINVAL
 
 
 def test_batch_argument_errors_without_gpu():

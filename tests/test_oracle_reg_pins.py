@@ -199,6 +199,8 @@ def test_correction_vanishes_beyond_radius_and_decays():
     y2 = oracle.reg_apply(P, W, v, f, bary, 2.0, x)
     y0 = oracle.reg_apply(P, W, v, f, bary, 1e-9, x)
     assert np.abs(y0).max() == 0.0
+    rows = np.array([5, 0, M - 1, 17])
+    assert np.array_equal(oracle.reg_apply(P, W, v, f, bary, 2.0, x, rows=rows), y2[rows])
     # the ring between 1 and 2 diameters adds little next to the self and neighbour corrections
     assert np.linalg.norm(y2 - y1) < 0.05 * np.linalg.norm(y1)
     # single pairs: the gap between the exact integral and the 3-point rule shrinks with the
