@@ -178,13 +178,14 @@ def run_sphere(args, torch, oracle, hmx, I):
     M = 3 * f.shape[0]
     prec = hmx.FP64 if args.precision == "fp64" else hmx.FP32_MIXED
     cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
-    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec)
+    reg = args.regularize == "on"
+    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec, regularize=int(reg))
     x_h = I.complex_vector(M, 0)
     vd, fd = torch.from_numpy(v).to(dev), torch.from_numpy(f).to(dev)
     xd = torch.from_numpy(x_h).to(cdt).to(dev)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    log(f"bench sphere: M={M} k={args.k} precision={args.precision}")
+    log(f"bench sphere: M={M} k={args.k} precision={args.precision} singular correction={reg}")
 
     def step():
         op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=args.k, prm=prm, stream=stream)
@@ -200,6 +201,8 @@ def run_sphere(args, torch, oracle, hmx, I):
     P, Wq = oracle.quad_points(v, f, bary, w)
     rows = np.sort(np.random.default_rng(123).choice(M, args.sample_rows, replace=False))
     yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, args.k, x_h, rows)
+    if reg:  # the corrected dense rows: every close pair's correction on top
+        yr = yr + oracle.reg_apply(P, Wq, v, f, bary, 2.0, x_h, rows=rows)
     rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
     log(f"rel_err on {args.sample_rows} sampled rows: {rel_err:.3e}")
     build_s = info["t_total_ms"] / 1e3
@@ -207,7 +210,8 @@ def run_sphere(args, torch, oracle, hmx, I):
     if args.cpu_baseline == "on":
         log("cpu baseline: oracle H-build + H-matvec on the host cores")
         c0 = time.perf_counter()
-        Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, args.k, leaf=64, eta=1.5, tol=1e-3)
+        Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, args.k, leaf=64, eta=1.5, tol=1e-3,
+                            mesh=(v, f, bary) if reg else None)
         c1 = time.perf_counter()
         Ho.matvec(x_h)
         c2 = time.perf_counter()
@@ -229,7 +233,8 @@ def run_sphere(args, torch, oracle, hmx, I):
     extra["cpu_baseline"] = cpu
     op.close()
     config = {"workload": f"unit icosphere L{args.level} ({f.shape[0]} triangles, {M} points), "
-                          f"Helmholtz k={args.k:g}, leaf 64, eta 1.5, ACA tol 1e-3, {args.precision}"}
+                          f"Helmholtz k={args.k:g}, leaf 64, eta 1.5, ACA tol 1e-3, {args.precision}"
+                          + (", singular correction (radius 2)" if reg else "")}
     line(args, ms_step, args.precision, config, extra)
 
 
@@ -420,6 +425,8 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=30)
     ap.add_argument("--sample-rows", type=int, default=384)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--regularize", choices=["on", "off"], default="off",
+                    help="sphere workload: near field with the singular correction")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel used to scale the HBM byte counters")
     args = ap.parse_args()

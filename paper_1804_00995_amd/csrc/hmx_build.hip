@@ -313,8 +313,12 @@ void build_near(hmx_op* op, hipStream_t s) {
   op->near_pool.alloc(std::max<size_t>(bytes, 1));
   // the singular correction of close pairs (Section 5.2) goes into the near field only
   RegArgs ra{};
+  DevBuf<int32_t> iperm;
   if (op->reg) {
+    iperm.alloc(op->M);
+    launch_iperm(op->perm.p, op->M, iperm.p, s);
     ra.perm = op->perm.p;
+    ra.iperm = iperm.p;
     ra.tgeo = op->tgeo.p;
     std::copy(op->reg_lag, op->reg_lag + 9, ra.lag);
   }

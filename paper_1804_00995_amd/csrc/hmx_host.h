@@ -209,6 +209,7 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
 // k_reg.hip: per-triangle records of the singular correction (TGEO doubles each)
 void launch_tri_geom(const double* vtx, const int32_t* tri, int64_t nt, double alpha,
                      double* tgeo, hipStream_t s);
+void launch_iperm(const int32_t* perm, int64_t M, int32_t* iperm, hipStream_t s);
 // k_aca.hip
 template <class T>
 void launch_aca(FarDesc* d, const int32_t* order, int nb, int* counter, int threads, int kind,
