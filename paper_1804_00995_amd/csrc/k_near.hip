@@ -1,7 +1,7 @@
 // k_near.hip -- assembly of dense blocks K_b[i, j] = G(x_{t+i}, x_{s+j}) w_{s+j}, column-major
 // (element (i, j) at j * m + i), used for the near field and for far blocks stored dense.  With
-// the singular correction (Section 5.2) a second kernel adds the corrections of the near field's
-// close pairs in place.
+// the singular correction (Section 5.2) the near-field kernel also corrects its block's close
+// pairs, in place, right after assembling it.
 #include "hmx_dev.h"
 #include "hmx_host.h"
 #include "hmx_reg_dev.h"
@@ -36,25 +36,27 @@ __global__ void __launch_bounds__(WG) assemble_kernel(
   }
 }
 
-// Singular correction of assembled near blocks (one workgroup per block), added in place.  A
-// close pair's correction needs one y-integral over the source triangle, which serves the target
-// with all three of the triangle's points, so the work is organised per (target, triangle): a
-// triangle belongs to the first of its points among the block's columns.  The block's targets and
-// its owned triangles' closeness data are staged in LDS (near blocks pair leaves, which hold at
-// most REG_LEAF points); then the (target, owned triangle) pairs are scanned in chunks of
+// Near blocks with the singular correction (one workgroup per block): the block is assembled as
+// above, then its close pairs are corrected in place while its lines are still in L2.  A close
+// pair's correction needs one y-integral over the source triangle, which serves the target with
+// all three of the triangle's points, so the work is organised per (target, triangle): a
+// triangle belongs to the first of its points among the block's columns.  The block's targets
+// and its owned triangles' closeness data are staged in LDS (near blocks pair leaves, which hold
+// at most REG_LEAF points); then the (target, owned triangle) pairs are scanned in chunks of
 // REG_CHUNK: (1) closeness is tested from LDS and the close pairs are queued; (2) the queued
 // integrals are computed with all lanes busy (FP64, the expensive part) and each of the
 // triangle's points in the block gets its entry corrected.  Every corrected entry is written by
-// exactly one thread.
+// exactly one thread.  Registers are allocated for four waves per SIMD (a few spilled: measured
+// slightly faster than the unconstrained three; five spill too much).
 constexpr int REG_CHUNK = 8 * WG;
 constexpr int REG_LEAF = 256;
 
 template <class T>
-__global__ void __launch_bounds__(WG) near_reg_kernel(
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) assemble_reg_kernel(
     const int32_t* __restrict__ tb, const int32_t* __restrict__ mm, const int32_t* __restrict__ sb,
     const int32_t* __restrict__ nn, const int64_t* __restrict__ off, const double* __restrict__ X,
     const double* __restrict__ Y, const double* __restrict__ Z, const double* __restrict__ W,
-    T* __restrict__ pool, RegArgs ra) {
+    int kern, const double* __restrict__ kp, T* __restrict__ pool, RegArgs ra) {
   __shared__ double tgt[3][REG_LEAF];     // target coordinates
   __shared__ double cen[4][REG_LEAF];     // owned triangles: centroid, (alpha d_T)^2
   __shared__ int tri_of[REG_LEAF];        // owned triangles: index
@@ -63,6 +65,22 @@ __global__ void __launch_bounds__(WG) near_reg_kernel(
   const int blk = blockIdx.x;
   const int t0 = tb[blk], m = mm[blk], s0 = sb[blk], n = nn[blk];
   T* K = pool + off[blk];
+  {
+    const double k = kp[t0];
+    int i = threadIdx.x % m, j = threadIdx.x / m;
+    const int di = WG % m, dj = WG / m;
+    for (int e = threadIdx.x; e < m * n; e += WG) {
+      K[e] = eval_entry<T>(kern, k, X[t0 + i], Y[t0 + i], Z[t0 + i], X[s0 + j], Y[s0 + j],
+                           Z[s0 + j], W[s0 + j]);
+      i += di;
+      j += dj;
+      if (i >= m) {
+        i -= m;
+        j += 1;
+      }
+    }
+  }
+  // (the barriers below also make the block's entries visible to every thread of the workgroup)
   if (threadIdx.x == 0) no = 0;
   for (int i = threadIdx.x; i < m; i += WG) {
     tgt[0][i] = X[t0 + i];
@@ -130,11 +148,12 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
                      const double* Z, const double* W, int kern, const double* k, T* pool,
                      const RegArgs* reg, hipStream_t s) {
   if (nblk <= 0) return;
-  hipLaunchKernelGGL(assemble_kernel<T>, dim3((unsigned)nblk), dim3(WG), 0, s, tb, m, sb, n, off,
-                     X, Y, Z, W, kern, k, pool);
   if (reg)
-    hipLaunchKernelGGL(near_reg_kernel<T>, dim3((unsigned)nblk), dim3(WG), 0, s, tb, m, sb, n, off,
-                       X, Y, Z, W, pool, *reg);
+    hipLaunchKernelGGL(assemble_reg_kernel<T>, dim3((unsigned)nblk), dim3(WG), 0, s, tb, m, sb, n,
+                       off, X, Y, Z, W, kern, k, pool, *reg);
+  else
+    hipLaunchKernelGGL(assemble_kernel<T>, dim3((unsigned)nblk), dim3(WG), 0, s, tb, m, sb, n, off,
+                       X, Y, Z, W, kern, k, pool);
   HMX_LAUNCHED();
 }
 
