@@ -52,6 +52,7 @@ def lib():
         L.hmo_tri_moments.argtypes = [P, P, P]
         L.hmo_tri_lagrange.argtypes = [P, P, P, P]
         L.hmo_reg_apply.argtypes = [P, P, P, P, i64, P, P, i64, i32, P, f64, P, P, i64, P, i32]
+        L.hmo_rect_rows.argtypes = [P, P, P, i64, P, P, P, P, i64, i32, f64, P, P, i64, P, i32]
         L.hmo_hbuild.restype = P
         L.hmo_hmatvec.argtypes = [P, P, P]
         L.hmo_hinfo.argtypes = [P, P]
@@ -137,6 +138,24 @@ def aca_dense(A, tol, rcap=None):
         raise RuntimeError("rank above capacity")
     k = r.value
     return U[:k].T.copy(), V[:k].T.copy(), bool(rc)
+
+
+def rect_matvec(targets, pts, w, kern, k, x, rows=None, nthreads=0):
+    """y = K x with K_il = G(t_i, x_l) w_l: the source quadrature's potential at other target
+    points (Section 5.1); rows selects target rows (all when None)."""
+    TX, TY, TZ = _soa(targets)
+    X, Y, Z = _soa(pts)
+    w = np.ascontiguousarray(w, np.float64)
+    x = np.ascontiguousarray(x, np.complex128)
+    if rows is None:
+        rp, nr = None, TX.shape[0]
+    else:
+        rows = np.ascontiguousarray(np.atleast_1d(rows), np.int64)
+        rp, nr = _p(rows), rows.shape[0]
+    y = np.empty(nr, np.complex128)
+    lib().hmo_rect_rows(_p(TX), _p(TY), _p(TZ), TX.shape[0], _p(X), _p(Y), _p(Z), _p(w), X.shape[0],
+                        kern, k, _p(x), rp, nr, _p(y), nthreads)
+    return y
 
 
 # ------------------------------------------------------------------ singular correction (O7)

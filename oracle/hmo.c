@@ -22,6 +22,9 @@
  *   O7 singular correction ................ Section 5.2 (regularization of the kernels): the
  *                                           1/(4 pi r) part integrated in y analytically over
  *                                           close source triangles, minus its Gauss value.
+ *   O8 collocation at other points ........ Section 5.1 (C_ij = int G(x_i, y) psi_j(y) dy for a
+ *                                           collection of points x_i), with the y-integral by
+ *                                           the quadrature of eq. (BEM).
  * Pinned by the CPU tests: closed-form sphere eigenvalues, quadrature exactness, exact-rank and
  * SVD (Eckart-Young) bounds for ACA, brute-force coverage of the block partition.
  */
@@ -115,6 +118,32 @@ void hmo_dense_rows(const double *X, const double *Y, const double *Z, const dou
         for (int64_t l = 0; l < M; ++l) {
             double xl[3] = {X[l], Y[l], Z[l]};
             acc += green(kern, k, xi, xl) * W[l] * x[l];
+        }
+        y[ii] = acc;
+    }
+}
+
+/* ---------------------------------------------------------------- O8: other target points */
+/* Section 5.1 (integrals with one integration and a collection of points): the potential of the
+ * source quadrature at targets that are not source points,
+ *   y_i = sum_l G(t_i, x_l) w_l x_l  (l ascending),
+ * for the requested target rows (all Mt when rows is NULL).  A target that coincides with a
+ * source point gets 0 from it, as in the square operator. */
+void hmo_rect_rows(const double *TX, const double *TY, const double *TZ, int64_t Mt,
+                   const double *X, const double *Y, const double *Z, const double *W, int64_t Ms,
+                   int32_t kern, double k, const cplx *x, const int64_t *rows, int64_t nrows,
+                   cplx *y, int32_t nthreads)
+{
+    set_threads(nthreads);
+    if (!rows) nrows = Mt;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t ii = 0; ii < nrows; ++ii) {
+        int64_t i = rows ? rows[ii] : ii;
+        double ti[3] = {TX[i], TY[i], TZ[i]};
+        cplx acc = 0.0;
+        for (int64_t l = 0; l < Ms; ++l) {
+            double xl[3] = {X[l], Y[l], Z[l]};
+            acc += green(kern, k, ti, xl) * W[l] * x[l];
         }
         y[ii] = acc;
     }
