@@ -167,6 +167,23 @@ hmx_status hmx_build(const double* vtx, int64_t n_vtx, const int32_t* tri, int64
 hmx_status hmx_build_points(const double* xyzw, int64_t M, int32_t kern, double k,
                             const hmx_params* p, void* stream, hmx_op** out);
 
+/* The potential of a source quadrature at other points (Section 5.1: the matrix
+ * C_ij = int G(x_i, y) psi_j(y) dy for a collection of points x_i, with the y-integral by the
+ * quadrature of eq. (BEM)): K_il = G(t_i, x_l) w_l for Mt targets t_i and Ms sources (x_l, w_l),
+ * e.g. the field radiated onto points off the surface.
+ *   txyz device, 3 x Mt doubles: the targets' X[Mt], Y[Mt], Z[Mt];
+ *   xyzw device, 4 x Ms doubles: the sources as in hmx_build_points (from hmx_quad_points).
+ * hmx_matvec then takes x with Ms entries (source order) and writes y with Mt entries (target
+ * order).  With tol > 0 the targets and the sources get a cluster tree each (two roots of one
+ * forest) and the block tree pairs target clusters with source clusters only; tol <= 0 gives the
+ * dense operator.  A target that coincides with a source gets 0 from it.  Errors: as
+ * hmx_build_points; HMX_EINVAL for Mt < 1 or Ms < 1 and for the singular correction (it needs a
+ * mesh), HMX_EUNSUPPORTED for row shares and for more than 2^23 - 1 points in total in H-matrix
+ * mode.  Synchronous. */
+hmx_status hmx_build_rect(const double* txyz, int64_t Mt, const double* xyzw, int64_t Ms,
+                          int32_t kern, double k, const hmx_params* p, void* stream,
+                          hmx_op** out);
+
 /* One surface of a batch: vtx, tri device arrays as in hmx_build, and the surface's wavenumber. */
 typedef struct {
   const double* vtx;
@@ -192,13 +209,14 @@ hmx_status hmx_build_batch(const hmx_mesh* meshes, int32_t n_meshes, const doubl
                            void* stream, hmx_op** out);
 
 /* Mesh offsets of an operator: *n_meshes receives the number of meshes (1 for operators built
- * by hmx_build / hmx_build_points); off (host, may be NULL) receives n_meshes + 1 offsets when
- * cap >= n_meshes + 1, else HMX_EINVAL. */
+ * by hmx_build / hmx_build_points / hmx_build_rect, whose offsets are {0, length of x}); off
+ * (host, may be NULL) receives n_meshes + 1 offsets when cap >= n_meshes + 1, else HMX_EINVAL. */
 hmx_status hmx_mesh_offsets(const hmx_op* op, int64_t* off, int32_t cap, int32_t* n_meshes);
 
 /* y = K x (Section 5.3: the compressed matrix applied through the product).
  *   x, y device, M complex entries each (c128 for FP64 operators, c64 for FP32 ones), in the
- *   original point order; x and y must not alias.
+ *   original point order (an hmx_build_rect operator: x has Ms entries, y Mt); x and y must not
+ *   alias.
  * Asynchronous on `stream`; allocates nothing and performs no host synchronisation, so it can
  * be captured in a HIP graph.  The operator holds the product's scratch vectors: products on
  * the same operator must not overlap in time (different operators are independent).
@@ -257,6 +275,8 @@ typedef struct {
   int64_t aca_bytes[4];
   int32_t aca_rounds; /* ACA launch rounds: 1 + continuation rounds (device pool exhausted) */
   int64_t row_begin, row_end; /* rows held, in cluster positions (all rows: 0, n_points) */
+  int64_t n_rows, n_cols;     /* product shape: y has n_rows entries, x has n_cols (n_points
+                                 both, except for hmx_build_rect operators: Mt and Ms) */
 } hmx_info_t;
 
 /* Sizes, counts and build timings of an operator. */

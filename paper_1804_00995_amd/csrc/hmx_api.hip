@@ -289,27 +289,73 @@ hmx_status hmx_build_points(const double* xyzw, int64_t M, int32_t kern, double 
   API_CATCH
 }
 
+hmx_status hmx_build_rect(const double* txyz, int64_t Mt, const double* xyzw, int64_t Ms,
+                          int32_t kern, double k, const hmx_params* p, void* stream,
+                          hmx_op** out) {
+  API_TRY
+  HMX_REQUIRE(txyz && xyzw && out, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(Mt >= 1 && Ms >= 1, HMX_EINVAL, "Mt and Ms must be >= 1");
+  check_build_args(kern, k);
+  hmx_params prm = resolve(p);
+  HMX_REQUIRE(!prm.regularize, HMX_EINVAL, "the singular correction needs the mesh (hmx_build)");
+  HMX_REQUIRE(prm.row_shares == 1, HMX_EUNSUPPORTED,
+              "row shares of an operator between different point sets");
+  hipStream_t s = as_stream(stream);
+  auto op = std::make_unique<hmx_op>();
+  op->M = Mt + Ms;
+  op->kern = kern;
+  op->k = k;
+  op->p = prm;
+  op->prec = prm.precision;
+  op->rect = true;
+  op->rows = Mt;
+  op->cols = Ms;
+  op->x_off = Mt;
+  // targets first (weight 0: they are never sources), then the sources; one tree root each
+  op->mesh_off = {0, Mt, Mt + Ms};
+  op->mesh_k = {k, k};
+  op->X.alloc(op->M);
+  op->Y.alloc(op->M);
+  op->Z.alloc(op->M);
+  op->W.alloc(op->M);
+  double* dst[3] = {op->X.p, op->Y.p, op->Z.p};
+  for (int d = 0; d < 3; ++d) {
+    HMX_HIP(hipMemcpyAsync(dst[d], txyz + d * Mt, Mt * 8, hipMemcpyDeviceToDevice, s));
+    HMX_HIP(hipMemcpyAsync(dst[d] + Mt, xyzw + d * Ms, Ms * 8, hipMemcpyDeviceToDevice, s));
+  }
+  fill_f64(op->W.p, 0.0, Mt, s);
+  HMX_HIP(hipMemcpyAsync(op->W.p + Mt, xyzw + 3 * Ms, Ms * 8, hipMemcpyDeviceToDevice, s));
+  HMX_HIP(hipStreamSynchronize(s));
+  finish_build(op.get(), s);
+  *out = op.release();
+  return HMX_OK;
+  API_CATCH
+}
+
 namespace {
 // The product's launches (no synchronisation, no allocation: capturable).
 void enqueue_matvec(const hmx_op* op, const void* x, void* y, hipStream_t s) {
   if (op->dense) {
     if (op->prec == HMX_FP64)
-      launch_dense_otf<double2>(op->X.p, op->Y.p, op->Z.p, op->W.p, op->M, op->kern, op->k,
-                                (const double2*)x, (double2*)op->partial.p, (double2*)y, s);
+      launch_dense_otf<double2>(op->X.p, op->Y.p, op->Z.p, op->W.p, op->rows, op->x_off, op->cols,
+                                op->kern, op->k, (const double2*)x, (double2*)op->partial.p,
+                                (double2*)y, s);
     else
-      launch_dense_otf<float2>(op->X.p, op->Y.p, op->Z.p, op->W.p, op->M, op->kern, op->k,
-                               (const float2*)x, (float2*)op->partial.p, (float2*)y, s);
+      launch_dense_otf<float2>(op->X.p, op->Y.p, op->Z.p, op->W.p, op->rows, op->x_off, op->cols,
+                               op->kern, op->k, (const float2*)x, (float2*)op->partial.p,
+                               (float2*)y, s);
     return;
   }
   auto run = [&](auto tag) {
     using T = decltype(tag);
     T* xp = (T*)op->xp.p;
     T* t = (T*)op->tbuf.p;
-    launch_gather<T>((const T*)x, op->perm.p, xp, op->M, s);
+    launch_gather<T>((const T*)x, op->perm.p, xp, op->M, op->x_off, s);
     launch_far_vt<T>(op->far.p, op->n_far, xp, t, s);
     launch_leaf_apply<T>(op->n_leaves, op->leaves.p, op->nbegin.p, op->nend.p, op->near_ptr.p,
                          op->near_sb.p, op->near_n.p, op->near_off.p, (const T*)op->near_pool.p,
-                         op->far_ptr.p, op->far_list.p, op->far.p, t, xp, op->perm.p, (T*)y, s);
+                         op->far_ptr.p, op->far_list.p, op->far.p, t, xp, op->perm.p, op->rows,
+                         (T*)y, s);
   };
   if (op->prec == HMX_FP64) run(double2{});
   else run(float2{});
@@ -425,10 +471,13 @@ hmx_status hmx_build_batch(const hmx_mesh* meshes, int32_t n_meshes, const doubl
 
 hmx_status hmx_mesh_offsets(const hmx_op* op, int64_t* off, int32_t cap, int32_t* n_meshes) {
   if (!op || !n_meshes) return fail(HMX_EINVAL, "null pointer");
-  const int32_t n = (int32_t)op->mesh_off.size() - 1;
+  // an operator between different point sets has one source set: offsets {0, cols} of x
+  const std::vector<int64_t> rect_off = {0, op->cols};
+  const std::vector<int64_t>& mo = op->rect ? rect_off : op->mesh_off;
+  const int32_t n = (int32_t)mo.size() - 1;
   if (off) {
     if (cap < n + 1) return fail(HMX_EINVAL, "offset array too small");
-    std::memcpy(off, op->mesh_off.data(), sizeof(int64_t) * (n + 1));
+    std::memcpy(off, mo.data(), sizeof(int64_t) * (n + 1));
   }
   *n_meshes = n;
   return HMX_OK;
@@ -468,6 +517,8 @@ hmx_status hmx_info(const hmx_op* op, hmx_info_t* out) {
   out->aca_rounds = op->aca_rounds;
   out->row_begin = op->dense ? 0 : op->row_begin;
   out->row_end = op->dense ? op->M : op->row_end;
+  out->n_rows = op->rows;
+  out->n_cols = op->cols;
   return HMX_OK;
 }
 

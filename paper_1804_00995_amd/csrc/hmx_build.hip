@@ -251,10 +251,12 @@ void build_blocks(hmx_op* op, hipStream_t s) {
   }
   op->row_begin = rb;
   op->row_end = re;
-  // the frontier starts with (root, root) of every mesh: meshes never interact
-  const int nroot = (int)op->mesh_off.size() - 1;
+  // the frontier starts with (root, root) of every mesh: meshes never interact; an operator
+  // between different point sets has the targets' root 0 and the sources' root 1 and starts
+  // from (0, 1) only
+  const int nroot = op->rect ? 1 : (int)op->mesh_off.size() - 1;
   std::vector<int2> roots(nroot);
-  for (int i = 0; i < nroot; ++i) roots[i] = make_int2(i, i);
+  for (int i = 0; i < nroot; ++i) roots[i] = op->rect ? make_int2(0, 1) : make_int2(i, i);
   if ((size_t)nroot > front.n) front.alloc(nroot);
   HMX_HIP(hipMemcpyAsync(front.p, roots.data(), sizeof(int2) * nroot, hipMemcpyHostToDevice, s));
   HMX_HIP(hipStreamSynchronize(s));
@@ -746,12 +748,16 @@ void finish_build(hmx_op* op, hipStream_t s) {
     op->mesh_k = {op->k};
   }
   HMX_REQUIRE(op->mesh_off.back() == op->M, HMX_EINTERNAL, "mesh offsets do not cover the points");
+  if (!op->rect) {
+    op->rows = op->cols = op->M;
+    op->x_off = 0;
+  }
   op->kpt.alloc(op->M);
   for (size_t i = 0; i + 1 < op->mesh_off.size(); ++i)
     fill_f64(op->kpt.p + op->mesh_off[i], op->mesh_k[i], op->mesh_off[i + 1] - op->mesh_off[i], s);
   if (op->p.tol <= 0) {
     op->dense = true;
-    op->partial.alloc((size_t)dense_otf_partial_len(op->M) * es);
+    op->partial.alloc((size_t)dense_otf_partial_len(op->rows, op->cols) * es);
     return;
   }
   if (op->prec == HMX_FP64) build_h<double2>(op, s);

@@ -291,7 +291,8 @@ void launch_far_rec_finish(FarRec* rec, const int64_t* toff, const int64_t* doff
 
 // k_matvec.hip
 template <class T>
-void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, hipStream_t s);
+void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, int64_t x_off,
+                   hipStream_t s);
 template <class T>
 void launch_far_vt(const FarRec* rec, int64_t nf, const T* xp, T* t, hipStream_t s);
 template <class T>
@@ -299,18 +300,24 @@ void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegi
                        const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
                        const int32_t* near_n, const int64_t* near_off, const T* near_pool,
                        const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
-                       const T* tbuf, const T* xp, const int32_t* perm, T* y,
+                       const T* tbuf, const T* xp, const int32_t* perm, int64_t y_rows, T* y,
                        hipStream_t s);
 template <class T>
 void launch_dense_otf(const double* X, const double* Y, const double* Z, const double* W,
-                      int64_t M, int kern, double k, const T* x, T* partial, T* y, hipStream_t s);
-int64_t dense_otf_partial_len(int64_t M);
+                      int64_t rows, int64_t so, int64_t cols, int kern, double k, const T* x,
+                      T* partial, T* y, hipStream_t s);
+int64_t dense_otf_partial_len(int64_t rows, int64_t cols);
 
 }  // namespace hmx
 
 // The operator object.
 struct hmx_op {
   int64_t M = 0;
+  // product shape: y has `rows` entries and x `cols`.  An operator between different point sets
+  // (hmx_build_rect) holds its targets as points [0, rows) and its sources as points
+  // [x_off, x_off + cols); the others have rows = cols = M and x_off = 0.
+  bool rect = false;
+  int64_t rows = 0, cols = 0, x_off = 0;
   int32_t kern = 1;
   double k = 0.0;
   hmx_params p{};

@@ -16,17 +16,23 @@
 
 namespace hmx {
 
+// xp[i] = x[perm[i] - x_off] for the source points (original index >= x_off), 0 for the others
+// (the target points of an operator between different point sets; x_off = 0 otherwise).
 template <class T>
 __global__ void gather_kernel(const T* __restrict__ x, const int32_t* __restrict__ perm,
-                              T* __restrict__ xp, int64_t M) {
+                              T* __restrict__ xp, int64_t M, int64_t x_off) {
   int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (i < M) xp[i] = x[perm[i]];
+  if (i < M) {
+    const int64_t o = perm[i];
+    xp[i] = o >= x_off ? x[o - x_off] : czero<T>();
+  }
 }
 
 template <class T>
-void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, hipStream_t s) {
+void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, int64_t x_off,
+                   hipStream_t s) {
   hipLaunchKernelGGL(gather_kernel<T>, dim3((unsigned)((M + WG - 1) / WG)), dim3(WG), 0, s, x, perm,
-                     xp, M);
+                     xp, M, x_off);
   HMX_LAUNCHED();
 }
 
@@ -101,7 +107,8 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
     const int64_t* __restrict__ near_off, const T* __restrict__ near_pool,
     const int64_t* __restrict__ far_ptr, const int32_t* __restrict__ far_list,
     const FarRec* __restrict__ far, const T* __restrict__ tbuf,
-    const T* __restrict__ xp, const int32_t* __restrict__ perm, T* __restrict__ y) {
+    const T* __restrict__ xp, const int32_t* __restrict__ perm, int64_t y_rows,
+    T* __restrict__ y) {
   __shared__ T part[NWAVE][MAX_LEAF_CHUNKS * WAVE];
   const int leaf = blockIdx.x;
   const int node = leaves[leaf];
@@ -158,7 +165,9 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
       s.x += part[q][i].x;
       s.y += part[q][i].y;
     }
-    y[perm[tb + i]] = s;
+    const int64_t o = perm[tb + i];
+    if (o < y_rows) y[o] = s;  // rows of the product only (not the sources of a
+                               // different-point-set operator)
   }
 }
 
@@ -167,51 +176,55 @@ void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegi
                        const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
                        const int32_t* near_n, const int64_t* near_off, const T* near_pool,
                        const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
-                       const T* tbuf, const T* xp, const int32_t* perm, T* y, hipStream_t s) {
+                       const T* tbuf, const T* xp, const int32_t* perm, int64_t y_rows, T* y,
+                       hipStream_t s) {
   hipLaunchKernelGGL(leaf_apply_kernel<T>, dim3(n_leaves), dim3(WG), 0, s, leaves, nbegin, nend,
                      near_ptr, near_sb, near_n, near_off, near_pool, far_ptr, far_list, far, tbuf,
-                     xp, perm, y);
+                     xp, perm, y_rows, y);
   HMX_LAUNCHED();
 }
 
 // ------------------------------------------------------------------------- dense on the fly
 constexpr int DOTF_CHUNK = 256;  // sources per workgroup (64 per wavefront)
 
-int64_t dense_otf_partial_len(int64_t M) {
-  int64_t nch = (M + DOTF_CHUNK - 1) / DOTF_CHUNK;
-  return nch * M;
+int64_t dense_otf_partial_len(int64_t rows, int64_t cols) {
+  int64_t nch = (cols + DOTF_CHUNK - 1) / DOTF_CHUNK;
+  return nch * rows;
 }
 
+// Rows are the points [0, rows), columns the points [so, so + cols) with x indexed from 0
+// (square operators: rows = cols = M, so = 0).
 template <class T>
 __global__ void __launch_bounds__(WG) dense_otf_kernel(const double* __restrict__ X,
                                                        const double* __restrict__ Y,
                                                        const double* __restrict__ Z,
-                                                       const double* __restrict__ W, int64_t M,
-                                                       int kern, double k, const T* __restrict__ x,
+                                                       const double* __restrict__ W, int64_t rows,
+                                                       int64_t so, int64_t cols, int kern, double k,
+                                                       const T* __restrict__ x,
                                                        T* __restrict__ partial) {
   __shared__ T part[NWAVE][WAVE];
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int64_t i = (int64_t)blockIdx.x * WAVE + lane;
   const int64_t j0 = (int64_t)blockIdx.y * DOTF_CHUNK + w * WAVE;
-  const int64_t j1 = min(j0 + WAVE, M);
+  const int64_t j1 = min(j0 + WAVE, cols);
   T acc = czero<T>();
-  if (i < M) {
+  if (i < rows) {
     const double tx = X[i], ty = Y[i], tz = Z[i];
     for (int64_t j = j0; j < j1; ++j) {
-      T g = eval_entry<T>(kern, k, tx, ty, tz, X[j], Y[j], Z[j], W[j]);
+      T g = eval_entry<T>(kern, k, tx, ty, tz, X[so + j], Y[so + j], Z[so + j], W[so + j]);
       cfma(acc, g, x[j]);
     }
   }
   part[w][lane] = acc;
   __syncthreads();
-  if (w == 0 && i < M) {
+  if (w == 0 && i < rows) {
     T s = part[0][lane];
 #pragma unroll
     for (int q = 1; q < NWAVE; ++q) {
       s.x += part[q][lane].x;
       s.y += part[q][lane].y;
     }
-    partial[(int64_t)blockIdx.y * M + i] = s;
+    partial[(int64_t)blockIdx.y * rows + i] = s;
   }
 }
 
@@ -231,27 +244,29 @@ __global__ void dense_reduce_kernel(const T* __restrict__ partial, int64_t nch, 
 
 template <class T>
 void launch_dense_otf(const double* X, const double* Y, const double* Z, const double* W,
-                      int64_t M, int kern, double k, const T* x, T* partial, T* y, hipStream_t s) {
-  if (M <= 0) return;
-  int64_t nrt = (M + WAVE - 1) / WAVE, nch = (M + DOTF_CHUNK - 1) / DOTF_CHUNK;
+                      int64_t rows, int64_t so, int64_t cols, int kern, double k, const T* x,
+                      T* partial, T* y, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  int64_t nrt = (rows + WAVE - 1) / WAVE, nch = (cols + DOTF_CHUNK - 1) / DOTF_CHUNK;
   hipLaunchKernelGGL(dense_otf_kernel<T>, dim3((unsigned)nrt, (unsigned)nch), dim3(WG), 0, s, X, Y,
-                     Z, W, M, kern, k, x, partial);
+                     Z, W, rows, so, cols, kern, k, x, partial);
   HMX_LAUNCHED();
-  hipLaunchKernelGGL(dense_reduce_kernel<T>, dim3((unsigned)((M + WG - 1) / WG)), dim3(WG), 0, s,
-                     partial, nch, M, y);
+  hipLaunchKernelGGL(dense_reduce_kernel<T>, dim3((unsigned)((rows + WG - 1) / WG)), dim3(WG), 0, s,
+                     partial, nch, rows, y);
   HMX_LAUNCHED();
 }
 
 #define HMX_INST(T)                                                                              \
-  template void launch_gather<T>(const T*, const int32_t*, T*, int64_t, hipStream_t);            \
+  template void launch_gather<T>(const T*, const int32_t*, T*, int64_t, int64_t, hipStream_t);   \
   template void launch_far_vt<T>(const FarRec*, int64_t, const T*, T*, hipStream_t);             \
   template void launch_leaf_apply<T>(int, const int32_t*, const int32_t*, const int32_t*,        \
                                      const int64_t*, const int32_t*, const int32_t*,             \
                                      const int64_t*, const T*, const int64_t*, const int32_t*,   \
-                                     const FarRec*, const T*, const T*, const int32_t*, T*,      \
-                                     hipStream_t);                                               \
+                                     const FarRec*, const T*, const T*, const int32_t*, int64_t, \
+                                     T*, hipStream_t);                                           \
   template void launch_dense_otf<T>(const double*, const double*, const double*, const double*,  \
-                                    int64_t, int, double, const T*, T*, T*, hipStream_t);
+                                    int64_t, int64_t, int64_t, int, double, const T*, T*, T*,    \
+                                    hipStream_t);
 HMX_INST(double2)
 HMX_INST(float2)
 #undef HMX_INST

@@ -65,7 +65,8 @@ class Info(C.Structure):
         (n, C.c_double) for n in ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms", "t_total_ms")] + [
         ("kernel_evals", C.c_int64), ("factor_bytes", C.c_int64), ("predicted_entries", C.c_int64),
         ("aca_blocks", C.c_int64 * 4), ("aca_ms", C.c_double * 4), ("aca_bytes", C.c_int64 * 4),
-        ("aca_rounds", C.c_int32), ("row_begin", C.c_int64), ("row_end", C.c_int64)]
+        ("aca_rounds", C.c_int32), ("row_begin", C.c_int64), ("row_end", C.c_int64),
+        ("n_rows", C.c_int64), ("n_cols", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -81,6 +82,7 @@ _sig = {
     "hmx_quad_points": [_P, _i64, _P, _i64, _P, _P, _i32, _P, _P],
     "hmx_build": [_P, _i64, _P, _i64, _P, _P, _i32, _i32, _f64, C.POINTER(Params), _P, C.POINTER(_P)],
     "hmx_build_points": [_P, _i64, _i32, _f64, C.POINTER(Params), _P, C.POINTER(_P)],
+    "hmx_build_rect": [_P, _i64, _P, _i64, _i32, _f64, C.POINTER(Params), _P, C.POINTER(_P)],
     "hmx_matvec": [_P, _P, _P, _P],
     "hmx_info": [_P, C.POINTER(Info)],
     "hmx_export_tree": [_P, _P, _P, _P, _P, _P, _P, _P],
@@ -198,6 +200,7 @@ class Operator:
         self.precision = precision
         self.info = self._info()
         self.M = self.info["n_points"]
+        self.rows, self.cols = self.info["n_rows"], self.info["n_cols"]
 
     @property
     def cdtype(self):
@@ -211,10 +214,12 @@ class Operator:
 
     def matvec(self, x, y=None, stream=None):
         import torch
-        if x.shape != (self.M,):
-            raise ValueError(f"x must have shape ({self.M},)")
+        if x.shape != (self.cols,):
+            raise ValueError(f"x must have shape ({self.cols},)")
         if y is None:
-            y = torch.empty_like(x)
+            y = torch.empty(self.rows, dtype=x.dtype, device=x.device)
+        elif y.shape != (self.rows,):
+            raise ValueError(f"y must have shape ({self.rows},)")
         _check(_lib.hmx_matvec(self._h, _dev(x, self.cdtype, "x"), _dev(y, self.cdtype, "y"),
                                _stream_ptr(stream)))
         return y
@@ -322,6 +327,20 @@ def build_points(xyzw, kern=HELMHOLTZ, k=0.0, prm: Params | None = None, stream=
     return Operator(h, prm.precision)
 
 
+def build_rect(targets, xyzw, kern=HELMHOLTZ, k=0.0, prm: Params | None = None,
+               stream=None) -> Operator:
+    """Potential of a source quadrature at other points: targets float64 (3, Mt) device tensor
+    (X, Y, Z), sources xyzw float64 (4, Ms) device tensor (X, Y, Z, W).  The operator maps
+    vectors of Ms entries to vectors of Mt entries."""
+    import torch
+    prm = prm or params()
+    h = C.c_void_p()
+    _check(_lib.hmx_build_rect(_dev(targets, torch.float64, "targets"), targets.shape[1],
+                               _dev(xyzw, torch.float64, "xyzw"), xyzw.shape[1], kern, float(k),
+                               C.byref(prm), _stream_ptr(stream), C.byref(h)))
+    return Operator(h, prm.precision)
+
+
 def build_batch(meshes, bary, w, kern=HELMHOLTZ, prm: Params | None = None, stream=None) -> Operator:
     """One block-diagonal operator for independent meshes: `meshes` is a list of
     (vtx float64 (nv,3), tri int32 (nt,3) device tensors, k).  Vectors are the per-mesh vectors
@@ -343,8 +362,8 @@ class Graph:
     """A product captured in a HIP graph (fixed operator, x and y); `launch(reps)` replays it."""
 
     def __init__(self, op, x, y):
-        if x.shape != (op.M,) or y.shape != (op.M,):
-            raise ValueError(f"x and y must have shape ({op.M},)")
+        if x.shape != (op.cols,) or y.shape != (op.rows,):
+            raise ValueError(f"x must have shape ({op.cols},) and y ({op.rows},)")
         self._op, self._x, self._y = op, x, y  # keep the captured buffers alive
         self._g = C.c_void_p()
         _check(_lib.hmx_graph_create(op._h, _dev(x, op.cdtype, "x"), _dev(y, op.cdtype, "y"),

@@ -111,6 +111,22 @@ def test_singular_correction_arguments_rejected_on_host(hmx):
     assert lib.hmx_build_batch(meshes, 1, one, w1, 1, 1, C.byref(p), None, C.byref(h)) == hmx.EINVAL
 
 
+def test_rect_argument_errors_without_gpu(hmx):
+    lib = hmx._lib
+    h = C.c_void_p()
+    fake = C.c_void_p(4096)
+    p = hmx.params()
+    assert lib.hmx_build_rect(None, 5, fake, 7, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build_rect(fake, 0, fake, 7, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build_rect(fake, 5, fake, 0, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build_rect(fake, 5, fake, 7, 1, -2.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    reg = hmx.params(regularize=1)
+    assert lib.hmx_build_rect(fake, 5, fake, 7, 1, 1.0, C.byref(reg), None, C.byref(h)) == hmx.EINVAL
+    shares = hmx.params(row_shares=2)
+    assert lib.hmx_build_rect(fake, 5, fake, 7, 1, 1.0, C.byref(shares), None,
+                              C.byref(h)) == hmx.EUNSUPPORTED
+
+
 def test_batch_argument_errors_without_gpu():
     import ctypes as C
     from paper_1804_00995_amd import hmx
