@@ -198,16 +198,17 @@ def run_sphere(args, torch, oracle, hmx, I):
     mv_ms = product_ms(op, xd, y, stream, args.matvec_reps)
     log(f"matvec {mv_ms:.3f} ms (median of {args.matvec_reps})")
     y_h = y.cpu().numpy().astype(np.complex128)
-    P, Wq = oracle.quad_points(v, f, bary, w)
-    rows = np.sort(np.random.default_rng(123).choice(M, args.sample_rows, replace=False))
-    yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, args.k, x_h, rows)
-    if reg:  # the corrected dense rows: every close pair's correction on top
-        yr = yr + oracle.reg_apply(P, Wq, v, f, bary, 2.0, x_h, rows=rows)
-    rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
-    log(f"rel_err on {args.sample_rows} sampled rows: {rel_err:.3e}")
     build_s = info["t_total_ms"] / 1e3
-    cpu = None
+    cpu, rel_err = None, None
     if args.cpu_baseline == "on":
+        # the oracle leg: the error of the GPU product on sampled rows, then the oracle timed
+        P, Wq = oracle.quad_points(v, f, bary, w)
+        rows = np.sort(np.random.default_rng(123).choice(M, args.sample_rows, replace=False))
+        yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, args.k, x_h, rows)
+        if reg:  # the corrected dense rows: every close pair's correction on top
+            yr = yr + oracle.reg_apply(P, Wq, v, f, bary, 2.0, x_h, rows=rows)
+        rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
+        log(f"rel_err on {args.sample_rows} sampled rows: {rel_err:.3e}")
         log("cpu baseline: oracle H-build + H-matvec on the host cores")
         c0 = time.perf_counter()
         Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, args.k, leaf=64, eta=1.5, tol=1e-3,
@@ -267,19 +268,21 @@ def run_batch(args, torch, oracle, hmx, I):
     mv_ms = product_ms(op, xd, y, stream, args.matvec_reps)
     off = op.mesh_offsets()
     y_h = y.cpu().numpy().astype(np.complex128)
-    rng = np.random.default_rng(77)
-    errs, num, den = [], 0.0, 0.0
-    for i, ((v, f), d) in enumerate(zip(meshes, descs)):
-        P, Wq = oracle.quad_points(v, f, bary, w)
-        rows = np.sort(rng.choice(P.shape[0], 24, replace=False))
-        yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, d["k"], x_h[off[i]:off[i + 1]], rows)
-        diff = np.linalg.norm(y_h[off[i] + rows] - yr)
-        errs.append(float(diff / np.linalg.norm(yr)))
-        num += diff ** 2
-        den += np.linalg.norm(yr) ** 2
-    log(f"batch errors: worst mesh {max(errs):.3e}, all sampled rows {np.sqrt(num / den):.3e}")
-    cpu = None
+    cpu, rel_err, rel_err_worst = None, None, None
     if args.cpu_baseline == "on":
+        # the oracle leg: errors of the GPU product on sampled rows of every mesh
+        rng = np.random.default_rng(77)
+        errs, num, den = [], 0.0, 0.0
+        for i, ((v, f), d) in enumerate(zip(meshes, descs)):
+            P, Wq = oracle.quad_points(v, f, bary, w)
+            rows = np.sort(rng.choice(P.shape[0], 24, replace=False))
+            yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, d["k"], x_h[off[i]:off[i + 1]], rows)
+            diff = np.linalg.norm(y_h[off[i] + rows] - yr)
+            errs.append(float(diff / np.linalg.norm(yr)))
+            num += diff ** 2
+            den += np.linalg.norm(yr) ** 2
+        rel_err, rel_err_worst = float(np.sqrt(num / den)), max(errs)
+        log(f"batch errors: worst mesh {rel_err_worst:.3e}, all sampled rows {rel_err:.3e}")
         # bounded sample: the oracle H-build + product of the first 8 meshes, scaled by points
         c0 = time.perf_counter()
         m_sample = 0
@@ -299,8 +302,8 @@ def run_batch(args, torch, oracle, hmx, I):
     extra = {
         "h_build_s": round(build_s, 4),
         "h_matvec_ms": round(mv_ms, 4),
-        "rel_err": float(np.sqrt(num / den)),
-        "rel_err_worst_mesh": max(errs),
+        "rel_err": rel_err,
+        "rel_err_worst_mesh": rel_err_worst,
         "kernel_evals_per_s": info["kernel_evals"] / build_s if build_s > 0 else None,
         "build_phases_ms": {k2: round(info[k2], 2) for k2 in
                             ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
@@ -312,6 +315,75 @@ def run_batch(args, torch, oracle, hmx, I):
     op.close()
     config = {"workload": f"64 seeded ellipsoids ({M} points), Helmholtz k U[2,30], leaf 64, "
                           f"eta 1.5, ACA tol 1e-3, one block-diagonal operator, {args.precision}"}
+    line(args, ms_step, args.precision, config, extra)
+
+
+def run_radiation(args, torch, oracle, hmx, I):
+    """The L6 sphere's quadrature (245 760 sources, k = 40) radiating onto a 512 x 512 grid in
+    the plane z = 0.2 through the sphere: the operator between different point sets."""
+    v, f = I.icosphere(args.level)
+    bary, w = I.rule_3pt()
+    prec = hmx.FP64 if args.precision == "fp64" else hmx.FP32_MIXED
+    cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
+    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec)
+    stream = torch.cuda.current_stream()
+    vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    xyzw = hmx.quad_points(vd, fd, bary, w, stream=stream)
+    nside = 512
+    g = np.linspace(-2.0, 2.0, nside)
+    gx, gy = np.meshgrid(g, g, indexing="ij")
+    T = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, 0.2)], 1)
+    td = torch.from_numpy(np.ascontiguousarray(T.T)).cuda()
+    Mt, Ms = T.shape[0], xyzw.shape[1]
+    x_h = I.complex_vector(Ms, 0)
+    xd = torch.from_numpy(x_h).to(cdt).cuda()
+    torch.cuda.synchronize()
+    log(f"bench radiation: {Ms} sources -> {Mt} grid targets, k={args.k}, precision={args.precision}")
+
+    def step():
+        op = hmx.build_rect(td, xyzw, kern=hmx.HELMHOLTZ, k=args.k, prm=prm, stream=stream)
+        return op, op.matvec(xd, stream=stream)
+
+    ms_step, aca = timed_steps(step, args.steps, args.warmup)
+    op, y = step()
+    torch.cuda.synchronize()
+    info = op.info
+    mv_ms = product_ms(op, xd, y, stream, args.matvec_reps)
+    log(f"matvec {mv_ms:.3f} ms (median of {args.matvec_reps})")
+    y_h = y.cpu().numpy().astype(np.complex128)
+    cpu, rel_err = None, None
+    if args.cpu_baseline == "on":
+        # the oracle leg: dense rows at sampled targets, timed, and the GPU product's error there
+        P, Wq = oracle.quad_points(v, f, bary, w)
+        rows = np.sort(np.random.default_rng(99).choice(Mt, args.sample_rows, replace=False))
+        c0 = time.perf_counter()
+        yr = oracle.rect_matvec(T, P, Wq, oracle.HELMHOLTZ, args.k, x_h, rows=rows)
+        c1 = time.perf_counter()
+        rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
+        log(f"rel_err on {args.sample_rows} sampled targets: {rel_err:.3e}")
+        cpu = {"value": round((c1 - c0) * 1e3 * Mt / len(rows), 1),
+               "unit": "ms per dense product at all targets (oracle, no H-matrix)",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"{len(rows)} dense target rows in {c1 - c0:.2f} s, scaled to the "
+                         f"{Mt} targets (the oracle has no H-matrix between point sets)"}
+    build_s = info["t_total_ms"] / 1e3
+    extra = {
+        "h_build_s": round(build_s, 4),
+        "h_matvec_ms": round(mv_ms, 4),
+        "rel_err": rel_err,
+        "kernel_evals_per_s": info["kernel_evals"] / build_s if build_s > 0 else None,
+        "build_phases_ms": {k2: round(info[k2], 2) for k2 in
+                            ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
+        "sizes": sizes(info),
+        "shape": [Mt, Ms],
+    }
+    extra.update(rooflines(info, aca, mv_ms, Mt + Ms, 16 if prec == hmx.FP64 else 8, args.precision))
+    extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
+    extra["cpu_baseline"] = cpu
+    op.close()
+    config = {"workload": f"unit icosphere L{args.level} quadrature ({Ms} sources) radiating onto a "
+                          f"{nside} x {nside} grid (z = 0.2, [-2, 2]^2, {Mt} targets), Helmholtz "
+                          f"k={args.k:g}, leaf 64, eta 1.5, ACA tol 1e-3, {args.precision}"}
     line(args, ms_step, args.precision, config, extra)
 
 
@@ -355,13 +427,16 @@ def run_large(args, torch, oracle, hmx, I):
     perm = op.export_tree()["perm"]
     rb, re = info["row_begin"], info["row_end"]
     rows = np.sort(np.random.default_rng(55).choice(perm[rb:re], args.sample_rows, replace=False))
-    P, Wq = oracle.quad_points(v, f, bary, w)
-    c0 = time.perf_counter()
-    yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, k, x_h, rows)
-    c1 = time.perf_counter()
     y_h = y.cpu().numpy().astype(np.complex128)
-    rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
-    log(f"rel_err on {args.sample_rows} sampled rows of the share: {rel_err:.3e}")
+    rel_err, c0, c1 = None, 0.0, 0.0
+    if args.cpu_baseline == "on":
+        # the oracle leg: dense rows of the share, timed, and the GPU product's error on them
+        P, Wq = oracle.quad_points(v, f, bary, w)
+        c0 = time.perf_counter()
+        yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, k, x_h, rows)
+        c1 = time.perf_counter()
+        rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
+        log(f"rel_err on {args.sample_rows} sampled rows of the share: {rel_err:.3e}")
     # learned layout against plain adaptive ACA: a model trained on this build's own ranks
     feat, ranks = R.block_data(op)
     model = R.train(feat, ranks, epochs=30)
@@ -418,7 +493,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["sphere", "batch", "large"], default="sphere")
+    ap.add_argument("--workload", choices=["sphere", "batch", "large", "radiation"],
+                    default="sphere")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--level", type=int, default=6)
     ap.add_argument("--k", type=float, default=40.0)
@@ -439,12 +515,14 @@ def main():
 
     import torch
 
-    import oracle
     from paper_1804_00995_amd import hmx
     from paper_1804_00995_amd import inputs as I
+    oracle = None
+    if args.cpu_baseline == "on":  # only the CPU-baseline leg loads the oracle
+        import oracle
 
-    {"sphere": run_sphere, "batch": run_batch, "large": run_large}[args.workload](
-        args, torch, oracle, hmx, I)
+    {"sphere": run_sphere, "batch": run_batch, "large": run_large,
+     "radiation": run_radiation}[args.workload](args, torch, oracle, hmx, I)
 
 
 if __name__ == "__main__":
