@@ -47,7 +47,9 @@ __device__ __forceinline__ float2 wave_sum2(float2 v) {
   return v;
 }
 
-// t_b[l] = sum_j V_b[j, l] xp[s_b + j]; wave w handles columns l = w, w + 4, ...
+// t_b[l] = sum_j V_b[j, l] xp[s_b + j]; wave w handles columns l = w, w + 4, ..., four (then two,
+// then one) at a time, with the element loop unrolled, so that several column loads per lane are
+// in flight (the kernel streams V from HBM)
 template <class T>
 __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ rec,
                                                     const T* __restrict__ xp, T* __restrict__ t) {
@@ -65,10 +67,36 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
     return l < f.split ? (const T*)f.V + l * ldv : (const T*)f.V1 + (l - f.split) * ldv;
   };
   int l = w;
+  for (; l + 3 * NWAVE < f.r; l += 4 * NWAVE) {
+    T a0 = czero<T>(), a1 = czero<T>(), a2 = czero<T>(), a3 = czero<T>();
+    const T* v0 = colv(l);
+    const T* v1 = colv(l + NWAVE);
+    const T* v2 = colv(l + 2 * NWAVE);
+    const T* v3 = colv(l + 3 * NWAVE);
+#pragma unroll 2
+    for (int j = lane; j < n; j += WAVE) {
+      T xj = xs[j];
+      cfma(a0, v0[j], xj);
+      cfma(a1, v1[j], xj);
+      cfma(a2, v2[j], xj);
+      cfma(a3, v3[j], xj);
+    }
+    a0 = wave_sum2(a0);
+    a1 = wave_sum2(a1);
+    a2 = wave_sum2(a2);
+    a3 = wave_sum2(a3);
+    if (lane == 0) {
+      tb[l] = a0;
+      tb[l + NWAVE] = a1;
+      tb[l + 2 * NWAVE] = a2;
+      tb[l + 3 * NWAVE] = a3;
+    }
+  }
   for (; l + NWAVE < f.r; l += 2 * NWAVE) {
     T a0 = czero<T>(), a1 = czero<T>();
     const T* v0 = colv(l);
     const T* v1 = colv(l + NWAVE);
+#pragma unroll 4
     for (int j = lane; j < n; j += WAVE) {
       T xj = xs[j];
       cfma(a0, v0[j], xj);
@@ -84,6 +112,7 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
   for (; l < f.r; l += NWAVE) {
     T a0 = czero<T>();
     const T* v0 = colv(l);
+#pragma unroll 4
     for (int j = lane; j < n; j += WAVE) cfma(a0, v0[j], xs[j]);
     a0 = wave_sum2(a0);
     if (lane == 0) tb[l] = a0;
@@ -120,6 +149,37 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
   T acc[MAX_LEAF_CHUNKS];
 #pragma unroll
   for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) acc[c] = czero<T>();
+  if (nch == 1) {
+    // leaves of at most 64 rows (the usual case): one accumulator per lane, so that eight
+    // column loads per lane can be in flight without the registers of the general path; lanes
+    // past the leaf's rows read row 0 and discard it
+    T a = czero<T>();
+    const bool on = lane < m;
+    const int i = on ? lane : 0;
+    for (int64_t it = w; it < nn + nfar; it += NWAVE) {
+      if (it < nn) {
+        const int64_t blk = n0 + it;
+        const int sb = near_sb[blk], n = near_n[blk];
+        const T* K = near_pool + near_off[blk] + i;
+        const T* xs = xp + sb;
+#pragma unroll 8
+        for (int j = 0; j < n; ++j) cfma(a, K[(int64_t)j * m], xs[j]);
+      } else {
+        const FarRec f = far[far_list[f0 + (it - nn)]];
+        const int o = tb - f.tb;
+        const T* U = (const T*)f.U + o + i;
+        const T* U1 = (const T*)f.U1 + o + i;
+        const T* tt = tbuf + f.toff;
+#pragma unroll 8
+        for (int l = 0; l < f.r; ++l) {
+          const T* col =
+              l < f.split ? U + (int64_t)l * f.ldu : U1 + (int64_t)(l - f.split) * f.ldu;
+          cfma(a, *col, tt[l]);
+        }
+      }
+    }
+    acc[0] = on ? a : czero<T>();
+  } else
   for (int64_t it = w; it < nn + nfar; it += NWAVE) {
     if (it < nn) {
       const int64_t blk = n0 + it;
