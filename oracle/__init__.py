@@ -53,6 +53,8 @@ def lib():
         L.hmo_tri_lagrange.argtypes = [P, P, P, P]
         L.hmo_reg_apply.argtypes = [P, P, P, P, i64, P, P, i64, i32, P, f64, P, P, i64, P, i32]
         L.hmo_rect_rows.argtypes = [P, P, P, i64, P, P, P, P, i64, i32, f64, P, P, i64, P, i32]
+        L.hmo_dense_matrix.argtypes = [P, P, P, P, i64, i32, f64, P]
+        L.hmo_reg_matrix.argtypes = [P, P, P, P, i64, P, P, i64, i32, P, f64, P, i32]
         L.hmo_hbuild.restype = P
         L.hmo_hmatvec.argtypes = [P, P, P]
         L.hmo_hinfo.argtypes = [P, P]
@@ -156,6 +158,56 @@ def rect_matvec(targets, pts, w, kern, k, x, rows=None, nthreads=0):
     lib().hmo_rect_rows(_p(TX), _p(TY), _p(TZ), TX.shape[0], _p(X), _p(Y), _p(Z), _p(w), X.shape[0],
                         kern, k, _p(x), rp, nr, _p(y), nthreads)
     return y
+
+
+# ------------------------------------------------------------------ Galerkin P1 (O9)
+def p1_matrix(vtx, tri, bary):
+    """Phi (M x nv): Phi[nq t + q, v] = lambda_v(point q of triangle t), the P1 hat function of
+    vertex v at the quadrature points (eq. (BEM): the basis functions evaluated at the points)."""
+    tri = np.asarray(tri)
+    B = np.asarray(bary, np.float64).reshape(-1, 3)
+    nq = B.shape[0]
+    Phi = np.zeros((nq * tri.shape[0], np.asarray(vtx).shape[0]))
+    for t in range(tri.shape[0]):
+        for q in range(nq):
+            for j in range(3):
+                Phi[nq * t + q, tri[t, j]] += B[q, j]
+    return Phi
+
+
+def dense_matrix(pts, w, kern, k):
+    """The point operator K = G W_y as an M x M matrix (G := 0 at r = 0)."""
+    X, Y, Z = _soa(pts)
+    w = np.ascontiguousarray(w, np.float64)
+    M = X.shape[0]
+    K = np.empty((M, M), np.complex128)
+    lib().hmo_dense_matrix(_p(X), _p(Y), _p(Z), _p(w), M, kern, k, _p(K))
+    return K
+
+
+def reg_matrix(pts, w, vtx, tri, bary, alpha, nthreads=0):
+    """The singular correction of every close pair as an M x M (real) matrix."""
+    X, Y, Z = _soa(pts)
+    w = np.ascontiguousarray(w, np.float64)
+    vtx = np.ascontiguousarray(vtx, np.float64)
+    tri = np.ascontiguousarray(tri, np.int32)
+    lag = lagrange_matrix(bary)
+    M = X.shape[0]
+    C = np.empty((M, M))
+    lib().hmo_reg_matrix(_p(X), _p(Y), _p(Z), _p(w), M, _p(vtx), _p(tri), tri.shape[0], 3, _p(lag),
+                         alpha, _p(C), nthreads)
+    return C
+
+
+def galerkin_matrix(vtx, tri, bary, wq, kern, k, reg_radius=None):
+    """A = Phi^T W_x K Phi (eq. (BEM) with P1 test and trial functions on the mesh), K the point
+    operator, plus the singular correction when reg_radius is given."""
+    P, W = quad_points(vtx, tri, bary, wq)
+    K = dense_matrix(P, W, kern, k)
+    if reg_radius is not None:
+        K = K + reg_matrix(P, W, vtx, tri, bary, reg_radius)
+    Phi = p1_matrix(vtx, tri, bary)
+    return Phi.T @ (W[:, None] * K) @ Phi, Phi, P, W
 
 
 # ------------------------------------------------------------------ singular correction (O7)

@@ -22,6 +22,8 @@
  *   O7 singular correction ................ Section 5.2 (regularization of the kernels): the
  *                                           1/(4 pi r) part integrated in y analytically over
  *                                           close source triangles, minus its Gauss value.
+ *   O9 Galerkin P1 operator ............... eq. (BEM): Phi^T W_x K Phi with the P1 basis at the
+ *                                           quadrature points (oracle/__init__.py, numpy)
  *   O8 collocation at other points ........ Section 5.1 (C_ij = int G(x_i, y) psi_j(y) dy for a
  *                                           collection of points x_i), with the y-integral by
  *                                           the quadrature of eq. (BEM).
@@ -346,6 +348,46 @@ void hmo_reg_apply(const double *X, const double *Y, const double *Z, const doub
             }
         }
         y[ii] = acc;
+    }
+}
+
+/* The point operator as a matrix: K[i * M + l] = G(x_i, x_l) w_l (row-major, M x M). */
+void hmo_dense_matrix(const double *X, const double *Y, const double *Z, const double *W, int64_t M,
+                      int32_t kern, double k, cplx *K)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < M; ++i) {
+        double xi[3] = {X[i], Y[i], Z[i]};
+        for (int64_t l = 0; l < M; ++l) {
+            double xl[3] = {X[l], Y[l], Z[l]};
+            K[i * M + l] = green(kern, k, xi, xl) * W[l];
+        }
+    }
+}
+
+/* The correction of every close pair as a matrix: C[i * M + l] = c(x_i, l) (row-major, M x M,
+ * zero for pairs that are not close). */
+void hmo_reg_matrix(const double *X, const double *Y, const double *Z, const double *W, int64_t M,
+                    const double *vtx, const int32_t *tri, int64_t ntri, int32_t nq,
+                    const double *lag, double alpha, double *C, int32_t nthreads)
+{
+    set_threads(nthreads);
+    reg_t R = {vtx, tri, nq, {0}, alpha};
+    memcpy(R.lag, lag, sizeof(R.lag));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < M; ++i) {
+        double xi[3] = {X[i], Y[i], Z[i]};
+        for (int64_t l = 0; l < M; ++l) C[i * M + l] = 0.0;
+        for (int64_t t = 0; t < ntri; ++t) {
+            double tv[9];
+            tri_vertices(&R, t, tv);
+            if (!tri_close(&R, xi, tv)) continue;
+            for (int q = 0; q < nq; ++q) {
+                int64_t l = nq * t + q;
+                double yl[3] = {X[l], Y[l], Z[l]};
+                C[i * M + l] = reg_corr(&R, xi, l, yl, W[l]);
+            }
+        }
     }
 }
 
