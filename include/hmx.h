@@ -184,6 +184,37 @@ hmx_status hmx_build_rect(const double* txyz, int64_t Mt, const double* xyzw, in
                           int32_t kern, double k, const hmx_params* p, void* stream,
                           hmx_op** out);
 
+/* Galerkin P1 operator (eq. (BEM) with test and trial functions: A = Phi^T W_x K Phi, Phi[k, v]
+ * the P1 hat function of vertex v at quadrature point k, W_x the point weights, K = G W_y the
+ * operator) and its iterative solve, as in the paper's acoustic example (Section 6: the Galerkin
+ * single-layer equation of the sound-soft sphere, with the kernel's correction).
+ * hmx_p1_create: the P1 space of the mesh `op` was built on (hmx_build with the same vtx, tri
+ * and rule; the caller keeps op alive while the space is used).  vtx, tri device arrays as in
+ * hmx_build; q_bary, q_w host.  Errors: HMX_EINVAL for null pointers, a rule or mesh that
+ * hmx_build rejects, or an operator whose point count is not n_q n_tri (or one built by
+ * hmx_build_rect); HMX_EUNSUPPORTED for a row-share operator.  Synchronous. */
+typedef struct hmx_p1 hmx_p1;
+hmx_status hmx_p1_create(const hmx_op* op, const double* vtx, int64_t n_vtx, const int32_t* tri,
+                         int64_t n_tri, const double* q_bary, const double* q_w, int32_t n_q,
+                         void* stream, hmx_p1** out);
+void hmx_p1_destroy(hmx_p1* p); /* NULL is accepted */
+/* xp = Phi xv (xv: n_vtx entries, xp: n_q n_tri, original point order) and yv = Phi^T W zp;
+ * device vectors of the operator's complex type (c128 or c64).  Asynchronous on `stream`. */
+hmx_status hmx_p1_interp(const hmx_p1* p, const void* xv, void* xp, void* stream);
+hmx_status hmx_p1_project(const hmx_p1* p, const void* zp, void* yv, void* stream);
+/* yv = A xv = Phi^T W K Phi xv (n_vtx entries each; the space holds the scratch, so products on
+ * one space must not overlap in time).  Asynchronous on `stream`; allocates nothing. */
+hmx_status hmx_galerkin_matvec(const hmx_p1* p, const void* xv, void* yv, void* stream);
+/* Solves A x = b by restarted GMRES(restart) from x = 0: classical Gram-Schmidt with one
+ * reorthogonalisation, stopping when the residual estimate is at most tol ||b|| or after
+ * max_iter products.  b, x device (n_vtx entries, the operator's complex type; x is
+ * overwritten).  *iters receives the products spent and *relres ||b - A x|| / ||b|| of the
+ * returned x (the true residual; the caller compares it with tol).  Inner products accumulate
+ * in FP64.  Errors: HMX_EINVAL for null pointers, restart outside [1, 1000], max_iter < 0 or a
+ * negative or non-finite tol.  Synchronous. */
+hmx_status hmx_gmres(const hmx_p1* p, const void* b, void* x, int32_t restart, int32_t max_iter,
+                     double tol, void* stream, int32_t* iters, double* relres);
+
 /* One surface of a batch: vtx, tri device arrays as in hmx_build, and the surface's wavenumber. */
 typedef struct {
   const double* vtx;

@@ -31,6 +31,7 @@ UNITS = [
     ("k_blocks.hip", True),
     ("k_near.hip", False),
     ("k_reg.hip", True),
+    ("k_p1.hip", False),
     ("k_aca.hip", False),
     ("k_far.hip", False),
     ("k_matvec.hip", False),

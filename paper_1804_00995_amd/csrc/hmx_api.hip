@@ -3,6 +3,7 @@
 // only sizes buffers, launches kernels and moves small index arrays.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -700,6 +701,247 @@ void hmx_destroy(hmx_op* op) {
   if (!op) return;
   (void)hipDeviceSynchronize();
   delete op;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ Galerkin P1 and GMRES
+// The P1 space of the mesh an operator was built on: the rule, the point weights (original
+// order), the triangles and, per vertex, its incidences (3 t + j, increasing t), plus scratch
+// vectors of M entries for the Galerkin product.
+struct hmx_p1 {
+  const hmx_op* op = nullptr;
+  int64_t nv = 0, nt = 0, M = 0;
+  hmx::P1Rule rule{};
+  hmx::DevBuf<int32_t> tri, inc;
+  hmx::DevBuf<int64_t> ptr;
+  hmx::DevBuf<double> w;
+  hmx::DevBuf<unsigned char> zp, kp;
+};
+
+namespace {
+
+template <class T>
+void galerkin_enqueue(const hmx_p1* P, const T* xv, T* yv, hipStream_t s) {
+  launch_p1_interp<T>(P->tri.p, P->nt, P->rule, xv, (T*)P->zp.p, s);
+  enqueue_matvec(P->op, P->zp.p, P->kp.p, s);
+  launch_p1_project<T>(P->ptr.p, P->inc.p, P->nv, P->rule, P->w.p, (const T*)P->kp.p, yv, s);
+}
+
+// Restarted GMRES(m) for A x = b, A = Phi^T W K Phi, from x = 0: classical Gram-Schmidt with one
+// reorthogonalisation (two batched dot launches per step), complex Givens rotations on the
+// host, stop when the residual estimate falls to tol ||b|| or after max_it products; each cycle
+// starts from the true residual b - A x, which is also what is reported.
+template <class T>
+void gmres_run(const hmx_p1* P, const T* b, T* x, int m, int max_it, double tol, hipStream_t s,
+               int32_t* iters, double* relres) {
+  using cd = std::complex<double>;
+  const int64_t n = P->nv;
+  DevBuf<T> V((size_t)n * (m + 1)), w(n), r(n);
+  DevBuf<double2> partial((size_t)mdot_chunks(n) * (m + 1)), dd(m + 1), hd(m + 1);
+  std::vector<double2> hbuf(m + 1);
+  auto col = [&](int c) { return V.p + (int64_t)c * n; };
+  auto dots = [&](int nc, const T* vec, std::vector<cd>& out) {
+    launch_mdot<T>(V.p, n, nc, vec, n, partial.p, dd.p, s);
+    HMX_HIP(hipMemcpyAsync(hbuf.data(), dd.p, nc * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HMX_HIP(hipStreamSynchronize(s));
+    out.resize(nc);
+    for (int c = 0; c < nc; ++c) out[c] = cd(hbuf[c].x, hbuf[c].y);
+  };
+  auto norm = [&](const T* vec) {
+    launch_mdot<T>(vec, n, 1, vec, n, partial.p, dd.p, s);
+    double2 v;
+    HMX_HIP(hipMemcpyAsync(&v, dd.p, sizeof(double2), hipMemcpyDeviceToHost, s));
+    HMX_HIP(hipStreamSynchronize(s));
+    return std::sqrt(std::max(v.x, 0.0));
+  };
+  auto subtract = [&](const std::vector<cd>& h, int nc, T* vec, double sign) {
+    for (int c = 0; c < nc; ++c) hbuf[c] = make_double2(h[c].real(), h[c].imag());
+    HMX_HIP(hipMemcpyAsync(hd.p, hbuf.data(), nc * sizeof(double2), hipMemcpyHostToDevice, s));
+    launch_gemv_update<T>(V.p, n, hd.p, nc, sign, vec, n, s);
+  };
+  HMX_HIP(hipMemsetAsync(x, 0, n * sizeof(T), s));
+  const double bnorm = norm(b);
+  int it = 0;
+  double res = 0.0;
+  if (bnorm == 0.0) {
+    *iters = 0;
+    *relres = 0.0;
+    return;
+  }
+  std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m), h, h2, y(m);
+  std::vector<double> cs(m);
+  auto Hc = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
+  for (;;) {
+    if (it == 0) {
+      HMX_HIP(hipMemcpyAsync(r.p, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+    } else {
+      galerkin_enqueue<T>(P, x, w.p, s);
+      launch_vec<T>(w.p, b, 0.0, 1, r.p, n, s);  // r = b - A x
+    }
+    const double beta = norm(r.p);
+    res = beta / bnorm;
+    if (res <= tol || it >= max_it) break;
+    launch_vec<T>(r.p, nullptr, 1.0 / beta, 0, col(0), n, s);
+    std::fill(g.begin(), g.end(), cd(0.0));
+    g[0] = beta;
+    int k = 0;  // columns of this cycle
+    while (k < m) {
+      const int j = k;
+      galerkin_enqueue<T>(P, col(j), w.p, s);
+      ++it;
+      dots(j + 1, w.p, h);
+      subtract(h, j + 1, w.p, -1.0);
+      dots(j + 1, w.p, h2);
+      subtract(h2, j + 1, w.p, -1.0);
+      for (int c = 0; c <= j; ++c) Hc(c, j) = h[c] + h2[c];
+      const double hn = norm(w.p);
+      Hc(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) {  // previous rotations
+        const cd t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
+        Hc(i + 1, j) = -std::conj(sn[i]) * Hc(i, j) + cs[i] * Hc(i + 1, j);
+        Hc(i, j) = t;
+      }
+      const cd a = Hc(j, j), bb = Hc(j + 1, j);
+      const double t = std::sqrt(std::norm(a) + std::norm(bb));
+      if (std::abs(a) == 0.0) {
+        cs[j] = 0.0;
+        sn[j] = 1.0;
+      } else {
+        cs[j] = std::abs(a) / t;
+        sn[j] = (a / std::abs(a)) * std::conj(bb) / t;
+      }
+      Hc(j, j) = cs[j] * a + sn[j] * bb;
+      Hc(j + 1, j) = 0.0;
+      g[j + 1] = -std::conj(sn[j]) * g[j];
+      g[j] = cs[j] * g[j];
+      ++k;
+      if (hn > 0.0) launch_vec<T>(w.p, nullptr, 1.0 / hn, 0, col(j + 1), n, s);
+      if (std::abs(g[j + 1]) <= tol * bnorm || it >= max_it || hn == 0.0) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {  // H y = g, upper triangular
+      cd acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= Hc(i, l) * y[l];
+      y[i] = acc / Hc(i, i);
+    }
+    subtract(y, k, x, 1.0);  // x += V y
+  }
+  *iters = it;
+  *relres = res;
+}
+
+}  // namespace
+
+extern "C" {
+
+hmx_status hmx_p1_create(const hmx_op* op, const double* vtx, int64_t n_vtx, const int32_t* tri,
+                         int64_t n_tri, const double* q_bary, const double* q_w, int32_t n_q,
+                         void* stream, hmx_p1** out) {
+  API_TRY
+  HMX_REQUIRE(op && vtx && tri && out, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(n_vtx >= 1 && n_tri >= 1, HMX_EINVAL, "empty mesh");
+  HMX_REQUIRE(!op->rect, HMX_EINVAL, "the P1 space needs an operator on the mesh's own points");
+  HMX_REQUIRE(op->M == n_tri * (int64_t)n_q, HMX_EINVAL,
+              "the operator's points are not this mesh's quadrature points (M != n_q n_tri)");
+  HMX_REQUIRE(op->dense || op->p.row_shares == 1, HMX_EUNSUPPORTED,
+              "the Galerkin product needs all rows of the operator (no row share)");
+  Rule r = make_rule(q_bary, q_w, n_q);
+  hipStream_t s = as_stream(stream);
+  auto P = std::make_unique<hmx_p1>();
+  P->op = op;
+  P->nv = n_vtx;
+  P->nt = n_tri;
+  P->M = op->M;
+  P->rule.nq = n_q;
+  for (int q = 0; q < n_q; ++q)
+    for (int j = 0; j < 3; ++j) P->rule.b[q][j] = r.b[q][j];
+  // point weights in the original order (and the range check of the triangles)
+  DevBuf<double> X(P->M), Y(P->M), Z(P->M);
+  P->w.alloc(P->M);
+  DevBuf<int> err(1);
+  fill_i32(err.p, 0, 1, s);
+  launch_quad(vtx, n_vtx, tri, n_tri, r, X.p, Y.p, Z.p, P->w.p, err.p, s);
+  const int e = read1(err.p, s);
+  HMX_REQUIRE(!(e & 1), HMX_EINVAL, "triangle vertex index out of range");
+  HMX_REQUIRE(!(e & 2), HMX_EINVAL, "non-finite vertex coordinate");
+  P->tri.alloc(3 * n_tri);
+  HMX_HIP(hipMemcpyAsync(P->tri.p, tri, 3 * n_tri * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  // vertex incidences (counting sort on the host: increasing t within each vertex)
+  std::vector<int32_t> ht;
+  to_host(ht, tri, 3 * n_tri, s);
+  std::vector<int64_t> hp(n_vtx + 1, 0);
+  for (int64_t i = 0; i < 3 * n_tri; ++i) hp[ht[i] + 1]++;
+  for (int64_t v = 0; v < n_vtx; ++v) hp[v + 1] += hp[v];
+  std::vector<int32_t> hi(3 * n_tri);
+  std::vector<int64_t> fillp(hp.begin(), hp.end() - 1);
+  for (int64_t i = 0; i < 3 * n_tri; ++i) hi[fillp[ht[i]]++] = (int32_t)i;
+  P->ptr.alloc(n_vtx + 1);
+  P->inc.alloc(3 * n_tri);
+  HMX_HIP(hipMemcpyAsync(P->ptr.p, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HMX_HIP(hipMemcpyAsync(P->inc.p, hi.data(), hi.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  P->zp.alloc((size_t)P->M * op->elem);
+  P->kp.alloc((size_t)P->M * op->elem);
+  HMX_HIP(hipStreamSynchronize(s));
+  *out = P.release();
+  return HMX_OK;
+  API_CATCH
+}
+
+void hmx_p1_destroy(hmx_p1* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  delete p;
+}
+
+hmx_status hmx_p1_interp(const hmx_p1* p, const void* xv, void* xp, void* stream) {
+  if (!p || !xv || !xp) return fail(HMX_EINVAL, "null pointer");
+  API_TRY
+  if (p->op->prec == HMX_FP64)
+    launch_p1_interp<double2>(p->tri.p, p->nt, p->rule, (const double2*)xv, (double2*)xp, as_stream(stream));
+  else
+    launch_p1_interp<float2>(p->tri.p, p->nt, p->rule, (const float2*)xv, (float2*)xp, as_stream(stream));
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_p1_project(const hmx_p1* p, const void* zp, void* yv, void* stream) {
+  if (!p || !zp || !yv) return fail(HMX_EINVAL, "null pointer");
+  API_TRY
+  if (p->op->prec == HMX_FP64)
+    launch_p1_project<double2>(p->ptr.p, p->inc.p, p->nv, p->rule, p->w.p, (const double2*)zp,
+                               (double2*)yv, as_stream(stream));
+  else
+    launch_p1_project<float2>(p->ptr.p, p->inc.p, p->nv, p->rule, p->w.p, (const float2*)zp,
+                              (float2*)yv, as_stream(stream));
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_galerkin_matvec(const hmx_p1* p, const void* xv, void* yv, void* stream) {
+  if (!p || !xv || !yv) return fail(HMX_EINVAL, "null pointer");
+  API_TRY
+  if (p->op->prec == HMX_FP64)
+    galerkin_enqueue<double2>(p, (const double2*)xv, (double2*)yv, as_stream(stream));
+  else
+    galerkin_enqueue<float2>(p, (const float2*)xv, (float2*)yv, as_stream(stream));
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_gmres(const hmx_p1* p, const void* b, void* x, int32_t restart, int32_t max_iter,
+                     double tol, void* stream, int32_t* iters, double* relres) {
+  API_TRY
+  HMX_REQUIRE(p && b && x && iters && relres, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(restart >= 1 && restart <= 1000, HMX_EINVAL, "restart must be in [1, 1000]");
+  HMX_REQUIRE(max_iter >= 0, HMX_EINVAL, "max_iter must be >= 0");
+  HMX_REQUIRE(std::isfinite(tol) && tol >= 0, HMX_EINVAL, "tol must be finite and >= 0");
+  hipStream_t s = as_stream(stream);
+  if (p->op->prec == HMX_FP64)
+    gmres_run<double2>(p, (const double2*)b, (double2*)x, restart, max_iter, tol, s, iters, relres);
+  else
+    gmres_run<float2>(p, (const float2*)b, (float2*)x, restart, max_iter, tol, s, iters, relres);
+  return HMX_OK;
+  API_CATCH
 }
 
 const char* hmx_last_error(void) { return g_err.c_str(); }

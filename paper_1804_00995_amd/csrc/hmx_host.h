@@ -206,6 +206,26 @@ void launch_assemble(const int32_t* tb, const int32_t* m, const int32_t* sb, con
                      const int64_t* off, int64_t nblk, const double* X, const double* Y,
                      const double* Z, const double* W, int kern, const double* kp, T* pool,
                      const RegArgs* reg, hipStream_t s);
+// k_p1.hip: P1 basis at the quadrature points and the GMRES vector kernels
+struct P1Rule {
+  double b[MAX_NQ][3];  // barycentric coordinates of the rule's points
+  int nq;
+};
+template <class T>
+void launch_p1_interp(const int32_t* tri, int64_t nt, const P1Rule& r, const T* xv, T* xp,
+                      hipStream_t s);
+template <class T>
+void launch_p1_project(const int64_t* ptr, const int32_t* inc, int64_t nv, const P1Rule& r,
+                       const double* w, const T* zp, T* yv, hipStream_t s);
+int mdot_chunks(int64_t n);
+template <class T>
+void launch_mdot(const T* V, int64_t ld, int nc, const T* w, int64_t n, double2* partial,
+                 double2* d, hipStream_t s);
+template <class T>
+void launch_gemv_update(const T* V, int64_t ld, const double2* h, int nc, double sign, T* w,
+                        int64_t n, hipStream_t s);
+template <class T>
+void launch_vec(const T* x, const T* b, double a, int sub, T* y, int64_t n, hipStream_t s);
 // k_reg.hip: per-triangle records of the singular correction (TGEO doubles each)
 void launch_tri_geom(const double* vtx, const int32_t* tri, int64_t nt, double alpha,
                      double* tgeo, hipStream_t s);

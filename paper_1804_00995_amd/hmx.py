@@ -83,6 +83,11 @@ _sig = {
     "hmx_build": [_P, _i64, _P, _i64, _P, _P, _i32, _i32, _f64, C.POINTER(Params), _P, C.POINTER(_P)],
     "hmx_build_points": [_P, _i64, _i32, _f64, C.POINTER(Params), _P, C.POINTER(_P)],
     "hmx_build_rect": [_P, _i64, _P, _i64, _i32, _f64, C.POINTER(Params), _P, C.POINTER(_P)],
+    "hmx_p1_create": [_P, _P, _i64, _P, _i64, _P, _P, _i32, _P, C.POINTER(_P)],
+    "hmx_p1_interp": [_P, _P, _P, _P],
+    "hmx_p1_project": [_P, _P, _P, _P],
+    "hmx_galerkin_matvec": [_P, _P, _P, _P],
+    "hmx_gmres": [_P, _P, _P, _i32, _i32, _f64, _P, C.POINTER(_i32), C.POINTER(_f64)],
     "hmx_matvec": [_P, _P, _P, _P],
     "hmx_info": [_P, C.POINTER(Info)],
     "hmx_export_tree": [_P, _P, _P, _P, _P, _P, _P, _P],
@@ -114,9 +119,11 @@ _lib.hmx_release_cache.argtypes = []
 _lib.hmx_release_cache.restype = None
 _lib.hmx_graph_destroy.argtypes = [_P]
 _lib.hmx_graph_destroy.restype = None
+_lib.hmx_p1_destroy.argtypes = [_P]
+_lib.hmx_p1_destroy.restype = None
 
 EXPORTED = sorted(list(_sig) + ["hmx_destroy", "hmx_last_error", "hmx_release_cache",
-                                "hmx_graph_destroy"])
+                                "hmx_graph_destroy", "hmx_p1_destroy"])
 
 
 class Mesh(C.Structure):
@@ -339,6 +346,65 @@ def build_rect(targets, xyzw, kern=HELMHOLTZ, k=0.0, prm: Params | None = None,
                                _dev(xyzw, torch.float64, "xyzw"), xyzw.shape[1], kern, float(k),
                                C.byref(prm), _stream_ptr(stream), C.byref(h)))
     return Operator(h, prm.precision)
+
+
+class P1:
+    """The P1 space of the mesh an operator was built on: the Galerkin product
+    A = Phi^T W K Phi and its GMRES solve (vectors of n_vtx entries, the operator's type)."""
+
+    def __init__(self, op, vtx, tri, bary, w, stream=None):
+        import torch
+        bary, w = _host_rule(bary, w)
+        self._op = op  # the space uses the operator
+        self.nv = vtx.shape[0]
+        self.M = op.M
+        self._h = C.c_void_p()
+        _check(_lib.hmx_p1_create(op._h, _dev(vtx, torch.float64, "vtx"), vtx.shape[0],
+                                  _dev(tri, torch.int32, "tri"), tri.shape[0], bary.ctypes.data_as(_P),
+                                  w.ctypes.data_as(_P), bary.shape[0], _stream_ptr(stream),
+                                  C.byref(self._h)))
+
+    def _vec(self, n, like):
+        import torch
+        return torch.empty(n, dtype=self._op.cdtype, device=like.device)
+
+    def interp(self, xv, stream=None):
+        xp = self._vec(self.M, xv)
+        _check(_lib.hmx_p1_interp(self._h, _dev(xv, self._op.cdtype, "xv"), _dev(xp, self._op.cdtype, "xp"),
+                                  _stream_ptr(stream)))
+        return xp
+
+    def project(self, zp, stream=None):
+        yv = self._vec(self.nv, zp)
+        _check(_lib.hmx_p1_project(self._h, _dev(zp, self._op.cdtype, "zp"), _dev(yv, self._op.cdtype, "yv"),
+                                   _stream_ptr(stream)))
+        return yv
+
+    def matvec(self, xv, stream=None):
+        yv = self._vec(self.nv, xv)
+        _check(_lib.hmx_galerkin_matvec(self._h, _dev(xv, self._op.cdtype, "xv"),
+                                        _dev(yv, self._op.cdtype, "yv"), _stream_ptr(stream)))
+        return yv
+
+    def gmres(self, b, tol=1e-8, restart=100, max_iter=1000, stream=None):
+        """x, iterations, true relative residual."""
+        x = self._vec(self.nv, b)
+        it, res = C.c_int32(0), C.c_double(0.0)
+        _check(_lib.hmx_gmres(self._h, _dev(b, self._op.cdtype, "b"), _dev(x, self._op.cdtype, "x"),
+                              restart, max_iter, float(tol), _stream_ptr(stream), C.byref(it),
+                              C.byref(res)))
+        return x, it.value, res.value
+
+    def close(self):
+        if self._h:
+            _lib.hmx_p1_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def build_batch(meshes, bary, w, kern=HELMHOLTZ, prm: Params | None = None, stream=None) -> Operator:

@@ -127,6 +127,21 @@ def test_rect_argument_errors_without_gpu(hmx):
                               C.byref(h)) == hmx.EUNSUPPORTED
 
 
+def test_galerkin_argument_errors_without_gpu(hmx):
+    lib = hmx._lib
+    h = C.c_void_p()
+    fake = C.c_void_p(4096)
+    bary = (C.c_double * 9)(2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3)
+    w = (C.c_double * 3)(1 / 3, 1 / 3, 1 / 3)
+    assert lib.hmx_p1_create(None, fake, 3, fake, 1, bary, w, 3, None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_p1_interp(None, fake, fake, None) == hmx.EINVAL
+    assert lib.hmx_p1_project(None, fake, fake, None) == hmx.EINVAL
+    assert lib.hmx_galerkin_matvec(None, fake, fake, None) == hmx.EINVAL
+    it, res = C.c_int32(0), C.c_double(0)
+    assert lib.hmx_gmres(None, fake, fake, 10, 10, 1e-6, None, C.byref(it), C.byref(res)) == hmx.EINVAL
+    lib.hmx_p1_destroy(None)  # NULL-safe
+
+
 def test_batch_argument_errors_without_gpu():
     import ctypes as C
     from paper_1804_00995_amd import hmx
