@@ -150,11 +150,12 @@ def sizes(info):
                                      "max_rank", "overflow_blocks", "bytes", "factor_bytes")}
 
 
-def line(args, ms_step, prec_name, config, extra):
+def line(args, ms_step, prec_name, config, extra,
+         unit="ms per step (H-build from device mesh + one H-matvec)"):
     out = {
         "metric": METRIC,
         "value": round(ms_step, 3),
-        "unit": "ms per step (H-build from device mesh + one H-matvec)",
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -387,6 +388,110 @@ def run_radiation(args, torch, oracle, hmx, I):
     line(args, ms_step, args.precision, config, extra)
 
 
+def mie_scattered(T, k, d, nmax=80):
+    """Sound-soft unit sphere, incident e^{ik x.d}: the closed-form exterior scattered field."""
+    from scipy import special
+    r = np.linalg.norm(T, axis=1)
+    ct = T @ d / r
+    s = np.zeros(len(r), np.complex128)
+    for n in range(nmax):
+        jn = special.spherical_jn(n, k)
+        hn = jn + 1j * special.spherical_yn(n, k)
+        hr = special.spherical_jn(n, k * r) + 1j * special.spherical_yn(n, k * r)
+        s -= (1j ** n) * (2 * n + 1) * jn / hn * hr * special.eval_legendre(n, ct)
+    return s
+
+
+def run_scattering(args, torch, oracle, hmx, I):
+    """The paper's acoustic example at the L6 sphere (40 962 vertices, 245 760 points), k = 40:
+    corrected Galerkin P1 single layer, GMRES to 1e-6, scattered field checked against the
+    closed-form series at exterior points."""
+    v, f = I.icosphere(args.level)
+    bary, w = I.rule_3pt()
+    d = np.array([0.0, 0.0, 1.0])
+    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, regularize=1)
+    stream = torch.cuda.current_stream()
+    vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    xyzw = hmx.quad_points(vd, fd, bary, w, stream=stream)
+    pinc = torch.exp(1j * args.k * xyzw[:3].T.to(torch.complex128) @ torch.from_numpy(d).to(torch.complex128).cuda())
+    torch.cuda.synchronize()
+    log(f"bench scattering: {v.shape[0]} vertices, {xyzw.shape[1]} points, k={args.k}")
+    last = {}
+
+    def step():
+        if "p1" in last:  # the previous step's space (its operator is closed by then)
+            last.pop("p1").close()
+        op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=args.k, prm=prm, stream=stream)
+        p1 = hmx.P1(op, vd, fd, bary, w, stream=stream)
+        b = p1.project(-pinc, stream=stream)
+        lam, it, res = p1.gmres(b, tol=1e-6, restart=200, max_iter=3000, stream=stream)
+        last.update(p1=p1, it=it, res=res)
+        return op, lam
+
+    ms_step, aca = timed_steps(step, args.steps, args.warmup)
+    op, lam = step()
+    torch.cuda.synchronize()
+    it, res, p1 = last["it"], last["res"], last["p1"]
+    info = op.info
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.matvec_reps):
+        p1.matvec(lam, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    gmv_ms = e0.elapsed_time(e1) / args.matvec_reps
+    # scattered field at exterior points against the closed form (outside the timed region)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((400, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    T = u * rng.uniform(1.5, 3.0, 400)[:, None]
+    rad = hmx.build_rect(torch.from_numpy(np.ascontiguousarray(T.T)).cuda(), xyzw, kern=hmx.HELMHOLTZ,
+                         k=args.k, prm=hmx.params(tol=1e-6))
+    ps = rad.matvec(p1.interp(lam)).cpu().numpy()
+    ex = mie_scattered(T, args.k, d)
+    field_err = float(np.abs(ps - ex).max() / np.abs(ex).max())
+    log(f"GMRES {it} iterations, relres {res:.2e}; Galerkin product {gmv_ms:.3f} ms; "
+        f"scattered field vs closed form {field_err:.3e}")
+    rad.close()
+    cpu = None
+    if args.cpu_baseline == "on":
+        # bounded sample: the oracle's corrected H-build and one product, the solve scaled by the
+        # GPU's iteration count (the oracle has no iterative solver)
+        P, Wq = oracle.quad_points(v, f, bary, w)
+        c0 = time.perf_counter()
+        Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, args.k, leaf=64, eta=1.5, tol=1e-3,
+                            mesh=(v, f, bary))
+        c1 = time.perf_counter()
+        Ho.matvec(I.complex_vector(P.shape[0], 0))
+        c2 = time.perf_counter()
+        Ho.close()
+        cpu = {"value": round(((c1 - c0) + it * (c2 - c1)) * 1e3, 1),
+               "unit": "ms per step (corrected H-build + GMRES products), estimated",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"oracle H-build {c1 - c0:.2f} s and one point-operator product "
+                         f"{c2 - c1:.2f} s, the solve scaled by {it} iterations"}
+    build_s = info["t_total_ms"] / 1e3
+    extra = {
+        "h_build_s": round(build_s, 4),
+        "gmres_iterations": it,
+        "gmres_relres": res,
+        "galerkin_matvec_ms": round(gmv_ms, 4),
+        "scattered_field_rel_err": field_err,
+        "build_phases_ms": {k2: round(info[k2], 2) for k2 in
+                            ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
+        "sizes": sizes(info),
+    }
+    extra.update(rooflines(info, aca, gmv_ms, xyzw.shape[1], 16, "fp64"))
+    extra["cpu_baseline"] = cpu
+    p1.close()
+    op.close()
+    config = {"workload": f"sound-soft unit sphere, icosphere L{args.level} ({v.shape[0]} vertices, "
+                          f"{xyzw.shape[1]} points), Helmholtz k={args.k:g}, corrected Galerkin P1 "
+                          f"single layer, ACA tol 1e-3, GMRES(200) to 1e-6, fp64"}
+    line(args, ms_step, "fp64", config, extra,
+         unit="ms per step (corrected H-build from device mesh + GMRES solve of the Galerkin system)")
+
+
 def run_large(args, torch, oracle, hmx, I):
     from paper_1804_00995_amd import rank_model as R
     v, f = I.icosphere(8)
@@ -493,7 +598,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["sphere", "batch", "large", "radiation"],
+    ap.add_argument("--workload", choices=["sphere", "batch", "large", "radiation", "scattering"],
                     default="sphere")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--level", type=int, default=6)
@@ -521,8 +626,8 @@ def main():
     if args.cpu_baseline == "on":  # only the CPU-baseline leg loads the oracle
         import oracle
 
-    {"sphere": run_sphere, "batch": run_batch, "large": run_large,
-     "radiation": run_radiation}[args.workload](args, torch, oracle, hmx, I)
+    {"sphere": run_sphere, "batch": run_batch, "large": run_large, "radiation": run_radiation,
+     "scattering": run_scattering}[args.workload](args, torch, oracle, hmx, I)
 
 
 if __name__ == "__main__":
