@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle_hmo.so")
 
 LAPLACE, HELMHOLTZ, POLY2 = 0, 1, 99
+GRADY_X, GRADY_Y, GRADY_Z = 2, 3, 4
 
 
 def build(force: bool = True) -> str:

@@ -42,6 +42,9 @@ typedef double complex cplx;
 #define HMO_LAPLACE 0
 #define HMO_HELMHOLTZ 1
 #define HMO_POLY2 99
+#define HMO_GRADY_X 2 /* d/dy_j of the Helmholtz kernel, j = 0, 1, 2 (Laplace at k = 0) */
+#define HMO_GRADY_Y 3
+#define HMO_GRADY_Z 4
 
 static const double PI = 3.14159265358979323846;
 
@@ -84,6 +87,7 @@ int hmo_quad_points(const double *vtx, int64_t nv, const int32_t *tri, int64_t n
 
 /* ------------------------------------------------------------------ Green kernel */
 /* G(x, y) = exp(i k |x - y|) / (4 pi |x - y|); Laplace is k = 0; 0 when |x - y| = 0.
+ * GRADY_j: the j-th component of its gradient in y (Section 5.1, grady[exp(ikr)/r]j).
  * The test-only kernel POLY2 is (1 + x.y)^2, a separable function of exact rank 10. */
 static cplx green(int kern, double k, const double *x, const double *y)
 {
@@ -94,6 +98,14 @@ static cplx green(int kern, double k, const double *x, const double *y)
     double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
     double r = sqrt(dx * dx + dy * dy + dz * dz);
     if (r == 0.0) return 0.0;
+    if (kern >= HMO_GRADY_X && kern <= HMO_GRADY_Z) {
+        /* d/dy_j of e^{ikr}/(4 pi r): (d/dr)(e^{ikr}/(4 pi r)) * dr/dy_j with
+         * (d/dr) = e^{ikr} (ikr - 1) / (4 pi r^2) and dr/dy_j = (y_j - x_j) / r */
+        int j = kern - HMO_GRADY_X;
+        double kr = k * r;
+        cplx e = cos(kr) + I * sin(kr);
+        return e * (I * kr - 1.0) / (4.0 * PI * r * r) * ((y[j] - x[j]) / r);
+    }
     double kr = (kern == HMO_LAPLACE) ? 0.0 : k * r;
     return (cos(kr) + I * sin(kr)) / (4.0 * PI * r);
 }
