@@ -49,6 +49,12 @@ typedef enum {
 typedef enum {
   HMX_LAPLACE = 0,    /* G = 1 / (4 pi r) */
   HMX_HELMHOLTZ = 1,  /* G = e^{ikr} / (4 pi r) */
+  /* Gradient kernels (Section 5.1: kernels such as grady[exp(ikr)/r]j, the j-th component of
+   * the gradient in y): dG/dy_j = e^{ikr} (ikr - 1) (y_j - x_j) / (4 pi r^3), Laplace at k = 0;
+   * 0 at r = 0.  Combined with the source normals they give the double-layer operator. */
+  HMX_GRADY_X = 2,
+  HMX_GRADY_Y = 3,
+  HMX_GRADY_Z = 4,
   HMX_TEST_POLY2 = 99 /* test only: G = (1 + x.y)^2, exact separable rank 10 */
 } hmx_kernel;
 

@@ -152,8 +152,9 @@ Rule make_rule(const double* q_bary, const double* q_w, int32_t nq) {
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 void check_build_args(int32_t kern, double k) {
-  HMX_REQUIRE(kern == HMX_LAPLACE || kern == HMX_HELMHOLTZ || kern == HMX_TEST_POLY2, HMX_EINVAL,
-              "unknown kernel");
+  HMX_REQUIRE(kern == HMX_LAPLACE || kern == HMX_HELMHOLTZ || kern == HMX_GRADY_X ||
+                  kern == HMX_GRADY_Y || kern == HMX_GRADY_Z || kern == HMX_TEST_POLY2,
+              HMX_EINVAL, "unknown kernel");
   HMX_REQUIRE(std::isfinite(k) && k >= 0, HMX_EINVAL, "k must be finite and >= 0");
 }
 

@@ -26,7 +26,14 @@ constexpr int NWAVE = WG / WAVE;
 constexpr double INV4PI = 0.079577471545947667884441881686257181;  // 1 / (4 pi)
 constexpr double TWO_PI = 6.283185307179586476925286766559005768;
 
-enum KernelId : int32_t { K_LAPLACE = 0, K_HELMHOLTZ = 1, K_POLY2 = 99 };
+enum KernelId : int32_t {
+  K_LAPLACE = 0,
+  K_HELMHOLTZ = 1,
+  K_GRADY_X = 2,  // dG/dy_j, j = kern - K_GRADY_X
+  K_GRADY_Y = 3,
+  K_GRADY_Z = 4,
+  K_POLY2 = 99
+};
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -68,6 +75,14 @@ __device__ __forceinline__ double2 green64(int kern, double k, double xx, double
   double r2 = dx * dx + dy * dy + dz * dz;
   if (r2 == 0.0) return make_double2(0.0, 0.0);
   double r = sqrt(r2);
+  if (kern >= K_GRADY_X && kern <= K_GRADY_Z) {
+    // dG/dy_j = e^{ikr} (ikr - 1) (y_j - x_j) / (4 pi r^3)
+    const double d = kern == K_GRADY_X ? -dx : (kern == K_GRADY_Y ? -dy : -dz);
+    const double f = d * INV4PI / (r2 * r), kr = k * r;
+    double s, c;
+    sincos(kr, &s, &c);
+    return make_double2(f * (-c - kr * s), f * (kr * c - s));
+  }
   double inv = INV4PI / r;
   if (kern == K_LAPLACE) return make_double2(inv, 0.0);
   double s, c;
@@ -87,6 +102,15 @@ __device__ __forceinline__ float2 green32(int kern, double k, double xx, double 
   double r2 = dx * dx + dy * dy + dz * dz;
   if (r2 == 0.0) return make_float2(0.0f, 0.0f);
   double r = sqrt(r2);
+  if (kern >= K_GRADY_X && kern <= K_GRADY_Z) {
+    const double d = kern == K_GRADY_X ? -dx : (kern == K_GRADY_Y ? -dy : -dz);
+    const float f = (float)(d * INV4PI / (r2 * r)), kr = (float)(k * r);
+    double ph = k * r;
+    ph = ph - TWO_PI * rint(ph * (1.0 / TWO_PI));
+    float s, c;
+    __sincosf((float)ph, &s, &c);
+    return make_float2(f * (-c - kr * s), f * (kr * c - s));
+  }
   float inv = (float)(INV4PI / r);
   if (kern == K_LAPLACE) return make_float2(inv, 0.0f);
   double ph = k * r;

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhmx.so")
 
 LAPLACE, HELMHOLTZ, TEST_POLY2 = 0, 1, 99
+GRADY_X, GRADY_Y, GRADY_Z = 2, 3, 4
 FP64, FP32_MIXED = 0, 1
 RANK_ADAPTIVE, RANK_LEARNED = 0, 1
 

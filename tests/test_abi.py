@@ -78,6 +78,10 @@ def test_bad_params_rejected_on_host(hmx):
     p = hmx.params()
     assert lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 1, -1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
     assert lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 42, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 5, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
+    reg = hmx.params(regularize=1)  # the correction is for the kernel itself, not its gradient
+    assert lib.hmx_build(fake, 3, fake, 1, bary, w, 3, hmx.GRADY_X, 1.0, C.byref(reg), None,
+                         C.byref(h)) == hmx.EINVAL
     badw = (C.c_double * 3)(0.3, 0.3, 0.3)
     assert lib.hmx_build(fake, 3, fake, 1, bary, badw, 3, 1, 1.0, C.byref(p), None, C.byref(h)) == hmx.EINVAL
     badb = (C.c_double * 9)(1.2, -0.1, -0.1, 1 / 6, 2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3)
