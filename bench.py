@@ -39,17 +39,24 @@ HBM_PEAK_GBS = 8000.0
 ACA_BIG_KERNEL = "hmx::aca_kernel<T, NT, true> (ACA of the far blocks with m + n >= 4096; NT = 512 for FP64, 256 for FP32)"
 PMC_SUMMARY = {"fp64": os.path.join(ROOT, "profiles", "aca_big_icosphere_L6_k40_fp64_pmc.txt"),
                "fp32": os.path.join(ROOT, "profiles", "aca_big_icosphere_L6_k40_fp32_pmc.txt")}
-ACA_SOURCE = os.path.join(ROOT, "paper_1804_00995_amd", "csrc", "k_aca.hip")
+# the large-block ACA kernel's source and the headers it includes: the counter summary's traffic
+# is used only while all of them are unchanged
+ACA_SOURCES = tuple(os.path.join(ROOT, "paper_1804_00995_amd", "csrc", f)
+                    for f in ("k_aca.hip", "hmx_dev.h", "hmx_host.h"))
+DIGEST_KEY = "aca sources sha256[:16]"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_digest(path):
+def source_digest(*paths):
     import hashlib
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(precision):
@@ -65,7 +72,7 @@ def measured_traffic(precision):
             if ": " in line and not line.startswith(" "):
                 key, _, val = line.partition(": ")  # keys may hold a colon ("sha256[:16]")
                 vals[key.strip()] = val.strip()
-    if vals.get("k_aca.hip sha256[:16]") != source_digest(ACA_SOURCE):
+    if vals.get(DIGEST_KEY) != source_digest(*ACA_SOURCES):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
