@@ -549,7 +549,8 @@ def run_large(args, torch, oracle, hmx, I):
         c1 = time.perf_counter()
         rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
         log(f"rel_err on {args.sample_rows} sampled rows of the share: {rel_err:.3e}")
-    # learned layout against plain adaptive ACA: a model trained on this build's own ranks
+    # learned layout against plain adaptive ACA: a model trained on the ranks of the adaptive
+    # build above
     feat, ranks = R.block_data(op)
     model = R.train(feat, ranks, epochs=30)
     model.install()

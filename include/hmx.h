@@ -42,7 +42,7 @@ typedef enum {
   HMX_EINVAL = -1,       /* invalid argument (checked before any work is enqueued) */
   HMX_ENOMEM = -2,       /* device or host allocation failed */
   HMX_EDEVICE = -3,      /* a HIP runtime call or kernel failed */
-  HMX_EUNSUPPORTED = -4, /* valid request outside what this build supports */
+  HMX_EUNSUPPORTED = -4, /* valid request outside what this library supports */
   HMX_EINTERNAL = -5     /* internal consistency check failed */
 } hmx_status;
 
