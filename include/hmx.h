@@ -107,7 +107,7 @@ typedef struct {
   int32_t row_shares; /* power of two >= 1 (default 1) */
   int32_t row_share;  /* 0 <= row_share < row_shares (default 0) */
   int64_t force_pool_bytes; /* > 0: size of the first ACA slot pool (tests force further rounds) */
-  int32_t max_far_mn; /* > 0 (default 16384): an admissible pair with more than max_far_mn
+  int32_t max_far_mn; /* > 0 (default 12288): an admissible pair with more than max_far_mn
                          points (m + n) is split into its children's pairs instead of becoming
                          one far block (smaller ranks, less ACA work and better balance per
                          block); 0: no limit (the plain admissibility recursion) */
@@ -137,7 +137,7 @@ typedef struct {
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
  * initial_rank 16, force_pred_scale 1, no rank cap, no pool limit, ACA schedule 4096 / 1024 /
- * concurrent / arenas, one row share, far blocks up to 16384 points, no singular correction
+ * concurrent / arenas, one row share, far blocks up to 12288 points, no singular correction
  * (reg_radius 2). */
 hmx_status hmx_params_default(hmx_params* p);
 
@@ -273,7 +273,7 @@ void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
 /* Autotuner of the build schedule (max_far_mn, aca_big_mn, aca_gram_min_mn, aca_mid_threads,
  * aca_big_threads, aca_small_mn, aca_wave, aca_serial of hmx_params).  Times
  * hmx_build_points(xyzw, M, kern, k) under a grid of settings, each stage at the best of the
- * previous ones: far-block bounds {none, 32768, 16384, 8192}; class thresholds {2048, 4096,
+ * previous ones: far-block bounds {none, 32768, 16384, 12288, 8192}; class thresholds {2048, 4096,
  * 8192, none} x Gram thresholds {0, 1024, 4096, none} on concurrent streams; middle-class
  * workgroups {256, 128, 64}; large-block workgroups {512, 256}; small-block bounds {512, 2048,
  * none}; the other wavefront setting; serial classes; best of two builds each.  *out receives *p (defaults when
@@ -281,7 +281,7 @@ void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
  * cache_path (host string, may be NULL): a JSON file of earlier choices keyed by device
  * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size and eta; a key
  * found there is returned without timing, a new one is added to the file.  Synchronous; builds
- * and frees up to 61 operators (30 settings, two builds each, one warm-up).  Errors: as
+ * and frees up to 63 operators (31 settings, two builds each, one warm-up).  Errors: as
  * hmx_build_points, HMX_EINVAL for tol <= 0 or an unwritable cache file. */
 hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
                         const hmx_params* p, const char* cache_path, void* stream,

@@ -68,7 +68,7 @@ void defaults(hmx_params* p) {
   p->row_shares = 1;
   p->row_share = 0;
   p->force_pool_bytes = 0;
-  p->max_far_mn = 16384;
+  p->max_far_mn = 12288;
   p->regularize = 0;
   p->reg_radius = 2.0;
 }

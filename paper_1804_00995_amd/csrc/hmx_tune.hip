@@ -20,7 +20,7 @@
 namespace {
 
 struct Choice {
-  int big = 4096, gram = 1024, serial = 0, maxmn = 16384, mid = 128, bigt = 0, small = 1024,
+  int big = 4096, gram = 1024, serial = 0, maxmn = 12288, mid = 128, bigt = 0, small = 1024,
       wave = 0;
   double ms = 0.0;
 };
@@ -76,7 +76,7 @@ std::map<std::string, Choice> read_cache(const char* path) {
     c.big = (int)field(body, "aca_big_mn", 4096);
     c.gram = (int)field(body, "aca_gram_min_mn", 1024);
     c.serial = (int)field(body, "aca_serial", 0);
-    c.maxmn = (int)field(body, "max_far_mn", 16384);
+    c.maxmn = (int)field(body, "max_far_mn", 12288);
     c.mid = (int)field(body, "aca_mid_threads", 128);
     c.bigt = (int)field(body, "aca_big_threads", 0);
     c.small = (int)field(body, "aca_small_mn", 1024);
@@ -156,7 +156,7 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
       // the far-block size bound first (default schedule), then the class thresholds
       // (concurrent classes), the two workgroup sizes, the small-block bound, then serial vs
       // concurrent at the best
-      const int maxmns[] = {0, 32768, 16384, 8192};
+      const int maxmns[] = {0, 32768, 16384, 12288, 8192};
       const int bigs[] = {2048, 4096, 8192, 1 << 30};
       const int grams[] = {0, 1024, 4096, 1 << 30};
       const int mids[] = {256, 128, 64};

@@ -60,7 +60,7 @@ def test_autotune_choice_and_cache(H, sphere4, tmp_path):
     assert prm.aca_big_mn in (2048, 4096, 8192, 1 << 30)
     assert prm.aca_gram_min_mn in (0, 1024, 4096, 1 << 30)
     assert prm.aca_serial in (0, 1) and ms > 0
-    assert prm.max_far_mn in (0, 32768, 16384, 8192)
+    assert prm.max_far_mn in (0, 32768, 16384, 12288, 8192)
     assert prm.aca_mid_threads in (256, 128, 64)
     assert prm.aca_big_threads in (0, 512, 256)
     assert prm.aca_small_mn in (1024, 512, 2048, 0)
