@@ -367,6 +367,8 @@ class P1:
 
     def _vec(self, n, like):
         import torch
+        if not self._op._h or not self._h:
+            raise RuntimeError("the P1 space or its operator has been closed")
         return torch.empty(n, dtype=self._op.cdtype, device=like.device)
 
     def interp(self, xv, stream=None):
@@ -437,6 +439,8 @@ class Graph:
                                      C.byref(self._g)))
 
     def launch(self, reps=1, stream=None):
+        if not self._op._h or not self._g:
+            raise RuntimeError("the graph or its operator has been closed")
         _check(_lib.hmx_graph_launch(self._g, reps, _stream_ptr(stream)))
 
     def close(self):

@@ -127,3 +127,13 @@ def test_sound_soft_sphere_end_to_end(H):
     ps = host(rad.matvec(p1.interp(lam)))
     ex = mie_scattered(T, k)
     assert np.abs(ps - ex).max() / np.abs(ex).max() <= 3e-3
+
+
+def test_closed_operator_is_refused(H):
+    v, f, op, p1 = space(H, 1, 2.0, False)
+    x = torch.zeros(v.shape[0], dtype=torch.complex128, device="cuda")
+    p1.matvec(x)
+    op.close()
+    with pytest.raises(RuntimeError):
+        p1.matvec(x)
+    p1.close()
