@@ -395,6 +395,82 @@ def run_radiation(args, torch, oracle, hmx, I):
     line(args, ms_step, args.precision, config, extra)
 
 
+# ALU ceiling of the dense on-the-fly product (evaluations per second), from the instructions the
+# built kernel's inner loop executes per evaluation of the Helmholtz kernel (gfx950 assembly; the
+# sin/cos argument reduction's fast path): FP64 mode 82 FP64 and 37 32-bit VALU instructions
+# plus 2 transcendental; FP32 mode 37 FP64, 22 32-bit and 4 transcendental.  A wave64 VALU
+# instruction occupies a 16-lane SIMD for 4 cycles, a transcendental for 16: 508 and 300 SIMD
+# cycles per 64 evaluations, over 1024 SIMDs at 2.4 GHz.
+DENSE_ALU_PEAK = {"fp64": 1024 * 2.4e9 * 64 / 508.0, "fp32": 1024 * 2.4e9 * 64 / 300.0}
+
+
+def run_dense(args, torch, oracle, hmx, I):
+    """The dense operator on the fly (tol <= 0): L3 sphere, 3 840 points, k = 5, and the same
+    kernel at L5 (61 440 points), where it fills the GPU."""
+    bary, w = I.rule_3pt()
+    prec = hmx.FP64 if args.precision == "fp64" else hmx.FP32_MIXED
+    cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
+    stream = torch.cuda.current_stream()
+    k = 5.0
+    rates = {}
+    for level in (3, 5):
+        v, f = I.icosphere(level)
+        vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+        M = 3 * f.shape[0]
+        x_h = I.complex_vector(M, 0)
+        xd = torch.from_numpy(x_h).to(cdt).cuda()
+        prm = hmx.params(tol=0.0, precision=prec)
+
+        def step():
+            op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, prm=prm, stream=stream)
+            return op, op.matvec(xd, stream=stream)
+
+        if level == 3:
+            ms_step, _ = timed_steps(step, args.steps, args.warmup)
+        op, y = step()
+        torch.cuda.synchronize()
+        mv_ms = product_ms(op, xd, y, stream, max(args.matvec_reps, 20))
+        rates[level] = (M, mv_ms, M * (M - 1) / (mv_ms * 1e-3))
+        log(f"dense L{level}: M={M}, product {mv_ms:.4f} ms, {rates[level][2]:.3e} evaluations/s")
+        if level == 3:
+            y3, x3, v3, f3 = y.cpu().numpy().astype(np.complex128), x_h, v, f
+        op.close()
+    cpu, rel_err = None, None
+    if args.cpu_baseline == "on":
+        # the oracle leg: the full dense product at 3 840 points on all host cores and on one
+        P, Wq = oracle.quad_points(v3, f3, bary, w)
+        cores = oracle.max_threads()
+        c0 = time.perf_counter()
+        yr = oracle.dense_matvec(P, Wq, oracle.HELMHOLTZ, k, x3)
+        c1 = time.perf_counter()
+        oracle.dense_matvec(P, Wq, oracle.HELMHOLTZ, k, x3, nthreads=1)
+        c2 = time.perf_counter()
+        oracle.dense_matvec(P[:1], Wq[:1], oracle.HELMHOLTZ, k, x3[:1], nthreads=cores)  # restore
+        rel_err = float(np.linalg.norm(y3 - yr) / np.linalg.norm(yr))
+        cpu = {"value": round((c1 - c0) * 1e3, 3), "unit": "ms per dense product (3 840 points)",
+               "cores": cores, "kind": "oracle",
+               "sample": f"the full product once; on one core {(c2 - c1) * 1e3:.1f} ms"}
+    M3, mv3, r3 = rates[3]
+    M5, mv5, r5 = rates[5]
+    peak = DENSE_ALU_PEAK[args.precision]
+    extra = {
+        "dense_matvec_ms": round(mv3, 4),
+        "rel_err": rel_err,
+        "kernel_evals_per_s": r3,
+        "kernel_evals_per_s_61440_points": r5,
+        "dense_matvec_ms_61440_points": round(mv5, 4),
+        "roofline": {"bound": "alu", "kernel": "hmx::dense_otf_kernel (one evaluation per pair "
+                     "and multiply-accumulate, on the fly)", "achieved": round(r5, 1),
+                     "peak": round(peak, 1), "unit": "evaluations/s", "frac": round(r5 / peak, 4),
+                     "traffic": None, "at": "61 440 points (3 840 points: %.3e/s)" % r3},
+        "cpu_baseline": cpu,
+    }
+    config = {"workload": f"unit icosphere L3 (1280 triangles, {M3} points), Helmholtz k=5, dense "
+                          f"operator on the fly, {args.precision}"}
+    line(args, ms_step, args.precision, config, extra,
+         unit="ms per step (dense operator from device mesh + one product)")
+
+
 def mie_scattered(T, k, d, nmax=80):
     """Sound-soft unit sphere, incident e^{ik x.d}: the closed-form exterior scattered field."""
     from scipy import special
@@ -606,8 +682,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["sphere", "batch", "large", "radiation", "scattering"],
-                    default="sphere")
+    ap.add_argument("--workload", choices=["sphere", "batch", "large", "radiation", "scattering",
+                                           "dense"], default="sphere")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--level", type=int, default=6)
     ap.add_argument("--k", type=float, default=40.0)
@@ -635,7 +711,7 @@ def main():
         import oracle
 
     {"sphere": run_sphere, "batch": run_batch, "large": run_large, "radiation": run_radiation,
-     "scattering": run_scattering}[args.workload](args, torch, oracle, hmx, I)
+     "scattering": run_scattering, "dense": run_dense}[args.workload](args, torch, oracle, hmx, I)
 
 
 if __name__ == "__main__":
