@@ -137,3 +137,12 @@ def test_closed_operator_is_refused(H):
     with pytest.raises(RuntimeError):
         p1.matvec(x)
     p1.close()
+
+
+def test_galerkin_on_dense_operator(H):
+    """The P1 space also serves a dense operator (tol <= 0): A equals the oracle's matrix to 1e-12."""
+    v, f, op, p1 = space(H, 2, 3.0, False, tol=0.0)
+    assert op.info["is_dense"] == 1
+    A, Phi, P, W = oracle.galerkin_matrix(v, f, *RULE, oracle.HELMHOLTZ, 3.0)
+    xv = I.complex_vector(v.shape[0], 6)
+    assert rel(host(p1.matvec(dev(xv))), A @ xv) <= 1e-12
