@@ -730,9 +730,10 @@ void galerkin_enqueue(const hmx_p1* P, const T* xv, T* yv, hipStream_t s) {
 }
 
 // Restarted GMRES(m) for A x = b, A = Phi^T W K Phi, from x = 0: classical Gram-Schmidt with one
-// reorthogonalisation (two batched dot launches per step), complex Givens rotations on the
-// host, stop when the residual estimate falls to tol ||b|| or after max_it products; each cycle
-// starts from the true residual b - A x, which is also what is reported.
+// reorthogonalisation (two batched dot launches per step, the coefficients applied from device
+// memory, one copy to the host per step), complex Givens rotations on the host, stop when the
+// residual estimate falls to tol ||b|| or after max_it products; each cycle starts from the true
+// residual b - A x, which is also what is reported.
 template <class T>
 void gmres_run(const hmx_p1* P, const T* b, T* x, int m, int max_it, double tol, hipStream_t s,
                int32_t* iters, double* relres) {
@@ -740,15 +741,11 @@ void gmres_run(const hmx_p1* P, const T* b, T* x, int m, int max_it, double tol,
   const int64_t n = P->nv;
   DevBuf<T> V((size_t)n * (m + 1)), w(n), r(n);
   DevBuf<double2> partial((size_t)mdot_chunks(n) * (m + 1)), dd(m + 1), hd(m + 1);
-  std::vector<double2> hbuf(m + 1);
+  // one step's Gram-Schmidt coefficients (two passes) and the new vector's squared norm stay on
+  // the device between the kernels and come back to the host in one copy
+  DevBuf<double2> step_d((size_t)2 * (m + 1) + 1);
+  std::vector<double2> hbuf(m + 1), step_h(2 * (m + 1) + 1);
   auto col = [&](int c) { return V.p + (int64_t)c * n; };
-  auto dots = [&](int nc, const T* vec, std::vector<cd>& out) {
-    launch_mdot<T>(V.p, n, nc, vec, n, partial.p, dd.p, s);
-    HMX_HIP(hipMemcpyAsync(hbuf.data(), dd.p, nc * sizeof(double2), hipMemcpyDeviceToHost, s));
-    HMX_HIP(hipStreamSynchronize(s));
-    out.resize(nc);
-    for (int c = 0; c < nc; ++c) out[c] = cd(hbuf[c].x, hbuf[c].y);
-  };
   auto norm = [&](const T* vec) {
     launch_mdot<T>(vec, n, 1, vec, n, partial.p, dd.p, s);
     double2 v;
@@ -770,7 +767,7 @@ void gmres_run(const hmx_p1* P, const T* b, T* x, int m, int max_it, double tol,
     *relres = 0.0;
     return;
   }
-  std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m), h, h2, y(m);
+  std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m), y(m);
   std::vector<double> cs(m);
   auto Hc = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
   for (;;) {
@@ -791,12 +788,20 @@ void gmres_run(const hmx_p1* P, const T* b, T* x, int m, int max_it, double tol,
       const int j = k;
       galerkin_enqueue<T>(P, col(j), w.p, s);
       ++it;
-      dots(j + 1, w.p, h);
-      subtract(h, j + 1, w.p, -1.0);
-      dots(j + 1, w.p, h2);
-      subtract(h2, j + 1, w.p, -1.0);
-      for (int c = 0; c <= j; ++c) Hc(c, j) = h[c] + h2[c];
-      const double hn = norm(w.p);
+      double2* d1 = step_d.p;
+      double2* d2 = step_d.p + (m + 1);
+      double2* dn = step_d.p + 2 * (m + 1);
+      launch_mdot<T>(V.p, n, j + 1, w.p, n, partial.p, d1, s);  // h = V^H w
+      launch_gemv_update<T>(V.p, n, d1, j + 1, -1.0, w.p, n, s);
+      launch_mdot<T>(V.p, n, j + 1, w.p, n, partial.p, d2, s);  // reorthogonalisation
+      launch_gemv_update<T>(V.p, n, d2, j + 1, -1.0, w.p, n, s);
+      launch_mdot<T>(w.p, n, 1, w.p, n, partial.p, dn, s);
+      HMX_HIP(hipMemcpyAsync(step_h.data(), step_d.p, step_h.size() * sizeof(double2),
+                             hipMemcpyDeviceToHost, s));
+      HMX_HIP(hipStreamSynchronize(s));
+      for (int c = 0; c <= j; ++c)
+        Hc(c, j) = cd(step_h[c].x, step_h[c].y) + cd(step_h[m + 1 + c].x, step_h[m + 1 + c].y);
+      const double hn = std::sqrt(std::max(step_h[2 * (m + 1)].x, 0.0));
       Hc(j + 1, j) = hn;
       for (int i = 0; i < j; ++i) {  // previous rotations
         const cd t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
