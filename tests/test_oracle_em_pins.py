@@ -1,0 +1,188 @@
+"""Pins of the oracle's electromagnetic equations (Section 6.2: EFIE, MFIE, CFIE on RWG elements),
+against facts the oracle does not use:
+  * RWG topology: one unknown per edge (3 n_t / 2 on a closed mesh), errors for an open mesh and
+    for a flipped triangle;
+  * the RWG functions: unit normal component across their own edge from both triangles, none
+    across the other edges, divergence +- l / A integrating to zero over the support;
+  * the RWG mass matrix equals the closed form from the moments of a triangle,
+    int_T y y^T = A / 12 (sum_k v_k v_k^T + 9 g g^T);
+  * the Mie coefficients of the PEC sphere conserve energy (extinction = scattering);
+  * the far field of the PEC unit sphere from the EFIE, the MFIE and the CFIE converges at second
+    order in h to the Mie series (Bohren & Huffman's S1, S2 with a_n = psi_n' / xi_n',
+    b_n = psi_n / xi_n); a flipped divergence term, a flipped double layer or a dropped identity
+    term misses it by more than 100 %.
+"""
+import numpy as np
+import pytest
+from scipy import special
+
+import oracle
+from oracle import rwg
+from paper_1804_00995_amd import inputs as I
+
+RULE = I.rule_3pt()
+K = 2.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+def test_edges_of_closed_mesh_and_errors():
+    v, f = I.icosphere(2)
+    edges, tedge, tsign = rwg.rwg_edges(f)
+    assert edges.shape[0] == 3 * f.shape[0] // 2
+    assert (edges[:, 0] < edges[:, 1]).all()
+    assert np.array_equal(edges, np.unique(edges, axis=0))  # increasing (a, b)
+    for e in (0, 17, edges.shape[0] - 1):  # one +1 and one -1 incidence per edge
+        assert sorted(tsign[tedge == e].tolist()) == [-1, 1]
+    with pytest.raises(ValueError):
+        rwg.rwg_edges(f[1:])  # open
+    g = f.copy()
+    g[5] = g[5][::-1]
+    with pytest.raises(ValueError):
+        rwg.rwg_edges(g)  # inconsistent orientation
+
+
+def test_rwg_normal_components_and_divergence():
+    v, f = I.icosphere(1)
+    mid = np.array([[0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])  # point q on edge q
+    Psi, Div, _ = rwg.rwg_matrices(v, f, mid)
+    edges, tedge, tsign = rwg.rwg_edges(f)
+    for t in range(f.shape[0]):
+        V = v[f[t]]
+        n = np.cross(V[1] - V[0], V[2] - V[0])
+        area = 0.5 * np.linalg.norm(n)
+        n /= np.linalg.norm(n)
+        for q in range(3):  # midpoint of the edge opposite vertex q
+            a, b = V[(q + 1) % 3], V[(q + 2) % 3]
+            nu = np.cross(b - a, n)
+            nu /= np.linalg.norm(nu)  # in-plane, pointing out of the triangle
+            for j in range(3):
+                e = tedge[t, j]
+                flux = Psi[:, 3 * t + q, e] @ nu
+                if j == q:
+                    assert abs(flux - tsign[t, j]) < 1e-13
+                else:
+                    assert abs(flux) < 1e-13
+            for j in range(3):
+                ln = np.linalg.norm(V[(j + 2) % 3] - V[(j + 1) % 3])
+                assert abs(Div[3 * t + q, tedge[t, j]] - tsign[t, j] * ln / area) < 1e-12
+    _, W = oracle.quad_points(v, f, *RULE)
+    _, Div3, _ = rwg.rwg_matrices(v, f, RULE[0])
+    assert np.abs(W @ Div3).max() < 1e-14
+
+
+def mass_closed_form(v, f):
+    edges, tedge, tsign = rwg.rwg_edges(f)
+    Mm = np.zeros((edges.shape[0],) * 2)
+    for t in range(f.shape[0]):
+        V = v[f[t]]
+        area = 0.5 * np.linalg.norm(np.cross(V[1] - V[0], V[2] - V[0]))
+        g = V.mean(0)
+        tr_yy = area / 12.0 * ((V ** 2).sum() + 9.0 * g @ g)
+        c = [tsign[t, j] * np.linalg.norm(V[(j + 2) % 3] - V[(j + 1) % 3]) / (2 * area) for j in range(3)]
+        for i in range(3):
+            for j in range(3):
+                # int_T (y - p_i).(y - p_j) = tr int y y^T - (p_i + p_j).int y + A p_i.p_j
+                m = tr_yy - (V[i] + V[j]) @ (area * g) + area * V[i] @ V[j]
+                Mm[tedge[t, i], tedge[t, j]] += c[i] * c[j] * m
+    return Mm
+
+
+def test_mass_matrix_closed_form():
+    v, f = I.icosphere(2)
+    mats, *_ = rwg.em_matrices(v, f, *RULE, K, parts=("Id",))
+    ref = mass_closed_form(v, f)
+    assert np.abs(mats["Id"] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def mie_coefficients(k):
+    nmax = int(k + 4 * k ** (1 / 3) + 10)
+    n = np.arange(1, nmax + 1)
+    jn, djn = special.spherical_jn(n, k), special.spherical_jn(n, k, derivative=True)
+    hn = jn + 1j * special.spherical_yn(n, k)
+    dhn = djn + 1j * special.spherical_yn(n, k, derivative=True)
+    return n, (jn + k * djn) / (hn + k * dhn), jn / hn
+
+
+def mie_pec_far_field(k, th, ph):
+    """F with E_s ~ F e^{ikR} / R for the PEC unit sphere and E_inc = x e^{ikz}."""
+    n, a, b = mie_coefficients(k)
+    mu = np.cos(th)
+    S1 = np.zeros_like(mu, complex)
+    S2 = np.zeros_like(mu, complex)
+    pi_prev, pi_cur = np.zeros_like(mu), np.ones_like(mu)
+    for i, nn in enumerate(n):
+        tau = nn * mu * pi_cur - (nn + 1) * pi_prev
+        c = (2 * nn + 1) / (nn * (nn + 1))
+        S1 += c * (a[i] * pi_cur + b[i] * tau)
+        S2 += c * (a[i] * tau + b[i] * pi_cur)
+        pi_prev, pi_cur = pi_cur, ((2 * nn + 1) * mu * pi_cur - (nn + 1) * pi_prev) / nn
+    e_th = np.stack([np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), -np.sin(th)], 1)
+    e_ph = np.stack([-np.sin(ph), np.cos(ph), np.zeros_like(ph)], 1)
+    return (np.cos(ph) * S2)[:, None] * e_th / (-1j * k) - (np.sin(ph) * S1)[:, None] * e_ph / (-1j * k)
+
+
+def test_mie_coefficients_conserve_energy():
+    for k in (0.5, 2.0, 7.0):
+        n, a, b = mie_coefficients(k)
+        ext = ((2 * n + 1) * (a + b).real).sum()
+        sca = ((2 * n + 1) * (abs(a) ** 2 + abs(b) ** 2)).sum()
+        assert abs(ext - sca) <= 1e-12 * sca
+
+
+def directions(n=40, seed=0):
+    rng = np.random.default_rng(seed)
+    th = np.arccos(rng.uniform(-1, 1, n))
+    ph = rng.uniform(0, 2 * np.pi, n)
+    return th, ph, np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1)
+
+
+def far_errors(level, betas, reg=2.0):
+    v, f = I.icosphere(level)
+    mats, Psi, Div, NxPsi, P, W = rwg.em_matrices(v, f, *RULE, K, reg_radius=reg)
+    Ei, Hi = rwg.plane_wave(P, K, [0.0, 0.0, 1.0], [1.0, 0.0, 0.0])
+    th, ph, u = directions()
+    ex = mie_pec_far_field(K, th, ph)
+    out = {}
+    for beta in betas:
+        x = np.linalg.solve(rwg.cfie_matrix(mats, beta), rwg.cfie_rhs(Psi, NxPsi, W, Ei, Hi, beta))
+        out[beta] = np.abs(rwg.far_field(Psi, P, W, x, K, u) - ex).max() / np.abs(ex).max()
+    return out, mats, (Psi, Div, NxPsi, P, W, Ei, Hi, u, ex)
+
+
+def test_pec_sphere_second_order_all_formulations():
+    betas = (1.0, 0.0, 0.5)
+    e = [far_errors(L, betas)[0] for L in (1, 2, 3)]
+    for beta in betas:
+        assert 3.0 <= e[0][beta] / e[1][beta] <= 5.5, (beta, e)
+        assert 3.0 <= e[1][beta] / e[2][beta] <= 5.5, (beta, e)
+        assert e[2][beta] < 1.2e-2, (beta, e)
+
+
+def test_pec_sphere_misses_with_wrong_terms():
+    errs, mats, (Psi, Div, NxPsi, P, W, Ei, Hi, u, ex) = far_errors(2, (1.0,))
+    K0 = oracle.dense_matrix(P, W, oracle.HELMHOLTZ, K) + oracle.reg_matrix(P, W, *I.icosphere(2), RULE[0], 2.0)
+
+    def err(A, b):
+        x = np.linalg.solve(A, b)
+        return np.abs(rwg.far_field(Psi, P, W, x, K, u) - ex).max() / np.abs(ex).max()
+
+    b1 = rwg.cfie_rhs(Psi, NxPsi, W, Ei, Hi, 1.0)
+    b0 = rwg.cfie_rhs(Psi, NxPsi, W, Ei, Hi, 0.0)
+    div_term = (1j / K) * Div.T @ (W[:, None] * (K0 @ Div))
+    assert errs[1.0] < 0.04
+    assert err(-(mats["T"] + 2 * div_term), b1) > 1.0
+    assert err(0.5 * mats["Id"] + mats["NxK"], b0) > 1.0
+    assert err(-mats["NxK"], b0) > 1.0
+
+
+def test_efie_matrix_symmetric_mass_positive():
+    """W G W is symmetric, so T is (the correction, exact in y only, is not)."""
+    v, f = I.icosphere(1)
+    mats, *_ = rwg.em_matrices(v, f, *RULE, 3.0)
+    T, Id = mats["T"], mats["Id"]
+    assert np.abs(T - T.T).max() <= 1e-14 * np.abs(T).max()
+    assert np.linalg.eigvalsh(Id).min() > 0
