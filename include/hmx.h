@@ -221,6 +221,56 @@ hmx_status hmx_galerkin_matvec(const hmx_p1* p, const void* xv, void* yv, void* 
 hmx_status hmx_gmres(const hmx_p1* p, const void* b, void* x, int32_t restart, int32_t max_iter,
                      double tol, void* stream, int32_t* iters, double* relres);
 
+/* Electromagnetic scattering (Section 6.2) on lowest-order Raviart-Thomas (RWG) elements
+ * (Section 4): one unknown per edge of a closed, consistently oriented mesh, edges numbered in
+ * increasing (a, b), a < b their vertex numbers.  On triangle t the edge opposite local vertex j
+ * carries psi(y) = s l / (2 A) (y - p_j) (l its length, A the area, p_j the opposite vertex,
+ * s = +1 on the triangle whose vertex order runs a -> b along the edge, -1 on the other), with
+ * divergence s l / A; n = (v1 - v0) x (v2 - v0) / |.| is outward for an outward-oriented mesh.
+ * The CFIE matrix, for beta in [0, 1], is
+ *   A = -beta T + (1 - beta) (Id / 2 - NxK),
+ *   T = i k sum_d Psi_d^T W K Psi_d - (i / k) D^T W K D       (EFIE; K the single layer),
+ *   NxK_ij = int int (n x psi_i)(x) . (grad_y G(x, y) x psi_j(y)) dx dy   (MFIE double layer),
+ *   Id the RWG mass matrix,
+ * all integrals by the point quadrature; beta = 1 is the EFIE (as -T), beta = 0 the MFIE.
+ * hmx_rwg_create: the space of the mesh the operators were built on (hmx_build with the same
+ * vtx, tri and rule): `single` the Helmholtz single layer (kernel HMX_HELMHOLTZ, with or without
+ * the correction) for beta > 0, grad_x/y/z the kernels HMX_GRADY_X/Y/Z for beta < 1 (all three
+ * or none), one wavenumber k > 0 and one precision; the caller keeps them alive while the space
+ * is used.  vtx, tri device arrays as in hmx_build; q_bary, q_w host.  Errors: HMX_EINVAL for
+ * null pointers, missing or mismatched operators, a mesh that is not closed and consistently
+ * oriented (every edge in exactly two triangles, run in opposite directions) or that hmx_build
+ * rejects; HMX_EUNSUPPORTED for row-share operators.  Synchronous. */
+typedef struct hmx_rwg hmx_rwg;
+hmx_status hmx_rwg_create(const hmx_op* single, const hmx_op* grad_x, const hmx_op* grad_y,
+                          const hmx_op* grad_z, const double* vtx, int64_t n_vtx,
+                          const int32_t* tri, int64_t n_tri, const double* q_bary,
+                          const double* q_w, int32_t n_q, void* stream, hmx_rwg** out);
+void hmx_rwg_destroy(hmx_rwg* r); /* NULL is accepted */
+/* Number of edges (unknowns), and the edges' vertex pairs (device int32, 2 per edge, a < b;
+ * asynchronous on `stream`). */
+hmx_status hmx_rwg_n_edges(const hmx_rwg* r, int64_t* n_edges);
+hmx_status hmx_rwg_edges(const hmx_rwg* r, int32_t* edges, void* stream);
+/* u = the field sum_e x_e psi_e at the quadrature points: 4 n_q n_tri entries, component-major
+ * (J_x, J_y, J_z, div J), original point order; x has n_edges entries.  Device vectors of the
+ * operators' complex type.  Asynchronous on `stream`. */
+hmx_status hmx_rwg_interp(const hmx_rwg* r, const void* x, void* u, void* stream);
+/* b_i = beta <psi_i, E_inc> - (1 - beta) <n x psi_i, H_inc>: the CFIE right-hand side from the
+ * incident fields at the quadrature points (3 n_q n_tri entries each, component-major; e_inc
+ * may be NULL when beta = 0, h_inc when beta = 1).  Asynchronous on `stream`. */
+hmx_status hmx_rwg_rhs(const hmx_rwg* r, double beta, const void* e_inc, const void* h_inc,
+                       void* b, void* stream);
+/* y = A x (n_edges entries each): 4 single-layer products for beta > 0 and 6 gradient-kernel
+ * products for beta < 1.  The space holds the scratch, so products on one space must not
+ * overlap in time.  Errors: HMX_EINVAL for null pointers, beta outside [0, 1] or an operator the
+ * beta needs that the space lacks.  Asynchronous on `stream`; allocates nothing. */
+hmx_status hmx_cfie_matvec(const hmx_rwg* r, double beta, const void* x, void* y, void* stream);
+/* Solves A x = b by restarted GMRES as hmx_gmres does (same stopping rule and reports).
+ * Errors: as hmx_cfie_matvec and hmx_gmres.  Synchronous. */
+hmx_status hmx_cfie_gmres(const hmx_rwg* r, double beta, const void* b, void* x, int32_t restart,
+                          int32_t max_iter, double tol, void* stream, int32_t* iters,
+                          double* relres);
+
 /* One surface of a batch: vtx, tri device arrays as in hmx_build, and the surface's wavenumber. */
 typedef struct {
   const double* vtx;

@@ -32,6 +32,7 @@ UNITS = [
     ("k_near.hip", False),
     ("k_reg.hip", True),
     ("k_p1.hip", False),
+    ("k_rwg.hip", False),
     ("k_aca.hip", False),
     ("k_far.hip", False),
     ("k_matvec.hip", False),

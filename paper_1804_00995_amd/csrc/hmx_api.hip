@@ -729,16 +729,15 @@ void galerkin_enqueue(const hmx_p1* P, const T* xv, T* yv, hipStream_t s) {
   launch_p1_project<T>(P->ptr.p, P->inc.p, P->nv, P->rule, P->w.p, (const T*)P->kp.p, yv, s);
 }
 
-// Restarted GMRES(m) for A x = b, A = Phi^T W K Phi, from x = 0: classical Gram-Schmidt with one
-// reorthogonalisation (two batched dot launches per step, the coefficients applied from device
-// memory, one copy to the host per step), complex Givens rotations on the host, stop when the
-// residual estimate falls to tol ||b|| or after max_it products; each cycle starts from the true
-// residual b - A x, which is also what is reported.
-template <class T>
-void gmres_run(const hmx_p1* P, const T* b, T* x, int m, int max_it, double tol, hipStream_t s,
-               int32_t* iters, double* relres) {
+// Restarted GMRES(m) for A x = b (apply(v, out): out = A v on the stream), from x = 0:
+// classical Gram-Schmidt with one reorthogonalisation (two batched dot launches per step, the
+// coefficients applied from device memory, one copy to the host per step), complex Givens
+// rotations on the host, stop when the residual estimate falls to tol ||b|| or after max_it
+// products; each cycle starts from the true residual b - A x, which is also what is reported.
+template <class T, class Apply>
+void gmres_run(Apply apply, int64_t n, const T* b, T* x, int m, int max_it, double tol,
+               hipStream_t s, int32_t* iters, double* relres) {
   using cd = std::complex<double>;
-  const int64_t n = P->nv;
   DevBuf<T> V((size_t)n * (m + 1)), w(n), r(n);
   DevBuf<double2> partial((size_t)mdot_chunks(n) * (m + 1)), dd(m + 1), hd(m + 1);
   // one step's Gram-Schmidt coefficients (two passes) and the new vector's squared norm stay on
@@ -774,7 +773,7 @@ void gmres_run(const hmx_p1* P, const T* b, T* x, int m, int max_it, double tol,
     if (it == 0) {
       HMX_HIP(hipMemcpyAsync(r.p, b, n * sizeof(T), hipMemcpyDeviceToDevice, s));
     } else {
-      galerkin_enqueue<T>(P, x, w.p, s);
+      apply(x, w.p);
       launch_vec<T>(w.p, b, 0.0, 1, r.p, n, s);  // r = b - A x
     }
     const double beta = norm(r.p);
@@ -786,7 +785,7 @@ void gmres_run(const hmx_p1* P, const T* b, T* x, int m, int max_it, double tol,
     int k = 0;  // columns of this cycle
     while (k < m) {
       const int j = k;
-      galerkin_enqueue<T>(P, col(j), w.p, s);
+      apply(col(j), w.p);
       ++it;
       double2* d1 = step_d.p;
       double2* d2 = step_d.p + (m + 1);
@@ -943,9 +942,11 @@ hmx_status hmx_gmres(const hmx_p1* p, const void* b, void* x, int32_t restart, i
   HMX_REQUIRE(std::isfinite(tol) && tol >= 0, HMX_EINVAL, "tol must be finite and >= 0");
   hipStream_t s = as_stream(stream);
   if (p->op->prec == HMX_FP64)
-    gmres_run<double2>(p, (const double2*)b, (double2*)x, restart, max_iter, tol, s, iters, relres);
+    gmres_run<double2>([&](const double2* v, double2* out) { galerkin_enqueue<double2>(p, v, out, s); },
+                       p->nv, (const double2*)b, (double2*)x, restart, max_iter, tol, s, iters, relres);
   else
-    gmres_run<float2>(p, (const float2*)b, (float2*)x, restart, max_iter, tol, s, iters, relres);
+    gmres_run<float2>([&](const float2* v, float2* out) { galerkin_enqueue<float2>(p, v, out, s); },
+                      p->nv, (const float2*)b, (float2*)x, restart, max_iter, tol, s, iters, relres);
   return HMX_OK;
   API_CATCH
 }
@@ -953,5 +954,279 @@ hmx_status hmx_gmres(const hmx_p1* p, const void* b, void* x, int32_t restart, i
 const char* hmx_last_error(void) { return g_err.c_str(); }
 
 void hmx_release_cache(void) { dev_release_cache(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ RWG elements, EFIE/MFIE/CFIE
+// The RWG space of a closed, consistently oriented mesh: per triangle the edge of each local
+// vertex (tedge), its orientation and a geometry record; per edge its two incidences 3 t + j
+// (the triangle running along it a -> b first); the point weights; and the operators: the
+// single layer for the EFIE terms, the three gradient kernels for the MFIE term.  Scratch: 14
+// vectors of M entries (the RWG field and its divergence, the four single-layer products, the
+// six gradient products).
+struct hmx_rwg {
+  const hmx_op* single = nullptr;
+  const hmx_op* grad[3] = {nullptr, nullptr, nullptr};
+  const hmx_op* any = nullptr;
+  int64_t nt = 0, ne = 0, M = 0;
+  double k = 0.0;
+  int32_t prec = HMX_FP64;
+  hmx::P1Rule rule{};
+  hmx::DevBuf<int32_t> tedge, einc, edges;
+  hmx::DevBuf<double> rec, w;
+  hmx::DevBuf<unsigned char> scratch;
+  template <class T>
+  T* vec(int i) const {
+    return (T*)scratch.p + (int64_t)i * M;
+  }
+};
+
+namespace {
+
+// y = A x, A = -beta T + (1 - beta) (Id / 2 - NxK):
+//   T = i k sum_d Psi_d^T W K Psi_d - (i / k) D^T W K D      (K the single layer)
+//   NxK x = <n x psi_i, c>,  c_e = G_{e+1} u_{e+2} - G_{e+2} u_{e+1}  (G_d the gradient kernels)
+template <class T>
+void cfie_enqueue(const hmx_rwg* R, double beta, const T* x, T* y, hipStream_t s) {
+  T* u = R->vec<T>(0);  // u_0..u_2 = Psi x, u_3 = D x  (slots 0..3)
+  launch_rwg_interp<T>(R->rec.p, R->tedge.p, R->nt, R->rule, x, u, s);
+  RwgTerms<T> a;
+  if (beta != 0.0) {
+    for (int d = 0; d < 4; ++d) enqueue_matvec(R->single, R->vec<T>(d), R->vec<T>(4 + d), s);
+    for (int d = 0; d < 3; ++d) a.ku[d] = R->vec<T>(4 + d);
+    a.kv = R->vec<T>(7);
+    a.aT = make_double2(0.0, -beta * R->k);
+    a.aD = make_double2(0.0, beta / R->k);
+  }
+  if (beta != 1.0) {
+    for (int e = 0; e < 3; ++e) {
+      const int e1 = (e + 1) % 3, e2 = (e + 2) % 3;
+      enqueue_matvec(R->grad[e1], R->vec<T>(e2), R->vec<T>(8 + e), s);
+      enqueue_matvec(R->grad[e2], R->vec<T>(e1), R->vec<T>(11 + e), s);
+      a.u[e] = R->vec<T>(e);
+      a.cp[e] = R->vec<T>(8 + e);
+      a.cm[e] = R->vec<T>(11 + e);
+    }
+    a.aI = 0.5 * (1.0 - beta);
+    a.aN = -(1.0 - beta);
+  }
+  launch_rwg_project<T>(R->einc.p, R->ne, R->rec.p, R->rule, R->w.p, a, y, s);
+}
+
+void check_beta(const hmx_rwg* R, double beta) {
+  HMX_REQUIRE(std::isfinite(beta) && beta >= 0.0 && beta <= 1.0, HMX_EINVAL,
+              "beta must be in [0, 1]");
+  HMX_REQUIRE(beta == 0.0 || R->single, HMX_EINVAL, "beta > 0 needs the single-layer operator");
+  HMX_REQUIRE(beta == 1.0 || R->grad[0], HMX_EINVAL, "beta < 1 needs the gradient operators");
+}
+
+}  // namespace
+
+extern "C" {
+
+hmx_status hmx_rwg_create(const hmx_op* single, const hmx_op* grad_x, const hmx_op* grad_y,
+                          const hmx_op* grad_z, const double* vtx, int64_t n_vtx,
+                          const int32_t* tri, int64_t n_tri, const double* q_bary,
+                          const double* q_w, int32_t n_q, void* stream, hmx_rwg** out) {
+  API_TRY
+  HMX_REQUIRE(vtx && tri && out, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(n_vtx >= 3 && n_tri >= 2, HMX_EINVAL, "empty mesh");
+  const int ng = (grad_x != nullptr) + (grad_y != nullptr) + (grad_z != nullptr);
+  HMX_REQUIRE(ng == 0 || ng == 3, HMX_EINVAL, "give all three gradient operators or none");
+  HMX_REQUIRE(single || ng == 3, HMX_EINVAL, "no operator given");
+  const hmx_op* ops[4] = {single, grad_x, grad_y, grad_z};
+  const hmx_op* any = single ? single : grad_x;
+  for (int i = 0; i < 4; ++i) {
+    const hmx_op* op = ops[i];
+    if (!op) continue;
+    HMX_REQUIRE(op->kern == (i == 0 ? HMX_HELMHOLTZ : HMX_GRADY_X + i - 1), HMX_EINVAL,
+                "the operators must be the Helmholtz single layer and its y-gradients x, y, z");
+    HMX_REQUIRE(!op->rect && op->mesh_off.size() <= 2, HMX_EINVAL,
+                "the RWG space needs operators on one mesh's own points");
+    HMX_REQUIRE(op->M == n_tri * (int64_t)n_q, HMX_EINVAL,
+                "the operator's points are not this mesh's quadrature points (M != n_q n_tri)");
+    HMX_REQUIRE(op->dense || op->p.row_shares == 1, HMX_EUNSUPPORTED,
+                "the RWG products need all rows of the operators (no row share)");
+    HMX_REQUIRE(op->prec == any->prec, HMX_EINVAL, "the operators differ in precision");
+    HMX_REQUIRE(op->k == any->k, HMX_EINVAL, "the operators differ in wavenumber");
+  }
+  HMX_REQUIRE(any->k > 0.0, HMX_EINVAL, "the electromagnetic equations need k > 0");
+  Rule r = make_rule(q_bary, q_w, n_q);
+  hipStream_t s = as_stream(stream);
+  auto R = std::make_unique<hmx_rwg>();
+  R->single = single;
+  R->grad[0] = grad_x;
+  R->grad[1] = grad_y;
+  R->grad[2] = grad_z;
+  R->any = any;
+  R->nt = n_tri;
+  R->M = any->M;
+  R->k = any->k;
+  R->prec = any->prec;
+  R->rule.nq = n_q;
+  for (int q = 0; q < n_q; ++q)
+    for (int j = 0; j < 3; ++j) R->rule.b[q][j] = r.b[q][j];
+  // point weights in the original order (and the range check of the triangles)
+  DevBuf<double> X(R->M), Y(R->M), Z(R->M);
+  R->w.alloc(R->M);
+  DevBuf<int> err(1);
+  fill_i32(err.p, 0, 1, s);
+  launch_quad(vtx, n_vtx, tri, n_tri, r, X.p, Y.p, Z.p, R->w.p, err.p, s);
+  const int e = read1(err.p, s);
+  HMX_REQUIRE(!(e & 1), HMX_EINVAL, "triangle vertex index out of range");
+  HMX_REQUIRE(!(e & 2), HMX_EINVAL, "non-finite vertex coordinate");
+  // edges: sort the 3 n_tri (triangle, local vertex) slots by the vertex pair of their edge
+  std::vector<int32_t> ht;
+  to_host(ht, tri, 3 * n_tri, s);
+  const int64_t ns = 3 * n_tri;
+  std::vector<uint64_t> key(ns);
+  for (int64_t i = 0; i < ns; ++i) {
+    const int64_t t = i / 3;
+    const int j = (int)(i % 3);
+    const uint32_t a = (uint32_t)ht[3 * t + (j + 1) % 3], b = (uint32_t)ht[3 * t + (j + 2) % 3];
+    key[i] = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
+  }
+  std::vector<int64_t> order(ns);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return key[x] != key[y] ? key[x] < key[y] : x < y;
+  });
+  std::vector<int32_t> tedge(ns), tsign(ns), einc, edges;
+  einc.reserve(ns);
+  edges.reserve(ns);
+  for (int64_t i = 0; i < ns;) {
+    int64_t j = i;
+    while (j < ns && key[order[j]] == key[order[i]]) ++j;
+    HMX_REQUIRE(j - i == 2, HMX_EINVAL, "every edge must belong to exactly two triangles");
+    const int64_t ed = (int64_t)edges.size() / 2;
+    int32_t plus = -1, minus = -1;
+    for (int64_t l = i; l < j; ++l) {
+      const int64_t slot = order[l], t = slot / 3;
+      const int jj = (int)(slot % 3);
+      const bool fwd = ht[3 * t + (jj + 1) % 3] < ht[3 * t + (jj + 2) % 3];
+      tedge[slot] = (int32_t)ed;
+      tsign[slot] = fwd ? 1 : -1;
+      (fwd ? plus : minus) = (int32_t)slot;
+    }
+    HMX_REQUIRE(plus >= 0 && minus >= 0, HMX_EINVAL,
+                "the two triangles of an edge must run along it in opposite directions");
+    einc.push_back(plus);
+    einc.push_back(minus);
+    edges.push_back((int32_t)(key[order[i]] >> 32));
+    edges.push_back((int32_t)(key[order[i]] & 0xffffffffu));
+    i = j;
+  }
+  R->ne = (int64_t)edges.size() / 2;
+  R->tedge.alloc(ns);
+  R->einc.alloc(einc.size());
+  R->edges.alloc(edges.size());
+  DevBuf<int32_t> dsign(ns);
+  HMX_HIP(hipMemcpyAsync(R->tedge.p, tedge.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HMX_HIP(hipMemcpyAsync(dsign.p, tsign.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HMX_HIP(hipMemcpyAsync(R->einc.p, einc.data(), einc.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+  HMX_HIP(hipMemcpyAsync(R->edges.p, edges.data(), edges.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+  R->rec.alloc((size_t)RWG_REC * n_tri);
+  launch_rwg_geom(vtx, tri, dsign.p, n_tri, R->rec.p, s);
+  R->scratch.alloc((size_t)14 * R->M * any->elem);
+  HMX_HIP(hipStreamSynchronize(s));
+  *out = R.release();
+  return HMX_OK;
+  API_CATCH
+}
+
+void hmx_rwg_destroy(hmx_rwg* r) {
+  if (!r) return;
+  (void)hipDeviceSynchronize();
+  delete r;
+}
+
+hmx_status hmx_rwg_n_edges(const hmx_rwg* r, int64_t* n_edges) {
+  if (!r || !n_edges) return fail(HMX_EINVAL, "null pointer");
+  *n_edges = r->ne;
+  return HMX_OK;
+}
+
+hmx_status hmx_rwg_edges(const hmx_rwg* r, int32_t* edges, void* stream) {
+  if (!r || !edges) return fail(HMX_EINVAL, "null pointer");
+  API_TRY
+  HMX_HIP(hipMemcpyAsync(edges, r->edges.p, 2 * r->ne * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                         as_stream(stream)));
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_rwg_interp(const hmx_rwg* r, const void* x, void* u, void* stream) {
+  if (!r || !x || !u) return fail(HMX_EINVAL, "null pointer");
+  API_TRY
+  if (r->prec == HMX_FP64)
+    launch_rwg_interp<double2>(r->rec.p, r->tedge.p, r->nt, r->rule, (const double2*)x,
+                               (double2*)u, as_stream(stream));
+  else
+    launch_rwg_interp<float2>(r->rec.p, r->tedge.p, r->nt, r->rule, (const float2*)x, (float2*)u,
+                              as_stream(stream));
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_rwg_rhs(const hmx_rwg* r, double beta, const void* e_inc, const void* h_inc,
+                       void* b, void* stream) {
+  API_TRY
+  HMX_REQUIRE(r && b, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(std::isfinite(beta) && beta >= 0.0 && beta <= 1.0, HMX_EINVAL,
+              "beta must be in [0, 1]");
+  HMX_REQUIRE(beta == 0.0 || e_inc, HMX_EINVAL, "beta > 0 needs the incident electric field");
+  HMX_REQUIRE(beta == 1.0 || h_inc, HMX_EINVAL, "beta < 1 needs the incident magnetic field");
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    RwgTerms<T> a;
+    for (int d = 0; d < 3; ++d) {
+      if (beta != 0.0) a.u[d] = (const T*)e_inc + d * r->M;
+      if (beta != 1.0) a.cp[d] = (const T*)h_inc + d * r->M;
+    }
+    a.aI = beta;
+    a.aN = -(1.0 - beta);
+    launch_rwg_project<T>(r->einc.p, r->ne, r->rec.p, r->rule, r->w.p, a, (T*)b, as_stream(stream));
+  };
+  if (r->prec == HMX_FP64)
+    run(double2{});
+  else
+    run(float2{});
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_cfie_matvec(const hmx_rwg* r, double beta, const void* x, void* y, void* stream) {
+  API_TRY
+  HMX_REQUIRE(r && x && y, HMX_EINVAL, "null pointer");
+  check_beta(r, beta);
+  if (r->prec == HMX_FP64)
+    cfie_enqueue<double2>(r, beta, (const double2*)x, (double2*)y, as_stream(stream));
+  else
+    cfie_enqueue<float2>(r, beta, (const float2*)x, (float2*)y, as_stream(stream));
+  return HMX_OK;
+  API_CATCH
+}
+
+hmx_status hmx_cfie_gmres(const hmx_rwg* r, double beta, const void* b, void* x, int32_t restart,
+                          int32_t max_iter, double tol, void* stream, int32_t* iters,
+                          double* relres) {
+  API_TRY
+  HMX_REQUIRE(r && b && x && iters && relres, HMX_EINVAL, "null pointer");
+  check_beta(r, beta);
+  HMX_REQUIRE(restart >= 1 && restart <= 1000, HMX_EINVAL, "restart must be in [1, 1000]");
+  HMX_REQUIRE(max_iter >= 0, HMX_EINVAL, "max_iter must be >= 0");
+  HMX_REQUIRE(std::isfinite(tol) && tol >= 0, HMX_EINVAL, "tol must be finite and >= 0");
+  hipStream_t s = as_stream(stream);
+  if (r->prec == HMX_FP64)
+    gmres_run<double2>([&](const double2* v, double2* o) { cfie_enqueue<double2>(r, beta, v, o, s); },
+                       r->ne, (const double2*)b, (double2*)x, restart, max_iter, tol, s, iters, relres);
+  else
+    gmres_run<float2>([&](const float2* v, float2* o) { cfie_enqueue<float2>(r, beta, v, o, s); },
+                      r->ne, (const float2*)b, (float2*)x, restart, max_iter, tol, s, iters, relres);
+  return HMX_OK;
+  API_CATCH
+}
 
 }  // extern "C"

@@ -226,6 +226,28 @@ void launch_gemv_update(const T* V, int64_t ld, const double2* h, int nc, double
                         int64_t n, hipStream_t s);
 template <class T>
 void launch_vec(const T* x, const T* b, double a, int sub, T* y, int64_t n, hipStream_t s);
+// k_rwg.hip: RWG elements at the quadrature points (records of RWG_REC doubles per triangle)
+constexpr int RWG_REC = 16;
+// Terms of the projection onto the RWG functions: coefficients and point vectors (M entries,
+// original point order); ku, kv for the single layer, u for the identity, cp - cm for n x psi.
+template <class T>
+struct RwgTerms {
+  double2 aT{0.0, 0.0}, aD{0.0, 0.0};
+  double aI = 0.0, aN = 0.0;
+  const T* ku[3] = {nullptr, nullptr, nullptr};
+  const T* kv = nullptr;
+  const T* u[3] = {nullptr, nullptr, nullptr};
+  const T* cp[3] = {nullptr, nullptr, nullptr};
+  const T* cm[3] = {nullptr, nullptr, nullptr};
+};
+void launch_rwg_geom(const double* vtx, const int32_t* tri, const int32_t* tsign, int64_t nt,
+                     double* rec, hipStream_t s);
+template <class T>
+void launch_rwg_interp(const double* rec, const int32_t* tedge, int64_t nt, const P1Rule& r,
+                       const T* x, T* u, hipStream_t s);
+template <class T>
+void launch_rwg_project(const int32_t* einc, int64_t ne, const double* rec, const P1Rule& r,
+                        const double* w, const RwgTerms<T>& a, T* y, hipStream_t s);
 // k_reg.hip: per-triangle records of the singular correction (TGEO doubles each)
 void launch_tri_geom(const double* vtx, const int32_t* tri, int64_t nt, double alpha,
                      double* tgeo, hipStream_t s);

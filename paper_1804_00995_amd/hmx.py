@@ -89,6 +89,13 @@ _sig = {
     "hmx_p1_project": [_P, _P, _P, _P],
     "hmx_galerkin_matvec": [_P, _P, _P, _P],
     "hmx_gmres": [_P, _P, _P, _i32, _i32, _f64, _P, C.POINTER(_i32), C.POINTER(_f64)],
+    "hmx_rwg_create": [_P, _P, _P, _P, _P, _i64, _P, _i64, _P, _P, _i32, _P, C.POINTER(_P)],
+    "hmx_rwg_n_edges": [_P, C.POINTER(_i64)],
+    "hmx_rwg_edges": [_P, _P, _P],
+    "hmx_rwg_interp": [_P, _P, _P, _P],
+    "hmx_rwg_rhs": [_P, _f64, _P, _P, _P, _P],
+    "hmx_cfie_matvec": [_P, _f64, _P, _P, _P],
+    "hmx_cfie_gmres": [_P, _f64, _P, _P, _i32, _i32, _f64, _P, C.POINTER(_i32), C.POINTER(_f64)],
     "hmx_matvec": [_P, _P, _P, _P],
     "hmx_info": [_P, C.POINTER(Info)],
     "hmx_export_tree": [_P, _P, _P, _P, _P, _P, _P, _P],
@@ -122,9 +129,11 @@ _lib.hmx_graph_destroy.argtypes = [_P]
 _lib.hmx_graph_destroy.restype = None
 _lib.hmx_p1_destroy.argtypes = [_P]
 _lib.hmx_p1_destroy.restype = None
+_lib.hmx_rwg_destroy.argtypes = [_P]
+_lib.hmx_rwg_destroy.restype = None
 
 EXPORTED = sorted(list(_sig) + ["hmx_destroy", "hmx_last_error", "hmx_release_cache",
-                                "hmx_graph_destroy", "hmx_p1_destroy"])
+                                "hmx_graph_destroy", "hmx_p1_destroy", "hmx_rwg_destroy"])
 
 
 class Mesh(C.Structure):
@@ -401,6 +410,103 @@ class P1:
     def close(self):
         if self._h:
             _lib.hmx_p1_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RWG:
+    """The RWG space of a closed, outward-oriented mesh (one unknown per edge, edges in increasing
+    vertex pairs) for the electromagnetic equations: the CFIE product
+    A = -beta T + (1 - beta) (Id / 2 - NxK) (beta = 1 the EFIE, 0 the MFIE), its right-hand side
+    and its GMRES solve.  `single` is the Helmholtz single layer of the mesh (needed for
+    beta > 0), `grads` its three y-gradient operators (needed for beta < 1)."""
+
+    def __init__(self, single, grads, vtx, tri, bary, w, stream=None):
+        import torch
+        bary, w = _host_rule(bary, w)
+        grads = list(grads) if grads is not None else [None, None, None]
+        self._ops = [o for o in [single] + grads if o is not None]  # the space uses them
+        if not self._ops:
+            raise ValueError("no operator given")
+        self._op = self._ops[0]
+        self.M = self._op.M
+        self._h = C.c_void_p()
+        hs = [o._h if o is not None else None for o in [single] + grads]
+        _check(_lib.hmx_rwg_create(hs[0], hs[1], hs[2], hs[3], _dev(vtx, torch.float64, "vtx"),
+                                   vtx.shape[0], _dev(tri, torch.int32, "tri"), tri.shape[0],
+                                   bary.ctypes.data_as(_P), w.ctypes.data_as(_P), bary.shape[0],
+                                   _stream_ptr(stream), C.byref(self._h)))
+        n = C.c_int64(0)
+        _check(_lib.hmx_rwg_n_edges(self._h, C.byref(n)))
+        self.n_edges = n.value
+
+    def _vec(self, n, like):
+        import torch
+        if not self._h or any(not o._h for o in self._ops):
+            raise RuntimeError("the RWG space or one of its operators has been closed")
+        return torch.empty(n, dtype=self._op.cdtype, device=like.device)
+
+    @staticmethod
+    def _size(t, n, name):
+        if t.numel() != n:
+            raise ValueError(f"{name} must have {n} entries, got {t.numel()}")
+
+    def edges(self, device="cuda", stream=None):
+        import torch
+        if not self._h:
+            raise RuntimeError("the RWG space has been closed")
+        e = torch.empty((self.n_edges, 2), dtype=torch.int32, device=device)
+        _check(_lib.hmx_rwg_edges(self._h, _dev(e, torch.int32, "edges"), _stream_ptr(stream)))
+        return e
+
+    def interp(self, x, stream=None):
+        """(4, M): J_x, J_y, J_z and div J at the quadrature points."""
+        self._size(x, self.n_edges, "x")
+        u = self._vec(4 * self.M, x)
+        _check(_lib.hmx_rwg_interp(self._h, _dev(x, self._op.cdtype, "x"), _dev(u, self._op.cdtype, "u"),
+                                   _stream_ptr(stream)))
+        return u.view(4, self.M)
+
+    def rhs(self, beta, e_inc=None, h_inc=None, stream=None):
+        """beta <psi, E_inc> - (1 - beta) <n x psi, H_inc>; fields (3, M) at the points."""
+        ref = e_inc if e_inc is not None else h_inc
+        if ref is None:
+            raise ValueError("no incident field given")
+        for t, name in ((e_inc, "e_inc"), (h_inc, "h_inc")):
+            if t is not None:
+                self._size(t, 3 * self.M, name)
+        b = self._vec(self.n_edges, ref)
+        ep = _dev(e_inc, self._op.cdtype, "e_inc") if e_inc is not None else None
+        hp = _dev(h_inc, self._op.cdtype, "h_inc") if h_inc is not None else None
+        _check(_lib.hmx_rwg_rhs(self._h, float(beta), ep, hp, _dev(b, self._op.cdtype, "b"),
+                                _stream_ptr(stream)))
+        return b
+
+    def matvec(self, beta, x, stream=None):
+        self._size(x, self.n_edges, "x")
+        y = self._vec(self.n_edges, x)
+        _check(_lib.hmx_cfie_matvec(self._h, float(beta), _dev(x, self._op.cdtype, "x"),
+                                    _dev(y, self._op.cdtype, "y"), _stream_ptr(stream)))
+        return y
+
+    def gmres(self, beta, b, tol=1e-8, restart=100, max_iter=1000, stream=None):
+        """x, iterations, true relative residual."""
+        self._size(b, self.n_edges, "b")
+        x = self._vec(self.n_edges, b)
+        it, res = C.c_int32(0), C.c_double(0.0)
+        _check(_lib.hmx_cfie_gmres(self._h, float(beta), _dev(b, self._op.cdtype, "b"),
+                                   _dev(x, self._op.cdtype, "x"), restart, max_iter, float(tol),
+                                   _stream_ptr(stream), C.byref(it), C.byref(res)))
+        return x, it.value, res.value
+
+    def close(self):
+        if self._h:
+            _lib.hmx_rwg_destroy(self._h)
             self._h = None
 
     def __del__(self):

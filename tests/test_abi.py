@@ -146,6 +146,27 @@ def test_galerkin_argument_errors_without_gpu(hmx):
     lib.hmx_p1_destroy(None)  # NULL-safe
 
 
+def test_rwg_argument_errors_without_gpu(hmx):
+    lib = hmx._lib
+    h = C.c_void_p()
+    fake = C.c_void_p(4096)
+    bary = (C.c_double * 9)(2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3, 1 / 6, 1 / 6, 1 / 6, 2 / 3)
+    w = (C.c_double * 3)(1 / 3, 1 / 3, 1 / 3)
+    # no operator, or one or two of the three gradient operators
+    assert lib.hmx_rwg_create(None, None, None, None, fake, 4, fake, 4, bary, w, 3, None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_rwg_create(None, fake, None, None, fake, 4, fake, 4, bary, w, 3, None, C.byref(h)) == hmx.EINVAL
+    assert lib.hmx_rwg_create(fake, fake, fake, None, fake, 4, fake, 4, bary, w, 3, None, C.byref(h)) == hmx.EINVAL
+    n = C.c_int64(0)
+    assert lib.hmx_rwg_n_edges(None, C.byref(n)) == hmx.EINVAL
+    assert lib.hmx_rwg_edges(None, fake, None) == hmx.EINVAL
+    assert lib.hmx_rwg_interp(None, fake, fake, None) == hmx.EINVAL
+    assert lib.hmx_rwg_rhs(None, 0.5, fake, fake, fake, None) == hmx.EINVAL
+    assert lib.hmx_cfie_matvec(None, 0.5, fake, fake, None) == hmx.EINVAL
+    it, res = C.c_int32(0), C.c_double(0)
+    assert lib.hmx_cfie_gmres(None, 0.5, fake, fake, 10, 10, 1e-6, None, C.byref(it), C.byref(res)) == hmx.EINVAL
+    lib.hmx_rwg_destroy(None)  # NULL-safe
+
+
 def test_batch_argument_errors_without_gpu():
     import ctypes as C
     from paper_1804_00995_amd import hmx

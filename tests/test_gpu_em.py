@@ -1,0 +1,172 @@
+"""GPU parity of the electromagnetic equations (Section 6.2: EFIE, MFIE, CFIE on RWG elements)
+through the C ABI, against the CPU oracle and the Mie series of the PEC sphere.
+
+Bars: edge numbering identical to the oracle's; the RWG field, its divergence and the
+right-hand side to 1e-14 of the oracle's matrices; the CFIE product (beta = 1, 0, 0.5) within
+1e-12 of the oracle's matrix on dense operators (without the correction, which needs an
+H-matrix) and 1e-6 on H-matrices at tol 1e-8 with the correction; GMRES
+solutions within 1e-6 of a dense solve of the oracle's system (1e-3 in FP32 mixed precision);
+the far field of the PEC unit sphere at L4 within 4e-3 of the Mie series (the oracle's error
+at L3 is 1e-2, second order in h)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import rwg
+from paper_1804_00995_amd import inputs as I
+from test_oracle_em_pins import directions, mie_pec_far_field
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+RULE = I.rule_3pt()
+K = 2.0
+D, POL = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0])
+
+
+@pytest.fixture(scope="module")
+def H():
+    oracle.build(force=False)
+    from paper_1804_00995_amd import hmx
+    return hmx
+
+
+@pytest.fixture(scope="module")
+def oracle_l2():
+    v, f = I.icosphere(2)
+    return (v, f) + rwg.em_matrices(v, f, *RULE, K, reg_radius=2.0)
+
+
+@pytest.fixture(scope="module")
+def oracle_l2_plain():
+    """Without the correction, which needs an H-matrix operator: for the dense operators."""
+    v, f = I.icosphere(2)
+    return (v, f) + rwg.em_matrices(v, f, *RULE, K)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def dev(a, cdt=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(cdt).cuda()
+
+
+def space(H, v, f, tol=1e-8, precision=0, parts=("single", "grad"), reg=True, k=K):
+    vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    single = grads = None
+    if "single" in parts:
+        single = H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=k,
+                         prm=H.params(tol=tol, regularize=int(reg), precision=precision))
+    if "grad" in parts:
+        grads = [H.build(vd, fd, *RULE, kern=H.GRADY_X + d, k=k, prm=H.params(tol=tol, precision=precision))
+                 for d in range(3)]
+    return H.RWG(single, grads, vd, fd, *RULE), single, grads
+
+
+def test_edges_interp_and_rhs_match_oracle(H, oracle_l2_plain):
+    v, f, mats, Psi, Div, NxPsi, P, W = oracle_l2_plain
+    sp, _, _ = space(H, v, f, tol=0.0, reg=False)
+    edges, _, _ = rwg.rwg_edges(f)
+    assert sp.n_edges == edges.shape[0]
+    assert np.array_equal(sp.edges().cpu().numpy(), edges)
+    x = I.complex_vector(sp.n_edges, 1)
+    u = host(sp.interp(dev(x)))
+    for d in range(3):
+        assert rel(u[d], Psi[d] @ x) <= 1e-14
+    assert rel(u[3], Div @ x) <= 1e-14
+    Ei, Hi = rwg.plane_wave(P, K, D, POL)
+    for beta in (1.0, 0.0, 0.5):
+        b = host(sp.rhs(beta, dev(Ei), dev(Hi)))
+        assert rel(b, rwg.cfie_rhs(Psi, NxPsi, W, Ei, Hi, beta)) <= 1e-14
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.0, 0.5])
+def test_cfie_product_dense_operators(H, oracle_l2_plain, beta):
+    v, f, mats, Psi, Div, NxPsi, P, W = oracle_l2_plain
+    sp, single, _ = space(H, v, f, tol=0.0, reg=False)
+    assert single.info["is_dense"] == 1
+    x = I.complex_vector(sp.n_edges, 2)
+    assert rel(host(sp.matvec(beta, dev(x))), rwg.cfie_matrix(mats, beta) @ x) <= 1e-12
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.0, 0.5])
+def test_cfie_product_hmatrix(H, beta):
+    v, f = I.icosphere(3)
+    mats, *_ = rwg.em_matrices(v, f, *RULE, K, reg_radius=2.0)
+    sp, single, grads = space(H, v, f, tol=1e-8)
+    assert single.info["n_far"] > 0 and grads[0].info["n_far"] > 0
+    x = I.complex_vector(sp.n_edges, 3)
+    assert rel(host(sp.matvec(beta, dev(x))), rwg.cfie_matrix(mats, beta) @ x) <= 1e-6
+
+
+def test_gmres_matches_dense_solve(H, oracle_l2):
+    v, f, mats, Psi, Div, NxPsi, P, W = oracle_l2
+    sp, _, _ = space(H, v, f, tol=1e-10)
+    Ei, Hi = rwg.plane_wave(P, K, D, POL)
+    for beta in (0.5, 1.0):
+        b = sp.rhs(beta, dev(Ei), dev(Hi))
+        x, it, res = sp.gmres(beta, b, tol=1e-11, restart=100, max_iter=2000)
+        assert res <= 1e-10 and 0 < it < 2000
+        ref = np.linalg.solve(rwg.cfie_matrix(mats, beta), rwg.cfie_rhs(Psi, NxPsi, W, Ei, Hi, beta))
+        assert rel(host(x), ref) <= 1e-6
+
+
+def test_fp32_mixed_solve(H, oracle_l2):
+    v, f, mats, Psi, Div, NxPsi, P, W = oracle_l2
+    sp, _, _ = space(H, v, f, tol=1e-6, precision=H.FP32_MIXED)
+    Ei, Hi = rwg.plane_wave(P, K, D, POL)
+    b = sp.rhs(0.5, dev(Ei, torch.complex64), dev(Hi, torch.complex64))
+    x, it, res = sp.gmres(0.5, b, tol=1e-5, restart=100, max_iter=500)
+    assert res <= 2e-5
+    ref = np.linalg.solve(rwg.cfie_matrix(mats, 0.5), rwg.cfie_rhs(Psi, NxPsi, W, Ei, Hi, 0.5))
+    assert rel(host(x), ref) <= 1e-3
+
+
+def test_pec_sphere_far_field_l4(H):
+    """CFIE (beta = 0.5) with H-matrices, GMRES, then the far field of the current: GPU
+    products and solve; the far-field sum of the returned current on the host."""
+    v, f = I.icosphere(4)
+    sp, _, _ = space(H, v, f, tol=1e-6)
+    P, W = oracle.quad_points(v, f, *RULE)
+    Ei, Hi = rwg.plane_wave(P, K, D, POL)
+    b = sp.rhs(0.5, dev(Ei), dev(Hi))
+    x, it, res = sp.gmres(0.5, b, tol=1e-8, restart=100, max_iter=1000)
+    assert res <= 1e-7 and it < 200
+    J = host(sp.interp(x))[:3].T
+    th, ph, u = directions()
+    Jh = (np.exp(-1j * K * (u @ P.T)) * W[None, :]) @ J
+    F = 1j * K / (4 * np.pi) * (Jh - u * (u * Jh).sum(1, keepdims=True))
+    ex = mie_pec_far_field(K, th, ph)
+    assert np.abs(F - ex).max() / np.abs(ex).max() <= 4e-3
+
+
+def test_argument_errors(H):
+    v, f = I.icosphere(1)
+    vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    lap = H.build(vd, fd, *RULE, kern=H.LAPLACE, k=0.0)
+    with pytest.raises(H.HmxError):
+        H.RWG(lap, None, vd, fd, *RULE)  # not the Helmholtz single layer
+    fo = torch.from_numpy(f[1:].copy()).cuda()
+    with pytest.raises(H.HmxError):
+        H.RWG(H.build(vd, fo, *RULE, kern=H.HELMHOLTZ, k=K), None, vd, fo, *RULE)  # open mesh
+    single = H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=K)
+    sp = H.RWG(single, None, vd, fd, *RULE)
+    x = torch.zeros(sp.n_edges, dtype=torch.complex128, device="cuda")
+    sp.matvec(1.0, x)
+    with pytest.raises(ValueError):
+        sp.matvec(1.0, x[1:].contiguous())  # wrong length
+    with pytest.raises(ValueError):
+        sp.rhs(1.0, torch.zeros(sp.M, dtype=torch.complex128, device="cuda"))  # one component
+    for beta in (0.5, -0.1, 1.5):
+        with pytest.raises(H.HmxError):
+            sp.matvec(beta, x)  # no gradient operators for beta < 1; beta outside [0, 1]
+    single.close()
+    with pytest.raises(RuntimeError):
+        sp.matvec(1.0, x)
+    sp.close()
