@@ -583,6 +583,159 @@ def run_scattering(args, torch, oracle, hmx, I):
          unit="ms per step (corrected H-build from device mesh + GMRES solve of the Galerkin system)")
 
 
+def mie_pec_far_field(k, th, ph):
+    """Far field F (E_s ~ F e^{ikR} / R) of the PEC unit sphere under E_inc = x e^{ikz}: the Mie
+    series with a_n = psi_n' / xi_n', b_n = psi_n / xi_n."""
+    from scipy import special
+    nmax = int(k + 4 * k ** (1 / 3) + 10)
+    mu = np.cos(th)
+    S1 = np.zeros_like(mu, complex)
+    S2 = np.zeros_like(mu, complex)
+    pi_prev, pi_cur = np.zeros_like(mu), np.ones_like(mu)
+    for n in range(1, nmax + 1):
+        jn, djn = special.spherical_jn(n, k), special.spherical_jn(n, k, derivative=True)
+        hn = jn + 1j * special.spherical_yn(n, k)
+        dhn = djn + 1j * special.spherical_yn(n, k, derivative=True)
+        a, b = (jn + k * djn) / (hn + k * dhn), jn / hn
+        tau = n * mu * pi_cur - (n + 1) * pi_prev
+        c = (2 * n + 1) / (n * (n + 1))
+        S1 += c * (a * pi_cur + b * tau)
+        S2 += c * (a * tau + b * pi_cur)
+        pi_prev, pi_cur = pi_cur, ((2 * n + 1) * mu * pi_cur - (n + 1) * pi_prev) / n
+    e_th = np.stack([np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), -np.sin(th)], 1)
+    e_ph = np.stack([-np.sin(ph), np.cos(ph), np.zeros_like(ph)], 1)
+    return ((np.cos(ph) * S2)[:, None] * e_th - (np.sin(ph) * S1)[:, None] * e_ph) / (-1j * k)
+
+
+class _EmOps:
+    """The operators and RWG space of one electromagnetic step, closed together."""
+
+    def __init__(self, single, grads, space):
+        self.single, self.grads, self.space = single, grads, space
+        self.info = single.info
+
+    def close(self):
+        self.space.close()
+        for o in [self.single] + self.grads:
+            o.close()
+
+
+def run_em(args, torch, oracle, hmx, I):
+    """The paper's electromagnetic example (Section 6.2) on the PEC unit sphere: CFIE with
+    beta = 0.5 on RWG elements (corrected single layer and the three gradient kernels as
+    H-matrices), GMRES to 1e-6, far field checked against the Mie series."""
+    level, k, beta = args.level, args.k, 0.5
+    v, f = I.icosphere(level)
+    bary, w = I.rule_3pt()
+    d, pol = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0])
+    stream = torch.cuda.current_stream()
+    vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    xyzw = hmx.quad_points(vd, fd, bary, w, stream=stream)
+    P = xyzw[:3].T.contiguous()
+    ph = torch.exp(1j * k * (P.to(torch.complex128) @ torch.from_numpy(d).to(torch.complex128).cuda()))
+    e_inc = (torch.from_numpy(pol).to(torch.complex128).cuda()[:, None] * ph[None, :]).contiguous()
+    h_inc = (torch.from_numpy(np.cross(d, pol)).to(torch.complex128).cuda()[:, None] * ph[None, :]).contiguous()
+    torch.cuda.synchronize()
+    log(f"bench em: {f.shape[0]} triangles, {xyzw.shape[1]} points, {3 * f.shape[0] // 2} edges, k={k}")
+    last = {}
+
+    def build_ops():
+        single = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, stream=stream,
+                           prm=hmx.params(tol=1e-3, regularize=1))
+        grads = [hmx.build(vd, fd, bary, w, kern=hmx.GRADY_X + i, k=k, stream=stream,
+                           prm=hmx.params(tol=1e-3)) for i in range(3)]
+        return single, grads
+
+    def step():
+        single, grads = build_ops()
+        sp = hmx.RWG(single, grads, vd, fd, bary, w, stream=stream)
+        b = sp.rhs(beta, e_inc, h_inc, stream=stream)
+        x, it, res = sp.gmres(beta, b, tol=1e-6, restart=200, max_iter=3000, stream=stream)
+        last.update(it=it, res=res, x=x)
+        return _EmOps(single, grads, sp), x
+
+    ms_step, aca = timed_steps(step, args.steps, args.warmup)
+    ops, x = step()
+    torch.cuda.synchronize()
+    it, res, sp = last["it"], last["res"], ops.space
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.matvec_reps):
+        sp.matvec(beta, x, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    cfie_ms = e0.elapsed_time(e1) / args.matvec_reps
+    # far field of the current against the Mie series (outside the timed region)
+    J = sp.interp(x)[:3].T.cpu().numpy().astype(np.complex128)
+    Pn, Wn = P.cpu().numpy(), xyzw[3].cpu().numpy()
+    rng = np.random.default_rng(0)
+    th, phi = np.arccos(rng.uniform(-1, 1, 100)), rng.uniform(0, 2 * np.pi, 100)
+    u = np.stack([np.sin(th) * np.cos(phi), np.sin(th) * np.sin(phi), np.cos(th)], 1)
+    Jh = (np.exp(-1j * k * (u @ Pn.T)) * Wn[None, :]) @ J
+    F = 1j * k / (4 * np.pi) * (Jh - u * (u * Jh).sum(1, keepdims=True))
+    ex = mie_pec_far_field(k, th, phi)
+    far_err = float(np.abs(F - ex).max() / np.abs(ex).max())
+    log(f"GMRES {it} iterations, relres {res:.2e}; CFIE product {cfie_ms:.3f} ms; "
+        f"far field vs Mie series {far_err:.3e}")
+    M = xyzw.shape[1]
+
+    def product_bytes(op, nr):
+        """Entries read once for nr vectors; per vector x read, xp written and read, y written
+        and the permutation twice."""
+        i = op.info
+        return 16 * (i["near_entries"] + i["far_entries"] + i["dense_far_entries"]) + nr * (16 * 4 * M + 8 * M)
+
+    # the single layer on 4 vectors and each gradient operator on 2, in one product each
+    cfie_bytes = product_bytes(ops.single, 4) + sum(product_bytes(g, 2) for g in ops.grads)
+    cpu = None
+    if args.cpu_baseline == "on":
+        # bounded sample: the oracle's four H-builds and one product of each, the solve scaled
+        # by the GPU's iteration count (4 single-layer and 6 gradient products per CFIE product)
+        Po, Wq = oracle.quad_points(v, f, bary, w)
+        xo = I.complex_vector(M, 0)
+        c0 = time.perf_counter()
+        Hs = oracle.HMatrix(Po, Wq, oracle.HELMHOLTZ, k, leaf=64, eta=1.5, tol=1e-3, mesh=(v, f, bary))
+        c1 = time.perf_counter()
+        Hs.matvec(xo)
+        c2 = time.perf_counter()
+        Hs.close()
+        Hg = oracle.HMatrix(Po, Wq, oracle.GRADY_X, k, leaf=64, eta=1.5, tol=1e-3)
+        c3 = time.perf_counter()
+        Hg.matvec(xo)
+        c4 = time.perf_counter()
+        Hg.close()
+        per_it = 4 * (c2 - c1) + 6 * (c4 - c3)
+        cpu = {"value": round(((c1 - c0) + 3 * (c3 - c2) + it * per_it) * 1e3, 1),
+               "unit": "ms per step (four H-builds + GMRES products), estimated",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"oracle corrected single-layer H-build {c1 - c0:.2f} s and product "
+                         f"{c2 - c1:.2f} s, one gradient-kernel H-build {c3 - c2:.2f} s (x3) and "
+                         f"product {c4 - c3:.2f} s, the solve scaled by {it} iterations"}
+    info = ops.info
+    extra = {
+        "h_build_s_single_layer": round(info["t_total_ms"] / 1e3, 4),
+        "h_build_s_gradients": [round(g.info["t_total_ms"] / 1e3, 4) for g in ops.grads],
+        "gmres_iterations": it,
+        "gmres_relres": res,
+        "cfie_matvec_ms": round(cfie_ms, 4),
+        "far_field_rel_err": far_err,
+        "sizes": sizes(info),
+    }
+    extra.update(rooflines(info, aca, cfie_ms, M, 16, "fp64"))
+    extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
+    extra["roofline_matvec"] = {"bound": "hbm", "achieved": round(cfie_bytes / (cfie_ms * 1e-3) / 1e9, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(cfie_bytes / (cfie_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "bytes_per_product": cfie_bytes}
+    extra["cpu_baseline"] = cpu
+    ops.close()
+    config = {"workload": f"PEC unit sphere, icosphere L{level} ({f.shape[0]} triangles, {M} points, "
+                          f"{3 * f.shape[0] // 2} RWG unknowns), k={k:g}, CFIE beta 0.5 (corrected "
+                          f"single layer + 3 gradient kernels), ACA tol 1e-3, GMRES(200) to 1e-6, fp64"}
+    line(args, ms_step, "fp64", config, extra,
+         unit="ms per step (4 H-builds from device mesh + GMRES solve of the CFIE system)")
+
+
 def run_large(args, torch, oracle, hmx, I):
     from paper_1804_00995_amd import rank_model as R
     v, f = I.icosphere(8)
@@ -691,10 +844,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["sphere", "batch", "large", "radiation", "scattering",
-                                           "dense"], default="sphere")
+                                           "em", "dense"], default="sphere")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--level", type=int, default=6)
-    ap.add_argument("--k", type=float, default=40.0)
+    ap.add_argument("--level", type=int, default=None,
+                    help="icosphere level (default 6; 5 for the em workload)")
+    ap.add_argument("--k", type=float, default=None,
+                    help="wavenumber (default 40; 20 for the em workload)")
     ap.add_argument("--matvec-reps", type=int, default=30)
     ap.add_argument("--sample-rows", type=int, default=384)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
@@ -703,6 +858,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel used to scale the HBM byte counters")
     args = ap.parse_args()
+    em = args.workload == "em"  # four operators: one level coarser at the same resolution per wavelength
+    args.level = args.level if args.level is not None else (5 if em else 6)
+    args.k = args.k if args.k is not None else (20.0 if em else 40.0)
     if args.gpus != 1:
         log("bench.py measures a single GPU; --gpus above 1 is not supported")
         sys.exit(2)
@@ -719,7 +877,8 @@ def main():
         import oracle
 
     {"sphere": run_sphere, "batch": run_batch, "large": run_large, "radiation": run_radiation,
-     "scattering": run_scattering, "dense": run_dense}[args.workload](args, torch, oracle, hmx, I)
+     "scattering": run_scattering, "em": run_em, "dense": run_dense}[args.workload](
+        args, torch, oracle, hmx, I)
 
 
 if __name__ == "__main__":

@@ -975,6 +975,8 @@ struct hmx_rwg {
   hmx::DevBuf<int32_t> tedge, einc, edges;
   hmx::DevBuf<double> rec, w;
   hmx::DevBuf<unsigned char> scratch;
+  // several-vector products: nr permuted inputs and nr intermediate vectors V^T x of one operator
+  hmx::DevBuf<unsigned char> xpm, tm;
   template <class T>
   T* vec(int i) const {
     return (T*)scratch.p + (int64_t)i * M;
@@ -986,23 +988,41 @@ namespace {
 // y = A x, A = -beta T + (1 - beta) (Id / 2 - NxK):
 //   T = i k sum_d Psi_d^T W K Psi_d - (i / k) D^T W K D      (K the single layer)
 //   NxK x = <n x psi_i, c>,  c_e = G_{e+1} u_{e+2} - G_{e+2} u_{e+1}  (G_d the gradient kernels)
+// y_r = K x_r for nr vectors: one several-vector product on an H-matrix operator (its entries
+// read once), one product per vector on a dense one
+template <class T>
+void matvec_n(const hmx_rwg* R, const hmx_op* op, int nr, const T* const* x, T* const* y,
+              hipStream_t s) {
+  if (op->dense) {
+    for (int r = 0; r < nr; ++r) enqueue_matvec(op, x[r], y[r], s);
+    return;
+  }
+  launch_matvec_multi<T>(op, nr, x, y, (T*)R->xpm.p, (T*)R->tm.p, s);
+}
+
 template <class T>
 void cfie_enqueue(const hmx_rwg* R, double beta, const T* x, T* y, hipStream_t s) {
   T* u = R->vec<T>(0);  // u_0..u_2 = Psi x, u_3 = D x  (slots 0..3)
   launch_rwg_interp<T>(R->rec.p, R->tedge.p, R->nt, R->rule, x, u, s);
   RwgTerms<T> a;
   if (beta != 0.0) {
-    for (int d = 0; d < 4; ++d) enqueue_matvec(R->single, R->vec<T>(d), R->vec<T>(4 + d), s);
+    const T* in[4] = {R->vec<T>(0), R->vec<T>(1), R->vec<T>(2), R->vec<T>(3)};
+    T* out[4] = {R->vec<T>(4), R->vec<T>(5), R->vec<T>(6), R->vec<T>(7)};
+    matvec_n<T>(R, R->single, 4, in, out, s);
     for (int d = 0; d < 3; ++d) a.ku[d] = R->vec<T>(4 + d);
     a.kv = R->vec<T>(7);
     a.aT = make_double2(0.0, -beta * R->k);
     a.aD = make_double2(0.0, beta / R->k);
   }
   if (beta != 1.0) {
+    // c_e = G_{e+1} u_{e+2} - G_{e+2} u_{e+1} (slots 8 + e and 11 + e): operator G_d takes
+    // u_{d+1} into slot 8 + (d - 1) and u_{d+2} into slot 11 + (d + 1)
+    for (int d = 0; d < 3; ++d) {
+      const T* in[2] = {R->vec<T>((d + 1) % 3), R->vec<T>((d + 2) % 3)};
+      T* out[2] = {R->vec<T>(8 + (d + 2) % 3), R->vec<T>(11 + (d + 1) % 3)};
+      matvec_n<T>(R, R->grad[d], 2, in, out, s);
+    }
     for (int e = 0; e < 3; ++e) {
-      const int e1 = (e + 1) % 3, e2 = (e + 2) % 3;
-      enqueue_matvec(R->grad[e1], R->vec<T>(e2), R->vec<T>(8 + e), s);
-      enqueue_matvec(R->grad[e2], R->vec<T>(e1), R->vec<T>(11 + e), s);
       a.u[e] = R->vec<T>(e);
       a.cp[e] = R->vec<T>(8 + e);
       a.cm[e] = R->vec<T>(11 + e);
@@ -1130,6 +1150,11 @@ hmx_status hmx_rwg_create(const hmx_op* single, const hmx_op* grad_x, const hmx_
   R->rec.alloc((size_t)RWG_REC * n_tri);
   launch_rwg_geom(vtx, tri, dsign.p, n_tri, R->rec.p, s);
   R->scratch.alloc((size_t)14 * R->M * any->elem);
+  int64_t tmax = 1;
+  for (int i = 0; i < 4; ++i)
+    if (ops[i]) tmax = std::max<int64_t>(tmax, ops[i]->t_len);
+  R->xpm.alloc((size_t)4 * R->M * any->elem);
+  R->tm.alloc((size_t)4 * tmax * any->elem);
   HMX_HIP(hipStreamSynchronize(s));
   *out = R.release();
   return HMX_OK;

@@ -226,6 +226,11 @@ void launch_gemv_update(const T* V, int64_t ld, const double2* h, int nc, double
                         int64_t n, hipStream_t s);
 template <class T>
 void launch_vec(const T* x, const T* b, double a, int sub, T* y, int64_t n, hipStream_t s);
+// k_matvec.hip: y_r = K x_r for nr = 2 or 4 vectors, the operator's entries read once; scratch
+// xpm of nr M and tm of nr max(t_len, 1) entries (H-matrix operators only)
+template <class T>
+void launch_matvec_multi(const hmx_op* op, int nr, const T* const* x, T* const* y, T* xpm, T* tm,
+                         hipStream_t s);
 // k_rwg.hip: RWG elements at the quadrature points (records of RWG_REC doubles per triangle)
 constexpr int RWG_REC = 16;
 // Terms of the projection onto the RWG functions: coefficients and point vectors (M entries,

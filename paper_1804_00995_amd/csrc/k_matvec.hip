@@ -244,6 +244,201 @@ void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegi
   HMX_LAUNCHED();
 }
 
+// ---------------------------------------------------------- several vectors at once (NR = 2, 4)
+// The same product for NR vectors: vector r of xp and t at offset r ldx and r ldt, output r to
+// y.p[r].  Every entry of V, U and the near blocks is loaded once and applied to the NR vectors,
+// so the operator's bytes are read once for all of them; the summation order per vector is that
+// of the one-vector kernels' general paths (one column, or one near-block column, at a time).
+template <class T>
+struct MultiOut {
+  T* p[4];
+};
+
+template <class T, int NR>
+__global__ void __launch_bounds__(WG) far_vt_multi_kernel(const FarRec* __restrict__ rec,
+                                                          const T* __restrict__ xp, int64_t ldx,
+                                                          T* __restrict__ t, int64_t ldt) {
+  const FarRec f = rec[blockIdx.x];
+  T* tb = t + f.toff;
+  const T* xs = xp + f.sb;
+  if (f.dense) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      for (int j = threadIdx.x; j < f.n; j += WG) tb[r * ldt + j] = xs[r * ldx + j];
+    return;
+  }
+  const int n = f.n, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int64_t ldv = f.ldv;
+  auto colv = [&](int l) -> const T* {
+    return l < f.split ? (const T*)f.V + l * ldv : (const T*)f.V1 + (l - f.split) * ldv;
+  };
+  int l = w;
+  for (; l + NWAVE < f.r; l += 2 * NWAVE) {
+    T a0[NR], a1[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a0[r] = a1[r] = czero<T>();
+    const T* v0 = colv(l);
+    const T* v1 = colv(l + NWAVE);
+#pragma unroll 2
+    for (int j = lane; j < n; j += WAVE) {
+      const T p0 = v0[j], p1 = v1[j];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const T xj = xs[r * ldx + j];
+        cfma(a0[r], p0, xj);
+        cfma(a1[r], p1, xj);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      a0[r] = wave_sum2(a0[r]);
+      a1[r] = wave_sum2(a1[r]);
+      if (lane == 0) {
+        tb[r * ldt + l] = a0[r];
+        tb[r * ldt + l + NWAVE] = a1[r];
+      }
+    }
+  }
+  for (; l < f.r; l += NWAVE) {
+    T a0[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a0[r] = czero<T>();
+    const T* v0 = colv(l);
+#pragma unroll 2
+    for (int j = lane; j < n; j += WAVE) {
+      const T p0 = v0[j];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cfma(a0[r], p0, xs[r * ldx + j]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      a0[r] = wave_sum2(a0[r]);
+      if (lane == 0) tb[r * ldt + l] = a0[r];
+    }
+  }
+}
+
+template <class T, int NR>
+__global__ void __launch_bounds__(WG) leaf_apply_multi_kernel(
+    const int32_t* __restrict__ leaves, const int32_t* __restrict__ nbegin,
+    const int32_t* __restrict__ nend, const int64_t* __restrict__ near_ptr,
+    const int32_t* __restrict__ near_sb, const int32_t* __restrict__ near_n,
+    const int64_t* __restrict__ near_off, const T* __restrict__ near_pool,
+    const int64_t* __restrict__ far_ptr, const int32_t* __restrict__ far_list,
+    const FarRec* __restrict__ far, const T* __restrict__ tbuf, int64_t ldt,
+    const T* __restrict__ xp, int64_t ldx, const int32_t* __restrict__ perm, int64_t y_rows,
+    MultiOut<T> y) {
+  __shared__ T part[NWAVE][MAX_LEAF_CHUNKS * WAVE];
+  const int leaf = blockIdx.x;
+  const int node = leaves[leaf];
+  const int tb = nbegin[node], m = nend[node] - tb;
+  const int64_t n0 = near_ptr[leaf], nn = near_ptr[leaf + 1] - n0;
+  const int64_t f0 = far_ptr[leaf], nfar = far_ptr[leaf + 1] - f0;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int nch = (m + WAVE - 1) / WAVE;
+  T acc[MAX_LEAF_CHUNKS][NR];
+#pragma unroll
+  for (int c = 0; c < MAX_LEAF_CHUNKS; ++c)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[c][r] = czero<T>();
+  for (int64_t it = w; it < nn + nfar; it += NWAVE) {
+    if (it < nn) {
+      const int64_t blk = n0 + it;
+      const int sb = near_sb[blk], n = near_n[blk];
+      const T* K = near_pool + near_off[blk];
+      const T* xs = xp + sb;
+#pragma unroll 2
+      for (int j = 0; j < n; ++j) {
+        T xj[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) xj[r] = xs[r * ldx + j];
+        const T* col = K + (int64_t)j * m;
+#pragma unroll
+        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
+          const int i = lane + c * WAVE;
+          if (c < nch && i < m) {
+            const T kij = col[i];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) cfma(acc[c][r], kij, xj[r]);
+          }
+        }
+      }
+    } else {
+      const FarRec f = far[far_list[f0 + (it - nn)]];
+      const int o = tb - f.tb;
+      const T* U = (const T*)f.U + o;
+      const T* tt = tbuf + f.toff;
+#pragma unroll 2
+      for (int l = 0; l < f.r; ++l) {
+        T tl[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) tl[r] = tt[r * ldt + l];
+        const T* col = l < f.split ? U + (int64_t)l * f.ldu
+                                   : (const T*)f.U1 + o + (int64_t)(l - f.split) * f.ldu;
+#pragma unroll
+        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
+          const int i = lane + c * WAVE;
+          if (c < nch && i < m) {
+            const T uil = col[i];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) cfma(acc[c][r], uil, tl[r]);
+          }
+        }
+      }
+    }
+  }
+  // one vector at a time through the same LDS buffer
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+#pragma unroll
+    for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) part[w][lane + c * WAVE] = acc[c][r];
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += WG) {
+      T s = part[0][i];
+#pragma unroll
+      for (int q = 1; q < NWAVE; ++q) {
+        s.x += part[q][i].x;
+        s.y += part[q][i].y;
+      }
+      const int64_t o = perm[tb + i];
+      if (o < y_rows) y.p[r][o] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// y_r = K x_r for r < nr (nr = 2 or 4): x_r, y_r device vectors of the product's shape; xpm holds
+// nr M and tm nr t_len entries of scratch.
+template <class T>
+void launch_matvec_multi(const hmx_op* op, int nr, const T* const* x, T* const* y, T* xpm, T* tm,
+                         hipStream_t s) {
+  const int64_t M = op->M, ldt = std::max<int64_t>(op->t_len, 1);
+  MultiOut<T> out{};
+  for (int r = 0; r < nr; ++r) {
+    launch_gather<T>(x[r], op->perm.p, xpm + r * M, M, op->x_off, s);
+    out.p[r] = y[r];
+  }
+  auto go = [&](auto nrc) {
+    constexpr int NR = decltype(nrc)::value;
+    if (op->n_far > 0) {
+      hipLaunchKernelGGL((far_vt_multi_kernel<T, NR>), dim3((unsigned)op->n_far), dim3(WG), 0, s,
+                         op->far.p, xpm, M, tm, ldt);
+      HMX_LAUNCHED();
+    }
+    hipLaunchKernelGGL((leaf_apply_multi_kernel<T, NR>), dim3(op->n_leaves), dim3(WG), 0, s,
+                       op->leaves.p, op->nbegin.p, op->nend.p, op->near_ptr.p, op->near_sb.p,
+                       op->near_n.p, op->near_off.p, (const T*)op->near_pool.p, op->far_ptr.p,
+                       op->far_list.p, op->far.p, tm, ldt, xpm, M, op->perm.p, op->rows, out);
+    HMX_LAUNCHED();
+  };
+  if (nr == 2)
+    go(std::integral_constant<int, 2>{});
+  else if (nr == 4)
+    go(std::integral_constant<int, 4>{});
+  else
+    throw Error(HMX_EINTERNAL, "launch_matvec_multi: nr must be 2 or 4");
+}
+
 // ------------------------------------------------------------------------- dense on the fly
 constexpr int DOTF_CHUNK = 256;  // sources per workgroup (64 per wavefront)
 
@@ -326,7 +521,9 @@ void launch_dense_otf(const double* X, const double* Y, const double* Z, const d
                                      T*, hipStream_t);                                           \
   template void launch_dense_otf<T>(const double*, const double*, const double*, const double*,  \
                                     int64_t, int64_t, int64_t, int, double, const T*, T*, T*,    \
-                                    hipStream_t);
+                                    hipStream_t);                                                \
+  template void launch_matvec_multi<T>(const hmx_op*, int, const T* const*, T* const*, T*, T*,   \
+                                       hipStream_t);
 HMX_INST(double2)
 HMX_INST(float2)
 #undef HMX_INST
