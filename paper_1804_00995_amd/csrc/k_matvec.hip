@@ -144,7 +144,10 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
   const int tb = nbegin[node], m = nend[node] - tb;
   const int64_t n0 = near_ptr[leaf], nn = near_ptr[leaf + 1] - n0;
   const int64_t f0 = far_ptr[leaf], nfar = far_ptr[leaf + 1] - f0;
-  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  // the wave index is uniform across the wave: marked so, the block descriptors and the
+  // x and t entries, whose addresses depend only on it, are read through scalar loads
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int nch = (m + WAVE - 1) / WAVE;
   T acc[MAX_LEAF_CHUNKS];
 #pragma unroll
@@ -273,6 +276,32 @@ __global__ void __launch_bounds__(WG) far_vt_multi_kernel(const FarRec* __restri
     return l < f.split ? (const T*)f.V + l * ldv : (const T*)f.V1 + (l - f.split) * ldv;
   };
   int l = w;
+  for (; l + 3 * NWAVE < f.r; l += 4 * NWAVE) {
+    T a[4][NR];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) a[c][r] = czero<T>();
+    const T* v[4] = {colv(l), colv(l + NWAVE), colv(l + 2 * NWAVE), colv(l + 3 * NWAVE)};
+    for (int j = lane; j < n; j += WAVE) {
+      T p[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) p[c] = v[c][j];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const T xj = xs[r * ldx + j];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cfma(a[c][r], p[c], xj);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        a[c][r] = wave_sum2(a[c][r]);
+        if (lane == 0) tb[r * ldt + l + c * NWAVE] = a[c][r];
+      }
+  }
   for (; l + NWAVE < f.r; l += 2 * NWAVE) {
     T a0[NR], a1[NR];
 #pragma unroll
@@ -334,13 +363,52 @@ __global__ void __launch_bounds__(WG) leaf_apply_multi_kernel(
   const int tb = nbegin[node], m = nend[node] - tb;
   const int64_t n0 = near_ptr[leaf], nn = near_ptr[leaf + 1] - n0;
   const int64_t f0 = far_ptr[leaf], nfar = far_ptr[leaf + 1] - f0;
-  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  // the wave index is uniform across the wave: marked so, the block descriptors and the
+  // x and t entries, whose addresses depend only on it, are read through scalar loads
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int nch = (m + WAVE - 1) / WAVE;
   T acc[MAX_LEAF_CHUNKS][NR];
 #pragma unroll
   for (int c = 0; c < MAX_LEAF_CHUNKS; ++c)
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[c][r] = czero<T>();
+  if (nch == 1) {
+    // leaves of at most 64 rows: one row per lane, more loads in flight (lanes past the leaf's
+    // rows read row 0 and discard it); the same summation order as the general path
+    const bool on = lane < m;
+    const int i = on ? lane : 0;
+    for (int64_t it = w; it < nn + nfar; it += NWAVE) {
+      if (it < nn) {
+        const int64_t blk = n0 + it;
+        const int sb = near_sb[blk], n = near_n[blk];
+        const T* K = near_pool + near_off[blk] + i;
+        const T* xs = xp + sb;
+#pragma unroll 4
+        for (int j = 0; j < n; ++j) {
+          const T kij = K[(int64_t)j * m];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(acc[0][r], kij, xs[r * ldx + j]);
+        }
+      } else {
+        const FarRec f = far[far_list[f0 + (it - nn)]];
+        const int o = tb - f.tb;
+        const T* U = (const T*)f.U + o + i;
+        const T* U1 = (const T*)f.U1 + o + i;
+        const T* tt = tbuf + f.toff;
+#pragma unroll 4
+        for (int l = 0; l < f.r; ++l) {
+          const T uil = l < f.split ? U[(int64_t)l * f.ldu] : U1[(int64_t)(l - f.split) * f.ldu];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(acc[0][r], uil, tt[r * ldt + l]);
+        }
+      }
+    }
+    if (!on) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[0][r] = czero<T>();
+    }
+  } else
   for (int64_t it = w; it < nn + nfar; it += NWAVE) {
     if (it < nn) {
       const int64_t blk = n0 + it;

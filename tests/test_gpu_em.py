@@ -95,11 +95,23 @@ def test_cfie_product_dense_operators(H, oracle_l2_plain, beta):
     assert rel(host(sp.matvec(beta, dev(x))), rwg.cfie_matrix(mats, beta) @ x) <= 1e-12
 
 
-@pytest.mark.parametrize("beta", [1.0, 0.0, 0.5])
-def test_cfie_product_hmatrix(H, beta):
+@pytest.fixture(scope="module")
+def oracle_l3():
     v, f = I.icosphere(3)
-    mats, *_ = rwg.em_matrices(v, f, *RULE, K, reg_radius=2.0)
-    sp, single, grads = space(H, v, f, tol=1e-8)
+    return v, f, rwg.em_matrices(v, f, *RULE, K, reg_radius=2.0)[0]
+
+
+@pytest.mark.parametrize("beta,leaf", [(1.0, 64), (0.0, 64), (0.5, 64), (0.5, 200)])
+def test_cfie_product_hmatrix(H, oracle_l3, beta, leaf):
+    """Several-vector H-matrix products (four vectors on the single layer, two on each gradient
+    operator); leaves of up to 64 rows take the one-row-per-lane path, larger ones the general
+    path."""
+    v, f, mats = oracle_l3
+    vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    prm = dict(tol=1e-8, leaf_size=leaf)
+    single = H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=K, prm=H.params(regularize=1, **prm))
+    grads = [H.build(vd, fd, *RULE, kern=H.GRADY_X + d, k=K, prm=H.params(**prm)) for d in range(3)]
+    sp = H.RWG(single, grads, vd, fd, *RULE)
     assert single.info["n_far"] > 0 and grads[0].info["n_far"] > 0
     x = I.complex_vector(sp.n_edges, 3)
     assert rel(host(sp.matvec(beta, dev(x))), rwg.cfie_matrix(mats, beta) @ x) <= 1e-6
