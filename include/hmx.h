@@ -310,6 +310,20 @@ hmx_status hmx_mesh_offsets(const hmx_op* op, int64_t* off, int32_t cap, int32_t
  * Errors: HMX_EINVAL for null pointers. */
 hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream);
 
+/* y_r = K x_r for r < nr (Section 5.3, as hmx_matvec, for several vectors at once): an H-matrix
+ * operator is applied to groups of four, then two, then one vector, each group in one product
+ * that reads the operator's entries once; a dense operator takes one product per vector.  The
+ * result of each vector is bit-identical to hmx_matvec's (same summation order).
+ *   x, y: host arrays of nr device pointers, each vector as in hmx_matvec (no aliasing).
+ *   work: device scratch of hmx_matvec_multi_work_bytes(op) bytes (0 for a dense operator, where
+ *   work may be NULL), owned by the caller; products using the same work buffer or operator
+ *   must not overlap in time.
+ * Asynchronous on `stream`; allocates nothing.  Errors: HMX_EINVAL for null pointers, nr < 1 or
+ * a missing work buffer. */
+hmx_status hmx_matvec_multi_work_bytes(const hmx_op* op, size_t* bytes);
+hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, void* const* y,
+                            void* work, void* stream);
+
 /* Product replay: hmx_matvec(op, x, y) captured once into a HIP graph (fixed operator and
  * vector addresses) and replayed with one launch per call.  The graph holds kernels only.
  * hmx_graph_create captures on a private stream and instantiates (synchronous); hmx_graph_launch

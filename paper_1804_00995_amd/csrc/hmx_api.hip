@@ -373,6 +373,47 @@ hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream) {
   API_CATCH
 }
 
+hmx_status hmx_matvec_multi_work_bytes(const hmx_op* op, size_t* bytes) {
+  if (!op || !bytes) return fail(HMX_EINVAL, "null pointer");
+  *bytes = op->dense ? 0 : (size_t)4 * (op->M + std::max<int64_t>(op->t_len, 1)) * op->elem;
+  return HMX_OK;
+}
+
+hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, void* const* y,
+                            void* work, void* stream) {
+  API_TRY
+  HMX_REQUIRE(op && x && y, HMX_EINVAL, "null pointer");
+  HMX_REQUIRE(nr >= 1, HMX_EINVAL, "nr must be >= 1");
+  for (int r = 0; r < nr; ++r) HMX_REQUIRE(x[r] && y[r], HMX_EINVAL, "null vector pointer");
+  HMX_REQUIRE(op->dense || work, HMX_EINVAL, "an H-matrix operator needs the work buffer");
+  hipStream_t s = as_stream(stream);
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    T* xpm = (T*)work;
+    T* tm = xpm + 4 * op->M;
+    for (int r0 = 0; r0 < nr;) {
+      const int left = nr - r0;
+      const int g = op->dense ? 1 : (left >= 4 ? 4 : left >= 2 ? 2 : 1);
+      if (g == 1) {
+        enqueue_matvec(op, x[r0], y[r0], s);
+      } else {
+        const T* xs[4];
+        T* ys[4];
+        for (int r = 0; r < g; ++r) {
+          xs[r] = (const T*)x[r0 + r];
+          ys[r] = (T*)y[r0 + r];
+        }
+        launch_matvec_multi<T>(op, g, xs, ys, xpm, tm, s);
+      }
+      r0 += g;
+    }
+  };
+  if (op->prec == HMX_FP64) run(double2{});
+  else run(float2{});
+  return HMX_OK;
+  API_CATCH
+}
+
 hmx_status hmx_graph_create(const hmx_op* op, const void* x, void* y, hmx_graph** out) {
   API_TRY
   HMX_REQUIRE(op && x && y && out, HMX_EINVAL, "null pointer");

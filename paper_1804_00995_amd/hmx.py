@@ -97,6 +97,8 @@ _sig = {
     "hmx_cfie_matvec": [_P, _f64, _P, _P, _P],
     "hmx_cfie_gmres": [_P, _f64, _P, _P, _i32, _i32, _f64, _P, C.POINTER(_i32), C.POINTER(_f64)],
     "hmx_matvec": [_P, _P, _P, _P],
+    "hmx_matvec_multi_work_bytes": [_P, C.POINTER(C.c_size_t)],
+    "hmx_matvec_multi": [_P, _i32, C.POINTER(_P), C.POINTER(_P), _P, _P],
     "hmx_info": [_P, C.POINTER(Info)],
     "hmx_export_tree": [_P, _P, _P, _P, _P, _P, _P, _P],
     "hmx_export_blocks": [_P, _P, _P, _P],
@@ -240,6 +242,29 @@ class Operator:
         _check(_lib.hmx_matvec(self._h, _dev(x, self.cdtype, "x"), _dev(y, self.cdtype, "y"),
                                _stream_ptr(stream)))
         return y
+
+    def matvec_multi(self, X, Y=None, stream=None):
+        """Y[r] = K X[r] for the nr rows of X (nr, cols): the operator's entries read once per
+        group of up to four vectors; each row bit-identical to matvec's."""
+        import torch
+        if X.dim() != 2 or X.shape[1] != self.cols:
+            raise ValueError(f"X must have shape (nr, {self.cols})")
+        nr = X.shape[0]
+        if Y is None:
+            Y = torch.empty((nr, self.rows), dtype=X.dtype, device=X.device)
+        elif Y.shape != (nr, self.rows):
+            raise ValueError(f"Y must have shape ({nr}, {self.rows})")
+        _dev(X, self.cdtype, "X")
+        _dev(Y, self.cdtype, "Y")
+        nb = C.c_size_t(0)
+        _check(_lib.hmx_matvec_multi_work_bytes(self._h, C.byref(nb)))
+        work = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=X.device)
+        xs = (_P * nr)(*[X[r].data_ptr() for r in range(nr)])
+        ys = (_P * nr)(*[Y[r].data_ptr() for r in range(nr)])
+        _check(_lib.hmx_matvec_multi(self._h, nr, xs, ys, C.c_void_p(work.data_ptr()),
+                                     _stream_ptr(stream)))
+        self._work = work  # kept until the next call so that the queued kernels can use it
+        return Y
 
     def __matmul__(self, x):
         return self.matvec(x)

@@ -146,6 +146,17 @@ def test_galerkin_argument_errors_without_gpu(hmx):
     lib.hmx_p1_destroy(None)  # NULL-safe
 
 
+def test_matvec_multi_argument_errors_without_gpu(hmx):
+    lib = hmx._lib
+    fake = C.c_void_p(4096)
+    ptrs = (C.c_void_p * 2)(4096, 8192)
+    nb = C.c_size_t(0)
+    assert lib.hmx_matvec_multi_work_bytes(None, C.byref(nb)) == hmx.EINVAL
+    assert lib.hmx_matvec_multi(None, 2, ptrs, ptrs, fake, None) == hmx.EINVAL
+    assert lib.hmx_matvec_multi(fake, 0, ptrs, ptrs, fake, None) == hmx.EINVAL  # nr < 1
+    assert lib.hmx_matvec_multi(fake, 2, None, ptrs, fake, None) == hmx.EINVAL
+
+
 def test_rwg_argument_errors_without_gpu(hmx):
     lib = hmx._lib
     h = C.c_void_p()
