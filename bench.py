@@ -625,6 +625,10 @@ def run_em(args, torch, oracle, hmx, I):
     beta = 0.5 on RWG elements (corrected single layer and the three gradient kernels as
     H-matrices), GMRES to 1e-6, far field checked against the Mie series."""
     level, k, beta = args.level, args.k, 0.5
+    fp32 = args.precision == "fp32"
+    prec = hmx.FP32_MIXED if fp32 else hmx.FP64
+    cdt = torch.complex64 if fp32 else torch.complex128
+    gtol = 1e-5 if fp32 else 1e-6  # c64 vectors: the true residual stalls near 1e-6
     v, f = I.icosphere(level)
     bary, w = I.rule_3pt()
     d, pol = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0])
@@ -633,24 +637,24 @@ def run_em(args, torch, oracle, hmx, I):
     xyzw = hmx.quad_points(vd, fd, bary, w, stream=stream)
     P = xyzw[:3].T.contiguous()
     ph = torch.exp(1j * k * (P.to(torch.complex128) @ torch.from_numpy(d).to(torch.complex128).cuda()))
-    e_inc = (torch.from_numpy(pol).to(torch.complex128).cuda()[:, None] * ph[None, :]).contiguous()
-    h_inc = (torch.from_numpy(np.cross(d, pol)).to(torch.complex128).cuda()[:, None] * ph[None, :]).contiguous()
+    e_inc = (torch.from_numpy(pol).to(torch.complex128).cuda()[:, None] * ph[None, :]).to(cdt).contiguous()
+    h_inc = (torch.from_numpy(np.cross(d, pol)).to(torch.complex128).cuda()[:, None] * ph[None, :]).to(cdt).contiguous()
     torch.cuda.synchronize()
     log(f"bench em: {f.shape[0]} triangles, {xyzw.shape[1]} points, {3 * f.shape[0] // 2} edges, k={k}")
     last = {}
 
     def build_ops():
         single = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, stream=stream,
-                           prm=hmx.params(tol=1e-3, regularize=1))
+                           prm=hmx.params(tol=1e-3, regularize=1, precision=prec))
         grads = [hmx.build(vd, fd, bary, w, kern=hmx.GRADY_X + i, k=k, stream=stream,
-                           prm=hmx.params(tol=1e-3)) for i in range(3)]
+                           prm=hmx.params(tol=1e-3, precision=prec)) for i in range(3)]
         return single, grads
 
     def step():
         single, grads = build_ops()
         sp = hmx.RWG(single, grads, vd, fd, bary, w, stream=stream)
         b = sp.rhs(beta, e_inc, h_inc, stream=stream)
-        x, it, res = sp.gmres(beta, b, tol=1e-6, restart=200, max_iter=3000, stream=stream)
+        x, it, res = sp.gmres(beta, b, tol=gtol, restart=200, max_iter=3000, stream=stream)
         last.update(it=it, res=res, x=x)
         return _EmOps(single, grads, sp), x
 
@@ -683,7 +687,8 @@ def run_em(args, torch, oracle, hmx, I):
         """Entries read once for nr vectors; per vector x read, xp written and read, y written
         and the permutation twice."""
         i = op.info
-        return 16 * (i["near_entries"] + i["far_entries"] + i["dense_far_entries"]) + nr * (16 * 4 * M + 8 * M)
+        es = 8 if fp32 else 16
+        return es * (i["near_entries"] + i["far_entries"] + i["dense_far_entries"]) + nr * (es * 4 * M + 8 * M)
 
     # the single layer on 4 vectors and each gradient operator on 2, in one product each
     cfie_bytes = product_bytes(ops.single, 4) + sum(product_bytes(g, 2) for g in ops.grads)
@@ -721,7 +726,7 @@ def run_em(args, torch, oracle, hmx, I):
         "far_field_rel_err": far_err,
         "sizes": sizes(info),
     }
-    extra.update(rooflines(info, aca, cfie_ms, M, 16, "fp64"))
+    extra.update(rooflines(info, aca, cfie_ms, M, 8 if fp32 else 16, args.precision))
     extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
     extra["roofline_matvec"] = {"bound": "hbm", "achieved": round(cfie_bytes / (cfie_ms * 1e-3) / 1e9, 1),
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -731,8 +736,9 @@ def run_em(args, torch, oracle, hmx, I):
     ops.close()
     config = {"workload": f"PEC unit sphere, icosphere L{level} ({f.shape[0]} triangles, {M} points, "
                           f"{3 * f.shape[0] // 2} RWG unknowns), k={k:g}, CFIE beta 0.5 (corrected "
-                          f"single layer + 3 gradient kernels), ACA tol 1e-3, GMRES(200) to 1e-6, fp64"}
-    line(args, ms_step, "fp64", config, extra,
+                          f"single layer + 3 gradient kernels), ACA tol 1e-3, GMRES(200) to {gtol:g}, "
+                          f"{args.precision}"}
+    line(args, ms_step, args.precision, config, extra,
          unit="ms per step (4 H-builds from device mesh + GMRES solve of the CFIE system)")
 
 
