@@ -16,6 +16,8 @@
  * applied to complex vectors.  The compression (cluster tree, admissibility, partially pivoted
  * ACA) is not described in the paper; libhmx uses a bounding-box bisection tree, the
  * admissibility min(diam) <= eta * dist, and ACA with the Frobenius-norm stopping rule at tol.
+ * On top of these operators: the Galerkin P1 system of the acoustic example and the EFIE, MFIE
+ * and CFIE on RWG elements of the electromagnetic one (Section 6), with their GMRES solves.
  *
  * Conventions for every entry point:
  *   - every function returns an hmx_status (0 = success); on failure nothing is returned through
@@ -25,8 +27,9 @@
  *     memory; the library never takes ownership of caller memory and copies what it keeps;
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream);
  *   - complex vectors are interleaved (re, im): double pairs for HMX_FP64 operators, float pairs
- *     for HMX_FP32_MIXED operators; vectors have one entry per quadrature point, in the original
- *     triangle-major order m = n_q * t + q.
+ *     for HMX_FP32_MIXED operators; operator vectors have one entry per quadrature point, in the
+ *     original triangle-major order m = n_q * t + q (the P1 and RWG spaces' vectors: one entry
+ *     per vertex or per edge).
  */
 #ifndef HMX_H
 #define HMX_H
