@@ -182,3 +182,31 @@ def test_argument_errors(H):
     with pytest.raises(RuntimeError):
         sp.matvec(1.0, x)
     sp.close()
+
+
+def test_cfie_product_graph_replays_equal_eager(H):
+    """The CFIE product allocates nothing and synchronises nothing, so it can be captured: each
+    replay (with eager work and synchronisation between replays) equals the eager product."""
+    v, f = I.icosphere(3)
+    sp, _, _ = space(H, v, f, tol=1e-6)
+    x = dev(I.complex_vector(sp.n_edges, 9))
+    ref = sp.matvec(0.5, x)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        sp.matvec(0.5, x, stream=s)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        y = sp.matvec(0.5, x, stream=s)
+    torch.cuda.synchronize()
+    for i in range(3):
+        y.zero_()
+        other = sp.matvec(1.0, x)  # eager work on the same space between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), i
+    del g, other
