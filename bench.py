@@ -87,11 +87,20 @@ def copy_calibration(mib):
     n = mib * (1 << 20) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
     for _ in range(5):
+        ev[0].record()
         torch.neg(a, out=b)
+        ev[1].record()
+        ev[1].synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
     torch.cuda.synchronize()
+    ms = float(np.median(times))
     print(json.dumps({"copy_calibration": {"bytes_read_per_launch": n * 8,
-                                           "bytes_written_per_launch": n * 8, "launches": 5}}))
+                                           "bytes_written_per_launch": n * 8, "launches": 5,
+                                           "median_ms": round(ms, 4),
+                                           "gb_per_s": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}}))
 
 
 def timed_steps(step, steps, warmup):
