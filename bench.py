@@ -234,9 +234,22 @@ def run_sphere(args, torch, oracle, hmx, I):
         Ho.matvec(x_h)
         c2 = time.perf_counter()
         Ho.close()
+        cores = oracle.max_threads()
         cpu = {"value": round((c2 - c0) * 1e3, 1), "unit": "ms per step (H-build + one H-matvec)",
-               "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": f"full workload once: build {c1 - c0:.2f} s, product {c2 - c1:.2f} s"}
+               "cores": cores, "kind": "oracle",
+               "sample": f"full workload once: build {c1 - c0:.2f} s, product {c2 - c1:.2f} s "
+                         f"(both on {cores} threads)"}
+        if args.cpu_one_core == "on":
+            # the same oracle on one core, beside the paper's single-core timings
+            c0 = time.perf_counter()
+            Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, args.k, leaf=64, eta=1.5, tol=1e-3,
+                                mesh=(v, f, bary) if reg else None, nthreads=1)
+            c1 = time.perf_counter()
+            Ho.matvec(x_h)
+            c2 = time.perf_counter()
+            Ho.close()
+            oracle.HMatrix(P[:8], Wq[:8], oracle.LAPLACE, 0.0, leaf=64, nthreads=cores).close()
+            cpu["one_core"] = {"build_s": round(c1 - c0, 2), "product_s": round(c2 - c1, 3)}
         log(f"cpu baseline {cpu}")
     extra = {
         "h_build_s": round(build_s, 4),
@@ -630,7 +643,7 @@ class _EmOps:
 
 
 def run_em(args, torch, oracle, hmx, I):
-    """The paper's electromagnetic example (Section 6.2) on the PEC unit sphere: CFIE with
+    """The paper's electromagnetic example (Section 5.5) on the PEC unit sphere: CFIE with
     beta = 0.5 on RWG elements (corrected single layer and the three gradient kernels as
     H-matrices), GMRES to 1e-6, far field checked against the Mie series."""
     level, k, beta = args.level, args.k, 0.5
@@ -868,6 +881,8 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=30)
     ap.add_argument("--sample-rows", type=int, default=384)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--cpu-one-core", choices=["on", "off"], default="off",
+                    help="sphere workload: also time the oracle on one core (about a minute)")
     ap.add_argument("--regularize", choices=["on", "off"], default="off",
                     help="sphere workload: near field with the singular correction")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -4,8 +4,8 @@
  * Problem statement (Alouges & Aussal, "FEM and BEM simulations with the Gypsilab framework",
  * arXiv 1804.00995):
  *   - a triangulated surface and a quadrature rule per triangle give the points and weights
- *     (x_k, w_k) of the discretisation (Section 3, "build the set of quadrature points/weights";
- *     Section 4.2, a domain is a mesh plus a quadrature formula);
+ *     (x_k, w_k) of the discretisation (Section 3: integrals are sums over the simplices' Gauss
+ *     points with their weights; Section 4.2, a domain is a mesh plus a quadrature formula);
  *   - the BEM matrices are products around the dense kernel matrix G_kl = G(x_k, y_l)
  *     (Section 5, eq. (BEM)), with the Helmholtz kernel G(x, y) = e^{ik|x-y|} / (4 pi |x-y|)
  *     (Section 5.2, eq. (Helmholtz));
@@ -17,7 +17,8 @@
  * ACA) is not described in the paper; libhmx uses a bounding-box bisection tree, the
  * admissibility min(diam) <= eta * dist, and ACA with the Frobenius-norm stopping rule at tol.
  * On top of these operators: the Galerkin P1 system of the acoustic example and the EFIE, MFIE
- * and CFIE on RWG elements of the electromagnetic one (Section 6), with their GMRES solves.
+ * and CFIE on RWG elements of the electromagnetic one (Sections 5.4 and 5.5), with their GMRES
+ * solves.
  *
  * Conventions for every entry point:
  *   - every function returns an hmx_status (0 = success); on failure nothing is returned through
@@ -195,7 +196,7 @@ hmx_status hmx_build_rect(const double* txyz, int64_t Mt, const double* xyzw, in
 
 /* Galerkin P1 operator (eq. (BEM) with test and trial functions: A = Phi^T W_x K Phi, Phi[k, v]
  * the P1 hat function of vertex v at quadrature point k, W_x the point weights, K = G W_y the
- * operator) and its iterative solve, as in the paper's acoustic example (Section 6: the Galerkin
+ * operator) and its iterative solve, as in the paper's acoustic example (Section 5.4: the Galerkin
  * single-layer equation of the sound-soft sphere, with the kernel's correction).
  * hmx_p1_create: the P1 space of the mesh `op` was built on (hmx_build with the same vtx, tri
  * and rule; the caller keeps op alive while the space is used).  vtx, tri device arrays as in
@@ -224,7 +225,7 @@ hmx_status hmx_galerkin_matvec(const hmx_p1* p, const void* xv, void* yv, void* 
 hmx_status hmx_gmres(const hmx_p1* p, const void* b, void* x, int32_t restart, int32_t max_iter,
                      double tol, void* stream, int32_t* iters, double* relres);
 
-/* Electromagnetic scattering (Section 6.2) on lowest-order Raviart-Thomas (RWG) elements
+/* Electromagnetic scattering (Section 5.5) on lowest-order Raviart-Thomas (RWG) elements
  * (Section 4): one unknown per edge of a closed, consistently oriented mesh, edges numbered in
  * increasing (a, b), a < b their vertex numbers.  On triangle t the edge opposite local vertex j
  * carries psi(y) = s l / (2 A) (y - p_j) (l its length, A the area, p_j the opposite vertex,
@@ -317,12 +318,13 @@ hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream);
  * operator is applied to groups of four, then two, then one vector, each group in one product
  * that reads the operator's entries once; a dense operator takes one product per vector.  The
  * result of each vector is bit-identical to hmx_matvec's (same summation order).
- *   x, y: host arrays of nr device pointers, each vector as in hmx_matvec (no aliasing).
+ *   x, y: host arrays of nr device pointers, each vector as in hmx_matvec; no y[r] may equal
+ *   any x[q] or another y[q] (HMX_EINVAL).
  *   work: device scratch of hmx_matvec_multi_work_bytes(op) bytes (0 for a dense operator, where
  *   work may be NULL), owned by the caller; products using the same work buffer or operator
  *   must not overlap in time.
- * Asynchronous on `stream`; allocates nothing.  Errors: HMX_EINVAL for null pointers, nr < 1 or
- * a missing work buffer. */
+ * Asynchronous on `stream`; allocates nothing.  Errors: HMX_EINVAL for null pointers, nr < 1,
+ * aliased vectors or a missing work buffer. */
 hmx_status hmx_matvec_multi_work_bytes(const hmx_op* op, size_t* bytes);
 hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, void* const* y,
                             void* work, void* stream);

@@ -875,40 +875,94 @@ void *hmo_hbuild(const double *X, const double *Y, const double *Z, const double
     return H;
 }
 
-/* y = H x with x, y in the original point order. */
+/* y = H x with x, y in the original point order.  Every entry of y sums the near blocks in list
+ * order (columns ascending), then the far blocks in list order (terms ascending), with
+ * t_l = sum_j V[l][j] x_j (columns ascending) per far block.  The rows are split over threads by
+ * cluster-tree leaves: each thread owns whole leaves and applies every block that covers them
+ * in that order, so the sums are the same for any thread count. */
 void hmo_hmatvec(const void *hp, const cplx *x, cplx *y)
 {
     const hmo_h *H = hp;
     const tree_t *T = &H->T;
-    int64_t M = H->M;
+    int64_t M = H->M, nn = H->nearL.n, nf = H->farL.n;
     cplx *xp = malloc(sizeof(cplx) * (size_t)M), *yp = calloc((size_t)M, sizeof(cplx));
     for (int64_t p = 0; p < M; ++p) xp[p] = x[T->perm[p]];
-    for (int64_t b = 0; b < H->nearL.n; ++b) {
-        int32_t t = H->nearL.t[b], s = H->nearL.s[b];
-        int64_t tb = T->begin[t], m = T->end[t] - tb, sb = T->begin[s], n = T->end[s] - sb;
-        const cplx *K = H->nearK[b];
-        for (int64_t j = 0; j < n; ++j)
-            for (int64_t i = 0; i < m; ++i) yp[tb + i] += K[j * m + i] * xp[sb + j];
+    /* the leaves in cluster order and the leaf of every position */
+    int64_t nl = 0, nodes = T->n;
+    for (int64_t i = 0; i < nodes; ++i) nl += T->child0[i] < 0;
+    int64_t *lb = malloc(sizeof(int64_t) * (size_t)(nl + 1));
+    int32_t *leaf_of = malloc(sizeof(int32_t) * (size_t)(M ? M : 1));
+    for (int64_t i = 0; i < nodes; ++i)
+        if (T->child0[i] < 0)
+            for (int64_t p = T->begin[i]; p < T->end[i]; ++p) leaf_of[p] = -1 - (int32_t)i;
+    /* number the leaves by position */
+    for (int64_t p = 0, q = 0; p < M; ++p)
+        if (p == 0 || leaf_of[p] != leaf_of[p - 1]) lb[q++] = p;
+    lb[nl] = M;
+    for (int64_t q = 0; q < nl; ++q)
+        for (int64_t p = lb[q]; p < lb[q + 1]; ++p) leaf_of[p] = (int32_t)q;
+    /* per leaf, the blocks covering it: near blocks, then far blocks, each in list order */
+    int64_t *ptr = calloc((size_t)(nl + 1), sizeof(int64_t));
+    for (int64_t b = 0; b < nn + nf; ++b) {
+        int32_t t = b < nn ? H->nearL.t[b] : H->farL.t[b - nn];
+        for (int64_t q = leaf_of[T->begin[t]]; q <= leaf_of[T->end[t] - 1]; ++q) ++ptr[q + 1];
     }
-    for (int64_t b = 0; b < H->farL.n; ++b) {
-        int32_t t = H->farL.t[b], s = H->farL.s[b];
-        int64_t tb = T->begin[t], m = T->end[t] - tb, sb = T->begin[s], n = T->end[s] - sb;
-        if (H->farDense[b]) {
-            const cplx *K = H->farDense[b];
-            for (int64_t j = 0; j < n; ++j)
-                for (int64_t i = 0; i < m; ++i) yp[tb + i] += K[j * m + i] * xp[sb + j];
-            continue;
-        }
+    for (int64_t q = 0; q < nl; ++q) ptr[q + 1] += ptr[q];
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)(nl + 1));
+    memcpy(fill, ptr, sizeof(int64_t) * (size_t)(nl + 1));
+    int64_t *lst = malloc(sizeof(int64_t) * (size_t)(ptr[nl] ? ptr[nl] : 1));
+    for (int64_t b = 0; b < nn + nf; ++b) {
+        int32_t t = b < nn ? H->nearL.t[b] : H->farL.t[b - nn];
+        for (int64_t q = leaf_of[T->begin[t]]; q <= leaf_of[T->end[t] - 1]; ++q) lst[fill[q]++] = b;
+    }
+    /* t_b = V_b^T x_s of the low-rank far blocks */
+    int64_t *toff = malloc(sizeof(int64_t) * (size_t)(nf + 1));
+    toff[0] = 0;
+    for (int64_t b = 0; b < nf; ++b) toff[b + 1] = toff[b] + (H->farDense[b] ? 0 : H->farF[b].rank);
+    cplx *tv = malloc(sizeof(cplx) * (size_t)(toff[nf] ? toff[nf] : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = 0; b < nf; ++b) {
+        if (H->farDense[b]) continue;
+        int32_t s = H->farL.s[b];
+        int64_t sb = T->begin[s], n = T->end[s] - sb;
         const aca_t *F = &H->farF[b];
         for (int64_t l = 0; l < F->rank; ++l) {
             cplx tl = 0.0;
             for (int64_t j = 0; j < n; ++j) tl += F->V[l * n + j] * xp[sb + j];
-            for (int64_t i = 0; i < m; ++i) yp[tb + i] += F->U[l * m + i] * tl;
+            tv[toff[b] + l] = tl;
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < nl; ++q) {
+        for (int64_t e = ptr[q]; e < ptr[q + 1]; ++e) {
+            int64_t b = lst[e];
+            int far = b >= nn;
+            int32_t t = far ? H->farL.t[b - nn] : H->nearL.t[b];
+            int32_t s = far ? H->farL.s[b - nn] : H->nearL.s[b];
+            int64_t tb = T->begin[t], m = T->end[t] - tb, sb = T->begin[s], n = T->end[s] - sb;
+            int64_t i0 = lb[q] - tb, i1 = lb[q + 1] - tb; /* this leaf's rows of the block */
+            const cplx *K = far ? H->farDense[b - nn] : H->nearK[b];
+            if (K) {
+                for (int64_t j = 0; j < n; ++j)
+                    for (int64_t i = i0; i < i1; ++i) yp[tb + i] += K[j * m + i] * xp[sb + j];
+                continue;
+            }
+            const aca_t *F = &H->farF[b - nn];
+            const cplx *tb_ = tv + toff[b - nn];
+            for (int64_t l = 0; l < F->rank; ++l)
+                for (int64_t i = i0; i < i1; ++i) yp[tb + i] += F->U[l * m + i] * tb_[l];
         }
     }
     for (int64_t p = 0; p < M; ++p) y[T->perm[p]] = yp[p];
     free(xp);
     free(yp);
+    free(lb);
+    free(leaf_of);
+    free(ptr);
+    free(fill);
+    free(lst);
+    free(toff);
+    free(tv);
 }
 
 /* Sizes: [0] nodes, [1] near blocks, [2] far blocks, [3] sum m*n over near, [4] sum r*(m+n)

@@ -1,11 +1,11 @@
-"""CPU FP64 oracle of the electromagnetic boundary integral equations (Section 6.2: EFIE, MFIE and
+"""CPU FP64 oracle of the electromagnetic boundary integral equations (Section 5.5: EFIE, MFIE and
 CFIE on lowest-order Raviart-Thomas / RWG elements, Section 4) -- test infrastructure only.
 
 Only the tests and the bench's CPU-baseline leg use this module.  Dense matrices throughout: the
 point operators come from the oracle's C kernels (``dense_matrix``, ``reg_matrix``), the RWG
 functions from their definition, evaluated at the quadrature points.
 
-Conventions (readings of Section 6.2, each written out here):
+Conventions (readings of Section 5.5, each written out here):
   * one unknown per edge of a closed, consistently oriented triangle mesh; edges numbered in
     increasing (a, b), a < b their vertex numbers;
   * on triangle t the edge opposite local vertex j carries psi(y) = s l / (2 A) (y - p_j), l the

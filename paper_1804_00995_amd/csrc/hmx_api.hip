@@ -385,6 +385,13 @@ hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, 
   HMX_REQUIRE(op && x && y, HMX_EINVAL, "null pointer");
   HMX_REQUIRE(nr >= 1, HMX_EINVAL, "nr must be >= 1");
   for (int r = 0; r < nr; ++r) HMX_REQUIRE(x[r] && y[r], HMX_EINVAL, "null vector pointer");
+  // vectors run in successive groups, so an output that is also an input (of any vector) or
+  // that appears twice would be overwritten before it is read or write over another result
+  for (int r = 0; r < nr; ++r)
+    for (int q = 0; q < nr; ++q) {
+      HMX_REQUIRE((const void*)y[r] != x[q], HMX_EINVAL, "an output vector aliases an input vector");
+      HMX_REQUIRE(q <= r || y[r] != y[q], HMX_EINVAL, "an output vector appears twice");
+    }
   HMX_REQUIRE(op->dense || work, HMX_EINVAL, "an H-matrix operator needs the work buffer");
   hipStream_t s = as_stream(stream);
   auto run = [&](auto tag) {

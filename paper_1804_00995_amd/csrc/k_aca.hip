@@ -1,7 +1,7 @@
 // k_aca.hip -- partially pivoted adaptive cross approximation of the far blocks.
 //
-// The paper compresses the kernel matrix "to the desired tolerance" without stating the method;
-// libhmx uses Bebendorf-style partial pivoting.  For a far block A (m x n, A_ij =
+// The paper compresses the kernel matrix to a given accuracy (Section 5.3) without stating the
+// method; libhmx uses Bebendorf-style partial pivoting.  For a far block A (m x n, A_ij =
 // G(x_{t+i}, x_{s+j}) w_{s+j}), step k with pivot row i_k:
 //   (1) residual row R_j = A(i_k, j) - sum_{l<k} u_l[i_k] v_l[j]
 //   (2) pivot column j_k = argmax over unused columns of |R_j|^2 (lowest index on ties); a row
@@ -10,7 +10,8 @@
 //   (3) v_k = R / R_{j_k}
 //   (4) u_k[i] = A(i, j_k) - sum_{l<k} v_l[j_k] u_l[i]
 //   (5) |S_k|_F^2 = |S_{k-1}|_F^2 + 2 Re sum_{l<k} (u_l^H u_k)(v_l^H v_k) + |u_k|^2 |v_k|^2
-//   (6) stop, keeping term k, when |u_k| |v_k| <= tol |S_k|_F
+//   (6) stop, keeping term k, when |u_k| |v_k| <= tol |S_k|_F has held at ACA_STOP_STEPS (two)
+//       consecutive steps; a zero residual row in between neither counts nor resets
 //   (7) next pivot row = argmax over unused rows of |u_k[i]|^2 (lowest index on ties).
 // A ~ sum_k u_k v_k^T with U (m x cap) and V (n x cap) stored column-major.  Pivot magnitudes,
 // norms and the cross terms are accumulated in FP64 in both precisions.

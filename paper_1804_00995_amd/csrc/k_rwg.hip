@@ -1,5 +1,5 @@
 // k_rwg.hip -- lowest-order Raviart-Thomas (RWG) elements at the quadrature points, for the
-// electromagnetic equations of Section 6.2 (EFIE, MFIE, CFIE).
+// electromagnetic equations of Section 5.5 (EFIE, MFIE, CFIE).
 //
 // On triangle t the unknown of the edge opposite local vertex j carries
 // psi(y) = c_j (y - p_j), c_j = s l_j / (2 A) (s = +-1 the edge's orientation on t), with

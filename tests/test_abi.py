@@ -155,6 +155,15 @@ def test_matvec_multi_argument_errors_without_gpu(hmx):
     assert lib.hmx_matvec_multi(None, 2, ptrs, ptrs, fake, None) == hmx.EINVAL
     assert lib.hmx_matvec_multi(fake, 0, ptrs, ptrs, fake, None) == hmx.EINVAL  # nr < 1
     assert lib.hmx_matvec_multi(fake, 2, None, ptrs, fake, None) == hmx.EINVAL
+    # aliasing is refused before the operator is read (the fake operator is never touched):
+    # an output equal to an input of a later group, and an output listed twice
+    xs = (C.c_void_p * 3)(4096, 8192, 12288)
+    ys = (C.c_void_p * 3)(16384, 20480, 4096)
+    assert lib.hmx_matvec_multi(fake, 3, xs, ys, fake, None) == hmx.EINVAL
+    assert b"aliases" in lib.hmx_last_error()
+    ys2 = (C.c_void_p * 3)(16384, 20480, 16384)
+    assert lib.hmx_matvec_multi(fake, 3, xs, ys2, fake, None) == hmx.EINVAL
+    assert b"twice" in lib.hmx_last_error()
 
 
 def test_rwg_argument_errors_without_gpu(hmx):

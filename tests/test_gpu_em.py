@@ -1,4 +1,4 @@
-"""GPU parity of the electromagnetic equations (Section 6.2: EFIE, MFIE, CFIE on RWG elements)
+"""GPU parity of the electromagnetic equations (Section 5.5: EFIE, MFIE, CFIE on RWG elements)
 through the C ABI, against the CPU oracle and the Mie series of the PEC sphere.
 
 Bars: edge numbering identical to the oracle's; the RWG field, its divergence and the

@@ -1,4 +1,4 @@
-"""Pins of the oracle's electromagnetic equations (Section 6.2: EFIE, MFIE, CFIE on RWG elements),
+"""Pins of the oracle's electromagnetic equations (Section 5.5: EFIE, MFIE, CFIE on RWG elements),
 against facts the oracle does not use:
   * RWG topology: one unknown per edge (3 n_t / 2 on a closed mesh), errors for an open mesh and
     for a flipped triangle;

@@ -325,6 +325,110 @@ def test_block_partition_brute_force(leaf):
     assert keys == sorted(keys)
 
 
+def _py_tree(P, idx, leaf):
+    """Brute-force restatement of the bisection keeping the nodes: (begin, end, children) with
+    positions in the cluster order of _py_cluster_order."""
+    order = []
+
+    def rec(ids):
+        b = len(order)
+        pts = P[ids]
+        lo, hi = pts.min(0), pts.max(0)
+        ext = hi - lo
+        ax = int(np.argmax(ext))
+        if len(ids) > leaf and ext[ax] > 0:
+            mid = 0.5 * (lo[ax] + hi[ax])
+            left = [i for i in ids if P[i, ax] < mid]
+            right = [i for i in ids if not P[i, ax] < mid]
+            if left and right:
+                kids = (rec(left), rec(right))
+                return (b, len(order), kids)
+        order.extend(ids)
+        return (b, len(order), None)
+
+    root = rec(list(idx))
+    return root, np.array(order)
+
+
+def _py_blocks(P, root, order, eta, max_mn=0):
+    """Brute-force restatement of the block recursion from (root, root): far when
+    min(diam^2) <= eta^2 dist^2 of the two point boxes (and, with max_mn > 0, the pair holds at
+    most max_mn points or pairs two leaves), near when both are leaves, otherwise recurse into
+    the children of each side that has them."""
+    near, far = [], []
+
+    def box(node):
+        p = P[order[node[0]:node[1]]]
+        return p.min(0), p.max(0)
+
+    def rec(t, s):
+        (lo1, hi1), (lo2, hi2) = box(t), box(s)
+        d1, d2 = ((hi1 - lo1) ** 2).sum(), ((hi2 - lo2) ** 2).sum()
+        gap = np.maximum(0.0, np.maximum(lo2 - hi1, lo1 - hi2))
+        lt, ls = t[2] is None, s[2] is None
+        small = max_mn <= 0 or (t[1] - t[0]) + (s[1] - s[0]) <= max_mn or (lt and ls)
+        if small and min(d1, d2) <= (eta * eta) * (gap ** 2).sum():
+            far.append((t[0], t[1], s[0], s[1]))
+        elif lt and ls:
+            near.append((t[0], t[1], s[0], s[1]))
+        else:
+            for tc in ([t] if lt else t[2]):
+                for sc in ([s] if ls else s[2]):
+                    rec(tc, sc)
+
+    rec(root, root)
+    return sorted(near), sorted(far)
+
+
+@pytest.mark.parametrize("level,leaf,max_mn", [(2, 16, 0), (2, 7, 0), (2, 16, 96), (3, 32, 0)])
+def test_block_tree_matches_brute_force(level, leaf, max_mn):
+    """The oracle's near and far lists equal a plain recursive restatement: this pins every far
+    block as the largest admissible pair on its branch (a stricter or looser comparison in the
+    oracle, e.g. eta * dist^2, changes the lists)."""
+    P, W, H = _tree_blocks(level, leaf, max_mn=max_mn)
+    root, order = _py_tree(P, range(P.shape[0]), leaf)
+    assert H.tree()["perm"].tolist() == order.tolist()
+    near, far = _py_blocks(P, root, order, 1.5, max_mn)
+    nearR, farR, _ = H.blocks()
+    assert [tuple(r) for r in nearR] == near
+    assert [tuple(r) for r in farR] == far
+    # the pin is sensitive to the reading: eta instead of eta^2 gives other lists
+    near_s, far_s = _py_blocks(P, root, order, np.sqrt(1.5), max_mn)
+    assert far_s != far
+
+
+def test_far_blocks_maximal():
+    """No far block's parent pair is admissible: recursing stops at the first admissible pair."""
+    P, W, H = _tree_blocks(3, 16)
+    T = H.tree()
+    perm = T["perm"]
+    parent = {}
+    for i, (c0, c1) in enumerate(zip(T["child0"], T["child1"])):
+        if c0 >= 0:
+            parent[(T["begin"][c0], T["end"][c0])] = (T["begin"][i], T["end"][i])
+            parent[(T["begin"][c1], T["end"][c1])] = (T["begin"][i], T["end"][i])
+
+    def adm(t, s):
+        p1, p2 = P[perm[t[0]:t[1]]], P[perm[s[0]:s[1]]]
+        d1, d2 = (np.ptp(p1, 0) ** 2).sum(), (np.ptp(p2, 0) ** 2).sum()
+        gap = np.maximum(0, np.maximum(p2.min(0) - p1.max(0), p1.min(0) - p2.max(0)))
+        return min(d1, d2) <= 2.25 * (gap ** 2).sum()
+
+    _, farR, _ = H.blocks()
+    checked = 0
+    for tb, te, sb, se in farR:
+        t, s = (tb, te), (sb, se)
+        # a larger pair is never more admissible (larger diameters, smaller distance), so the
+        # pair of the two parents (or of one parent and the root side) covers the pair the
+        # recursion actually came from
+        pt, ps = parent.get(t, t), parent.get(s, s)
+        if (pt, ps) == (t, s):
+            continue
+        assert not adm(pt, ps), (t, s)
+        checked += 1
+    assert checked > 0
+
+
 def test_near_blocks_not_admissible():
     P, W, H = _tree_blocks(3, 16)
     nearR, _, _ = H.blocks()
@@ -424,6 +528,25 @@ def test_hmatvec_close_to_dense(kern, k):
     yh = H.matvec(x)
     assert np.linalg.norm(yh - y) / np.linalg.norm(y) <= 1e-3
     assert H.info["n_far"] > 0 and H.info["s_far"] < H.info["n_far"] * 64 * 64
+
+
+def test_hmatvec_same_for_any_thread_count():
+    """The oracle's product splits rows over threads by leaves with the serial summation order:
+    one thread and all threads give bit-identical results."""
+    cores = oracle.max_threads()
+    v, f = I.icosphere(3)
+    P, W = oracle.quad_points(v, f, *I.rule_3pt())
+    x = I.complex_vector(P.shape[0], 5)
+    ys = []
+    try:
+        for nt in (1, max(cores, 2)):
+            H = oracle.HMatrix(P, W, oracle.HELMHOLTZ, 8.0, leaf=16, tol=1e-3, nthreads=nt)
+            ys.append(H.matvec(x))
+            H.close()
+    finally:
+        oracle.HMatrix(P[:8], W[:8], oracle.LAPLACE, 0.0, leaf=16, nthreads=cores).close()
+    assert oracle.max_threads() == cores
+    assert np.array_equal(ys[0], ys[1])
 
 
 def test_hmatvec_tolerance_controls_error():
