@@ -329,6 +329,22 @@ hmx_status hmx_matvec_multi_work_bytes(const hmx_op* op, size_t* bytes);
 hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, void* const* y,
                             void* work, void* stream);
 
+/* hmx_matvec_multi without a work buffer, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  The scratch is a
+ * static device array of HMX_STATIC_WORK_BYTES bytes inside the library, one on each device it
+ * runs on, held until the process ends; its address is looked up once per device on the first
+ * call there (that call synchronises nothing but may load the library's code object).  Results
+ * are bit-identical to hmx_matvec_multi's.  Every call on one device shares that device's array:
+ * calls that overlap in time on one device (any streams, any operators) race and give wrong
+ * results; calls in order on one stream, or separated by synchronisation, are safe.  Nothing in
+ * the array needs clearing between calls (every entry a product reads it has written first).
+ * Asynchronous on `stream`; allocates nothing (no hipMalloc, no library allocation).
+ * Errors: as hmx_matvec_multi; HMX_EINVAL when hmx_matvec_multi_work_bytes(op) exceeds
+ * HMX_STATIC_WORK_BYTES; HMX_EDEVICE when the array's device address cannot be obtained. */
+#define HMX_STATIC_WORK_BYTES ((size_t)64 << 20)
+hmx_status hmx_matvec_multi_static(const hmx_op* op, int32_t nr, const void* const* x,
+                                   void* const* y, void* stream);
+
 /* Product replay: hmx_matvec(op, x, y) captured once into a HIP graph (fixed operator and
  * vector addresses) and replayed with one launch per call.  The graph holds kernels only.
  * hmx_graph_create captures on a private stream and instantiates (synchronous); hmx_graph_launch

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -336,7 +337,7 @@ hmx_status hmx_build_rect(const double* txyz, int64_t Mt, const double* xyzw, in
 
 namespace {
 // The product's launches (no synchronisation, no allocation: capturable).
-void enqueue_matvec(const hmx_op* op, const void* x, void* y, hipStream_t s) {
+static void enqueue_matvec(const hmx_op* op, const void* x, void* y, hipStream_t s) {
   if (op->dense) {
     if (op->prec == HMX_FP64)
       launch_dense_otf<double2>(op->X.p, op->Y.p, op->Z.p, op->W.p, op->rows, op->x_off, op->cols,
@@ -373,15 +374,24 @@ hmx_status hmx_matvec(const hmx_op* op, const void* x, void* y, void* stream) {
   API_CATCH
 }
 
+namespace {
+// Scratch of the several-vector product: 4 permuted vectors and 4 vectors of far-block
+// coefficients V^H x (each group holds at most four vectors).
+static size_t multi_work_bytes(const hmx_op* op) {
+  return op->dense ? 0 : (size_t)4 * (op->M + std::max<int64_t>(op->t_len, 1)) * op->elem;
+}
+}  // namespace
+
 hmx_status hmx_matvec_multi_work_bytes(const hmx_op* op, size_t* bytes) {
   if (!op || !bytes) return fail(HMX_EINVAL, "null pointer");
-  *bytes = op->dense ? 0 : (size_t)4 * (op->M + std::max<int64_t>(op->t_len, 1)) * op->elem;
+  *bytes = multi_work_bytes(op);
   return HMX_OK;
 }
 
-hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, void* const* y,
-                            void* work, void* stream) {
-  API_TRY
+namespace {
+// Argument checks of the several-vector product (host only, before any enqueue).
+static void check_multi_args(const hmx_op* op, int32_t nr, const void* const* x,
+                             void* const* y) {
   HMX_REQUIRE(op && x && y, HMX_EINVAL, "null pointer");
   HMX_REQUIRE(nr >= 1, HMX_EINVAL, "nr must be >= 1");
   for (int r = 0; r < nr; ++r) HMX_REQUIRE(x[r] && y[r], HMX_EINVAL, "null vector pointer");
@@ -392,8 +402,11 @@ hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, 
       HMX_REQUIRE((const void*)y[r] != x[q], HMX_EINVAL, "an output vector aliases an input vector");
       HMX_REQUIRE(q <= r || y[r] != y[q], HMX_EINVAL, "an output vector appears twice");
     }
-  HMX_REQUIRE(op->dense || work, HMX_EINVAL, "an H-matrix operator needs the work buffer");
-  hipStream_t s = as_stream(stream);
+}
+
+// The several-vector product's launches on `work` (no synchronisation, no allocation).
+static void enqueue_multi(const hmx_op* op, int32_t nr, const void* const* x, void* const* y,
+                          void* work, hipStream_t s) {
   auto run = [&](auto tag) {
     using T = decltype(tag);
     T* xpm = (T*)work;
@@ -417,6 +430,60 @@ hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, 
   };
   if (op->prec == HMX_FP64) run(double2{});
   else run(float2{});
+}
+}  // namespace
+
+hmx_status hmx_matvec_multi(const hmx_op* op, int32_t nr, const void* const* x, void* const* y,
+                            void* work, void* stream) {
+  API_TRY
+  check_multi_args(op, nr, x, y);
+  HMX_REQUIRE(op->dense || work, HMX_EINVAL, "an H-matrix operator needs the work buffer");
+  enqueue_multi(op, nr, x, y, work, as_stream(stream));
+  return HMX_OK;
+  API_CATCH
+}
+
+// ------------------------------------------------------------ product without allocation
+// Scratch of hmx_matvec_multi_static: a file-scope device array, one copy on every device the
+// library runs on, held until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it only stands for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[HMX_STATIC_WORK_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+static void* static_scratch() {
+  int dev = 0;
+  HMX_HIP(hipGetDevice(&dev));
+  HMX_REQUIRE(dev >= 0 && dev < kMaxDevices, HMX_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      throw Error(HMX_EDEVICE, std::string("hipGetSymbolAddress of the static scratch: ") +
+                                   hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+hmx_status hmx_matvec_multi_static(const hmx_op* op, int32_t nr, const void* const* x,
+                                   void* const* y, void* stream) {
+  API_TRY
+  check_multi_args(op, nr, x, y);
+  const size_t need = multi_work_bytes(op);
+  HMX_REQUIRE(need <= HMX_STATIC_WORK_BYTES, HMX_EINVAL,
+              "the operator's product needs " + std::to_string(need) +
+                  " bytes of scratch, more than the static scratch holds (" +
+                  std::to_string((size_t)HMX_STATIC_WORK_BYTES) + " bytes)");
+  void* work = need > 0 ? static_scratch() : nullptr;
+  enqueue_multi(op, nr, x, y, work, as_stream(stream));
   return HMX_OK;
   API_CATCH
 }

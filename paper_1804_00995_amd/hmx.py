@@ -23,6 +23,7 @@ FP64, FP32_MIXED = 0, 1
 RANK_ADAPTIVE, RANK_LEARNED = 0, 1
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5
+STATIC_WORK_BYTES = 64 << 20  # HMX_STATIC_WORK_BYTES: scratch of hmx_matvec_multi_static
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1804_00995_amd.build`")
@@ -99,6 +100,7 @@ _sig = {
     "hmx_matvec": [_P, _P, _P, _P],
     "hmx_matvec_multi_work_bytes": [_P, C.POINTER(C.c_size_t)],
     "hmx_matvec_multi": [_P, _i32, C.POINTER(_P), C.POINTER(_P), _P, _P],
+    "hmx_matvec_multi_static": [_P, _i32, C.POINTER(_P), C.POINTER(_P), _P],
     "hmx_info": [_P, C.POINTER(Info)],
     "hmx_export_tree": [_P, _P, _P, _P, _P, _P, _P, _P],
     "hmx_export_blocks": [_P, _P, _P, _P],
@@ -264,6 +266,24 @@ class Operator:
         _check(_lib.hmx_matvec_multi(self._h, nr, xs, ys, C.c_void_p(work.data_ptr()),
                                      _stream_ptr(stream)))
         self._work = work  # kept until the next call so that the queued kernels can use it
+        return Y
+
+    def matvec_multi_static(self, X, Y=None, stream=None):
+        """matvec_multi on the library's static scratch (no work buffer is allocated; products on
+        one device must not overlap in time).  Y may be given to keep the call allocation-free."""
+        import torch
+        if X.dim() != 2 or X.shape[1] != self.cols:
+            raise ValueError(f"X must have shape (nr, {self.cols})")
+        nr = X.shape[0]
+        if Y is None:
+            Y = torch.empty((nr, self.rows), dtype=X.dtype, device=X.device)
+        elif Y.shape != (nr, self.rows):
+            raise ValueError(f"Y must have shape ({nr}, {self.rows})")
+        _dev(X, self.cdtype, "X")
+        _dev(Y, self.cdtype, "Y")
+        xs = (_P * nr)(*[X[r].data_ptr() for r in range(nr)])
+        ys = (_P * nr)(*[Y[r].data_ptr() for r in range(nr)])
+        _check(_lib.hmx_matvec_multi_static(self._h, nr, xs, ys, _stream_ptr(stream)))
         return Y
 
     def __matmul__(self, x):
