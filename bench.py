@@ -8,6 +8,9 @@ Workloads (synthetic, seeded), selected with --workload:
   batch             64 seeded ellipsoids (semi-axes U[0.5, 2], 2 000-40 000 triangles
                     log-uniform, k U[2, 30], vector seed 1000 + i) built and applied as one
                     block-diagonal operator;
+  target            the same batch in FP32 mixed precision with the learned rank layout (network
+                    trained on the sphere workload's FP64 and FP32 ranks) and the autotuned batch
+                    schedule, reported against the plain FP64 batch;
   large             one eighth (row share 0 of 8) of the prolate (2, 1, 1) ellipsoid with
                     1 310 720 triangles (3 932 160 points), k = 120, leaf 128, tol 1e-4, FP32;
                     100 products replayed in one HIP graph.
@@ -277,6 +280,22 @@ def run_sphere(args, torch, oracle, hmx, I):
     line(args, ms_step, args.precision, config, extra)
 
 
+def batch_errors(oracle, meshes, descs, bary, w, x_h, y_h, off, rows_per_mesh=24, seed=77):
+    """Relative errors of a batch product on seeded sampled rows of every mesh against the
+    oracle's dense rows: (all sampled rows together, worst mesh)."""
+    rng = np.random.default_rng(seed)
+    errs, num, den = [], 0.0, 0.0
+    for i, ((v, f), d) in enumerate(zip(meshes, descs)):
+        P, Wq = oracle.quad_points(v, f, bary, w)
+        rows = np.sort(rng.choice(P.shape[0], rows_per_mesh, replace=False))
+        yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, d["k"], x_h[off[i]:off[i + 1]], rows)
+        diff = np.linalg.norm(y_h[off[i] + rows] - yr)
+        errs.append(float(diff / np.linalg.norm(yr)))
+        num += diff ** 2
+        den += np.linalg.norm(yr) ** 2
+    return float(np.sqrt(num / den)), max(errs)
+
+
 def run_batch(args, torch, oracle, hmx, I):
     descs = I.batch_ellipsoids(64, seed=0)
     bary, w = I.rule_3pt()
@@ -309,17 +328,7 @@ def run_batch(args, torch, oracle, hmx, I):
     cpu, rel_err, rel_err_worst = None, None, None
     if args.cpu_baseline == "on":
         # the oracle leg: errors of the GPU product on sampled rows of every mesh
-        rng = np.random.default_rng(77)
-        errs, num, den = [], 0.0, 0.0
-        for i, ((v, f), d) in enumerate(zip(meshes, descs)):
-            P, Wq = oracle.quad_points(v, f, bary, w)
-            rows = np.sort(rng.choice(P.shape[0], 24, replace=False))
-            yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, d["k"], x_h[off[i]:off[i + 1]], rows)
-            diff = np.linalg.norm(y_h[off[i] + rows] - yr)
-            errs.append(float(diff / np.linalg.norm(yr)))
-            num += diff ** 2
-            den += np.linalg.norm(yr) ** 2
-        rel_err, rel_err_worst = float(np.sqrt(num / den)), max(errs)
+        rel_err, rel_err_worst = batch_errors(oracle, meshes, descs, bary, w, x_h, y_h, off)
         log(f"batch errors: worst mesh {rel_err_worst:.3e}, all sampled rows {rel_err:.3e}")
         # bounded sample: the oracle H-build + product of the first 8 meshes, scaled by points
         c0 = time.perf_counter()
@@ -354,6 +363,140 @@ def run_batch(args, torch, oracle, hmx, I):
     config = {"workload": f"64 seeded ellipsoids ({M} points), Helmholtz k U[2,30], leaf 64, "
                           f"eta 1.5, ACA tol 1e-3, one block-diagonal operator, {args.precision}"}
     line(args, ms_step, args.precision, config, extra)
+
+
+def run_target(args, torch, oracle, hmx, I):
+    """The batch of 64 ellipsoids in its target form -- FP32 mixed precision, the learned
+    rank layout from a network trained on the 245 760-point sphere's ranks (k = 40, FP64 and
+    FP32 builds; the ellipsoids are never seen in training) and the batch schedule picked by
+    the autotuner -- against the plain FP64 batch (adaptive ACA, default schedule)."""
+    from paper_1804_00995_amd import rank_model as R
+    bary, w = I.rule_3pt()
+    # training data: far-block features and ranks of the sphere workload in both precisions
+    vs, fs = I.icosphere(6)
+    vsd, fsd = torch.from_numpy(vs).cuda(), torch.from_numpy(fs).cuda()
+    feats, ranks = [], []
+    for prec in (hmx.FP64, hmx.FP32_MIXED):
+        op = hmx.build(vsd, fsd, bary, w, kern=hmx.HELMHOLTZ, k=40.0,
+                       prm=hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec))
+        f_, r_ = R.block_data(op)
+        feats.append(f_)
+        ranks.append(r_)
+        op.close()
+    t0 = time.perf_counter()
+    model = R.train(np.concatenate(feats), np.concatenate(ranks), epochs=args.train_epochs)
+    train_s = time.perf_counter() - t0
+    log(f"rank model: {sum(len(r) for r in ranks)} sphere blocks, {args.train_epochs} epochs in "
+        f"{train_s:.1f} s, alpha {model.alpha:.3f}, final loss {model.history[-1]:.4f}")
+
+    descs = I.batch_ellipsoids(64, seed=0)
+    meshes, dev = [], []
+    for d in descs:
+        v, f = I.batch_mesh(d)
+        meshes.append((v, f))
+        dev.append((torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda(), d["k"]))
+    x_h = np.concatenate([I.complex_vector(3 * f.shape[0], d["seed"]) for d, (_, f) in zip(descs, meshes)])
+    M = x_h.shape[0]
+    stream = torch.cuda.current_stream()
+
+    def measure(prm, label):
+        cdt = torch.complex128 if prm.precision == hmx.FP64 else torch.complex64
+        xd = torch.from_numpy(x_h).to(cdt).cuda()
+
+        def step():
+            op = hmx.build_batch(dev, bary, w, kern=hmx.HELMHOLTZ, prm=prm, stream=stream)
+            return op, op.matvec(xd, stream=stream)
+
+        ms, aca = timed_steps(step, args.steps, args.warmup)
+        op, y = step()
+        torch.cuda.synchronize()
+        info = op.info
+        mv = product_ms(op, xd, y, stream, args.matvec_reps)
+        y_h = y.cpu().numpy().astype(np.complex128)
+        err = worst = None
+        if oracle is not None:  # the oracle leg: sampled rows of every mesh
+            err, worst = batch_errors(oracle, meshes, descs, bary, w, x_h, y_h, op.mesh_offsets())
+            log(f"{label}: errors {err:.3e} (worst mesh {worst:.3e})")
+        log(f"{label}: {ms:.1f} ms/step, product {mv:.3f} ms")
+        res = {"ms_per_step": round(ms, 3), "h_build_s": round(info["t_total_ms"] / 1e3, 4),
+               "h_matvec_ms": round(mv, 4), "rel_err": err, "rel_err_worst_mesh": worst,
+               "build_phases_ms": {k2: round(info[k2], 2) for k2 in
+                                   ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
+               "sizes": sizes(info), "pool_used_bytes": info["factor_bytes"],
+               "fallback_rate": info["overflow_blocks"] / max(info["n_far"], 1),
+               "aca_rounds": info["aca_rounds"], "predicted_entries": info["predicted_entries"]}
+        return res, info, aca, mv, op
+
+    plain_prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=hmx.FP64)
+    plain, _, _, _, op = measure(plain_prm, "plain FP64 batch")
+    op.close()
+    model.install()
+    try:
+        base = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=hmx.FP32_MIXED,
+                          rank_model=hmx.RANK_LEARNED)
+        t0 = time.perf_counter()
+        tuned, tune_ms = hmx.autotune_batch(dev, bary, w, kern=hmx.HELMHOLTZ, prm=base,
+                                            cache_path=args.tune_cache, stream=stream)
+        tune_s = time.perf_counter() - t0
+        sched = {k2: getattr(tuned, k2) for k2 in ("max_far_mn", "aca_big_mn", "aca_gram_min_mn",
+                                                   "aca_mid_threads", "aca_big_threads",
+                                                   "aca_small_mn", "aca_wave", "aca_serial")}
+        log(f"autotuned batch schedule in {tune_s:.1f} s: {sched} ({tune_ms:.1f} ms)")
+        tgt, info, aca, mv, op = measure(tuned, "FP32 + learned + autotuned batch")
+        # the same schedule without the learned layout: the product must be bit-identical
+        adapt_prm = hmx.params(**{**{k2: getattr(tuned, k2) for k2, _ in hmx.Params._fields_},
+                                  "rank_model": hmx.RANK_ADAPTIVE, "struct_size": tuned.struct_size})
+        op_a = hmx.build_batch(dev, bary, w, kern=hmx.HELMHOLTZ, prm=adapt_prm, stream=stream)
+        xd = torch.from_numpy(x_h).to(torch.complex64).cuda()
+        same = bool(torch.equal(op.matvec(xd), op_a.matvec(xd)))
+        adapt_bytes = op_a.info["bytes"]
+        op_a.close()
+    finally:
+        hmx.set_rank_model(None)
+    tgt.update({"schedule": sched, "autotune_s": round(tune_s, 1),
+                "product_equals_adaptive_same_schedule": same,
+                "adaptive_same_schedule_bytes": adapt_bytes})
+    extra = {
+        "h_build_s": tgt["h_build_s"],
+        "h_matvec_ms": tgt["h_matvec_ms"],
+        "rel_err": tgt["rel_err"],
+        "rel_err_worst_mesh": tgt["rel_err_worst_mesh"],
+        "kernel_evals_per_s": info["kernel_evals"] / (info["t_total_ms"] / 1e3),
+        "target": tgt,
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64": round(plain["ms_per_step"] / tgt["ms_per_step"], 3),
+        "rank_model": {"training_blocks": int(sum(len(r) for r in ranks)),
+                       "epochs": args.train_epochs, "train_s": round(train_s, 2),
+                       "alpha": model.alpha, "beta": model.beta,
+                       "final_loss": float(model.history[-1])},
+    }
+    extra.update(rooflines(info, aca, mv, M, 8, "fp32"))
+    extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
+    op.close()
+    cpu = None
+    if oracle is not None:
+        # bounded sample: the oracle's plain FP64 H-build + product of the first 8 meshes,
+        # scaled by points
+        c0 = time.perf_counter()
+        m_sample = 0
+        for (v, f), d in list(zip(meshes, descs))[:8]:
+            P, Wq = oracle.quad_points(v, f, bary, w)
+            Ho = oracle.HMatrix(P, Wq, oracle.HELMHOLTZ, d["k"], leaf=64, eta=1.5, tol=1e-3)
+            Ho.matvec(I.complex_vector(P.shape[0], d["seed"]))
+            Ho.close()
+            m_sample += P.shape[0]
+        c1 = time.perf_counter()
+        cpu = {"value": round((c1 - c0) * 1e3 * M / m_sample, 1),
+               "unit": "ms per step (H-build + one H-matvec), scaled by points",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"first 8 of the 64 meshes ({m_sample} of {M} points) in {c1 - c0:.2f} s, "
+                         "plain FP64, scaled linearly by points"}
+    extra["cpu_baseline"] = cpu
+    config = {"workload": f"64 seeded ellipsoids ({M} points), Helmholtz k U[2,30], leaf 64, "
+                          "eta 1.5, ACA tol 1e-3: FP32 mixed + learned rank layout (network "
+                          "trained on the L6 sphere's FP64 and FP32 ranks) + autotuned batch "
+                          "schedule, against the plain FP64 batch"}
+    line(args, tgt["ms_per_step"], "fp32", config, extra)
 
 
 def run_radiation(args, torch, oracle, hmx, I):
@@ -871,8 +1014,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["sphere", "batch", "large", "radiation", "scattering",
-                                           "em", "dense"], default="sphere")
+    ap.add_argument("--workload", choices=["sphere", "batch", "target", "large", "radiation",
+                                           "scattering", "em", "dense"], default="sphere")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--level", type=int, default=None,
                     help="icosphere level (default 6; 5 for the em workload)")
@@ -885,6 +1028,10 @@ def main():
                     help="sphere workload: also time the oracle on one core (about a minute)")
     ap.add_argument("--regularize", choices=["on", "off"], default="off",
                     help="sphere workload: near field with the singular correction")
+    ap.add_argument("--train-epochs", type=int, default=60,
+                    help="target workload: epochs of the rank network's training")
+    ap.add_argument("--tune-cache", default=None,
+                    help="target workload: autotuner cache file (default: search afresh)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel used to scale the HBM byte counters")
     args = ap.parse_args()
@@ -906,7 +1053,8 @@ def main():
     if args.cpu_baseline == "on":  # only the CPU-baseline leg loads the oracle
         import oracle
 
-    {"sphere": run_sphere, "batch": run_batch, "large": run_large, "radiation": run_radiation,
+    {"sphere": run_sphere, "batch": run_batch, "target": run_target, "large": run_large,
+     "radiation": run_radiation,
      "scattering": run_scattering, "em": run_em, "dense": run_dense}[args.workload](
         args, torch, oracle, hmx, I)
 

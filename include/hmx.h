@@ -364,13 +364,24 @@ void hmx_graph_destroy(hmx_graph* g); /* NULL is accepted */
  * none}; the other wavefront setting; serial classes; best of two builds each.  *out receives *p (defaults when
  * NULL) with the fastest settings, *best_ms (may be NULL) that build time in ms.
  * cache_path (host string, may be NULL): a JSON file of earlier choices keyed by device
- * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size and eta; a key
- * found there is returned without timing, a new one is added to the file.  Synchronous; builds
+ * architecture, precision, kernel, floor(log2 M), tolerance decade, leaf size, eta and the rank
+ * model; a key found there is returned without timing, a new one is added to the file.  Synchronous; builds
  * and frees up to 63 operators (31 settings, two builds each, one warm-up).  Errors: as
  * hmx_build_points, HMX_EINVAL for tol <= 0 or an unwritable cache file. */
 hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, double k,
                         const hmx_params* p, const char* cache_path, void* stream,
                         hmx_params* out, double* best_ms);
+
+/* The same search for a batch (hmx_build_batch of meshes, n_meshes, q_bary, q_w, n_q, kern,
+ * with *p's method, precision and rank model): each setting is timed on the whole batch build.
+ * Cache key as hmx_autotune's with "|batch<n_meshes>" after the kernel and M the total number
+ * of points; a learned-layout search (p->rank_model = HMX_RANK_LEARNED, model set) is keyed
+ * apart ("|learned") from an adaptive one.  Synchronous; builds and frees up to 63 batch
+ * operators.  Errors: as hmx_build_batch, HMX_EINVAL for tol <= 0 or an unwritable cache. */
+hmx_status hmx_autotune_batch(const hmx_mesh* meshes, int32_t n_meshes, const double* q_bary,
+                              const double* q_w, int32_t n_q, int32_t kern, const hmx_params* p,
+                              const char* cache_path, void* stream, hmx_params* out,
+                              double* best_ms);
 
 typedef struct {
   int64_t n_points, n_nodes, n_leaves, n_near, n_far;

@@ -25,8 +25,10 @@ struct Choice {
   double ms = 0.0;
 };
 
-// "<arch>|<precision>|<kernel>|M2^<floor(log2 M)>|tol1e<round(log10 tol)>|leaf<L>|eta<eta>"
-std::string class_key(int64_t M, int32_t kern, const hmx_params& p) {
+// "<arch>|<precision>|<kernel>|M2^<floor(log2 M)>|tol1e<round(log10 tol)>|leaf<L>|eta<eta>",
+// with "|batch<n>" after the kernel for a batch of n meshes and "|learned" at the end for the
+// learned layout
+std::string class_key(int64_t M, int32_t kern, const hmx_params& p, int32_t n_meshes = 0) {
   int dev = 0;
   HMX_HIP(hipGetDevice(&dev));
   hipDeviceProp_t prop;
@@ -38,8 +40,10 @@ std::string class_key(int64_t M, int32_t kern, const hmx_params& p) {
   const long te = std::lround(std::log10(p.tol));
   std::ostringstream o;
   o << arch << "|" << (p.precision == HMX_FP64 ? "fp64" : "fp32") << "|"
-    << (kern == HMX_LAPLACE ? "laplace" : kern == HMX_HELMHOLTZ ? "helmholtz" : "poly2")
-    << "|M2^" << lm << "|tol1e" << te << "|leaf" << p.leaf_size << "|eta" << p.eta;
+    << (kern == HMX_LAPLACE ? "laplace" : kern == HMX_HELMHOLTZ ? "helmholtz" : "poly2");
+  if (n_meshes > 0) o << "|batch" << n_meshes;
+  o << "|M2^" << lm << "|tol1e" << te << "|leaf" << p.leaf_size << "|eta" << p.eta;
+  if (p.rank_model == HMX_RANK_LEARNED) o << "|learned";
   return o.str();
 }
 
@@ -112,20 +116,119 @@ void write_cache(const char* path, const std::map<std::string, Choice>& m) {
               "cannot replace the autotuner cache file");
 }
 
-// Best of `reps` synchronous builds, in ms (wall clock around the synchronous call).
-double time_build(const double* xyzw, int64_t M, int32_t kern, double k, const hmx_params& p,
-                  void* stream, int reps) {
+// Best of `reps` synchronous builds, in ms (wall clock around the synchronous call);
+// build(p, &op) makes one operator.
+template <class Build>
+double time_build(Build build, const hmx_params& p, int reps) {
   double best = 1e300;
   for (int r = 0; r < reps; ++r) {
     hmx_op* op = nullptr;
     const auto t0 = std::chrono::steady_clock::now();
-    const hmx_status st = hmx_build_points(xyzw, M, kern, k, &p, stream, &op);
+    const hmx_status st = build(p, &op);
     const auto t1 = std::chrono::steady_clock::now();
     if (st != HMX_OK) throw hmx::Error(st, hmx_last_error());
     hmx_destroy(op);
     best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
   }
   return best;
+}
+
+// The search: the far-block size bound first (default schedule), then the class thresholds
+// (concurrent classes), the two workgroup sizes, the small-block bound, the other wavefront
+// setting, then serial vs concurrent at the best; each setting the best of two builds.
+template <class Build>
+Choice search(Build build, const hmx_params& base) {
+  const int maxmns[] = {0, 32768, 16384, 12288, 8192};
+  const int bigs[] = {2048, 4096, 8192, 1 << 30};
+  const int grams[] = {0, 1024, 4096, 1 << 30};
+  const int mids[] = {256, 128, 64};
+  const int bigts[] = {512, 256};
+  const int smalls[] = {512, 2048, 0};
+  hmx_params q = base;
+  q.aca_serial = 0;
+  (void)time_build(build, q, 1);  // warm the allocator and the code
+  Choice best{q.aca_big_mn, q.aca_gram_min_mn, 0, q.max_far_mn, q.aca_mid_threads,
+              q.aca_big_threads, q.aca_small_mn, q.aca_wave, 1e300};
+  auto trial = [&](const hmx_params& t) {
+    const double ms = time_build(build, t, 2);
+    if (ms < best.ms)
+      best = Choice{t.aca_big_mn, t.aca_gram_min_mn, t.aca_serial, t.max_far_mn,
+                    t.aca_mid_threads, t.aca_big_threads, t.aca_small_mn, t.aca_wave, ms};
+  };
+  for (int mx : maxmns) {
+    q.max_far_mn = mx;
+    trial(q);
+  }
+  q.max_far_mn = best.maxmn;
+  for (int b : bigs)
+    for (int g : grams) {
+      q.aca_big_mn = b;
+      q.aca_gram_min_mn = g;
+      trial(q);
+    }
+  q.aca_big_mn = best.big;
+  q.aca_gram_min_mn = best.gram;
+  for (int mt : mids) {
+    q.aca_mid_threads = mt;
+    trial(q);
+  }
+  q.aca_mid_threads = best.mid;
+  for (int bt : bigts) {
+    q.aca_big_threads = bt;
+    trial(q);
+  }
+  q.aca_big_threads = best.bigt;
+  for (int sm : smalls) {
+    q.aca_small_mn = sm;
+    trial(q);
+  }
+  q.aca_small_mn = best.small;
+  q.aca_wave = 1 - q.aca_wave;
+  trial(q);
+  q.aca_wave = best.wave;
+  q.aca_serial = 1;
+  trial(q);
+  return best;
+}
+
+hmx_params resolve_base(const hmx_params* p) {
+  hmx_params base;
+  if (p) {
+    base = *p;
+  } else {
+    const hmx_status st = hmx_params_default(&base);
+    if (st != HMX_OK) throw hmx::Error(st, hmx_last_error());
+  }
+  HMX_REQUIRE(base.struct_size == (int32_t)sizeof(hmx_params), HMX_EINVAL,
+              "hmx_params.struct_size does not match this library (use hmx_params_default)");
+  HMX_REQUIRE(base.tol > 0, HMX_EINVAL, "the autotuner needs an H-matrix build (tol > 0)");
+  return base;
+}
+
+// The cached or searched choice for `key`, written into *out (the caller's base otherwise).
+template <class Build>
+void tune(Build build, const hmx_params& base, const std::string& key, const char* cache_path,
+          hmx_params* out, double* best_ms) {
+  auto cache = read_cache(cache_path);
+  auto hit = cache.find(key);
+  Choice best;
+  if (hit != cache.end()) {
+    best = hit->second;
+  } else {
+    best = search(build, base);
+    cache[key] = best;
+    write_cache(cache_path, cache);
+  }
+  *out = base;
+  out->aca_big_mn = best.big;
+  out->aca_gram_min_mn = best.gram;
+  out->aca_serial = best.serial;
+  out->max_far_mn = best.maxmn;
+  out->aca_mid_threads = best.mid;
+  out->aca_big_threads = best.bigt;
+  out->aca_small_mn = best.small;
+  out->aca_wave = best.wave;
+  if (best_ms) *best_ms = best.ms;
 }
 
 }  // namespace
@@ -136,89 +239,38 @@ extern "C" hmx_status hmx_autotune(const double* xyzw, int64_t M, int32_t kern, 
   try {
     HMX_REQUIRE(xyzw && out, HMX_EINVAL, "null pointer");
     HMX_REQUIRE(M >= 1, HMX_EINVAL, "M must be >= 1");
-    hmx_params base;
-    if (p) {
-      base = *p;
-    } else {
-      const hmx_status st = hmx_params_default(&base);
-      if (st != HMX_OK) return st;
-    }
-    HMX_REQUIRE(base.struct_size == (int32_t)sizeof(hmx_params), HMX_EINVAL,
-                "hmx_params.struct_size does not match this library (use hmx_params_default)");
-    HMX_REQUIRE(base.tol > 0, HMX_EINVAL, "the autotuner needs an H-matrix build (tol > 0)");
-    const std::string key = class_key(M, kern, base);
-    auto cache = read_cache(cache_path);
-    auto hit = cache.find(key);
-    Choice best;
-    if (hit != cache.end()) {
-      best = hit->second;
-    } else {
-      // the far-block size bound first (default schedule), then the class thresholds
-      // (concurrent classes), the two workgroup sizes, the small-block bound, then serial vs
-      // concurrent at the best
-      const int maxmns[] = {0, 32768, 16384, 12288, 8192};
-      const int bigs[] = {2048, 4096, 8192, 1 << 30};
-      const int grams[] = {0, 1024, 4096, 1 << 30};
-      const int mids[] = {256, 128, 64};
-      const int bigts[] = {512, 256};
-      const int smalls[] = {512, 2048, 0};
-      hmx_params q = base;
-      q.aca_serial = 0;
-      (void)time_build(xyzw, M, kern, k, q, stream, 1);  // warm the allocator and the code
-      best = Choice{q.aca_big_mn, q.aca_gram_min_mn, 0, q.max_far_mn, q.aca_mid_threads,
-                    q.aca_big_threads, q.aca_small_mn, q.aca_wave, 1e300};
-      auto trial = [&](const hmx_params& t) {
-        const double ms = time_build(xyzw, M, kern, k, t, stream, 2);
-        if (ms < best.ms)
-          best = Choice{t.aca_big_mn, t.aca_gram_min_mn, t.aca_serial, t.max_far_mn,
-                        t.aca_mid_threads, t.aca_big_threads, t.aca_small_mn, t.aca_wave, ms};
-      };
-      for (int mx : maxmns) {
-        q.max_far_mn = mx;
-        trial(q);
-      }
-      q.max_far_mn = best.maxmn;
-      for (int b : bigs)
-        for (int g : grams) {
-          q.aca_big_mn = b;
-          q.aca_gram_min_mn = g;
-          trial(q);
-        }
-      q.aca_big_mn = best.big;
-      q.aca_gram_min_mn = best.gram;
-      for (int mt : mids) {
-        q.aca_mid_threads = mt;
-        trial(q);
-      }
-      q.aca_mid_threads = best.mid;
-      for (int bt : bigts) {
-        q.aca_big_threads = bt;
-        trial(q);
-      }
-      q.aca_big_threads = best.bigt;
-      for (int sm : smalls) {
-        q.aca_small_mn = sm;
-        trial(q);
-      }
-      q.aca_small_mn = best.small;
-      q.aca_wave = 1 - q.aca_wave;
-      trial(q);
-      q.aca_wave = best.wave;
-      q.aca_serial = 1;
-      trial(q);
-      cache[key] = best;
-      write_cache(cache_path, cache);
-    }
-    *out = base;
-    out->aca_big_mn = best.big;
-    out->aca_gram_min_mn = best.gram;
-    out->aca_serial = best.serial;
-    out->max_far_mn = best.maxmn;
-    out->aca_mid_threads = best.mid;
-    out->aca_big_threads = best.bigt;
-    out->aca_small_mn = best.small;
-    out->aca_wave = best.wave;
-    if (best_ms) *best_ms = best.ms;
+    const hmx_params base = resolve_base(p);
+    auto build = [&](const hmx_params& q, hmx_op** op) {
+      return hmx_build_points(xyzw, M, kern, k, &q, stream, op);
+    };
+    tune(build, base, class_key(M, kern, base), cache_path, out, best_ms);
+    return HMX_OK;
+  } catch (const hmx::Error& e) {
+    hmx::set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    hmx::set_last_error(e.what());
+    return HMX_EINTERNAL;
+  }
+}
+
+extern "C" hmx_status hmx_autotune_batch(const hmx_mesh* meshes, int32_t n_meshes,
+                                         const double* q_bary, const double* q_w, int32_t n_q,
+                                         int32_t kern, const hmx_params* p,
+                                         const char* cache_path, void* stream, hmx_params* out,
+                                         double* best_ms) {
+  try {
+    HMX_REQUIRE(meshes && q_bary && q_w && out, HMX_EINVAL, "null pointer");
+    HMX_REQUIRE(n_meshes >= 1, HMX_EINVAL, "n_meshes must be >= 1");
+    HMX_REQUIRE(n_q >= 1, HMX_EINVAL, "n_q must be >= 1");
+    const hmx_params base = resolve_base(p);
+    int64_t M = 0;
+    for (int32_t i = 0; i < n_meshes; ++i) M += (int64_t)n_q * meshes[i].n_tri;
+    HMX_REQUIRE(M >= 1, HMX_EINVAL, "the batch has no points");
+    auto build = [&](const hmx_params& q, hmx_op** op) {
+      return hmx_build_batch(meshes, n_meshes, q_bary, q_w, n_q, kern, &q, stream, op);
+    };
+    tune(build, base, class_key(M, kern, base, n_meshes), cache_path, out, best_ms);
     return HMX_OK;
   } catch (const hmx::Error& e) {
     hmx::set_last_error(e.what());

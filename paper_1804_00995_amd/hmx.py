@@ -117,6 +117,8 @@ _sig = {
     "hmx_import_far": [_P, _P, _P, _P],
     "hmx_autotune": [_P, _i64, _i32, _f64, C.POINTER(Params), C.c_char_p, _P, C.POINTER(Params),
                      C.POINTER(_f64)],
+    "hmx_autotune_batch": [_P, _i32, _P, _P, _i32, _i32, C.POINTER(Params), C.c_char_p, _P,
+                           C.POINTER(Params), C.POINTER(_f64)],
 }
 MLP_NPARAMS = 4545
 for _name, _args in _sig.items():
@@ -617,6 +619,26 @@ def autotune(xyzw, kern=HELMHOLTZ, k=0.0, prm: Params | None = None, cache_path=
     path = None if cache_path is None else os.fsencode(cache_path)
     _check(_lib.hmx_autotune(_dev(xyzw, torch.float64, "xyzw"), xyzw.shape[1], kern, float(k),
                              C.byref(prm), path, _stream_ptr(stream), C.byref(out), C.byref(ms)))
+    return out, ms.value
+
+
+def autotune_batch(meshes, bary, w, kern=HELMHOLTZ, prm: Params | None = None, cache_path=None,
+                   stream=None):
+    """Fastest ACA schedule for build_batch(meshes, bary, w, kern, prm): returns (params with the
+    chosen schedule, build ms)."""
+    import torch
+    bary, w = _host_rule(bary, w)
+    prm = prm or params()
+    arr = (Mesh * len(meshes))()
+    for i, (vtx, tri, k) in enumerate(meshes):
+        arr[i] = Mesh(_dev(vtx, torch.float64, "vtx").value, vtx.shape[0],
+                      _dev(tri, torch.int32, "tri").value, tri.shape[0], float(k))
+    out = Params()
+    ms = C.c_double(0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(_lib.hmx_autotune_batch(arr, len(meshes), bary.ctypes.data_as(_P), w.ctypes.data_as(_P),
+                                   bary.shape[0], kern, C.byref(prm), path, _stream_ptr(stream),
+                                   C.byref(out), C.byref(ms)))
     return out, ms.value
 
 
