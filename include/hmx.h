@@ -391,7 +391,7 @@ typedef struct {
   int64_t dense_far_entries;
   int64_t max_rank, sum_rank;
   int64_t overflow_blocks; /* blocks moved to a larger slot, or continued in a later round */
-  int64_t bytes;           /* device bytes held by the operator */
+  int64_t bytes;           /* device bytes held by the operator (slot pools trimmed to use) */
   int32_t precision, is_dense;
   double t_tree_ms, t_blocks_ms, t_near_ms, t_aca_ms, t_total_ms; /* build phases (events) */
   int64_t kernel_evals;    /* Green-kernel evaluations spent in the build */
@@ -410,6 +410,11 @@ typedef struct {
   int64_t row_begin, row_end; /* rows held, in cluster positions (all rows: 0, n_points) */
   int64_t n_rows, n_cols;     /* product shape: y has n_rows entries, x has n_cols (n_points
                                  both, except for hmx_build_rect operators: Mt and Ms) */
+  int64_t pool_reserved_bytes; /* factor-slot pools reserved during the build (the generic
+                                  estimate, or the learned layout's predictions, plus any
+                                  continuation pools); after ACA each pool is trimmed to the
+                                  slots it handed out (factor_bytes), the rest going back to the
+                                  library's allocator for later buffers */
 } hmx_info_t;
 
 /* Sizes, counts and build timings of an operator. */

@@ -636,6 +636,7 @@ hmx_status hmx_info(const hmx_op* op, hmx_info_t* out) {
   out->row_end = op->dense ? op->M : op->row_end;
   out->n_rows = op->rows;
   out->n_cols = op->cols;
+  out->pool_reserved_bytes = op->pool_reserved_bytes;
   return HMX_OK;
 }
 

@@ -427,6 +427,7 @@ void build_far(hmx_op* op, hipStream_t s) {
   gcap = std::max<int64_t>(gcap, 1);
   wl("descriptors built: blocks, pool entries", (double)nf, (double)gcap);
   DevBuf<T> gpool(gcap);
+  op->pool_reserved_bytes = gcap * (int64_t)sizeof(T);
   wl("pool allocated (GiB)", (double)gcap * sizeof(T) / (1 << 30));
   DevBuf<uint8_t> flags(std::max<int64_t>(flag_bytes, 1));
   DevBuf<int32_t> rank(nf1), ipiv(nf1), status(nf1);
@@ -602,10 +603,13 @@ void build_far(hmx_op* op, hipStream_t s) {
       int64_t ncap = std::min<int64_t>(quantize_up(std::max<int64_t>(need, min_pool)),
                                        quantize_down((int64_t)(0.6 * (double)free_b) / (int64_t)sizeof(T)));
       HMX_REQUIRE(ncap > 0, HMX_ENOMEM, "device memory exhausted during ACA");
-      used_old += std::min<int64_t>((int64_t)read1(gtop.p, s), gcap);
+      const int64_t top = std::min<int64_t>((int64_t)read1(gtop.p, s), gcap);
+      used_old += top;
       wl("round: blocks left, new pool entries", (double)list.size(), (double)ncap);
+      gpool.shrink(top);  // the retired pool keeps the slots it handed out
       old_pools.push_back(std::move(gpool));
       gpool.alloc(ncap);
+      op->pool_reserved_bytes += ncap * (int64_t)sizeof(T);
       wl("round: pool allocated");
       gcap = ncap;
       fill_i64((int64_t*)gtop.p, 0, 1, s);
@@ -684,7 +688,9 @@ void build_far(hmx_op* op, hipStream_t s) {
                          op->W.p, op->kern, op->kpt.p, (T*)op->dense_pool.p, nullptr, s);
     HMX_HIP(hipStreamSynchronize(s));
   }
-  // keep the pools (they hold the factors)
+  // keep the pools (they hold the factors), trimmed to the slots handed out: the reserve above
+  // them goes back to the allocator
+  gpool.shrink(std::min(h.used, gcap));
   op->far_pools.clear();
   {
     DevBuf<unsigned char> g;

@@ -33,10 +33,12 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::hmx::Error(code, msg); \
   } while (0)
 
-// Device memory: a caching allocator (freed blocks are kept per size class and reused, so that
+// Device memory: a caching allocator (freed buffers stay mapped and are reused, so that
 // repeated builds do not map and unmap memory; dev_free waits for the device first, as hipFree
-// does).  dev_release_cache returns the cached blocks to the runtime.
+// does).  dev_shrink keeps the first `bytes` of a buffer and hands the rest to later
+// allocations; dev_release_cache returns the entirely free blocks to the runtime.
 void* dev_alloc(size_t bytes);
+size_t dev_shrink(void* p, size_t bytes);
 void dev_free(void* p);
 void dev_release_cache();
 size_t dev_cached_bytes();  // bytes of free blocks the cache holds on the current device
@@ -69,6 +71,13 @@ struct DevBuf {
     if (p) dev_free(p);
     p = nullptr;
     n = 0;
+  }
+  // Keeps the first `count` elements (at least one) and gives the rest back to the allocator.
+  void shrink(size_t count) {
+    count = count < 1 ? 1 : count;
+    if (!p || count >= n) return;
+    dev_shrink(p, count * sizeof(T));
+    n = count;
   }
   size_t bytes() const { return n * sizeof(T); }
   T* get() const { return p; }
@@ -396,7 +405,7 @@ struct hmx_op {
   // far field
   int64_t n_far = 0, far_entries = 0, dense_far = 0, dense_far_entries = 0, max_rank = 0,
           sum_rank = 0, overflow_blocks = 0, t_len = 0, pool_used_bytes = 0,
-          predicted_entries = 0;
+          pool_reserved_bytes = 0, predicted_entries = 0;
   hmx::DevBuf<int2> farL;
   hmx::DevBuf<hmx::FarRec> far;
   std::vector<hmx::DevBuf<unsigned char>> far_pools;  // factor slots (ACA writes in place)

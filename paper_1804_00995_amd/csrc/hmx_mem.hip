@@ -1,23 +1,51 @@
 // hmx_mem.hip -- caching device allocator behind DevBuf.
 //
-// Blocks are rounded up (512 B below 1 MiB, 2 MiB above) and, when freed, kept in a per-device
-// free list keyed by size.  An allocation takes the smallest cached block that is large enough
-// and at most twice the request; otherwise it calls hipMalloc, and on failure releases the
-// cache and retries once.  A free first waits for the device (the block may still be read by
-// queued work), as hipFree does, but keeps the mapping.
+// Per device, a SegmentCache (hmx_segcache.h) over hipMalloc'd blocks: sizes are rounded (512 B
+// below 1 MiB, 2 MiB above); a freed buffer stays mapped and serves a later request of at most
+// twice its size; a buffer sized from an estimate can be shrunk to what it used, its tail then
+// serving later requests; on hipMalloc failure the entirely free blocks are released and the
+// call retried once.  A free or shrink first waits for the device (the memory may still be read
+// by queued work), as hipFree does, but keeps the mapping.
 #include <map>
+#include <memory>
 #include <mutex>
-#include <unordered_map>
 
 #include "hmx_host.h"
+#include "hmx_segcache.h"
 
 namespace hmx {
 namespace {
 
+struct HipBackend {
+  void* alloc(size_t sz) {
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, sz);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    if (e != hipSuccess) hip_fail(e, "hipMalloc", __FILE__, __LINE__);
+    return p;
+  }
+  void* alloc_or_throw(size_t sz) {
+    HMX_HIP(hipDeviceSynchronize());
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) hip_fail(e, "hipMalloc", __FILE__, __LINE__);
+    return p;
+  }
+  void release(void* p) { (void)hipFree(p); }
+};
+
 struct Cache {
   std::mutex mu;
-  std::unordered_map<void*, std::pair<int, size_t>> live;  // block -> (device, size)
-  std::map<int, std::multimap<size_t, void*>> per_dev;
+  std::map<int, std::unique_ptr<SegmentCache<HipBackend>>> per_dev;
+  std::map<void*, int> owner;  // live buffer -> device
+  SegmentCache<HipBackend>& dev(int d) {
+    auto& c = per_dev[d];
+    if (!c) c = std::make_unique<SegmentCache<HipBackend>>(HipBackend{});
+    return *c;
+  }
 };
 
 Cache& cache() {
@@ -25,52 +53,32 @@ Cache& cache() {
   return *c;
 }
 
-size_t round_size(size_t b) {
-  if (b <= (1u << 20)) return (b + 511) & ~size_t(511);
-  const size_t g = size_t(2) << 20;
-  return (b + g - 1) / g * g;
-}
-
-void release_locked(Cache& c, int dev) {
-  auto& fl = c.per_dev[dev];
-  for (auto& kv : fl) (void)hipFree(kv.second);
-  fl.clear();
+int current_device() {
+  int dev = 0;
+  HMX_HIP(hipGetDevice(&dev));
+  return dev;
 }
 
 }  // namespace
 
 void* dev_alloc(size_t bytes) {
   if (bytes == 0) return nullptr;
-  int dev = 0;
-  HMX_HIP(hipGetDevice(&dev));
-  const size_t sz = round_size(bytes);
+  const int dev = current_device();
   Cache& c = cache();
-  {
-    std::lock_guard<std::mutex> g(c.mu);
-    auto& fl = c.per_dev[dev];
-    auto it = fl.lower_bound(sz);
-    if (it != fl.end() && it->first <= 2 * sz) {
-      void* p = it->second;
-      c.live[p] = {dev, it->first};
-      fl.erase(it);
-      return p;
-    }
-  }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, sz);
-  if (e == hipErrorOutOfMemory) {
-    (void)hipGetLastError();
-    {
-      std::lock_guard<std::mutex> g(c.mu);
-      HMX_HIP(hipDeviceSynchronize());
-      release_locked(c, dev);
-    }
-    e = hipMalloc(&p, sz);
-  }
-  if (e != hipSuccess) hip_fail(e, "hipMalloc", __FILE__, __LINE__);
   std::lock_guard<std::mutex> g(c.mu);
-  c.live[p] = {dev, sz};
+  void* p = c.dev(dev).alloc(bytes);
+  c.owner[p] = dev;
   return p;
+}
+
+size_t dev_shrink(void* p, size_t bytes) {
+  if (!p) return 0;
+  Cache& c = cache();
+  (void)hipDeviceSynchronize();
+  std::lock_guard<std::mutex> g(c.mu);
+  auto it = c.owner.find(p);
+  HMX_REQUIRE(it != c.owner.end(), HMX_EINTERNAL, "dev_shrink of a buffer the cache does not hold");
+  return c.dev(it->second).shrink(p, bytes);
 }
 
 void dev_free(void* p) {
@@ -78,13 +86,13 @@ void dev_free(void* p) {
   Cache& c = cache();
   (void)hipDeviceSynchronize();
   std::lock_guard<std::mutex> g(c.mu);
-  auto it = c.live.find(p);
-  if (it == c.live.end()) {
+  auto it = c.owner.find(p);
+  if (it == c.owner.end()) {
     (void)hipFree(p);
     return;
   }
-  c.per_dev[it->second.first].emplace(it->second.second, p);
-  c.live.erase(it);
+  c.dev(it->second).free(p);
+  c.owner.erase(it);
 }
 
 size_t dev_cached_bytes() {
@@ -92,9 +100,7 @@ size_t dev_cached_bytes() {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   Cache& c = cache();
   std::lock_guard<std::mutex> g(c.mu);
-  size_t b = 0;
-  for (const auto& kv : c.per_dev[dev]) b += kv.first;
-  return b;
+  return c.dev(dev).free_bytes();
 }
 
 void dev_release_cache() {
@@ -103,7 +109,7 @@ void dev_release_cache() {
   Cache& c = cache();
   (void)hipDeviceSynchronize();
   std::lock_guard<std::mutex> g(c.mu);
-  release_locked(c, dev);
+  c.dev(dev).release();
 }
 
 }  // namespace hmx

@@ -68,7 +68,7 @@ class Info(C.Structure):
         ("kernel_evals", C.c_int64), ("factor_bytes", C.c_int64), ("predicted_entries", C.c_int64),
         ("aca_blocks", C.c_int64 * 4), ("aca_ms", C.c_double * 4), ("aca_bytes", C.c_int64 * 4),
         ("aca_rounds", C.c_int32), ("row_begin", C.c_int64), ("row_end", C.c_int64),
-        ("n_rows", C.c_int64), ("n_cols", C.c_int64)]
+        ("n_rows", C.c_int64), ("n_cols", C.c_int64), ("pool_reserved_bytes", C.c_int64)]
 
     def as_dict(self):
         d = {}
