@@ -158,9 +158,15 @@ def rooflines(info, aca, mv_ms, M, elem, precision):
         "roofline_matvec": {"bound": "hbm", "achieved": round(mv_gbs, 1), "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(mv_gbs / HBM_PEAK_GBS, 4),
                             "bytes_per_product": mv_bytes},
-        "aca_classes": {"blocks": info["aca_blocks"],
+        "aca_classes": {"order": ["large (m + n >= aca_big_mn)", "middle", "wavefront (m, n <= 64)",
+                                  "small (m + n < aca_small_mn)"],
+                        "blocks": info["aca_blocks"],
                         "first_launch_ms": [round(t, 3) for t in info["aca_ms"]],
-                        "algorithmic_bytes": info["aca_bytes"]},
+                        "algorithmic_bytes": info["aca_bytes"],
+                        "algorithmic_gb_per_s": [round(b / (t * 1e-3) / 1e9, 1) if t > 0 and b > 0 else None
+                                                 for b, t in zip(info["aca_bytes"], info["aca_ms"])],
+                        "frac_of_peak": [round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t > 0 and b > 0 else None
+                                         for b, t in zip(info["aca_bytes"], info["aca_ms"])]},
     }
 
 
@@ -199,7 +205,8 @@ def run_sphere(args, torch, oracle, hmx, I):
     prec = hmx.FP64 if args.precision == "fp64" else hmx.FP32_MIXED
     cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
     reg = args.regularize == "on"
-    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec, regularize=int(reg))
+    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec, regularize=int(reg),
+                     aca_serial=int(args.aca_serial == "on"))
     x_h = I.complex_vector(M, 0)
     vd, fd = torch.from_numpy(v).to(dev), torch.from_numpy(f).to(dev)
     xd = torch.from_numpy(x_h).to(cdt).to(dev)
@@ -1026,6 +1033,8 @@ def main():
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-one-core", choices=["on", "off"], default="off",
                     help="sphere workload: also time the oracle on one core (about a minute)")
+    ap.add_argument("--aca-serial", choices=["on", "off"], default="off",
+                    help="sphere workload: run the ACA classes one after the other (schedule knob)")
     ap.add_argument("--regularize", choices=["on", "off"], default="off",
                     help="sphere workload: near field with the singular correction")
     ap.add_argument("--train-epochs", type=int, default=60,
