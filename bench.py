@@ -142,8 +142,9 @@ def product_ms(op, xd, y, stream, reps):
     return float(np.median(times))
 
 
-def rooflines(info, aca, mv_ms, M, elem, precision):
-    stored = info["near_entries"] + info["far_entries"] + info["dense_far_entries"]
+def rooflines(info, aca, mv_ms, M, elem, precision, near_stored=True):
+    # bytes a product reads: the stored entries (the near blocks only when stored) and vectors
+    stored = (info["near_entries"] if near_stored else 0) + info["far_entries"] + info["dense_far_entries"]
     mv_bytes = elem * (stored + 4 * M) + 8 * M
     mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
     aca_ms = float(np.mean([a[0] for a in aca])) if aca else info["aca_ms"][0]
@@ -206,7 +207,8 @@ def run_sphere(args, torch, oracle, hmx, I):
     cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
     reg = args.regularize == "on"
     prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec, regularize=int(reg),
-                     aca_serial=int(args.aca_serial == "on"))
+                     aca_serial=int(args.aca_serial == "on"),
+                     near_mode=int(args.near_mode == "otf"))
     x_h = I.complex_vector(M, 0)
     vd, fd = torch.from_numpy(v).to(dev), torch.from_numpy(f).to(dev)
     xd = torch.from_numpy(x_h).to(cdt).to(dev)
@@ -270,7 +272,8 @@ def run_sphere(args, torch, oracle, hmx, I):
                             ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
         "sizes": sizes(info),
     }
-    extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision))
+    extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision,
+                           near_stored=args.near_mode == "stored"))
     # kernel evaluations per second by phase: near-field assembly (its phase time includes the
     # block bookkeeping), and ACA rows and columns; the ALU ceiling of one evaluation beside them
     near_s, aca_s = info["t_near_ms"] / 1e3, info["t_aca_ms"] / 1e3
@@ -283,7 +286,8 @@ def run_sphere(args, torch, oracle, hmx, I):
     op.close()
     config = {"workload": f"unit icosphere L{args.level} ({f.shape[0]} triangles, {M} points), "
                           f"Helmholtz k={args.k:g}, leaf 64, eta 1.5, ACA tol 1e-3, {args.precision}"
-                          + (", singular correction (radius 2)" if reg else "")}
+                          + (", singular correction (radius 2)" if reg else "")
+                          + (", near field computed in the product" if args.near_mode == "otf" else "")}
     line(args, ms_step, args.precision, config, extra)
 
 
@@ -1033,6 +1037,9 @@ def main():
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-one-core", choices=["on", "off"], default="off",
                     help="sphere workload: also time the oracle on one core (about a minute)")
+    ap.add_argument("--near-mode", choices=["stored", "otf"], default="stored",
+                    help="sphere workload: near blocks stored in the build, or computed in each "
+                         "product (near_mode 1)")
     ap.add_argument("--aca-serial", choices=["on", "off"], default="off",
                     help="sphere workload: run the ACA classes one after the other (schedule knob)")
     ap.add_argument("--regularize", choices=["on", "off"], default="off",

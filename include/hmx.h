@@ -137,12 +137,21 @@ typedef struct {
    * near-field blocks: the product costs the same with or without it. */
   int32_t regularize; /* 0 (default) or 1 */
   double reg_radius;  /* > 0 (default 2) */
+  /* Near field (Section 4: terms may be stored or computed on the fly): 0 (default) assembles
+   * the near blocks once in the build and the product reads them; 1 stores nothing and the
+   * product evaluates each near entry G(x_i, y_j) w_j again, from source tiles staged in LDS
+   * (the same entries, so the same product up to rounding; no near-field memory, no assembly
+   * time, about one kernel evaluation per near entry per product).  1 needs regularize = 0
+   * (HMX_EUNSUPPORTED otherwise: the correction lives in stored blocks); ignored by dense
+   * operators (tol <= 0), whose product is always computed on the fly.  With near_mode = 1,
+   * hmx_matvec_multi applies the operator one vector at a time. */
+  int32_t near_mode;
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,
  * initial_rank 16, force_pred_scale 1, no rank cap, no pool limit, ACA schedule 4096 / 1024 /
  * concurrent / arenas, one row share, far blocks up to 12288 points, no singular correction
- * (reg_radius 2). */
+ * (reg_radius 2), stored near field. */
 hmx_status hmx_params_default(hmx_params* p);
 
 typedef struct hmx_op hmx_op; /* opaque, library-owned; free with hmx_destroy */

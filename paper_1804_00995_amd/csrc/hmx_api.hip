@@ -72,6 +72,7 @@ void defaults(hmx_params* p) {
   p->max_far_mn = 12288;
   p->regularize = 0;
   p->reg_radius = 2.0;
+  p->near_mode = 0;
 }
 
 hmx_params resolve(const hmx_params* in) {
@@ -122,6 +123,10 @@ hmx_params resolve(const hmx_params* in) {
               "reg_radius must be finite and > 0");
   HMX_REQUIRE(p.regularize == 0 || p.tol > 0, HMX_EUNSUPPORTED,
               "the singular correction needs an H-matrix operator (tol > 0)");
+  HMX_REQUIRE(p.near_mode == 0 || p.near_mode == 1, HMX_EINVAL, "near_mode must be 0 or 1");
+  HMX_REQUIRE(p.near_mode == 0 || p.regularize == 0, HMX_EUNSUPPORTED,
+              "near_mode 1 (near field computed in the product) cannot carry the singular "
+              "correction, which is assembled into stored near blocks");
   return p;
 }
 
@@ -355,10 +360,11 @@ static void enqueue_matvec(const hmx_op* op, const void* x, void* y, hipStream_t
     T* t = (T*)op->tbuf.p;
     launch_gather<T>((const T*)x, op->perm.p, xp, op->M, op->x_off, s);
     launch_far_vt<T>(op->far.p, op->n_far, xp, t, s);
+    const NearOtfArgs otf{op->X.p, op->Y.p, op->Z.p, op->W.p, op->kern, op->kpt.p};
     launch_leaf_apply<T>(op->n_leaves, op->leaves.p, op->nbegin.p, op->nend.p, op->near_ptr.p,
                          op->near_sb.p, op->near_n.p, op->near_off.p, (const T*)op->near_pool.p,
                          op->far_ptr.p, op->far_list.p, op->far.p, t, xp, op->perm.p, op->rows,
-                         (T*)y, s);
+                         (T*)y, s, op->p.near_mode == 1 ? &otf : nullptr);
   };
   if (op->prec == HMX_FP64) run(double2{});
   else run(float2{});
@@ -413,7 +419,8 @@ static void enqueue_multi(const hmx_op* op, int32_t nr, const void* const* x, vo
     T* tm = xpm + 4 * op->M;
     for (int r0 = 0; r0 < nr;) {
       const int left = nr - r0;
-      const int g = op->dense ? 1 : (left >= 4 ? 4 : left >= 2 ? 2 : 1);
+      // (an operator whose near field is computed in the product takes one vector at a time)
+      const int g = op->dense || op->p.near_mode == 1 ? 1 : (left >= 4 ? 4 : left >= 2 ? 2 : 1);
       if (g == 1) {
         enqueue_matvec(op, x[r0], y[r0], s);
       } else {
@@ -1105,11 +1112,12 @@ namespace {
 //   T = i k sum_d Psi_d^T W K Psi_d - (i / k) D^T W K D      (K the single layer)
 //   NxK x = <n x psi_i, c>,  c_e = G_{e+1} u_{e+2} - G_{e+2} u_{e+1}  (G_d the gradient kernels)
 // y_r = K x_r for nr vectors: one several-vector product on an H-matrix operator (its entries
-// read once), one product per vector on a dense one
+// read once), one product per vector on a dense one or on one whose near field is computed in
+// the product
 template <class T>
 void matvec_n(const hmx_rwg* R, const hmx_op* op, int nr, const T* const* x, T* const* y,
               hipStream_t s) {
-  if (op->dense) {
+  if (op->dense || op->p.near_mode == 1) {
     for (int r = 0; r < nr; ++r) enqueue_matvec(op, x[r], y[r], s);
     return;
   }

@@ -309,6 +309,7 @@ void build_near(hmx_op* op, hipStream_t s) {
   scan_excl_i64(sizes.p, op->near_off.p, nn, s);
   scan_excl_i64(lcnt.p, op->near_ptr.p, nl, s);
   op->near_entries = read1(op->near_off.p + nn, s);
+  if (op->p.near_mode == 1) return;  // the product evaluates the near blocks itself
   size_t bytes = (size_t)op->near_entries * sizeof(T);
   if (op->p.pool_limit_bytes > 0 && (int64_t)bytes > op->p.pool_limit_bytes)
     throw Error(HMX_ENOMEM, "near field exceeds pool_limit_bytes");

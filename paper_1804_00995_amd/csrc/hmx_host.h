@@ -351,13 +351,23 @@ void launch_gather(const T* x, const int32_t* perm, T* xp, int64_t M, int64_t x_
                    hipStream_t s);
 template <class T>
 void launch_far_vt(const FarRec* rec, int64_t nf, const T* xp, T* t, hipStream_t s);
+// The points and kernel of an operator whose near field is computed in the product.
+struct NearOtfArgs {
+  const double* X;
+  const double* Y;
+  const double* Z;
+  const double* W;
+  int kern;
+  const double* kp;
+};
+// otf: null for stored near blocks (near_pool), else the near field is evaluated in the kernel
 template <class T>
 void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegin,
                        const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
                        const int32_t* near_n, const int64_t* near_off, const T* near_pool,
                        const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
                        const T* tbuf, const T* xp, const int32_t* perm, int64_t y_rows, T* y,
-                       hipStream_t s);
+                       hipStream_t s, const NearOtfArgs* otf = nullptr);
 template <class T>
 void launch_dense_otf(const double* X, const double* Y, const double* Z, const double* W,
                       int64_t rows, int64_t so, int64_t cols, int kern, double k, const T* x,

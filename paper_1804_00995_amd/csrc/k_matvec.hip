@@ -128,7 +128,23 @@ void launch_far_vt(const FarRec* rec, int64_t nf, const T* xp, T* t, hipStream_t
 
 constexpr int MAX_LEAF_CHUNKS = 4;  // rows per leaf <= 4 * 64
 
-template <class T>
+// The near field computed in the product (near_mode 1): the points and the kernel.
+struct NearOtf {
+  const double* X;
+  const double* Y;
+  const double* Z;
+  const double* W;
+  int kern;
+  const double* kp;
+};
+
+// OTF = false: near blocks read from near_pool.  OTF = true: near blocks evaluated here.  For each
+// near block of the leaf in turn, the workgroup stages the block's source points and x entries
+// in LDS (one per thread), then wave w evaluates the sources j = w, w + 4, ... against all of
+// the leaf's rows (targets kept in registers), accumulating K_ij x_j; the far blocks follow as
+// in the stored case.  Each row's terms are summed per wave in a fixed order, then over the
+// waves, so the product is deterministic.
+template <class T, bool OTF>
 __global__ void __launch_bounds__(WG) leaf_apply_kernel(
     const int32_t* __restrict__ leaves, const int32_t* __restrict__ nbegin,
     const int32_t* __restrict__ nend, const int64_t* __restrict__ near_ptr,
@@ -137,12 +153,12 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
     const int64_t* __restrict__ far_ptr, const int32_t* __restrict__ far_list,
     const FarRec* __restrict__ far, const T* __restrict__ tbuf,
     const T* __restrict__ xp, const int32_t* __restrict__ perm, int64_t y_rows,
-    T* __restrict__ y) {
+    T* __restrict__ y, NearOtf otf) {
   __shared__ T part[NWAVE][MAX_LEAF_CHUNKS * WAVE];
   const int leaf = blockIdx.x;
   const int node = leaves[leaf];
   const int tb = nbegin[node], m = nend[node] - tb;
-  const int64_t n0 = near_ptr[leaf], nn = near_ptr[leaf + 1] - n0;
+  const int64_t n0 = near_ptr[leaf], nn_all = near_ptr[leaf + 1] - n0;
   const int64_t f0 = far_ptr[leaf], nfar = far_ptr[leaf + 1] - f0;
   // the wave index is uniform across the wave: marked so, the block descriptors and the
   // x and t entries, whose addresses depend only on it, are read through scalar loads
@@ -152,11 +168,51 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
   T acc[MAX_LEAF_CHUNKS];
 #pragma unroll
   for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) acc[c] = czero<T>();
+  int64_t nn = nn_all;  // near blocks left to the per-wave loops below
+  if constexpr (OTF) {
+    constexpr int TILE = MAX_LEAF_CHUNKS * WAVE;  // a near block's sources (a leaf: <= 256)
+    __shared__ double spt[4][TILE];              // source x, y, z, w
+    __shared__ T sxp[TILE];                      // source entries of x
+    const double k = otf.kp[tb];
+    double tx[MAX_LEAF_CHUNKS], ty[MAX_LEAF_CHUNKS], tz[MAX_LEAF_CHUNKS];
+#pragma unroll
+    for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
+      const int i = min(lane + c * WAVE, m - 1);
+      tx[c] = otf.X[tb + i];
+      ty[c] = otf.Y[tb + i];
+      tz[c] = otf.Z[tb + i];
+    }
+    for (int64_t b = 0; b < nn_all; ++b) {
+      const int64_t blk = n0 + b;
+      const int sb = near_sb[blk], n = near_n[blk];
+      for (int j = threadIdx.x; j < n; j += WG) {
+        spt[0][j] = otf.X[sb + j];
+        spt[1][j] = otf.Y[sb + j];
+        spt[2][j] = otf.Z[sb + j];
+        spt[3][j] = otf.W[sb + j];
+        sxp[j] = xp[sb + j];
+      }
+      __syncthreads();
+      for (int j = w; j < n; j += NWAVE) {
+        const double sx = spt[0][j], sy = spt[1][j], sz = spt[2][j], sw = spt[3][j];
+        const T xj = sxp[j];
+#pragma unroll
+        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
+          if (c < nch) {
+            const T g = eval_entry<T>(otf.kern, k, tx[c], ty[c], tz[c], sx, sy, sz, sw);
+            cfma(acc[c], g, xj);
+          }
+        }
+      }
+      __syncthreads();  // the tile is read by every wave before the next block replaces it
+    }
+    nn = 0;
+  }
   if (nch == 1) {
     // leaves of at most 64 rows (the usual case): one accumulator per lane, so that eight
     // column loads per lane can be in flight without the registers of the general path; lanes
     // past the leaf's rows read row 0 and discard it
-    T a = czero<T>();
+    T a = acc[0];  // (the near field's sum when it was computed above)
     const bool on = lane < m;
     const int i = on ? lane : 0;
     for (int64_t it = w; it < nn + nfar; it += NWAVE) {
@@ -240,10 +296,17 @@ void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegi
                        const int32_t* near_n, const int64_t* near_off, const T* near_pool,
                        const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
                        const T* tbuf, const T* xp, const int32_t* perm, int64_t y_rows, T* y,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(leaf_apply_kernel<T>, dim3(n_leaves), dim3(WG), 0, s, leaves, nbegin, nend,
-                     near_ptr, near_sb, near_n, near_off, near_pool, far_ptr, far_list, far, tbuf,
-                     xp, perm, y_rows, y);
+                       hipStream_t s, const NearOtfArgs* otf) {
+  NearOtf o{};
+  if (otf) o = NearOtf{otf->X, otf->Y, otf->Z, otf->W, otf->kern, otf->kp};
+  if (otf)
+    hipLaunchKernelGGL((leaf_apply_kernel<T, true>), dim3(n_leaves), dim3(WG), 0, s, leaves,
+                       nbegin, nend, near_ptr, near_sb, near_n, near_off, near_pool, far_ptr,
+                       far_list, far, tbuf, xp, perm, y_rows, y, o);
+  else
+    hipLaunchKernelGGL((leaf_apply_kernel<T, false>), dim3(n_leaves), dim3(WG), 0, s, leaves,
+                       nbegin, nend, near_ptr, near_sb, near_n, near_off, near_pool, far_ptr,
+                       far_list, far, tbuf, xp, perm, y_rows, y, o);
   HMX_LAUNCHED();
 }
 
@@ -586,7 +649,7 @@ void launch_dense_otf(const double* X, const double* Y, const double* Z, const d
                                      const int64_t*, const int32_t*, const int32_t*,             \
                                      const int64_t*, const T*, const int64_t*, const int32_t*,   \
                                      const FarRec*, const T*, const T*, const int32_t*, int64_t, \
-                                     T*, hipStream_t);                                           \
+                                     T*, hipStream_t, const NearOtfArgs*);                       \
   template void launch_dense_otf<T>(const double*, const double*, const double*, const double*,  \
                                     int64_t, int64_t, int64_t, int, double, const T*, T*, T*,    \
                                     hipStream_t);                                                \

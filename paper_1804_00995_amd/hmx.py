@@ -56,6 +56,7 @@ class Params(C.Structure):
         ("aca_wave", C.c_int32),
         ("regularize", C.c_int32),
         ("reg_radius", C.c_double),
+        ("near_mode", C.c_int32),
     ]
 
 
