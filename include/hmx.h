@@ -303,7 +303,10 @@ typedef struct {
  * concatenated in mesh order; each slice is that mesh's product K_i x_i.  meshes host array.
  * Requires p->tol > 0 (the dense form is the single-mesh hmx_build).  Errors: as hmx_build for
  * each mesh, HMX_EINVAL for n_meshes < 1 or tol <= 0, HMX_EUNSUPPORTED for more than 2^23 - 1
- * points in total.  Synchronous. */
+ * points in total.  Synchronous.
+ * There is no product over an array of separate operators: the batch is one operator, so that
+ * hmx_matvec (and a graph of it) applies every mesh in one launch set, and hmx_mesh_offsets
+ * gives each mesh's slice of x and y. */
 hmx_status hmx_build_batch(const hmx_mesh* meshes, int32_t n_meshes, const double* q_bary,
                            const double* q_w, int32_t n_q, int32_t kern, const hmx_params* p,
                            void* stream, hmx_op** out);
