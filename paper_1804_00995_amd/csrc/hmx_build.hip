@@ -427,7 +427,8 @@ void build_far(hmx_op* op, hipStream_t s) {
   if (op->p.force_pool_bytes > 0) gcap = op->p.force_pool_bytes / (int64_t)sizeof(T);
   gcap = std::max<int64_t>(gcap, 1);
   wl("descriptors built: blocks, pool entries", (double)nf, (double)gcap);
-  DevBuf<T> gpool(gcap);
+  DevBuf<T> gpool;
+  gpool.alloc_block(gcap);  // trimmed after ACA: a block of its own
   op->pool_reserved_bytes = gcap * (int64_t)sizeof(T);
   wl("pool allocated (GiB)", (double)gcap * sizeof(T) / (1 << 30));
   DevBuf<uint8_t> flags(std::max<int64_t>(flag_bytes, 1));
@@ -609,7 +610,7 @@ void build_far(hmx_op* op, hipStream_t s) {
       wl("round: blocks left, new pool entries", (double)list.size(), (double)ncap);
       gpool.shrink(top);  // the retired pool keeps the slots it handed out
       old_pools.push_back(std::move(gpool));
-      gpool.alloc(ncap);
+      gpool.alloc_block(ncap);
       op->pool_reserved_bytes += ncap * (int64_t)sizeof(T);
       wl("round: pool allocated");
       gcap = ncap;

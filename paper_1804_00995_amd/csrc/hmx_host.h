@@ -38,6 +38,7 @@ struct Error : std::runtime_error {
 // does).  dev_shrink keeps the first `bytes` of a buffer and hands the rest to later
 // allocations; dev_release_cache returns the entirely free blocks to the runtime.
 void* dev_alloc(size_t bytes);
+void* dev_alloc_block(size_t bytes);  // a block of its own, for a buffer that will be shrunk
 size_t dev_shrink(void* p, size_t bytes);
 void dev_free(void* p);
 void dev_release_cache();
@@ -71,6 +72,13 @@ struct DevBuf {
     if (p) dev_free(p);
     p = nullptr;
     n = 0;
+  }
+  // A buffer that will be shrunk: a block of its own, so that the shrink frees only its tail.
+  void alloc_block(size_t count) {
+    reset();
+    if (count == 0) return;
+    p = (T*)dev_alloc_block(count * sizeof(T));
+    n = count;
   }
   // Keeps the first `count` elements (at least one) and gives the rest back to the allocator.
   void shrink(size_t count) {

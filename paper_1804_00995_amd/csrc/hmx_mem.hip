@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 
 #include "hmx_host.h"
 #include "hmx_segcache.h"
@@ -27,11 +28,21 @@ struct HipBackend {
     if (e != hipSuccess) hip_fail(e, "hipMalloc", __FILE__, __LINE__);
     return p;
   }
-  void* alloc_or_throw(size_t sz) {
+  void* alloc_or_throw(size_t sz, size_t n_blocks, size_t block_bytes, size_t stranded) {
     HMX_HIP(hipDeviceSynchronize());
     void* p = nullptr;
     const hipError_t e = hipMalloc(&p, sz);
-    if (e != hipSuccess) hip_fail(e, "hipMalloc", __FILE__, __LINE__);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      size_t fb = 0, tb = 0;
+      (void)hipMemGetInfo(&fb, &tb);
+      throw Error(e == hipErrorOutOfMemory ? HMX_ENOMEM : HMX_EDEVICE,
+                  "hipMalloc of " + std::to_string(sz) + " bytes failed (" + hipGetErrorString(e) +
+                      "); device free " + std::to_string(fb) + " of " + std::to_string(tb) +
+                      " bytes; the library holds " + std::to_string(n_blocks) + " blocks of " +
+                      std::to_string(block_bytes) + " bytes, " + std::to_string(stranded) +
+                      " of them free beside live buffers");
+    }
     return p;
   }
   void release(void* p) { (void)hipFree(p); }
@@ -67,6 +78,16 @@ void* dev_alloc(size_t bytes) {
   Cache& c = cache();
   std::lock_guard<std::mutex> g(c.mu);
   void* p = c.dev(dev).alloc(bytes);
+  c.owner[p] = dev;
+  return p;
+}
+
+void* dev_alloc_block(size_t bytes) {
+  if (bytes == 0) return nullptr;
+  const int dev = current_device();
+  Cache& c = cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  void* p = c.dev(dev).alloc_block(bytes);
   c.owner[p] = dev;
   return p;
 }

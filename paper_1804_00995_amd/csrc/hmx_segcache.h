@@ -4,7 +4,8 @@
 // A block is one allocation from the backend (hipMalloc on the device).  Each block is cut into
 // consecutive segments, live or free, that cover it exactly.  alloc() hands out a whole free
 // segment (the smallest one of at least the rounded request and at most twice it) or a new
-// block; shrink() keeps the first part of a live segment and frees the rest, so that a buffer
+// block; alloc_block() takes a whole block of about the request's size, for buffers that will be
+// shrunk; shrink() keeps the first part of a live segment and frees the rest, so that a buffer
 // sized from an estimate can give back what it did not use; free() marks a segment free and
 // merges it with free neighbours of the same block; release() returns to the backend the blocks
 // that are entirely free.  Segments never cross blocks, so a block goes back to the backend only
@@ -33,7 +34,9 @@ class SegmentCache {
   explicit SegmentCache(Backend be) : be_(be) {}
 
   // A live segment of at least `bytes` (rounded), or nullptr for 0 bytes.  Throws what the
-  // backend throws when it cannot allocate (after releasing the free blocks once).
+  // backend throws when it cannot allocate (after releasing the free blocks once); the backend
+  // is told how many blocks the cache still holds, their bytes and their unreleasable free
+  // bytes, for its message.
   void* alloc(size_t bytes) {
     if (bytes == 0) return nullptr;
     const size_t sz = seg_round(bytes);
@@ -47,7 +50,36 @@ class SegmentCache {
     char* p = (char*)be_.alloc(sz);
     if (p == nullptr) {
       release();
-      p = (char*)be_.alloc_or_throw(sz);
+      size_t nb = 0, bb = 0, sf = 0;
+      stats(&nb, &bb, &sf);
+      p = (char*)be_.alloc_or_throw(sz, nb, bb, sf);
+    }
+    blocks_[p] = sz;
+    segs_[p] = Seg{p, sz, true};
+    return p;
+  }
+
+  // A block of its own for a buffer that will be shrunk (a pool sized from an estimate): an
+  // entirely free cached block of at least the rounded size and at most 1/8 more, or a new
+  // block of exactly that size.  Shrinking it later leaves free only its own unused tail.
+  void* alloc_block(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    const size_t sz = seg_round(bytes);
+    for (auto it = free_.lower_bound(sz); it != free_.end() && it->first <= sz + sz / 8; ++it) {
+      char* p = it->second;
+      auto b = blocks_.find(p);
+      if (b != blocks_.end() && b->second == it->first) {
+        free_.erase(it);
+        segs_.at(p).live = true;
+        return p;
+      }
+    }
+    char* p = (char*)be_.alloc(sz);
+    if (p == nullptr) {
+      release();
+      size_t nb = 0, bb = 0, sf = 0;
+      stats(&nb, &bb, &sf);
+      p = (char*)be_.alloc_or_throw(sz, nb, bb, sf);
     }
     blocks_[p] = sz;
     segs_[p] = Seg{p, sz, true};
@@ -105,6 +137,24 @@ class SegmentCache {
         ++it;
       }
     }
+  }
+
+  // Blocks, their bytes, and the bytes of free segments in blocks that also hold live ones
+  // (which release() cannot return).
+  void stats(size_t* n_blocks, size_t* block_bytes, size_t* stranded_free) const {
+    size_t nb = 0, bb = 0, sf = 0;
+    for (const auto& b : blocks_) {
+      ++nb;
+      bb += b.second;
+      const Seg& first = segs_.at(b.first);
+      if (!(first.size == b.second && !first.live)) {
+        for (auto it = segs_.find(b.first); it != segs_.end() && it->second.block == b.first; ++it)
+          if (!it->second.live) sf += it->second.size;
+      }
+    }
+    *n_blocks = nb;
+    *block_bytes = bb;
+    *stranded_free = sf;
   }
 
   size_t free_bytes() const {

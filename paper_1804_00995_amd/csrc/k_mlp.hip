@@ -6,11 +6,11 @@
 // parameter vector is W1 (64 x 4) | b1 (64) | W2 (64 x 64) | b2 (64) | W3 (64) | b3 (1), FP32.
 //
 // Training step on a minibatch of B samples (mean squared error):
-//   mlp_fwdbwd: one thread per sample: activations, residual and the back-propagated errors
-//               dL/dz2, dL/dz1, stored per sample (structure of arrays, sample index fastest);
-//   mlp_grad:   one wavefront per parameter: its gradient summed over the batch in a fixed order
-//               (FP64 accumulation), so the result does not depend on scheduling;
-//   mlp_adam:   one thread per parameter: bias-corrected Adam update.
+//   mlp_tile_grad: one wavefront per 16 samples: forward and backward pass with the 64 x 64
+//                  layer on the FP32 matrix cores, and the tile's partial gradient;
+//   mlp_reduce:    one thread per parameter: the tiles' partials summed in a fixed order (FP64),
+//                  so the result does not depend on scheduling;
+//   mlp_adam:      one thread per parameter: bias-corrected Adam update.
 #include "hmx_dev.h"
 #include "hmx_host.h"
 
@@ -98,113 +98,194 @@ void launch_mlp_predict(const float* theta, const float* norm, const float* feat
   HMX_LAUNCHED();
 }
 
-// Per-sample forward and backward pass over samples [b0, b0 + B) of (X, y); X standardized.
-// Cache layout (floats, sample fastest): x[4][B] h1[64][B] h2[64][B] dz1[64][B] dz2[64][B]
-// do[B] r2[B].
-__global__ void __launch_bounds__(WG) mlp_fwdbwd_kernel(const float* __restrict__ theta,
-                                                        const float* __restrict__ X,
-                                                        const float* __restrict__ y, int64_t b0,
-                                                        int B, float* __restrict__ cache) {
-  __shared__ float w[MLP_NPARAMS];
-  for (int q = threadIdx.x; q < MLP_NPARAMS; q += WG) w[q] = theta[q];
-  __syncthreads();
-  const int s = blockIdx.x * WG + threadIdx.x;
-  if (s >= B) return;
-  float* cx = cache;
-  float* ch1 = cx + (int64_t)NI * B;
-  float* ch2 = ch1 + (int64_t)NH * B;
-  float* cd1 = ch2 + (int64_t)NH * B;
-  float* cd2 = cd1 + (int64_t)NH * B;
-  float* cdo = cd2 + (int64_t)NH * B;
-  float* cr2 = cdo + B;
-  const int64_t g = b0 + s;
+// ------------------------------------------------------------------------------ training
+// Minibatch gradient of the mean squared error over samples [b0, b0 + B) of (X, y), X
+// standardized.  One wavefront per tile of 16 samples (a 4096-sample batch is 256 wavefronts,
+// one per CU); lane l works on sample s = l % 16 of the tile and on the 16 hidden units
+//   u(t, g) = 16 (t / 4) + 4 g + (t % 4),  t = 0..15,  g = l / 16,
+// in both hidden layers.  With that assignment the 64 x 64 layer and its transpose run on the
+// FP32 matrix cores (v_mfma_f32_16x16x4f32: A 16 x 4 from lane i + 16 k, B 4 x 16 from lane
+// j + 16 k, D 16 x 16 in lane j + 16 (i / 4), element i % 4) with every operand already in the
+// lane that supplies it:
+//   Z2^T = W2 H1^T      (A = W2 rows, B = the lane's own h1[t], k-step t)
+//   dH1^T = W2^T dZ2^T  (A = W2 columns, B = the lane's own dz2[t]); its D element (m, r) is
+//                        unit u(4 m + r, g), the lane's own z1 unit, so dZ1 needs no movement.
+// The weight gradients sum over the tile's samples: dZ2 and H1 go through LDS (transposed) into
+// gW2 = dZ2^T H1 on the matrix cores; gW1, the biases and W3 sum 16 samples per lane.  Each
+// tile writes its partial gradient (FP32 sums of 16 samples) and its loss sum; mlp_reduce adds
+// the tiles in FP64 in tile order, so the result does not depend on scheduling.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int MLP_TILE = 16;  // samples per wavefront
+
+__device__ __forceinline__ int mlp_unit(int t, int g) { return 16 * (t >> 2) + 4 * g + (t & 3); }
+
+__global__ void __launch_bounds__(WAVE) mlp_tile_grad_kernel(const float* __restrict__ theta,
+                                                             const float* __restrict__ X,
+                                                             const float* __restrict__ y,
+                                                             int64_t b0, int B,
+                                                             float* __restrict__ partial) {
+  __shared__ float sdz2[MLP_TILE][NH + 1];  // dL/dz2 (sample, unit)
+  __shared__ float sh1[MLP_TILE][NH + 1];   // h1 = relu(z1)
+  __shared__ float sdz1[MLP_TILE][NH + 1];  // dL/dz1
+  __shared__ float sh2[MLP_TILE][NH + 1];   // h2 = relu(z2)
+  __shared__ float sx[MLP_TILE][NI];
+  __shared__ float sdo[MLP_TILE], sr2[MLP_TILE];
+  const int l = threadIdx.x, s = l & 15, g = l >> 4;
+  const int tile = blockIdx.x;
+  const int si = tile * MLP_TILE + s;  // sample within the batch
+  const bool valid = si < B;
+  const int64_t gs = b0 + (valid ? si : 0);
+  const float* W1 = theta + OW1;
+  const float* b1 = theta + OB1;
+  const float* W2 = theta + OW2;
+  const float* b2 = theta + OB2;
+  const float* w3 = theta + OW3;
   float x[NI];
 #pragma unroll
-  for (int c = 0; c < NI; ++c) {
-    x[c] = X[4 * g + c];
-    cx[(int64_t)c * B + s] = x[c];
+  for (int c = 0; c < NI; ++c) x[c] = valid ? X[4 * gs + c] : 0.0f;
+  // layer 1 on the lane's 16 units
+  float z1[16], h1[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int u = mlp_unit(t, g);
+    float z = b1[u];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) z = fmaf(W1[u * NI + c], x[c], z);
+    z1[t] = z;
+    h1[t] = fmaxf(z, 0.0f);
   }
-  float z1[NH];
+  // Z2^T = W2 H1^T: output tile m holds units 16 m + i (rows) by the 16 samples (columns)
+  f32x4 z2v[4];
 #pragma unroll
-  for (int j = 0; j < NH; ++j) {
-    float z = w[OB1 + j];
+  for (int m = 0; m < 4; ++m) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int c = 0; c < NI; ++c) z = fmaf(w[OW1 + j * NI + c], x[c], z);
-    z1[j] = z;
-    ch1[(int64_t)j * B + s] = fmaxf(z, 0.0f);
+    for (int t = 0; t < 16; ++t)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(W2[(16 * m + s) * NH + mlp_unit(t, g)], h1[t],
+                                                 acc, 0, 0, 0);
+    z2v[m] = acc;
   }
-  float o = w[OB3];
-  float z2[NH];  // pre-activations, then dL/dz2 in place
+  // z2 of the lane's sample s at unit 16 m + 4 g + r = u(4 m + r, g); output and residual
+  float z2[16], part = 0.0f;
 #pragma unroll
-  for (int j = 0; j < NH; ++j) {
-    float z = w[OB2 + j];
-#pragma unroll
-    for (int c = 0; c < NH; ++c) z = fmaf(w[OW2 + j * NH + c], fmaxf(z1[c], 0.0f), z);
-    z2[j] = z;
-    const float h2 = fmaxf(z, 0.0f);
-    ch2[(int64_t)j * B + s] = h2;
-    o = fmaf(w[OW3 + j], h2, o);
+  for (int t = 0; t < 16; ++t) {
+    const int u = mlp_unit(t, g);
+    z2[t] = z2v[t >> 2][t & 3] + b2[u];
+    part = fmaf(w3[u], fmaxf(z2[t], 0.0f), part);
   }
-  const float r = o - y[g];
-  const float dout = 2.0f * r / (float)B;
-  cdo[s] = dout;
-  cr2[s] = r * r;
+  part += __shfl_xor(part, 16, WAVE);
+  part += __shfl_xor(part, 32, WAVE);
+  const float o = part + theta[OB3];
+  const float r = valid ? o - y[gs] : 0.0f;
+  const float dout = 2.0f * r / (float)B;  // d(mean of r^2)/do
+  // dL/dz2 in the lane's layout (it is also the B operand of the next product)
+  float dz2[16];
 #pragma unroll
-  for (int j = 0; j < NH; ++j) {
-    z2[j] = z2[j] > 0.0f ? dout * w[OW3 + j] : 0.0f;
-    cd2[(int64_t)j * B + s] = z2[j];
+  for (int t = 0; t < 16; ++t) {
+    const int u = mlp_unit(t, g);
+    dz2[t] = z2[t] > 0.0f ? dout * w3[u] : 0.0f;
+    sdz2[s][u] = dz2[t];
+    sh1[s][u] = h1[t];
+    sh2[s][u] = fmaxf(z2[t], 0.0f);
   }
+  // dH1^T = W2^T dZ2^T: output tile m holds inputs 16 m + i (rows) by the samples
 #pragma unroll
-  for (int i = 0; i < NH; ++i) {
-    float d = 0.0f;
+  for (int m = 0; m < 4; ++m) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int j = 0; j < NH; ++j) d = fmaf(z2[j], w[OW2 + j * NH + i], d);
-    cd1[(int64_t)i * B + s] = z1[i] > 0.0f ? d : 0.0f;
+    for (int t = 0; t < 16; ++t)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(W2[mlp_unit(t, g) * NH + 16 * m + s], dz2[t],
+                                                 acc, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = 4 * m + q;  // element q of tile m is unit u(t, g), the lane's z1[t]
+      sdz1[s][mlp_unit(t, g)] = z1[t] > 0.0f ? acc[q] : 0.0f;
+    }
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int c = 0; c < NI; ++c) sx[s][c] = x[c];
+    sdo[s] = dout;
+    sr2[s] = r * r;
+  }
+  __syncthreads();
+  float* out = partial + (int64_t)tile * (MLP_NPARAMS + 1);
+  // gW2 = dZ2^T H1 (64 x 64, summed over the 16 samples): 16 output tiles, k = 4 samples
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+    for (int nv = 0; nv < 4; ++nv) {
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sdz2[4 * k + g][16 * mu + s],
+                                                   sh1[4 * k + g][16 * nv + s], acc, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[OW2 + (16 * mu + 4 * g + q) * NH + 16 * nv + s] = acc[q];
+    }
+  }
+  // lane l = unit u: W1 row, biases and W3 over the 16 samples
+  {
+    const int u = l;
+    float gw1[NI] = {0.0f, 0.0f, 0.0f, 0.0f}, gb1 = 0.0f, gb2 = 0.0f, gw3 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < MLP_TILE; ++q) {
+      const float d1 = sdz1[q][u];
+#pragma unroll
+      for (int c = 0; c < NI; ++c) gw1[c] = fmaf(d1, sx[q][c], gw1[c]);
+      gb1 += d1;
+      gb2 += sdz2[q][u];
+      gw3 = fmaf(sdo[q], sh2[q][u], gw3);
+    }
+#pragma unroll
+    for (int c = 0; c < NI; ++c) out[OW1 + u * NI + c] = gw1[c];
+    out[OB1 + u] = gb1;
+    out[OB2 + u] = gb2;
+    out[OW3 + u] = gw3;
+  }
+  if (l == 0) {
+    float gb3 = 0.0f, loss = 0.0f;
+#pragma unroll
+    for (int q = 0; q < MLP_TILE; ++q) {
+      gb3 += sdo[q];
+      loss += sr2[q];
+    }
+    out[OB3] = gb3;
+    out[MLP_NPARAMS] = loss;
   }
 }
 
-// Gradient of parameter p (p < MLP_NPARAMS) summed over the batch; p == MLP_NPARAMS gives the
-// batch loss (1/B) sum r^2.  One wavefront per output value, fixed summation order.
-__global__ void __launch_bounds__(WG) mlp_grad_kernel(const float* __restrict__ cache, int B,
-                                                      float* __restrict__ grad) {
-  const int p = blockIdx.x * NWAVE + threadIdx.x / WAVE;
-  const int lane = threadIdx.x & (WAVE - 1);
-  if (p > MLP_NPARAMS) return;
-  const float* cx = cache;
-  const float* ch1 = cx + (int64_t)NI * B;
-  const float* ch2 = ch1 + (int64_t)NH * B;
-  const float* cd1 = ch2 + (int64_t)NH * B;
-  const float* cd2 = cd1 + (int64_t)NH * B;
-  const float* cdo = cd2 + (int64_t)NH * B;
-  const float* cr2 = cdo + B;
-  const float* a = nullptr;  // first factor
-  const float* b = nullptr;  // second factor (nullptr: 1)
-  double scale = 1.0;
-  if (p < OB1) {
-    const int j = (p - OW1) / NI, c = (p - OW1) % NI;
-    a = cd1 + (int64_t)j * B;
-    b = cx + (int64_t)c * B;
-  } else if (p < OW2) {
-    a = cd1 + (int64_t)(p - OB1) * B;
-  } else if (p < OB2) {
-    const int j = (p - OW2) / NH, i = (p - OW2) % NH;
-    a = cd2 + (int64_t)j * B;
-    b = ch1 + (int64_t)i * B;
-  } else if (p < OW3) {
-    a = cd2 + (int64_t)(p - OB2) * B;
-  } else if (p < OB3) {
-    a = cdo;
-    b = ch2 + (int64_t)(p - OW3) * B;
-  } else if (p == OB3) {
-    a = cdo;
-  } else {
-    a = cr2;
-    scale = 1.0 / (double)B;
-  }
+// grad[p] = sum over the tiles of their partial gradients (FP64); p == MLP_NPARAMS gives the
+// batch loss (1/B) sum r^2.  A workgroup takes 64 parameters (one per lane); wavefront q sums
+// the tiles q, q + 4, q + 8, ... in that order, and the four sums are added in wavefront order,
+// so the result is the same on every run.
+__global__ void __launch_bounds__(WG) mlp_reduce_kernel(const float* __restrict__ partial,
+                                                        int ntiles, int B,
+                                                        float* __restrict__ grad) {
+  __shared__ double sums[NWAVE][WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), q = threadIdx.x / WAVE;
+  const int p = blockIdx.x * WAVE + lane;
   double acc = 0.0;
-  for (int s = lane; s < B; s += WAVE) acc += b ? (double)a[s] * (double)b[s] : (double)a[s];
-  acc = wave_sum(acc);
-  if (lane == 0) grad[p] = (float)(acc * scale);
+  if (p <= MLP_NPARAMS) {
+    const float* col = partial + p;
+    int t = q;
+    for (; t + 7 * NWAVE < ntiles; t += 8 * NWAVE) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = col[(int64_t)(t + u * NWAVE) * (MLP_NPARAMS + 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += (double)v[u];
+    }
+    for (; t < ntiles; t += NWAVE) acc += (double)col[(int64_t)t * (MLP_NPARAMS + 1)];
+  }
+  sums[q][lane] = acc;
+  __syncthreads();
+  if (q == 0 && p <= MLP_NPARAMS) {
+    double a = sums[0][lane];
+#pragma unroll
+    for (int w = 1; w < NWAVE; ++w) a += sums[w][lane];
+    grad[p] = (float)(p == MLP_NPARAMS ? a / (double)B : a);
+  }
 }
 
 __global__ void mlp_adam_kernel(float* __restrict__ theta, const float* __restrict__ grad,
@@ -220,15 +301,19 @@ __global__ void mlp_adam_kernel(float* __restrict__ theta, const float* __restri
   theta[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
 }
 
-size_t mlp_cache_floats(int B) { return (size_t)(NI + 4 * NH + 2) * (size_t)B; }
+// scratch of launch_mlp_grad: one partial gradient (and loss sum) per tile of 16 samples
+size_t mlp_cache_floats(int B) {
+  return (size_t)((B + MLP_TILE - 1) / MLP_TILE) * (size_t)(MLP_NPARAMS + 1);
+}
 
 void launch_mlp_grad(const float* theta, const float* X, const float* y, int64_t b0, int B,
                      float* cache, float* grad, hipStream_t s) {
-  hipLaunchKernelGGL(mlp_fwdbwd_kernel, dim3((B + WG - 1) / WG), dim3(WG), 0, s, theta, X, y, b0,
-                     B, cache);
+  const int ntiles = (B + MLP_TILE - 1) / MLP_TILE;
+  hipLaunchKernelGGL(mlp_tile_grad_kernel, dim3(ntiles), dim3(WAVE), 0, s, theta, X, y, b0, B,
+                     cache);
   HMX_LAUNCHED();
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3((MLP_NPARAMS + 1 + NWAVE - 1) / NWAVE), dim3(WG), 0, s,
-                     cache, B, grad);
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((MLP_NPARAMS + 1 + WAVE - 1) / WAVE), dim3(WG), 0, s,
+                     cache, ntiles, B, grad);
   HMX_LAUNCHED();
 }
 

@@ -25,7 +25,7 @@ struct MallocBackend {
     (*live)[p] = sz;
     return p;
   }
-  void* alloc_or_throw(size_t sz) {
+  void* alloc_or_throw(size_t sz, size_t, size_t, size_t) {
     void* p = alloc(sz);
     if (!p) throw std::bad_alloc();
     return p;
@@ -98,6 +98,21 @@ int main() {
     c.free(x);
     c.release();
     budget = size_t(1) << 40;
+    // a buffer meant to be shrunk takes a block of its own: not a larger cached block (whose
+    // tail it would strand), but a whole free block within 1/8 of its size
+    char* big = (char*)c.alloc(150 * MiB);
+    c.free(big);
+    char* pool = (char*)c.alloc_block(80 * MiB);
+    check(pool != big && c.n_blocks() == 2, "no larger cached block for a block allocation");
+    c.shrink(pool, 50 * MiB);
+    check(c.free_bytes() == 150 * MiB + 30 * MiB, "its tail is its own");
+    c.free(pool);
+    char* again = (char*)c.alloc_block(76 * MiB);
+    check(again == pool, "a whole free block within 1/8 is reused");
+    c.free(again);
+    check(c.consistent(), "consistent after block allocations");
+    c.release();
+    check(c.n_blocks() == 0, "all released after block allocations");
   }
   // random sequence
   {
@@ -119,7 +134,7 @@ int main() {
       const int op = (int)(rng() % 10);
       if (op < 4 || bufs.empty()) {
         const size_t req = 1 + rng() % (rng() % 2 ? (3 * MiB) : (256 * size_t(1) << 10));
-        char* p = (char*)c.alloc(req);
+        char* p = (char*)(rng() % 4 == 0 ? c.alloc_block(req) : c.alloc(req));
         Buf b{p, req, (unsigned char)(1 + rng() % 250)};
         fill(b);
         bufs.push_back(b);

@@ -61,9 +61,10 @@ def test_matches_stored_near_field(H, precision, leaf):
     ot = H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=15.0, prm=H.params(near_mode=1, **kw))
     assert ot.info["near_entries"] == st.info["near_entries"] > 0 and ot.info["n_far"] > 0
     es = 16 if precision == 0 else 8
-    # no near-field storage: the operator is smaller by the near entries (within the rounding of
-    # the allocator's block sizes)
-    assert st.info["bytes"] - ot.info["bytes"] >= 0.9 * es * st.info["near_entries"]
+    # no near-field storage: the operator is smaller by the near entries (the slot pools, whose
+    # trimmed size depends on how the blocks fell to workgroups, are left out of the comparison)
+    held = lambda op: op.info["bytes"] - op.info["factor_bytes"]
+    assert held(st) - held(ot) >= 0.99 * es * st.info["near_entries"]
     x = I.complex_vector(P.shape[0], 4)
     ys, yo = apply(st, x), apply(ot, x)
     # the same factors (the build does not depend on the near mode) and the same near entries
