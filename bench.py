@@ -13,7 +13,8 @@ Workloads (synthetic, seeded), selected with --workload:
                     schedule, reported against the plain FP64 batch;
   large             one eighth (row share 0 of 8) of the prolate (2, 1, 1) ellipsoid with
                     1 310 720 triangles (3 932 160 points), k = 120, leaf 128, tol 1e-4, FP32;
-                    100 products replayed in one HIP graph.
+                    100 products replayed in one HIP graph; --large-shares all: the whole
+                    operator as its 8 row shares built and applied in turn.
 One step = one full pass of the hot path with the mesh and the vector already resident in device
 memory: quadrature points, cluster tree, block tree, near-field blocks, ACA of the far blocks,
 and one H-matrix product.
@@ -919,105 +920,177 @@ def run_em(args, torch, oracle, hmx, I):
 
 
 def run_large(args, torch, oracle, hmx, I):
+    """The prolate workload.  --large-shares one: row share 0 of 8 (one GPU's part of the
+    row-sharded operator), 100 products replayed in a HIP graph, and the learned layout (a
+    network trained on the adaptive ranks of share 1, so share 0 is held out) against plain
+    adaptive ACA.  --large-shares all: the whole operator on the one GPU, as its 8 row shares
+    built and applied one after the other (each closed before the next), their products summed;
+    a step is the 8 builds and products."""
     from paper_1804_00995_amd import rank_model as R
     v, f = I.icosphere(8)
     v = I.ellipsoid(v, (2.0, 1.0, 1.0))
     bary, w = I.rule_3pt()
     M = 3 * f.shape[0]
     k = 120.0
-    shares, share = 8, 0
+    shares = 8
+    whole = args.large_shares == "all"
+
     # far blocks bounded to 32 768 points (the fastest bound of a sweep at this size)
-    prm = hmx.params(tol=1e-4, leaf_size=128, precision=hmx.FP32_MIXED, row_shares=shares,
-                     row_share=share, max_far_mn=32768)
+    def prm(share, **kw):
+        return hmx.params(tol=1e-4, leaf_size=128, precision=hmx.FP32_MIXED, row_shares=shares,
+                          row_share=share, max_far_mn=32768, **kw)
+
     vd, fd = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
     x_h = I.complex_vector(M, 0)
     xd = torch.from_numpy(x_h).to(torch.complex64).cuda()
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    log(f"bench large: M={M}, row share {share} of {shares}")
+    log(f"bench large: M={M}, " + ("all 8 row shares in turn" if whole else "row share 0 of 8"))
 
-    def step():
-        op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, prm=prm, stream=stream)
-        return op, op.matvec(xd, stream=stream)
+    def graph_ms(op, y, reps):
+        g = op.graph(xd, y)
+        g.launch(1, stream=stream)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        g.launch(reps, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        g.close()
+        return ev0.elapsed_time(ev1) / reps
 
-    ms_step, aca = timed_steps(step, args.steps, args.warmup)
-    op, _ = step()
-    torch.cuda.synchronize()
-    info = op.info
-    y = torch.zeros_like(xd)
-    g = op.graph(xd, y)
-    g.launch(1, stream=stream)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    g.launch(100, stream=stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    mv_ms = ev0.elapsed_time(ev1) / 100
-    g.close()
-    log(f"100 products in one graph: {mv_ms:.3f} ms each")
-    perm = op.export_tree()["perm"]
-    rb, re = info["row_begin"], info["row_end"]
-    rows = np.sort(np.random.default_rng(55).choice(perm[rb:re], args.sample_rows, replace=False))
+    if whole:
+        def step():
+            y = torch.zeros_like(xd)
+            infos = []
+            for r in range(shares):
+                op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, prm=prm(r), stream=stream)
+                y += op.matvec(xd, stream=stream)
+                infos.append(op.info)
+                op.close()
+            return _Whole(infos), y
+
+        ms_step, aca = timed_steps(step, args.steps, args.warmup)
+        # product of the whole operator: each share's product replayed in a graph, summed
+        y = torch.zeros_like(xd)
+        mv_ms, build_ms, infos = 0.0, 0.0, []
+        for r in range(shares):
+            op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, prm=prm(r), stream=stream)
+            ys = torch.zeros_like(xd)
+            mv_ms += graph_ms(op, ys, args.large_reps)
+            y += ys
+            infos.append(op.info)
+            build_ms += op.info["t_total_ms"]
+            op.close()
+        torch.cuda.synchronize()
+        log(f"whole operator: build {build_ms:.1f} ms, product {mv_ms:.2f} ms (8 shares, "
+            f"{args.large_reps} graph replays each)")
+        info = _Whole(infos).info
+        rows = np.sort(np.random.default_rng(55).choice(M, args.sample_rows, replace=False))
+    else:
+        # the network: trained on the adaptive ranks of share 1
+        op1 = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, prm=prm(1), stream=stream)
+        feat, ranks = R.block_data(op1)
+        op1.close()
+        model = R.train(feat, ranks, epochs=30)
+
+        def step():
+            op = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, prm=prm(0), stream=stream)
+            return op, op.matvec(xd, stream=stream)
+
+        ms_step, aca = timed_steps(step, args.steps, args.warmup)
+        op, _ = step()
+        torch.cuda.synchronize()
+        info = op.info
+        y = torch.zeros_like(xd)
+        mv_ms = graph_ms(op, y, args.large_reps)
+        log(f"{args.large_reps} products in one graph: {mv_ms:.3f} ms each")
+        perm = op.export_tree()["perm"]
+        rb, re = info["row_begin"], info["row_end"]
+        rows = np.sort(np.random.default_rng(55).choice(perm[rb:re], args.sample_rows, replace=False))
+        op.close()
+        model.install()
+        try:
+            t0 = time.perf_counter()
+            opL = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, stream=stream,
+                            prm=prm(0, rank_model=hmx.RANK_LEARNED))
+            torch.cuda.synchronize()
+            t_learned = time.perf_counter() - t0
+        finally:
+            hmx.set_rank_model(None)
+        yL = opL.matvec(xd, stream=stream)
+        torch.cuda.synchronize()
+        learned = {"trained_on": "adaptive ranks of row share 1 (share 0 held out)",
+                   "build_s": round(t_learned, 3), "factor_bytes": opL.info["factor_bytes"],
+                   "bytes": opL.info["bytes"], "pool_reserved_bytes": opL.info["pool_reserved_bytes"],
+                   "adaptive_pool_reserved_bytes": info["pool_reserved_bytes"],
+                   "predicted_entries": opL.info["predicted_entries"],
+                   "overflow_blocks": opL.info["overflow_blocks"], "aca_rounds": opL.info["aca_rounds"],
+                   "product_equals_adaptive": bool(torch.equal(yL, y))}
+        opL.close()
     y_h = y.cpu().numpy().astype(np.complex128)
     rel_err, c0, c1 = None, 0.0, 0.0
     if args.cpu_baseline == "on":
-        # the oracle leg: dense rows of the share, timed, and the GPU product's error on them
+        # the oracle leg: sampled dense rows, timed, and the GPU product's error on them
         P, Wq = oracle.quad_points(v, f, bary, w)
         c0 = time.perf_counter()
         yr = oracle.dense_rows(P, Wq, oracle.HELMHOLTZ, k, x_h, rows)
         c1 = time.perf_counter()
         rel_err = float(np.linalg.norm(y_h[rows] - yr) / np.linalg.norm(yr))
-        log(f"rel_err on {args.sample_rows} sampled rows of the share: {rel_err:.3e}")
-    # learned layout against plain adaptive ACA: a model trained on the ranks of the adaptive
-    # build above
-    feat, ranks = R.block_data(op)
-    model = R.train(feat, ranks, epochs=30)
-    model.install()
-    info_a = info
-    op.close()
-    t0 = time.perf_counter()
-    opL = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=k, stream=stream,
-                    prm=hmx.params(tol=1e-4, leaf_size=128, precision=hmx.FP32_MIXED,
-                                   row_shares=shares, row_share=share, max_far_mn=32768,
-                                   rank_model=hmx.RANK_LEARNED))
-    torch.cuda.synchronize()
-    t_learned = time.perf_counter() - t0
-    yL = opL.matvec(xd, stream=stream)
-    torch.cuda.synchronize()
-    same = bool(torch.equal(yL, y))
-    learned = {"build_s": round(t_learned, 3), "factor_bytes": opL.info["factor_bytes"],
-               "bytes": opL.info["bytes"], "predicted_entries": opL.info["predicted_entries"],
-               "overflow_blocks": opL.info["overflow_blocks"], "aca_rounds": opL.info["aca_rounds"],
-               "product_equals_adaptive": same}
-    opL.close()
-    hmx.set_rank_model(None)
+        log(f"rel_err on {args.sample_rows} sampled rows: {rel_err:.3e}")
     cpu = None
     if args.cpu_baseline == "on":
-        n_rows = re - rb
+        n_rows = M if whole else info["row_end"] - info["row_begin"]
         cpu = {"value": round((c1 - c0) * 1e3 * n_rows / len(rows), 1),
-               "unit": "ms per dense product of the share's rows (oracle, no H-matrix)",
+               "unit": "ms per dense product of the rows measured (oracle, no H-matrix)",
                "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": f"{len(rows)} dense rows in {c1 - c0:.2f} s, scaled to the share's "
-                         f"{n_rows} rows (the oracle's H-build does not fit this size in minutes)"}
-    build_s = info_a["t_total_ms"] / 1e3
+               "sample": f"{len(rows)} dense rows in {c1 - c0:.2f} s, scaled to {n_rows} rows "
+                         "(the oracle's H-build does not fit this size in minutes)"}
+    build_s = info["t_total_ms"] / 1e3
     extra = {
         "h_build_s": round(build_s, 4),
         "h_matvec_ms": round(mv_ms, 4),
         "rel_err": rel_err,
-        "kernel_evals_per_s": info_a["kernel_evals"] / build_s if build_s > 0 else None,
-        "build_phases_ms": {k2: round(info_a[k2], 2) for k2 in
+        "kernel_evals_per_s": info["kernel_evals"] / build_s if build_s > 0 else None,
+        "build_phases_ms": {k2: round(info[k2], 2) for k2 in
                             ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
-        "sizes": sizes(info_a),
-        "rows": [rb, re],
-        "learned_vs_adaptive": learned,
+        "sizes": sizes(info),
     }
-    extra.update(rooflines(info_a, aca, mv_ms, M, 8, "fp32"))
+    if whole:
+        extra["shares"] = [{"rows": [i["row_begin"], i["row_end"]], "build_ms": round(i["t_total_ms"], 1),
+                            "bytes": i["bytes"], "far_entries": i["far_entries"]} for i in infos]
+    else:
+        extra["rows"] = [info["row_begin"], info["row_end"]]
+        extra["learned_vs_adaptive"] = learned
+    extra.update(rooflines(info, aca, mv_ms, M, 8, "fp32"))
     extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
     extra["cpu_baseline"] = cpu
+    part = ("the whole operator as its 8 row shares built and applied in turn"
+            if whole else "row share 0 of 8")
     config = {"workload": f"prolate (2,1,1) L8 ({f.shape[0]} triangles, {M} points), k=120, "
-                          f"leaf 128, eta 1.5, far blocks <= 32768 points, ACA tol 1e-4, fp32, row share {share} of {shares} "
-                          f"(rows {rb}-{re}), 100 products in one HIP graph"}
+                          f"leaf 128, eta 1.5, far blocks <= 32768 points, ACA tol 1e-4, fp32, {part}, "
+                          f"{args.large_reps} products in one HIP graph per operator"}
     line(args, ms_step, "fp32", config, extra)
+
+
+class _Whole:
+    """Totals over the row shares of one operator, shaped like Operator.info for the bench."""
+
+    def __init__(self, infos):
+        add = ("near_entries", "far_entries", "dense_far_entries", "kernel_evals", "n_near",
+               "n_far", "dense_far", "overflow_blocks", "factor_bytes")
+        t = {k: sum(i[k] for i in infos) for k in add}
+        t.update({k: sum(i[k] for i in infos) for k in ("t_total_ms", "t_tree_ms", "t_blocks_ms",
+                                                        "t_near_ms", "t_aca_ms")})
+        t["max_rank"] = max(i["max_rank"] for i in infos)
+        t["bytes"] = max(i["bytes"] for i in infos)  # one share held at a time
+        t["aca_ms"] = [sum(i["aca_ms"][c] for i in infos) for c in range(4)]
+        t["aca_bytes"] = [sum(i["aca_bytes"][c] for i in infos) for c in range(4)]
+        t["aca_blocks"] = [sum(i["aca_blocks"][c] for i in infos) for c in range(4)]
+        t["aca_rounds"] = max(i["aca_rounds"] for i in infos)
+        self.info = t
+
+    def close(self):
+        pass
 
 
 def main():
@@ -1044,6 +1117,10 @@ def main():
                     help="sphere workload: run the ACA classes one after the other (schedule knob)")
     ap.add_argument("--regularize", choices=["on", "off"], default="off",
                     help="sphere workload: near field with the singular correction")
+    ap.add_argument("--large-shares", choices=["one", "all"], default="one",
+                    help="large workload: row share 0 of 8, or the whole operator as its 8 shares")
+    ap.add_argument("--large-reps", type=int, default=100,
+                    help="large workload: products replayed in one graph per operator")
     ap.add_argument("--train-epochs", type=int, default=60,
                     help="target workload: epochs of the rank network's training")
     ap.add_argument("--tune-cache", default=None,
