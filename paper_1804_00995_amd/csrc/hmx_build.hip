@@ -208,19 +208,32 @@ void build_tree(hmx_op* op, hipStream_t s) {
                 "a leaf holds more than 256 points (coincident points)");
 }
 
-// Sort a device list of (t, s) pairs into the lexicographic order of their node ranges.
-void sort_pairs(hmx_op* op, DevBuf<int2>& L, int64_t n, hipStream_t s) {
+// Sort the near and far lists of (t, s) pairs, each into the lexicographic order of their node
+// ranges, with one radix sort: key = (list, rank(t), rank(s)), the ranks in (begin, end) order,
+// in ceil(log2(2 n_nodes^2)) bits.
+void sort_pairs(hmx_op* op, DevBuf<int2>& nearL, int64_t nn, DevBuf<int2>& farL, int64_t nf,
+                hipStream_t s) {
+  const int64_t n = nn + nf;
   if (n <= 1) return;
-  // key = (begin_t, 63 - level_t, begin_s, 63 - level_s) in 23 + 6 + 23 + 6 bits (M < 2^23)
+  const int64_t NN = op->n_nodes;
+  DevBuf<int64_t> cnt(op->M), start(op->M + 1);
+  DevBuf<int32_t> deep(op->M), rank(NN);
+  launch_node_rank(op->nbegin.p, op->nlevel.p, (int)NN, op->M, cnt.p, start.p, deep.p, rank.p, s);
+  int bits = 1;
+  while ((bits < 62) && ((uint64_t)1 << bits) < (uint64_t)NN * (uint64_t)NN) ++bits;
+  const uint64_t far_bit = (uint64_t)1 << bits;  // the far list after the near list
   DevBuf<uint64_t> key(n), skey(n);
   DevBuf<int32_t> val(n), sval(n);
   DevBuf<unsigned char> tmp;
-  launch_pair_keys(L.p, n, n, op->nbegin.p, op->nlevel.p, key.p, val.p, s);
-  radix_sort_u64_pairs(key.p, skey.p, val.p, sval.p, n, 58, tmp, s);
-  DevBuf<int2> out(n);
-  launch_pair_gather(L.p, sval.p, n, out.p, s);
+  launch_pair_rank_keys(nearL.p, nn, rank.p, NN, 0, 0, key.p, val.p, s);
+  launch_pair_rank_keys(farL.p, nf, rank.p, NN, far_bit, nn, key.p, val.p, s);
+  radix_sort_u64_pairs(key.p, skey.p, val.p, sval.p, n, bits + 1, tmp, s);
+  DevBuf<int2> out_near(std::max<int64_t>(nn, 1)), out_far(std::max<int64_t>(nf, 1));
+  launch_pair_gather2(nearL.p, nn, farL.p, sval.p, nn, out_near.p, s);
+  launch_pair_gather2(nearL.p, nn, farL.p, sval.p + nn, nf, out_far.p, s);
   HMX_HIP(hipStreamSynchronize(s));
-  L = std::move(out);
+  nearL = std::move(out_near);
+  farL = std::move(out_far);
 }
 
 // ------------------------------------------------------------------------------ block tree
@@ -284,8 +297,7 @@ void build_blocks(hmx_op* op, hipStream_t s) {
   }
   op->n_near = n_near;
   op->n_far = n_far;
-  sort_pairs(op, nearL, n_near, s);
-  sort_pairs(op, farL, n_far, s);
+  sort_pairs(op, nearL, n_near, farL, n_far, s);
   op->nearL = std::move(nearL);
   op->farL = std::move(farL);
 }

@@ -162,6 +162,9 @@ void launch_quad(const double* vtx, int64_t nv, const int32_t* tri, int64_t nt, 
                  double* X, double* Y, double* Z, double* W, int* err, hipStream_t s);
 // k_scan.hip
 void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);  // out[n] = total
+// the same without synchronisation, on caller scratch of scan_work_len(n) entries
+int64_t scan_work_len(int64_t n);
+void scan_excl_i64_work(const int64_t* in, int64_t* out, int64_t n, int64_t* work, hipStream_t s);
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
@@ -201,9 +204,13 @@ void launch_block_level(const int2* front, int nfront, const double* box, const 
                         int re, double eta2, int max_mn, int2* next, int* next_cnt,
                         int2* nearL, int* near_cnt, int2* farL, int* far_cnt, int* err,
                         hipStream_t s);
-void launch_pair_keys(const int2* pairs, int64_t n, int64_t npad, const int32_t* nbegin,
-                      const int32_t* level, uint64_t* key, int32_t* val, hipStream_t s);
-void launch_pair_gather(const int2* in, const int32_t* idx, int64_t n, int2* out, hipStream_t s);
+void launch_node_rank(const int32_t* nbegin, const int32_t* level, int n_nodes, int64_t M,
+                      int64_t* cnt, int64_t* start, int32_t* deep, int32_t* rank, hipStream_t s);
+void launch_pair_rank_keys(const int2* pairs, int64_t n, const int32_t* rank, int64_t n_nodes,
+                           uint64_t list_bit, int64_t offset, uint64_t* key, int32_t* val,
+                           hipStream_t s);
+void launch_pair_gather2(const int2* a, int64_t na, const int2* b, const int32_t* idx, int64_t n,
+                         int2* out, hipStream_t s);
 void launch_near_prep(const int2* nearL, int64_t n, const int32_t* nbegin, const int32_t* nend,
                       const int32_t* leaf_of_node, int64_t* sizes, int64_t* leaf_cnt, hipStream_t s);
 void launch_far_prep(const int2* farL, int64_t n, const int32_t* nbegin, const int32_t* nend,

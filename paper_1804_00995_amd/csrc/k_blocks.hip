@@ -94,42 +94,78 @@ void launch_block_level(const int2* front, int nfront, const double* box, const 
   HMX_LAUNCHED();
 }
 
-// Sort key of a block (t, s) equivalent to the lexicographic order of
-// (t.begin, t.end, s.begin, s.end): two distinct nodes with the same begin are nested, and the
-// deeper one ends first, so (begin, end) orders like (begin, -level).
-// Layout: [t.begin:23][63 - t.level:6][s.begin:23][63 - s.level:6]; padding keys are ~0.
-__global__ void pair_keys_kernel(const int2* __restrict__ pairs, int64_t n, int64_t npad,
-                                 const int32_t* __restrict__ nbegin, const int32_t* __restrict__ level,
-                                 uint64_t* __restrict__ key, int32_t* __restrict__ val) {
-  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (i >= npad) return;
-  if (i >= n) {
-    key[i] = ~0ull;
-    val[i] = -1;
-    return;
-  }
-  int2 p = pairs[i];
-  uint64_t k = ((uint64_t)nbegin[p.x] << 35) | ((uint64_t)(63 - level[p.x]) << 29) |
-               ((uint64_t)nbegin[p.y] << 6) | (uint64_t)(63 - level[p.y]);
-  key[i] = k;
-  val[i] = (int32_t)i;
+// Rank of every cluster-tree node in the order of (begin, end), for short sort keys.  The nodes
+// that start at one position p form a chain of left children at consecutive levels (a node
+// that is not a leaf starts where its left child starts), and the deeper one ends first, so
+//   rank = start[p] + (deepest level starting at p - level),
+// with start the exclusive scan of the number of nodes starting at each position.
+__global__ void node_begin_count_kernel(const int32_t* __restrict__ nbegin,
+                                        const int32_t* __restrict__ level, int n_nodes,
+                                        int64_t* __restrict__ cnt, int32_t* __restrict__ deep) {
+  const int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= n_nodes) return;
+  atomicAdd((unsigned long long*)&cnt[nbegin[i]], 1ull);
+  atomicMax(&deep[nbegin[i]], level[i]);
 }
-void launch_pair_keys(const int2* pairs, int64_t n, int64_t npad, const int32_t* nbegin,
-                      const int32_t* level, uint64_t* key, int32_t* val, hipStream_t s) {
-  hipLaunchKernelGGL(pair_keys_kernel, dim3((unsigned)((npad + WG - 1) / WG)), dim3(WG), 0, s,
-                     pairs, n, npad, nbegin, level, key, val);
+__global__ void node_rank_kernel(const int32_t* __restrict__ nbegin,
+                                 const int32_t* __restrict__ level, int n_nodes,
+                                 const int64_t* __restrict__ start,
+                                 const int32_t* __restrict__ deep, int32_t* __restrict__ rank) {
+  const int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= n_nodes) return;
+  const int p = nbegin[i];
+  rank[i] = (int32_t)(start[p] + (deep[p] - level[i]));
+}
+void launch_node_rank(const int32_t* nbegin, const int32_t* level, int n_nodes, int64_t M,
+                      int64_t* cnt, int64_t* start, int32_t* deep, int32_t* rank, hipStream_t s) {
+  fill_i64(cnt, 0, M, s);
+  fill_i32(deep, -1, M, s);
+  const unsigned g = (unsigned)((n_nodes + WG - 1) / WG);
+  hipLaunchKernelGGL(node_begin_count_kernel, dim3(g), dim3(WG), 0, s, nbegin, level, n_nodes, cnt,
+                     deep);
+  HMX_LAUNCHED();
+  scan_excl_i64(cnt, start, M, s);
+  hipLaunchKernelGGL(node_rank_kernel, dim3(g), dim3(WG), 0, s, nbegin, level, n_nodes, start, deep,
+                     rank);
   HMX_LAUNCHED();
 }
 
-__global__ void pair_gather_kernel(const int2* __restrict__ in, const int32_t* __restrict__ idx,
-                                   int64_t n, int2* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (i < n) out[i] = in[idx[i]];
+// Keys of a block list from the node ranks: (list << 2 bits) | rank_t * n_nodes + rank_s, whose
+// order is the lexicographic order of (list, t.begin, t.end, s.begin, s.end); val = the pair's
+// index in the concatenated lists (offset + i).
+__global__ void pair_rank_keys_kernel(const int2* __restrict__ pairs, int64_t n,
+                                      const int32_t* __restrict__ rank, int64_t n_nodes,
+                                      uint64_t list_bit, int64_t offset,
+                                      uint64_t* __restrict__ key, int32_t* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  const int2 p = pairs[i];
+  key[offset + i] = list_bit | ((uint64_t)rank[p.x] * (uint64_t)n_nodes + (uint64_t)rank[p.y]);
+  val[offset + i] = (int32_t)(offset + i);
 }
-void launch_pair_gather(const int2* in, const int32_t* idx, int64_t n, int2* out, hipStream_t s) {
+void launch_pair_rank_keys(const int2* pairs, int64_t n, const int32_t* rank, int64_t n_nodes,
+                           uint64_t list_bit, int64_t offset, uint64_t* key, int32_t* val,
+                           hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(pair_gather_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, in,
-                     idx, n, out);
+  hipLaunchKernelGGL(pair_rank_keys_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s,
+                     pairs, n, rank, n_nodes, list_bit, offset, key, val);
+  HMX_LAUNCHED();
+}
+
+// out[i] = the pair at index idx[i] of the concatenated lists (a, na entries, then b)
+__global__ void pair_gather2_kernel(const int2* __restrict__ a, int64_t na,
+                                    const int2* __restrict__ b, const int32_t* __restrict__ idx,
+                                    int64_t n, int2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = idx[i];
+  out[i] = j < na ? a[j] : b[j - na];
+}
+void launch_pair_gather2(const int2* a, int64_t na, const int2* b, const int32_t* idx, int64_t n,
+                         int2* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(pair_gather2_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, s, a,
+                     na, b, idx, n, out);
   HMX_LAUNCHED();
 }
 

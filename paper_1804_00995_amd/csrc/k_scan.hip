@@ -80,19 +80,26 @@ __global__ void __launch_bounds__(WG) scan_apply_kernel(const int64_t* __restric
   if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = boff[nb];
 }
 
-void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+int64_t scan_work_len(int64_t n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1; }
+
+void scan_excl_i64_work(const int64_t* in, int64_t* out, int64_t n, int64_t* bsum,
+                        hipStream_t s) {
   if (n == 0) {
     fill_i64(out, 0, 1, s);
     return;
   }
   int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
-  DevBuf<int64_t> bsum(nb + 1);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(WG), 0, s, in, n, bsum.p);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(WG), 0, s, in, n, bsum);
   HMX_LAUNCHED();
-  hipLaunchKernelGGL(scan_offsets_kernel, dim3(1), dim3(WG), 0, s, bsum.p, nb);
+  hipLaunchKernelGGL(scan_offsets_kernel, dim3(1), dim3(WG), 0, s, bsum, nb);
   HMX_LAUNCHED();
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(WG), 0, s, in, n, bsum.p, nb, out);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(WG), 0, s, in, n, bsum, nb, out);
   HMX_LAUNCHED();
+}
+
+void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  DevBuf<int64_t> bsum(scan_work_len(n));
+  scan_excl_i64_work(in, out, n, bsum.p, s);
   HMX_HIP(hipStreamSynchronize(s));  // bsum is freed on return
 }
 
