@@ -209,7 +209,8 @@ def run_sphere(args, torch, oracle, hmx, I):
     reg = args.regularize == "on"
     prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec, regularize=int(reg),
                      aca_serial=int(args.aca_serial == "on"),
-                     near_mode=int(args.near_mode == "otf"))
+                     near_mode=int(args.near_mode == "otf" and not reg))  # (the correction
+    # lives in stored near blocks)
     x_h = I.complex_vector(M, 0)
     vd, fd = torch.from_numpy(v).to(dev), torch.from_numpy(f).to(dev)
     xd = torch.from_numpy(x_h).to(cdt).to(dev)
@@ -227,6 +228,27 @@ def run_sphere(args, torch, oracle, hmx, I):
     info = op.info
     mv_ms = product_ms(op, xd, y, stream, args.matvec_reps)
     log(f"matvec {mv_ms:.3f} ms (median of {args.matvec_reps})")
+    # several vectors at once: ms per vector of hmx_matvec_multi (groups of four read the
+    # operator once), to show where the per-vector cost stops falling
+    multi = {}
+    if args.multi_vectors > 1:
+        for nr in (2, 4, 8, 16):
+            if nr > args.multi_vectors:
+                break
+            X = xd.unsqueeze(0).repeat(nr, 1).contiguous()
+            Y = torch.empty_like(X)
+            op.matvec_multi(X, Y, stream=stream)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            times = []
+            for _ in range(5):
+                ev0.record(stream)
+                op.matvec_multi(X, Y, stream=stream)
+                ev1.record(stream)
+                ev1.synchronize()
+                times.append(ev0.elapsed_time(ev1))
+            multi[str(nr)] = round(float(np.median(times)) / nr, 4)
+        multi["1"] = round(mv_ms, 4)
+        log(f"ms per vector, several-vector product: {multi}")
     y_h = y.cpu().numpy().astype(np.complex128)
     build_s = info["t_total_ms"] / 1e3
     cpu, rel_err = None, None
@@ -274,7 +296,7 @@ def run_sphere(args, torch, oracle, hmx, I):
         "sizes": sizes(info),
     }
     extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision,
-                           near_stored=args.near_mode == "stored"))
+                           near_stored=prm.near_mode == 0))
     # kernel evaluations per second by phase: near-field assembly (its phase time includes the
     # block bookkeeping), and ACA rows and columns; the ALU ceiling of one evaluation beside them
     near_s, aca_s = info["t_near_ms"] / 1e3, info["t_aca_ms"] / 1e3
@@ -283,12 +305,15 @@ def run_sphere(args, torch, oracle, hmx, I):
         "aca_rows_columns": (info["kernel_evals"] - info["near_entries"]) / aca_s if aca_s > 0 else None,
         "alu_ceiling": DENSE_ALU_PEAK[args.precision],
     }
+    if multi:
+        extra["ms_per_vector_several"] = multi
     extra["cpu_baseline"] = cpu
     op.close()
     config = {"workload": f"unit icosphere L{args.level} ({f.shape[0]} triangles, {M} points), "
                           f"Helmholtz k={args.k:g}, leaf 64, eta 1.5, ACA tol 1e-3, {args.precision}"
                           + (", singular correction (radius 2)" if reg else "")
-                          + (", near field computed in the product" if args.near_mode == "otf" else "")}
+                          + (", near field computed in the product"
+                             if args.near_mode == "otf" and not reg else "")}
     line(args, ms_step, args.precision, config, extra)
 
 
@@ -1110,9 +1135,12 @@ def main():
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-one-core", choices=["on", "off"], default="off",
                     help="sphere workload: also time the oracle on one core (about a minute)")
-    ap.add_argument("--near-mode", choices=["stored", "otf"], default="stored",
-                    help="sphere workload: near blocks stored in the build, or computed in each "
-                         "product (near_mode 1)")
+    ap.add_argument("--near-mode", choices=["stored", "otf"], default="otf",
+                    help="sphere workload: near blocks computed in each product (near_mode 1, the "
+                         "default: faster per step and no near-field memory) or stored in the build")
+    ap.add_argument("--multi-vectors", type=int, default=0,
+                    help="sphere workload: also time the several-vector product for 2, 4, 8, 16 "
+                         "vectors up to this many")
     ap.add_argument("--aca-serial", choices=["on", "off"], default="off",
                     help="sphere workload: run the ACA classes one after the other (schedule knob)")
     ap.add_argument("--regularize", choices=["on", "off"], default="off",
