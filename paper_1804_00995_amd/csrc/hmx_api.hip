@@ -364,7 +364,7 @@ static void enqueue_matvec(const hmx_op* op, const void* x, void* y, hipStream_t
     launch_leaf_apply<T>(op->n_leaves, op->leaves.p, op->nbegin.p, op->nend.p, op->near_ptr.p,
                          op->near_sb.p, op->near_n.p, op->near_off.p, (const T*)op->near_pool.p,
                          op->far_ptr.p, op->far_list.p, op->far.p, t, xp, op->perm.p, op->rows,
-                         (T*)y, s, op->p.near_mode == 1 ? &otf : nullptr);
+                         (T*)y, op->max_leaf_rows, s, op->p.near_mode == 1 ? &otf : nullptr);
   };
   if (op->prec == HMX_FP64) run(double2{});
   else run(float2{});

@@ -203,9 +203,13 @@ void build_tree(hmx_op* op, hipStream_t s) {
   to_host(hb, op->nbegin.p, total, s);
   to_host(he, op->nend.p, total, s);
   to_host(hc, op->child0.p, total, s);
-  for (int i = 0; i < total; ++i)
-    HMX_REQUIRE(hc[i] >= 0 || he[i] - hb[i] <= 256, HMX_EUNSUPPORTED,
+  op->max_leaf_rows = 0;
+  for (int i = 0; i < total; ++i) {
+    if (hc[i] >= 0) continue;
+    HMX_REQUIRE(he[i] - hb[i] <= 256, HMX_EUNSUPPORTED,
                 "a leaf holds more than 256 points (coincident points)");
+    op->max_leaf_rows = std::max(op->max_leaf_rows, he[i] - hb[i]);
+  }
 }
 
 // Sort the near and far lists of (t, s) pairs, each into the lexicographic order of their node

@@ -382,7 +382,7 @@ void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegi
                        const int32_t* near_n, const int64_t* near_off, const T* near_pool,
                        const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
                        const T* tbuf, const T* xp, const int32_t* perm, int64_t y_rows, T* y,
-                       hipStream_t s, const NearOtfArgs* otf = nullptr);
+                       int max_leaf_rows, hipStream_t s, const NearOtfArgs* otf = nullptr);
 template <class T>
 void launch_dense_otf(const double* X, const double* Y, const double* Z, const double* W,
                       int64_t rows, int64_t so, int64_t cols, int kern, double k, const T* x,
@@ -418,6 +418,7 @@ struct hmx_op {
   int64_t row_begin = 0, row_end = 0;
   // tree (breadth-first node numbering)
   int n_nodes = 0, n_leaves = 0, depth = 0;
+  int max_leaf_rows = 0;  // points of the largest leaf (at most 256)
   hmx::DevBuf<int32_t> nbegin, nend, nlevel, child0, child1, parent;
   hmx::DevBuf<double> box;
   hmx::DevBuf<int32_t> leaves, leaf_of_node;

@@ -63,16 +63,17 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
   const int n = f.n, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int64_t ldv = f.ldv;
   // column l of V: in the first segment below f.split, else in the second
-  auto colv = [&](int l) -> const T* {
-    return l < f.split ? (const T*)f.V + l * ldv : (const T*)f.V1 + (l - f.split) * ldv;
+  using gT = HMX_GLOBAL T;  // factor addresses read from the record: global space
+  auto colv = [&](int l) -> const gT* {
+    return l < f.split ? (const gT*)f.V + l * ldv : (const gT*)f.V1 + (l - f.split) * ldv;
   };
   int l = w;
   for (; l + 3 * NWAVE < f.r; l += 4 * NWAVE) {
     T a0 = czero<T>(), a1 = czero<T>(), a2 = czero<T>(), a3 = czero<T>();
-    const T* v0 = colv(l);
-    const T* v1 = colv(l + NWAVE);
-    const T* v2 = colv(l + 2 * NWAVE);
-    const T* v3 = colv(l + 3 * NWAVE);
+    const gT* v0 = colv(l);
+    const gT* v1 = colv(l + NWAVE);
+    const gT* v2 = colv(l + 2 * NWAVE);
+    const gT* v3 = colv(l + 3 * NWAVE);
 #pragma unroll 2
     for (int j = lane; j < n; j += WAVE) {
       T xj = xs[j];
@@ -94,8 +95,8 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
   }
   for (; l + NWAVE < f.r; l += 2 * NWAVE) {
     T a0 = czero<T>(), a1 = czero<T>();
-    const T* v0 = colv(l);
-    const T* v1 = colv(l + NWAVE);
+    const gT* v0 = colv(l);
+    const gT* v1 = colv(l + NWAVE);
 #pragma unroll 4
     for (int j = lane; j < n; j += WAVE) {
       T xj = xs[j];
@@ -111,7 +112,7 @@ __global__ void __launch_bounds__(WG) far_vt_kernel(const FarRec* __restrict__ r
   }
   for (; l < f.r; l += NWAVE) {
     T a0 = czero<T>();
-    const T* v0 = colv(l);
+    const gT* v0 = colv(l);
 #pragma unroll 4
     for (int j = lane; j < n; j += WAVE) cfma(a0, v0[j], xs[j]);
     a0 = wave_sum2(a0);
@@ -138,13 +139,76 @@ struct NearOtf {
   const double* kp;
 };
 
+// a[c] += sum_{l < nc} col_l[row[c]] tt[l], col_l = col + l ld (one segment of a far block's U).
+// The factor address comes from the block record in memory, where the compiler cannot infer its
+// space: as a global-space pointer its loads count only against the vector-memory counter, so
+// the scalar loads of tt do not wait for them.
+template <class T, int NCH>
+__device__ __forceinline__ void far_cols(T (&a)[NCH], const int (&row)[NCH], const T* colp,
+                                         int64_t ld, const T* __restrict__ tt, int nc) {
+  using gT = HMX_GLOBAL T;
+  const gT* col = (const gT*)colp;
+#pragma unroll(8 / NCH)
+  for (int l = 0; l < nc; ++l, col += ld) {
+    const T tl = tt[l];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) cfma(a[c], col[row[c]], tl);
+  }
+}
+
+// The stored blocks of one leaf of m <= NCH * 64 rows, for wave w: near blocks it = w, w + 4, ...
+// below nn, then far blocks, accumulated into acc[c] (row lane + 64 c).  The loads carry no
+// condition: lanes past the leaf's rows read its last row and their sums are discarded, so
+// that 8 / NCH columns of NCH loads each can be in flight per wave.
+template <class T, int NCH, int MAXCH>
+__device__ __forceinline__ void leaf_blocks(
+    T (&acc)[MAXCH], int lane, int w, int m, int tb, int64_t n0, int64_t nn,
+    int64_t f0, int64_t nfar, const int32_t* __restrict__ near_sb,
+    const int32_t* __restrict__ near_n, const int64_t* __restrict__ near_off,
+    const T* __restrict__ near_pool, const int32_t* __restrict__ far_list,
+    const FarRec* __restrict__ far, const T* __restrict__ tbuf, const T* __restrict__ xp) {
+  T a[NCH];
+  int row[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    a[c] = acc[c];
+    row[c] = min(lane + c * WAVE, m - 1);
+  }
+  for (int64_t it = w; it < nn + nfar; it += NWAVE) {
+    if (it < nn) {
+      const int64_t blk = n0 + it;
+      const int sb = near_sb[blk], n = near_n[blk];
+      const T* K = near_pool + near_off[blk];
+      const T* xs = xp + sb;
+#pragma unroll(8 / NCH)
+      for (int j = 0; j < n; ++j) {
+        const T xj = xs[j];
+        const T* col = K + (int64_t)j * m;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) cfma(a[c], col[row[c]], xj);
+      }
+    } else {
+      const FarRec f = far[far_list[f0 + (it - nn)]];
+      const int o = tb - f.tb;
+      const T* tt = tbuf + f.toff;
+      // columns below f.split in the first segment of U, the rest in the second
+      const int r0 = min(f.r, f.split);
+      far_cols<T, NCH>(a, row, (const T*)f.U + o, f.ldu, tt, r0);
+      far_cols<T, NCH>(a, row, (const T*)f.U1 + o, f.ldu, tt + r0, f.r - r0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = lane + c * WAVE < m ? a[c] : czero<T>();
+}
+
 // OTF = false: near blocks read from near_pool.  OTF = true: near blocks evaluated here.  For each
 // near block of the leaf in turn, the workgroup stages the block's source points and x entries
 // in LDS (one per thread), then wave w evaluates the sources j = w, w + 4, ... against all of
 // the leaf's rows (targets kept in registers), accumulating K_ij x_j; the far blocks follow as
 // in the stored case.  Each row's terms are summed per wave in a fixed order, then over the
 // waves, so the product is deterministic.
-template <class T, bool OTF>
+// MAXCH: 64-row chunks of the largest leaf (the kernel's registers and LDS are sized for it).
+template <class T, bool OTF, int MAXCH>
 __global__ void __launch_bounds__(WG) leaf_apply_kernel(
     const int32_t* __restrict__ leaves, const int32_t* __restrict__ nbegin,
     const int32_t* __restrict__ nend, const int64_t* __restrict__ near_ptr,
@@ -154,7 +218,7 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
     const FarRec* __restrict__ far, const T* __restrict__ tbuf,
     const T* __restrict__ xp, const int32_t* __restrict__ perm, int64_t y_rows,
     T* __restrict__ y, NearOtf otf) {
-  __shared__ T part[NWAVE][MAX_LEAF_CHUNKS * WAVE];
+  __shared__ T part[NWAVE][MAXCH * WAVE];
   const int leaf = blockIdx.x;
   const int node = leaves[leaf];
   const int tb = nbegin[node], m = nend[node] - tb;
@@ -165,18 +229,18 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int nch = (m + WAVE - 1) / WAVE;
-  T acc[MAX_LEAF_CHUNKS];
+  T acc[MAXCH];
 #pragma unroll
-  for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) acc[c] = czero<T>();
+  for (int c = 0; c < MAXCH; ++c) acc[c] = czero<T>();
   int64_t nn = nn_all;  // near blocks left to the per-wave loops below
   if constexpr (OTF) {
-    constexpr int TILE = MAX_LEAF_CHUNKS * WAVE;  // a near block's sources (a leaf: <= 256)
+    constexpr int TILE = MAXCH * WAVE;  // a near block's sources (a leaf)
     __shared__ double spt[4][TILE];              // source x, y, z, w
     __shared__ T sxp[TILE];                      // source entries of x
     const double k = otf.kp[tb];
-    double tx[MAX_LEAF_CHUNKS], ty[MAX_LEAF_CHUNKS], tz[MAX_LEAF_CHUNKS];
+    double tx[MAXCH], ty[MAXCH], tz[MAXCH];
 #pragma unroll
-    for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
+    for (int c = 0; c < MAXCH; ++c) {
       const int i = min(lane + c * WAVE, m - 1);
       tx[c] = otf.X[tb + i];
       ty[c] = otf.Y[tb + i];
@@ -197,7 +261,7 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
         const double sx = spt[0][j], sy = spt[1][j], sz = spt[2][j], sw = spt[3][j];
         const T xj = sxp[j];
 #pragma unroll
-        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
+        for (int c = 0; c < MAXCH; ++c) {
           if (c < nch) {
             const T g = eval_entry<T>(otf.kern, k, tx[c], ty[c], tz[c], sx, sy, sz, sw);
             cfma(acc[c], g, xj);
@@ -208,74 +272,22 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
     }
     nn = 0;
   }
-  if (nch == 1) {
-    // leaves of at most 64 rows (the usual case): one accumulator per lane, so that eight
-    // column loads per lane can be in flight without the registers of the general path; lanes
-    // past the leaf's rows read row 0 and discard it
-    T a = acc[0];  // (the near field's sum when it was computed above)
-    const bool on = lane < m;
-    const int i = on ? lane : 0;
-    for (int64_t it = w; it < nn + nfar; it += NWAVE) {
-      if (it < nn) {
-        const int64_t blk = n0 + it;
-        const int sb = near_sb[blk], n = near_n[blk];
-        const T* K = near_pool + near_off[blk] + i;
-        const T* xs = xp + sb;
-#pragma unroll 8
-        for (int j = 0; j < n; ++j) cfma(a, K[(int64_t)j * m], xs[j]);
-      } else {
-        const FarRec f = far[far_list[f0 + (it - nn)]];
-        const int o = tb - f.tb;
-        const T* U = (const T*)f.U + o + i;
-        const T* U1 = (const T*)f.U1 + o + i;
-        const T* tt = tbuf + f.toff;
-#pragma unroll 8
-        for (int l = 0; l < f.r; ++l) {
-          const T* col =
-              l < f.split ? U + (int64_t)l * f.ldu : U1 + (int64_t)(l - f.split) * f.ldu;
-          cfma(a, *col, tt[l]);
-        }
-      }
-    }
-    acc[0] = on ? a : czero<T>();
-  } else
-  for (int64_t it = w; it < nn + nfar; it += NWAVE) {
-    if (it < nn) {
-      const int64_t blk = n0 + it;
-      const int sb = near_sb[blk], n = near_n[blk];
-      const T* K = near_pool + near_off[blk];
-      const T* xs = xp + sb;
-#pragma unroll 4
-      for (int j = 0; j < n; ++j) {
-        const T xj = xs[j];
-        const T* col = K + (int64_t)j * m;
+  if (MAXCH == 1 || nch == 1)
+    leaf_blocks<T, 1, MAXCH>(acc, lane, w, m, tb, n0, nn, f0, nfar, near_sb, near_n, near_off,
+                             near_pool, far_list, far, tbuf, xp);
+  else if (MAXCH == 2 || nch == 2)
+    leaf_blocks<T, (MAXCH < 2 ? MAXCH : 2), MAXCH>(acc, lane, w, m, tb, n0, nn, f0, nfar, near_sb,
+                                                   near_n, near_off, near_pool, far_list, far,
+                                                   tbuf, xp);
+  else if (MAXCH == 3 || nch == 3)
+    leaf_blocks<T, (MAXCH < 3 ? MAXCH : 3), MAXCH>(acc, lane, w, m, tb, n0, nn, f0, nfar, near_sb,
+                                                   near_n, near_off, near_pool, far_list, far,
+                                                   tbuf, xp);
+  else
+    leaf_blocks<T, MAXCH, MAXCH>(acc, lane, w, m, tb, n0, nn, f0, nfar, near_sb, near_n, near_off,
+                                 near_pool, far_list, far, tbuf, xp);
 #pragma unroll
-        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
-          int i = lane + c * WAVE;
-          if (c < nch && i < m) cfma(acc[c], col[i], xj);
-        }
-      }
-    } else {
-      const FarRec f = far[far_list[f0 + (it - nn)]];
-      const int o = tb - f.tb;
-      const T* U = (const T*)f.U + o;
-      const T* tt = tbuf + f.toff;
-#pragma unroll 4
-      for (int l = 0; l < f.r; ++l) {
-        const T tl = tt[l];
-        // column l of U: in the first segment below f.split, else in the second
-        const T* col = l < f.split ? U + (int64_t)l * f.ldu
-                                   : (const T*)f.U1 + o + (int64_t)(l - f.split) * f.ldu;
-#pragma unroll
-        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
-          int i = lane + c * WAVE;
-          if (c < nch && i < m) cfma(acc[c], col[i], tl);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) part[w][lane + c * WAVE] = acc[c];
+  for (int c = 0; c < MAXCH; ++c) part[w][lane + c * WAVE] = acc[c];
   __syncthreads();
   for (int i = threadIdx.x; i < m; i += WG) {
     T s = part[0][i];
@@ -290,24 +302,46 @@ __global__ void __launch_bounds__(WG) leaf_apply_kernel(
   }
 }
 
+template <class T, bool OTF, int MAXCH>
+void leaf_apply_launch(int n_leaves, const int32_t* leaves, const int32_t* nbegin,
+                       const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
+                       const int32_t* near_n, const int64_t* near_off, const T* near_pool,
+                       const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
+                       const T* tbuf, const T* xp, const int32_t* perm, int64_t y_rows, T* y,
+                       hipStream_t s, const NearOtf& o) {
+  hipLaunchKernelGGL((leaf_apply_kernel<T, OTF, MAXCH>), dim3(n_leaves), dim3(WG), 0, s, leaves,
+                     nbegin, nend, near_ptr, near_sb, near_n, near_off, near_pool, far_ptr,
+                     far_list, far, tbuf, xp, perm, y_rows, y, o);
+  HMX_LAUNCHED();
+}
+
 template <class T>
 void launch_leaf_apply(int n_leaves, const int32_t* leaves, const int32_t* nbegin,
                        const int32_t* nend, const int64_t* near_ptr, const int32_t* near_sb,
                        const int32_t* near_n, const int64_t* near_off, const T* near_pool,
                        const int64_t* far_ptr, const int32_t* far_list, const FarRec* far,
                        const T* tbuf, const T* xp, const int32_t* perm, int64_t y_rows, T* y,
-                       hipStream_t s, const NearOtfArgs* otf) {
+                       int max_leaf_rows, hipStream_t s, const NearOtfArgs* otf) {
+  if (n_leaves <= 0) return;
+  HMX_REQUIRE(max_leaf_rows >= 1 && max_leaf_rows <= MAX_LEAF_CHUNKS * WAVE, HMX_EINTERNAL,
+              "leaf rows outside [1, 256]");
   NearOtf o{};
   if (otf) o = NearOtf{otf->X, otf->Y, otf->Z, otf->W, otf->kern, otf->kp};
-  if (otf)
-    hipLaunchKernelGGL((leaf_apply_kernel<T, true>), dim3(n_leaves), dim3(WG), 0, s, leaves,
-                       nbegin, nend, near_ptr, near_sb, near_n, near_off, near_pool, far_ptr,
-                       far_list, far, tbuf, xp, perm, y_rows, y, o);
-  else
-    hipLaunchKernelGGL((leaf_apply_kernel<T, false>), dim3(n_leaves), dim3(WG), 0, s, leaves,
-                       nbegin, nend, near_ptr, near_sb, near_n, near_off, near_pool, far_ptr,
-                       far_list, far, tbuf, xp, perm, y_rows, y, o);
-  HMX_LAUNCHED();
+  const int ch = (max_leaf_rows + WAVE - 1) / WAVE;
+#define HMX_LEAF_LAUNCH(OTF, CH)                                                                 \
+  leaf_apply_launch<T, OTF, CH>(n_leaves, leaves, nbegin, nend, near_ptr, near_sb, near_n,       \
+                                near_off, near_pool, far_ptr, far_list, far, tbuf, xp, perm,     \
+                                y_rows, y, s, o)
+  if (otf) {
+    if (ch == 1) HMX_LEAF_LAUNCH(true, 1);
+    else if (ch == 2) HMX_LEAF_LAUNCH(true, 2);
+    else HMX_LEAF_LAUNCH(true, 4);
+  } else {
+    if (ch == 1) HMX_LEAF_LAUNCH(false, 1);
+    else if (ch == 2) HMX_LEAF_LAUNCH(false, 2);
+    else HMX_LEAF_LAUNCH(false, 4);
+  }
+#undef HMX_LEAF_LAUNCH
 }
 
 // ---------------------------------------------------------- several vectors at once (NR = 2, 4)
@@ -335,8 +369,9 @@ __global__ void __launch_bounds__(WG) far_vt_multi_kernel(const FarRec* __restri
   }
   const int n = f.n, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int64_t ldv = f.ldv;
-  auto colv = [&](int l) -> const T* {
-    return l < f.split ? (const T*)f.V + l * ldv : (const T*)f.V1 + (l - f.split) * ldv;
+  using gT = HMX_GLOBAL T;  // factor addresses read from the record: global space
+  auto colv = [&](int l) -> const gT* {
+    return l < f.split ? (const gT*)f.V + l * ldv : (const gT*)f.V1 + (l - f.split) * ldv;
   };
   int l = w;
   for (; l + 3 * NWAVE < f.r; l += 4 * NWAVE) {
@@ -345,7 +380,7 @@ __global__ void __launch_bounds__(WG) far_vt_multi_kernel(const FarRec* __restri
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int r = 0; r < NR; ++r) a[c][r] = czero<T>();
-    const T* v[4] = {colv(l), colv(l + NWAVE), colv(l + 2 * NWAVE), colv(l + 3 * NWAVE)};
+    const gT* v[4] = {colv(l), colv(l + NWAVE), colv(l + 2 * NWAVE), colv(l + 3 * NWAVE)};
     for (int j = lane; j < n; j += WAVE) {
       T p[4];
 #pragma unroll
@@ -369,8 +404,8 @@ __global__ void __launch_bounds__(WG) far_vt_multi_kernel(const FarRec* __restri
     T a0[NR], a1[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) a0[r] = a1[r] = czero<T>();
-    const T* v0 = colv(l);
-    const T* v1 = colv(l + NWAVE);
+    const gT* v0 = colv(l);
+    const gT* v1 = colv(l + NWAVE);
 #pragma unroll 2
     for (int j = lane; j < n; j += WAVE) {
       const T p0 = v0[j], p1 = v1[j];
@@ -395,7 +430,7 @@ __global__ void __launch_bounds__(WG) far_vt_multi_kernel(const FarRec* __restri
     T a0[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) a0[r] = czero<T>();
-    const T* v0 = colv(l);
+    const gT* v0 = colv(l);
 #pragma unroll 2
     for (int j = lane; j < n; j += WAVE) {
       const T p0 = v0[j];
@@ -456,8 +491,9 @@ __global__ void __launch_bounds__(WG) leaf_apply_multi_kernel(
       } else {
         const FarRec f = far[far_list[f0 + (it - nn)]];
         const int o = tb - f.tb;
-        const T* U = (const T*)f.U + o + i;
-        const T* U1 = (const T*)f.U1 + o + i;
+        using gT = HMX_GLOBAL T;
+        const gT* U = (const gT*)f.U + o + i;
+        const gT* U1 = (const gT*)f.U1 + o + i;
         const T* tt = tbuf + f.toff;
 #pragma unroll 4
         for (int l = 0; l < f.r; ++l) {
@@ -497,15 +533,16 @@ __global__ void __launch_bounds__(WG) leaf_apply_multi_kernel(
     } else {
       const FarRec f = far[far_list[f0 + (it - nn)]];
       const int o = tb - f.tb;
-      const T* U = (const T*)f.U + o;
+      using gT = HMX_GLOBAL T;
+      const gT* U = (const gT*)f.U + o;
       const T* tt = tbuf + f.toff;
 #pragma unroll 2
       for (int l = 0; l < f.r; ++l) {
         T tl[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) tl[r] = tt[r * ldt + l];
-        const T* col = l < f.split ? U + (int64_t)l * f.ldu
-                                   : (const T*)f.U1 + o + (int64_t)(l - f.split) * f.ldu;
+        const gT* col = l < f.split ? U + (int64_t)l * f.ldu
+                                    : (const gT*)f.U1 + o + (int64_t)(l - f.split) * f.ldu;
 #pragma unroll
         for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
           const int i = lane + c * WAVE;
@@ -649,7 +686,7 @@ void launch_dense_otf(const double* X, const double* Y, const double* Z, const d
                                      const int64_t*, const int32_t*, const int32_t*,             \
                                      const int64_t*, const T*, const int64_t*, const int32_t*,   \
                                      const FarRec*, const T*, const T*, const int32_t*, int64_t, \
-                                     T*, hipStream_t, const NearOtfArgs*);                       \
+                                     T*, int, hipStream_t, const NearOtfArgs*);                  \
   template void launch_dense_otf<T>(const double*, const double*, const double*, const double*,  \
                                     int64_t, int64_t, int64_t, int, double, const T*, T*, T*,    \
                                     hipStream_t);                                                \
