@@ -146,9 +146,10 @@ struct NearOtf {
 template <class T, int NCH>
 __device__ __forceinline__ void far_cols(T (&a)[NCH], const int (&row)[NCH], const T* colp,
                                          int64_t ld, const T* __restrict__ tt, int nc) {
+  constexpr int UNR = 8 / NCH;  // columns per unrolled round (8 loads in flight per lane)
   using gT = HMX_GLOBAL T;
   const gT* col = (const gT*)colp;
-#pragma unroll(8 / NCH)
+#pragma unroll UNR
   for (int l = 0; l < nc; ++l, col += ld) {
     const T tl = tt[l];
 #pragma unroll
@@ -167,6 +168,7 @@ __device__ __forceinline__ void leaf_blocks(
     const int32_t* __restrict__ near_n, const int64_t* __restrict__ near_off,
     const T* __restrict__ near_pool, const int32_t* __restrict__ far_list,
     const FarRec* __restrict__ far, const T* __restrict__ tbuf, const T* __restrict__ xp) {
+  constexpr int UNR = 8 / NCH;  // near-block columns per unrolled round
   T a[NCH];
   int row[NCH];
 #pragma unroll
@@ -180,7 +182,7 @@ __device__ __forceinline__ void leaf_blocks(
       const int sb = near_sb[blk], n = near_n[blk];
       const T* K = near_pool + near_off[blk];
       const T* xs = xp + sb;
-#pragma unroll(8 / NCH)
+#pragma unroll UNR
       for (int j = 0; j < n; ++j) {
         const T xj = xs[j];
         const T* col = K + (int64_t)j * m;
@@ -448,7 +450,85 @@ __global__ void __launch_bounds__(WG) far_vt_multi_kernel(const FarRec* __restri
   }
 }
 
-template <class T, int NR>
+// a[c][r] += sum_{l < nc} col_l[row[c]] tt[r ldt + l], col_l = col + l ld (one segment of U).
+template <class T, int NR, int NCH>
+__device__ __forceinline__ void far_cols_multi(T (&a)[NCH][NR], const int (&row)[NCH],
+                                               const T* colp, int64_t ld,
+                                               const T* __restrict__ tt, int64_t ldt, int nc) {
+  constexpr int UNR = NCH < 4 ? 4 / NCH : 1;  // columns per unrolled round
+  using gT = HMX_GLOBAL T;
+  const gT* col = (const gT*)colp;
+#pragma unroll UNR
+  for (int l = 0; l < nc; ++l, col += ld) {
+    T tl[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tl[r] = tt[r * ldt + l];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const T uil = col[row[c]];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cfma(a[c][r], uil, tl[r]);
+    }
+  }
+}
+
+// The blocks of one leaf for NR vectors, as leaf_blocks does for one: the same order of sums per
+// vector, condition-free loads (lanes past the leaf's rows read its last row and drop the sums).
+template <class T, int NR, int NCH, int MAXCH>
+__device__ __forceinline__ void leaf_blocks_multi(
+    T (&acc)[MAXCH][NR], int lane, int w, int m, int tb, int64_t n0, int64_t nn, int64_t f0,
+    int64_t nfar, const int32_t* __restrict__ near_sb, const int32_t* __restrict__ near_n,
+    const int64_t* __restrict__ near_off, const T* __restrict__ near_pool,
+    const int32_t* __restrict__ far_list, const FarRec* __restrict__ far,
+    const T* __restrict__ tbuf, int64_t ldt, const T* __restrict__ xp, int64_t ldx) {
+  constexpr int UNR = NCH < 4 ? 4 / NCH : 1;  // near-block columns per unrolled round
+  T a[NCH][NR];
+  int row[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    row[c] = min(lane + c * WAVE, m - 1);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a[c][r] = czero<T>();
+  }
+  for (int64_t it = w; it < nn + nfar; it += NWAVE) {
+    if (it < nn) {
+      const int64_t blk = n0 + it;
+      const int sb = near_sb[blk], n = near_n[blk];
+      const T* K = near_pool + near_off[blk];
+      const T* xs = xp + sb;
+#pragma unroll UNR
+      for (int j = 0; j < n; ++j) {
+        T xj[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) xj[r] = xs[r * ldx + j];
+        const T* col = K + (int64_t)j * m;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const T kij = col[row[c]];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(a[c][r], kij, xj[r]);
+        }
+      }
+    } else {
+      const FarRec f = far[far_list[f0 + (it - nn)]];
+      const int o = tb - f.tb;
+      const T* tt = tbuf + f.toff;
+      // columns below f.split in the first segment of U, the rest in the second
+      const int r0 = min(f.r, f.split);
+      far_cols_multi<T, NR, NCH>(a, row, (const T*)f.U + o, f.ldu, tt, ldt, r0);
+      far_cols_multi<T, NR, NCH>(a, row, (const T*)f.U1 + o, f.ldu, tt + r0, ldt, f.r - r0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const bool on = lane + c * WAVE < m;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[c][r] = on ? a[c][r] : czero<T>();
+  }
+}
+
+// MAXCH: 64-row chunks of the largest leaf, as in leaf_apply_kernel.
+template <class T, int NR, int MAXCH>
 __global__ void __launch_bounds__(WG) leaf_apply_multi_kernel(
     const int32_t* __restrict__ leaves, const int32_t* __restrict__ nbegin,
     const int32_t* __restrict__ nend, const int64_t* __restrict__ near_ptr,
@@ -458,7 +538,7 @@ __global__ void __launch_bounds__(WG) leaf_apply_multi_kernel(
     const FarRec* __restrict__ far, const T* __restrict__ tbuf, int64_t ldt,
     const T* __restrict__ xp, int64_t ldx, const int32_t* __restrict__ perm, int64_t y_rows,
     MultiOut<T> y) {
-  __shared__ T part[NWAVE][MAX_LEAF_CHUNKS * WAVE];
+  __shared__ T part[NWAVE][MAXCH * WAVE];
   const int leaf = blockIdx.x;
   const int node = leaves[leaf];
   const int tb = nbegin[node], m = nend[node] - tb;
@@ -469,100 +549,33 @@ __global__ void __launch_bounds__(WG) leaf_apply_multi_kernel(
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int nch = (m + WAVE - 1) / WAVE;
-  T acc[MAX_LEAF_CHUNKS][NR];
+  T acc[MAXCH][NR];
 #pragma unroll
-  for (int c = 0; c < MAX_LEAF_CHUNKS; ++c)
+  for (int c = 0; c < MAXCH; ++c)
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[c][r] = czero<T>();
-  if (nch == 1) {
-    // leaves of at most 64 rows: one row per lane, more loads in flight (lanes past the leaf's
-    // rows read row 0 and discard it); the same summation order as the general path
-    const bool on = lane < m;
-    const int i = on ? lane : 0;
-    for (int64_t it = w; it < nn + nfar; it += NWAVE) {
-      if (it < nn) {
-        const int64_t blk = n0 + it;
-        const int sb = near_sb[blk], n = near_n[blk];
-        const T* K = near_pool + near_off[blk] + i;
-        const T* xs = xp + sb;
-#pragma unroll 4
-        for (int j = 0; j < n; ++j) {
-          const T kij = K[(int64_t)j * m];
-#pragma unroll
-          for (int r = 0; r < NR; ++r) cfma(acc[0][r], kij, xs[r * ldx + j]);
-        }
-      } else {
-        const FarRec f = far[far_list[f0 + (it - nn)]];
-        const int o = tb - f.tb;
-        using gT = HMX_GLOBAL T;
-        const gT* U = (const gT*)f.U + o + i;
-        const gT* U1 = (const gT*)f.U1 + o + i;
-        const T* tt = tbuf + f.toff;
-#pragma unroll 4
-        for (int l = 0; l < f.r; ++l) {
-          const T uil = l < f.split ? U[(int64_t)l * f.ldu] : U1[(int64_t)(l - f.split) * f.ldu];
-#pragma unroll
-          for (int r = 0; r < NR; ++r) cfma(acc[0][r], uil, tt[r * ldt + l]);
-        }
-      }
-    }
-    if (!on) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[0][r] = czero<T>();
-    }
-  } else
-  for (int64_t it = w; it < nn + nfar; it += NWAVE) {
-    if (it < nn) {
-      const int64_t blk = n0 + it;
-      const int sb = near_sb[blk], n = near_n[blk];
-      const T* K = near_pool + near_off[blk];
-      const T* xs = xp + sb;
-#pragma unroll 2
-      for (int j = 0; j < n; ++j) {
-        T xj[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) xj[r] = xs[r * ldx + j];
-        const T* col = K + (int64_t)j * m;
-#pragma unroll
-        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
-          const int i = lane + c * WAVE;
-          if (c < nch && i < m) {
-            const T kij = col[i];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) cfma(acc[c][r], kij, xj[r]);
-          }
-        }
-      }
-    } else {
-      const FarRec f = far[far_list[f0 + (it - nn)]];
-      const int o = tb - f.tb;
-      using gT = HMX_GLOBAL T;
-      const gT* U = (const gT*)f.U + o;
-      const T* tt = tbuf + f.toff;
-#pragma unroll 2
-      for (int l = 0; l < f.r; ++l) {
-        T tl[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) tl[r] = tt[r * ldt + l];
-        const gT* col = l < f.split ? U + (int64_t)l * f.ldu
-                                    : (const gT*)f.U1 + o + (int64_t)(l - f.split) * f.ldu;
-#pragma unroll
-        for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) {
-          const int i = lane + c * WAVE;
-          if (c < nch && i < m) {
-            const T uil = col[i];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) cfma(acc[c][r], uil, tl[r]);
-          }
-        }
-      }
-    }
-  }
+  if (MAXCH == 1 || nch == 1)
+    leaf_blocks_multi<T, NR, 1, MAXCH>(acc, lane, w, m, tb, n0, nn, f0, nfar, near_sb, near_n,
+                                       near_off, near_pool, far_list, far, tbuf, ldt, xp, ldx);
+  else if (MAXCH == 2 || nch == 2)
+    leaf_blocks_multi<T, NR, (MAXCH < 2 ? MAXCH : 2), MAXCH>(acc, lane, w, m, tb, n0, nn, f0,
+                                                             nfar, near_sb, near_n, near_off,
+                                                             near_pool, far_list, far, tbuf, ldt,
+                                                             xp, ldx);
+  else if (MAXCH == 3 || nch == 3)
+    leaf_blocks_multi<T, NR, (MAXCH < 3 ? MAXCH : 3), MAXCH>(acc, lane, w, m, tb, n0, nn, f0,
+                                                             nfar, near_sb, near_n, near_off,
+                                                             near_pool, far_list, far, tbuf, ldt,
+                                                             xp, ldx);
+  else
+    leaf_blocks_multi<T, NR, MAXCH, MAXCH>(acc, lane, w, m, tb, n0, nn, f0, nfar, near_sb, near_n,
+                                           near_off, near_pool, far_list, far, tbuf, ldt, xp,
+                                           ldx);
   // one vector at a time through the same LDS buffer
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
 #pragma unroll
-    for (int c = 0; c < MAX_LEAF_CHUNKS; ++c) part[w][lane + c * WAVE] = acc[c][r];
+    for (int c = 0; c < MAXCH; ++c) part[w][lane + c * WAVE] = acc[c][r];
     __syncthreads();
     for (int i = threadIdx.x; i < m; i += WG) {
       T s = part[0][i];
@@ -584,6 +597,9 @@ template <class T>
 void launch_matvec_multi(const hmx_op* op, int nr, const T* const* x, T* const* y, T* xpm, T* tm,
                          hipStream_t s) {
   const int64_t M = op->M, ldt = std::max<int64_t>(op->t_len, 1);
+  HMX_REQUIRE(op->max_leaf_rows >= 1 && op->max_leaf_rows <= MAX_LEAF_CHUNKS * WAVE,
+              HMX_EINTERNAL, "leaf rows outside [1, 256]");
+  const int ch = (op->max_leaf_rows + WAVE - 1) / WAVE;
   MultiOut<T> out{};
   for (int r = 0; r < nr; ++r) {
     launch_gather<T>(x[r], op->perm.p, xpm + r * M, M, op->x_off, s);
@@ -596,11 +612,22 @@ void launch_matvec_multi(const hmx_op* op, int nr, const T* const* x, T* const* 
                          op->far.p, xpm, M, tm, ldt);
       HMX_LAUNCHED();
     }
-    hipLaunchKernelGGL((leaf_apply_multi_kernel<T, NR>), dim3(op->n_leaves), dim3(WG), 0, s,
-                       op->leaves.p, op->nbegin.p, op->nend.p, op->near_ptr.p, op->near_sb.p,
-                       op->near_n.p, op->near_off.p, (const T*)op->near_pool.p, op->far_ptr.p,
-                       op->far_list.p, op->far.p, tm, ldt, xpm, M, op->perm.p, op->rows, out);
-    HMX_LAUNCHED();
+    auto leaves = [&](auto chc) {
+      constexpr int CH = decltype(chc)::value;
+      hipLaunchKernelGGL((leaf_apply_multi_kernel<T, NR, CH>), dim3(op->n_leaves), dim3(WG), 0,
+                         s, op->leaves.p, op->nbegin.p, op->nend.p, op->near_ptr.p,
+                         op->near_sb.p, op->near_n.p, op->near_off.p, (const T*)op->near_pool.p,
+                         op->far_ptr.p, op->far_list.p, op->far.p, tm, ldt, xpm, M, op->perm.p,
+                         op->rows, out);
+      HMX_LAUNCHED();
+    };
+    if (op->n_leaves <= 0) return;
+    if (ch == 1)
+      leaves(std::integral_constant<int, 1>{});
+    else if (ch == 2)
+      leaves(std::integral_constant<int, 2>{});
+    else
+      leaves(std::integral_constant<int, 4>{});
   };
   if (nr == 2)
     go(std::integral_constant<int, 2>{});
