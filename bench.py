@@ -338,7 +338,8 @@ def run_batch(args, torch, oracle, hmx, I):
     bary, w = I.rule_3pt()
     prec = hmx.FP64 if args.precision == "fp64" else hmx.FP32_MIXED
     cdt = torch.complex128 if prec == hmx.FP64 else torch.complex64
-    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec)
+    prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec,
+                     near_mode=int(args.near_mode == "otf"))
     meshes, dev = [], []
     for d in descs:
         v, f = I.batch_mesh(d)
@@ -393,12 +394,14 @@ def run_batch(args, torch, oracle, hmx, I):
                             ("t_tree_ms", "t_blocks_ms", "t_near_ms", "t_aca_ms")},
         "sizes": sizes(info),
     }
-    extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision))
+    extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision,
+                           near_stored=prm.near_mode == 0))
     extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
     extra["cpu_baseline"] = cpu
     op.close()
     config = {"workload": f"64 seeded ellipsoids ({M} points), Helmholtz k U[2,30], leaf 64, "
-                          f"eta 1.5, ACA tol 1e-3, one block-diagonal operator, {args.precision}"}
+                          f"eta 1.5, ACA tol 1e-3, one block-diagonal operator, {args.precision}"
+                          + (", near field computed in the product" if prm.near_mode else "")}
     line(args, ms_step, args.precision, config, extra)
 
 
@@ -464,13 +467,14 @@ def run_target(args, torch, oracle, hmx, I):
                "aca_rounds": info["aca_rounds"], "predicted_entries": info["predicted_entries"]}
         return res, info, aca, mv, op
 
-    plain_prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=hmx.FP64)
+    nm = int(args.near_mode == "otf")  # the same near-field policy in both forms
+    plain_prm = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=hmx.FP64, near_mode=nm)
     plain, _, _, _, op = measure(plain_prm, "plain FP64 batch")
     op.close()
     model.install()
     try:
         base = hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=hmx.FP32_MIXED,
-                          rank_model=hmx.RANK_LEARNED)
+                          rank_model=hmx.RANK_LEARNED, near_mode=nm)
         t0 = time.perf_counter()
         tuned, tune_ms = hmx.autotune_batch(dev, bary, w, kern=hmx.HELMHOLTZ, prm=base,
                                             cache_path=args.tune_cache, stream=stream)
@@ -507,7 +511,7 @@ def run_target(args, torch, oracle, hmx, I):
                        "alpha": model.alpha, "beta": model.beta,
                        "final_loss": float(model.history[-1])},
     }
-    extra.update(rooflines(info, aca, mv, M, 8, "fp32"))
+    extra.update(rooflines(info, aca, mv, M, 8, "fp32", near_stored=nm == 0))
     extra["roofline"]["traffic"] = None  # counters were taken on the sphere workload
     op.close()
     cpu = None
@@ -532,7 +536,8 @@ def run_target(args, torch, oracle, hmx, I):
     config = {"workload": f"64 seeded ellipsoids ({M} points), Helmholtz k U[2,30], leaf 64, "
                           "eta 1.5, ACA tol 1e-3: FP32 mixed + learned rank layout (network "
                           "trained on the L6 sphere's FP64 and FP32 ranks) + autotuned batch "
-                          "schedule, against the plain FP64 batch"}
+                          "schedule, against the plain FP64 batch"
+                          + (" (both with the near field computed in the product)" if nm else "")}
     line(args, tgt["ms_per_step"], "fp32", config, extra)
 
 
@@ -1136,8 +1141,9 @@ def main():
     ap.add_argument("--cpu-one-core", choices=["on", "off"], default="off",
                     help="sphere workload: also time the oracle on one core (about a minute)")
     ap.add_argument("--near-mode", choices=["stored", "otf"], default="otf",
-                    help="sphere workload: near blocks computed in each product (near_mode 1, the "
-                         "default: faster per step and no near-field memory) or stored in the build")
+                    help="sphere, batch and target workloads: near blocks computed in each product "
+                         "(near_mode 1, the default: faster per step and no near-field memory) or "
+                         "stored in the build")
     ap.add_argument("--multi-vectors", type=int, default=0,
                     help="sphere workload: also time the several-vector product for 2, 4, 8, 16 "
                          "vectors up to this many")

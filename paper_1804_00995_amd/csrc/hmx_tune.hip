@@ -44,6 +44,7 @@ std::string class_key(int64_t M, int32_t kern, const hmx_params& p, int32_t n_me
   if (n_meshes > 0) o << "|batch" << n_meshes;
   o << "|M2^" << lm << "|tol1e" << te << "|leaf" << p.leaf_size << "|eta" << p.eta;
   if (p.rank_model == HMX_RANK_LEARNED) o << "|learned";
+  if (p.near_mode == 1) o << "|nearotf";  // no near-field assembly in the timed builds
   return o.str();
 }
 

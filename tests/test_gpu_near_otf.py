@@ -128,3 +128,23 @@ def test_correction_needs_stored_blocks(H):
     with pytest.raises(H.HmxError) as e:
         H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=3.0, prm=H.params(near_mode=2))
     assert e.value.code == H.EINVAL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_stored_near_field(H, precision):
+    # a batch of meshes with their own wavenumbers: each leaf takes its mesh's k
+    descs = I.batch_ellipsoids(5, seed=7, t_min=300, t_max=2500)
+    meshes = []
+    for d in descs:
+        v, f = I.batch_mesh(d)
+        meshes.append((torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda(), d["k"]))
+    kw = dict(tol=1e-4, precision=precision)
+    st = H.build_batch(meshes, *RULE, kern=H.HELMHOLTZ, prm=H.params(**kw))
+    ot = H.build_batch(meshes, *RULE, kern=H.HELMHOLTZ, prm=H.params(near_mode=1, **kw))
+    assert ot.info["near_entries"] == st.info["near_entries"] > 0
+    M = int(st.mesh_offsets()[-1])
+    x = I.complex_vector(M, 11)
+    ys, yo = apply(st, x), apply(ot, x)
+    assert rel(yo, ys) <= (1e-13 if precision == 0 else 2e-6)
+    st.close()
+    ot.close()
