@@ -146,6 +146,9 @@ typedef struct {
    * operators (tol <= 0), whose product is always computed on the fly.  With near_mode = 1,
    * hmx_matvec_multi applies the operator one vector at a time. */
   int32_t near_mode;
+  /* > 0: initial capacity, in pairs, of the block recursion's frontier and list buffers (tests
+   * force the path that enlarges them and runs the recursion again); 0: from the leaf count. */
+  int64_t force_block_cap;
 } hmx_params;
 
 /* Fills `p` with the defaults: tol 1e-3, leaf 64, eta 1.5, FP64, adaptive ranks,

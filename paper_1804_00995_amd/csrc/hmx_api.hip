@@ -73,6 +73,7 @@ void defaults(hmx_params* p) {
   p->regularize = 0;
   p->reg_radius = 2.0;
   p->near_mode = 0;
+  p->force_block_cap = 0;
 }
 
 hmx_params resolve(const hmx_params* in) {
@@ -124,6 +125,7 @@ hmx_params resolve(const hmx_params* in) {
   HMX_REQUIRE(p.regularize == 0 || p.tol > 0, HMX_EUNSUPPORTED,
               "the singular correction needs an H-matrix operator (tol > 0)");
   HMX_REQUIRE(p.near_mode == 0 || p.near_mode == 1, HMX_EINVAL, "near_mode must be 0 or 1");
+  HMX_REQUIRE(p.force_block_cap >= 0, HMX_EINVAL, "force_block_cap must be >= 0");
   HMX_REQUIRE(p.near_mode == 0 || p.regularize == 0, HMX_EUNSUPPORTED,
               "near_mode 1 (near field computed in the product) cannot carry the singular "
               "correction, which is assembled into stored near blocks");

@@ -243,11 +243,6 @@ void sort_pairs(hmx_op* op, DevBuf<int2>& nearL, int64_t nn, DevBuf<int2>& farL,
 // ------------------------------------------------------------------------------ block tree
 void build_blocks(hmx_op* op, hipStream_t s) {
   const double eta2 = op->p.eta * op->p.eta;
-  size_t fcap = 1024, ncap = std::max<size_t>(1024, 64 * (size_t)op->n_leaves),
-         xcap = std::max<size_t>(1024, 64 * (size_t)op->n_leaves);
-  DevBuf<int2> front(fcap), next(fcap), nearL(ncap), farL(xcap);
-  DevBuf<int> cnt(4);  // next, near, far, error flag
-  fill_i32(cnt.p, 0, 4, s);
   // row share: the point range of node number row_share at tree level log2(row_shares)
   int rb = 0, re = (int)op->M;
   if (op->p.row_shares > 1) {
@@ -274,34 +269,59 @@ void build_blocks(hmx_op* op, hipStream_t s) {
   const int nroot = op->rect ? 1 : (int)op->mesh_off.size() - 1;
   std::vector<int2> roots(nroot);
   for (int i = 0; i < nroot; ++i) roots[i] = op->rect ? make_int2(0, 1) : make_int2(i, i);
-  if ((size_t)nroot > front.n) front.alloc(nroot);
-  HMX_HIP(hipMemcpyAsync(front.p, roots.data(), sizeof(int2) * nroot, hipMemcpyHostToDevice, s));
-  HMX_HIP(hipStreamSynchronize(s));
-  int64_t nfront = nroot, n_near = 0, n_far = 0;
-  while (nfront > 0) {
-    if ((size_t)(4 * nfront) > next.n) {
-      next.alloc(std::max<size_t>(4 * nfront, 2 * next.n));
-    }
-    if (nearL.n < (size_t)(n_near + nfront)) grow(nearL, 2 * (n_near + nfront), n_near, s);
-    if (farL.n < (size_t)(n_far + nfront)) grow(farL, 2 * (n_far + nfront), n_far, s);
-    fill_i32(cnt.p, 0, 1, s);
-    launch_block_level(front.p, (int)nfront, op->box.p, op->child0.p, op->child1.p,
-                       op->nbegin.p, op->nend.p, rb, re, eta2, op->p.max_far_mn, next.p, cnt.p,
-                       nearL.p, cnt.p + 1,
-                       farL.p, cnt.p + 2, cnt.p + 3, s);
-    int c[4];
-    HMX_HIP(hipMemcpyAsync(c, cnt.p, sizeof(c), hipMemcpyDeviceToHost, s));
-    HMX_HIP(hipStreamSynchronize(s));
-    HMX_REQUIRE(c[3] == 0, HMX_EUNSUPPORTED,
-                "a block crosses the row-share boundary (use fewer row shares)");
-    nfront = c[0];
-    n_near = c[1];
-    n_far = c[2];
-    std::swap(front, next);
+  // Every level descends all non-leaf sides of its pairs, so the recursion ends within the
+  // tree's depth: all levels are queued at once and the sizes read back once.  Buffers that
+  // turn out too small (the counters still count what was dropped) are enlarged and the
+  // recursion runs again.
+  const int levels = op->depth;
+  HMX_REQUIRE(levels >= 1, HMX_EINTERNAL, "empty cluster tree");
+  const int64_t nl = op->n_leaves;
+  int64_t fcap = std::max<int64_t>({1024, 32 * nl, 2 * (int64_t)nroot});
+  int64_t ncap = std::max<int64_t>(1024, 64 * nl), xcap = std::max<int64_t>(1024, 64 * nl);
+  if (op->p.force_block_cap > 0) {
+    fcap = std::max<int64_t>(op->p.force_block_cap, nroot);
+    ncap = xcap = op->p.force_block_cap;
   }
-  op->n_near = n_near;
-  op->n_far = n_far;
-  sort_pairs(op, nearL, n_near, farL, n_far, s);
+  // counters: [L] pairs after level L, [levels] near, [levels + 1] far, [levels + 2] error
+  // bits, [levels + 3] the roots
+  DevBuf<int> cnt(levels + 4);
+  std::vector<int> c(levels + 4);
+  DevBuf<int2> buf[2], nearL, farL;
+  for (int attempt = 0;; ++attempt) {
+    HMX_REQUIRE(attempt < 64, HMX_EINTERNAL, "block recursion buffers did not converge");
+    buf[0].alloc(fcap);
+    buf[1].alloc(fcap);
+    nearL.alloc(ncap);
+    farL.alloc(xcap);
+    fill_i32(cnt.p, 0, levels + 3, s);
+    fill_i32(cnt.p + levels + 3, nroot, 1, s);
+    HMX_HIP(hipMemcpyAsync(buf[0].p, roots.data(), sizeof(int2) * nroot, hipMemcpyHostToDevice,
+                           s));
+    for (int L = 0; L < levels; ++L)
+      launch_block_level(buf[L & 1].p, L == 0 ? cnt.p + levels + 3 : cnt.p + L - 1, fcap,
+                         op->box.p, op->child0.p, op->child1.p, op->nbegin.p, op->nend.p, rb, re,
+                         eta2, op->p.max_far_mn, buf[(L + 1) & 1].p, fcap, cnt.p + L, nearL.p,
+                         ncap, cnt.p + levels, farL.p, xcap, cnt.p + levels + 1,
+                         cnt.p + levels + 2, s);
+    HMX_HIP(hipMemcpyAsync(c.data(), cnt.p, sizeof(int) * (levels + 3), hipMemcpyDeviceToHost, s));
+    HMX_HIP(hipStreamSynchronize(s));
+    const int err = c[levels + 2];
+    HMX_REQUIRE((err & 1) == 0, HMX_EUNSUPPORTED,
+                "a block crosses the row-share boundary (use fewer row shares)");
+    if (err & 2) {
+      int64_t fmax = 0;
+      for (int L = 0; L < levels; ++L) fmax = std::max<int64_t>(fmax, c[L]);
+      fcap = std::max<int64_t>(2 * fcap, 2 * fmax);
+      ncap = std::max<int64_t>(2 * ncap, 2 * (int64_t)c[levels]);
+      xcap = std::max<int64_t>(2 * xcap, 2 * (int64_t)c[levels + 1]);
+      continue;
+    }
+    HMX_REQUIRE(c[levels - 1] == 0, HMX_EINTERNAL, "block recursion deeper than the cluster tree");
+    break;
+  }
+  op->n_near = c[levels];
+  op->n_far = c[levels + 1];
+  sort_pairs(op, nearL, op->n_near, farL, op->n_far, s);
   op->nearL = std::move(nearL);
   op->farL = std::move(farL);
 }

@@ -199,11 +199,13 @@ void launch_start_node(int n_nodes, const int32_t* nbegin, const int32_t* child0
                        int32_t* start_node, hipStream_t s);
 void launch_leaf_index(int n_leaves, const int32_t* leaves, int32_t* leaf_of_node, hipStream_t s);
 // k_blocks.hip
-void launch_block_level(const int2* front, int nfront, const double* box, const int32_t* child0,
-                        const int32_t* child1, const int32_t* nbegin, const int32_t* nend, int rb,
-                        int re, double eta2, int max_mn, int2* next, int* next_cnt,
-                        int2* nearL, int* near_cnt, int2* farL, int* far_cnt, int* err,
-                        hipStream_t s);
+// one level of the block recursion; nfront is a device counter (see k_blocks.hip)
+void launch_block_level(const int2* front, const int* nfront, int64_t front_cap,
+                        const double* box, const int32_t* child0, const int32_t* child1,
+                        const int32_t* nbegin, const int32_t* nend, int rb, int re, double eta2,
+                        int max_mn, int2* next, int64_t next_cap, int* next_cnt, int2* nearL,
+                        int64_t near_cap, int* near_cnt, int2* farL, int64_t far_cap,
+                        int* far_cnt, int* err, hipStream_t s);
 void launch_node_rank(const int32_t* nbegin, const int32_t* level, int n_nodes, int64_t M,
                       int64_t* cnt, int64_t* start, int32_t* deep, int32_t* rank, hipStream_t s);
 void launch_pair_rank_keys(const int2* pairs, int64_t n, const int32_t* rank, int64_t n_nodes,

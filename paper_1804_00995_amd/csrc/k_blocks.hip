@@ -6,8 +6,10 @@
 // (root, root), a pair is far (admissible) when min(diam_t^2, diam_s^2) <= eta^2 dist^2; otherwise
 // it is near when both nodes are leaves; otherwise the non-leaf side(s) are split into their
 // children (2 or 4 pairs).  The traversal is level synchronous: one thread per pair of the
-// current frontier.  Compiled without floating-point contraction so that the squared sizes are
+// current frontier, every level queued by the host before any size is read back.  Compiled without floating-point contraction so that the squared sizes are
 // evaluated exactly as written.
+#include <algorithm>
+
 #include "hmx_dev.h"
 #include "hmx_host.h"
 
@@ -31,66 +33,100 @@ __device__ __forceinline__ double dist2(const double* a, const double* b) {
 
 // Row shares: only pairs whose row node meets the point range [rb, re) (cluster positions) are
 // followed, and a block is emitted only when its row node lies inside the range; a block that
-// would straddle the range sets *err (the caller picks the range as a node below every emitted
-// block).  rb = 0, re = M keeps everything.
+// would straddle the range sets bit 1 of *err (the caller picks the range as a node below every
+// emitted block).  rb = 0, re = M keeps everything.
+//
+// One level of the recursion.  Its frontier size is read from the device (*nfront_p, of which
+// at most front_cap pairs are in `front`) and the pairs are taken in a grid-stride loop, so the
+// host queues every level without reading a size back.  An output past its buffer's capacity
+// is dropped and sets bit 2 of *err; the counters still count it, so the host learns the sizes
+// it needs and runs the recursion again with larger buffers.
 __global__ void __launch_bounds__(WG) block_level_kernel(
-    const int2* __restrict__ front, int nfront, const double* __restrict__ box,
-    const int32_t* __restrict__ child0, const int32_t* __restrict__ child1,
-    const int32_t* __restrict__ nbegin, const int32_t* __restrict__ nend, int rb, int re,
-    double eta2, int max_mn, int2* __restrict__ next, int* next_cnt, int2* __restrict__ nearL,
-    int* near_cnt, int2* __restrict__ farL, int* far_cnt, int* err) {
-  int i = blockIdx.x * WG + threadIdx.x;
-  if (i >= nfront) return;
-  int2 ts = front[i];
-  int t = ts.x, s = ts.y;
-  const int tb = nbegin[t], te = nend[t];
-  if (te <= rb || tb >= re) return;  // rows outside the share
-  const bool inside = tb >= rb && te <= re;
-  const double* bt = box + 6 * (int64_t)t;
-  const double* bs = box + 6 * (int64_t)s;
-  double dt = diam2(bt), ds = diam2(bs);
-  double dmin = dt < ds ? dt : ds;
-  int t0 = child0[t], s0 = child0[s];
-  bool lt = t0 < 0, ls = s0 < 0;
-  // an admissible pair is far unless it exceeds max_mn points (then its children are taken,
-  // down to leaf pairs, which are far whatever their size)
-  const bool small = max_mn <= 0 || (te - tb) + (nend[s] - nbegin[s]) <= max_mn || (lt && ls);
-  if (small && dmin <= eta2 * dist2(bt, bs)) {
-    if (inside) farL[atomicAdd(far_cnt, 1)] = ts;
-    else atomicOr(err, 1);
-    return;
-  }
-  if (!small && lt && ls) return;  // unreachable: leaf pairs are small
-  if (lt && ls) {
-    if (inside) nearL[atomicAdd(near_cnt, 1)] = ts;
-    else atomicOr(err, 1);
-  } else if (lt) {
-    int q = atomicAdd(next_cnt, 2);
-    next[q] = make_int2(t, s0);
-    next[q + 1] = make_int2(t, child1[s]);
-  } else if (ls) {
-    int q = atomicAdd(next_cnt, 2);
-    next[q] = make_int2(t0, s);
-    next[q + 1] = make_int2(child1[t], s);
-  } else {
-    int t1 = child1[t], s1 = child1[s];
-    int q = atomicAdd(next_cnt, 4);
-    next[q] = make_int2(t0, s0);
-    next[q + 1] = make_int2(t0, s1);
-    next[q + 2] = make_int2(t1, s0);
-    next[q + 3] = make_int2(t1, s1);
+    const int2* __restrict__ front, const int* __restrict__ nfront_p, int64_t front_cap,
+    const double* __restrict__ box, const int32_t* __restrict__ child0,
+    const int32_t* __restrict__ child1, const int32_t* __restrict__ nbegin,
+    const int32_t* __restrict__ nend, int rb, int re, double eta2, int max_mn,
+    int2* __restrict__ next, int64_t next_cap, int* next_cnt, int2* __restrict__ nearL,
+    int64_t near_cap, int* near_cnt, int2* __restrict__ farL, int64_t far_cap, int* far_cnt,
+    int* err) {
+  const int64_t nfront = min((int64_t)*nfront_p, front_cap);
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < nfront; i += stride) {
+    const int2 ts = front[i];
+    const int t = ts.x, s = ts.y;
+    const int tb = nbegin[t], te = nend[t];
+    if (te <= rb || tb >= re) continue;  // rows outside the share
+    const bool inside = tb >= rb && te <= re;
+    const double* bt = box + 6 * (int64_t)t;
+    const double* bs = box + 6 * (int64_t)s;
+    const double dt = diam2(bt), ds = diam2(bs);
+    const double dmin = dt < ds ? dt : ds;
+    const int t0 = child0[t], s0 = child0[s];
+    const bool lt = t0 < 0, ls = s0 < 0;
+    // an admissible pair is far unless it exceeds max_mn points (then its children are taken,
+    // down to leaf pairs, which are far whatever their size)
+    const bool small = max_mn <= 0 || (te - tb) + (nend[s] - nbegin[s]) <= max_mn || (lt && ls);
+    if (small && dmin <= eta2 * dist2(bt, bs)) {
+      if (!inside) {
+        atomicOr(err, 1);
+      } else {
+        const int q = atomicAdd(far_cnt, 1);
+        if (q < far_cap) farL[q] = ts;
+        else atomicOr(err, 2);
+      }
+      continue;
+    }
+    if (!small && lt && ls) continue;  // unreachable: leaf pairs are small
+    if (lt && ls) {
+      if (!inside) {
+        atomicOr(err, 1);
+      } else {
+        const int q = atomicAdd(near_cnt, 1);
+        if (q < near_cap) nearL[q] = ts;
+        else atomicOr(err, 2);
+      }
+      continue;
+    }
+    // the children of the non-leaf side(s): 2 or 4 pairs
+    int2 c[4];
+    int nc;
+    if (lt) {
+      c[0] = make_int2(t, s0);
+      c[1] = make_int2(t, child1[s]);
+      nc = 2;
+    } else if (ls) {
+      c[0] = make_int2(t0, s);
+      c[1] = make_int2(child1[t], s);
+      nc = 2;
+    } else {
+      const int t1 = child1[t], s1 = child1[s];
+      c[0] = make_int2(t0, s0);
+      c[1] = make_int2(t0, s1);
+      c[2] = make_int2(t1, s0);
+      c[3] = make_int2(t1, s1);
+      nc = 4;
+    }
+    const int q = atomicAdd(next_cnt, nc);
+    if (q + nc <= next_cap) {
+      for (int j = 0; j < nc; ++j) next[q + j] = c[j];
+    } else {
+      atomicOr(err, 2);
+    }
   }
 }
 
-void launch_block_level(const int2* front, int nfront, const double* box, const int32_t* child0,
-                        const int32_t* child1, const int32_t* nbegin, const int32_t* nend, int rb,
-                        int re, double eta2, int max_mn, int2* next, int* next_cnt,
-                        int2* nearL, int* near_cnt, int2* farL, int* far_cnt, int* err,
-                        hipStream_t s) {
-  if (nfront <= 0) return;
-  hipLaunchKernelGGL(block_level_kernel, dim3((nfront + WG - 1) / WG), dim3(WG), 0, s, front,
-                     nfront, box, child0, child1, nbegin, nend, rb, re, eta2, max_mn, next,
-                     next_cnt, nearL, near_cnt, farL, far_cnt, err);
+void launch_block_level(const int2* front, const int* nfront, int64_t front_cap,
+                        const double* box, const int32_t* child0, const int32_t* child1,
+                        const int32_t* nbegin, const int32_t* nend, int rb, int re, double eta2,
+                        int max_mn, int2* next, int64_t next_cap, int* next_cnt, int2* nearL,
+                        int64_t near_cap, int* near_cnt, int2* farL, int64_t far_cap,
+                        int* far_cnt, int* err, hipStream_t s) {
+  // a fixed grid: the frontier size is known only on the device
+  const int64_t want = (front_cap + WG - 1) / WG;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 512));
+  hipLaunchKernelGGL(block_level_kernel, dim3(grid), dim3(WG), 0, s, front, nfront, front_cap,
+                     box, child0, child1, nbegin, nend, rb, re, eta2, max_mn, next, next_cap,
+                     next_cnt, nearL, near_cap, near_cnt, farL, far_cap, far_cnt, err);
   HMX_LAUNCHED();
 }
 

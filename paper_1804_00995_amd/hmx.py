@@ -57,6 +57,7 @@ class Params(C.Structure):
         ("regularize", C.c_int32),
         ("reg_radius", C.c_double),
         ("near_mode", C.c_int32),
+        ("force_block_cap", C.c_int64),
     ]
 
 

@@ -71,7 +71,8 @@ def test_bad_params_rejected_on_host(hmx):
                      ({"aca_arena": 2}, hmx.EINVAL), ({"aca_wave": 3}, hmx.EINVAL),
                      ({"regularize": 2}, hmx.EINVAL), ({"regularize": 1, "reg_radius": 0.0}, hmx.EINVAL),
                      ({"regularize": 1, "reg_radius": float("nan")}, hmx.EINVAL),
-                     ({"regularize": 1, "tol": 0.0}, hmx.EUNSUPPORTED)]:
+                     ({"regularize": 1, "tol": 0.0}, hmx.EUNSUPPORTED),
+                     ({"force_block_cap": -1}, hmx.EINVAL)]:
         p = hmx.params(**kw)
         rc = lib.hmx_build(fake, 3, fake, 1, bary, w, 3, 1, 5.0, C.byref(p), None, C.byref(h))
         assert rc == code, (kw, rc, lib.hmx_last_error())

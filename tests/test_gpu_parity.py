@@ -111,6 +111,18 @@ def test_tree_and_blocks_identical(H, level, leaf, max_mn):
     assert op.info["n_leaves"] == int((To["child0"] < 0).sum())
 
 
+@pytest.mark.parametrize("cap", [1, 16, 300])
+def test_block_recursion_with_small_buffers(H, cap):
+    # buffers far below the lists' sizes: the recursion drops what does not fit, counts it, and
+    # runs again with larger buffers until nothing is dropped; the lists equal the oracle's
+    op, P, W = build(H, 4, leaf_size=32, tol=1e-3, force_block_cap=cap)
+    Ho = oracle.HMatrix(P, W, 1, 5.0, leaf=32, tol=1e-3)
+    nearG, farG, _ = op.export_blocks()
+    nearO, farO, _ = Ho.blocks()
+    assert np.array_equal(nearG, nearO) and np.array_equal(farG, farO)
+    assert len(nearG) > 300 and len(farG) > 300
+
+
 # ------------------------------------------------------------------------------ H product (a5-a7)
 @pytest.mark.parametrize("level,kern,k", [(3, 1, 5.0), (3, 0, 0.0), (4, 1, 10.0), (4, 1, 25.0)])
 def test_hmatvec_within_tolerance_of_dense(H, level, kern, k):
