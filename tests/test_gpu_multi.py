@@ -1,7 +1,8 @@
 """The several-vector product hmx_matvec_multi through the C ABI: every vector's result is
 bit-identical to the one-vector product's (the kernels keep its summation order), for FP64 and
-FP32 H-matrices, leaves of 64 and 200 points (both paths of the leaf kernel), an operator
-between different point sets and a dense operator, with 1 to 7 vectors (groups of 4, 2, 1)."""
+FP32 H-matrices, leaves of 64, 128 and 200 points (the leaf kernel's one-, two- and four-chunk
+instances), an operator between different point sets and a dense operator, with 1 to 7 vectors
+(groups of 4, 2, 1)."""
 import numpy as np
 import pytest
 
@@ -32,7 +33,7 @@ def check(op, nr, seed):
         assert torch.equal(Y[r], op.matvec(X[r].contiguous())), (nr, r)
 
 
-@pytest.mark.parametrize("precision,leaf", [(0, 64), (1, 64), (0, 200)])
+@pytest.mark.parametrize("precision,leaf", [(0, 64), (1, 64), (0, 128), (1, 128), (0, 200)])
 def test_hmatrix_bit_identical(H, precision, leaf):
     v, f = I.icosphere(4)
     op = H.build(torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda(), *RULE, kern=H.HELMHOLTZ,

@@ -53,7 +53,7 @@ def test_all_near_equals_dense_oracle(H, leaf):
     op.close()
 
 
-@pytest.mark.parametrize("precision,leaf", [(0, 64), (1, 64), (0, 200), (1, 128)])
+@pytest.mark.parametrize("precision,leaf", [(0, 64), (1, 64), (0, 128), (1, 128), (0, 200)])
 def test_matches_stored_near_field(H, precision, leaf):
     v, f, vd, fd, P, W = sphere(4)
     kw = dict(tol=1e-6, leaf_size=leaf, precision=precision)
