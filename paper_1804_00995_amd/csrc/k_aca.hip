@@ -739,14 +739,16 @@ __device__ void aca_block(FarDesc* __restrict__ descs, int b, const double* __re
 // Length of the LDS residual buffer (a multiple of NT) of the large-block class.  FP64 and
 // 512-thread FP32 workgroups keep most of the partial residual in LDS: 7680 / 15360 entries with
 // 512 threads (one workgroup per CU), 3328 FP64 entries with 256 threads (two per CU).  FP32
-// 256-thread workgroups keep 1024 entries and run three per CU, which leaves LDS for the other
-// classes on the same CUs (measured faster for FP32, slower for FP64).  The other classes keep
-// their partial residual in the factor slot.
+// 256-thread workgroups run three per CU, their registers filling the CU, and keep 4352 entries
+// each, as much as three workgroups' LDS allows (52.7 KB each): the residual of blocks up to that
+// length no longer goes through the factor slot between windows (1024 entries built the 245 760-
+// point sphere 2.5 % and the 3.93M-point share 2.7 % slower).  The other classes keep their
+// partial residual in the factor slot.
 template <class T, int NT, bool BIG>
 constexpr int aca_rl() {
   return !BIG ? 0
          : NT >= 512 ? (sizeof(T) == 16 ? 7680 : 15360)
-                     : (sizeof(T) == 16 ? 3328 : 1024);
+                     : (sizeof(T) == 16 ? 3328 : 4352);
 }
 // Minimum waves per SIMD the register allocation has to allow.  The FP32 small-block kind is
 // bound by the latency of its steps, not by bandwidth: six waves per SIMD (a few spilled
