@@ -39,8 +39,9 @@ __device__ __forceinline__ double dist2(const double* a, const double* b) {
 // One level of the recursion.  Its frontier size is read from the device (*nfront_p, of which
 // at most front_cap pairs are in `front`) and the pairs are taken in a grid-stride loop, so the
 // host queues every level without reading a size back.  An output past its buffer's capacity
-// is dropped and sets bit 2 of *err; the counters still count it, so the host learns the sizes
-// it needs and runs the recursion again with larger buffers.
+// is dropped and sets bit 2 of *err; the counters still count it, so the host learns the size
+// the level needed, and every later level returns at once (its frontier would hold entries
+// that were never written).  The host then runs the recursion again with larger buffers.
 __global__ void __launch_bounds__(WG) block_level_kernel(
     const int2* __restrict__ front, const int* __restrict__ nfront_p, int64_t front_cap,
     const double* __restrict__ box, const int32_t* __restrict__ child0,
@@ -49,6 +50,9 @@ __global__ void __launch_bounds__(WG) block_level_kernel(
     int2* __restrict__ next, int64_t next_cap, int* next_cnt, int2* __restrict__ nearL,
     int64_t near_cap, int* near_cnt, int2* __restrict__ farL, int64_t far_cap, int* far_cnt,
     int* err) {
+  // after a dropped output the frontier is incomplete (and holds unwritten entries): the levels
+  // that follow do nothing, and the host runs the recursion again with larger buffers
+  if (*err & 2) return;
   const int64_t nfront = min((int64_t)*nfront_p, front_cap);
   const int64_t stride = (int64_t)gridDim.x * WG;
   for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < nfront; i += stride) {

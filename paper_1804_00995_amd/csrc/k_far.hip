@@ -209,8 +209,10 @@ __global__ void __launch_bounds__(WG) far_rec_kernel(
     v[7 + cls] = 1;
     v[11 + cls] = (int64_t)es * mn * r * (r + 1) / 2;
   }
-  // one atomic per wavefront and statistic
-  const int lane = threadIdx.x & 63;
+  // one atomic per workgroup and statistic (wavefront sums, then the four wavefronts in LDS):
+  // one per wavefront kept thousands of atomics queued on each of the few addresses
+  __shared__ unsigned long long wsum[NWAVE][FAR_STATS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x / WAVE;
 #pragma unroll
   for (int q = 0; q < FAR_STATS; ++q) {
     unsigned long long x = v[q];
@@ -219,7 +221,15 @@ __global__ void __launch_bounds__(WG) far_rec_kernel(
       const unsigned long long y = __shfl_xor(x, o, 64);
       x = q == 2 ? (x > y ? x : y) : x + y;
     }
-    if (lane == 0 && x) {
+    if (lane == 0) wsum[w][q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < FAR_STATS) {
+    const int q = threadIdx.x;
+    unsigned long long x = wsum[0][q];
+#pragma unroll
+    for (int u = 1; u < NWAVE; ++u) x = q == 2 ? (x > wsum[u][q] ? x : wsum[u][q]) : x + wsum[u][q];
+    if (x) {
       if (q == 2)
         atomicMax(&stats[q], x);
       else

@@ -285,14 +285,15 @@ def test_fp32_mixed_against_oracle_and_fp64(H, level, k, rows):
 
 
 # ------------------------------------------------------------------------------ row shares
-@pytest.mark.parametrize("shares", [2, 4, 8])
-def test_row_shares_sum_to_whole_product(H, shares):
+@pytest.mark.parametrize("shares,near_mode", [(2, 0), (4, 0), (8, 0), (4, 1)])
+def test_row_shares_sum_to_whole_product(H, shares, near_mode):
     """The operator split by rows into `shares` parts (one per device of a row-sharded build):
     each share's blocks are the whole operator's blocks whose row node lies in the share, and
     the shares' products add up to the whole product bit for bit (each row comes from exactly
-    one share, computed with the same blocks in the same order)."""
+    one share, computed with the same blocks in the same order), with the near field stored or
+    computed in the product."""
     v, f, vd, fd = mesh(4)
-    full = H.build(vd, fd, *RULE, kern=1, k=12.0)
+    full = H.build(vd, fd, *RULE, kern=1, k=12.0, prm=H.params(near_mode=near_mode))
     x = torch.from_numpy(I.complex_vector(full.M, 8)).cuda()
     y_full = full.matvec(x)
     nearF, farF, rankF = full.export_blocks()
@@ -300,7 +301,8 @@ def test_row_shares_sum_to_whole_product(H, shares):
     covered = np.zeros(full.M, bool)
     perm = full.export_tree()["perm"]
     for r in range(shares):
-        op = H.build(vd, fd, *RULE, kern=1, k=12.0, prm=H.params(row_shares=shares, row_share=r))
+        op = H.build(vd, fd, *RULE, kern=1, k=12.0,
+                     prm=H.params(row_shares=shares, row_share=r, near_mode=near_mode))
         rb, re = op.info["row_begin"], op.info["row_end"]
         assert 0 <= rb < re <= full.M
         covered[rb:re] = True
