@@ -298,11 +298,13 @@ def run_sphere(args, torch, oracle, hmx, I):
     extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision,
                            near_stored=prm.near_mode == 0))
     # kernel evaluations per second by phase: near-field assembly (its phase time includes the
-    # block bookkeeping), and ACA rows and columns; the ALU ceiling of one evaluation beside them
+    # block bookkeeping; none when the product computes the near field), and ACA rows and
+    # columns; the ALU ceiling of one evaluation beside them
     near_s, aca_s = info["t_near_ms"] / 1e3, info["t_aca_ms"] / 1e3
+    near_built = info["near_entries"] if prm.near_mode == 0 else 0
     extra["evals_per_s"] = {
-        "near_assembly": info["near_entries"] / near_s if near_s > 0 else None,
-        "aca_rows_columns": (info["kernel_evals"] - info["near_entries"]) / aca_s if aca_s > 0 else None,
+        "near_assembly": near_built / near_s if near_built and near_s > 0 else None,
+        "aca_rows_columns": (info["kernel_evals"] - near_built) / aca_s if aca_s > 0 else None,
         "alu_ceiling": DENSE_ALU_PEAK[args.precision],
     }
     if multi:

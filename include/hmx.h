@@ -409,7 +409,8 @@ typedef struct {
   int64_t bytes;           /* device bytes held by the operator (slot pools trimmed to use) */
   int32_t precision, is_dense;
   double t_tree_ms, t_blocks_ms, t_near_ms, t_aca_ms, t_total_ms; /* build phases (events) */
-  int64_t kernel_evals;    /* Green-kernel evaluations spent in the build */
+  int64_t kernel_evals;    /* Green-kernel evaluations spent in the build (near entries only when
+                            * they are stored: near_mode 0) */
   int64_t factor_bytes;    /* device bytes of the slots holding far-block factors (used part) */
   int64_t predicted_entries; /* learned layout: sum of r_alloc * (m + n) over far blocks */
   /* ACA by block class: [0] m + n >= aca_big_mn (aca_big_threads-thread workgroups), [1] the

@@ -155,8 +155,11 @@ void build_tree(hmx_op* op, hipStream_t s) {
   DevBuf<int32_t> choff(max_chunked_nodes + 1), saxis(max_chunked_nodes), ccnt(chunk_cap),
       cleft(chunk_cap);
   DevBuf<double> pbox(6 * chunk_cap), smid(max_chunked_nodes);
+  // a node splits only if it holds more than `leaf` points, and the nodes of one level are
+  // disjoint, so a level adds at most 2 min(count, M / (leaf + 1)) nodes
+  const int64_t max_split = M / ((int64_t)leaf + 1);
   while (count > 0) {
-    size_t need = (size_t)total + 2 * (size_t)count;
+    size_t need = (size_t)total + 2 * (size_t)std::min<int64_t>(count, max_split);
     if (need > cap) {
       size_t nc = std::max(need, 2 * cap);
       grow(nbegin, nc, total, s);
@@ -215,6 +218,11 @@ void build_tree(hmx_op* op, hipStream_t s) {
   launch_leaf_marks(total, op->nbegin.p, op->child0.p, flag.p, s);
   launch_start_node(total, op->nbegin.p, op->child0.p, start.p, s);
   scan_excl_i64(flag.p, scan.p, M, s);
+  // the node ranges come back with the leaf count (one wait)
+  std::vector<int32_t> hb(total), he(total), hc(total);
+  HMX_HIP(hipMemcpyAsync(hb.data(), op->nbegin.p, 4 * (size_t)total, hipMemcpyDeviceToHost, s));
+  HMX_HIP(hipMemcpyAsync(he.data(), op->nend.p, 4 * (size_t)total, hipMemcpyDeviceToHost, s));
+  HMX_HIP(hipMemcpyAsync(hc.data(), op->child0.p, 4 * (size_t)total, hipMemcpyDeviceToHost, s));
   op->n_leaves = (int)read1(scan.p + M, s);
   op->leaves.alloc(op->n_leaves);
   launch_leaf_list(M, flag.p, scan.p, start.p, op->leaves.p, s);
@@ -224,10 +232,6 @@ void build_tree(hmx_op* op, hipStream_t s) {
   HMX_HIP(hipStreamSynchronize(s));
   // the product holds one leaf's rows in a workgroup (at most 4 x 64); a leaf can exceed the
   // leaf size only when its points coincide
-  std::vector<int32_t> hb, he, hc;
-  to_host(hb, op->nbegin.p, total, s);
-  to_host(he, op->nend.p, total, s);
-  to_host(hc, op->child0.p, total, s);
   op->max_leaf_rows = 0;
   for (int i = 0; i < total; ++i) {
     if (hc[i] >= 0) continue;
@@ -794,7 +798,7 @@ void build_h(hmx_op* op, hipStream_t s) {
   build_blocks(op, s);
   op->t_blocks = tm.stop();
   build_near<T>(op, s);
-  op->kernel_evals += op->near_entries;
+  if (op->p.near_mode == 0) op->kernel_evals += op->near_entries;
   op->t_near = tm.stop();
   build_far<T>(op, s);
   op->t_aca = tm.stop();
