@@ -60,6 +60,8 @@ def test_matches_stored_near_field(H, precision, leaf):
     st = H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=15.0, prm=H.params(**kw))
     ot = H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=15.0, prm=H.params(near_mode=1, **kw))
     assert ot.info["near_entries"] == st.info["near_entries"] > 0 and ot.info["n_far"] > 0
+    # the build evaluates the near entries only when it stores them
+    assert st.info["kernel_evals"] - ot.info["kernel_evals"] == st.info["near_entries"]
     es = 16 if precision == 0 else 8
     # no near-field storage: the operator is smaller by the near entries (the slot pools, whose
     # trimmed size depends on how the blocks fell to workgroups, are left out of the comparison)
