@@ -116,8 +116,8 @@ typedef struct {
                          one far block (smaller ranks, less ACA work and better balance per
                          block); 0: no limit (the plain admissibility recursion) */
   int32_t aca_big_threads; /* workgroup size of the blocks with m + n >= aca_big_mn: 512 (one
-                              workgroup per CU), 256 (two per CU) or 0 (default: 512 for FP64,
-                              256 for FP32) */
+                              workgroup per CU), 256 (two per CU in FP64, three in FP32) or 0
+                              (default: 512 for FP64, 256 for FP32) */
   int32_t aca_small_mn; /* >= 0 (default 1024): blocks with m + n below it (other than the
                            wavefront blocks) run in 64-thread workgroups holding 256 ACA
                            coefficients, many per CU, with direct cross sums whatever
