@@ -62,6 +62,26 @@ __device__ __forceinline__ void cfms(double2& a, double2 b, double2 c) {
   a.y = fma(-b.y, c.x, a.y);
 }
 
+// r = sqrt(r2) and y = 1 / r for r2 > 0 without the square-root and division sequences: the
+// hardware reciprocal square root y0, one third-order Newton step y = y0 (1 + e/2 + 3 e^2/8)
+// with e = 1 - r2 y0^2 (the relative error is cubed, so a start good to about 2^-18 ends at
+// rounding level), then r0 = r2 y and one Newton step of the square root with the exact
+// residual r2 - r0^2 (an fma), which rounds r like the IEEE square root except in rare near-ties.
+// Outside [2^-900, 2^900] (never reached by surface meshes of sane coordinates) the IEEE
+// square root and division.
+__device__ __forceinline__ void dist_inv(double r2, double& r, double& y) {
+  if (r2 < 0x1p-900 || r2 > 0x1p900) {
+    r = sqrt(r2);
+    y = 1.0 / r;
+    return;
+  }
+  const double y0 = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-(r2 * y0), y0, 1.0);
+  y = fma(y0 * e, fma(0.375, e, 0.5), y0);
+  const double r0 = r2 * y;
+  r = fma(0.5 * y, fma(-r0, r0, r2), r0);
+}
+
 // Green kernel between a target x and a source y, FP64 throughout:
 // G = e^{i k r} / (4 pi r), r = |x - y|; 0 when r == 0; Laplace is the real 1/(4 pi r);
 // POLY2 is the test-only separable kernel (1 + x.y)^2.
@@ -74,16 +94,17 @@ __device__ __forceinline__ double2 green64(int kern, double k, double xx, double
   double dx = xx - yx, dy = xy - yy, dz = xz - yz;
   double r2 = dx * dx + dy * dy + dz * dz;
   if (r2 == 0.0) return make_double2(0.0, 0.0);
-  double r = sqrt(r2);
+  double r, ir;
+  dist_inv(r2, r, ir);
   if (kern >= K_GRADY_X && kern <= K_GRADY_Z) {
     // dG/dy_j = e^{ikr} (ikr - 1) (y_j - x_j) / (4 pi r^3)
     const double d = kern == K_GRADY_X ? -dx : (kern == K_GRADY_Y ? -dy : -dz);
-    const double f = d * INV4PI / (r2 * r), kr = k * r;
+    const double f = d * INV4PI * (ir * ir * ir), kr = k * r;
     double s, c;
     sincos(kr, &s, &c);
     return make_double2(f * (-c - kr * s), f * (kr * c - s));
   }
-  double inv = INV4PI / r;
+  double inv = INV4PI * ir;
   if (kern == K_LAPLACE) return make_double2(inv, 0.0);
   double s, c;
   sincos(k * r, &s, &c);
@@ -101,17 +122,18 @@ __device__ __forceinline__ float2 green32(int kern, double k, double xx, double 
   double dx = xx - yx, dy = xy - yy, dz = xz - yz;
   double r2 = dx * dx + dy * dy + dz * dz;
   if (r2 == 0.0) return make_float2(0.0f, 0.0f);
-  double r = sqrt(r2);
+  double r, ir;
+  dist_inv(r2, r, ir);
   if (kern >= K_GRADY_X && kern <= K_GRADY_Z) {
     const double d = kern == K_GRADY_X ? -dx : (kern == K_GRADY_Y ? -dy : -dz);
-    const float f = (float)(d * INV4PI / (r2 * r)), kr = (float)(k * r);
+    const float f = (float)(d * INV4PI * (ir * ir * ir)), kr = (float)(k * r);
     double ph = k * r;
     ph = ph - TWO_PI * rint(ph * (1.0 / TWO_PI));
     float s, c;
     __sincosf((float)ph, &s, &c);
     return make_float2(f * (-c - kr * s), f * (kr * c - s));
   }
-  float inv = (float)(INV4PI / r);
+  float inv = (float)(INV4PI * ir);
   if (kern == K_LAPLACE) return make_float2(inv, 0.0f);
   double ph = k * r;
   ph = ph - TWO_PI * rint(ph * (1.0 / TWO_PI));

@@ -402,3 +402,30 @@ def test_kernel_values_match_golden(H, precision, bound):
         assert abs(complex(y[0]) - g) <= bound * abs(g), (r, k, y[0], g)
         assert y[1] == 0  # K_11 = 0 (r = 0) and K_10 x_0 = 0
         op.close()
+
+
+@pytest.mark.parametrize("kern,k,lo,hi,bound", [(0, 0.0, -140.0, 140.0, 1e-15),
+                                                (1, 40.0, -2.0, 1.0, 1e-12)])
+def test_distance_and_reciprocal_over_wide_range(H, kern, k, lo, hi, bound):
+    """Column 0 of the dense FP64 operator (a source of weight 1 at the origin) at targets whose
+    distances span 10^lo to 10^hi, including the ranges that take the IEEE square root and
+    division instead of the refined reciprocal square root, against numpy in FP64: 1 / (4 pi r)
+    within a few ulp, and e^{ikr} / (4 pi r) within k r times the rounding of r."""
+    rng = np.random.default_rng(5)
+    n = 4000
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    t = d * (10.0 ** rng.uniform(lo, hi, n))[:, None]
+    pts = np.vstack([np.zeros((1, 3)), t])
+    xyzw = torch.from_numpy(np.ascontiguousarray(
+        np.vstack([pts.T, np.ones((1, n + 1))]))).cuda()
+    op = H.build_points(xyzw, kern=kern, k=k, prm=H.params(tol=0.0))
+    x = np.zeros(n + 1, np.complex128)
+    x[0] = 1.0
+    y = apply(op, x)
+    op.close()
+    r = np.sqrt((t * t).sum(axis=1))
+    g = np.exp(1j * k * r) / (4.0 * np.pi * r)
+    assert y[0] == 0
+    err = np.abs(y[1:] - g) / np.abs(g)
+    assert err.max() <= bound, (err.max(), r[err.argmax()])
