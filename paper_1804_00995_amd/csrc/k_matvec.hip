@@ -656,7 +656,9 @@ __global__ void __launch_bounds__(WG) dense_otf_kernel(const double* __restrict_
                                                        const T* __restrict__ x,
                                                        T* __restrict__ partial) {
   __shared__ T part[NWAVE][WAVE];
-  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  // the wavefront index is uniform, so the source loop and its loads (one source for all 64
+  // lanes) run on the scalar unit
+  const int lane = threadIdx.x & (WAVE - 1), w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   const int64_t i = (int64_t)blockIdx.x * WAVE + lane;
   const int64_t j0 = (int64_t)blockIdx.y * DOTF_CHUNK + w * WAVE;
   const int64_t j1 = min(j0 + WAVE, cols);
