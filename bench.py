@@ -612,13 +612,15 @@ def run_radiation(args, torch, oracle, hmx, I):
     line(args, ms_step, args.precision, config, extra)
 
 
-# ALU ceiling of the dense on-the-fly product (evaluations per second), from the instructions the
-# built kernel's inner loop executes per evaluation of the Helmholtz kernel (gfx950 assembly; the
-# sin/cos argument reduction's fast path): FP64 mode 82 FP64 and 37 32-bit VALU instructions
-# plus 2 transcendental; FP32 mode 37 FP64, 22 32-bit and 4 transcendental.  A wave64 VALU
-# instruction occupies a 16-lane SIMD for 4 cycles, a transcendental for 16: 508 and 300 SIMD
-# cycles per 64 evaluations, over 1024 SIMDs at 2.4 GHz.
-DENSE_ALU_PEAK = {"fp64": 1024 * 2.4e9 * 64 / 508.0, "fp32": 1024 * 2.4e9 * 64 / 300.0}
+# ALU ceiling of the dense on-the-fly product (evaluations per second), from the VALU
+# instructions the built kernel issues per evaluation of the Helmholtz kernel (SQ_INSTS_VALU and
+# SQ_INSTS_VALU_TRANS_* over the 61 440-point product): FP64 mode 100.8, one of them
+# transcendental (the reciprocal square root); FP32 mode 42.4, three transcendental.  A wave64
+# VALU instruction occupies a 16-lane SIMD for 4 cycles; the transcendentals overlap with the
+# rest (the measured FP32 rate is above what a serial 16-cycle transcendental would allow), so
+# 4 x 99.8 = 399 and 4 x 39.4 = 158 SIMD cycles per 64 evaluations, over 1024 SIMDs at 2.4 GHz.
+DENSE_ALU_CYCLES = {"fp64": 4 * (100.8 - 1.0), "fp32": 4 * (42.4 - 3.0)}
+DENSE_ALU_PEAK = {p: 1024 * 2.4e9 * 64 / c for p, c in DENSE_ALU_CYCLES.items()}
 
 
 def run_dense(args, torch, oracle, hmx, I):

@@ -110,9 +110,12 @@ def test_rect_graph_and_several_vectors(H):
         o.close()
 
 
-def test_full_size_sampled_rows(H):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_sampled_rows(H, precision):
+    # the bench's sphere workload in both precisions, as it is timed
     v, f, vd, fd, P, W = sphere(6)
-    op = H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=40.0, prm=H.params(near_mode=1))
+    op = H.build(vd, fd, *RULE, kern=H.HELMHOLTZ, k=40.0,
+                 prm=H.params(near_mode=1, precision=precision))
     assert op.info["bytes"] < op.info["factor_bytes"] * 1.2
     x = I.complex_vector(P.shape[0], 0)
     y = apply(op, x)
