@@ -8,8 +8,14 @@
 
 namespace hmx {
 
-// One workgroup per block; consecutive threads write consecutive entries.  Thread e handles
-// entries e, e + WG, ... with (i, j) advanced incrementally (no per-entry division).
+// One workgroup per block, in one of two layouts chosen per precision (measured):
+//  - FP64 (an evaluation is about 100 VALU instructions): consecutive threads take consecutive
+//    entries of the column-major block, so every lane is busy whatever m is; thread e handles
+//    entries e, e + WG, ... with (i, j) advanced incrementally (no per-entry division);
+//  - FP32 mixed (about 40, so that the loads weigh more): each wavefront takes whole columns j
+//    (uniform across its lanes, so the source point comes through scalar loads) and its lanes
+//    the rows of a chunk of 64, whose targets are loaded once; lanes past the last row evaluate
+//    a clamped row and store nothing.
 template <class T>
 __global__ void __launch_bounds__(WG) assemble_kernel(
     const int32_t* __restrict__ tb, const int32_t* __restrict__ mm, const int32_t* __restrict__ sb,
@@ -20,18 +26,31 @@ __global__ void __launch_bounds__(WG) assemble_kernel(
   const int t0 = tb[blk], m = mm[blk], s0 = sb[blk], n = nn[blk];
   const double k = kp[t0];  // wavenumber of the block's mesh
   T* K = pool + off[blk];
-  const int64_t total = (int64_t)m * n;
-  int i = threadIdx.x % m, j = threadIdx.x / m;
-  const int di = WG % m, dj = WG / m;
-  for (int64_t e = threadIdx.x; e < total; e += WG) {
-    double tx = X[t0 + i], ty = Y[t0 + i], tz = Z[t0 + i];
-    double sx = X[s0 + j], sy = Y[s0 + j], sz = Z[s0 + j], sw = W[s0 + j];
-    K[e] = eval_entry<T>(kern, k, tx, ty, tz, sx, sy, sz, sw);
-    i += di;
-    j += dj;
-    if (i >= m) {
-      i -= m;
-      j += 1;
+  if constexpr (sizeof(T) == 16) {
+    const int64_t total = (int64_t)m * n;
+    int i = threadIdx.x % m, j = threadIdx.x / m;
+    const int di = WG % m, dj = WG / m;
+    for (int64_t e = threadIdx.x; e < total; e += WG) {
+      K[e] = eval_entry<T>(kern, k, X[t0 + i], Y[t0 + i], Z[t0 + i], X[s0 + j], Y[s0 + j],
+                           Z[s0 + j], W[s0 + j]);
+      i += di;
+      j += dj;
+      if (i >= m) {
+        i -= m;
+        j += 1;
+      }
+    }
+  } else {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    for (int r0 = 0; r0 < m; r0 += WAVE) {
+      const int i = min(r0 + lane, m - 1);
+      const bool live = r0 + lane < m;
+      const double tx = X[t0 + i], ty = Y[t0 + i], tz = Z[t0 + i];
+      for (int j = w; j < n; j += NWAVE) {
+        const T v = eval_entry<T>(kern, k, tx, ty, tz, X[s0 + j], Y[s0 + j], Z[s0 + j], W[s0 + j]);
+        if (live) K[(int64_t)j * m + r0 + lane] = v;
+      }
     }
   }
 }
