@@ -197,12 +197,16 @@ def test_deterministic(H):
     assert np.array_equal(y1, y2)
 
 
-def test_forced_dense_fallback(H):
-    # a rank cap of 2 forces ACA past its cap on most blocks: those are stored exactly
-    op, P, W = build(H, 3, kern=1, k=5.0, tol=1e-3, force_rank_cap=2)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forced_dense_fallback(H, precision):
+    # a rank cap of 2 forces ACA past its cap on most blocks: those are stored exactly, by the
+    # assembly kernel in its FP64 or FP32 layout
+    op, P, W = build(H, 3, kern=1, k=5.0, tol=1e-3, force_rank_cap=2, precision=precision)
     assert op.info["dense_far"] > 0
     x = I.complex_vector(P.shape[0], 0)
-    assert rel(apply(op, x), oracle.dense_matvec(P, W, 1, 5.0, x)) <= 1e-3
+    y = apply(op, x, torch.complex128 if precision == 0 else torch.complex64)
+    assert rel(y, oracle.dense_matvec(P, W, 1, 5.0, x)) <= 1e-3
+    op.close()
 
 
 def test_overflow_continuation_identical(H):
