@@ -297,6 +297,21 @@ def run_sphere(args, torch, oracle, hmx, I):
     }
     extra.update(rooflines(info, aca, mv_ms, M, 16 if prec == hmx.FP64 else 8, args.precision,
                            near_stored=prm.near_mode == 0))
+    if args.aca_serial != "on":
+        # each ACA class on its own: one more build (untimed) with the classes one after the
+        # other, whose first launches are then each class's own duration (concurrent, a class's
+        # launch also spans the time it waits for room beside the others)
+        ops = hmx.build(vd, fd, bary, w, kern=hmx.HELMHOLTZ, k=args.k, stream=stream,
+                        prm=hmx.params(tol=1e-3, leaf_size=64, eta=1.5, precision=prec,
+                                       regularize=int(reg), aca_serial=1,
+                                       near_mode=prm.near_mode))
+        alone = list(ops.info["aca_ms"])
+        ops.close()
+        cls = extra["aca_classes"]
+        cls["alone_ms"] = [round(t, 3) for t in alone]
+        cls["alone_frac_of_peak"] = [round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t > 0 and b > 0
+                                     else None for b, t in zip(cls["algorithmic_bytes"], alone)]
+        log(f"ACA classes one at a time: {cls['alone_ms']} ms")
     # kernel evaluations per second by phase: near-field assembly (its phase time includes the
     # block bookkeeping; none when the product computes the near field), and ACA rows and
     # columns; the ALU ceiling of one evaluation beside them
